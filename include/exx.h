@@ -1,0 +1,184 @@
+/*
+ * exx.h -- C ABI of the THC-oo-K k-point exact-exchange build for gfx950.
+ *
+ * Method: Rettig, Lee, Head-Gordon, "Even Faster Exact Exchange for Solids via
+ * Tensor Hypercontraction" (THC-oo-K, Sec. 2.3, Algorithm 2). Given occupied
+ * orbitals on the real-space grid of every k-point and a fixed set of N_ISDF
+ * interpolation points, one "K-build" returns the exchange matrix K^k for every
+ * k and the exchange energy E_x. It runs in three calls:
+ *
+ *   exx_isdf_fit   occupied-pair ISDF fit, one per momentum transfer q
+ *                  (Eqs. 7-8 and 13 restricted to occupied pairs, Eq. 16);
+ *   exx_coulomb_V  FFT-Poisson Coulomb matrices of the interpolating vectors
+ *                  (Eq. 9 / Eq. 15 by GPW, Algorithm 2 "FFT" and "M^q" lines);
+ *   exx_build_K    k-convolution and exchange contraction (Eq. 14, the X^k and
+ *                  K_ij lines of Algorithm 2) and E_x (Eq. 18).
+ *
+ * Conventions
+ * -----------
+ * Cell: orthorhombic, edges L[3] (bohr). Grid point g = (g1,g2,g3) sits at
+ *   r_g = sum_i (g_i/n_i) L_i e_i; flat grid index r = (g1*n2 + g2)*n3 + g3.
+ * k-mesh: Gamma-centred, k_n = sum_i (n_i/N_i) b_i, b_i = 2 pi/L_i e_i, flat
+ *   index n in C order. Momentum transfer m(n, n') = (n' - n) mod N per axis,
+ *   q_m = sum_i (m_i/N_i) b_i.
+ * Orbitals: psi_in(r) is the full Bloch orbital (no e^{-ik.r} removed), one
+ *   row of N_g values per (n, i).
+ * Coulomb kernel for transfer m at FFT index g: v^m(g) = 4 pi/|K|^2 with
+ *   K = sum_i kappa_i b_i/N_i, kappa_i = wrap_{N_i n_i}(N_i g_i + m_i),
+ *   wrap_L(x) = ((x + floor(L/2)) mod L) - floor(L/2); the K = 0 term is
+ *   dropped (no Madelung correction).
+ * Forward FFT sign: F(g) = sum_r f(r) exp(-2 pi i g.r/n).
+ * Complex numbers are interleaved (re, im) pairs: "c128" = 2 x double,
+ *   "c64" = 2 x float. Arrays are C order (last index fastest).
+ * Fit gauge: xi^m_P(r) interpolates e^{-i q_m.r} conj psi_in(r) psi_{j,n+m}(r).
+ *   Bloch gauge: Vb^m_PQ = e^{-i q_m.(r_P - r_Q)} V^m_PQ, with
+ *   V^m_PQ = (Omega/N_g^2) sum_g v^m(g) F_P(g) conj F_Q(g), F_P = FFT(xi^m_P).
+ *
+ * Ownership and errors
+ * --------------------
+ * Every array argument is caller-owned DEVICE memory unless marked "host";
+ * the library never frees caller memory. Scratch memory belongs to the handle
+ * (allocated on first use, grown on demand, released by exx_destroy). Calls
+ * are asynchronous on the given stream (0 = default stream) and return a
+ * status; no C++ exception crosses the ABI. Shape and argument checks happen
+ * before any launch; on error nothing is launched and exx_last_error(h)
+ * returns a message. A handle must not be used by two host threads at once.
+ * Calls that share a handle must be ordered (same stream or synchronised),
+ * because they share the handle's scratch memory.
+ */
+#ifndef EXX_H
+#define EXX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EXX_OK = 0,
+  EXX_ERR_ARG = -1,         /* null pointer, bad enum, bad handle */
+  EXX_ERR_SHAPE = -2,       /* sizes out of the supported range */
+  EXX_ERR_NOMEM = -3,       /* scratch allocation failed */
+  EXX_ERR_NOT_PD = -4,      /* reserved: fit metric not positive definite */
+  EXX_ERR_NONFINITE = -5,   /* reserved: non-finite input detected */
+  EXX_ERR_DEVICE = -6,      /* a HIP runtime call failed */
+  EXX_ERR_UNSUPPORTED = -7  /* precision or size not built in */
+} exx_status;
+
+/* Bulk arithmetic type. G^n, S^m, the Cholesky factorisation, the fit solve
+ * and E_x are FP64 in every mode; EXX_F32 runs the grid-sized GEMMs, the
+ * k-DFT step, the FFTs and the Coulomb contraction in FP32 (c64 storage);
+ * EXX_BF16 additionally rounds the operands of the Coulomb contraction to
+ * bfloat16 (FP32 accumulation). */
+typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2 } exx_prec;
+
+typedef struct {
+  double L[3];       /* orthorhombic cell edges, bohr */
+  int32_t grid[3];   /* n1, n2, n3: each 2..128 and 2*3*5-smooth */
+  int32_t kmesh[3];  /* N1, N2, N3: each 1..8, N_k = N1*N2*N3 <= 64 */
+  int32_t n_occ;     /* occupied orbitals per k, 1..512 */
+  int32_t n_ao;      /* basis functions per k, 1..4096 */
+  int32_t n_isdf;    /* interpolation points, 1..2048 */
+} exx_cell;
+
+typedef struct exx_context* exx_handle_t;
+
+/* Create a handle bound to HIP device `device`. */
+exx_status exx_create(exx_handle_t* h, int device);
+/* Release the handle and its scratch memory (synchronises the device). */
+exx_status exx_destroy(exx_handle_t h);
+/* Message of the last failing call on this handle ("" if none). Never NULL. */
+const char* exx_last_error(exx_handle_t h);
+/* Bytes of scratch the handle currently holds. */
+exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes);
+
+/*
+ * exx_isdf_fit -- occupied-pair ISDF fit per transfer q (Sec. 2.2-2.3,
+ * Eqs. 7-8 and 13 restricted to occupied pairs as in Eq. 16; Algorithm 2
+ * "Compute xi"). For every transfer m it forms the fit metric
+ *   S^m_PQ = e^{i q_m.(r_P - r_Q)} sum_n G^n_PQ conj G^{n+m}_PQ,
+ *   G^n_PQ = sum_i psi_in(r_P) conj psi_in(r_Q),
+ * the right-hand side
+ *   Z^m_P(r) = e^{i q_m.(r_P - r)} sum_n Gamma^n(P,r) conj Gamma^{n+m}(P,r),
+ *   Gamma^n(P,r) = sum_i psi_in(r_P) conj psi_in(r)
+ * (the k-sum evaluated as a circular correlation by DFTs over the k-mesh),
+ * factorises S^m by FP64 Cholesky in point order -- a point whose Schur
+ * pivot is below 1e-12 * max_P S^m_PP is dropped and gets xi_P = 0 -- and
+ * solves S^m xi^m(r) = Z^m(r) on every grid point.
+ *
+ *   psi_grid [N_k][n_occ][N_g]    c128 (EXX_F64) or c64 (other modes)
+ *   occ_pts  [N_k][n_isdf][n_occ] c128: psi_in(r_P), used for G^n and S^m
+ *   pts      [n_isdf] int32 flat grid indices of the points, distinct
+ *   xi       out [N_k][n_isdf][N_g], same complex type as psi_grid
+ *   S        out [N_k][n_isdf][n_isdf] c128, full Hermitian S^m
+ *   rank     out [N_k] int32: retained points per q
+ */
+exx_status exx_isdf_fit(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                        const void* psi_grid, const void* occ_pts, const int32_t* pts,
+                        void* xi, void* S, int32_t* rank, hipStream_t stream);
+
+/*
+ * exx_coulomb_V -- Coulomb matrices of the interpolating vectors by
+ * FFT-Poisson (Eq. 9 and Eq. 15 evaluated by GPW; Algorithm 2 "FFT" and
+ * "M^q" lines): F^m_P = FFT(xi^m_P), V^m = (Omega/N_g^2) F diag(v^m) F^H,
+ * returned in the Bloch gauge Vb^m_PQ = e^{-i q_m.(r_P - r_Q)} V^m_PQ.
+ *
+ *   xi  [N_k][n_isdf][N_g] as written by exx_isdf_fit (not modified)
+ *   pts [n_isdf] int32
+ *   V   out [N_k][n_isdf][n_isdf] c128, Vb^m (Hermitian)
+ */
+exx_status exx_coulomb_V(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                         const void* xi, const int32_t* pts, void* V, hipStream_t stream);
+
+/*
+ * exx_build_K -- exchange matrices and energy (Eq. 14 with the oo fit,
+ * Algorithm 2 X^k and K lines, Eq. 18):
+ *   Y^n = sum_m Vb^m o G^{n+m}   (k-convolution, by DFTs over the k-mesh)
+ *   K^n = (1/N_k) A^n^H Y^n A^n,  A^n_{P mu} = phi_mu^n(r_P)
+ *   E_x = -(1/N_k^2) sum_n sum_PQ Y^n_PQ conj G^n_PQ   (Ha per cell, FP64)
+ *
+ *   ao_pts  [N_k][n_isdf][n_ao] c128: phi_mu^n(r_P)
+ *   occ_pts [N_k][n_isdf][n_occ] c128
+ *   V       [N_k][n_isdf][n_isdf] c128 from exx_coulomb_V
+ *   K       out [N_k][n_ao][n_ao] c128
+ *   Ex      out [1] double (device)
+ */
+exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                       const void* ao_pts, const void* occ_pts, const void* V,
+                       void* K, double* Ex, hipStream_t stream);
+
+/*
+ * exx_build -- one whole K-build: exx_isdf_fit, exx_coulomb_V and
+ * exx_build_K back to back on one stream, with xi, S and V kept in the
+ * handle's scratch. Arguments as above.
+ */
+exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                     const void* psi_grid, const void* occ_pts, const void* ao_pts,
+                     const int32_t* pts, void* K, double* Ex, int32_t* rank,
+                     hipStream_t stream);
+
+/*
+ * exx_select_points -- interpolation points by QR with column pivoting
+ * (Sec. 2.1 after Eq. 5), computed as greedy pivoted Cholesky of the pair
+ * Gram matrix |Gamma(r, r')|^2, Gamma(r, r') = sum_{n,i} psi_in(r) conj
+ * psi_in(r'), in FP64: pivot = argmax of the Schur diagonal (ties to the
+ * smallest index); pivoting stops when the pivot drops below 1e-12 times the
+ * first one, and the remaining slots take the unselected points of highest
+ * density sum_{n,i} |psi_in(r)|^2 (ties to the smallest index).
+ *
+ *   psi_grid [N_k][n_occ][N_g] c128
+ *   pts      out [n_isdf] int32
+ *   n_pivot  out [1] int32: number of points chosen by pivoting
+ */
+exx_status exx_select_points(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
+                             int32_t* pts, int32_t* n_pivot, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EXX_H */

@@ -1,0 +1,203 @@
+"""O2: THC-oo-K exchange build with one occupied-pair ISDF fit per transfer q (oracle).
+
+TEST INFRASTRUCTURE ONLY (see package docstring).
+
+Follows Sec. 2.3 (Eqs. 16-18) and the per-iteration body of Algorithm 2
+(compute xi, FFT xi, M^q, the k-convolved intermediate, K_ij), with the
+per-q fit in the full-Bloch gauge. Notation (orbitals psi_in(r) of k-point n
+on the grid, interpolation points r_P, transfer m with q_m):
+
+1. Gather: Psi^n_{Pi} = psi_in(r_P), X^n_{mu P} = conj phi_mu^n(r_P),
+   G^n = Psi^n Psi^n^H  (G^n_PQ = sum_i psi_in(r_P) conj psi_in(r_Q)).
+2. Fit metric of the least-squares problem (Eqs. 7-8 and 13 restricted to
+   occupied pairs): the pair matrix B_m has one row per (n, i, j),
+   B_m[(n,i,j), P] = e^{-i q_m.r_P} conj psi_in(r_P) psi_{j,n+m}(r_P),
+   and S^m = B_m^H B_m (formed literally).
+3. Right-hand side B_m^H A_m(r) (Eq. 7/13), written through
+   Gamma^n(P, r) = sum_i psi_in(r_P) conj psi_in(r):
+   Z^m_P(r) = e^{i q_m.(r_P - r)} sum_n Gamma^n(P, r) conj Gamma^{n+m}(P, r)
+   with a direct sum over n.
+4. Solve S^m xi^m(r) = Z^m(r) by an FP64 Cholesky factorisation in the given
+   point order; a point whose Schur-complement pivot falls below
+   rel_tol * max_P S_PP is dropped (xi_P = 0).
+5. F^m_P = FFT(xi^m_P); V^m_PQ = (Omega/N_g^2) sum_g v^m(g) F_P conj F_Q
+   (M^q of Eq. 15 by GPW).
+6. Bloch-gauge Coulomb matrix Vb^m_PQ = e^{-i q_m.(r_P - r_Q)} V^m_PQ.
+7. k-convolution (Algorithm 2, X^k line): Y^n = sum_{n'} Vb^{m(n,n')} o G^{n'}
+   by a direct sum.
+8. K^n = (1/N_k) X^n Y^n X^n^H  (Eq. 14 restricted to the oo fit).
+9. E_x = -(1/N_k^2) sum_n sum_PQ Y^n_PQ conj G^n_PQ (Eq. 18, closed shell per
+   cell); also -(1/N_k^2) sum_m Tr(V^m S^m).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+import scipy.linalg as sla
+
+from . import coulomb
+
+
+def cholesky_drop(S: np.ndarray, rel_tol: float = 1e-12):
+    """Cholesky of Hermitian PSD S in the given order, dropping tiny pivots.
+
+    Returns (L, keep): L is lower triangular with zero columns for dropped
+    points, keep[p] says whether point p was retained. The retained block
+    satisfies S[R][:, R] = L[R][:, R] L[R][:, R]^H.
+    """
+    n = S.shape[0]
+    tol = rel_tol * float(np.max(S.diagonal().real))
+    L = np.zeros((n, n), dtype=np.complex128)
+    keep = np.zeros(n, dtype=bool)
+    for p in range(n):
+        col = S[p:, p] - L[p:, :p] @ L[p, :p].conj()
+        d = float(col[0].real)
+        if not (np.isfinite(d) and d > 0.0 and d >= tol):
+            continue
+        keep[p] = True
+        s = np.sqrt(d)
+        L[p, p] = s
+        L[p + 1:, p] = col[1:] / s
+    return L, keep
+
+
+def solve_drop(L: np.ndarray, keep: np.ndarray, Z: np.ndarray) -> np.ndarray:
+    """xi = S_RR^{-1} Z_R on the retained points, zero on dropped points."""
+    R = np.flatnonzero(keep)
+    Lr = L[np.ix_(R, R)]
+    y = sla.solve_triangular(Lr, Z[R], lower=True, check_finite=False)
+    x = sla.solve_triangular(Lr, y, lower=True, trans="C", check_finite=False)
+    xi = np.zeros_like(Z)
+    xi[R] = x
+    return xi
+
+
+def gather(psi: np.ndarray, pts: np.ndarray, ao_pts: np.ndarray):
+    """Psi^n (N_I, n_occ), X^n (N, N_I) and G^n (N_I, N_I) for every k."""
+    nk = psi.shape[0]
+    Psi = np.stack([psi[n][:, pts].T for n in range(nk)])
+    X = ao_pts.conj()
+    G = np.einsum("npi,nqi->npq", Psi, Psi.conj())
+    return Psi, X, G
+
+
+def pair_rows(psi_pts: np.ndarray, kmesh, m: int, phase_P: np.ndarray) -> np.ndarray:
+    """B_m: rows (n, i, j) -> e^{-i q_m.r_P} conj psi_in(r_P) psi_{j,n+m}(r_P)."""
+    nk, nI, no = psi_pts.shape
+    rows = []
+    for n in range(nk):
+        n2 = coulomb.add_index(kmesh, n, m)
+        blk = psi_pts[n].conj().T[:, None, :] * psi_pts[n2].T[None, :, :]
+        rows.append(blk.reshape(no * no, nI) * phase_P[None, :])
+    return np.concatenate(rows, axis=0)
+
+
+def _gamma(Psi_n, psi_n_chunk):
+    return Psi_n @ psi_n_chunk.conj()
+
+
+def coulomb_matrix(L, grid, kmesh, m: int, xi: np.ndarray) -> np.ndarray:
+    """Step 5: V^m_PQ = (Omega/N_g^2) sum_g v^m(g) F_P(g) conj F_Q(g), F_P = FFT(xi_P)."""
+    grid = tuple(int(x) for x in grid)
+    nI, ng = xi.shape
+    omega = float(np.prod(L))
+    F = sfft.fftn(xi.reshape((nI,) + grid), axes=(1, 2, 3), workers=-1).reshape(nI, ng)
+    v = coulomb.kernel(L, grid, kmesh, m).reshape(-1)
+    return (omega / ng ** 2) * ((F * v[None, :]) @ F.conj().T)
+
+
+def bloch_gauge(L, grid, kmesh, m: int, pts, V: np.ndarray) -> np.ndarray:
+    """Step 6: Vb^m_PQ = e^{-i q_m.(r_P - r_Q)} V^m_PQ."""
+    q = coulomb.qvec(L, kmesh, m)
+    ph = np.exp(-1j * (coulomb.positions(L, grid, pts) @ q))
+    return V * (ph[:, None] * ph.conj()[None, :])
+
+
+def contract(kmesh, G: np.ndarray, X: np.ndarray, Vb: np.ndarray):
+    """Steps 7-9: Y^n, K^n and E_x from Vb^m (N_k, N_I, N_I), G^n and X^n."""
+    nk = G.shape[0]
+    Y = np.zeros_like(G)
+    for n in range(nk):
+        for n2 in range(nk):
+            Y[n] += Vb[coulomb.transfer_index(kmesh, n, n2)] * G[n2]
+    K = np.stack([X[n] @ Y[n] @ X[n].conj().T for n in range(nk)]) / nk
+    Ex = -float(np.sum(Y * G.conj()).real) / nk ** 2
+    return Y, K, Ex
+
+
+def thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol=1e-12, keep_intermediates=(),
+             gamma_store_bytes=24 << 30, chunk=1 << 15):
+    """Run O2. Returns a dict with K (N_k, N, N), Ex, Ex_trVS, V, Vb, S, G, Y, rank.
+
+    ``keep_intermediates`` may include "Z" and "xi" to also return those
+    (N_k, N_I, N_g) arrays (small cells only).
+    """
+    L = np.asarray(L, dtype=np.float64)
+    grid = tuple(int(x) for x in grid)
+    kmesh = tuple(int(x) for x in kmesh)
+    pts = np.asarray(pts, dtype=np.int64)
+    nk, no, ng = psi.shape
+    nI = len(pts)
+
+    Psi, X, G = gather(psi, pts, ao_pts)
+    rP = coulomb.positions(L, grid, pts)
+
+    store = nk * nI * ng * 16 <= gamma_store_bytes
+    Gam = None
+    if store:
+        Gam = np.empty((nk, nI, ng), dtype=np.complex128)
+        for n in range(nk):
+            Gam[n] = _gamma(Psi[n], psi[n])
+
+    out = {"G": G, "X": X}
+    S_all = np.zeros((nk, nI, nI), dtype=np.complex128)
+    V_all = np.zeros((nk, nI, nI), dtype=np.complex128)
+    Vb_all = np.zeros((nk, nI, nI), dtype=np.complex128)
+    rank = np.zeros(nk, dtype=np.int64)
+    keep_sets = []
+    kept = {k: np.zeros((nk, nI, ng), dtype=np.complex128) for k in keep_intermediates}
+
+    r_all = coulomb.positions(L, grid)
+    for m in range(nk):
+        q = coulomb.qvec(L, kmesh, m)
+        ph_P = np.exp(-1j * (rP @ q))
+        # step 2: fit metric, literally B^H B
+        B = pair_rows(Psi, kmesh, m, ph_P)
+        S = B.conj().T @ B
+        del B
+        S_all[m] = S
+        Lc, keep = cholesky_drop(S, rel_tol)
+        rank[m] = int(keep.sum())
+        keep_sets.append(keep)
+        # step 3: right-hand side, direct k-sum, chunked over r
+        xi = np.empty((nI, ng), dtype=np.complex128)
+        for c0 in range(0, ng, chunk):
+            c1 = min(ng, c0 + chunk)
+            Z = np.zeros((nI, c1 - c0), dtype=np.complex128)
+            for n in range(nk):
+                n2 = coulomb.add_index(kmesh, n, m)
+                ga = Gam[n, :, c0:c1] if store else _gamma(Psi[n], psi[n][:, c0:c1])
+                gb = Gam[n2, :, c0:c1] if store else _gamma(Psi[n2], psi[n2][:, c0:c1])
+                Z += ga * gb.conj()
+            ph_r = np.exp(-1j * (r_all[c0:c1] @ q))
+            Z *= ph_P.conj()[:, None] * ph_r[None, :]
+            if "Z" in kept:
+                kept["Z"][m, :, c0:c1] = Z
+            # step 4: least-squares solve on the retained points
+            xi[:, c0:c1] = solve_drop(Lc, keep, Z)
+        if "xi" in kept:
+            kept["xi"][m] = xi
+        # steps 5-6: Coulomb matrix, Bloch gauge
+        V_all[m] = coulomb_matrix(L, grid, kmesh, m, xi)
+        del xi
+        Vb_all[m] = bloch_gauge(L, grid, kmesh, m, pts, V_all[m])
+
+    # steps 7-9
+    Y, K, Ex = contract(kmesh, G, X, Vb_all)
+    Ex_trVS = -float(sum(np.trace(V_all[m] @ S_all[m]).real for m in range(nk))) / nk ** 2
+
+    out.update(dict(K=K, Ex=Ex, Ex_trVS=Ex_trVS, V=V_all, Vb=Vb_all, S=S_all, Y=Y,
+                    rank=rank, keep=np.stack(keep_sets)))
+    out.update(kept)
+    return out
