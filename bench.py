@@ -1,0 +1,219 @@
+"""Throughput of the THC-oo-K exchange build (K^k for all k plus E_x) on one GPU.
+
+Workload: the 48-atom four-ring cell (14.0 x 17.8 x 12.9 bohr, C6H6 x 4) on a
+2x2x2 Gamma-centred k-mesh; s + p Gaussians per atom (N = 192), n_occ = 84,
+grid 60x75x54 (N_g = 243000), N_ISDF = 420 points chosen on the GPU by
+pivoted-Cholesky QRCP. Seeded synthetic orbitals; inputs are resident in HBM
+before the timed region. One step = one whole K-build (fit, Coulomb
+matrices, contraction) through the C ABI.
+
+Prints one JSON line. Options: --steps K --warmup W --gpus N (N must be 1)
+--prec f64|f32 (the path reported as `value`; both are timed) --no-cpu.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "K-builds/sec (all k) vs plain FP64 GPU at |ΔE_x|≤1e-5 Ha/cell; MFMA %"
+PEAK = {  # MI355X published dense peaks
+    "hbm_GBs": 8000.0,
+    "fp64_TF": 78.6,
+    "fp32_TF": 157.3,
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_work(cell, n_isdf, prec):
+    """Per-launch algorithmic flops / bytes of each phase (one K-build)."""
+    nk, ng, no, na = cell.N_k, cell.N_g, cell.n_occ, cell.n_ao
+    ni = n_isdf
+    cs = 16 if prec == "f64" else 8
+    return {
+        "gamma": ("flop", 8.0 * nk * ni * no * ng),
+        "kcorr": ("byte", 2.0 * nk * ni * ng * cs),
+        "solve": ("flop", 8.0 * nk * ni * ni * ng),
+        "fft": ("byte", 2.0 * nk * ni * ng * cs),
+        "coulomb": ("flop", 4.0 * nk * ni * ni * ng),
+        "K": ("flop", 8.0 * nk * (na * ni * ni + na * na * ni)),
+    }
+
+
+def roofline(phases, work, prec, steps):
+    """Roofline entry for the phase with the largest time."""
+    best = max((p for p in phases if p in work), key=lambda p: phases[p][0])
+    ms, calls = phases[best]
+    avg_s = ms / max(calls, 1) / 1e3
+    kind, amount = work[best]
+    if kind == "byte":
+        achieved = amount / avg_s / 1e9
+        return best, {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                      "frac": achieved / PEAK["hbm_GBs"], "traffic": None}
+    achieved = amount / avg_s / 1e12
+    peak = PEAK["fp64_TF"] if (best == "solve" or prec == "f64") else PEAK["fp32_TF"]
+    return best, {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                  "frac": achieved / peak, "traffic": None}
+
+
+def cpu_baseline(cell, psi, pts, ao):
+    """The FP64 oracle on a bounded sample: all Gamma^n plus the fit/FFT/Coulomb of one q."""
+    from oracle import thc
+    from oracle._threads import WORKERS
+
+    t0 = time.perf_counter()
+    o = thc.thc_oo_k(cell.L, cell.grid, cell.kmesh, psi, pts, ao, m_subset=[cell.N_k - 1])
+    wall = time.perf_counter() - t0
+    sec = o["seconds"]
+    est = sec["gamma"] + cell.N_k * float(np.mean(sec["per_q"])) + sec["contract"]
+    return {
+        "value": 1.0 / est,
+        "unit": "K-builds/s",
+        "cores": WORKERS,
+        "kind": "oracle",
+        "sample": (f"oracle Gamma^n for all {cell.N_k} k plus steps 2-6 for one of {cell.N_k} "
+                   f"transfers ({wall:.1f} s wall); build time extrapolated as "
+                   f"gamma + N_k * per_q + contract = {est:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", choices=("f64", "f32"), default="f64")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the build is not sharded "
+              "across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    cell = synth.make_config(2)
+    t0 = time.perf_counter()
+    C = synth.orbital_coeffs(cell)
+    psi = synth.orbitals_on_grid(cell, C)
+    log(f"inputs generated in {time.perf_counter() - t0:.1f} s")
+    nk, no, ng, ni, na = cell.N_k, cell.n_occ, cell.N_g, cell.n_isdf, cell.n_ao
+
+    h = exx.Handle(0)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, no, na, ni)
+    t_psi64 = torch.from_numpy(psi).to(dev)
+    t_pts = torch.empty((ni,), dtype=torch.int32, device=dev)
+    t_npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+    t0 = time.perf_counter()
+    exx.exx_select_points(h, c, t_psi64, t_pts, t_npiv)
+    torch.cuda.synchronize()
+    log(f"points selected on the GPU in {time.perf_counter() - t0:.2f} s")
+    pts = t_pts.cpu().numpy().astype(np.int64)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(nk)])
+    t_ao = torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev)
+    t_occ = torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev)
+    t_psi32 = t_psi64.to(torch.complex64)
+
+    results = {}
+    for prec in ("f64", "f32"):
+        p = exx.PREC[prec]
+        t_psi = t_psi64 if prec == "f64" else t_psi32
+        K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+        Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+        rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+
+        def step():
+            exx.exx_build(h, c, p, t_psi, t_occ, t_ao, t_pts, K, Ex, rank)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        log(f"[{prec}] warmup done")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        # per-phase HIP-event timing on the build's stream, separate runs
+        h.set_timing(True)
+        for _ in range(args.steps):
+            step()
+        phases = h.phase_times()
+        h.set_timing(False)
+        log(f"[{prec}] {args.steps} steps in {el:.3f} s; phases(ms/call): " +
+            ", ".join(f"{k}={v[0] / max(v[1], 1):.2f}" for k, v in phases.items()))
+        results[prec] = {
+            "value": args.steps / el,
+            "ms_per_step": el / args.steps * 1e3,
+            "Ex": float(Ex.cpu()[0]),
+            "K": K.cpu().numpy(),
+            "rank": rank.cpu().tolist(),
+            "phases": phases,
+        }
+
+    ref64 = results["f64"]
+    r32 = results["f32"]
+    dEx_32 = abs(r32["Ex"] - ref64["Ex"])
+    dK_32 = float(np.abs(r32["K"] - ref64["K"]).max())
+    # stored oracle values for this workload, when the GPU picked the oracle's points
+    oracle_check = None
+    gpath = os.path.join(ROOT, "tests", "golden", "config2.json")
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath))
+        if gold["pts"] == [int(x) for x in pts]:
+            oracle_check = {"dEx_f64": abs(ref64["Ex"] - gold["Ex"]), "dEx_f32": abs(r32["Ex"] - gold["Ex"])}
+    sel = results[args.prec]
+    work = algorithmic_work(cell, ni, args.prec)
+    dom, roof = roofline(sel["phases"], work, args.prec, args.steps)
+    out = {
+        "metric": METRIC,
+        "value": sel["value"],
+        "unit": "K-builds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sel["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "f64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "THC-oo-K K-build, 48-atom four-ring cell, 2x2x2 k-mesh, N=192, n_occ=84, "
+                        "grid 60x75x54, N_ISDF=420",
+            "N_k": nk, "N_g": ng, "n_occ": no, "n_ao": na, "n_isdf": ni,
+            "prec": args.prec,
+        },
+        "roofline": dict(roof, kernel=dom),
+        "paths": {
+            "f64": {"value": ref64["value"], "ms_per_step": ref64["ms_per_step"], "Ex": ref64["Ex"]},
+            "f32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "Ex": r32["Ex"],
+                    "dEx_vs_f64": dEx_32, "maxdK_vs_f64": dK_32,
+                    "speedup_vs_f64": r32["value"] / ref64["value"]},
+        },
+        "oracle_check": oracle_check,
+        "phases_ms": {k: v[0] / max(v[1], 1) for k, v in sel["phases"].items()},
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(cell, psi, pts, ao)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

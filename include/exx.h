@@ -177,6 +177,24 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec,
 exx_status exx_select_points(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
                              int32_t* pts, int32_t* n_pivot, hipStream_t stream);
 
+/*
+ * Per-phase timing (instrumentation, not part of the method). When enabled,
+ * the library records a pair of HIP events on the call's stream around each
+ * phase of every subsequent call. exx_phase_times synchronises on those
+ * events and returns, per phase, the summed elapsed milliseconds and the
+ * number of recorded intervals since timing was enabled or last read, then
+ * resets the counters.
+ *
+ * Phases: 0 G^n, 1 S^m, 2 Cholesky, 3 S^+ (triangular inverse and W^H W),
+ * 4 Gamma^n, 5 Z^m k-correlation, 6 fit solve, 7 grid FFT, 8 Coulomb
+ * contraction, 9 k-convolution Y^n, 10 K^n, 11 E_x.
+ *
+ *   ms    out [n] double (host), calls out [n] int32 (host), n <= EXX_NPHASE
+ */
+#define EXX_NPHASE 12
+exx_status exx_set_timing(exx_handle_t h, int enable);
+exx_status exx_phase_times(exx_handle_t h, double* ms, int32_t* calls, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,10 +24,11 @@ import numpy as np
 import scipy.fft as sfft
 
 from . import coulomb
+from ._threads import WORKERS
 
 
 def _fft(a, grid):
-    return sfft.fftn(a.reshape((-1,) + tuple(grid)), axes=(1, 2, 3), workers=-1)
+    return sfft.fftn(a.reshape((-1,) + tuple(grid)), axes=(1, 2, 3), workers=WORKERS)
 
 
 def exchange_energy(L, grid, kmesh, psi: np.ndarray) -> float:

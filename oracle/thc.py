@@ -32,11 +32,14 @@ on the grid, interpolation points r_P, transfer m with q_m):
 
 from __future__ import annotations
 
+import time
+
 import numpy as np
 import scipy.fft as sfft
 import scipy.linalg as sla
 
 from . import coulomb
+from ._threads import WORKERS
 
 
 def cholesky_drop(S: np.ndarray, rel_tol: float = 1e-12):
@@ -102,7 +105,7 @@ def coulomb_matrix(L, grid, kmesh, m: int, xi: np.ndarray) -> np.ndarray:
     grid = tuple(int(x) for x in grid)
     nI, ng = xi.shape
     omega = float(np.prod(L))
-    F = sfft.fftn(xi.reshape((nI,) + grid), axes=(1, 2, 3), workers=-1).reshape(nI, ng)
+    F = sfft.fftn(xi.reshape((nI,) + grid), axes=(1, 2, 3), workers=WORKERS).reshape(nI, ng)
     v = coulomb.kernel(L, grid, kmesh, m).reshape(-1)
     return (omega / ng ** 2) * ((F * v[None, :]) @ F.conj().T)
 
@@ -127,12 +130,15 @@ def contract(kmesh, G: np.ndarray, X: np.ndarray, Vb: np.ndarray):
 
 
 def thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol=1e-12, keep_intermediates=(),
-             gamma_store_bytes=24 << 30, chunk=1 << 15):
+             gamma_store_bytes=24 << 30, chunk=1 << 15, m_subset=None):
     """Run O2. Returns a dict with K (N_k, N, N), Ex, Ex_trVS, V, Vb, S, G, Y, rank.
 
     ``keep_intermediates`` may include "Z" and "xi" to also return those
-    (N_k, N_I, N_g) arrays (small cells only).
+    (N_k, N_I, N_g) arrays (small cells only). ``m_subset`` restricts steps
+    2-6 to the listed transfers (timing samples only: K and E_x are then
+    incomplete). ``out["seconds"]`` holds wall-clock seconds per section.
     """
+    t0 = time.perf_counter()
     L = np.asarray(L, dtype=np.float64)
     grid = tuple(int(x) for x in grid)
     kmesh = tuple(int(x) for x in kmesh)
@@ -150,6 +156,7 @@ def thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol=1e-12, keep_intermediates
         for n in range(nk):
             Gam[n] = _gamma(Psi[n], psi[n])
 
+    t_gamma = time.perf_counter() - t0
     out = {"G": G, "X": X}
     S_all = np.zeros((nk, nI, nI), dtype=np.complex128)
     V_all = np.zeros((nk, nI, nI), dtype=np.complex128)
@@ -159,7 +166,9 @@ def thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol=1e-12, keep_intermediates
     kept = {k: np.zeros((nk, nI, ng), dtype=np.complex128) for k in keep_intermediates}
 
     r_all = coulomb.positions(L, grid)
-    for m in range(nk):
+    t_m = []
+    for m in (range(nk) if m_subset is None else m_subset):
+        tm0 = time.perf_counter()
         q = coulomb.qvec(L, kmesh, m)
         ph_P = np.exp(-1j * (rP @ q))
         # step 2: fit metric, literally B^H B
@@ -192,12 +201,16 @@ def thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol=1e-12, keep_intermediates
         V_all[m] = coulomb_matrix(L, grid, kmesh, m, xi)
         del xi
         Vb_all[m] = bloch_gauge(L, grid, kmesh, m, pts, V_all[m])
+        t_m.append(time.perf_counter() - tm0)
 
     # steps 7-9
+    tc0 = time.perf_counter()
     Y, K, Ex = contract(kmesh, G, X, Vb_all)
+    t_contract = time.perf_counter() - tc0
     Ex_trVS = -float(sum(np.trace(V_all[m] @ S_all[m]).real for m in range(nk))) / nk ** 2
 
     out.update(dict(K=K, Ex=Ex, Ex_trVS=Ex_trVS, V=V_all, Vb=Vb_all, S=S_all, Y=Y,
-                    rank=rank, keep=np.stack(keep_sets)))
+                    rank=rank, keep=np.stack(keep_sets),
+                    seconds={"gamma": t_gamma, "per_q": t_m, "contract": t_contract}))
     out.update(kept)
     return out

@@ -1,0 +1,468 @@
+// C ABI entry points: argument checks, scratch layout and the launch sequence
+// of one THC-oo-K exchange build.
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace exx {
+
+Geom make_geom(const exx_cell& c) {
+  Geom g;
+  for (int a = 0; a < 3; ++a) {
+    g.L[a] = c.L[a];
+    g.n[a] = c.grid[a];
+    g.N[a] = c.kmesh[a];
+  }
+  g.nk = c.kmesh[0] * c.kmesh[1] * c.kmesh[2];
+  g.ng = c.grid[0] * c.grid[1] * c.grid[2];
+  g.no = c.n_occ;
+  g.nao = c.n_ao;
+  g.ni = c.n_isdf;
+  g.omega = c.L[0] * c.L[1] * c.L[2];
+  return g;
+}
+
+exx_status fail(exx_context* h, exx_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+exx_status hip_check(exx_context* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return EXX_OK;
+  return fail(h, EXX_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* ws_get(exx_context* h, size_t bytes, exx_status* st) {
+  *st = EXX_OK;
+  if (h->ws.cap >= bytes) return h->ws.base;
+  if (h->ws.base) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      *st = hip_check(h, e, "hipDeviceSynchronize");
+      return nullptr;
+    }
+    (void)hipFree(h->ws.base);
+    h->ws.base = nullptr;
+    h->ws.cap = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *st = fail(h, EXX_ERR_NOMEM, "scratch allocation of " + std::to_string(bytes) + " bytes failed");
+    return nullptr;
+  }
+  h->ws.base = (char*)p;
+  h->ws.cap = bytes;
+  return p;
+}
+
+static hipEvent_t take_event(exx_context* h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+PhaseTimer::PhaseTimer(exx_context* h, int phase, hipStream_t st) : h_(h), phase_(phase), st_(st) {
+  if (!h_->timing) return;
+  a_ = take_event(h_);
+  if (a_ && hipEventRecord(a_, st_) != hipSuccess) a_ = nullptr;
+}
+
+PhaseTimer::~PhaseTimer() {
+  if (!a_) return;
+  hipEvent_t b = take_event(h_);
+  if (!b) return;
+  if (hipEventRecord(b, st_) != hipSuccess) return;
+  h_->recs.push_back({phase_, a_, b});
+}
+
+namespace {
+
+size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+bool smooth235(int n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+exx_status check_cell(exx_context* h, const exx_cell* c, exx_prec prec) {
+  if (!c) return fail(h, EXX_ERR_ARG, "cell is NULL");
+  if (prec != EXX_F64 && prec != EXX_F32 && prec != EXX_BF16)
+    return fail(h, EXX_ERR_ARG, "unknown precision");
+  for (int a = 0; a < 3; ++a) {
+    if (!(c->L[a] > 0.0)) return fail(h, EXX_ERR_SHAPE, "cell edges must be positive");
+    if (c->grid[a] < 2 || c->grid[a] > 128 || !smooth235(c->grid[a]))
+      return fail(h, EXX_ERR_SHAPE, "grid sizes must be 2..128 and 2*3*5-smooth");
+    if (c->kmesh[a] < 1 || c->kmesh[a] > 8) return fail(h, EXX_ERR_SHAPE, "k-mesh sizes must be 1..8");
+  }
+  if (c->n_occ < 1 || c->n_occ > 512) return fail(h, EXX_ERR_SHAPE, "n_occ must be 1..512");
+  if (c->n_ao < 1 || c->n_ao > 4096) return fail(h, EXX_ERR_SHAPE, "n_ao must be 1..4096");
+  if (c->n_isdf < 1 || c->n_isdf > 2048) return fail(h, EXX_ERR_SHAPE, "n_isdf must be 1..2048");
+  Geom g = make_geom(*c);
+  if (g.ni > g.ng) return fail(h, EXX_ERR_SHAPE, "n_isdf exceeds the number of grid points");
+  if (!kcorr_supported(g)) return fail(h, EXX_ERR_UNSUPPORTED, "k-mesh shape not built in");
+  if (!fft_supported(g, prec == EXX_F64))
+    return fail(h, EXX_ERR_UNSUPPORTED, "grid shape not supported by the FFT (n2*n3 <= 8192)");
+  return EXX_OK;
+}
+
+// scratch layout shared by the three calls
+struct Layout {
+  size_t G, Lf, W, Sp, keep, Y, T, epart, cpart, S2, V2, rank2, grid, grid2, total;
+  int nsplit;
+};
+
+Layout layout(const Geom& g, exx_prec prec, bool build) {
+  Layout L;
+  const size_t mat = al(sizeof(double2) * (size_t)g.nk * g.ni * g.ni);
+  const size_t cs = prec == EXX_F64 ? sizeof(double2) : sizeof(float2);
+  size_t o = 0;
+  L.G = o;
+  o += mat;
+  L.Lf = o;
+  o += mat;
+  L.W = o;
+  o += mat;
+  L.Sp = o;
+  o += mat;
+  L.keep = o;
+  o += al(sizeof(int32_t) * (size_t)g.nk * g.ni);
+  L.Y = o;
+  o += mat;
+  L.T = o;
+  o += al(sizeof(double2) * (size_t)g.nk * g.ni * g.nao);
+  L.epart = o;
+  o += al(sizeof(double) * 1024);
+  L.nsplit = coulomb_nsplit(g);
+  L.cpart = o;
+  o += al(coulomb_partial_bytes(g, L.nsplit));
+  L.S2 = o;
+  o += build ? mat : 0;
+  L.V2 = o;
+  o += build ? mat : 0;
+  L.rank2 = o;
+  o += al(sizeof(int32_t) * g.nk);
+  L.grid = o;
+  o += al(cs * (size_t)g.nk * g.ni * g.ng);
+  L.grid2 = o;
+  o += build ? al(cs * (size_t)g.nk * g.ni * g.ng) : 0;
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
+                    const void* psi, const void* occ, const int32_t* pts, void* xi, void* S,
+                    int32_t* rank, hipStream_t st) {
+  double2* G = (double2*)(ws + L.G);
+  double2* Lf = (double2*)(ws + L.Lf);
+  double2* W = (double2*)(ws + L.W);
+  double2* Sp = (double2*)(ws + L.Sp);
+  int32_t* keep = (int32_t*)(ws + L.keep);
+  void* grid = ws + L.grid;
+  const long nn = (long)g.ni * g.ni;
+  hipError_t e;
+  // a0: G^n = Psi^n Psi^n^H (FP64)
+  {
+  PhaseTimer pt(h, PH_GRAM, st);
+  e = gemm<double, double, double, double>(g.ni, g.ni, g.no, g.nk, A_N, occ, g.no,
+                                           (long)g.ni * g.no, B_C, occ, g.no, (long)g.ni * g.no, G,
+                                           g.ni, nn, 1.0, false, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "G gemm");
+  // a2 at the points: S^m = e^{iq(r_P - r_Q)} sum_n G^n o conj G^{n+m}
+  {
+    PhaseTimer pt(h, PH_METRIC, st);
+    e = launch_kcorr<double>(g, tb, G, S, g.ni, pts, true, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "S kcorr");
+  // a3: Cholesky with drop, inverse factor, S^+ = W^H W
+  {
+    PhaseTimer pt(h, PH_CHOL, st);
+    e = hipMemcpyAsync(Lf, S, sizeof(double2) * g.nk * nn, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_check(h, e, "copy S");
+    e = launch_chol_drop(g, Lf, keep, rank, 1e-12, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "cholesky");
+  {
+    PhaseTimer pt(h, PH_PINV, st);
+    e = launch_tri_inv(g, Lf, keep, W, st);
+    if (e != hipSuccess) return hip_check(h, e, "triangular inverse");
+    e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,
+                                             g.ni, nn, Sp, g.ni, nn, 1.0, false, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "S+ gemm");
+  // a1: Gamma^n(P, r)
+  {
+    PhaseTimer pt(h, PH_GAMMA, st);
+    e = launch_gamma<T>(g, occ, psi, grid, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
+  // a2: Z^m in place
+  {
+    PhaseTimer pt(h, PH_KCORR, st);
+    e = launch_kcorr<T>(g, tb, grid, grid, g.ng, pts, false, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "Z kcorr");
+  // a4: xi^m = S^+ Z^m, FP64 arithmetic
+  {
+    PhaseTimer pt(h, PH_SOLVE, st);
+    e = gemm<double, double, T, T>(g.ni, g.ng, g.ni, g.nk, A_N, Sp, g.ni, nn, B_N, grid, g.ng,
+                                   (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, 1.0, false, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "solve gemm");
+  return EXX_OK;
+}
+
+template <typename T>
+exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
+                        const void* xi, const int32_t* pts, void* V, hipStream_t st) {
+  void* F = ws + L.grid;
+  hipError_t e;
+  {
+    PhaseTimer pt(h, PH_FFT, st);
+    e = launch_fft3d<T>(g, tb, xi, F, (long)g.nk * g.ni, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "fft");
+  {
+    PhaseTimer pt(h, PH_COULOMB, st);
+    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "coulomb");
+  return EXX_OK;
+}
+
+exx_status buildK_impl(exx_context* h, const Geom& g, char* ws, const Layout& L, const void* ao,
+                       const void* occ, const void* V, void* K, double* Ex, hipStream_t st) {
+  double2* G = (double2*)(ws + L.G);
+  double2* Y = (double2*)(ws + L.Y);
+  double2* T = (double2*)(ws + L.T);
+  const long nn = (long)g.ni * g.ni;
+  hipError_t e;
+  {
+    PhaseTimer pt(h, PH_GRAM, st);
+    e = gemm<double, double, double, double>(g.ni, g.ni, g.no, g.nk, A_N, occ, g.no,
+                                             (long)g.ni * g.no, B_C, occ, g.no, (long)g.ni * g.no,
+                                             G, g.ni, nn, 1.0, false, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "G gemm");
+  // c1: Y^n = sum_m Vb^m o G^{n+m}
+  {
+    PhaseTimer pt(h, PH_KCONV, st);
+    e = launch_kconv(g, (const double2*)V, G, Y, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "k-convolution");
+  // c2: K^n = (1/N_k) A^H (Y A)
+  PhaseTimer ptk(h, PH_KMAT, st);
+  e = gemm<double, double, double, double>(g.ni, g.nao, g.ni, g.nk, A_N, Y, g.ni, nn, B_N, ao,
+                                           g.nao, (long)g.ni * g.nao, T, g.nao,
+                                           (long)g.ni * g.nao, 1.0, false, st);
+  if (e != hipSuccess) return hip_check(h, e, "Y A gemm");
+  e = gemm<double, double, double, double>(g.nao, g.nao, g.ni, g.nk, A_C, ao, g.nao,
+                                           (long)g.ni * g.nao, B_N, T, g.nao, (long)g.ni * g.nao, K,
+                                           g.nao, (long)g.nao * g.nao, 1.0 / g.nk, false, st);
+  if (e != hipSuccess) return hip_check(h, e, "A^H T gemm");
+  // c3: E_x
+  PhaseTimer pte(h, PH_ENERGY, st);
+  e = launch_energy(g, Y, G, (double*)(ws + L.epart), Ex, st);
+  if (e != hipSuccess) return hip_check(h, e, "energy");
+  return EXX_OK;
+}
+
+exx_status setup(exx_context* h, const exx_cell* cell, exx_prec prec, bool build, Geom* g,
+                 Tables* tb, Layout* L, char** ws, hipStream_t st) {
+  exx_status s = check_cell(h, cell, prec);
+  if (s != EXX_OK) return s;
+  if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  *g = make_geom(*cell);
+  *L = layout(*g, prec, build);
+  *ws = (char*)ws_get(h, L->total, &s);
+  if (s != EXX_OK) return s;
+  return get_tables(h, *g, tb, st);
+}
+
+}  // namespace
+}  // namespace exx
+
+using namespace exx;
+
+extern "C" {
+
+exx_status exx_create(exx_handle_t* h, int device) {
+  if (!h) return EXX_ERR_ARG;
+  *h = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return EXX_ERR_DEVICE;
+  exx_context* c = new (std::nothrow) exx_context();
+  if (!c) return EXX_ERR_NOMEM;
+  c->device = device;
+  *h = c;
+  return EXX_OK;
+}
+
+exx_status exx_destroy(exx_handle_t h) {
+  if (!h) return EXX_ERR_ARG;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  if (h->ws.base) (void)hipFree(h->ws.base);
+  if (h->tables) (void)hipFree(h->tables);
+  if (h->small) (void)hipFree(h->small);
+  for (auto& r : h->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : h->pool) (void)hipEventDestroy(e);
+  delete h;
+  return EXX_OK;
+}
+
+const char* exx_last_error(exx_handle_t h) { return h ? h->err.c_str() : "null handle"; }
+
+exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes) {
+  if (!h || !bytes) return EXX_ERR_ARG;
+  *bytes = h->ws.cap + h->tables_cap + h->small_cap;
+  return EXX_OK;
+}
+
+exx_status exx_isdf_fit(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* psi_grid,
+                        const void* occ_pts, const int32_t* pts, void* xi, void* S, int32_t* rank,
+                        hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!psi_grid || !occ_pts || !pts || !xi || !S || !rank)
+    return fail(h, EXX_ERR_ARG, "exx_isdf_fit: null array argument");
+  Geom g;
+  Tables tb;
+  Layout L;
+  char* ws;
+  exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
+  if (s != EXX_OK) return s;
+  if (prec == EXX_F64)
+    return fit_impl<double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+  return fit_impl<float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+}
+
+exx_status exx_coulomb_V(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* xi,
+                         const int32_t* pts, void* V, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!xi || !pts || !V) return fail(h, EXX_ERR_ARG, "exx_coulomb_V: null array argument");
+  Geom g;
+  Tables tb;
+  Layout L;
+  char* ws;
+  exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
+  if (s != EXX_OK) return s;
+  if (prec == EXX_F64) return coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
+  return coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
+}
+
+exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* ao_pts,
+                       const void* occ_pts, const void* V, void* K, double* Ex,
+                       hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!ao_pts || !occ_pts || !V || !K || !Ex)
+    return fail(h, EXX_ERR_ARG, "exx_build_K: null array argument");
+  Geom g;
+  Tables tb;
+  Layout L;
+  char* ws;
+  exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
+  if (s != EXX_OK) return s;
+  return buildK_impl(h, g, ws, L, ao_pts, occ_pts, V, K, Ex, stream);
+}
+
+exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* psi_grid,
+                     const void* occ_pts, const void* ao_pts, const int32_t* pts, void* K,
+                     double* Ex, int32_t* rank, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!psi_grid || !occ_pts || !ao_pts || !pts || !K || !Ex || !rank)
+    return fail(h, EXX_ERR_ARG, "exx_build: null array argument");
+  Geom g;
+  Tables tb;
+  Layout L;
+  char* ws;
+  exx_status s = setup(h, cell, prec, true, &g, &tb, &L, &ws, stream);
+  if (s != EXX_OK) return s;
+  void* xi = ws + L.grid2;
+  void* S = ws + L.S2;
+  void* V = ws + L.V2;
+  if (prec == EXX_F64) {
+    s = fit_impl<double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
+  } else {
+    s = fit_impl<float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
+  }
+  if (s != EXX_OK) return s;
+  return buildK_impl(h, g, ws, L, ao_pts, occ_pts, V, K, Ex, stream);
+}
+
+exx_status exx_set_timing(exx_handle_t h, int enable) {
+  if (!h) return EXX_ERR_ARG;
+  (void)hipSetDevice(h->device);
+  for (auto& r : h->recs) {
+    (void)hipEventSynchronize(r.b);
+    h->pool.push_back(r.a);
+    h->pool.push_back(r.b);
+  }
+  h->recs.clear();
+  h->timing = enable != 0;
+  return EXX_OK;
+}
+
+exx_status exx_phase_times(exx_handle_t h, double* ms, int32_t* calls, int32_t n) {
+  if (!h || !ms || !calls || n < 0) return EXX_ERR_ARG;
+  (void)hipSetDevice(h->device);
+  for (int i = 0; i < n; ++i) {
+    ms[i] = 0.0;
+    calls[i] = 0;
+  }
+  exx_status st = EXX_OK;
+  for (auto& r : h->recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) st = hip_check(h, e, "phase timing");
+    if (r.phase < n) {
+      ms[r.phase] += (double)t;
+      calls[r.phase] += 1;
+    }
+    h->pool.push_back(r.a);
+    h->pool.push_back(r.b);
+  }
+  h->recs.clear();
+  return st;
+}
+
+exx_status exx_select_points(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
+                             int32_t* pts, int32_t* n_pivot, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!psi_grid || !pts || !n_pivot)
+    return fail(h, EXX_ERR_ARG, "exx_select_points: null array argument");
+  exx_status s = check_cell(h, cell, EXX_F64);
+  if (s != EXX_OK) return s;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  Geom g = make_geom(*cell);
+  void* ws = ws_get(h, select_scratch_bytes(g), &s);
+  if (s != EXX_OK) return s;
+  e = launch_select(g, (const double2*)psi_grid, pts, n_pivot, ws, stream);
+  return hip_check(h, e, "select");
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+// Shared device helpers and internal declarations of the exchange library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/exx.h"
+
+namespace exx {
+
+// ---------------------------------------------------------------------------
+// complex helpers: float2 / double2 storage, arithmetic in the element type
+// ---------------------------------------------------------------------------
+template <typename T> struct c2t;
+template <> struct c2t<double> { using type = double2; };
+template <> struct c2t<float> { using type = float2; };
+template <typename T> using cplx = typename c2t<T>::type;
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T x, T y) {
+  cplx<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x + b.x, a.y + b.y);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x - b.x, a.y - b.y);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) {
+  return mk<T>(a.x, -a.y);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) {
+  return mk<T>(a.x * s, a.y * s);
+}
+// load an element of storage type S and widen/narrow it to compute type T
+template <typename T, typename S>
+__device__ __forceinline__ cplx<T> cload(const cplx<S>* p) {
+  cplx<S> v = *p;
+  return mk<T>((T)v.x, (T)v.y);
+}
+template <typename S, typename T>
+__device__ __forceinline__ void cstore(cplx<S>* p, cplx<T> v) {
+  *p = mk<S>((S)v.x, (S)v.y);
+}
+
+__host__ __device__ __forceinline__ int wrap_sym(int x, int L) {
+  // ((x + floor(L/2)) mod L) - floor(L/2), with a non-negative mod
+  int h = L / 2;
+  int t = (x + h) % L;
+  if (t < 0) t += L;
+  return t - h;
+}
+
+// ---------------------------------------------------------------------------
+// geometry passed to kernels by value
+// ---------------------------------------------------------------------------
+struct Geom {
+  double L[3];
+  int n[3];    // grid
+  int N[3];    // k-mesh
+  int nk, ng, no, nao, ni;
+  double omega;
+};
+
+Geom make_geom(const exx_cell& c);
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace exx
+
+struct exx_context {
+  int device = 0;
+  std::string err;
+  exx::Arena ws;            // grid-sized scratch + small matrices
+  // per-axis root tables e^{-2 pi i t / (N_i n_i)} for the Bloch phases and
+  // twiddle tables for the FFT, cached per geometry
+  void* tables = nullptr;
+  size_t tables_cap = 0;
+  int tab_key[6] = {0, 0, 0, 0, 0, 0};
+  // persistent small buffers for exx_build
+  void* small = nullptr;
+  size_t small_cap = 0;
+  // per-phase timing: recorded (phase, start, stop) events and a free pool
+  bool timing = false;
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace exx {
+
+// status helpers
+exx_status fail(exx_context* h, exx_status s, const std::string& msg);
+exx_status hip_check(exx_context* h, hipError_t e, const char* what);
+
+// scratch: returns pointer to >= bytes of workspace (grown on demand)
+void* ws_get(exx_context* h, size_t bytes, exx_status* st);
+
+enum Phase {
+  PH_GRAM = 0,
+  PH_METRIC,
+  PH_CHOL,
+  PH_PINV,
+  PH_GAMMA,
+  PH_KCORR,
+  PH_SOLVE,
+  PH_FFT,
+  PH_COULOMB,
+  PH_KCONV,
+  PH_KMAT,
+  PH_ENERGY,
+  PH_COUNT
+};
+
+// records events around a phase when timing is enabled on the handle
+class PhaseTimer {
+ public:
+  PhaseTimer(exx_context* h, int phase, hipStream_t st);
+  ~PhaseTimer();
+
+ private:
+  exx_context* h_;
+  int phase_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (each returns hipGetLastError() of its launches)
+// ---------------------------------------------------------------------------
+enum OpA { A_N = 0, A_C = 1 };           // A[i][k]  or conj(A[k][i])
+enum OpB { B_N = 0, B_R = 1, B_C = 2 };  // B[k][j], conj(B[k][j]) or conj(B[j][k])
+
+// C[b] = alpha * opA(A[b]) * opB(B[b]) (+ C[b] if accumulate), complex,
+// computed in type T, with storage types TA, TB, TC.
+template <typename T, typename TA, typename TB, typename TC>
+hipError_t gemm(int M, int N, int K, int batch, OpA oa, const void* A, long lda, long sA, OpB ob,
+                const void* B, long ldb, long sB, void* C, long ldc, long sC, T alpha_re,
+                bool accumulate, hipStream_t st);
+
+// Gamma^n(P, r) = sum_i occ[n][P][i] conj psi[n][i][r]  (fit right-hand side factor)
+template <typename T>
+hipError_t launch_gamma(const Geom& g, const void* occ_pts, const void* psi, void* gam,
+                        hipStream_t st);
+
+// Per-axis phase tables: tab[a][t] = exp(-2 pi i t / (N_a n_a)), t in [0, N_a n_a)
+// FFT twiddles: tw[a][t] = exp(-2 pi i t / n_a)
+struct Tables {
+  const double2* root[3];
+  const double2* tw64[3];
+  const float2* tw32[3];
+};
+exx_status get_tables(exx_context* h, const Geom& g, Tables* t, hipStream_t st);
+
+// k-autocorrelation with Bloch phase:
+// out[m][P][c] = e^{i q_m.(r_P - r_c)} sum_n in[n][P][c] conj in[n+m][P][c]
+// columns c are grid points (cols_are_points false) or the points pts[c].
+template <typename T>
+hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* out, int ncol,
+                        const int32_t* pts, bool cols_are_points, hipStream_t st);
+bool kcorr_supported(const Geom& g);
+
+// Cholesky with pivot drop, triangular inverse, pseudo-inverse S^+
+hipError_t launch_chol_drop(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
+                            double rel_tol, hipStream_t st);
+hipError_t launch_tri_inv(const Geom& g, const double2* Lf, const int32_t* keep, double2* W,
+                          hipStream_t st);
+
+// 3-D FFT of nfun functions (forward); pass 1 reads `in`, writes `out`; pass 2 in place
+template <typename T>
+hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
+                        hipStream_t st);
+bool fft_supported(const Geom& g, bool fp64);
+
+// Coulomb contraction: V^m (Bloch gauge) from F^m
+template <typename T>
+hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
+                          void* partial, int nsplit, double2* V, hipStream_t st);
+size_t coulomb_partial_bytes(const Geom& g, int nsplit);
+int coulomb_nsplit(const Geom& g);
+
+// k-convolution Y^n = sum_m Vb^m o G^{n+m}
+hipError_t launch_kconv(const Geom& g, const double2* Vb, const double2* G, double2* Y,
+                        hipStream_t st);
+// E_x = -(1/N_k^2) sum Re(Y conj G)
+hipError_t launch_energy(const Geom& g, const double2* Y, const double2* G, double* partial,
+                         double* Ex, hipStream_t st);
+
+// point selection kernels
+hipError_t launch_select(const Geom& g, const double2* psi, int32_t* pts, int32_t* n_pivot,
+                         void* scratch, hipStream_t st);
+size_t select_scratch_bytes(const Geom& g);
+
+}  // namespace exx

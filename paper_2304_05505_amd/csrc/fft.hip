@@ -1,0 +1,249 @@
+// 3-D forward FFT of many functions on the cell grid, mixed radix 2/3/4/5,
+// Stockham autosort in LDS. Pass 1 transforms whole (y, z) planes held in LDS
+// (one HBM read and one write per plane); pass 2 transforms x lines for a block
+// of contiguous (y, z) columns.
+#include "common.h"
+
+namespace exx {
+
+namespace {
+
+constexpr int FFT_NT = 256;
+constexpr int FFT_MAXPTS = 8192;  // complex values held in LDS by one workgroup
+constexpr int FFT_CB = 32;        // (y, z) columns per workgroup in pass 2
+
+struct Plan1 {
+  int n;
+  int ns;
+  int r[10];
+};
+
+Plan1 plan_for(int n) {
+  Plan1 p{};
+  p.n = n;
+  int m = n;
+  while (m % 4 == 0 && m != 8 && m / 4 != 2) {
+    p.r[p.ns++] = 4;
+    m /= 4;
+  }
+  const int pr[4] = {4, 2, 3, 5};
+  for (int k = 0; k < 4; ++k)
+    while (m % pr[k] == 0) {
+      p.r[p.ns++] = pr[k];
+      m /= pr[k];
+    }
+  if (m != 1) p.ns = -1;
+  return p;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cplx<T>* v) {
+  if (R == 2) {
+    cplx<T> a = v[0], b = v[1];
+    v[0] = cadd<T>(a, b);
+    v[1] = csub<T>(a, b);
+  } else if (R == 4) {
+    cplx<T> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+    cplx<T> s02 = cadd<T>(a0, a2), d02 = csub<T>(a0, a2);
+    cplx<T> s13 = cadd<T>(a1, a3), d13 = csub<T>(a1, a3);
+    v[0] = cadd<T>(s02, s13);
+    v[2] = csub<T>(s02, s13);
+    // -i * d13 = (d13.y, -d13.x)
+    v[1] = mk<T>(d02.x + d13.y, d02.y - d13.x);
+    v[3] = mk<T>(d02.x - d13.y, d02.y + d13.x);
+  } else if (R == 3) {
+    const T s = (T)0.86602540378443864676372317075294;
+    cplx<T> a0 = v[0], a1 = v[1], a2 = v[2];
+    cplx<T> t = cadd<T>(a1, a2), d = csub<T>(a1, a2);
+    v[0] = cadd<T>(a0, t);
+    cplx<T> m = mk<T>(a0.x - (T)0.5 * t.x, a0.y - (T)0.5 * t.y);
+    // -i s d = (s d.y, -s d.x)
+    v[1] = mk<T>(m.x + s * d.y, m.y - s * d.x);
+    v[2] = mk<T>(m.x - s * d.y, m.y + s * d.x);
+  } else if (R == 5) {
+    const T c1 = (T)0.30901699437494742410229341718282;   // cos(2 pi/5)
+    const T c2 = (T)-0.80901699437494742410229341718282;  // cos(4 pi/5)
+    const T s1 = (T)0.95105651629515357211643933337938;   // sin(2 pi/5)
+    const T s2 = (T)0.58778525229247312916870595463907;   // sin(4 pi/5)
+    cplx<T> a0 = v[0];
+    cplx<T> t1 = cadd<T>(v[1], v[4]), d1 = csub<T>(v[1], v[4]);
+    cplx<T> t2 = cadd<T>(v[2], v[3]), d2 = csub<T>(v[2], v[3]);
+    v[0] = cadd<T>(a0, cadd<T>(t1, t2));
+    cplx<T> m1 = mk<T>(a0.x + c1 * t1.x + c2 * t2.x, a0.y + c1 * t1.y + c2 * t2.y);
+    cplx<T> m2 = mk<T>(a0.x + c2 * t1.x + c1 * t2.x, a0.y + c2 * t1.y + c1 * t2.y);
+    // X1 = m1 - i (s1 d1 + s2 d2); X4 = m1 + i (...)
+    cplx<T> e1 = mk<T>(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+    // X2 = m2 - i (s2 d1 - s1 d2); X3 = m2 + i (...)
+    cplx<T> e2 = mk<T>(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+    v[1] = mk<T>(m1.x + e1.y, m1.y - e1.x);
+    v[4] = mk<T>(m1.x - e1.y, m1.y + e1.x);
+    v[2] = mk<T>(m2.x + e2.y, m2.y - e2.x);
+    v[3] = mk<T>(m2.x - e2.y, m2.y + e2.x);
+  }
+}
+
+// One Stockham stage of radix R on `nlines` lines of length n stored in LDS
+// (element stride es, line stride ls); Ns = product of the radices done so far.
+template <typename T, int R>
+__device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, int es, int ls,
+                                      const cplx<T>* __restrict__ tw) {
+  constexpr int MAXB = (FFT_MAXPTS / R + FFT_NT - 1) / FFT_NT;
+  const int nb = n / R;
+  const int total = nlines * nb;
+  const int tid = threadIdx.x;
+  cplx<T> v[MAXB][R];
+#pragma unroll
+  for (int s = 0; s < MAXB; ++s) {
+    const int b = tid + s * FFT_NT;
+    if (b < total) {
+      const int line = b / nb, j = b % nb;
+      const cplx<T>* src = buf + line * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[s][r] = src[(j + r * nb) * es];
+    }
+  }
+  __syncthreads();
+  const int span = n / R;  // n / (Ns * R) * Ns
+#pragma unroll
+  for (int s = 0; s < MAXB; ++s) {
+    const int b = tid + s * FFT_NT;
+    if (b < total) {
+      const int line = b / nb, j = b % nb;
+      const int jm = j % Ns;
+      const int step = jm * (span / Ns);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[s][r] = cmul<T>(v[s][r], tw[step * r]);
+      dft_small<T, R>(v[s]);
+      const int idxD = (j / Ns) * Ns * R + jm;
+      cplx<T>* dst = buf + line * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[(idxD + r * Ns) * es] = v[s][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void fft_lines(cplx<T>* buf, const Plan1& p, int nlines, int es, int ls,
+                          const cplx<T>* tw) {
+  int Ns = 1;
+  for (int s = 0; s < p.ns; ++s) {
+    const int R = p.r[s];
+    if (R == 4)
+      stage<T, 4>(buf, p.n, Ns, nlines, es, ls, tw);
+    else if (R == 2)
+      stage<T, 2>(buf, p.n, Ns, nlines, es, ls, tw);
+    else if (R == 3)
+      stage<T, 3>(buf, p.n, Ns, nlines, es, ls, tw);
+    else
+      stage<T, 5>(buf, p.n, Ns, nlines, es, ls, tw);
+    Ns *= R;
+  }
+}
+
+// pass 1: one (function, x) plane per workgroup; z lines then y lines
+template <typename T>
+__global__ __launch_bounds__(FFT_NT) void fft_yz_kernel(const cplx<T>* __restrict__ in,
+                                                        cplx<T>* __restrict__ out, Plan1 py,
+                                                        Plan1 pz, const cplx<T>* twy,
+                                                        const cplx<T>* twz) {
+  extern __shared__ char smem_raw[];
+  cplx<T>* buf = (cplx<T>*)smem_raw;
+  const int n2 = py.n, n3 = pz.n, np = n2 * n3;
+  const long off = (long)blockIdx.x * np;
+  for (int e = threadIdx.x; e < np; e += FFT_NT) buf[e] = in[off + e];
+  __syncthreads();
+  fft_lines<T>(buf, pz, n2, 1, n3, twz);
+  fft_lines<T>(buf, py, n3, n3, 1, twy);
+  for (int e = threadIdx.x; e < np; e += FFT_NT) out[off + e] = buf[e];
+}
+
+// pass 2: x lines of FFT_CB contiguous (y, z) columns of one function
+template <typename T>
+__global__ __launch_bounds__(FFT_NT) void fft_x_kernel(cplx<T>* __restrict__ data, Plan1 px,
+                                                       int np, int nblk, const cplx<T>* twx) {
+  extern __shared__ char smem_raw[];
+  cplx<T>* buf = (cplx<T>*)smem_raw;
+  const int n1 = px.n;
+  const long f = blockIdx.x / nblk;
+  const int c0 = (blockIdx.x % nblk) * FFT_CB;
+  const int cw = min(FFT_CB, np - c0);
+  cplx<T>* base = data + f * (long)n1 * np + c0;
+  for (int e = threadIdx.x; e < n1 * FFT_CB; e += FFT_NT) {
+    const int x = e / FFT_CB, c = e % FFT_CB;
+    buf[e] = (c < cw) ? base[(long)x * np + c] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  fft_lines<T>(buf, px, FFT_CB, FFT_CB, 1, twx);
+  for (int e = threadIdx.x; e < n1 * FFT_CB; e += FFT_NT) {
+    const int x = e / FFT_CB, c = e % FFT_CB;
+    if (c < cw) base[(long)x * np + c] = buf[e];
+  }
+}
+
+template <typename T>
+const cplx<T>* twp(const Tables& tb, int a);
+template <>
+const double2* twp<double>(const Tables& tb, int a) {
+  return tb.tw64[a];
+}
+template <>
+const float2* twp<float>(const Tables& tb, int a) {
+  return tb.tw32[a];
+}
+
+}  // namespace
+
+bool fft_supported(const Geom& g, bool fp64) {
+  (void)fp64;
+  for (int a = 0; a < 3; ++a) {
+    if (g.n[a] < 1 || g.n[a] > 128) return false;
+    if (plan_for(g.n[a]).ns < 0) return false;
+  }
+  if (g.n[1] * g.n[2] > FFT_MAXPTS) return false;
+  if (g.n[0] * FFT_CB > FFT_MAXPTS) return false;
+  return true;
+}
+
+template <typename T>
+hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
+                        hipStream_t st) {
+  Plan1 px = plan_for(g.n[0]), py = plan_for(g.n[1]), pz = plan_for(g.n[2]);
+  const int np = g.n[1] * g.n[2];
+  size_t lds1 = (size_t)np * sizeof(cplx<T>);
+  size_t lds2 = (size_t)g.n[0] * FFT_CB * sizeof(cplx<T>);
+  hipError_t e = hipFuncSetAttribute((const void*)fft_yz_kernel<T>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)fft_x_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds2);
+  if (e != hipSuccess) return e;
+  const long nplanes = nfun * g.n[0];
+  for (long p0 = 0; p0 < nplanes; p0 += (1L << 30)) {
+    long cnt = nplanes - p0 < (1L << 30) ? nplanes - p0 : (1L << 30);
+    hipLaunchKernelGGL(fft_yz_kernel<T>, dim3((unsigned)cnt), dim3(FFT_NT), lds1, st,
+                       (const cplx<T>*)in + p0 * np, (cplx<T>*)out + p0 * np, py, pz, twp<T>(tb, 1),
+                       twp<T>(tb, 2));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int nblk = (np + FFT_CB - 1) / FFT_CB;
+  const long nwg = nfun * nblk;
+  const long fper = (1L << 30) / nblk;
+  for (long f0 = 0; f0 < nfun; f0 += fper) {
+    long cnt = nfun - f0 < fper ? nfun - f0 : fper;
+    hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)(cnt * nblk)), dim3(FFT_NT), lds2, st,
+                       (cplx<T>*)out + f0 * (long)g.ng, px, np, nblk, twp<T>(tb, 0));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  (void)nwg;
+  return hipSuccess;
+}
+
+template hipError_t launch_fft3d<double>(const Geom&, const Tables&, const void*, void*, long,
+                                         hipStream_t);
+template hipError_t launch_fft3d<float>(const Geom&, const Tables&, const void*, void*, long,
+                                        hipStream_t);
+
+}  // namespace exx

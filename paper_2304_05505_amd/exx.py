@@ -1,0 +1,253 @@
+"""Thin ctypes binding of libexx.so (argument marshalling only).
+
+Every function takes torch tensors that already live on the GPU, checks
+their dtype, shape and contiguity, and passes raw device pointers plus the
+current HIP stream to the C ABI declared in ``include/exx.h``. All arithmetic
+runs in the library's HIP kernels; if the library is missing this module
+raises at import time instead of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+import torch
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libexx.so"
+
+EXX_F64, EXX_F32, EXX_BF16 = 0, 1, 2
+PREC = {"f64": EXX_F64, "f32": EXX_F32, "bf16": EXX_BF16}
+_STATUS = {
+    0: "EXX_OK",
+    -1: "EXX_ERR_ARG",
+    -2: "EXX_ERR_SHAPE",
+    -3: "EXX_ERR_NOMEM",
+    -4: "EXX_ERR_NOT_PD",
+    -5: "EXX_ERR_NONFINITE",
+    -6: "EXX_ERR_DEVICE",
+    -7: "EXX_ERR_UNSUPPORTED",
+}
+
+EXPORTED = (
+    "exx_create",
+    "exx_destroy",
+    "exx_last_error",
+    "exx_scratch_bytes",
+    "exx_isdf_fit",
+    "exx_coulomb_V",
+    "exx_build_K",
+    "exx_build",
+    "exx_select_points",
+    "exx_set_timing",
+    "exx_phase_times",
+)
+
+PHASES = ("G", "S", "cholesky", "pinv", "gamma", "kcorr", "solve", "fft", "coulomb",
+          "kconv", "K", "energy")
+
+
+class ExxCell(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_double * 3),
+        ("grid", ctypes.c_int32 * 3),
+        ("kmesh", ctypes.c_int32 * 3),
+        ("n_occ", ctypes.c_int32),
+        ("n_ao", ctypes.c_int32),
+        ("n_isdf", ctypes.c_int32),
+    ]
+
+
+class ExxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not _LIB_PATH.exists():
+        raise ImportError(
+            f"{_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+        )
+    lib = ctypes.CDLL(str(_LIB_PATH))
+    vp, i32p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)
+    cellp = ctypes.POINTER(ExxCell)
+    sig = {
+        "exx_create": ([ctypes.POINTER(vp), ctypes.c_int], ctypes.c_int),
+        "exx_destroy": ([vp], ctypes.c_int),
+        "exx_last_error": ([vp], ctypes.c_char_p),
+        "exx_scratch_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "exx_isdf_fit": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "exx_coulomb_V": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
+        "exx_build_K": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "exx_build": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "exx_select_points": ([vp, cellp, vp, vp, vp, vp], ctypes.c_int),
+        "exx_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "exx_phase_times": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.c_int32], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    del i32p
+    return lib
+
+
+_lib = _load()
+
+
+def library_path() -> str:
+    return str(_LIB_PATH)
+
+
+def make_cell(L, grid, kmesh, n_occ, n_ao, n_isdf) -> ExxCell:
+    c = ExxCell()
+    for i in range(3):
+        c.L[i] = float(L[i])
+        c.grid[i] = int(grid[i])
+        c.kmesh[i] = int(kmesh[i])
+    c.n_occ, c.n_ao, c.n_isdf = int(n_occ), int(n_ao), int(n_isdf)
+    return c
+
+
+def _nk(c: ExxCell) -> int:
+    return c.kmesh[0] * c.kmesh[1] * c.kmesh[2]
+
+
+def _ng(c: ExxCell) -> int:
+    return c.grid[0] * c.grid[1] * c.grid[2]
+
+
+def _ptr(t: torch.Tensor, name: str, dtype, shape, device) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _grid_dtype(prec: int):
+    return torch.complex128 if prec == EXX_F64 else torch.complex64
+
+
+class Handle:
+    """Owns an exx_handle_t bound to one GPU."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        st = _lib.exx_create(ctypes.byref(h), int(device))
+        if st != 0:
+            raise ExxError(st, f"exx_create(device={device}) failed")
+        self._h = h
+        self.device = torch.device("cuda", int(device))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.exx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != 0:
+            raise ExxError(st, _lib.exx_last_error(self._h).decode())
+
+    @property
+    def raw(self):
+        return self._h
+
+    def set_timing(self, enable: bool):
+        self._check(_lib.exx_set_timing(self._h, 1 if enable else 0))
+
+    def phase_times(self) -> dict:
+        """{phase: (total_ms, calls)} since timing was enabled or last read."""
+        n = len(PHASES)
+        ms = (ctypes.c_double * n)()
+        calls = (ctypes.c_int32 * n)()
+        self._check(_lib.exx_phase_times(self._h, ms, calls, n))
+        return {PHASES[i]: (ms[i], calls[i]) for i in range(n)}
+
+    def scratch_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        self._check(_lib.exx_scratch_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+
+def exx_isdf_fit(h: Handle, cell: ExxCell, prec: int, psi_grid, occ_pts, pts, xi, S, rank):
+    nk, ng, ni, no = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ
+    d = h.device
+    gd = _grid_dtype(prec)
+    args = (
+        _ptr(psi_grid, "psi_grid", gd, (nk, no, ng), d),
+        _ptr(occ_pts, "occ_pts", torch.complex128, (nk, ni, no), d),
+        _ptr(pts, "pts", torch.int32, (ni,), d),
+        _ptr(xi, "xi", gd, (nk, ni, ng), d),
+        _ptr(S, "S", torch.complex128, (nk, ni, ni), d),
+        _ptr(rank, "rank", torch.int32, (nk,), d),
+    )
+    h._check(_lib.exx_isdf_fit(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
+
+
+def exx_coulomb_V(h: Handle, cell: ExxCell, prec: int, xi, pts, V):
+    nk, ng, ni = _nk(cell), _ng(cell), cell.n_isdf
+    d = h.device
+    args = (
+        _ptr(xi, "xi", _grid_dtype(prec), (nk, ni, ng), d),
+        _ptr(pts, "pts", torch.int32, (ni,), d),
+        _ptr(V, "V", torch.complex128, (nk, ni, ni), d),
+    )
+    h._check(_lib.exx_coulomb_V(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
+
+
+def exx_build_K(h: Handle, cell: ExxCell, prec: int, ao_pts, occ_pts, V, K, Ex):
+    nk, ni, no, na = _nk(cell), cell.n_isdf, cell.n_occ, cell.n_ao
+    d = h.device
+    args = (
+        _ptr(ao_pts, "ao_pts", torch.complex128, (nk, ni, na), d),
+        _ptr(occ_pts, "occ_pts", torch.complex128, (nk, ni, no), d),
+        _ptr(V, "V", torch.complex128, (nk, ni, ni), d),
+        _ptr(K, "K", torch.complex128, (nk, na, na), d),
+        _ptr(Ex, "Ex", torch.float64, (1,), d),
+    )
+    h._check(_lib.exx_build_K(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
+
+
+def exx_build(h: Handle, cell: ExxCell, prec: int, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank):
+    nk, ng, ni, no, na = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ, cell.n_ao
+    d = h.device
+    args = (
+        _ptr(psi_grid, "psi_grid", _grid_dtype(prec), (nk, no, ng), d),
+        _ptr(occ_pts, "occ_pts", torch.complex128, (nk, ni, no), d),
+        _ptr(ao_pts, "ao_pts", torch.complex128, (nk, ni, na), d),
+        _ptr(pts, "pts", torch.int32, (ni,), d),
+        _ptr(K, "K", torch.complex128, (nk, na, na), d),
+        _ptr(Ex, "Ex", torch.float64, (1,), d),
+        _ptr(rank, "rank", torch.int32, (nk,), d),
+    )
+    h._check(_lib.exx_build(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
+
+
+def exx_select_points(h: Handle, cell: ExxCell, psi_grid, pts, n_pivot):
+    nk, ng, ni, no = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ
+    d = h.device
+    args = (
+        _ptr(psi_grid, "psi_grid", torch.complex128, (nk, no, ng), d),
+        _ptr(pts, "pts", torch.int32, (ni,), d),
+        _ptr(n_pivot, "n_pivot", torch.int32, (1,), d),
+    )
+    h._check(_lib.exx_select_points(h.raw, ctypes.byref(cell), *args, _stream(d)))

@@ -1,0 +1,118 @@
+"""Full-size parity on the benchmark workload (48-atom four-ring cell, 2x2x2 mesh,
+N = 192, n_occ = 84, grid 60x75x54, N_ISDF = 420), in the launch configuration
+the benchmark times (exx_build), against stored FP64 oracle values written by
+tests/golden/make_golden.py, plus properties that hold at any size.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+
+from gpu_helpers import from_cplx_list, load_golden
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    gold = load_golden("config2.json")
+    cell = synth.make_config(2)
+    C = synth.orbital_coeffs(cell)
+    psi = synth.orbitals_on_grid(cell, C)
+    pts = np.asarray(gold["pts"], dtype=np.int64)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, cell.n_isdf)
+    t = {
+        "psi": torch.from_numpy(psi).to(dev),
+        "occ": torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev),
+        "ao": torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+        "pts": torch.from_numpy(pts.astype(np.int32)).to(dev),
+    }
+    return dict(gold=gold, cell=cell, C=C, psi=psi, pts=pts, h=h, c=c, t=t, exx=exx, torch=torch)
+
+
+def _build(f, prec):
+    torch, exx, cell = f["torch"], f["exx"], f["cell"]
+    dev = torch.device("cuda", 0)
+    t = f["t"]
+    psi = t["psi"] if prec == "f64" else t["psi"].to(torch.complex64)
+    K = torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128, device=dev)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((cell.N_k,), dtype=torch.int32, device=dev)
+    exx.exx_build(f["h"], f["c"], exx.PREC[prec], psi, t["occ"], t["ao"], t["pts"], K, Ex, rank)
+    torch.cuda.synchronize()
+    return K.cpu().numpy(), float(Ex.cpu()[0]), rank.cpu().numpy()
+
+
+def test_full_size_fp64_build_matches_oracle(full):
+    gold = full["gold"]
+    K, Ex, rank = _build(full, "f64")
+    tol = 64 * EPS64 * max(gold["cond_S"])
+    print(f"Ex gpu {Ex:.12f} oracle {gold['Ex']:.12f} tol(rel) {tol:.1e}")
+    assert rank.tolist() == gold["rank"]
+    assert abs(Ex - gold["Ex"]) <= tol * abs(gold["Ex"])
+    idx = np.asarray(gold["K_idx"])
+    ref = from_cplx_list(gold["K_val"])
+    got = K[idx[:, 0], idx[:, 1], idx[:, 2]]
+    assert np.abs(got - ref).max() <= tol * gold["maxabs_K"]
+    assert np.abs(np.diagonal(K[0]) - from_cplx_list(gold["K0_diag"])).max() <= tol * gold["maxabs_K"]
+    # properties at full size: Hermitian K^k, and E_x = -(1/N_k) sum_k Tr(C^H K C)
+    for n in range(K.shape[0]):
+        assert np.abs(K[n] - K[n].conj().T).max() <= 1e-12 * np.abs(K[n]).max()
+    C = full["C"]
+    E_K = -sum(np.trace(C[n].conj().T @ K[n] @ C[n]).real for n in range(K.shape[0])) / K.shape[0]
+    assert abs(E_K - Ex) <= tol * abs(Ex)
+
+
+def test_full_size_fp64_coulomb_samples(full):
+    torch, exx, cell = full["torch"], full["exx"], full["cell"]
+    gold = full["gold"]
+    dev = torch.device("cuda", 0)
+    t = full["t"]
+    nk, ni, ng = cell.N_k, cell.n_isdf, cell.N_g
+    xi = torch.empty((nk, ni, ng), dtype=torch.complex128, device=dev)
+    S = torch.empty((nk, ni, ni), dtype=torch.complex128, device=dev)
+    V = torch.empty((nk, ni, ni), dtype=torch.complex128, device=dev)
+    rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+    exx.exx_isdf_fit(full["h"], full["c"], exx.EXX_F64, t["psi"], t["occ"], t["pts"], xi, S, rank)
+    exx.exx_coulomb_V(full["h"], full["c"], exx.EXX_F64, xi, t["pts"], V)
+    torch.cuda.synchronize()
+    del xi
+    tol = 64 * EPS64 * max(gold["cond_S"])
+    idx = np.asarray(gold["Vb_idx"])
+    Vs = V.cpu().numpy()[idx[:, 0], idx[:, 1], idx[:, 2]]
+    Ss = S.cpu().numpy()[idx[:, 0], idx[:, 1], idx[:, 2]]
+    assert np.abs(Vs - from_cplx_list(gold["Vb_val"])).max() <= tol * gold["maxabs_Vb"]
+    sref = from_cplx_list(gold["S_val"])
+    assert np.abs(Ss - sref).max() <= 1e-13 * np.abs(sref).max()
+
+
+def test_full_size_fp32_error_report(full):
+    gold = full["gold"]
+    K, Ex, rank = _build(full, "f32")
+    idx = np.asarray(gold["K_idx"])
+    dK = float(np.abs(K[idx[:, 0], idx[:, 1], idx[:, 2]] - from_cplx_list(gold["K_val"])).max())
+    dE = abs(Ex - gold["Ex"])
+    print(f"f32 full size: |dEx| {dE:.3e} Ha/cell, max|dK| (sampled) {dK:.3e}")
+    assert rank.tolist() == gold["rank"]
+    assert dE <= 1e-3 and dK <= 1e-3
+
+
+def test_full_size_point_selection(full):
+    torch, exx, cell = full["torch"], full["exx"], full["cell"]
+    dev = torch.device("cuda", 0)
+    pts = torch.empty((cell.n_isdf,), dtype=torch.int32, device=dev)
+    npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+    exx.exx_select_points(full["h"], full["c"], full["t"]["psi"], pts, npiv)
+    torch.cuda.synchronize()
+    assert int(npiv.cpu()[0]) == full["gold"]["n_pivot"]
+    assert pts.cpu().numpy().tolist() == full["gold"]["pts"]

@@ -1,0 +1,111 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 tolerance. Both sides compute the same quantities in FP64 but solve the
+fit differently (GPU: explicit pseudo-inverse from the inverted Cholesky
+factor; oracle: two triangular solves) and sum in different orders. The
+forward error of either solve is bounded by ~cond(S^m) * eps64 relative, so
+every comparison uses  tol = 64 * eps64 * max_m cond(S^m_RR)  relative to the
+largest entry of the compared array (floor 1e-12); E_x is compared relative
+to |E_x|. Integer outputs (ranks) must match exactly.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import select, thc
+
+from gpu_helpers import inputs, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+
+
+def _tol(o):
+    conds = []
+    for m in range(o["S"].shape[0]):
+        R = np.flatnonzero(o["keep"][m])
+        conds.append(np.linalg.cond(o["S"][m][np.ix_(R, R)]))
+    return max(1e-12, 64 * EPS64 * max(conds))
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+CELLS = {
+    # name: (factory, n_isdf override)
+    "gamma-config1": lambda: synth.make_config(1),
+    "k222-ragged": lambda: synth.make_random_cell((6.0, 6.5, 7.0), 2, (12, 15, 10), (2, 2, 2), 3, 30,
+                                                  (11, 1, 1)),
+    "k321": lambda: synth.make_random_cell((5.0, 6.0, 7.5), 3, (16, 18, 20), (3, 2, 1), 5, 100,
+                                           (11, 2, 1)),
+    "k333": lambda: synth.make_random_cell((5.0, 5.0, 5.0), 2, (10, 12, 9), (3, 3, 3), 2, 40,
+                                           (11, 3, 1)),
+    "k444": lambda: synth.make_random_cell((5.0, 5.0, 5.0), 2, (8, 8, 8), (4, 4, 4), 2, 30,
+                                           (11, 4, 1)),
+    "k211": lambda: synth.make_random_cell((6.0, 5.0, 5.0), 2, (12, 10, 10), (2, 1, 1), 3, 33,
+                                           (11, 5, 1)),
+    "k121": lambda: synth.make_random_cell((5.0, 6.0, 5.0), 2, (10, 12, 10), (1, 2, 1), 3, 33,
+                                           (11, 6, 1)),
+    "k112": lambda: synth.make_random_cell((5.0, 5.0, 6.0), 2, (10, 10, 12), (1, 1, 2), 3, 33,
+                                           (11, 7, 1)),
+    "k221": lambda: synth.make_random_cell((5.0, 5.0, 6.0), 2, (10, 10, 12), (2, 2, 1), 3, 20,
+                                           (11, 8, 1)),
+    "k123": lambda: synth.make_random_cell((5.0, 5.0, 6.0), 2, (10, 10, 12), (1, 2, 3), 2, 45,
+                                           (11, 9, 1)),
+}
+
+
+def _oracle(cell, psi, pts, ao):
+    return thc.thc_oo_k(cell.L, cell.grid, cell.kmesh, psi, pts, ao, keep_intermediates=("xi",))
+
+
+@pytest.mark.parametrize("name", list(CELLS))
+def test_fp64_stages_match_oracle(name, gpu):
+    cell = CELLS[name]()
+    base = inputs(cell)
+    pts, _ = select.select_points(base["psi"], cell.n_isdf)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    o = _oracle(cell, base["psi"], pts, ao)
+    g = run_gpu(cell, base["psi"], pts, ao, "f64")
+    tol = _tol(o)
+    print(f"{name}: tol {tol:.2e}")
+    assert np.array_equal(g["rank"], o["rank"])
+    assert _rel(g["S"], o["S"]) <= 1e-13
+    assert _rel(g["xi"], o["xi"]) <= tol
+    assert _rel(g["V"], o["Vb"]) <= tol
+    assert _rel(g["K"], o["K"]) <= tol
+    assert abs(g["Ex"] - o["Ex"]) <= tol * abs(o["Ex"])
+
+
+def test_fused_build_equals_stages(gpu):
+    cell = CELLS["k222-ragged"]()
+    base = inputs(cell)
+    pts, _ = select.select_points(base["psi"], cell.n_isdf)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    a = run_gpu(cell, base["psi"], pts, ao, "f64", stages=True)
+    b = run_gpu(cell, base["psi"], pts, ao, "f64", stages=False)
+    assert np.array_equal(a["K"], b["K"])
+    assert a["Ex"] == b["Ex"]
+    assert np.array_equal(a["rank"], b["rank"])
+
+
+@pytest.mark.parametrize("name", ["gamma-config1", "k222-ragged", "k333"])
+def test_fp32_mode_error_report(name, gpu):
+    """Mixed mode: bulk FP32, fit solve and E_x in FP64. Error reported and bounded."""
+    cell = CELLS[name]()
+    base = inputs(cell)
+    pts, _ = select.select_points(base["psi"], cell.n_isdf)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    o = _oracle(cell, base["psi"], pts, ao)
+    g = run_gpu(cell, base["psi"], pts, ao, "f32")
+    dE = abs(g["Ex"] - o["Ex"])
+    dK = float(np.abs(g["K"] - o["K"]).max())
+    print(f"{name}: f32 |dEx| {dE:.3e} (rel {dE / abs(o['Ex']):.2e}) max|dK| {dK:.3e}")
+    assert np.array_equal(g["rank"], o["rank"])
+    # FP32 data carries ~1e-7 relative error, amplified at most by cond(S)
+    cond_tol = _tol(o) / (64 * EPS64) * 1e-6
+    assert dE <= max(1e-5, cond_tol) * abs(o["Ex"])
+    assert dK <= max(1e-4, cond_tol) * np.abs(o["K"]).max()
