@@ -69,12 +69,18 @@ typedef enum {
   EXX_ERR_UNSUPPORTED = -7  /* precision or size not built in */
 } exx_status;
 
-/* Bulk arithmetic type. G^n, S^m, the Cholesky factorisation, the fit solve
- * and E_x are FP64 in every mode; EXX_F32 runs the grid-sized GEMMs, the
- * k-DFT step, the FFTs and the Coulomb contraction in FP32 (c64 storage);
- * EXX_BF16 additionally rounds the operands of the Coulomb contraction to
- * bfloat16 (FP32 accumulation). */
-typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2 } exx_prec;
+/* Arithmetic precision of the build. G^n, S^m, the Cholesky factorisation,
+ * the pseudo-inverse, the k-convolution, K^n and E_x are FP64 in every mode.
+ *   EXX_F64    everything FP64; psi_grid and xi are c128.
+ *   EXX_F32    the grid-sized fit GEMM (Gamma^n) and the k-correlation Z^m
+ *              run in FP32 (psi_grid and xi c64); the fit solve applies the
+ *              FP64 pseudo-inverse in FP64 arithmetic; FFT and Coulomb
+ *              contraction in FP32 on the matrix cores, FP32 accumulation
+ *              flushed into FP64 every 64 grid points.
+ *   EXX_BF16   reserved (not built in: EXX_ERR_UNSUPPORTED).
+ *   EXX_MIXED  the whole fit in FP64 (psi_grid c128), xi stored c64, FFT and
+ *              Coulomb contraction in FP32 as in EXX_F32. */
+typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 } exx_prec;
 
 typedef struct {
   double L[3];       /* orthorhombic cell edges, bohr */
@@ -110,10 +116,10 @@ exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes);
  * pivot is below 1e-12 * max_P S^m_PP is dropped and gets xi_P = 0 -- and
  * solves S^m xi^m(r) = Z^m(r) on every grid point.
  *
- *   psi_grid [N_k][n_occ][N_g]    c128 (EXX_F64) or c64 (other modes)
+ *   psi_grid [N_k][n_occ][N_g]    c128 (EXX_F64, EXX_MIXED) or c64 (EXX_F32)
  *   occ_pts  [N_k][n_isdf][n_occ] c128: psi_in(r_P), used for G^n and S^m
  *   pts      [n_isdf] int32 flat grid indices of the points, distinct
- *   xi       out [N_k][n_isdf][N_g], same complex type as psi_grid
+ *   xi       out [N_k][n_isdf][N_g], c128 (EXX_F64) or c64 (other modes)
  *   S        out [N_k][n_isdf][n_isdf] c128, full Hermitian S^m
  *   rank     out [N_k] int32: retained points per q
  */

@@ -2,6 +2,7 @@
 // of one THC-oo-K exchange build.
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "common.h"
 
@@ -96,7 +97,7 @@ bool smooth235(int n) {
 
 exx_status check_cell(exx_context* h, const exx_cell* c, exx_prec prec) {
   if (!c) return fail(h, EXX_ERR_ARG, "cell is NULL");
-  if (prec != EXX_F64 && prec != EXX_F32 && prec != EXX_BF16)
+  if (prec != EXX_F64 && prec != EXX_F32 && prec != EXX_BF16 && prec != EXX_MIXED)
     return fail(h, EXX_ERR_ARG, "unknown precision");
   for (int a = 0; a < 3; ++a) {
     if (!(c->L[a] > 0.0)) return fail(h, EXX_ERR_SHAPE, "cell edges must be positive");
@@ -117,14 +118,16 @@ exx_status check_cell(exx_context* h, const exx_cell* c, exx_prec prec) {
 
 // scratch layout shared by the three calls
 struct Layout {
-  size_t G, Lf, W, Sp, keep, Y, T, epart, cpart, S2, V2, rank2, grid, grid2, total;
+  size_t G, Lf, W, Sp, keep, Y, T, epart, cpart, S2, V2, rank2, tol, Tinv, grid, grid2, total;
   int nsplit;
 };
 
 Layout layout(const Geom& g, exx_prec prec, bool build) {
   Layout L;
   const size_t mat = al(sizeof(double2) * (size_t)g.nk * g.ni * g.ni);
-  const size_t cs = prec == EXX_F64 ? sizeof(double2) : sizeof(float2);
+  // Gamma/Z (and F) buffer: FP64 unless the fit itself runs in FP32; xi: FP64 only in EXX_F64
+  const size_t cs = (prec == EXX_F64 || prec == EXX_MIXED) ? sizeof(double2) : sizeof(float2);
+  const size_t cx = prec == EXX_F64 ? sizeof(double2) : sizeof(float2);
   size_t o = 0;
   L.G = o;
   o += mat;
@@ -151,15 +154,20 @@ Layout layout(const Geom& g, exx_prec prec, bool build) {
   o += build ? mat : 0;
   L.rank2 = o;
   o += al(sizeof(int32_t) * g.nk);
+  L.tol = o;
+  o += al(sizeof(double) * g.nk);
+  L.Tinv = o;
+  o += al(sizeof(double2) * (size_t)g.nk * 32 * g.ni);
   L.grid = o;
   o += al(cs * (size_t)g.nk * g.ni * g.ng);
   L.grid2 = o;
-  o += build ? al(cs * (size_t)g.nk * g.ni * g.ng) : 0;
+  o += build ? al(cx * (size_t)g.nk * g.ni * g.ng) : 0;
   L.total = o;
   return L;
 }
 
-template <typename T>
+// TF: type of Gamma^n / Z^m (and of psi_grid); TX: storage type of xi
+template <typename TF, typename TX>
 exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                     const void* psi, const void* occ, const int32_t* pts, void* xi, void* S,
                     int32_t* rank, hipStream_t st) {
@@ -190,12 +198,12 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
     PhaseTimer pt(h, PH_CHOL, st);
     e = hipMemcpyAsync(Lf, S, sizeof(double2) * g.nk * nn, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_check(h, e, "copy S");
-    e = launch_chol_drop(g, Lf, keep, rank, 1e-12, st);
+    e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "cholesky");
   {
     PhaseTimer pt(h, PH_PINV, st);
-    e = launch_tri_inv(g, Lf, keep, W, st);
+    e = launch_tri_inv_blocked(g, Lf, keep, W, (double2*)(ws + L.Tinv), st);
     if (e != hipSuccess) return hip_check(h, e, "triangular inverse");
     e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,
                                              g.ni, nn, Sp, g.ni, nn, 1.0, false, st);
@@ -204,20 +212,25 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   // a1: Gamma^n(P, r)
   {
     PhaseTimer pt(h, PH_GAMMA, st);
-    e = launch_gamma<T>(g, occ, psi, grid, st);
+    if (std::is_same<TF, double>::value)
+      e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
+                                        psi, g.ng, (long)g.no * g.ng, grid, g.ng,
+                                        (long)g.ni * g.ng, st);
+    else
+      e = launch_gamma<TF>(g, occ, psi, grid, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
   // a2: Z^m in place
   {
     PhaseTimer pt(h, PH_KCORR, st);
-    e = launch_kcorr<T>(g, tb, grid, grid, g.ng, pts, false, st);
+    e = launch_kcorr<TF>(g, tb, grid, grid, g.ng, pts, false, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "Z kcorr");
   // a4: xi^m = S^+ Z^m, FP64 arithmetic
   {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = gemm<double, double, T, T>(g.ni, g.ng, g.ni, g.nk, A_N, Sp, g.ni, nn, B_N, grid, g.ng,
-                                   (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, 1.0, false, st);
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, false, grid, g.ng,
+                            (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
   return EXX_OK;
@@ -349,8 +362,10 @@ exx_status exx_isdf_fit(exx_handle_t h, const exx_cell* cell, exx_prec prec, con
   exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
   if (s != EXX_OK) return s;
   if (prec == EXX_F64)
-    return fit_impl<double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-  return fit_impl<float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+    return fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+  if (prec == EXX_MIXED)
+    return fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+  return fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
 }
 
 exx_status exx_coulomb_V(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* xi,
@@ -401,10 +416,13 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   void* S = ws + L.S2;
   void* V = ws + L.V2;
   if (prec == EXX_F64) {
-    s = fit_impl<double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+    s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
     if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
+  } else if (prec == EXX_MIXED) {
+    s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
   } else {
-    s = fit_impl<float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+    s = fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
     if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
   }
   if (s != EXX_OK) return s;

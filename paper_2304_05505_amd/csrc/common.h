@@ -167,6 +167,13 @@ hipError_t gemm(int M, int N, int K, int batch, OpA oa, const void* A, long lda,
                 const void* B, long ldb, long sB, void* C, long ldc, long sC, T alpha_re,
                 bool accumulate, hipStream_t st);
 
+// C[b] = A[b] * op(B[b]) on the matrix cores in FP64: A (M x K) c128, B (K x N) and
+// C (M x N) row-major with storage types TB, TC; op = conj if conjB.
+template <typename TB, typename TC>
+hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                         bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                         hipStream_t st);
+
 // Gamma^n(P, r) = sum_i occ[n][P][i] conj psi[n][i][r]  (fit right-hand side factor)
 template <typename T>
 hipError_t launch_gamma(const Geom& g, const void* occ_pts, const void* psi, void* gam,
@@ -189,11 +196,12 @@ hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* o
                         const int32_t* pts, bool cols_are_points, hipStream_t st);
 bool kcorr_supported(const Geom& g);
 
-// Cholesky with pivot drop, triangular inverse, pseudo-inverse S^+
-hipError_t launch_chol_drop(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
-                            double rel_tol, hipStream_t st);
-hipError_t launch_tri_inv(const Geom& g, const double2* Lf, const int32_t* keep, double2* W,
-                          hipStream_t st);
+// Blocked Cholesky with pivot drop (A: S^m in, L in the lower triangle out;
+// tol: [N_k] scratch) and blocked inverse W = L^{-1} (T: [N_k][32][N_I] scratch)
+hipError_t launch_chol_blocked(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
+                               double* tol, double rel_tol, hipStream_t st);
+hipError_t launch_tri_inv_blocked(const Geom& g, const double2* Lf, const int32_t* keep,
+                                  double2* W, double2* T, hipStream_t st);
 
 // 3-D FFT of nfun functions (forward); pass 1 reads `in`, writes `out`; pass 2 in place
 template <typename T>

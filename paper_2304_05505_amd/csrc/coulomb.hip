@@ -113,6 +113,161 @@ __global__ __launch_bounds__(NT) void coulomb_partial_kernel(const cplx<T>* __re
   }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core version of the partial contraction. A lane (row li = lane % 16,
+// group gq = lane / 16) loads 4 consecutive grid values of its row, so the k
+// index of MFMA step t is g0 + 4 gq + t for both operands (the k order of a
+// sum is free). X = v(g) F_P (rows P), Y = conj F_Q (rows Q):
+//   Re += Re X Re F_Q + Im X Im F_Q,  Im += Im X Re F_Q - Re X Im F_Q.
+// FP64 storage: v_mfma_f64_16x16x4_f64. FP32 storage: v_mfma_f32_16x16x4_f32
+// whose FP32 accumulators are flushed into FP64 every FLUSH grid points.
+// ---------------------------------------------------------------------------
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int MW = 2;       // 16-blocks per wave in each direction (wave tile 32 x 32)
+constexpr int MTILE = 64;   // workgroup tile (2 x 2 waves)
+constexpr int FLUSH = 64;   // FP32 accumulation length before the FP64 flush
+
+__device__ __forceinline__ double kernel_v(const CoulArgs& a, int m1, int m2, int m3, long g) {
+  const int n23 = a.n[1] * a.n[2];
+  const int g1 = (int)(g / n23), g2 = (int)((g / a.n[2]) % a.n[1]), g3 = (int)(g % a.n[2]);
+  const int k1 = wrap_sym(a.N[0] * g1 + m1, a.N[0] * a.n[0]);
+  const int k2 = wrap_sym(a.N[1] * g2 + m2, a.N[1] * a.n[1]);
+  const int k3 = wrap_sym(a.N[2] * g3 + m3, a.N[2] * a.n[2]);
+  const double K1 = k1 * (2.0 * M_PI / (a.N[0] * a.L[0]));
+  const double K2 = k2 * (2.0 * M_PI / (a.N[1] * a.L[1]));
+  const double K3 = k3 * (2.0 * M_PI / (a.N[2] * a.L[2]));
+  const double kk = K1 * K1 + K2 * K2 + K3 * K3;
+  return kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void coulomb_mfma_kernel(const cplx<T>* __restrict__ F,
+                                                           double2* __restrict__ part, CoulArgs a,
+                                                           long nwork, long nwork_pad) {
+  const long per = nwork_pad / 8;
+  const long w = (blockIdx.x % 8) * per + blockIdx.x / 8;  // XCD-contiguous ranges
+  if (w >= nwork) return;
+  int tile = (int)(w % a.ntile);
+  const long ms = w / a.ntile;
+  const int m = (int)(ms / a.nsplit), s = (int)(ms % a.nsplit);
+  int ti = 0;
+  while (tile > ti) {
+    tile -= ti + 1;
+    ++ti;
+  }
+  const int tj = tile;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, gq = lane >> 4;
+  const int P0 = ti * MTILE + (wave & 1) * (MW * 16);
+  const int Q0 = tj * MTILE + (wave >> 1) * (MW * 16);
+  const long g0 = (long)s * a.chunk;
+  const long g1 = min((long)a.ng, g0 + a.chunk);
+  const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
+  const int m1 = m / (a.N[1] * a.N[2]), m2 = (m / a.N[2]) % a.N[1], m3 = m % a.N[2];
+
+  constexpr bool F64 = sizeof(T) == 8;
+  double accr[MW][MW][4], acci[MW][MW][4];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < MW; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) accr[i][j][v] = acci[i][j][v] = 0.0;
+  d4v dr[MW][MW], di[MW][MW];
+  f4v fr[MW][MW], fi[MW][MW];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+      dr[i][j] = d4v{0, 0, 0, 0};
+      di[i][j] = d4v{0, 0, 0, 0};
+      fr[i][j] = f4v{0, 0, 0, 0};
+      fi[i][j] = f4v{0, 0, 0, 0};
+    }
+
+  int since = 0;
+  for (long k0 = g0; k0 < g1; k0 += 16) {
+    const long gb = k0 + 4 * gq;
+    T vv[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) vv[t] = (gb + t < g1) ? (T)kernel_v(a, m1, m2, m3, gb + t) : (T)0;
+    cplx<T> x[MW][4], y[MW][4];
+#pragma unroll
+    for (int i = 0; i < MW; ++i) {
+      const int P = P0 + 16 * i + li;
+      const int Q = Q0 + 16 * i + li;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool ok = gb + t < g1;
+        cplx<T> xv = (ok && P < a.ni) ? Fm[(long)P * a.ng + gb + t] : mk<T>(0, 0);
+        x[i][t] = mk<T>(xv.x * vv[t], xv.y * vv[t]);
+        y[i][t] = (ok && Q < a.ni) ? Fm[(long)Q * a.ng + gb + t] : mk<T>(0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < MW; ++i)
+#pragma unroll
+        for (int j = 0; j < MW; ++j) {
+          if constexpr (F64) {
+            dr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i][t].x, y[j][t].x, dr[i][j], 0, 0, 0);
+            dr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i][t].y, y[j][t].y, dr[i][j], 0, 0, 0);
+            di[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i][t].y, y[j][t].x, di[i][j], 0, 0, 0);
+            di[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[i][t].x, y[j][t].y, di[i][j], 0, 0, 0);
+          } else {
+            fr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x[i][t].x, (float)y[j][t].x, fr[i][j], 0, 0, 0);
+            fr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x[i][t].y, (float)y[j][t].y, fr[i][j], 0, 0, 0);
+            fi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x[i][t].y, (float)y[j][t].x, fi[i][j], 0, 0, 0);
+            fi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-(float)x[i][t].x, (float)y[j][t].y, fi[i][j], 0, 0, 0);
+          }
+        }
+    if constexpr (!F64) {
+      since += 16;
+      if (since >= FLUSH) {
+        since = 0;
+#pragma unroll
+        for (int i = 0; i < MW; ++i)
+#pragma unroll
+          for (int j = 0; j < MW; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              accr[i][j][v] += (double)fr[i][j][v];
+              acci[i][j][v] += (double)fi[i][j][v];
+            }
+            fr[i][j] = f4v{0, 0, 0, 0};
+            fi[i][j] = f4v{0, 0, 0, 0};
+          }
+      }
+    }
+  }
+  double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // output rows: f64 MFMA register v holds row 4 v + lane/16, f32 holds 4 (lane/16) + v
+      const int P = P0 + 16 * i + (F64 ? 4 * v + gq : 4 * gq + v);
+      if (P >= a.ni) continue;
+#pragma unroll
+      for (int j = 0; j < MW; ++j) {
+        const int Q = Q0 + 16 * j + li;
+        if (Q >= a.ni) continue;
+        double re, im;
+        if constexpr (F64) {
+          re = dr[i][j][v];
+          im = di[i][j][v];
+        } else {
+          re = accr[i][j][v] + (double)fr[i][j][v];
+          im = acci[i][j][v] + (double)fi[i][j][v];
+        }
+        out[(long)P * a.ni + Q] = make_double2(re, im);
+      }
+    }
+}
+
 struct ReduceArgs {
   const double2* root[3];
   int n[3];
@@ -122,8 +277,7 @@ struct ReduceArgs {
 };
 
 // V[m][P][Q] = scale * e^{-i q_m.(r_P - r_Q)} sum_s part (mirrored for upper tiles)
-template <typename T>
-__global__ __launch_bounds__(256) void coulomb_reduce_kernel(const cplx<T>* __restrict__ part,
+__global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __restrict__ part,
                                                              const int32_t* __restrict__ pts,
                                                              double2* __restrict__ V,
                                                              ReduceArgs a) {
@@ -132,13 +286,13 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const cplx<T>* __re
   const int m = blockIdx.y;
   if (idx >= nn) return;
   const int P = (int)(idx / a.ni), Q = (int)(idx % a.ni);
-  const bool lower = (P / TM) >= (Q / TM);
+  const bool lower = (P / MTILE) >= (Q / MTILE);
   const long src = lower ? ((long)P * a.ni + Q) : ((long)Q * a.ni + P);
   double sx = 0.0, sy = 0.0;
   for (int s = 0; s < a.nsplit; ++s) {
-    cplx<T> v = part[((long)m * a.nsplit + s) * nn + src];
-    sx += (double)v.x;
-    sy += (double)v.y;
+    const double2 v = part[((long)m * a.nsplit + s) * nn + src];
+    sx += v.x;
+    sy += v.y;
   }
   if (!lower) sy = -sy;
   sx *= a.scale;
@@ -171,7 +325,7 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const cplx<T>* __re
 }  // namespace
 
 int coulomb_nsplit(const Geom& g) {
-  const int nt = (g.ni + TM - 1) / TM;
+  const int nt = (g.ni + MTILE - 1) / MTILE;
   const long tiles = (long)nt * (nt + 1) / 2 * g.nk;
   long ns = (4096 + tiles - 1) / tiles;
   const long maxs = (g.ng + 1023) / 1024;  // keep chunks >= ~1k points
@@ -197,11 +351,13 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.ni = g.ni;
   a.nk = g.nk;
   a.nsplit = nsplit;
-  a.chunk = (int)((((long)g.ng + nsplit - 1) / nsplit + TK - 1) / TK * TK);
-  const int nt = (g.ni + TM - 1) / TM;
+  a.chunk = (int)((((long)g.ng + nsplit - 1) / nsplit + FLUSH - 1) / FLUSH * FLUSH);
+  const int nt = (g.ni + MTILE - 1) / MTILE;
   a.ntile = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(coulomb_partial_kernel<T>, dim3(a.ntile, g.nk * nsplit), dim3(NT), 0, st,
-                     (const cplx<T>*)F, (cplx<T>*)partial, a);
+  const long nwork = (long)a.ntile * g.nk * nsplit;
+  const long pad = (nwork + 7) / 8 * 8;
+  hipLaunchKernelGGL(coulomb_mfma_kernel<T>, dim3((unsigned)pad), dim3(256), 0, st,
+                     (const cplx<T>*)F, (double2*)partial, a, nwork, pad);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   ReduceArgs r;
@@ -214,8 +370,8 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   r.nsplit = nsplit;
   r.scale = g.omega / ((double)g.ng * (double)g.ng);
   const long nn = (long)g.ni * g.ni;
-  hipLaunchKernelGGL(coulomb_reduce_kernel<T>, dim3((unsigned)((nn + 255) / 256), g.nk), dim3(256),
-                     0, st, (const cplx<T>*)partial, pts, V, r);
+  hipLaunchKernelGGL(coulomb_reduce_kernel, dim3((unsigned)((nn + 255) / 256), g.nk), dim3(256), 0,
+                     st, (const double2*)partial, pts, V, r);
   return hipGetLastError();
 }
 

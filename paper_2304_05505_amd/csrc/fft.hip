@@ -1,14 +1,17 @@
 // 3-D forward FFT of many functions on the cell grid, mixed radix 2/3/4/5,
 // Stockham autosort in LDS. Pass 1 transforms whole (y, z) planes held in LDS
 // (one HBM read and one write per plane); pass 2 transforms x lines for a block
-// of contiguous (y, z) columns.
+// of contiguous (y, z) columns. Twiddle tables are staged in LDS; butterflies
+// are dealt to threads so that neighbouring lanes touch neighbouring LDS
+// addresses (unit-stride direction fastest).
 #include "common.h"
 
 namespace exx {
 
 namespace {
 
-constexpr int FFT_NT = 256;
+constexpr int NT1 = 512;          // threads of the plane pass
+constexpr int NT2 = 256;          // threads of the x pass
 constexpr int FFT_MAXPTS = 8192;  // complex values held in LDS by one workgroup
 constexpr int FFT_CB = 32;        // (y, z) columns per workgroup in pass 2
 
@@ -84,31 +87,34 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
 
 // One Stockham stage of radix R on `nlines` lines of length n stored in LDS
 // (element stride es, line stride ls); Ns = product of the radices done so far.
-template <typename T, int R>
+// With LINE_FAST the butterfly index runs over lines first (use when ls == 1).
+template <typename T, int R, int NT, bool LINE_FAST>
 __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, int es, int ls,
-                                      const cplx<T>* __restrict__ tw) {
-  constexpr int MAXB = (FFT_MAXPTS / R + FFT_NT - 1) / FFT_NT;
+                                      const cplx<T>* tw) {
+  constexpr int MAXB = (FFT_MAXPTS / R + NT - 1) / NT;
   const int nb = n / R;
   const int total = nlines * nb;
   const int tid = threadIdx.x;
   cplx<T> v[MAXB][R];
 #pragma unroll
   for (int s = 0; s < MAXB; ++s) {
-    const int b = tid + s * FFT_NT;
+    const int b = tid + s * NT;
     if (b < total) {
-      const int line = b / nb, j = b % nb;
+      const int line = LINE_FAST ? b % nlines : b / nb;
+      const int j = LINE_FAST ? b / nlines : b % nb;
       const cplx<T>* src = buf + line * ls;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[s][r] = src[(j + r * nb) * es];
     }
   }
   __syncthreads();
-  const int span = n / R;  // n / (Ns * R) * Ns
+  const int span = n / R;
 #pragma unroll
   for (int s = 0; s < MAXB; ++s) {
-    const int b = tid + s * FFT_NT;
+    const int b = tid + s * NT;
     if (b < total) {
-      const int line = b / nb, j = b % nb;
+      const int line = LINE_FAST ? b % nlines : b / nb;
+      const int j = LINE_FAST ? b / nlines : b % nb;
       const int jm = j % Ns;
       const int step = jm * (span / Ns);
 #pragma unroll
@@ -123,59 +129,65 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, i
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, int NT, bool LINE_FAST>
 __device__ void fft_lines(cplx<T>* buf, const Plan1& p, int nlines, int es, int ls,
                           const cplx<T>* tw) {
   int Ns = 1;
   for (int s = 0; s < p.ns; ++s) {
     const int R = p.r[s];
     if (R == 4)
-      stage<T, 4>(buf, p.n, Ns, nlines, es, ls, tw);
+      stage<T, 4, NT, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
     else if (R == 2)
-      stage<T, 2>(buf, p.n, Ns, nlines, es, ls, tw);
+      stage<T, 2, NT, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
     else if (R == 3)
-      stage<T, 3>(buf, p.n, Ns, nlines, es, ls, tw);
+      stage<T, 3, NT, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
     else
-      stage<T, 5>(buf, p.n, Ns, nlines, es, ls, tw);
+      stage<T, 5, NT, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
     Ns *= R;
   }
 }
 
 // pass 1: one (function, x) plane per workgroup; z lines then y lines
 template <typename T>
-__global__ __launch_bounds__(FFT_NT) void fft_yz_kernel(const cplx<T>* __restrict__ in,
-                                                        cplx<T>* __restrict__ out, Plan1 py,
-                                                        Plan1 pz, const cplx<T>* twy,
-                                                        const cplx<T>* twz) {
+__global__ __launch_bounds__(NT1) void fft_yz_kernel(const cplx<T>* __restrict__ in,
+                                                     cplx<T>* __restrict__ out, Plan1 py, Plan1 pz,
+                                                     const cplx<T>* __restrict__ twy,
+                                                     const cplx<T>* __restrict__ twz) {
   extern __shared__ char smem_raw[];
-  cplx<T>* buf = (cplx<T>*)smem_raw;
   const int n2 = py.n, n3 = pz.n, np = n2 * n3;
+  cplx<T>* buf = (cplx<T>*)smem_raw;
+  cplx<T>* ty = buf + np;
+  cplx<T>* tz = ty + n2;
   const long off = (long)blockIdx.x * np;
-  for (int e = threadIdx.x; e < np; e += FFT_NT) buf[e] = in[off + e];
+  for (int e = threadIdx.x; e < np; e += NT1) buf[e] = in[off + e];
+  for (int e = threadIdx.x; e < n2; e += NT1) ty[e] = twy[e];
+  for (int e = threadIdx.x; e < n3; e += NT1) tz[e] = twz[e];
   __syncthreads();
-  fft_lines<T>(buf, pz, n2, 1, n3, twz);
-  fft_lines<T>(buf, py, n3, n3, 1, twy);
-  for (int e = threadIdx.x; e < np; e += FFT_NT) out[off + e] = buf[e];
+  fft_lines<T, NT1, false>(buf, pz, n2, 1, n3, tz);
+  fft_lines<T, NT1, true>(buf, py, n3, n3, 1, ty);
+  for (int e = threadIdx.x; e < np; e += NT1) out[off + e] = buf[e];
 }
 
 // pass 2: x lines of FFT_CB contiguous (y, z) columns of one function
 template <typename T>
-__global__ __launch_bounds__(FFT_NT) void fft_x_kernel(cplx<T>* __restrict__ data, Plan1 px,
-                                                       int np, int nblk, const cplx<T>* twx) {
+__global__ __launch_bounds__(NT2) void fft_x_kernel(cplx<T>* __restrict__ data, Plan1 px, int np,
+                                                    int nblk, const cplx<T>* __restrict__ twx) {
   extern __shared__ char smem_raw[];
-  cplx<T>* buf = (cplx<T>*)smem_raw;
   const int n1 = px.n;
+  cplx<T>* buf = (cplx<T>*)smem_raw;
+  cplx<T>* tx = buf + n1 * FFT_CB;
   const long f = blockIdx.x / nblk;
   const int c0 = (blockIdx.x % nblk) * FFT_CB;
   const int cw = min(FFT_CB, np - c0);
   cplx<T>* base = data + f * (long)n1 * np + c0;
-  for (int e = threadIdx.x; e < n1 * FFT_CB; e += FFT_NT) {
+  for (int e = threadIdx.x; e < n1 * FFT_CB; e += NT2) {
     const int x = e / FFT_CB, c = e % FFT_CB;
     buf[e] = (c < cw) ? base[(long)x * np + c] : mk<T>(0, 0);
   }
+  for (int e = threadIdx.x; e < n1; e += NT2) tx[e] = twx[e];
   __syncthreads();
-  fft_lines<T>(buf, px, FFT_CB, FFT_CB, 1, twx);
-  for (int e = threadIdx.x; e < n1 * FFT_CB; e += FFT_NT) {
+  fft_lines<T, NT2, true>(buf, px, FFT_CB, FFT_CB, 1, tx);
+  for (int e = threadIdx.x; e < n1 * FFT_CB; e += NT2) {
     const int x = e / FFT_CB, c = e % FFT_CB;
     if (c < cw) base[(long)x * np + c] = buf[e];
   }
@@ -210,8 +222,8 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
                         hipStream_t st) {
   Plan1 px = plan_for(g.n[0]), py = plan_for(g.n[1]), pz = plan_for(g.n[2]);
   const int np = g.n[1] * g.n[2];
-  size_t lds1 = (size_t)np * sizeof(cplx<T>);
-  size_t lds2 = (size_t)g.n[0] * FFT_CB * sizeof(cplx<T>);
+  size_t lds1 = (size_t)(np + g.n[1] + g.n[2]) * sizeof(cplx<T>);
+  size_t lds2 = (size_t)(g.n[0] * FFT_CB + g.n[0]) * sizeof(cplx<T>);
   hipError_t e = hipFuncSetAttribute((const void*)fft_yz_kernel<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
   if (e != hipSuccess) return e;
@@ -221,23 +233,21 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
   const long nplanes = nfun * g.n[0];
   for (long p0 = 0; p0 < nplanes; p0 += (1L << 30)) {
     long cnt = nplanes - p0 < (1L << 30) ? nplanes - p0 : (1L << 30);
-    hipLaunchKernelGGL(fft_yz_kernel<T>, dim3((unsigned)cnt), dim3(FFT_NT), lds1, st,
+    hipLaunchKernelGGL(fft_yz_kernel<T>, dim3((unsigned)cnt), dim3(NT1), lds1, st,
                        (const cplx<T>*)in + p0 * np, (cplx<T>*)out + p0 * np, py, pz, twp<T>(tb, 1),
                        twp<T>(tb, 2));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   const int nblk = (np + FFT_CB - 1) / FFT_CB;
-  const long nwg = nfun * nblk;
   const long fper = (1L << 30) / nblk;
   for (long f0 = 0; f0 < nfun; f0 += fper) {
     long cnt = nfun - f0 < fper ? nfun - f0 : fper;
-    hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)(cnt * nblk)), dim3(FFT_NT), lds2, st,
+    hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)(cnt * nblk)), dim3(NT2), lds2, st,
                        (cplx<T>*)out + f0 * (long)g.ng, px, np, nblk, twp<T>(tb, 0));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  (void)nwg;
   return hipSuccess;
 }
 

@@ -1,6 +1,5 @@
-// ISDF fit kernels: Bloch-phase tables, the k-mesh autocorrelation that forms
-// the fit metric S^m and the right-hand side Z^m, the FP64 Cholesky with pivot
-// drop and the triangular inverse used for the least-squares solve.
+// ISDF fit kernels: Bloch-phase tables and the k-mesh autocorrelation that
+// forms the fit metric S^m and the right-hand side Z^m.
 #include <cmath>
 
 #include "common.h"
@@ -246,118 +245,5 @@ template hipError_t launch_kcorr<double>(const Geom&, const Tables&, const void*
                                          const int32_t*, bool, hipStream_t);
 template hipError_t launch_kcorr<float>(const Geom&, const Tables&, const void*, void*, int,
                                         const int32_t*, bool, hipStream_t);
-
-// ---------------------------------------------------------------------------
-// Cholesky in point order with pivot drop: one workgroup per transfer m.
-// A (n x n, row-major) holds S^m on entry and L in its lower triangle on exit
-// (dropped columns zero, strict upper triangle undefined).
-// ---------------------------------------------------------------------------
-constexpr int CH_NT = 1024;
-
-__global__ __launch_bounds__(CH_NT) void chol_drop_kernel(double2* Aall, int n, int32_t* keepall,
-                                                          int32_t* rank, double rel_tol) {
-  const int m = blockIdx.x;
-  double2* A = Aall + (long)m * n * n;
-  int32_t* keep = keepall + (long)m * n;
-  __shared__ double red[CH_NT];
-  __shared__ int s_kept;
-  const int tid = threadIdx.x;
-  double mx = 0.0;
-  for (int i = tid; i < n; i += CH_NT) mx = fmax(mx, A[(long)i * n + i].x);
-  red[tid] = mx;
-  __syncthreads();
-  for (int s = CH_NT / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-    __syncthreads();
-  }
-  const double tol = rel_tol * red[0];
-  if (tid == 0) s_kept = 0;
-  __syncthreads();
-  for (int p = 0; p < n; ++p) {
-    const double d = A[(long)p * n + p].x;
-    const bool kp = (d >= tol) && isfinite(d) && d > 0.0;
-    __syncthreads();  // every thread has read the pivot before it is overwritten
-    if (!kp) {
-      for (int i = p + tid; i < n; i += CH_NT) A[(long)i * n + p] = make_double2(0.0, 0.0);
-      if (tid == 0) keep[p] = 0;
-      __syncthreads();
-      continue;
-    }
-    const double sd = sqrt(d), inv = 1.0 / sd;
-    for (int i = p + tid; i < n; i += CH_NT) {
-      double2 v = A[(long)i * n + p];
-      A[(long)i * n + p] = (i == p) ? make_double2(sd, 0.0) : make_double2(v.x * inv, v.y * inv);
-    }
-    if (tid == 0) {
-      keep[p] = 1;
-      s_kept += 1;
-    }
-    __syncthreads();
-    // trailing update of the lower triangle: A[i][j] -= L[i][p] conj(L[j][p]), p < j <= i
-    const int w = n - p - 1;
-    const long tot = (long)w * w;
-    for (long e = tid; e < tot; e += CH_NT) {
-      const int i = p + 1 + (int)(e / w);
-      const int j = p + 1 + (int)(e % w);
-      if (j > i) continue;
-      double2 li = A[(long)i * n + p];
-      double2 lj = A[(long)j * n + p];
-      double2 a = A[(long)i * n + j];
-      a.x -= li.x * lj.x + li.y * lj.y;
-      a.y -= li.y * lj.x - li.x * lj.y;
-      A[(long)i * n + j] = a;
-    }
-    __syncthreads();
-  }
-  if (tid == 0) rank[m] = s_kept;
-}
-
-hipError_t launch_chol_drop(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
-                            double rel_tol, hipStream_t st) {
-  hipLaunchKernelGGL(chol_drop_kernel, dim3(g.nk), dim3(CH_NT), 0, st, A, g.ni, keep, rank,
-                     rel_tol);
-  return hipGetLastError();
-}
-
-// W = L_RR^{-1} scattered back to n x n (zero rows/cols for dropped points).
-// One thread per column j, forward substitution down the column.
-__global__ __launch_bounds__(256) void tri_inv_kernel(const double2* __restrict__ Lall,
-                                                      const int32_t* __restrict__ keepall,
-                                                      double2* __restrict__ Wall, int n) {
-  const int m = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const double2* L = Lall + (long)m * n * n;
-  const int32_t* keep = keepall + (long)m * n;
-  double2* W = Wall + (long)m * n * n;
-  for (int i = 0; i < j; ++i) W[(long)i * n + j] = make_double2(0.0, 0.0);
-  if (!keep[j]) {
-    for (int i = j; i < n; ++i) W[(long)i * n + j] = make_double2(0.0, 0.0);
-    return;
-  }
-  W[(long)j * n + j] = make_double2(1.0 / L[(long)j * n + j].x, 0.0);
-  for (int i = j + 1; i < n; ++i) {
-    if (!keep[i]) {
-      W[(long)i * n + j] = make_double2(0.0, 0.0);
-      continue;
-    }
-    double sx = 0.0, sy = 0.0;
-    for (int k = j; k < i; ++k) {
-      double2 l = L[(long)i * n + k];
-      double2 w = W[(long)k * n + j];
-      sx += l.x * w.x - l.y * w.y;
-      sy += l.x * w.y + l.y * w.x;
-    }
-    const double inv = 1.0 / L[(long)i * n + i].x;
-    W[(long)i * n + j] = make_double2(-sx * inv, -sy * inv);
-  }
-}
-
-hipError_t launch_tri_inv(const Geom& g, const double2* Lf, const int32_t* keep, double2* W,
-                          hipStream_t st) {
-  dim3 grid((g.ni + 255) / 256, g.nk);
-  hipLaunchKernelGGL(tri_inv_kernel, grid, dim3(256), 0, st, Lf, keep, W, g.ni);
-  return hipGetLastError();
-}
 
 }  // namespace exx

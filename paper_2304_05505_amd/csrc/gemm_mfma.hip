@@ -1,0 +1,156 @@
+// Grid-sized complex FP64 GEMMs on the matrix cores (v_mfma_f64_16x16x4_f64),
+// complex products by four real MFMAs (4M).
+//
+//  * zgemm_nn: C[b] = A[b] * op(B[b]) with A (M x K, c128, small, L2-resident)
+//    and B (K x N) / C (M x N) long row-major panels over the grid (N = N_g).
+//    Used for Gamma^n = Psi^n conj(psi^n) and for the fit solve xi = S^+ Z.
+//    Operand fragments are read straight from global memory (no LDS): a lane
+//    loads one complex of a 16-column B strip, so each 16-lane group reads a
+//    contiguous 256-byte segment.
+//  * The workgroup order is XCD-aware: hardware deals workgroups round robin
+//    over the 8 XCDs; remapping gives every XCD a contiguous range of tiles,
+//    so the row tiles that share one B column strip run on the same XCD and
+//    reuse it from that XCD's L2.
+#include "common.h"
+
+namespace exx {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// logical tile index from the hardware workgroup id (XCD-contiguous ranges)
+__device__ __forceinline__ long xcd_remap(long bid, long total_padded) {
+  const long per = total_padded / NXCD;
+  return (bid % NXCD) * per + bid / NXCD;
+}
+
+// Wave tile: WM x WN blocks of 16x16; workgroup = 2 x 2 waves.
+template <typename TB, typename TC, int WM, int WN, int CONJB>
+__global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nrt, long ntiles,
+                                                     long ntiles_pad, const double2* __restrict__ A,
+                                                     long lda, long sA,
+                                                     const cplx<TB>* __restrict__ B, long ldb,
+                                                     long sB, cplx<TC>* __restrict__ C, long ldc,
+                                                     long sC) {
+  const long t = xcd_remap(blockIdx.x, ntiles_pad);
+  if (t >= ntiles) return;
+  const int rt = (int)(t % nrt);
+  const long ct = t / nrt;
+  const long b = blockIdx.y;
+  A += b * sA;
+  B += b * sB;
+  C += b * sC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = rt * (2 * WM * 16) + (wave & 1) * (WM * 16);
+  const long col0 = ct * (2 * WN * 16) + (wave >> 1) * (WN * 16);
+
+  d4 are[WM][WN], aim[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      are[i][j] = d4{0, 0, 0, 0};
+      aim[i][j] = d4{0, 0, 0, 0};
+    }
+
+  double2 fa[WM], fb[WN], na[WM], nb[WN];
+  auto load = [&](int k0, double2* xa, double2* xb) {
+    const int k = k0 + lk;
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const int r = row0 + i * 16 + li;
+      xa[i] = (r < M && k < K) ? A[(long)r * lda + k] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const long c = col0 + j * 16 + li;
+      double2 v = make_double2(0.0, 0.0);
+      if (c < N && k < K) {
+        cplx<TB> s = B[(long)k * ldb + c];
+        v = make_double2((double)s.x, CONJB ? -(double)s.y : (double)s.y);
+      }
+      xb[j] = v;
+    }
+  };
+  load(0, fa, fb);
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const bool more = k0 + 4 < K;
+    if (more) load(k0 + 4, na, nb);
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const double ar = fa[i].x, ai = fa[i].y, nai = -fa[i].y;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        are[i][j] = mfma64(ar, fb[j].x, are[i][j]);
+        are[i][j] = mfma64(nai, fb[j].y, are[i][j]);
+        aim[i][j] = mfma64(ar, fb[j].y, aim[i][j]);
+        aim[i][j] = mfma64(ai, fb[j].x, aim[i][j]);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < WM; ++i) fa[i] = na[i];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) fb[j] = nb[j];
+    }
+  }
+  // D layout of v_mfma_f64_16x16x4_f64: register v of a lane holds row
+  // 4*v + lane/16, column lane%16 of the 16x16 block
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + i * 16 + 4 * v + lk;
+      if (r >= M) continue;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const long c = col0 + j * 16 + li;
+        if (c < N) C[(long)r * ldc + c] = mk<TC>((TC)are[i][j][v], (TC)aim[i][j][v]);
+      }
+    }
+}
+
+template <typename TB, typename TC, int CONJB>
+hipError_t run_nn(int M, int N, int K, int batch, const void* A, long lda, long sA, const void* B,
+                  long ldb, long sB, void* C, long ldc, long sC, hipStream_t st) {
+  constexpr int WM = 2, WN = 4;
+  const int nrt = (M + 2 * WM * 16 - 1) / (2 * WM * 16);
+  const long nct = ((long)N + 2 * WN * 16 - 1) / (2 * WN * 16);
+  const long ntiles = nrt * nct;
+  const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
+  hipLaunchKernelGGL((zgemm_nn_mfma<TB, TC, WM, WN, CONJB>), dim3((unsigned)pad, batch), dim3(256),
+                     0, st, M, N, K, nrt, ntiles, pad, (const double2*)A, lda, sA,
+                     (const cplx<TB>*)B, ldb, sB, (cplx<TC>*)C, ldc, sC);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename TB, typename TC>
+hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                         bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                         hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (conjB) return run_nn<TB, TC, 1>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+  return run_nn<TB, TC, 0>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+}
+
+template hipError_t zgemm_nn_grid<double, double>(int, int, int, int, const void*, long, long,
+                                                  bool, const void*, long, long, void*, long, long,
+                                                  hipStream_t);
+template hipError_t zgemm_nn_grid<float, float>(int, int, int, int, const void*, long, long, bool,
+                                                const void*, long, long, void*, long, long,
+                                                hipStream_t);
+template hipError_t zgemm_nn_grid<double, float>(int, int, int, int, const void*, long, long, bool,
+                                                 const void*, long, long, void*, long, long,
+                                                 hipStream_t);
+
+}  // namespace exx

@@ -16,8 +16,8 @@ import torch
 
 _LIB_PATH = pathlib.Path(__file__).resolve().parent / "libexx.so"
 
-EXX_F64, EXX_F32, EXX_BF16 = 0, 1, 2
-PREC = {"f64": EXX_F64, "f32": EXX_F32, "bf16": EXX_BF16}
+EXX_F64, EXX_F32, EXX_BF16, EXX_MIXED = 0, 1, 2, 3
+PREC = {"f64": EXX_F64, "f32": EXX_F32, "bf16": EXX_BF16, "mixed": EXX_MIXED}
 _STATUS = {
     0: "EXX_OK",
     -1: "EXX_ERR_ARG",
@@ -137,7 +137,11 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def _grid_dtype(prec: int):
+def _psi_dtype(prec: int):
+    return torch.complex128 if prec in (EXX_F64, EXX_MIXED) else torch.complex64
+
+
+def _xi_dtype(prec: int):
     return torch.complex128 if prec == EXX_F64 else torch.complex64
 
 
@@ -191,12 +195,11 @@ class Handle:
 def exx_isdf_fit(h: Handle, cell: ExxCell, prec: int, psi_grid, occ_pts, pts, xi, S, rank):
     nk, ng, ni, no = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ
     d = h.device
-    gd = _grid_dtype(prec)
     args = (
-        _ptr(psi_grid, "psi_grid", gd, (nk, no, ng), d),
+        _ptr(psi_grid, "psi_grid", _psi_dtype(prec), (nk, no, ng), d),
         _ptr(occ_pts, "occ_pts", torch.complex128, (nk, ni, no), d),
         _ptr(pts, "pts", torch.int32, (ni,), d),
-        _ptr(xi, "xi", gd, (nk, ni, ng), d),
+        _ptr(xi, "xi", _xi_dtype(prec), (nk, ni, ng), d),
         _ptr(S, "S", torch.complex128, (nk, ni, ni), d),
         _ptr(rank, "rank", torch.int32, (nk,), d),
     )
@@ -207,7 +210,7 @@ def exx_coulomb_V(h: Handle, cell: ExxCell, prec: int, xi, pts, V):
     nk, ng, ni = _nk(cell), _ng(cell), cell.n_isdf
     d = h.device
     args = (
-        _ptr(xi, "xi", _grid_dtype(prec), (nk, ni, ng), d),
+        _ptr(xi, "xi", _xi_dtype(prec), (nk, ni, ng), d),
         _ptr(pts, "pts", torch.int32, (ni,), d),
         _ptr(V, "V", torch.complex128, (nk, ni, ni), d),
     )
@@ -231,7 +234,7 @@ def exx_build(h: Handle, cell: ExxCell, prec: int, psi_grid, occ_pts, ao_pts, pt
     nk, ng, ni, no, na = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ, cell.n_ao
     d = h.device
     args = (
-        _ptr(psi_grid, "psi_grid", _grid_dtype(prec), (nk, no, ng), d),
+        _ptr(psi_grid, "psi_grid", _psi_dtype(prec), (nk, no, ng), d),
         _ptr(occ_pts, "occ_pts", torch.complex128, (nk, ni, no), d),
         _ptr(ao_pts, "ao_pts", torch.complex128, (nk, ni, na), d),
         _ptr(pts, "pts", torch.int32, (ni,), d),

@@ -32,9 +32,10 @@ def run_gpu(cell, psi, pts, ao_pts, prec="f64", stages=True, handle=None):
     h = handle or exx.Handle(0)
     p = exx.PREC[prec]
     c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, len(pts))
+    wide = prec in ("f64", "mixed")
     gd = torch.complex128 if prec == "f64" else torch.complex64
     nk, no, ng, ni, na = cell.N_k, cell.n_occ, cell.N_g, len(pts), cell.n_ao
-    t_psi = torch.from_numpy(psi.astype(np.complex128 if prec == "f64" else np.complex64)).to(dev)
+    t_psi = torch.from_numpy(psi.astype(np.complex128 if wide else np.complex64)).to(dev)
     occ = np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))
     t_occ = torch.from_numpy(occ).to(dev)
     t_ao = torch.from_numpy(np.ascontiguousarray(np.transpose(ao_pts, (0, 2, 1)))).to(dev)

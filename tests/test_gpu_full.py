@@ -44,7 +44,7 @@ def _build(f, prec):
     torch, exx, cell = f["torch"], f["exx"], f["cell"]
     dev = torch.device("cuda", 0)
     t = f["t"]
-    psi = t["psi"] if prec == "f64" else t["psi"].to(torch.complex64)
+    psi = t["psi"] if prec in ("f64", "mixed") else t["psi"].to(torch.complex64)
     K = torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128, device=dev)
     Ex = torch.empty((1,), dtype=torch.float64, device=dev)
     rank = torch.empty((cell.N_k,), dtype=torch.int32, device=dev)
@@ -94,6 +94,20 @@ def test_full_size_fp64_coulomb_samples(full):
     assert np.abs(Vs - from_cplx_list(gold["Vb_val"])).max() <= tol * gold["maxabs_Vb"]
     sref = from_cplx_list(gold["S_val"])
     assert np.abs(Ss - sref).max() <= 1e-13 * np.abs(sref).max()
+
+
+def test_full_size_mixed_meets_accuracy_target(full):
+    """The mixed build against the FP64 oracle: |dE_x| <= 1e-5 Ha/cell, max|dK| <= 1e-6."""
+    gold = full["gold"]
+    K, Ex, rank = _build(full, "mixed")
+    idx = np.asarray(gold["K_idx"])
+    dK = float(np.abs(K[idx[:, 0], idx[:, 1], idx[:, 2]] - from_cplx_list(gold["K_val"])).max())
+    dK0 = float(np.abs(np.diagonal(K[0]) - from_cplx_list(gold["K0_diag"])).max())
+    dE = abs(Ex - gold["Ex"])
+    print(f"mixed full size: |dEx| {dE:.3e} Ha/cell, max|dK| (sampled) {max(dK, dK0):.3e}")
+    assert rank.tolist() == gold["rank"]
+    assert dE <= 1e-5
+    assert max(dK, dK0) <= 1e-6
 
 
 def test_full_size_fp32_error_report(full):

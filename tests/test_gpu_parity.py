@@ -92,9 +92,29 @@ def test_fused_build_equals_stages(gpu):
     assert np.array_equal(a["rank"], b["rank"])
 
 
+@pytest.mark.parametrize("name", ["gamma-config1", "k222-ragged", "k333", "k444"])
+def test_mixed_mode_matches_oracle(name, gpu):
+    """EXX_MIXED: FP64 fit, xi stored in FP32, FP32 FFT and Coulomb contraction with FP64
+    flushes. xi rounding (eps32 relative) and FP32 products bound the error of V at
+    ~1e-6 relative; E_x and K inherit it."""
+    cell = CELLS[name]()
+    base = inputs(cell)
+    pts, _ = select.select_points(base["psi"], cell.n_isdf)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    o = _oracle(cell, base["psi"], pts, ao)
+    g = run_gpu(cell, base["psi"], pts, ao, "mixed")
+    dE = abs(g["Ex"] - o["Ex"])
+    dK = float(np.abs(g["K"] - o["K"]).max())
+    print(f"{name}: mixed |dEx| {dE:.3e} (rel {dE / abs(o['Ex']):.2e}) max|dK| {dK:.3e}")
+    assert np.array_equal(g["rank"], o["rank"])
+    assert _rel(g["V"], o["Vb"]) <= 1e-5
+    assert dE <= 1e-6 * abs(o["Ex"])
+    assert dK <= 1e-5 * np.abs(o["K"]).max()
+
+
 @pytest.mark.parametrize("name", ["gamma-config1", "k222-ragged", "k333"])
 def test_fp32_mode_error_report(name, gpu):
-    """Mixed mode: bulk FP32, fit solve and E_x in FP64. Error reported and bounded."""
+    """EXX_F32: bulk FP32 (Gamma, Z, FFT, Coulomb), FP64 solve and E_x. Error reported and bounded."""
     cell = CELLS[name]()
     base = inputs(cell)
     pts, _ = select.select_points(base["psi"], cell.n_isdf)
