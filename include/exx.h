@@ -72,19 +72,21 @@ typedef enum {
 /* Arithmetic precision of the build. G^n, S^m, the Cholesky factorisation,
  * the pseudo-inverse, the k-convolution, K^n and E_x are FP64 in every mode.
  *   EXX_F64    everything FP64; psi_grid and xi are c128.
+ *   EXX_MIXED  the whole fit in FP64 (psi_grid c128); xi stored c64; FFT in
+ *              FP32; the Coulomb contraction multiplies the FP32-stored
+ *              transforms on the FP64 matrix cores (exact products, FP64
+ *              accumulation).
  *   EXX_F32    the grid-sized fit GEMM (Gamma^n) and the k-correlation Z^m
- *              run in FP32 (psi_grid and xi c64); the fit solve applies the
- *              FP64 pseudo-inverse in FP64 arithmetic; FFT and Coulomb
- *              contraction in FP32 on the matrix cores, FP32 accumulation
+ *              in FP32 (psi_grid and xi c64); the fit solve applies the FP64
+ *              pseudo-inverse in FP64 arithmetic; FFT in FP32; Coulomb
+ *              contraction on FP32 matrix cores with FP32 accumulation
  *              flushed into FP64 every 64 grid points.
- *   EXX_BF16   reserved (not built in: EXX_ERR_UNSUPPORTED).
- *   EXX_MIXED  the whole fit in FP64 (psi_grid c128), xi stored c64, FFT and
- *              Coulomb contraction in FP32 as in EXX_F32. */
+ *   EXX_BF16   reserved (not built in: EXX_ERR_UNSUPPORTED). */
 typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 } exx_prec;
 
 typedef struct {
   double L[3];       /* orthorhombic cell edges, bohr */
-  int32_t grid[3];   /* n1, n2, n3: each 2..128 and 2*3*5-smooth */
+  int32_t grid[3];   /* n1, n2, n3: each 2..128, 2*3*5-smooth, n2*n3 <= 6144 */
   int32_t kmesh[3];  /* N1, N2, N3: each 1..8, N_k = N1*N2*N3 <= 64 */
   int32_t n_occ;     /* occupied orbitals per k, 1..512 */
   int32_t n_ao;      /* basis functions per k, 1..4096 */

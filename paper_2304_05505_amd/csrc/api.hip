@@ -1,5 +1,6 @@
 // C ABI entry points: argument checks, scratch layout and the launch sequence
 // of one THC-oo-K exchange build.
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <type_traits>
@@ -112,7 +113,7 @@ exx_status check_cell(exx_context* h, const exx_cell* c, exx_prec prec) {
   if (g.ni > g.ng) return fail(h, EXX_ERR_SHAPE, "n_isdf exceeds the number of grid points");
   if (!kcorr_supported(g)) return fail(h, EXX_ERR_UNSUPPORTED, "k-mesh shape not built in");
   if (!fft_supported(g, prec == EXX_F64))
-    return fail(h, EXX_ERR_UNSUPPORTED, "grid shape not supported by the FFT (n2*n3 <= 8192)");
+    return fail(h, EXX_ERR_UNSUPPORTED, "grid shape not supported by the FFT (n2*n3 <= 6144)");
   return EXX_OK;
 }
 
@@ -215,7 +216,7 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
     if (std::is_same<TF, double>::value)
       e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
                                         psi, g.ng, (long)g.no * g.ng, grid, g.ng,
-                                        (long)g.ni * g.ng, st);
+                                        (long)g.ni * g.ng, st, h->tile_gamma);
     else
       e = launch_gamma<TF>(g, occ, psi, grid, st);
   }
@@ -230,15 +231,16 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   {
     PhaseTimer pt(h, PH_SOLVE, st);
     e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, false, grid, g.ng,
-                            (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st);
+                            (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
   return EXX_OK;
 }
 
+// f64mma: contraction on FP64 matrix cores (exact products of the FP32-stored F)
 template <typename T>
 exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
-                        const void* xi, const int32_t* pts, void* V, hipStream_t st) {
+                        const void* xi, const int32_t* pts, void* V, bool f64mma, hipStream_t st) {
   void* F = ws + L.grid;
   hipError_t e;
   {
@@ -248,7 +250,7 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {
     PhaseTimer pt(h, PH_COULOMB, st);
-    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, st);
+    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, f64mma, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "coulomb");
   return EXX_OK;
@@ -320,6 +322,9 @@ exx_status exx_create(exx_handle_t* h, int device) {
   exx_context* c = new (std::nothrow) exx_context();
   if (!c) return EXX_ERR_NOMEM;
   c->device = device;
+  // wave tiles of the grid GEMMs (16x16 blocks); EXX_TILE_GAMMA / EXX_TILE_SOLVE override
+  if (const char* v = getenv("EXX_TILE_GAMMA")) c->tile_gamma = atoi(v);
+  if (const char* v = getenv("EXX_TILE_SOLVE")) c->tile_solve = atoi(v);
   *h = c;
   return EXX_OK;
 }
@@ -379,8 +384,8 @@ exx_status exx_coulomb_V(exx_handle_t h, const exx_cell* cell, exx_prec prec, co
   char* ws;
   exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
   if (s != EXX_OK) return s;
-  if (prec == EXX_F64) return coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
-  return coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
+  if (prec == EXX_F64) return coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, true, stream);
+  return coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, prec == EXX_MIXED, stream);
 }
 
 exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* ao_pts,
@@ -417,13 +422,13 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   void* V = ws + L.V2;
   if (prec == EXX_F64) {
     s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
+    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, true, stream);
   } else if (prec == EXX_MIXED) {
     s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, true, stream);
   } else {
     s = fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, false, stream);
   }
   if (s != EXX_OK) return s;
   return buildK_impl(h, g, ws, L, ao_pts, occ_pts, V, K, Ex, stream);

@@ -106,6 +106,9 @@ struct exx_context {
   // persistent small buffers for exx_build
   void* small = nullptr;
   size_t small_cap = 0;
+  // wave tiles of the grid GEMMs (see zgemm_nn_grid)
+  int tile_gamma = 22;
+  int tile_solve = 22;
   // per-phase timing: recorded (phase, start, stop) events and a free pool
   bool timing = false;
   struct Rec {
@@ -168,11 +171,12 @@ hipError_t gemm(int M, int N, int K, int batch, OpA oa, const void* A, long lda,
                 bool accumulate, hipStream_t st);
 
 // C[b] = A[b] * op(B[b]) on the matrix cores in FP64: A (M x K) c128, B (K x N) and
-// C (M x N) row-major with storage types TB, TC; op = conj if conjB.
+// C (M x N) row-major with storage types TB, TC; op = conj if conjB. `tile` picks the
+// wave tile in 16x16 blocks (22, 24, 42, 44; workgroup = 2 x 2 waves).
 template <typename TB, typename TC>
 hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
-                         hipStream_t st);
+                         hipStream_t st, int tile);
 
 // Gamma^n(P, r) = sum_i occ[n][P][i] conj psi[n][i][r]  (fit right-hand side factor)
 template <typename T>
@@ -209,10 +213,10 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
                         hipStream_t st);
 bool fft_supported(const Geom& g, bool fp64);
 
-// Coulomb contraction: V^m (Bloch gauge) from F^m
+// Coulomb contraction: V^m (Bloch gauge) from F^m; f64mma: FP64 matrix cores for FP32 storage
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
-                          void* partial, int nsplit, double2* V, hipStream_t st);
+                          void* partial, int nsplit, double2* V, bool f64mma, hipStream_t st);
 size_t coulomb_partial_bytes(const Geom& g, int nsplit);
 int coulomb_nsplit(const Geom& g);
 

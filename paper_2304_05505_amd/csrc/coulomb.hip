@@ -5,14 +5,13 @@
 // on the fly from the K-box rule. A reduction kernel sums the chunks, mirrors
 // the upper triangle and applies the Bloch-gauge phase.
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 
 namespace exx {
 
 namespace {
-
-constexpr int TM = 64, TK = 16, NT = 256;
 
 struct CoulArgs {
   double L[3];
@@ -21,102 +20,10 @@ struct CoulArgs {
   int ng, ni, nk, nsplit, chunk, ntile;
 };
 
-__device__ __forceinline__ double sqrt_kernel(const CoulArgs& a, int m, long g) {
-  const int n23 = a.n[1] * a.n[2];
-  const int g1 = (int)(g / n23), g2 = (int)((g / a.n[2]) % a.n[1]), g3 = (int)(g % a.n[2]);
-  const int m1 = m / (a.N[1] * a.N[2]), m2 = (m / a.N[2]) % a.N[1], m3 = m % a.N[2];
-  const int k1 = wrap_sym(a.N[0] * g1 + m1, a.N[0] * a.n[0]);
-  const int k2 = wrap_sym(a.N[1] * g2 + m2, a.N[1] * a.n[1]);
-  const int k3 = wrap_sym(a.N[2] * g3 + m3, a.N[2] * a.n[2]);
-  const double K1 = k1 * (2.0 * M_PI / (a.N[0] * a.L[0]));
-  const double K2 = k2 * (2.0 * M_PI / (a.N[1] * a.L[1]));
-  const double K3 = k3 * (2.0 * M_PI / (a.N[2] * a.L[2]));
-  const double kk = K1 * K1 + K2 * K2 + K3 * K3;
-  // sqrt(4 pi / |K|^2)
-  return kk > 0.0 ? 3.5449077018110320546 / sqrt(kk) : 0.0;
-}
-
-// partial[m][s][P][Q] = sum_{g in chunk s} w(g) F[m][P][g] conj F[m][Q][g] for lower tiles
-template <typename T>
-__global__ __launch_bounds__(NT) void coulomb_partial_kernel(const cplx<T>* __restrict__ F,
-                                                             cplx<T>* __restrict__ part,
-                                                             CoulArgs a) {
-  __shared__ cplx<T> As[TK][TM];
-  __shared__ cplx<T> Bs[TK][TM];
-  __shared__ T sw[TK];
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  // triangular tile index -> (ti, tj), ti >= tj
-  int t = blockIdx.x, ti = 0;
-  while (t > ti) {
-    t -= ti + 1;
-    ++ti;
-  }
-  const int tj = t;
-  const int m = blockIdx.y / a.nsplit, s = blockIdx.y % a.nsplit;
-  const long g0 = (long)s * a.chunk;
-  const long g1 = min((long)a.ng, g0 + a.chunk);
-  const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
-  const int i0 = ti * TM, j0 = tj * TM;
-  cplx<T> acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = mk<T>(0, 0);
-  for (long k0 = g0; k0 < g1; k0 += TK) {
-    if (tid < TK) {
-      long g = k0 + tid;
-      sw[tid] = (g < g1) ? (T)sqrt_kernel(a, m, g) : (T)0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < (TM * TK) / NT; ++r) {
-      const int e = tid + NT * r;
-      const int i = e / TK, k = e % TK;
-      const long g = k0 + k;
-      cplx<T> va = mk<T>(0, 0), vb = mk<T>(0, 0);
-      if (g < g1) {
-        if (i0 + i < a.ni) va = cscale<T>(Fm[(long)(i0 + i) * a.ng + g], sw[k]);
-        if (j0 + i < a.ni) vb = cscale<T>(Fm[(long)(j0 + i) * a.ng + g], sw[k]);
-      }
-      As[k][i] = va;
-      Bs[k][i] = vb;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      cplx<T> x[4], y[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = As[kk][ty + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) y[v] = Bs[kk][tx + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          // x * conj(y)
-          acc[u][v].x += x[u].x * y[v].x + x[u].y * y[v].y;
-          acc[u][v].y += x[u].y * y[v].x - x[u].x * y[v].y;
-        }
-    }
-    __syncthreads();
-  }
-  cplx<T>* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int P = i0 + ty + 16 * u;
-    if (P >= a.ni) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int Q = j0 + tx + 16 * v;
-      if (Q < a.ni) out[(long)P * a.ni + Q] = acc[u][v];
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Matrix-core version of the partial contraction. A lane (row li = lane % 16,
-// group gq = lane / 16) loads 4 consecutive grid values of its row, so the k
-// index of MFMA step t is g0 + 4 gq + t for both operands (the k order of a
+// group gq = lane / 16) loads TPL consecutive grid values of its row, so the k
+// index of MFMA step t is g0 + TPL gq + t for both operands (the k order of a
 // sum is free). X = v(g) F_P (rows P), Y = conj F_Q (rows Q):
 //   Re += Re X Re F_Q + Im X Im F_Q,  Im += Im X Re F_Q - Re X Im F_Q.
 // FP64 storage: v_mfma_f64_16x16x4_f64. FP32 storage: v_mfma_f32_16x16x4_f32
@@ -128,6 +35,8 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int MW = 2;       // 16-blocks per wave in each direction (wave tile 32 x 32)
 constexpr int MTILE = 64;   // workgroup tile (2 x 2 waves)
 constexpr int FLUSH = 64;   // FP32 accumulation length before the FP64 flush
+constexpr int TPL = 2;      // consecutive grid values per lane and chunk
+constexpr int CK = 4 * TPL; // grid points per chunk
 
 __device__ __forceinline__ double kernel_v(const CoulArgs& a, int m1, int m2, int m3, long g) {
   const int n23 = a.n[1] * a.n[2];
@@ -142,10 +51,88 @@ __device__ __forceinline__ double kernel_v(const CoulArgs& a, int m1, int m2, in
   return kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
 }
 
-template <typename T>
+// Accumulators of one wave tile (MW x MW blocks of 16x16, real and imaginary).
+template <bool F64MMA>
+struct CAcc;
+
+template <>
+struct CAcc<true> {  // FP64 matrix cores, FP64 accumulation
+  d4v r[MW][MW], i[MW][MW];
+  __device__ void init() {
+#pragma unroll
+    for (int a = 0; a < MW; ++a)
+#pragma unroll
+      for (int b = 0; b < MW; ++b) r[a][b] = i[a][b] = d4v{0, 0, 0, 0};
+  }
+  // (xr + i xi) * conj(yr + i yi) for block (a, b)
+  __device__ void mac(int a, int b, double xr, double xi, double yr, double yi) {
+    r[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr, r[a][b], 0, 0, 0);
+    r[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi, r[a][b], 0, 0, 0);
+    i[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yr, i[a][b], 0, 0, 0);
+    i[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xr, yi, i[a][b], 0, 0, 0);
+  }
+  __device__ void chunk_done(int) {}
+  __device__ double re(int a, int b, int v) const { return r[a][b][v]; }
+  __device__ double im(int a, int b, int v) const { return i[a][b][v]; }
+  // register v of a lane holds row 4 v + lane/16 of the block
+  static __device__ int row(int gq, int v) { return 4 * v + gq; }
+};
+
+template <>
+struct CAcc<false> {  // FP32 matrix cores, FP32 accumulation flushed into FP64
+  f4v r[MW][MW], i[MW][MW];
+  double sr[MW][MW][4], si[MW][MW][4];
+  int since;
+  __device__ void init() {
+    since = 0;
+#pragma unroll
+    for (int a = 0; a < MW; ++a)
+#pragma unroll
+      for (int b = 0; b < MW; ++b) {
+        r[a][b] = i[a][b] = f4v{0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sr[a][b][v] = si[a][b][v] = 0.0;
+      }
+  }
+  __device__ void mac(int a, int b, float xr, float xi, float yr, float yi) {
+    r[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, yr, r[a][b], 0, 0, 0);
+    r[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yi, r[a][b], 0, 0, 0);
+    i[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yr, i[a][b], 0, 0, 0);
+    i[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-xr, yi, i[a][b], 0, 0, 0);
+  }
+  __device__ void flush() {
+#pragma unroll
+    for (int a = 0; a < MW; ++a)
+#pragma unroll
+      for (int b = 0; b < MW; ++b) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          sr[a][b][v] += (double)r[a][b][v];
+          si[a][b][v] += (double)i[a][b][v];
+        }
+        r[a][b] = i[a][b] = f4v{0, 0, 0, 0};
+      }
+  }
+  __device__ void chunk_done(int npts) {
+    since += npts;
+    if (since >= FLUSH) {
+      since = 0;
+      flush();
+    }
+  }
+  __device__ double re(int a, int b, int v) const { return sr[a][b][v] + (double)r[a][b][v]; }
+  __device__ double im(int a, int b, int v) const { return si[a][b][v] + (double)i[a][b][v]; }
+  // register v of a lane holds row 4 (lane/16) + v of the block
+  static __device__ int row(int gq, int v) { return 4 * gq + v; }
+};
+
+// T: storage of F. F64MMA: FP64 matrix cores (exact products of FP32 inputs, FP64
+// accumulation) even for FP32 storage; otherwise FP32 matrix cores with flushes.
+template <typename T, bool F64MMA>
 __global__ __launch_bounds__(256) void coulomb_mfma_kernel(const cplx<T>* __restrict__ F,
                                                            double2* __restrict__ part, CoulArgs a,
                                                            long nwork, long nwork_pad) {
+  using TO = typename std::conditional<F64MMA, double, float>::type;
   const long per = nwork_pad / 8;
   const long w = (blockIdx.x % 8) * per + blockIdx.x / 8;  // XCD-contiguous ranges
   if (w >= nwork) return;
@@ -167,103 +154,58 @@ __global__ __launch_bounds__(256) void coulomb_mfma_kernel(const cplx<T>* __rest
   const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
   const int m1 = m / (a.N[1] * a.N[2]), m2 = (m / a.N[2]) % a.N[1], m3 = m % a.N[2];
 
-  constexpr bool F64 = sizeof(T) == 8;
-  double accr[MW][MW][4], acci[MW][MW][4];
-#pragma unroll
-  for (int i = 0; i < MW; ++i)
-#pragma unroll
-    for (int j = 0; j < MW; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) accr[i][j][v] = acci[i][j][v] = 0.0;
-  d4v dr[MW][MW], di[MW][MW];
-  f4v fr[MW][MW], fi[MW][MW];
-#pragma unroll
-  for (int i = 0; i < MW; ++i)
-#pragma unroll
-    for (int j = 0; j < MW; ++j) {
-      dr[i][j] = d4v{0, 0, 0, 0};
-      di[i][j] = d4v{0, 0, 0, 0};
-      fr[i][j] = f4v{0, 0, 0, 0};
-      fi[i][j] = f4v{0, 0, 0, 0};
-    }
-
-  int since = 0;
-  for (long k0 = g0; k0 < g1; k0 += 16) {
-    const long gb = k0 + 4 * gq;
-    T vv[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) vv[t] = (gb + t < g1) ? (T)kernel_v(a, m1, m2, m3, gb + t) : (T)0;
-    cplx<T> x[MW][4], y[MW][4];
+  CAcc<F64MMA> acc;
+  acc.init();
+  // double-buffered register pipeline over CK-point grid chunks
+  cplx<T> rx[2][MW][TPL], ry[2][MW][TPL];
+  auto load = [&](long k0, cplx<T> (*xx)[TPL], cplx<T> (*yy)[TPL]) {
+    const long gb = k0 + TPL * gq;
 #pragma unroll
     for (int i = 0; i < MW; ++i) {
       const int P = P0 + 16 * i + li;
       const int Q = Q0 + 16 * i + li;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TPL; ++t) {
         const bool ok = gb + t < g1;
-        cplx<T> xv = (ok && P < a.ni) ? Fm[(long)P * a.ng + gb + t] : mk<T>(0, 0);
-        x[i][t] = mk<T>(xv.x * vv[t], xv.y * vv[t]);
-        y[i][t] = (ok && Q < a.ni) ? Fm[(long)Q * a.ng + gb + t] : mk<T>(0, 0);
+        xx[i][t] = (ok && P < a.ni) ? Fm[(long)P * a.ng + gb + t] : mk<T>(0, 0);
+        yy[i][t] = (ok && Q < a.ni) ? Fm[(long)Q * a.ng + gb + t] : mk<T>(0, 0);
       }
     }
+  };
+  auto compute = [&](long k0, cplx<T> (*xx)[TPL], cplx<T> (*yy)[TPL]) {
+    const long gb = k0 + TPL * gq;
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TPL; ++t) {
+      const TO vv = (gb + t < g1) ? (TO)kernel_v(a, m1, m2, m3, gb + t) : (TO)0;
 #pragma unroll
-      for (int i = 0; i < MW; ++i)
+      for (int i = 0; i < MW; ++i) {
+        const TO xr = (TO)xx[i][t].x * vv, xi = (TO)xx[i][t].y * vv;
 #pragma unroll
-        for (int j = 0; j < MW; ++j) {
-          if constexpr (F64) {
-            dr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i][t].x, y[j][t].x, dr[i][j], 0, 0, 0);
-            dr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i][t].y, y[j][t].y, dr[i][j], 0, 0, 0);
-            di[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i][t].y, y[j][t].x, di[i][j], 0, 0, 0);
-            di[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[i][t].x, y[j][t].y, di[i][j], 0, 0, 0);
-          } else {
-            fr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x[i][t].x, (float)y[j][t].x, fr[i][j], 0, 0, 0);
-            fr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x[i][t].y, (float)y[j][t].y, fr[i][j], 0, 0, 0);
-            fi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x[i][t].y, (float)y[j][t].x, fi[i][j], 0, 0, 0);
-            fi[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-(float)x[i][t].x, (float)y[j][t].y, fi[i][j], 0, 0, 0);
-          }
-        }
-    if constexpr (!F64) {
-      since += 16;
-      if (since >= FLUSH) {
-        since = 0;
-#pragma unroll
-        for (int i = 0; i < MW; ++i)
-#pragma unroll
-          for (int j = 0; j < MW; ++j) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              accr[i][j][v] += (double)fr[i][j][v];
-              acci[i][j][v] += (double)fi[i][j][v];
-            }
-            fr[i][j] = f4v{0, 0, 0, 0};
-            fi[i][j] = f4v{0, 0, 0, 0};
-          }
+        for (int j = 0; j < MW; ++j) acc.mac(i, j, xr, xi, (TO)yy[j][t].x, (TO)yy[j][t].y);
       }
     }
+    acc.chunk_done(CK);
+  };
+  // ping-pong between two statically indexed register buffers
+  if (g0 < g1) load(g0, rx[0], ry[0]);
+  for (long k0 = g0; k0 < g1; k0 += 2 * CK) {
+    if (k0 + CK < g1) load(k0 + CK, rx[1], ry[1]);
+    compute(k0, rx[0], ry[0]);
+    if (k0 + CK >= g1) break;
+    if (k0 + 2 * CK < g1) load(k0 + 2 * CK, rx[0], ry[0]);
+    compute(k0 + CK, rx[1], ry[1]);
   }
   double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
 #pragma unroll
   for (int i = 0; i < MW; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      // output rows: f64 MFMA register v holds row 4 v + lane/16, f32 holds 4 (lane/16) + v
-      const int P = P0 + 16 * i + (F64 ? 4 * v + gq : 4 * gq + v);
+      const int P = P0 + 16 * i + CAcc<F64MMA>::row(gq, v);
       if (P >= a.ni) continue;
 #pragma unroll
       for (int j = 0; j < MW; ++j) {
         const int Q = Q0 + 16 * j + li;
-        if (Q >= a.ni) continue;
-        double re, im;
-        if constexpr (F64) {
-          re = dr[i][j][v];
-          im = di[i][j][v];
-        } else {
-          re = accr[i][j][v] + (double)fr[i][j][v];
-          im = acci[i][j][v] + (double)fi[i][j][v];
-        }
-        out[(long)P * a.ni + Q] = make_double2(re, im);
+        if (Q < a.ni) out[(long)P * a.ni + Q] = make_double2(acc.re(i, j, v), acc.im(i, j, v));
       }
     }
 }
@@ -340,7 +282,7 @@ size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
 
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
-                          void* partial, int nsplit, double2* V, hipStream_t st) {
+                          void* partial, int nsplit, double2* V, bool f64mma, hipStream_t st) {
   CoulArgs a;
   for (int i = 0; i < 3; ++i) {
     a.L[i] = g.L[i];
@@ -356,8 +298,12 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.ntile = nt * (nt + 1) / 2;
   const long nwork = (long)a.ntile * g.nk * nsplit;
   const long pad = (nwork + 7) / 8 * 8;
-  hipLaunchKernelGGL(coulomb_mfma_kernel<T>, dim3((unsigned)pad), dim3(256), 0, st,
-                     (const cplx<T>*)F, (double2*)partial, a, nwork, pad);
+  if (f64mma || sizeof(T) == 8)
+    hipLaunchKernelGGL((coulomb_mfma_kernel<T, true>), dim3((unsigned)pad), dim3(256), 0, st,
+                       (const cplx<T>*)F, (double2*)partial, a, nwork, pad);
+  else
+    hipLaunchKernelGGL((coulomb_mfma_kernel<T, false>), dim3((unsigned)pad), dim3(256), 0, st,
+                       (const cplx<T>*)F, (double2*)partial, a, nwork, pad);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   ReduceArgs r;
@@ -376,8 +322,8 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
 }
 
 template hipError_t launch_coulomb<double>(const Geom&, const Tables&, const void*, const int32_t*,
-                                           void*, int, double2*, hipStream_t);
+                                           void*, int, double2*, bool, hipStream_t);
 template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void*, const int32_t*,
-                                          void*, int, double2*, hipStream_t);
+                                          void*, int, double2*, bool, hipStream_t);
 
 }  // namespace exx

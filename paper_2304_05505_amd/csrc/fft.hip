@@ -12,8 +12,9 @@ namespace {
 
 constexpr int NT1 = 512;          // threads of the plane pass
 constexpr int NT2 = 256;          // threads of the x pass
-constexpr int FFT_MAXPTS = 8192;  // complex values held in LDS by one workgroup
+constexpr int FFT_MAXPTS = 6144;  // largest (y, z) plane held in LDS by one workgroup
 constexpr int FFT_CB = 32;        // (y, z) columns per workgroup in pass 2
+constexpr int FFT_MAXX = 128;     // longest x line
 
 struct Plan1 {
   int n;
@@ -88,10 +89,10 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
 // One Stockham stage of radix R on `nlines` lines of length n stored in LDS
 // (element stride es, line stride ls); Ns = product of the radices done so far.
 // With LINE_FAST the butterfly index runs over lines first (use when ls == 1).
-template <typename T, int R, int NT, bool LINE_FAST>
+template <typename T, int R, int NT, int MAXPTS, bool LINE_FAST>
 __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, int es, int ls,
                                       const cplx<T>* tw) {
-  constexpr int MAXB = (FFT_MAXPTS / R + NT - 1) / NT;
+  constexpr int MAXB = (MAXPTS / R + NT - 1) / NT;
   const int nb = n / R;
   const int total = nlines * nb;
   const int tid = threadIdx.x;
@@ -129,20 +130,20 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, i
   __syncthreads();
 }
 
-template <typename T, int NT, bool LINE_FAST>
+template <typename T, int NT, int MAXPTS, bool LINE_FAST>
 __device__ void fft_lines(cplx<T>* buf, const Plan1& p, int nlines, int es, int ls,
                           const cplx<T>* tw) {
   int Ns = 1;
   for (int s = 0; s < p.ns; ++s) {
     const int R = p.r[s];
     if (R == 4)
-      stage<T, 4, NT, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
+      stage<T, 4, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
     else if (R == 2)
-      stage<T, 2, NT, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
+      stage<T, 2, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
     else if (R == 3)
-      stage<T, 3, NT, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
+      stage<T, 3, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
     else
-      stage<T, 5, NT, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
+      stage<T, 5, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
     Ns *= R;
   }
 }
@@ -163,8 +164,8 @@ __global__ __launch_bounds__(NT1) void fft_yz_kernel(const cplx<T>* __restrict__
   for (int e = threadIdx.x; e < n2; e += NT1) ty[e] = twy[e];
   for (int e = threadIdx.x; e < n3; e += NT1) tz[e] = twz[e];
   __syncthreads();
-  fft_lines<T, NT1, false>(buf, pz, n2, 1, n3, tz);
-  fft_lines<T, NT1, true>(buf, py, n3, n3, 1, ty);
+  fft_lines<T, NT1, FFT_MAXPTS, false>(buf, pz, n2, 1, n3, tz);
+  fft_lines<T, NT1, FFT_MAXPTS, true>(buf, py, n3, n3, 1, ty);
   for (int e = threadIdx.x; e < np; e += NT1) out[off + e] = buf[e];
 }
 
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(NT2) void fft_x_kernel(cplx<T>* __restrict__ data, 
   }
   for (int e = threadIdx.x; e < n1; e += NT2) tx[e] = twx[e];
   __syncthreads();
-  fft_lines<T, NT2, true>(buf, px, FFT_CB, FFT_CB, 1, tx);
+  fft_lines<T, NT2, FFT_CB * FFT_MAXX, true>(buf, px, FFT_CB, FFT_CB, 1, tx);
   for (int e = threadIdx.x; e < n1 * FFT_CB; e += NT2) {
     const int x = e / FFT_CB, c = e % FFT_CB;
     if (c < cw) base[(long)x * np + c] = buf[e];
@@ -213,7 +214,7 @@ bool fft_supported(const Geom& g, bool fp64) {
     if (plan_for(g.n[a]).ns < 0) return false;
   }
   if (g.n[1] * g.n[2] > FFT_MAXPTS) return false;
-  if (g.n[0] * FFT_CB > FFT_MAXPTS) return false;
+  if (g.n[0] > FFT_MAXX) return false;
   return true;
 }
 

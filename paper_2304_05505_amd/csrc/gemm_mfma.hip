@@ -61,7 +61,9 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
       aim[i][j] = d4{0, 0, 0, 0};
     }
 
-  double2 fa[WM], fb[WN], na[WM], nb[WN];
+  // NPF-deep register pipeline: slot s holds the fragments of k-step s (mod NPF)
+  constexpr int NPF = 3;
+  double2 fa[NPF][WM], fb[NPF][WN];
   auto load = [&](int k0, double2* xa, double2* xb) {
     const int k = k0 + lk;
 #pragma unroll
@@ -80,26 +82,26 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
       xb[j] = v;
     }
   };
-  load(0, fa, fb);
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const bool more = k0 + 4 < K;
-    if (more) load(k0 + 4, na, nb);
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-      const double ar = fa[i].x, ai = fa[i].y, nai = -fa[i].y;
+  for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
+  for (int k0 = 0; k0 < K; k0 += 4 * NPF) {
 #pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        are[i][j] = mfma64(ar, fb[j].x, are[i][j]);
-        are[i][j] = mfma64(nai, fb[j].y, are[i][j]);
-        aim[i][j] = mfma64(ar, fb[j].y, aim[i][j]);
-        aim[i][j] = mfma64(ai, fb[j].x, aim[i][j]);
+    for (int s = 0; s < NPF; ++s) {
+      const int kk = k0 + 4 * s;
+      if (kk < K) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+          const double ar = fa[s][i].x, ai = fa[s][i].y, nai = -fa[s][i].y;
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            are[i][j] = mfma64(ar, fb[s][j].x, are[i][j]);
+            are[i][j] = mfma64(nai, fb[s][j].y, are[i][j]);
+            aim[i][j] = mfma64(ar, fb[s][j].y, aim[i][j]);
+            aim[i][j] = mfma64(ai, fb[s][j].x, aim[i][j]);
+          }
+        }
+        if (kk + 4 * NPF < K) load(kk + 4 * NPF, fa[s], fb[s]);
       }
-    }
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < WM; ++i) fa[i] = na[i];
-#pragma unroll
-      for (int j = 0; j < WN; ++j) fb[j] = nb[j];
     }
   }
   // D layout of v_mfma_f64_16x16x4_f64: register v of a lane holds row
@@ -118,10 +120,9 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
     }
 }
 
-template <typename TB, typename TC, int CONJB>
+template <typename TB, typename TC, int WM, int WN, int CONJB>
 hipError_t run_nn(int M, int N, int K, int batch, const void* A, long lda, long sA, const void* B,
                   long ldb, long sB, void* C, long ldc, long sC, hipStream_t st) {
-  constexpr int WM = 2, WN = 4;
   const int nrt = (M + 2 * WM * 16 - 1) / (2 * WM * 16);
   const long nct = ((long)N + 2 * WN * 16 - 1) / (2 * WN * 16);
   const long ntiles = nrt * nct;
@@ -132,25 +133,42 @@ hipError_t run_nn(int M, int N, int K, int batch, const void* A, long lda, long 
   return hipGetLastError();
 }
 
+template <typename TB, typename TC, int CONJB>
+hipError_t run_nn_tile(int tile, int M, int N, int K, int batch, const void* A, long lda, long sA,
+                       const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                       hipStream_t st) {
+  switch (tile) {
+    case 22:
+      return run_nn<TB, TC, 2, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+    case 44:
+      return run_nn<TB, TC, 4, 4, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+    case 42:
+      return run_nn<TB, TC, 4, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+    default:
+      return run_nn<TB, TC, 2, 4, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+  }
+}
+
 }  // namespace
 
 template <typename TB, typename TC>
 hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
-                         hipStream_t st) {
+                         hipStream_t st, int tile) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  if (conjB) return run_nn<TB, TC, 1>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
-  return run_nn<TB, TC, 0>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+  if (conjB)
+    return run_nn_tile<TB, TC, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+  return run_nn_tile<TB, TC, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
 }
 
 template hipError_t zgemm_nn_grid<double, double>(int, int, int, int, const void*, long, long,
                                                   bool, const void*, long, long, void*, long, long,
-                                                  hipStream_t);
+                                                  hipStream_t, int);
 template hipError_t zgemm_nn_grid<float, float>(int, int, int, int, const void*, long, long, bool,
                                                 const void*, long, long, void*, long, long,
-                                                hipStream_t);
+                                                hipStream_t, int);
 template hipError_t zgemm_nn_grid<double, float>(int, int, int, int, const void*, long, long, bool,
                                                  const void*, long, long, void*, long, long,
-                                                 hipStream_t);
+                                                 hipStream_t, int);
 
 }  // namespace exx
