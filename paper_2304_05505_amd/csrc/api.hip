@@ -197,7 +197,7 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   // a3: Cholesky with drop, inverse factor, S^+ = W^H W
   {
     PhaseTimer pt(h, PH_CHOL, st);
-    e = hipMemcpyAsync(Lf, S, sizeof(double2) * g.nk * nn, hipMemcpyDeviceToDevice, st);
+    e = launch_copy(Lf, (const double2*)S, (long)g.nk * nn, st);
     if (e != hipSuccess) return hip_check(h, e, "copy S");
     e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, st);
   }
@@ -334,7 +334,7 @@ exx_status exx_destroy(exx_handle_t h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   if (h->ws.base) (void)hipFree(h->ws.base);
-  if (h->tables) (void)hipFree(h->tables);
+  for (auto& te : h->tabs) (void)hipFree(te.buf);
   if (h->small) (void)hipFree(h->small);
   for (auto& r : h->recs) {
     (void)hipEventDestroy(r.a);
@@ -349,7 +349,9 @@ const char* exx_last_error(exx_handle_t h) { return h ? h->err.c_str() : "null h
 
 exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes) {
   if (!h || !bytes) return EXX_ERR_ARG;
-  *bytes = h->ws.cap + h->tables_cap + h->small_cap;
+  size_t tb = 0;
+  for (auto& te : h->tabs) tb += te.bytes;
+  *bytes = h->ws.cap + tb + h->small_cap;
   return EXX_OK;
 }
 

@@ -121,6 +121,11 @@ __global__ __launch_bounds__(PNT) void chol_panel_kernel(double2* __restrict__ A
   }
 }
 
+__global__ void copy_kernel(double2* __restrict__ dst, const double2* __restrict__ src, long n) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[e];
+}
+
 // W := 0 (whole n x n of every m)
 __global__ void zero_kernel(double2* __restrict__ W, long total) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -171,6 +176,12 @@ __global__ __launch_bounds__(PNT) void diag_inv_kernel(const double2* __restrict
 }
 
 }  // namespace
+
+hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_chol_blocked(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
                                double* tol, double rel_tol, hipStream_t st) {

@@ -99,10 +99,13 @@ struct exx_context {
   std::string err;
   exx::Arena ws;            // grid-sized scratch + small matrices
   // per-axis root tables e^{-2 pi i t / (N_i n_i)} for the Bloch phases and
-  // twiddle tables for the FFT, cached per geometry
-  void* tables = nullptr;
-  size_t tables_cap = 0;
-  int tab_key[6] = {0, 0, 0, 0, 0, 0};
+  // twiddle tables for the FFT, one device buffer per (grid, k-mesh) shape
+  struct TabEntry {
+    int key[6];
+    void* buf;
+    size_t bytes;
+  };
+  std::vector<TabEntry> tabs;
   // persistent small buffers for exx_build
   void* small = nullptr;
   size_t small_cap = 0;
@@ -199,6 +202,9 @@ template <typename T>
 hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* out, int ncol,
                         const int32_t* pts, bool cols_are_points, hipStream_t st);
 bool kcorr_supported(const Geom& g);
+
+// dst[0:n] = src[0:n] (a kernel, so that captured sequences hold no copy nodes)
+hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st);
 
 // Blocked Cholesky with pivot drop (A: S^m in, L in the lower triangle out;
 // tol: [N_k] scratch) and blocked inverse W = L^{-1} (T: [N_k][32][N_I] scratch)

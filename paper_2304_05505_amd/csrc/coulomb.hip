@@ -38,19 +38,6 @@ constexpr int FLUSH = 64;   // FP32 accumulation length before the FP64 flush
 constexpr int TPL = 2;      // consecutive grid values per lane and chunk
 constexpr int CK = 4 * TPL; // grid points per chunk
 
-__device__ __forceinline__ double kernel_v(const CoulArgs& a, int m1, int m2, int m3, long g) {
-  const int n23 = a.n[1] * a.n[2];
-  const int g1 = (int)(g / n23), g2 = (int)((g / a.n[2]) % a.n[1]), g3 = (int)(g % a.n[2]);
-  const int k1 = wrap_sym(a.N[0] * g1 + m1, a.N[0] * a.n[0]);
-  const int k2 = wrap_sym(a.N[1] * g2 + m2, a.N[1] * a.n[1]);
-  const int k3 = wrap_sym(a.N[2] * g3 + m3, a.N[2] * a.n[2]);
-  const double K1 = k1 * (2.0 * M_PI / (a.N[0] * a.L[0]));
-  const double K2 = k2 * (2.0 * M_PI / (a.N[1] * a.L[1]));
-  const double K3 = k3 * (2.0 * M_PI / (a.N[2] * a.L[2]));
-  const double kk = K1 * K1 + K2 * K2 + K3 * K3;
-  return kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
-}
-
 // Accumulators of one wave tile (MW x MW blocks of 16x16, real and imaginary).
 template <bool F64MMA>
 struct CAcc;
@@ -129,7 +116,7 @@ struct CAcc<false> {  // FP32 matrix cores, FP32 accumulation flushed into FP64
 // T: storage of F. F64MMA: FP64 matrix cores (exact products of FP32 inputs, FP64
 // accumulation) even for FP32 storage; otherwise FP32 matrix cores with flushes.
 template <typename T, bool F64MMA>
-__global__ __launch_bounds__(256) void coulomb_mfma_kernel(const cplx<T>* __restrict__ F,
+__global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __restrict__ F,
                                                            double2* __restrict__ part, CoulArgs a,
                                                            long nwork, long nwork_pad) {
   using TO = typename std::conditional<F64MMA, double, float>::type;
@@ -154,6 +141,39 @@ __global__ __launch_bounds__(256) void coulomb_mfma_kernel(const cplx<T>* __rest
   const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
   const int m1 = m / (a.N[1] * a.N[2]), m2 = (m / a.N[2]) % a.N[1], m3 = m % a.N[2];
 
+  // per-axis squared components of K for this transfer: |K|^2 = T0[g1] + T1[g2] + T2[g3]
+  __shared__ double sK2[3][128];
+  for (int e = threadIdx.x; e < a.n[0] + a.n[1] + a.n[2]; e += 256) {
+    const int ax = e < a.n[0] ? 0 : (e < a.n[0] + a.n[1] ? 1 : 2);
+    const int gi = e - (ax == 0 ? 0 : (ax == 1 ? a.n[0] : a.n[0] + a.n[1]));
+    const int mi = ax == 0 ? m1 : (ax == 1 ? m2 : m3);
+    const int kap = wrap_sym(a.N[ax] * gi + mi, a.N[ax] * a.n[ax]);
+    const double K = kap * (2.0 * M_PI / (a.N[ax] * a.L[ax]));
+    sK2[ax][gi] = K * K;
+  }
+  __syncthreads();
+  const int n2 = a.n[1], n3 = a.n[2];
+  // v^m at TPL consecutive grid points starting at gb (int32 index arithmetic)
+  auto vchunk = [&](long gb, double* vv) {
+    int g = (int)gb;
+    int q = g / n3;
+    int c3 = g - q * n3;
+    int c1 = q / n2;
+    int c2 = q - c1 * n2;
+#pragma unroll
+    for (int t = 0; t < TPL; ++t) {
+      const double kk = sK2[0][c1] + sK2[1][c2] + sK2[2][c3];
+      vv[t] = (gb + t < g1 && kk > 0.0) ? 4.0 * M_PI / kk : 0.0;
+      if (++c3 == n3) {
+        c3 = 0;
+        if (++c2 == n2) {
+          c2 = 0;
+          if (++c1 == a.n[0]) c1 = 0;
+        }
+      }
+    }
+  };
+
   CAcc<F64MMA> acc;
   acc.init();
   // double-buffered register pipeline over CK-point grid chunks
@@ -174,9 +194,11 @@ __global__ __launch_bounds__(256) void coulomb_mfma_kernel(const cplx<T>* __rest
   };
   auto compute = [&](long k0, cplx<T> (*xx)[TPL], cplx<T> (*yy)[TPL]) {
     const long gb = k0 + TPL * gq;
+    double vd[TPL];
+    vchunk(gb, vd);
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
-      const TO vv = (gb + t < g1) ? (TO)kernel_v(a, m1, m2, m3, gb + t) : (TO)0;
+      const TO vv = (TO)vd[t];
 #pragma unroll
       for (int i = 0; i < MW; ++i) {
         const TO xr = (TO)xx[i][t].x * vv, xi = (TO)xx[i][t].y * vv;

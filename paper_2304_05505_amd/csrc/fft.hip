@@ -4,6 +4,8 @@
 // of contiguous (y, z) columns. Twiddle tables are staged in LDS; butterflies
 // are dealt to threads so that neighbouring lanes touch neighbouring LDS
 // addresses (unit-stride direction fastest).
+#include <algorithm>
+
 #include "common.h"
 
 namespace exx {
@@ -150,7 +152,7 @@ __device__ void fft_lines(cplx<T>* buf, const Plan1& p, int nlines, int es, int 
 
 // pass 1: one (function, x) plane per workgroup; z lines then y lines
 template <typename T>
-__global__ __launch_bounds__(NT1) void fft_yz_kernel(const cplx<T>* __restrict__ in,
+__global__ __launch_bounds__(NT1) void fft_yz1_kernel(const cplx<T>* __restrict__ in,
                                                      cplx<T>* __restrict__ out, Plan1 py, Plan1 pz,
                                                      const cplx<T>* __restrict__ twy,
                                                      const cplx<T>* __restrict__ twz) {
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(NT1) void fft_yz_kernel(const cplx<T>* __restrict__
 
 // pass 2: x lines of FFT_CB contiguous (y, z) columns of one function
 template <typename T>
-__global__ __launch_bounds__(NT2) void fft_x_kernel(cplx<T>* __restrict__ data, Plan1 px, int np,
+__global__ __launch_bounds__(NT2) void fft_x1_kernel(cplx<T>* __restrict__ data, Plan1 px, int np,
                                                     int nblk, const cplx<T>* __restrict__ twx) {
   extern __shared__ char smem_raw[];
   const int n1 = px.n;
@@ -191,6 +193,105 @@ __global__ __launch_bounds__(NT2) void fft_x_kernel(cplx<T>* __restrict__ data, 
   for (int e = threadIdx.x; e < n1 * FFT_CB; e += NT2) {
     const int x = e / FFT_CB, c = e % FFT_CB;
     if (c < cw) base[(long)x * np + c] = buf[e];
+  }
+}
+
+// pass 1: (function, x) planes, z lines then y lines. Workgroups loop over
+// planes; the next plane is loaded into registers while the current one is
+// transformed in LDS.
+constexpr int PRE1 = (FFT_MAXPTS + NT1 - 1) / NT1;
+template <typename T>
+__global__ __launch_bounds__(NT1) void fft_yz_kernel(const cplx<T>* __restrict__ in,
+                                                     cplx<T>* __restrict__ out, long nplanes,
+                                                     Plan1 py, Plan1 pz,
+                                                     const cplx<T>* __restrict__ twy,
+                                                     const cplx<T>* __restrict__ twz) {
+  extern __shared__ char smem_raw[];
+  const int n2 = py.n, n3 = pz.n, np = n2 * n3;
+  cplx<T>* buf = (cplx<T>*)smem_raw;
+  cplx<T>* ty = buf + np;
+  cplx<T>* tz = ty + n2;
+  for (int e = threadIdx.x; e < n2; e += NT1) ty[e] = twy[e];
+  for (int e = threadIdx.x; e < n3; e += NT1) tz[e] = twz[e];
+  cplx<T> pre[PRE1];
+  long p = blockIdx.x;
+  if (p < nplanes) {
+#pragma unroll
+    for (int k = 0; k < PRE1; ++k) {
+      const int e = threadIdx.x + k * NT1;
+      if (e < np) pre[k] = in[p * np + e];
+    }
+  }
+  for (; p < nplanes; p += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < PRE1; ++k) {
+      const int e = threadIdx.x + k * NT1;
+      if (e < np) buf[e] = pre[k];
+    }
+    __syncthreads();
+    const long pn = p + gridDim.x;
+    if (pn < nplanes) {
+#pragma unroll
+      for (int k = 0; k < PRE1; ++k) {
+        const int e = threadIdx.x + k * NT1;
+        if (e < np) pre[k] = in[pn * np + e];
+      }
+    }
+    fft_lines<T, NT1, FFT_MAXPTS, false>(buf, pz, n2, 1, n3, tz);
+    fft_lines<T, NT1, FFT_MAXPTS, true>(buf, py, n3, n3, 1, ty);
+    for (int e = threadIdx.x; e < np; e += NT1) out[p * np + e] = buf[e];
+    __syncthreads();
+  }
+}
+
+// pass 2: x lines of FFT_CB contiguous (y, z) columns; workgroups loop over
+// column blocks with a register prefetch of the next block.
+constexpr int PRE2 = (FFT_CB * FFT_MAXX + NT2 - 1) / NT2;
+template <typename T>
+__global__ __launch_bounds__(NT2) void fft_x_kernel(cplx<T>* __restrict__ data, long nwork,
+                                                    Plan1 px, int np, int nblk,
+                                                    const cplx<T>* __restrict__ twx) {
+  extern __shared__ char smem_raw[];
+  const int n1 = px.n;
+  cplx<T>* buf = (cplx<T>*)smem_raw;
+  cplx<T>* tx = buf + n1 * FFT_CB;
+  for (int e = threadIdx.x; e < n1; e += NT2) tx[e] = twx[e];
+  const int npts = n1 * FFT_CB;
+  cplx<T> pre[PRE2];
+  auto fetch = [&](long w) {
+    const long f = w / nblk;
+    const int c0 = (int)(w % nblk) * FFT_CB;
+    const int cw = min(FFT_CB, np - c0);
+    const cplx<T>* base = data + f * (long)n1 * np + c0;
+#pragma unroll
+    for (int k = 0; k < PRE2; ++k) {
+      const int e = threadIdx.x + k * NT2;
+      if (e < npts) {
+        const int x = e / FFT_CB, c = e % FFT_CB;
+        pre[k] = (c < cw) ? base[(long)x * np + c] : mk<T>(0, 0);
+      }
+    }
+  };
+  long w = blockIdx.x;
+  if (w < nwork) fetch(w);
+  for (; w < nwork; w += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < PRE2; ++k) {
+      const int e = threadIdx.x + k * NT2;
+      if (e < npts) buf[e] = pre[k];
+    }
+    __syncthreads();
+    if (w + gridDim.x < nwork) fetch(w + gridDim.x);
+    fft_lines<T, NT2, FFT_CB * FFT_MAXX, true>(buf, px, FFT_CB, FFT_CB, 1, tx);
+    const long f = w / nblk;
+    const int c0 = (int)(w % nblk) * FFT_CB;
+    const int cw = min(FFT_CB, np - c0);
+    cplx<T>* base = data + f * (long)n1 * np + c0;
+    for (int e = threadIdx.x; e < npts; e += NT2) {
+      const int x = e / FFT_CB, c = e % FFT_CB;
+      if (c < cw) base[(long)x * np + c] = buf[e];
+    }
+    __syncthreads();
   }
 }
 
@@ -232,23 +333,47 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
                           (int)lds2);
   if (e != hipSuccess) return e;
   const long nplanes = nfun * g.n[0];
-  for (long p0 = 0; p0 < nplanes; p0 += (1L << 30)) {
-    long cnt = nplanes - p0 < (1L << 30) ? nplanes - p0 : (1L << 30);
-    hipLaunchKernelGGL(fft_yz_kernel<T>, dim3((unsigned)cnt), dim3(NT1), lds1, st,
-                       (const cplx<T>*)in + p0 * np, (cplx<T>*)out + p0 * np, py, pz, twp<T>(tb, 1),
-                       twp<T>(tb, 2));
+  const int np1 = np;
+  // FP64 planes fill the register file; they run one plane per workgroup. FP32
+  // planes run in persistent workgroups that prefetch the next plane.
+  if (sizeof(T) == 8) {
+    e = hipFuncSetAttribute((const void*)fft_yz1_kernel<T>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)fft_x1_kernel<T>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fft_yz1_kernel<T>, dim3((unsigned)nplanes), dim3(NT1), lds1, st,
+                       (const cplx<T>*)in, (cplx<T>*)out, py, pz, twp<T>(tb, 1), twp<T>(tb, 2));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const int nblk1 = (np1 + FFT_CB - 1) / FFT_CB;
+    hipLaunchKernelGGL(fft_x1_kernel<T>, dim3((unsigned)(nfun * nblk1)), dim3(NT2), lds2, st,
+                       (cplx<T>*)out, px, np1, nblk1, twp<T>(tb, 0));
+    return hipGetLastError();
   }
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      ncu = v;
+  }
+  // resident workgroups per CU bounded by LDS (160 KB per CU)
+  const long wpc1 = lds1 > 0 ? std::max<long>(1, (160L * 1024) / (long)lds1) : 1;
+  const long grid1 = std::min<long>(nplanes, ncu * std::min<long>(wpc1, 4) * 2);
+  hipLaunchKernelGGL(fft_yz_kernel<T>, dim3((unsigned)grid1), dim3(NT1), lds1, st,
+                     (const cplx<T>*)in, (cplx<T>*)out, nplanes, py, pz, twp<T>(tb, 1),
+                     twp<T>(tb, 2));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const int nblk = (np + FFT_CB - 1) / FFT_CB;
-  const long fper = (1L << 30) / nblk;
-  for (long f0 = 0; f0 < nfun; f0 += fper) {
-    long cnt = nfun - f0 < fper ? nfun - f0 : fper;
-    hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)(cnt * nblk)), dim3(NT2), lds2, st,
-                       (cplx<T>*)out + f0 * (long)g.ng, px, np, nblk, twp<T>(tb, 0));
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
+  const long nwork = nfun * nblk;
+  const long wpc2 = std::max<long>(1, (160L * 1024) / (long)lds2);
+  const long grid2 = std::min<long>(nwork, ncu * std::min<long>(wpc2, 8) * 2);
+  hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)grid2), dim3(NT2), lds2, st, (cplx<T>*)out,
+                     nwork, px, np, nblk, twp<T>(tb, 0));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   return hipSuccess;
 }
 

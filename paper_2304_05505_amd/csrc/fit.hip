@@ -16,22 +16,20 @@ exx_status get_tables(exx_context* h, const Geom& g, Tables* t, hipStream_t st) 
     nroot += (size_t)g.n[a] * g.N[a];
     ntw += (size_t)g.n[a];
   }
-  size_t bytes = nroot * sizeof(double2) + ntw * (sizeof(double2) + sizeof(float2)) + 256;
-  bool same = h->tables != nullptr;
-  for (int a = 0; a < 6; ++a) same = same && key[a] == h->tab_key[a];
-  if (!same) {
-    if (h->tables_cap < bytes) {
-      if (h->tables) {
-        hipError_t e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_check(h, e, "hipStreamSynchronize");
-        (void)hipFree(h->tables);
-        h->tables = nullptr;
-        h->tables_cap = 0;
-      }
-      hipError_t e = hipMalloc(&h->tables, bytes);
-      if (e != hipSuccess) return fail(h, EXX_ERR_NOMEM, "table allocation failed");
-      h->tables_cap = bytes;
+  const exx_context::TabEntry* hit = nullptr;
+  for (const auto& te : h->tabs) {
+    bool same = true;
+    for (int a = 0; a < 6; ++a) same = same && te.key[a] == key[a];
+    if (same) {
+      hit = &te;
+      break;
     }
+  }
+  if (!hit) {
+    size_t bytes = nroot * sizeof(double2) + ntw * (sizeof(double2) + sizeof(float2)) + 256;
+    void* buf = nullptr;
+    hipError_t e = hipMalloc(&buf, bytes);
+    if (e != hipSuccess) return fail(h, EXX_ERR_NOMEM, "table allocation failed");
     std::vector<double2> r64;
     std::vector<double2> w64;
     std::vector<float2> w32;
@@ -49,20 +47,29 @@ exx_status get_tables(exx_context* h, const Geom& g, Tables* t, hipStream_t st) 
         w32.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
       }
     }
-    char* base = (char*)h->tables;
-    // synchronous upload: tables change only with the geometry
-    hipError_t e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = hipMemcpy(base, r64.data(), r64.size() * sizeof(double2), hipMemcpyHostToDevice);
+    char* base = (char*)buf;
+    // synchronous upload, once per shape (never inside a captured sequence)
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+      e = hipMemcpy(base, r64.data(), r64.size() * sizeof(double2), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(base + nroot * sizeof(double2), w64.data(), w64.size() * sizeof(double2),
                     hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(base + (nroot + ntw) * sizeof(double2), w32.data(), w32.size() * sizeof(float2),
                     hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_check(h, e, "table upload");
-    for (int a = 0; a < 6; ++a) h->tab_key[a] = key[a];
+    if (e != hipSuccess) {
+      (void)hipFree(buf);
+      return hip_check(h, e, "table upload");
+    }
+    exx_context::TabEntry te;
+    for (int a = 0; a < 6; ++a) te.key[a] = key[a];
+    te.buf = buf;
+    te.bytes = bytes;
+    h->tabs.push_back(te);
+    hit = &h->tabs.back();
   }
-  const double2* r = (const double2*)h->tables;
+  const double2* r = (const double2*)hit->buf;
   const double2* w = r + nroot;
   const float2* w2 = (const float2*)(w + ntw);
   size_t o1 = 0, o2 = 0;
