@@ -186,6 +186,44 @@ exx_status exx_select_points(exx_handle_t h, const exx_cell* cell, const void* p
                              int32_t* pts, int32_t* n_pivot, hipStream_t stream);
 
 /*
+ * exx_build_batched -- many independent K-builds (cells of different shapes,
+ * k-meshes and sizes) in one call, each exactly as exx_build. All items use
+ * the same precision mode. The handle's scratch is sized once for the
+ * largest item and the items run one after another on `stream`.
+ *
+ * flags:
+ *   EXX_BATCH_GRAPH  record the whole batch once into a HIP graph (stream
+ *                    capture) and launch it as one graph; a later call with
+ *                    the same items (same shapes and pointers) and precision
+ *                    replays the cached graph. No allocation or host copy
+ *                    happens inside the recorded sequence. Needs a
+ *                    non-default stream (EXX_ERR_ARG otherwise).
+ *   EXX_BATCH_TUNE   before the first launch, time the candidate wave tiles
+ *                    of the two grid-sized GEMMs (Gamma^n and the fit solve)
+ *                    once per size class (n_isdf, N_g, n_occ, N_k) and keep
+ *                    the fastest in the handle; later builds of the same
+ *                    class use it.
+ *
+ *   items  [n] host array; every pointer in it is device memory as in
+ *          exx_build (psi_grid, occ_pts, ao_pts, pts in; K, Ex, rank out)
+ */
+typedef struct {
+  exx_cell cell;
+  const void* psi_grid;
+  const void* occ_pts;
+  const void* ao_pts;
+  const int32_t* pts;
+  void* K;
+  double* Ex;
+  int32_t* rank;
+} exx_batch_item;
+
+#define EXX_BATCH_GRAPH 1
+#define EXX_BATCH_TUNE 2
+exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_batch_item* items,
+                             exx_prec prec, int32_t flags, hipStream_t stream);
+
+/*
  * Per-phase timing (instrumentation, not part of the method). When enabled,
  * the library records a pair of HIP events on the call's stream around each
  * phase of every subsequent call. exx_phase_times synchronises on those

@@ -245,7 +245,7 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
   hipError_t e;
   {
     PhaseTimer pt(h, PH_FFT, st);
-    e = launch_fft3d<T>(g, tb, xi, F, (long)g.nk * g.ni, st);
+    e = launch_fft3d<T>(g, tb, xi, F, (long)g.nk * g.ni, h->ncu, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {
@@ -300,6 +300,8 @@ exx_status setup(exx_context* h, const exx_cell* cell, exx_prec prec, bool build
   if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  e = fft_prepare(&h->ncu);
+  if (e != hipSuccess) return hip_check(h, e, "FFT set-up");
   *g = make_geom(*cell);
   *L = layout(*g, prec, build);
   *ws = (char*)ws_get(h, L->total, &s);
@@ -335,6 +337,7 @@ exx_status exx_destroy(exx_handle_t h) {
   (void)hipDeviceSynchronize();
   if (h->ws.base) (void)hipFree(h->ws.base);
   for (auto& te : h->tabs) (void)hipFree(te.buf);
+  for (auto& ge : h->graphs) (void)hipGraphExecDestroy(ge.exec);
   if (h->small) (void)hipFree(h->small);
   for (auto& r : h->recs) {
     (void)hipEventDestroy(r.a);
@@ -472,6 +475,200 @@ exx_status exx_phase_times(exx_handle_t h, double* ms, int32_t* calls, int32_t n
   h->recs.clear();
   return st;
 }
+
+}  // extern "C"
+
+namespace {
+
+exx_status build_one(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
+                     exx_prec prec, const exx_batch_item& it, hipStream_t st) {
+  void* xi = ws + L.grid2;
+  void* S = ws + L.S2;
+  void* V = ws + L.V2;
+  exx_status s;
+  if (prec == EXX_F64) {
+    s = fit_impl<double, double>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
+                                 st);
+    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, it.pts, V, true, st);
+  } else if (prec == EXX_MIXED) {
+    s = fit_impl<double, float>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
+                                st);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, it.pts, V, true, st);
+  } else {
+    s = fit_impl<float, float>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
+                               st);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, it.pts, V, false, st);
+  }
+  if (s != EXX_OK) return s;
+  return buildK_impl(h, g, ws, L, it.ao_pts, it.occ_pts, V, it.K, it.Ex, st);
+}
+
+void tune_key(const Geom& g, exx_prec prec, long* key) {
+  key[0] = g.ni;
+  key[1] = g.ng;
+  key[2] = g.no;
+  key[3] = g.nk;
+  key[4] = (long)prec;
+}
+
+const exx_context::Tune* find_tune(const exx_context* h, const long* key) {
+  for (const auto& t : h->tuned) {
+    bool same = true;
+    for (int i = 0; i < 5; ++i) same = same && t.key[i] == key[i];
+    if (same) return &t;
+  }
+  return nullptr;
+}
+
+// time the candidate wave tiles of the Gamma and solve GEMMs on one real build
+exx_status autotune(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
+                    exx_prec prec, const exx_batch_item& it, hipStream_t st) {
+  long key[5];
+  tune_key(g, prec, key);
+  if (find_tune(h, key)) return EXX_OK;
+  const int cand[3] = {22, 24, 42};
+  double best_g = 1e300, best_s = 1e300;
+  int tg = h->tile_gamma, ts = h->tile_solve;
+  const int sg = h->tile_gamma, ss = h->tile_solve;
+  const bool timing = h->timing;
+  for (int c : cand) {
+    h->tile_gamma = h->tile_solve = c;
+    exx_status s = exx_set_timing(h, 1);
+    if (s != EXX_OK) break;
+    s = build_one(h, g, tb, ws, L, prec, it, st);
+    double ms[EXX_NPHASE];
+    int32_t calls[EXX_NPHASE];
+    exx_status s2 = exx_phase_times(h, ms, calls, EXX_NPHASE);
+    if (s != EXX_OK || s2 != EXX_OK) {
+      h->tile_gamma = sg;
+      h->tile_solve = ss;
+      exx_set_timing(h, timing ? 1 : 0);
+      return s != EXX_OK ? s : s2;
+    }
+    if (ms[PH_GAMMA] < best_g) {
+      best_g = ms[PH_GAMMA];
+      tg = c;
+    }
+    if (ms[PH_SOLVE] < best_s) {
+      best_s = ms[PH_SOLVE];
+      ts = c;
+    }
+  }
+  exx_set_timing(h, timing ? 1 : 0);
+  h->tile_gamma = sg;
+  h->tile_solve = ss;
+  exx_context::Tune t;
+  for (int i = 0; i < 5; ++i) t.key[i] = key[i];
+  t.gamma = tg;
+  t.solve = ts;
+  h->tuned.push_back(t);
+  return EXX_OK;
+}
+
+}  // namespace
+
+extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_batch_item* items,
+                                        exx_prec prec, int32_t flags, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (n < 0 || (n > 0 && !items)) return fail(h, EXX_ERR_ARG, "exx_build_batched: bad item list");
+  if (n == 0) return EXX_OK;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  e = fft_prepare(&h->ncu);
+  if (e != hipSuccess) return hip_check(h, e, "FFT set-up");
+  // validate everything and size the scratch before anything is launched
+  std::vector<Geom> geo(n);
+  std::vector<Layout> lay(n);
+  std::vector<Tables> tabs(n);
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    const exx_batch_item& it = items[i];
+    exx_status s = check_cell(h, &it.cell, prec);
+    if (s != EXX_OK) return fail(h, s, "item " + std::to_string(i) + ": " + h->err);
+    if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
+    if (!it.psi_grid || !it.occ_pts || !it.ao_pts || !it.pts || !it.K || !it.Ex || !it.rank)
+      return fail(h, EXX_ERR_ARG, "item " + std::to_string(i) + ": null array");
+    geo[i] = make_geom(it.cell);
+    lay[i] = layout(geo[i], prec, true);
+    need = lay[i].total > need ? lay[i].total : need;
+  }
+  exx_status s;
+  char* ws = (char*)ws_get(h, need, &s);
+  if (s != EXX_OK) return s;
+  for (int i = 0; i < n; ++i) {
+    s = get_tables(h, geo[i], &tabs[i], stream);
+    if (s != EXX_OK) return s;
+  }
+  if (flags & EXX_BATCH_TUNE) {
+    for (int i = 0; i < n; ++i) {
+      s = autotune(h, geo[i], tabs[i], ws, lay[i], prec, items[i], stream);
+      if (s != EXX_OK) return s;
+    }
+  }
+  auto run_all = [&]() -> exx_status {
+    const int sg = h->tile_gamma, ss = h->tile_solve;
+    for (int i = 0; i < n; ++i) {
+      long key[5];
+      tune_key(geo[i], prec, key);
+      if (const exx_context::Tune* t = find_tune(h, key)) {
+        h->tile_gamma = t->gamma;
+        h->tile_solve = t->solve;
+      }
+      exx_status r = build_one(h, geo[i], tabs[i], ws, lay[i], prec, items[i], stream);
+      h->tile_gamma = sg;
+      h->tile_solve = ss;
+      if (r != EXX_OK) return r;
+    }
+    return EXX_OK;
+  };
+  if (!(flags & EXX_BATCH_GRAPH)) return run_all();
+  if (stream == nullptr)
+    return fail(h, EXX_ERR_ARG, "EXX_BATCH_GRAPH needs a non-default stream (capture)");
+
+  // signature: precision, workspace base and every item field
+  std::vector<long> sig;
+  sig.push_back((long)prec);
+  sig.push_back((long)(size_t)ws);
+  for (int i = 0; i < n; ++i) {
+    const exx_batch_item& it = items[i];
+    const int32_t* c = (const int32_t*)&it.cell;
+    for (size_t k = 0; k < sizeof(exx_cell) / sizeof(int32_t); ++k) sig.push_back(c[k]);
+    for (const void* p : {(const void*)it.psi_grid, it.occ_pts, it.ao_pts, (const void*)it.pts,
+                          (const void*)it.K, (const void*)it.Ex, (const void*)it.rank})
+      sig.push_back((long)(size_t)p);
+    long key[5];
+    tune_key(geo[i], prec, key);
+    const exx_context::Tune* t = find_tune(h, key);
+    sig.push_back(t ? t->gamma * 100 + t->solve : 0);
+  }
+  for (const auto& ge : h->graphs)
+    if (ge.sig == sig) return hip_check(h, hipGraphLaunch(ge.exec, stream), "hipGraphLaunch");
+  const bool timing = h->timing;
+  h->timing = false;  // no event records inside the captured sequence
+  e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    h->timing = timing;
+    return hip_check(h, e, "hipStreamBeginCapture");
+  }
+  s = run_all();
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(stream, &graph);
+  h->timing = timing;
+  if (s != EXX_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return hip_check(h, e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_check(h, e, "hipGraphInstantiate");
+  h->graphs.push_back({sig, exec});
+  return hip_check(h, hipGraphLaunch(exec, stream), "hipGraphLaunch");
+}
+
+extern "C" {
 
 exx_status exx_select_points(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
                              int32_t* pts, int32_t* n_pivot, hipStream_t stream) {

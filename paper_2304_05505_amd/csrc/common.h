@@ -112,6 +112,19 @@ struct exx_context {
   // wave tiles of the grid GEMMs (see zgemm_nn_grid)
   int tile_gamma = 22;
   int tile_solve = 22;
+  int ncu = 256;
+  // autotuned wave tiles per size class: key (ni, ng, no, nk, prec) -> (gamma, solve)
+  struct Tune {
+    long key[5];
+    int gamma, solve;
+  };
+  std::vector<Tune> tuned;
+  // cached graphs of batched builds, keyed by a signature of the batch
+  struct GraphEntry {
+    std::vector<long> sig;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
   // per-phase timing: recorded (phase, start, stop) events and a free pool
   bool timing = false;
   struct Rec {
@@ -213,10 +226,12 @@ hipError_t launch_chol_blocked(const Geom& g, double2* A, int32_t* keep, int32_t
 hipError_t launch_tri_inv_blocked(const Geom& g, const double2* Lf, const int32_t* keep,
                                   double2* W, double2* T, hipStream_t st);
 
-// 3-D FFT of nfun functions (forward); pass 1 reads `in`, writes `out`; pass 2 in place
+// 3-D FFT of nfun functions (forward); pass 1 reads `in`, writes `out`; pass 2 in place.
+// fft_prepare sets kernel attributes once and returns the CU count.
+hipError_t fft_prepare(int* ncu);
 template <typename T>
 hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
-                        hipStream_t st);
+                        int ncu, hipStream_t st);
 bool fft_supported(const Geom& g, bool fp64);
 
 // Coulomb contraction: V^m (Bloch gauge) from F^m; f64mma: FP64 matrix cores for FP32 storage

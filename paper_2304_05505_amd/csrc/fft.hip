@@ -319,67 +319,80 @@ bool fft_supported(const Geom& g, bool fp64) {
   return true;
 }
 
+// Raise the dynamic-LDS limit of the four FFT kernels to what grids up to the
+// supported maximum need. Called once per process before any launch (and
+// therefore never inside a captured launch sequence).
+static hipError_t fft_attributes() {
+  static hipError_t done = hipErrorNotReady;
+  if (done != hipErrorNotReady) return done;
+  const int l1d = (FFT_MAXPTS + 2 * 128) * (int)sizeof(double2);
+  const int l2d = (FFT_MAXX * FFT_CB + FFT_MAXX) * (int)sizeof(double2);
+  const int l1f = (FFT_MAXPTS + 2 * 128) * (int)sizeof(float2);
+  const int l2f = (FFT_MAXX * FFT_CB + FFT_MAXX) * (int)sizeof(float2);
+  hipError_t e = hipFuncSetAttribute((const void*)fft_yz1_kernel<double>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, l1d);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)fft_x1_kernel<double>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l2d);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)fft_yz_kernel<float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l1f);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)fft_x_kernel<float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l2f);
+  done = e;
+  return e;
+}
+
+hipError_t fft_prepare(int* ncu) {
+  hipError_t e = fft_attributes();
+  if (e != hipSuccess) return e;
+  int dev = 0, v = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess && v > 0) *ncu = v;
+  return e;
+}
+
 template <typename T>
 hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
-                        hipStream_t st) {
+                        int ncu, hipStream_t st) {
   Plan1 px = plan_for(g.n[0]), py = plan_for(g.n[1]), pz = plan_for(g.n[2]);
   const int np = g.n[1] * g.n[2];
   size_t lds1 = (size_t)(np + g.n[1] + g.n[2]) * sizeof(cplx<T>);
   size_t lds2 = (size_t)(g.n[0] * FFT_CB + g.n[0]) * sizeof(cplx<T>);
-  hipError_t e = hipFuncSetAttribute((const void*)fft_yz_kernel<T>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)fft_x_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds2);
-  if (e != hipSuccess) return e;
   const long nplanes = nfun * g.n[0];
-  const int np1 = np;
-  // FP64 planes fill the register file; they run one plane per workgroup. FP32
-  // planes run in persistent workgroups that prefetch the next plane.
+  const int nblk = (np + FFT_CB - 1) / FFT_CB;
+  hipError_t e;
   if (sizeof(T) == 8) {
-    e = hipFuncSetAttribute((const void*)fft_yz1_kernel<T>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)fft_x1_kernel<T>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
-    if (e != hipSuccess) return e;
+    // FP64 planes fill the register file; they run one plane per workgroup
     hipLaunchKernelGGL(fft_yz1_kernel<T>, dim3((unsigned)nplanes), dim3(NT1), lds1, st,
                        (const cplx<T>*)in, (cplx<T>*)out, py, pz, twp<T>(tb, 1), twp<T>(tb, 2));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nblk1 = (np1 + FFT_CB - 1) / FFT_CB;
-    hipLaunchKernelGGL(fft_x1_kernel<T>, dim3((unsigned)(nfun * nblk1)), dim3(NT2), lds2, st,
-                       (cplx<T>*)out, px, np1, nblk1, twp<T>(tb, 0));
+    hipLaunchKernelGGL(fft_x1_kernel<T>, dim3((unsigned)(nfun * nblk)), dim3(NT2), lds2, st,
+                       (cplx<T>*)out, px, np, nblk, twp<T>(tb, 0));
     return hipGetLastError();
   }
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      ncu = v;
-  }
-  // resident workgroups per CU bounded by LDS (160 KB per CU)
-  const long wpc1 = lds1 > 0 ? std::max<long>(1, (160L * 1024) / (long)lds1) : 1;
-  const long grid1 = std::min<long>(nplanes, ncu * std::min<long>(wpc1, 4) * 2);
+  // FP32 planes: persistent workgroups that prefetch the next plane
+  const long wpc1 = std::max<long>(1, (160L * 1024) / (long)lds1);
+  const long grid1 = std::min<long>(nplanes, (long)ncu * std::min<long>(wpc1, 4) * 2);
   hipLaunchKernelGGL(fft_yz_kernel<T>, dim3((unsigned)grid1), dim3(NT1), lds1, st,
                      (const cplx<T>*)in, (cplx<T>*)out, nplanes, py, pz, twp<T>(tb, 1),
                      twp<T>(tb, 2));
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int nblk = (np + FFT_CB - 1) / FFT_CB;
   const long nwork = nfun * nblk;
   const long wpc2 = std::max<long>(1, (160L * 1024) / (long)lds2);
-  const long grid2 = std::min<long>(nwork, ncu * std::min<long>(wpc2, 8) * 2);
+  const long grid2 = std::min<long>(nwork, (long)ncu * std::min<long>(wpc2, 8) * 2);
   hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)grid2), dim3(NT2), lds2, st, (cplx<T>*)out,
                      nwork, px, np, nblk, twp<T>(tb, 0));
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 template hipError_t launch_fft3d<double>(const Geom&, const Tables&, const void*, void*, long,
-                                         hipStream_t);
-template hipError_t launch_fft3d<float>(const Geom&, const Tables&, const void*, void*, long,
+                                         int, hipStream_t);
+template hipError_t launch_fft3d<float>(const Geom&, const Tables&, const void*, void*, long, int,
                                         hipStream_t);
 
 }  // namespace exx

@@ -41,7 +41,10 @@ EXPORTED = (
     "exx_select_points",
     "exx_set_timing",
     "exx_phase_times",
+    "exx_build_batched",
 )
+
+EXX_BATCH_GRAPH, EXX_BATCH_TUNE = 1, 2
 
 PHASES = ("G", "S", "cholesky", "pinv", "gamma", "kcorr", "solve", "fft", "coulomb",
           "kconv", "K", "energy")
@@ -55,6 +58,19 @@ class ExxCell(ctypes.Structure):
         ("n_occ", ctypes.c_int32),
         ("n_ao", ctypes.c_int32),
         ("n_isdf", ctypes.c_int32),
+    ]
+
+
+class ExxBatchItem(ctypes.Structure):
+    _fields_ = [
+        ("cell", ExxCell),
+        ("psi_grid", ctypes.c_void_p),
+        ("occ_pts", ctypes.c_void_p),
+        ("ao_pts", ctypes.c_void_p),
+        ("pts", ctypes.c_void_p),
+        ("K", ctypes.c_void_p),
+        ("Ex", ctypes.c_void_p),
+        ("rank", ctypes.c_void_p),
     ]
 
 
@@ -83,6 +99,8 @@ def _load():
         "exx_build": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "exx_select_points": ([vp, cellp, vp, vp, vp, vp], ctypes.c_int),
         "exx_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "exx_build_batched": ([vp, ctypes.c_int32, ctypes.POINTER(ExxBatchItem), ctypes.c_int,
+                               ctypes.c_int32, vp], ctypes.c_int),
         "exx_phase_times": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                              ctypes.c_int32], ctypes.c_int),
     }
@@ -254,3 +272,29 @@ def exx_select_points(h: Handle, cell: ExxCell, psi_grid, pts, n_pivot):
         _ptr(n_pivot, "n_pivot", torch.int32, (1,), d),
     )
     h._check(_lib.exx_select_points(h.raw, ctypes.byref(cell), *args, _stream(d)))
+
+
+def exx_build_batched(h: Handle, items, prec: int, flags: int = 0, stream=None):
+    """Run many K-builds. ``items``: list of dicts with keys cell, psi_grid, occ_pts,
+    ao_pts, pts, K, Ex, rank (device tensors as for exx_build). ``stream``: a
+    torch.cuda.Stream (required with EXX_BATCH_GRAPH; the current stream otherwise)."""
+    d = h.device
+    arr = (ExxBatchItem * len(items))()
+    for i, it in enumerate(items):
+        c = it["cell"]
+        nk, ng, ni, no, na = _nk(c), _ng(c), c.n_isdf, c.n_occ, c.n_ao
+        arr[i].cell = c
+        arr[i].psi_grid = _ptr(it["psi_grid"], "psi_grid", _psi_dtype(prec), (nk, no, ng), d)
+        arr[i].occ_pts = _ptr(it["occ_pts"], "occ_pts", torch.complex128, (nk, ni, no), d)
+        arr[i].ao_pts = _ptr(it["ao_pts"], "ao_pts", torch.complex128, (nk, ni, na), d)
+        arr[i].pts = _ptr(it["pts"], "pts", torch.int32, (ni,), d)
+        arr[i].K = _ptr(it["K"], "K", torch.complex128, (nk, na, na), d)
+        arr[i].Ex = _ptr(it["Ex"], "Ex", torch.float64, (1,), d)
+        arr[i].rank = _ptr(it["rank"], "rank", torch.int32, (nk,), d)
+    if stream is None:
+        if flags & EXX_BATCH_GRAPH:
+            raise ValueError("EXX_BATCH_GRAPH needs an explicit non-default torch.cuda.Stream")
+        st = _stream(d)
+    else:
+        st = stream.cuda_stream
+    h._check(_lib.exx_build_batched(h.raw, len(items), arr, prec, flags, st))

@@ -1,0 +1,126 @@
+"""Batched builds (exx_build_batched): heterogeneous cells in one call, with and
+without graph capture and tile autotuning, against the single-cell build and
+the FP64 oracle. Graph replays are checked one by one with eager work and
+synchronisations between them."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import select, thc
+
+pytestmark = pytest.mark.gpu
+
+
+def _cells():
+    return [
+        synth.make_config(1),
+        synth.make_random_cell((6.0, 6.5, 7.0), 2, (12, 15, 10), (2, 2, 2), 3, 30, (12, 1, 1)),
+        synth.make_random_cell((5.0, 6.0, 7.5), 3, (16, 18, 20), (3, 2, 1), 5, 100, (12, 2, 1)),
+        synth.make_random_cell((5.0, 5.0, 5.0), 2, (10, 12, 9), (3, 3, 3), 2, 40, (12, 3, 1)),
+    ]
+
+
+@pytest.fixture(scope="module")
+def batch():
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    cases = []
+    for cell in _cells():
+        C = synth.orbital_coeffs(cell)
+        psi = synth.orbitals_on_grid(cell, C)
+        pts, _ = select.select_points(psi, cell.n_isdf)
+        ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+        ref = thc.thc_oo_k(cell.L, cell.grid, cell.kmesh, psi, pts, ao)
+        t = {
+            "cell": exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, len(pts)),
+            "psi64": torch.from_numpy(psi).to(dev),
+            "occ_pts": torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev),
+            "ao_pts": torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+            "pts": torch.from_numpy(pts.astype(np.int32)).to(dev),
+            "K": torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128, device=dev),
+            "Ex": torch.empty((1,), dtype=torch.float64, device=dev),
+            "rank": torch.empty((cell.N_k,), dtype=torch.int32, device=dev),
+        }
+        cases.append((cell, ref, t))
+    return cases
+
+
+def _items(cases, prec):
+    import torch
+
+    out = []
+    for cell, ref, t in cases:
+        psi = t["psi64"] if prec in ("f64", "mixed") else t["psi64"].to(torch.complex64)
+        out.append({"cell": t["cell"], "psi_grid": psi, "occ_pts": t["occ_pts"], "ao_pts": t["ao_pts"],
+                    "pts": t["pts"], "K": t["K"], "Ex": t["Ex"], "rank": t["rank"]})
+    return out
+
+
+def _single(h, exx, it, prec):
+    import torch
+
+    K = torch.empty_like(it["K"])
+    Ex = torch.empty_like(it["Ex"])
+    rank = torch.empty_like(it["rank"])
+    exx.exx_build(h, it["cell"], exx.PREC[prec], it["psi_grid"], it["occ_pts"], it["ao_pts"],
+                  it["pts"], K, Ex, rank)
+    torch.cuda.synchronize()
+    return K.cpu().numpy(), float(Ex.cpu()[0]), rank.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("flags", [0, 2, 1, 3])
+def test_batched_equals_single_builds(batch, prec, flags, gpu):
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    h = exx.Handle(0)
+    items = _items(batch, prec)
+    singles = [_single(h, exx, it, prec) for it in items]
+    stream = torch.cuda.Stream() if flags & exx.EXX_BATCH_GRAPH else None
+    reps = 3 if flags & exx.EXX_BATCH_GRAPH else 1
+    for rep in range(reps):
+        for it in items:
+            it["K"].zero_()
+            it["Ex"].zero_()
+            it["rank"].zero_()
+        torch.cuda.synchronize()
+        if stream is not None:
+            stream.wait_stream(torch.cuda.current_stream())
+            exx.exx_build_batched(h, items, exx.PREC[prec], flags, stream=stream)
+            stream.synchronize()
+        else:
+            exx.exx_build_batched(h, items, exx.PREC[prec], flags)
+            torch.cuda.synchronize()
+        # eager work between replays
+        _ = (items[0]["K"].abs().sum()).item()
+        for (cell, ref, t), it, (Ks, Es, rs) in zip(batch, items, singles):
+            K = it["K"].cpu().numpy()
+            Ex = float(it["Ex"].cpu()[0])
+            assert np.array_equal(it["rank"].cpu().numpy(), rs)
+            assert np.abs(K - Ks).max() <= 1e-13 * np.abs(Ks).max(), f"rep {rep}"
+            assert abs(Ex - Es) <= 1e-13 * abs(Es), f"rep {rep}"
+            assert np.array_equal(rs, ref["rank"])
+            # same tolerance rule as the parity tests: 64 eps64 cond(S_RR) relative (FP64);
+            # the mixed mode adds FP32 storage of xi (eps32 relative, amplified like the solve)
+            conds = []
+            for m in range(ref["S"].shape[0]):
+                R = np.flatnonzero(ref["keep"][m])
+                conds.append(np.linalg.cond(ref["S"][m][np.ix_(R, R)]))
+            eps = np.finfo(np.float64).eps if prec == "f64" else np.finfo(np.float32).eps
+            tol = max(1e-12, 64 * eps * max(conds))
+            assert abs(Ex - ref["Ex"]) <= tol * abs(ref["Ex"])
+
+
+def test_graph_requires_a_stream(batch, gpu):
+    from paper_2304_05505_amd import exx
+
+    h = exx.Handle(0)
+    items = _items(batch, "f64")
+    with pytest.raises(ValueError):
+        exx.exx_build_batched(h, items, exx.EXX_F64, exx.EXX_BATCH_GRAPH)
