@@ -61,63 +61,106 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
       aim[i][j] = d4{0, 0, 0, 0};
     }
 
-  // NPF-deep register pipeline: slot s holds the fragments of k-step s (mod NPF)
+  // NPF-deep register pipeline: slot s holds the fragments of k-step s (mod NPF).
+  // Loads are unconditional with indices clamped into the operands: rows past M
+  // and columns past N only feed outputs that are never stored, and k past K is
+  // zeroed on the A side when the slot is consumed. With no branch or select
+  // between a load and its use, the wait before each k-step covers only that
+  // slot's loads. B fragments stay in their storage type until consumed.
   constexpr int NPF = 3;
-  double2 fa[NPF][WM], fb[NPF][WN];
-  auto load = [&](int k0, double2* xa, double2* xb) {
+  double2 fa[NPF][WM];
+  cplx<TB> fb[NPF][WN];
+  auto load = [&](int k0, double2* xa, cplx<TB>* xb) {
     const int k = k0 + lk;
+    const long kc = k < K ? k : K - 1;
 #pragma unroll
     for (int i = 0; i < WM; ++i) {
       const int r = row0 + i * 16 + li;
-      xa[i] = (r < M && k < K) ? A[(long)r * lda + k] : make_double2(0.0, 0.0);
+      xa[i] = A[(long)(r < M ? r : M - 1) * lda + kc];
     }
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
       const long c = col0 + j * 16 + li;
-      double2 v = make_double2(0.0, 0.0);
-      if (c < N && k < K) {
-        cplx<TB> s = B[(long)k * ldb + c];
-        v = make_double2((double)s.x, CONJB ? -(double)s.y : (double)s.y);
-      }
-      xb[j] = v;
+      xb[j] = B[kc * ldb + (c < N ? c : N - 1)];
     }
   };
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
-  for (int k0 = 0; k0 < K; k0 += 4 * NPF) {
+  const int niter = (K + 4 * NPF - 1) / (4 * NPF);
+  for (int it = 0; it < niter; ++it) {
 #pragma unroll
     for (int s = 0; s < NPF; ++s) {
-      const int kk = k0 + 4 * s;
-      if (kk < K) {
+      const bool kin = 4 * (it * NPF + s) + lk < K;
+      double br[WN], bi[WN];
 #pragma unroll
-        for (int i = 0; i < WM; ++i) {
-          const double ar = fa[s][i].x, ai = fa[s][i].y, nai = -fa[s][i].y;
-#pragma unroll
-          for (int j = 0; j < WN; ++j) {
-            are[i][j] = mfma64(ar, fb[s][j].x, are[i][j]);
-            are[i][j] = mfma64(nai, fb[s][j].y, are[i][j]);
-            aim[i][j] = mfma64(ar, fb[s][j].y, aim[i][j]);
-            aim[i][j] = mfma64(ai, fb[s][j].x, aim[i][j]);
-          }
-        }
-        if (kk + 4 * NPF < K) load(kk + 4 * NPF, fa[s], fb[s]);
+      for (int j = 0; j < WN; ++j) {
+        br[j] = (double)fb[s][j].x;
+        bi[j] = CONJB ? -(double)fb[s][j].y : (double)fb[s][j].y;
       }
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const double ar = kin ? fa[s][i].x : 0.0, ai = kin ? fa[s][i].y : 0.0;
+        const double nai = -ai;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          are[i][j] = mfma64(ar, br[j], are[i][j]);
+          are[i][j] = mfma64(nai, bi[j], are[i][j]);
+          aim[i][j] = mfma64(ar, bi[j], aim[i][j]);
+          aim[i][j] = mfma64(ai, br[j], aim[i][j]);
+        }
+      }
+      // refill the slot with k-step (it + 1) * NPF + s (masked at use past K). The
+      // scheduling barriers keep the refill after this slot's MFMAs, so it lands
+      // in the same registers and the loop carries no copies.
+      __builtin_amdgcn_sched_barrier(0);
+      load(4 * ((it + 1) * NPF + s), fa[s], fb[s]);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   // D layout of v_mfma_f64_16x16x4_f64: register v of a lane holds row
   // 4*v + lane/16, column lane%16 of the 16x16 block
+  if constexpr (sizeof(TC) == sizeof(double)) {
 #pragma unroll
-  for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = row0 + i * 16 + 4 * v + lk;
-      if (r >= M) continue;
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + i * 16 + 4 * v + lk;
+        if (r >= M) continue;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          const long c = col0 + j * 16 + li;
+          if (c < N) C[(long)r * ldc + c] = mk<TC>(are[i][j][v], aim[i][j][v]);
+        }
+      }
+  } else {
+    // Narrowing needs the accumulators in VALU registers. Each lane round-trips
+    // its own values through this wave's LDS slice (the LDS write takes matrix
+    // registers directly, and LDS accesses of one wave complete in order); a
+    // direct conversion makes the compiler carry the accumulators in VALU
+    // registers and copy them in and out of the matrix registers on every
+    // iteration.
+    __shared__ double stage[4][2][64 * 4];
+    typedef __attribute__((address_space(3))) volatile double lds_f64;
+    lds_f64* sre = (lds_f64*)stage[wave][0];
+    lds_f64* sim = (lds_f64*)stage[wave][1];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
-        const long c = col0 + j * 16 + li;
-        if (c < N) C[(long)r * ldc + c] = mk<TC>((TC)are[i][j][v], (TC)aim[i][j][v]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          sre[v * 64 + lane] = are[i][j][v];
+          sim[v * 64 + lane] = aim[i][j][v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double xr = sre[v * 64 + lane], xi = sim[v * 64 + lane];
+          const int r = row0 + i * 16 + 4 * v + lk;
+          const long c = col0 + j * 16 + li;
+          if (r < M && c < N) C[(long)r * ldc + c] = mk<TC>((TC)xr, (TC)xi);
+        }
       }
-    }
+  }
 }
 
 template <typename TB, typename TC, int WM, int WN, int CONJB>
@@ -156,6 +199,7 @@ hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                          hipStream_t st, int tile) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (K <= 0) return hipErrorInvalidValue;
   if (conjB)
     return run_nn_tile<TB, TC, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
   return run_nn_tile<TB, TC, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
