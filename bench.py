@@ -57,6 +57,51 @@ def algorithmic_work(cell, n_isdf, prec):
     }
 
 
+# HBM traffic of the dominant kernel of each phase at this workload, from two
+# rocprofv3 counter runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; KiB
+# per dispatch). A plain 1 GiB device copy reads 524 313 KiB of FETCH_SIZE and
+# 1 048 576 KiB of WRITE_SIZE on MI355X, so fetch counts are scaled by 2.0 and write
+# counts by 1.0. Each entry names the source file of its kernels and that file's
+# SHA-256 prefix when the counters were taken; a changed file reports null.
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524312.8125, 1.0
+TRAFFIC = {
+    # (phase, path): (source, sha256[:16], FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ("solve", "f64"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 16499298.2, 12757500.0),
+    ("solve", "mixed"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 16195238.8, 6420254.4),
+    ("solve", "f32"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 10106401.2, 6425021.1),
+    ("gamma", "f64"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 1311050.3, 12757500.0),
+    ("gamma", "mixed"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 1311050.3, 12757500.0),
+    ("gamma", "f32"): ("gemm.hip", "04e1ff7ac33225d7", 5041303.9, 6378750.1),
+    ("coulomb", "f64"): ("coulomb.hip", "0ea60aa7eec985c6", 10739856.6, 243689.7),
+    ("coulomb", "mixed"): ("coulomb.hip", "0ea60aa7eec985c6", 4874858.5, 242664.6),
+    ("coulomb", "f32"): ("coulomb.hip", "0ea60aa7eec985c6", 10707815.6, 244540.2),
+    ("fft", "f64"): ("fft.hip", "e70bd9dd61c12049", 6390621.2 + 7579020.8, 12757536.3 + 12757500.0),
+    ("fft", "mixed"): ("fft.hip", "e70bd9dd61c12049", 3200645.2 + 4589710.8, 6381900.0 + 6778800.0),
+    ("fft", "f32"): ("fft.hip", "e70bd9dd61c12049", 3200645.2 + 4589710.8, 6381900.0 + 6778800.0),
+    ("kcorr", "f64"): ("fit.hip", "01c53048f397523a", 6379021.4, 12757500.0),
+    ("kcorr", "mixed"): ("fit.hip", "01c53048f397523a", 6379004.9, 12757500.0),
+    ("kcorr", "f32"): ("fit.hip", "01c53048f397523a", 3189587.6, 6378750.0),
+}
+
+
+def traffic_bytes(phase, path):
+    """HBM bytes per launch of the phase's kernel, or None if unmeasured or changed."""
+    import hashlib
+
+    ent = TRAFFIC.get((phase, path))
+    if ent is None:
+        return None
+    src, digest, fetch_kib, write_kib = ent
+    fn = os.path.join(ROOT, "paper_2304_05505_amd", "csrc", src)
+    try:
+        cur = hashlib.sha256(open(fn, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if cur != digest:
+        return None
+    return 1024.0 * (fetch_kib * FETCH_SCALE + write_kib * WRITE_SCALE)
+
+
 FP64_PHASES = {"f64": {"gamma", "solve", "coulomb", "K"}, "mixed": {"gamma", "solve", "K"},
                "f32": {"solve", "K"}}
 
@@ -67,14 +112,15 @@ def roofline(phases, work, prec, steps):
     ms, calls = phases[best]
     avg_s = ms / max(calls, 1) / 1e3
     kind, amount = work[best]
+    traffic = traffic_bytes(best, prec)
     if kind == "byte":
         achieved = amount / avg_s / 1e9
         return best, {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-                      "frac": achieved / PEAK["hbm_GBs"], "traffic": None}
+                      "frac": achieved / PEAK["hbm_GBs"], "traffic": traffic}
     achieved = amount / avg_s / 1e12
     peak = PEAK["fp64_TF"] if best in FP64_PHASES[prec] else PEAK["fp32_TF"]
     return best, {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                  "frac": achieved / peak, "traffic": None}
+                  "frac": achieved / peak, "traffic": traffic}
 
 
 def cpu_baseline(cell, psi, pts, ao):
@@ -105,6 +151,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", choices=("auto", "f64", "mixed", "f32"), default="auto")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiling target: one build per precision path and a 1 GiB device "
+                         "copy, no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the build is not sharded "
@@ -139,6 +188,24 @@ def main():
     t_occ = torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev)
     t_psi32 = t_psi64.to(torch.complex64)
 
+    if args.profile:
+        # one build per precision path, then a plain 1 GiB device copy whose
+        # counter readings calibrate the HBM traffic counters
+        K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+        Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+        rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+        for prec in ("f64", "mixed", "f32"):
+            t_psi = t_psi32 if prec == "f32" else t_psi64
+            exx.exx_build(h, c, exx.PREC[prec], t_psi, t_occ, t_ao, t_pts, K, Ex, rank)
+            torch.cuda.synchronize()
+            log(f"profile target [{prec}] done: Ex {float(Ex.cpu()[0]):.12f}")
+        src = torch.ones((1 << 27,), dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"profile target: copied {src.numel() * 8} bytes")
+        return
+
     results = {}
     for prec in ("f64", "mixed", "f32"):
         p = exx.PREC[prec]
@@ -150,19 +217,19 @@ def main():
         def step():
             exx.exx_build(h, c, p, t_psi, t_occ, t_ao, t_pts, K, Ex, rank)
 
+        # per-phase HIP events on the build's stream, recorded inside the timed
+        # region; the warmup steps fill the handle's event pool
+        h.set_timing(True)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        h.phase_times()
         log(f"[{prec}] warmup done")
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        # per-phase HIP-event timing on the build's stream, separate runs
-        h.set_timing(True)
-        for _ in range(args.steps):
-            step()
         phases = h.phase_times()
         h.set_timing(False)
         log(f"[{prec}] {args.steps} steps in {el:.3f} s; phases(ms/call): " +
