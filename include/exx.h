@@ -186,6 +186,118 @@ exx_status exx_select_points(exx_handle_t h, const exx_cell* cell, const void* p
                              int32_t* pts, int32_t* n_pivot, hipStream_t stream);
 
 /*
+ * Learned point selection. The paper picks the interpolation points by QRCP
+ * or k-means (Sec. 2.1 after Eq. 5); here a small network scores every grid
+ * point from three descriptors of the occupied density and a greedy
+ * non-maximum suppression turns the scores into N_ISDF points. It is trained
+ * to reproduce QRCP selections, and a fit-residual probe sends a cell back to
+ * QRCP (exx_select_points) when the proposal is poor.
+ *
+ * Network: 3 -> 64 -> 64 -> 1, SiLU after both hidden layers, output = logit.
+ * Parameters theta: EXX_MLP_NPARAM float32 values, in order W1 (64 x 3, row
+ * major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1). Evaluation rounds
+ * the weights W1, W2, w3 to bfloat16 (nearest even) and keeps the biases and
+ * all arithmetic in FP32. Features are float32 [N_g][3].
+ */
+#define EXX_MLP_NPARAM 4481
+
+/*
+ * exx_mlp_features -- descriptors of every grid point, from
+ *   rho(r) = (1/N_k) sum_{n,i} |psi_in(r)|^2:
+ *   f0 = ln(rho / mean_r rho)
+ *   f1 = ln|grad rho| - (4/3) ln rho (fourth-order periodic central differences)
+ *   f2 = sum |psi_in(r)|^4 / (sum |psi_in(r)|^2)^2 (local orbital weight)
+ * each standardised as (f_j - norm[2j]) / norm[2j+1].
+ *
+ *   psi_grid [N_k][n_occ][N_g] c128
+ *   norm     host [6] double: mean and scale of f0, f1, f2 (scales > 0)
+ *   feat     out [N_g][3] float32
+ */
+exx_status exx_mlp_features(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
+                            const double* norm, float* feat, hipStream_t stream);
+
+/*
+ * exx_mlp_forward -- score[i] = network logit of feat[i], i < n (n >= 0).
+ *   feat [n][3] float32, theta [EXX_MLP_NPARAM] float32, score out [n] float32
+ */
+exx_status exx_mlp_forward(exx_handle_t h, int64_t n, const float* feat, const float* theta,
+                           float* score, hipStream_t stream);
+
+/*
+ * exx_mlp_backward -- gradient of the weighted binary cross-entropy
+ *   L = sum_q w_q (softplus(s_q) - t_q s_q) / sum_q w_q,  w_q = 1 + wpos t_q,
+ * over the batch q < n of rows idx[q] of feat and target (rows 0..n-1 when
+ * idx is NULL), with respect to theta (through the bfloat16-rounded weights:
+ * the gradient of the rounded network is returned for the FP32 parameters).
+ * Per-block partial sums are reduced in a fixed order, so the result is
+ * deterministic. An idx entry outside [0, rows) contributes nothing.
+ *
+ *   idx    [n] int32 or NULL (then rows == n)
+ *   feat   [rows][3], target [rows] float32 (targets in [0, 1]); wpos >= 0
+ *   grad   out [EXX_MLP_NPARAM] float32;  loss out [1] double
+ */
+exx_status exx_mlp_backward(exx_handle_t h, int64_t n, const int32_t* idx, int64_t rows,
+                            const float* feat, const float* target, float wpos, const float* theta,
+                            float* grad, double* loss, hipStream_t stream);
+
+/*
+ * exx_mlp_adam -- one Adam step (Kingma and Ba) in place, all float32 [np]:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   theta -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps);  step >= 1.
+ */
+exx_status exx_mlp_adam(exx_handle_t h, int32_t np, float* theta, const float* grad, float* m,
+                        float* v, int32_t step, float lr, float beta1, float beta2, float eps,
+                        hipStream_t stream);
+
+/*
+ * exx_mlp_targets -- soft training targets t(r) = exp(-d(r)^2 / (2 sigma^2)), d
+ * the periodic minimum-image distance from grid point r to the nearest of the
+ * npts points pts (flat grid indices, 1 <= npts <= 2048); sigma > 0 in bohr.
+ *   target out [N_g] float32
+ */
+exx_status exx_mlp_targets(exx_handle_t h, const exx_cell* cell, const int32_t* pts, int32_t npts,
+                           double sigma, float* target, hipStream_t stream);
+
+/*
+ * exx_mlp_nms -- greedy selection of k points (1 <= k <= N_g): the highest
+ * score first (NaN below every number, ties to the smaller index), each pick
+ * removing the unpicked points closer than h = (Omega/k)^{1/3}/2 (periodic
+ * minimum image); if fewer than k survive, the rest of the slots take the
+ * unpicked points in score order.
+ *   score [N_g] float32;  pts out [k] int32 in pick order
+ */
+exx_status exx_mlp_nms(exx_handle_t h, const exx_cell* cell, const float* score, int32_t k,
+                       int32_t* pts, hipStream_t stream);
+
+/*
+ * exx_mlp_probe -- relative fit residual of the point set pts (n_isdf points)
+ * on n_probe grid points r_j drawn by SplitMix64 from seed (j-th draw mod N_g):
+ *   resid = sum_j max(C(r_j,r_j) - C(r_j,P) C(P,P)^+ C(P,r_j), 0) / sum_j C(r_j,r_j)
+ * with C(r,r') = |Gamma(r,r')|^2, Gamma(r,r') = sum_{n,i} psi_in(r) conj psi_in(r'),
+ * the Gram matrix that QRCP pivots on (the Schur complement is the squared
+ * distance of the pair row at r_j from the span of the rows at the points);
+ * C(P,P)^+ uses the fit's Cholesky with pivot drop. 1 <= n_probe <= 8192,
+ * N_k n_occ <= 65536. Point indices outside [0, N_g) are clamped into it.
+ *   psi_grid [N_k][n_occ][N_g] c128;  pts [n_isdf] int32;  resid out [1] double
+ */
+exx_status exx_mlp_probe(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
+                         const int32_t* pts, int32_t n_probe, uint64_t seed, double* resid,
+                         hipStream_t stream);
+
+/*
+ * exx_select_points_mlp -- features, network, NMS for n_isdf points, then the
+ * probe (n_probe points, a fixed seed). If the residual exceeds tau (or is not
+ * a number) the points are recomputed by exx_select_points and
+ * *used_fallback = 1, else 0. Synchronises the stream to read the residual.
+ *   psi_grid, norm, theta as above;  pts out [n_isdf] int32
+ *   used_fallback  out, host int32;  resid_out  out, host double (may be NULL)
+ */
+exx_status exx_select_points_mlp(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
+                                 const double* norm, const float* theta, double tau,
+                                 int32_t n_probe, int32_t* pts, int32_t* used_fallback,
+                                 double* resid_out, hipStream_t stream);
+
+/*
  * exx_build_batched -- many independent K-builds (cells of different shapes,
  * k-meshes and sizes) in one call, each exactly as exx_build. All items use
  * the same precision mode. The handle's scratch is sized once for the

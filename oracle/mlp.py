@@ -13,13 +13,19 @@ occupied density instead, trained to reproduce QRCP selections:
   each standardised with fixed (mean, scale) constants;
 * network: 3 -> 64 -> 64 -> 1 with SiLU after the hidden layers; the score is
   the logit s(r);
-* targets: t(r) = exp(-d(r)^2 / (2 h^2)) with d the periodic minimum-image
-  distance to the nearest QRCP point and h = (Omega / N_ISDF)^{1/3} / 2;
+* targets: t(r) = exp(-d(r)^2 / (2 sigma^2)) with d the periodic minimum-image
+  distance to the nearest QRCP point and a given width sigma (the training
+  driver uses sigma = (Omega / N_ISDF)^{1/3} / 4, half the suppression radius);
 * loss: weighted binary cross-entropy
     L = sum_r w(r) [softplus(s) - t s] / sum_r w(r),  w = 1 + wpos t;
 * optimiser: Adam;
 * inference: greedy top-N_ISDF by score with non-maximum suppression within
-  radius h (periodic minimum image).
+  radius h = (Omega / N_ISDF)^{1/3} / 2 (periodic minimum image);
+* probe: relative fit residual of a point set P on probe points r_j,
+  sum_j [C(r_j,r_j) - C(r_j,P) C(P,P)^+ C(P,r_j)]_+ / sum_j C(r_j,r_j), where
+  C(r,r') = |Gamma(r,r')|^2 is the Gram matrix of the pair rows
+  z_{ww'}(r) = psi_w(r) conj psi_w'(r) that QRCP pivots on (Sec. 2.1): the
+  Schur complement is the squared distance of z(r_j) from span{z(r_P)}.
 
 Parameters are one flat FP64 vector: W1 (64x3), b1 (64), W2 (64x64), b2 (64),
 w3 (64), b3 (1).
@@ -150,17 +156,21 @@ def nms_radius(L, n_isdf) -> float:
     return 0.5 * (float(np.prod(L)) / n_isdf) ** (1.0 / 3.0)
 
 
-def targets(L, grid, pts, chunk=4096) -> np.ndarray:
-    """t(r) = exp(-d^2 / (2 h^2)) to the nearest of the points ``pts`` (flat indices)."""
+def target_width(L, n_isdf) -> float:
+    """Default target width sigma = (Omega / N_ISDF)^{1/3} / 4."""
+    return 0.25 * (float(np.prod(L)) / n_isdf) ** (1.0 / 3.0)
+
+
+def targets(L, grid, pts, sigma, chunk=4096) -> np.ndarray:
+    """t(r) = exp(-d^2 / (2 sigma^2)) to the nearest of the points ``pts`` (flat indices)."""
     L = np.asarray(L, dtype=np.float64)
     idx = np.unravel_index(np.arange(int(np.prod(grid))), grid)
     r = np.stack([idx[i] * (L[i] / grid[i]) for i in range(3)], axis=1)
     q = r[np.asarray(pts)]
-    h = nms_radius(L, len(pts))
     out = np.empty(len(r))
     for c0 in range(0, len(r), chunk):
         d2 = min_image_dist2(L, r[c0:c0 + chunk], q).min(axis=1)
-        out[c0:c0 + chunk] = np.exp(-d2 / (2 * h * h))
+        out[c0:c0 + chunk] = np.exp(-d2 / (2 * sigma * sigma))
     return out
 
 
@@ -186,3 +196,25 @@ def nms_select(L, grid, scores: np.ndarray, n_isdf: int) -> np.ndarray:
         rest = [int(i) for i in order if int(i) not in set(chosen)]
         chosen += rest[: n_isdf - len(chosen)]
     return np.asarray(chosen, dtype=np.int64)
+
+
+def probe_residual(psi: np.ndarray, pts, probe, rel_tol: float = 1e-12) -> float:
+    """Relative fit residual of the points ``pts`` on the grid points ``probe``
+    (both flat indices; orbitals psi (N_k, n_occ, N_g)), FP64, by the Schur
+    complement of the Gram matrix C = |Gamma|^2 with C(P,P) factorised by the
+    fit's Cholesky with pivot drop."""
+    from . import thc
+
+    nk, no, ng = psi.shape
+    A = psi.reshape(nk * no, ng)
+    AP = A[:, np.asarray(pts)]
+    AR = A[:, np.asarray(probe)]
+    Cpp = np.abs(AP.T @ AP.conj()) ** 2
+    Cpr = np.abs(AP.T @ AR.conj()) ** 2
+    crr = np.sum(np.abs(AR) ** 2, axis=0) ** 2
+    L, keep = thc.cholesky_drop(Cpp.astype(np.complex128), rel_tol)
+    R = np.flatnonzero(keep)
+    y = np.linalg.solve(L[np.ix_(R, R)], Cpr[R].astype(np.complex128))
+    q = np.sum(np.abs(y) ** 2, axis=0)
+    den = float(np.sum(crr))
+    return float(np.sum(np.maximum(crr - q, 0.0)) / den) if den > 0 else 1.0

@@ -1,5 +1,8 @@
 // C ABI entry points: argument checks, scratch layout and the launch sequence
 // of one THC-oo-K exchange build.
+#include <algorithm>
+#include <climits>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -668,6 +671,17 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   return hip_check(h, hipGraphLaunch(exec, stream), "hipGraphLaunch");
 }
 
+namespace {
+
+// limits of the fit-residual probe (scratch grows with N_k n_occ (N_ISDF + n_probe))
+exx_status probe_args(exx_context* h, const Geom& g, int32_t n_probe) {
+  if (n_probe < 1 || n_probe > 8192)
+    return fail(h, EXX_ERR_SHAPE, "probe: n_probe must be 1..8192");
+  if ((long)g.nk * g.no > 65536) return fail(h, EXX_ERR_SHAPE, "probe: N_k n_occ above 65536");
+  return EXX_OK;
+}
+}  // namespace
+
 extern "C" {
 
 exx_status exx_select_points(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
@@ -685,6 +699,181 @@ exx_status exx_select_points(exx_handle_t h, const exx_cell* cell, const void* p
   if (s != EXX_OK) return s;
   e = launch_select(g, (const double2*)psi_grid, pts, n_pivot, ws, stream);
   return hip_check(h, e, "select");
+}
+
+// ---------------------------------------------------------------------------
+// learned selector
+// ---------------------------------------------------------------------------
+exx_status exx_mlp_features(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
+                            const double* norm, float* feat, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!psi_grid || !norm || !feat) return fail(h, EXX_ERR_ARG, "exx_mlp_features: null argument");
+  for (int i = 0; i < 3; ++i)
+    if (!(norm[2 * i + 1] > 0.0) || !std::isfinite(norm[2 * i]))
+      return fail(h, EXX_ERR_ARG, "exx_mlp_features: scales must be positive, means finite");
+  exx_status s = check_cell(h, cell, EXX_F64);
+  if (s != EXX_OK) return s;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  Geom g = make_geom(*cell);
+  void* ws = ws_get(h, mlp_feature_scratch_bytes(g), &s);
+  if (s != EXX_OK) return s;
+  return hip_check(h, launch_mlp_features(g, (const double2*)psi_grid, norm, feat, ws, stream),
+                   "features");
+}
+
+exx_status exx_mlp_forward(exx_handle_t h, int64_t n, const float* feat, const float* theta,
+                           float* score, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (n < 0 || n > INT32_MAX) return fail(h, EXX_ERR_SHAPE, "exx_mlp_forward: n out of range");
+  if (n == 0) return EXX_OK;
+  if (!feat || !theta || !score) return fail(h, EXX_ERR_ARG, "exx_mlp_forward: null argument");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  return hip_check(h, launch_mlp_forward((long)n, feat, theta, score, stream), "forward");
+}
+
+exx_status exx_mlp_backward(exx_handle_t h, int64_t n, const int32_t* idx, int64_t rows,
+                            const float* feat, const float* target, float wpos, const float* theta,
+                            float* grad, double* loss, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (n < 1 || n > INT32_MAX) return fail(h, EXX_ERR_SHAPE, "exx_mlp_backward: n out of range");
+  if (rows < 1 || rows > INT32_MAX || (!idx && rows != n))
+    return fail(h, EXX_ERR_SHAPE, "exx_mlp_backward: rows out of range (must equal n without idx)");
+  if (!feat || !target || !theta || !grad || !loss)
+    return fail(h, EXX_ERR_ARG, "exx_mlp_backward: null argument");
+  if (!(wpos >= 0.0f) || !std::isfinite(wpos))
+    return fail(h, EXX_ERR_ARG, "exx_mlp_backward: wpos must be finite and >= 0");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  exx_status s;
+  void* ws = ws_get(h, mlp_grad_scratch_bytes((long)n), &s);
+  if (s != EXX_OK) return s;
+  return hip_check(h, launch_mlp_grad((long)n, idx, (long)rows, feat, target, wpos, theta, grad,
+                                      loss, ws, stream),
+                   "backward");
+}
+
+exx_status exx_mlp_adam(exx_handle_t h, int32_t np, float* theta, const float* grad, float* m,
+                        float* v, int32_t step, float lr, float beta1, float beta2, float eps,
+                        hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (np < 1) return fail(h, EXX_ERR_SHAPE, "exx_mlp_adam: np must be >= 1");
+  if (!theta || !grad || !m || !v) return fail(h, EXX_ERR_ARG, "exx_mlp_adam: null argument");
+  if (step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps >= 0.0f) || !std::isfinite(lr))
+    return fail(h, EXX_ERR_ARG, "exx_mlp_adam: step >= 1, 0 <= beta < 1, eps >= 0 required");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  return hip_check(h, launch_adam(np, theta, grad, m, v, step, lr, beta1, beta2, eps, stream),
+                   "adam");
+}
+
+exx_status exx_mlp_targets(exx_handle_t h, const exx_cell* cell, const int32_t* pts, int32_t npts,
+                           double sigma, float* target, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!pts || !target) return fail(h, EXX_ERR_ARG, "exx_mlp_targets: null argument");
+  if (!(sigma > 0.0) || !std::isfinite(sigma))
+    return fail(h, EXX_ERR_ARG, "exx_mlp_targets: sigma must be positive and finite");
+  exx_status s = check_cell(h, cell, EXX_F64);
+  if (s != EXX_OK) return s;
+  Geom g = make_geom(*cell);
+  if (npts < 1 || npts > 2048 || npts > g.ng)
+    return fail(h, EXX_ERR_SHAPE, "exx_mlp_targets: npts must be 1..min(2048, N_g)");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  return hip_check(h, launch_targets(g, pts, npts, sigma, target, stream), "targets");
+}
+
+exx_status exx_mlp_nms(exx_handle_t h, const exx_cell* cell, const float* score, int32_t k,
+                       int32_t* pts, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!score || !pts) return fail(h, EXX_ERR_ARG, "exx_mlp_nms: null argument");
+  exx_status s = check_cell(h, cell, EXX_F64);
+  if (s != EXX_OK) return s;
+  Geom g = make_geom(*cell);
+  if (k < 1 || k > g.ng) return fail(h, EXX_ERR_SHAPE, "exx_mlp_nms: k must be 1..N_g");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  void* ws = ws_get(h, mlp_nms_scratch_bytes(g), &s);
+  if (s != EXX_OK) return s;
+  return hip_check(h, launch_nms(g, score, k, pts, ws, stream), "nms");
+}
+
+exx_status exx_mlp_probe(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
+                         const int32_t* pts, int32_t n_probe, uint64_t seed, double* resid,
+                         hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!psi_grid || !pts || !resid) return fail(h, EXX_ERR_ARG, "exx_mlp_probe: null argument");
+  exx_status s = check_cell(h, cell, EXX_F64);
+  if (s != EXX_OK) return s;
+  Geom g = make_geom(*cell);
+  if ((s = probe_args(h, g, n_probe)) != EXX_OK) return s;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  void* ws = ws_get(h, mlp_probe_scratch_bytes(g, n_probe), &s);
+  if (s != EXX_OK) return s;
+  return hip_check(
+      h, launch_mlp_probe(g, (const double2*)psi_grid, pts, n_probe, seed, resid, ws, stream),
+      "probe");
+}
+
+exx_status exx_select_points_mlp(exx_handle_t h, const exx_cell* cell, const void* psi_grid,
+                                 const double* norm, const float* theta, double tau,
+                                 int32_t n_probe, int32_t* pts, int32_t* used_fallback,
+                                 double* resid_out, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!psi_grid || !norm || !theta || !pts || !used_fallback)
+    return fail(h, EXX_ERR_ARG, "exx_select_points_mlp: null argument");
+  if (!(tau >= 0.0)) return fail(h, EXX_ERR_ARG, "exx_select_points_mlp: tau must be >= 0");
+  for (int i = 0; i < 3; ++i)
+    if (!(norm[2 * i + 1] > 0.0) || !std::isfinite(norm[2 * i]))
+      return fail(h, EXX_ERR_ARG, "exx_select_points_mlp: scales must be positive, means finite");
+  exx_status s = check_cell(h, cell, EXX_F64);
+  if (s != EXX_OK) return s;
+  Geom g = make_geom(*cell);
+  if ((s = probe_args(h, g, n_probe)) != EXX_OK) return s;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  // scratch: [feat | score | resid | max(feature, nms, probe, QRCP scratch)]
+  const size_t fb = al(sizeof(float) * 3 * (size_t)g.ng), sb = al(sizeof(float) * (size_t)g.ng);
+  size_t inner = mlp_feature_scratch_bytes(g);
+  inner = std::max(inner, mlp_nms_scratch_bytes(g));
+  inner = std::max(inner, mlp_probe_scratch_bytes(g, n_probe));
+  inner = std::max(inner, select_scratch_bytes(g));
+  char* ws = (char*)ws_get(h, fb + sb + al(sizeof(double)) + inner, &s);
+  if (s != EXX_OK) return s;
+  float* feat = (float*)ws;
+  float* score = (float*)(ws + fb);
+  double* dres = (double*)(ws + fb + sb);
+  void* rest = ws + fb + sb + al(sizeof(double));
+  const double2* psi = (const double2*)psi_grid;
+  e = launch_mlp_features(g, psi, norm, feat, rest, stream);
+  if (e == hipSuccess) e = launch_mlp_forward((long)g.ng, feat, theta, score, stream);
+  if (e == hipSuccess) e = launch_nms(g, score, g.ni, pts, rest, stream);
+  if (e == hipSuccess)
+    e = launch_mlp_probe(g, psi, pts, n_probe, 0x2304055050ull, dres, rest, stream);
+  double resid = 0.0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&resid, dres, sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_check(h, e, "learned selection");
+  if (resid_out) *resid_out = resid;
+  *used_fallback = 0;
+  if (!(resid <= tau)) {  // also taken when the residual is not a number
+    int32_t* npiv = (int32_t*)(ws + fb);  // the score buffer is free again
+    e = launch_select(g, psi, pts, npiv, rest, stream);
+    if (e != hipSuccess) return hip_check(h, e, "QRCP fallback");
+    *used_fallback = 1;
+  }
+  return EXX_OK;
 }
 
 }  // extern "C"

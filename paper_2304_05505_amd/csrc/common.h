@@ -253,4 +253,25 @@ hipError_t launch_select(const Geom& g, const double2* psi, int32_t* pts, int32_
                          void* scratch, hipStream_t st);
 size_t select_scratch_bytes(const Geom& g);
 
+// learned selector: descriptors, network, training step, targets, NMS, probe
+hipError_t launch_mlp_features(const Geom& g, const double2* psi, const double* norm, float* feat,
+                               void* scratch, hipStream_t st);
+size_t mlp_feature_scratch_bytes(const Geom& g);
+hipError_t launch_mlp_forward(long n, const float* feat, const float* theta, float* score,
+                              hipStream_t st);
+hipError_t launch_mlp_grad(long n, const int32_t* idx, long rows, const float* feat,
+                           const float* tgt, float wpos, const float* theta, float* grad,
+                           double* loss, void* scratch, hipStream_t st);
+size_t mlp_grad_scratch_bytes(long n);
+hipError_t launch_adam(int np, float* theta, const float* g, float* m, float* v, int step, float lr,
+                       float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_targets(const Geom& g, const int32_t* pts, int npts, double sigma, float* t,
+                          hipStream_t st);
+hipError_t launch_nms(const Geom& g, const float* score, int k, int32_t* pts, void* scratch,
+                      hipStream_t st);
+size_t mlp_nms_scratch_bytes(const Geom& g);
+hipError_t launch_mlp_probe(const Geom& g, const double2* psi, const int32_t* pts, int nr,
+                            unsigned long long seed, double* resid, void* scratch, hipStream_t st);
+size_t mlp_probe_scratch_bytes(const Geom& g, int nr);
+
 }  // namespace exx

@@ -42,9 +42,18 @@ EXPORTED = (
     "exx_set_timing",
     "exx_phase_times",
     "exx_build_batched",
+    "exx_mlp_features",
+    "exx_mlp_forward",
+    "exx_mlp_backward",
+    "exx_mlp_adam",
+    "exx_mlp_targets",
+    "exx_mlp_nms",
+    "exx_mlp_probe",
+    "exx_select_points_mlp",
 )
 
 EXX_BATCH_GRAPH, EXX_BATCH_TUNE = 1, 2
+EXX_MLP_NPARAM = 4481
 
 PHASES = ("G", "S", "cholesky", "pinv", "gamma", "kcorr", "solve", "fft", "coulomb",
           "kconv", "K", "energy")
@@ -103,12 +112,25 @@ def _load():
                                ctypes.c_int32, vp], ctypes.c_int),
         "exx_phase_times": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                              ctypes.c_int32], ctypes.c_int),
+        "exx_mlp_features": ([vp, cellp, vp, ctypes.POINTER(ctypes.c_double), vp, vp], ctypes.c_int),
+        "exx_mlp_forward": ([vp, ctypes.c_int64, vp, vp, vp, vp], ctypes.c_int),
+        "exx_mlp_backward": ([vp, ctypes.c_int64, vp, ctypes.c_int64, vp, vp, ctypes.c_float, vp,
+                              vp, vp, vp], ctypes.c_int),
+        "exx_mlp_adam": ([vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float,
+                          ctypes.c_float, ctypes.c_float, ctypes.c_float, vp], ctypes.c_int),
+        "exx_mlp_targets": ([vp, cellp, vp, ctypes.c_int32, ctypes.c_double, vp, vp],
+                            ctypes.c_int),
+        "exx_mlp_nms": ([vp, cellp, vp, ctypes.c_int32, vp, vp], ctypes.c_int),
+        "exx_mlp_probe": ([vp, cellp, vp, vp, ctypes.c_int32, ctypes.c_uint64, vp, vp],
+                          ctypes.c_int),
+        "exx_select_points_mlp": ([vp, cellp, vp, ctypes.POINTER(ctypes.c_double), vp,
+                                   ctypes.c_double, ctypes.c_int32, vp, i32p,
+                                   ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = res
-    del i32p
     return lib
 
 
@@ -298,3 +320,95 @@ def exx_build_batched(h: Handle, items, prec: int, flags: int = 0, stream=None):
     else:
         st = stream.cuda_stream
     h._check(_lib.exx_build_batched(h.raw, len(items), arr, prec, flags, st))
+
+
+# ---------------------------------------------------------------------------
+# learned selector
+# ---------------------------------------------------------------------------
+def _norm6(norm):
+    vals = [float(x) for x in norm]
+    if len(vals) != 6:
+        raise ValueError("norm must hold 6 numbers (mean, scale) x 3")
+    return (ctypes.c_double * 6)(*vals)
+
+
+def exx_mlp_features(h: Handle, cell: ExxCell, psi_grid, norm, feat):
+    nk, ng, no = _nk(cell), _ng(cell), cell.n_occ
+    d = h.device
+    args = (_ptr(psi_grid, "psi_grid", torch.complex128, (nk, no, ng), d), _norm6(norm),
+            _ptr(feat, "feat", torch.float32, (ng, 3), d))
+    h._check(_lib.exx_mlp_features(h.raw, ctypes.byref(cell), *args, _stream(d)))
+
+
+def exx_mlp_forward(h: Handle, feat, theta, score):
+    d = h.device
+    n = feat.shape[0]
+    args = (_ptr(feat, "feat", torch.float32, (n, 3), d),
+            _ptr(theta, "theta", torch.float32, (EXX_MLP_NPARAM,), d),
+            _ptr(score, "score", torch.float32, (n,), d))
+    h._check(_lib.exx_mlp_forward(h.raw, n, *args, _stream(d)))
+
+
+def exx_mlp_backward(h: Handle, feat, target, wpos: float, theta, grad, loss, idx=None):
+    """Gradient over rows idx of (feat, target), or all rows when idx is None."""
+    d = h.device
+    rows = feat.shape[0]
+    n = rows if idx is None else idx.shape[0]
+    if idx is not None:
+        _ptr(idx, "idx", torch.int32, (n,), d)
+    args = (None if idx is None else idx.data_ptr(), rows,
+            _ptr(feat, "feat", torch.float32, (rows, 3), d),
+            _ptr(target, "target", torch.float32, (rows,), d), float(wpos),
+            _ptr(theta, "theta", torch.float32, (EXX_MLP_NPARAM,), d),
+            _ptr(grad, "grad", torch.float32, (EXX_MLP_NPARAM,), d),
+            _ptr(loss, "loss", torch.float64, (1,), d))
+    h._check(_lib.exx_mlp_backward(h.raw, n, *args, _stream(d)))
+
+
+def exx_mlp_adam(h: Handle, theta, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999,
+                 eps=1e-8):
+    d = h.device
+    n = theta.shape[0]
+    args = [_ptr(t, name, torch.float32, (n,), d)
+            for t, name in ((theta, "theta"), (grad, "grad"), (m, "m"), (v, "v"))]
+    h._check(_lib.exx_mlp_adam(h.raw, n, *args, int(step), float(lr), float(beta1), float(beta2),
+                               float(eps), _stream(d)))
+
+
+def exx_mlp_targets(h: Handle, cell: ExxCell, pts, sigma: float, target):
+    d = h.device
+    npts = pts.shape[0]
+    args = (_ptr(pts, "pts", torch.int32, (npts,), d), npts, float(sigma),
+            _ptr(target, "target", torch.float32, (_ng(cell),), d))
+    h._check(_lib.exx_mlp_targets(h.raw, ctypes.byref(cell), *args, _stream(d)))
+
+
+def exx_mlp_nms(h: Handle, cell: ExxCell, score, pts):
+    d = h.device
+    k = pts.shape[0]
+    args = (_ptr(score, "score", torch.float32, (_ng(cell),), d), k,
+            _ptr(pts, "pts", torch.int32, (k,), d))
+    h._check(_lib.exx_mlp_nms(h.raw, ctypes.byref(cell), *args, _stream(d)))
+
+
+def exx_mlp_probe(h: Handle, cell: ExxCell, psi_grid, pts, n_probe: int, seed: int, resid):
+    nk, ng, no, ni = _nk(cell), _ng(cell), cell.n_occ, cell.n_isdf
+    d = h.device
+    args = (_ptr(psi_grid, "psi_grid", torch.complex128, (nk, no, ng), d),
+            _ptr(pts, "pts", torch.int32, (ni,), d), int(n_probe), int(seed) & (2**64 - 1),
+            _ptr(resid, "resid", torch.float64, (1,), d))
+    h._check(_lib.exx_mlp_probe(h.raw, ctypes.byref(cell), *args, _stream(d)))
+
+
+def exx_select_points_mlp(h: Handle, cell: ExxCell, psi_grid, norm, theta, tau: float,
+                          n_probe: int, pts):
+    """Returns (used_fallback: bool, residual: float); pts is filled in place."""
+    nk, ng, no, ni = _nk(cell), _ng(cell), cell.n_occ, cell.n_isdf
+    d = h.device
+    used = ctypes.c_int32(0)
+    resid = ctypes.c_double(0.0)
+    args = (_ptr(psi_grid, "psi_grid", torch.complex128, (nk, no, ng), d), _norm6(norm),
+            _ptr(theta, "theta", torch.float32, (EXX_MLP_NPARAM,), d), float(tau), int(n_probe),
+            _ptr(pts, "pts", torch.int32, (ni,), d), ctypes.byref(used), ctypes.byref(resid))
+    h._check(_lib.exx_select_points_mlp(h.raw, ctypes.byref(cell), *args, _stream(d)))
+    return bool(used.value), float(resid.value)

@@ -1,0 +1,257 @@
+"""Learned interpolation-point selector: training driver and inference helper.
+
+The network, its gradient, Adam, the descriptors, the targets, the selection
+and the fit-residual probe are HIP kernels behind the C ABI (see the
+``exx_mlp_*`` and ``exx_select_points_mlp`` entry points in include/exx.h);
+this module only generates the seeded training cells, moves tensors and runs
+the loop.
+
+Training data: seeded random cells of 8-48 atoms (s + p Gaussians per atom,
+n_occ = round(1.75 atoms), N_ISDF = 5 n_occ, Gamma-only and 2x2x2 k-meshes
+alternating, cell volume at the density of the 48-atom ring cell, grids of
+about 4.9 points per bohr). Labels are the QRCP points of each cell
+(exx_select_points, pivoted Cholesky of |Gamma(r, r')|^2, Sec. 2.1), turned
+into soft targets exp(-d^2 / (2 sigma^2)), sigma = (Omega/N_ISDF)^{1/3} / 4.
+The last cells are held out to calibrate the fallback threshold tau on the
+probe residual.
+
+Run ``python -m paper_2304_05505_amd.mlp --out weights.json`` on a GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import pathlib
+import sys
+import time
+
+import numpy as np
+
+ROOT = pathlib.Path(__file__).resolve().parent.parent
+if str(ROOT) not in sys.path:
+    sys.path.insert(0, str(ROOT))
+
+import synth  # noqa: E402
+from synth.cells import RING_CELL_L, SEED_ROOT  # noqa: E402
+
+WEIGHTS = pathlib.Path(__file__).resolve().parent / "mlp_weights.json"
+PROBE_SEED = 0x2304055050
+N_PROBE = 2048
+HID = 64
+
+
+def training_cell(i: int):
+    """Training cell number i (seeded by (SEED_ROOT, 6, i))."""
+    rng = np.random.default_rng([SEED_ROOT, 6, i])
+    na = int(rng.integers(8, 49))
+    km = (1, 1, 1) if i % 2 == 0 else (2, 2, 2)
+    L = np.asarray(RING_CELL_L) * (na / 48.0) ** (1.0 / 3.0)
+    grid = tuple(synth.smooth_grid_size(4.9 * x) for x in L)
+    n_occ = int(round(1.75 * na))
+    return synth.make_random_cell(L, na, grid, km, n_occ, 5 * n_occ, (SEED_ROOT, 6, i),
+                                  name=f"train{i}-a{na}-k{km[0]}")
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-style initial parameters, flat float32 in the EXX_MLP_NPARAM layout."""
+    rng = np.random.default_rng(seed)
+    parts = [
+        rng.standard_normal((HID, 3)) * math.sqrt(1.0 / 3.0),
+        np.zeros(HID),
+        rng.standard_normal((HID, HID)) * math.sqrt(1.0 / HID),
+        np.zeros(HID),
+        rng.standard_normal(HID) * math.sqrt(1.0 / HID),
+        np.array([-4.0]),
+    ]
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+
+
+def target_width(L, n_isdf) -> float:
+    return 0.25 * (float(np.prod(L)) / n_isdf) ** (1.0 / 3.0)
+
+
+def load_weights(path=WEIGHTS) -> dict:
+    d = json.loads(pathlib.Path(path).read_text())
+    d["theta"] = np.asarray(d["theta"], dtype=np.float32)
+    return d
+
+
+class CellData:
+    """Orbitals of one cell on the GPU plus its C-ABI cell descriptor."""
+
+    def __init__(self, cell, dev):
+        import torch
+
+        from synth.fast import orbitals_on_grid_torch
+
+        from . import exx
+
+        self.cell = cell
+        C = synth.orbital_coeffs(cell)
+        self.psi = orbitals_on_grid_torch(cell, C, dev)
+        self.c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, cell.n_isdf)
+        self.dev = dev
+        self.torch = torch
+
+    def qrcp(self, h):
+        from . import exx
+
+        t = self.torch
+        pts = t.empty((self.cell.n_isdf,), dtype=t.int32, device=self.dev)
+        npiv = t.empty((1,), dtype=t.int32, device=self.dev)
+        exx.exx_select_points(h, self.c, self.psi, pts, npiv)
+        return pts
+
+    def features(self, h, norm):
+        from . import exx
+
+        t = self.torch
+        F = t.empty((self.cell.N_g, 3), dtype=t.float32, device=self.dev)
+        exx.exx_mlp_features(h, self.c, self.psi, norm, F)
+        return F
+
+    def targets(self, h, pts):
+        from . import exx
+
+        t = self.torch
+        T = t.empty((self.cell.N_g,), dtype=t.float32, device=self.dev)
+        exx.exx_mlp_targets(h, self.c, pts, target_width(self.cell.L, self.cell.n_isdf), T)
+        return T
+
+    def probe(self, h, pts):
+        from . import exx
+
+        t = self.torch
+        r = t.empty((1,), dtype=t.float64, device=self.dev)
+        exx.exx_mlp_probe(h, self.c, self.psi, pts, N_PROBE, PROBE_SEED, r)
+        return float(r.cpu()[0])
+
+    def select(self, h, norm, theta, tau):
+        from . import exx
+
+        t = self.torch
+        pts = t.empty((self.cell.n_isdf,), dtype=t.int32, device=self.dev)
+        used, resid = exx.exx_select_points_mlp(h, self.c, self.psi, norm, theta, tau, N_PROBE, pts)
+        return pts, used, resid
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def train(n_cells=200, n_val=20, steps=4000, batch=65536, lr=3e-3, wpos=20.0, seed=0,
+          n_norm=20):
+    import torch
+
+    from . import exx
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    ident = (0.0, 1.0, 0.0, 1.0, 0.0, 1.0)
+    t0 = time.perf_counter()
+    # 1. standardisation constants from the raw descriptors of the first cells
+    s1 = torch.zeros(3, dtype=torch.float64, device=dev)
+    s2 = torch.zeros(3, dtype=torch.float64, device=dev)
+    cnt = 0
+    for i in range(n_norm):
+        cd = CellData(training_cell(i), dev)
+        F = cd.features(h, ident).double()
+        s1 += F.sum(0)
+        s2 += (F * F).sum(0)
+        cnt += F.shape[0]
+        del cd, F
+    mean = (s1 / cnt).cpu().numpy()
+    std = np.sqrt(np.maximum((s2 / cnt).cpu().numpy() - mean * mean, 1e-30))
+    norm = tuple(float(x) for pair in zip(mean, std) for x in pair)
+    log(f"[mlp] norm {norm} from {n_norm} cells ({time.perf_counter() - t0:.1f} s)")
+    # 2. descriptors and QRCP targets of the training cells; QRCP residuals of the held-out cells
+    feats, tgts, val = [], [], []
+    sel_time = 0.0
+    for i in range(n_cells):
+        cd = CellData(training_cell(i), dev)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        pts = cd.qrcp(h)
+        torch.cuda.synchronize()
+        sel_time += time.perf_counter() - ts
+        if i < n_cells - n_val:
+            feats.append(cd.features(h, norm))
+            tgts.append(cd.targets(h, pts))
+        else:
+            val.append((i, cd.probe(h, pts)))
+        del cd
+        if (i + 1) % 20 == 0:
+            log(f"[mlp] {i + 1}/{n_cells} cells prepared ({time.perf_counter() - t0:.1f} s)")
+    X = torch.cat(feats)
+    T = torch.cat(tgts)
+    del feats, tgts
+    total = X.shape[0]
+    log(f"[mlp] {total} training points; mean target {float(T.mean()):.4f}; "
+        f"QRCP time {sel_time:.1f} s")
+    # 3. Adam on random mini-batches (cosine learning-rate decay)
+    theta = torch.from_numpy(init_params(seed)).to(dev)
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    g = torch.empty_like(theta)
+    loss = torch.empty((1,), dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    hist = []
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, total, (batch,), generator=gen, device=dev, dtype=torch.int32)
+        exx.exx_mlp_backward(h, X, T, wpos, theta, g, loss, idx=idx)
+        rate = lr * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / steps))
+        exx.exx_mlp_adam(h, theta, g, m, v, step, rate)
+        if step % 250 == 0 or step == 1:
+            lv = float(loss.cpu()[0])
+            hist.append((step, lv))
+            log(f"[mlp] step {step} loss {lv:.5f}")
+    # full-data loss at the end
+    exx.exx_mlp_backward(h, X, T, wpos, theta, g, loss)
+    final_loss = float(loss.cpu()[0])
+    del X, T
+    # 4. held-out cells: probe residual of the learned points vs QRCP; tau
+    rows = []
+    for i, r_qrcp in val:
+        cd = CellData(training_cell(i), dev)
+        pts, used, r_mlp = cd.select(h, norm, theta, float("inf"))
+        rows.append({"cell": i, "resid_qrcp": r_qrcp, "resid_mlp": r_mlp})
+        del cd
+    ratios = np.array([r["resid_mlp"] / r["resid_qrcp"] for r in rows])
+    tau = 1.5 * max(r["resid_mlp"] for r in rows)
+    log(f"[mlp] held-out residual ratio MLP/QRCP: median {np.median(ratios):.3f}, "
+        f"max {ratios.max():.3f}; tau = {tau:.3e}")
+    return {
+        "format": "exx-mlp-selector-1",
+        "layout": "W1(64x3) b1(64) W2(64x64) b2(64) w3(64) b3(1); weights evaluated in bfloat16",
+        "theta": [float(x) for x in theta.cpu().numpy()],
+        "norm": list(norm),
+        "tau": tau,
+        "n_probe": N_PROBE,
+        "probe_seed": PROBE_SEED,
+        "train": {"cells": n_cells - n_val, "held_out": n_val, "points": int(total), "steps": steps,
+                  "batch": batch, "lr": lr, "wpos": wpos, "seed": seed, "final_loss": final_loss,
+                  "loss_history": hist, "seconds": time.perf_counter() - t0},
+        "held_out": rows,
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--out", default=str(WEIGHTS))
+    ap.add_argument("--cells", type=int, default=200)
+    ap.add_argument("--val", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--wpos", type=float, default=20.0)
+    args = ap.parse_args(argv)
+    res = train(args.cells, args.val, args.steps, args.batch, args.lr, args.wpos)
+    pathlib.Path(args.out).write_text(json.dumps(res, indent=1))
+    log(f"[mlp] wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

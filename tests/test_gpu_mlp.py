@@ -1,0 +1,251 @@
+"""Learned point selector on the GPU against the FP64 reference (oracle/mlp.py):
+descriptors, network forward, gradient, Adam, targets, NMS (index-exact), the
+fit-residual probe, and the selection entry point with its QRCP fallback.
+
+The probe residual is a relative quantity in [0, 1]; both sides compute it in
+FP64 from the same Gram entries, and it is compared to 1e-6 relative plus 1e-10
+absolute (the floor covers point sets that span the pair space, where the
+residual is rounding noise).
+
+The network runs with bfloat16-rounded weights and FP32 arithmetic; the
+reference is evaluated at the same rounded weights in FP64, so the remaining
+differences are FP32 rounding: forward logits agree to 1e-4 (absolute, logits
+of order 1, 64-term FP32 sums) and gradients to 1e-3 of their largest entry.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as ref
+from oracle import select
+
+pytestmark = pytest.mark.gpu
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix_points(seed, n, ng):
+    """Counter-based SplitMix64 (Steele, Lea, Flood 2014): draw j is the output
+    function of state seed + (j + 1) * 0x9e3779b97f4a7c15, reduced mod ng."""
+    out = []
+    for j in range(n):
+        z = (seed + 0x9E3779B97F4A7C15 * (j + 1)) & MASK64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        z ^= z >> 31
+        out.append(z % ng)
+    return np.asarray(out, dtype=np.int64)
+
+
+def bf16_round(x32):
+    """Round float32 values to bfloat16 (nearest even), returned as float32."""
+    u = np.asarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def rounded_params(theta32):
+    """The parameters the kernels evaluate: weights bfloat16-rounded, biases as given."""
+    p = ref.unpack(np.asarray(theta32, dtype=np.float64))
+    out = {k: np.asarray(v, dtype=np.float32) for k, v in p.items()}
+    for k in ("W1", "W2", "w3"):
+        out[k] = bf16_round(out[k])
+    return ref.pack({k: v.astype(np.float64) for k, v in out.items()})
+
+
+def _cells():
+    return [
+        synth.make_random_cell((5.0, 5.5, 6.0), 3, (15, 16, 18), (2, 1, 1), 4, 24, (21, 1, 1)),
+        synth.make_random_cell((6.0, 5.0, 5.5), 4, (18, 15, 16), (1, 1, 1), 5, 30, (21, 2, 1)),
+    ]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    cells = []
+    for cell in _cells():
+        psi = synth.orbitals_on_grid(cell, synth.orbital_coeffs(cell))
+        c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, cell.n_isdf)
+        cells.append((cell, psi, c, torch.from_numpy(psi).to(dev)))
+    return exx, torch, dev, h, cells
+
+
+NORM = (0.1, 1.3, -2.0, 0.7, 0.4, 0.25)
+
+
+def test_features_match_reference(env, gpu):
+    exx, torch, dev, h, cells = env
+    for cell, psi, c, t_psi in cells:
+        F = torch.empty((cell.N_g, 3), dtype=torch.float32, device=dev)
+        exx.exx_mlp_features(h, c, t_psi, NORM, F)
+        got = F.cpu().numpy().astype(np.float64)
+        want = ref.features(cell.L, cell.grid, psi, norm=((0.1, 1.3), (-2.0, 0.7), (0.4, 0.25)))
+        assert np.allclose(got, want, rtol=2e-6, atol=2e-6), np.abs(got - want).max()
+
+
+def test_forward_matches_reference(env, gpu):
+    exx, torch, dev, h, _ = env
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((3001, 3)).astype(np.float32)  # several blocks and a ragged tail
+    theta = ref.init_params(1).astype(np.float32)
+    theta[ref.NPARAM - 1] = 0.3
+    s = torch.empty((3001,), dtype=torch.float32, device=dev)
+    exx.exx_mlp_forward(h, torch.from_numpy(X).to(dev), torch.from_numpy(theta).to(dev), s)
+    got = s.cpu().numpy().astype(np.float64)
+    want = ref.forward(rounded_params(theta), X.astype(np.float64))
+    assert np.abs(got - want).max() <= 1e-4
+    # rounding the weights matters at this tolerance: the unrounded network differs
+    assert np.abs(ref.forward(theta.astype(np.float64), X.astype(np.float64)) - want).max() > 1e-3
+
+
+@pytest.mark.parametrize("use_idx", [False, True])
+def test_backward_matches_reference(env, gpu, use_idx):
+    exx, torch, dev, h, _ = env
+    rng = np.random.default_rng(6)
+    rows = 2000
+    X = rng.standard_normal((rows, 3)).astype(np.float32)
+    t = (rng.uniform(0, 1, rows) ** 4).astype(np.float32)
+    theta = ref.init_params(2).astype(np.float32)
+    wpos = 20.0
+    if use_idx:
+        idx = rng.integers(0, rows, 1499).astype(np.int32)  # repeats and a ragged last block
+    else:
+        idx = np.arange(rows, dtype=np.int32)
+    g = torch.empty((exx.EXX_MLP_NPARAM,), dtype=torch.float32, device=dev)
+    loss = torch.empty((1,), dtype=torch.float64, device=dev)
+    exx.exx_mlp_backward(h, torch.from_numpy(X).to(dev), torch.from_numpy(t).to(dev), wpos,
+                         torch.from_numpy(theta).to(dev), g, loss,
+                         idx=torch.from_numpy(idx).to(dev) if use_idx else None)
+    got = g.cpu().numpy().astype(np.float64)
+    th = rounded_params(theta)
+    Xs, ts = X[idx].astype(np.float64), t[idx].astype(np.float64)
+    w = 1.0 + wpos * ts
+    want = ref.grad(th, Xs, ts, w)
+    assert np.abs(got - want).max() <= 1e-3 * np.abs(want).max()
+    assert np.linalg.norm(got - want) <= 1e-4 * np.linalg.norm(want)
+    assert abs(float(loss.cpu()[0]) - ref.loss(th, Xs, ts, w)) <= 1e-5 * ref.loss(th, Xs, ts, w)
+
+
+def test_backward_skips_rows_outside_the_table(env, gpu):
+    exx, torch, dev, h, _ = env
+    rng = np.random.default_rng(7)
+    rows = 300
+    X = torch.from_numpy(rng.standard_normal((rows, 3)).astype(np.float32)).to(dev)
+    t = torch.from_numpy(rng.uniform(0, 1, rows).astype(np.float32)).to(dev)
+    theta = torch.from_numpy(ref.init_params(3).astype(np.float32)).to(dev)
+    good = rng.integers(0, rows, 100).astype(np.int32)
+    bad = np.concatenate([good, np.array([-1, rows, rows + 7, -5], dtype=np.int32)])
+    out = []
+    for idx in (good, bad):
+        g = torch.empty((exx.EXX_MLP_NPARAM,), dtype=torch.float32, device=dev)
+        loss = torch.empty((1,), dtype=torch.float64, device=dev)
+        exx.exx_mlp_backward(h, X, t, 5.0, theta, g, loss, idx=torch.from_numpy(idx).to(dev))
+        out.append((g.cpu().numpy(), float(loss.cpu()[0])))
+    assert np.allclose(out[0][0], out[1][0], rtol=1e-6, atol=1e-9)
+    assert abs(out[0][1] - out[1][1]) <= 1e-12 * abs(out[0][1])
+
+
+def test_adam_matches_reference(env, gpu):
+    exx, torch, dev, h, _ = env
+    rng = np.random.default_rng(8)
+    n = 777
+    th, g, m, v = (rng.standard_normal(n).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    T = [torch.from_numpy(a.copy()).to(dev) for a in (th, g, m, v)]
+    exx.exx_mlp_adam(h, T[0], T[1], T[2], T[3], 7, 3e-3, 0.9, 0.999, 1e-8)
+    want, wm, wv = ref.adam_step(th.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                                 v.astype(np.float64), 7, lr=3e-3)
+    assert np.allclose(T[0].cpu().numpy(), want, rtol=1e-6, atol=1e-6)
+    assert np.allclose(T[2].cpu().numpy(), wm, rtol=1e-6, atol=1e-7)
+    assert np.allclose(T[3].cpu().numpy(), wv, rtol=1e-6, atol=1e-7)
+
+
+def test_targets_match_reference(env, gpu):
+    exx, torch, dev, h, cells = env
+    rng = np.random.default_rng(9)
+    for cell, psi, c, _ in cells:
+        pts = rng.choice(cell.N_g, 17, replace=False)
+        sigma = ref.target_width(cell.L, 17)
+        t = torch.empty((cell.N_g,), dtype=torch.float32, device=dev)
+        exx.exx_mlp_targets(h, c, torch.from_numpy(pts.astype(np.int32)).to(dev), sigma, t)
+        want = ref.targets(cell.L, cell.grid, pts, sigma)
+        assert np.abs(t.cpu().numpy() - want).max() <= 1e-6
+
+
+@pytest.mark.parametrize("k", [1, 24, 700, 4000])
+def test_nms_matches_reference_exactly(env, gpu, k):
+    exx, torch, dev, h, cells = env
+    cell, _, c, _ = cells[0]
+    rng = np.random.default_rng(10 + k)
+    # two-decimal scores: many exact ties, decided by the smaller index
+    sc = np.round(rng.standard_normal(cell.N_g), 2).astype(np.float32)
+    sc[rng.choice(cell.N_g, 5, replace=False)] = np.nan
+    pts = torch.empty((k,), dtype=torch.int32, device=dev)
+    exx.exx_mlp_nms(h, c, torch.from_numpy(sc).to(dev), pts)
+    want = ref.nms_select(cell.L, cell.grid, sc.astype(np.float64), k)
+    assert np.array_equal(pts.cpu().numpy().astype(np.int64), want)
+
+
+def test_probe_matches_reference(env, gpu):
+    exx, torch, dev, h, cells = env
+    for cell, psi, c, t_psi in cells:
+        pts, _ = select.select_points(psi, cell.n_isdf)
+        for n_probe, seed in ((300, 12345), (1, 7)):
+            probe = splitmix_points(seed, n_probe, cell.N_g)
+            r = torch.empty((1,), dtype=torch.float64, device=dev)
+            exx.exx_mlp_probe(h, c, t_psi, torch.from_numpy(pts.astype(np.int32)).to(dev), n_probe,
+                              seed, r)
+            want = ref.probe_residual(psi, pts, probe)
+            got = float(r.cpu()[0])
+            assert abs(got - want) <= 1e-10 + 1e-6 * want, (got, want)
+
+
+def test_selection_pipeline_and_fallback(env, gpu):
+    exx, torch, dev, h, cells = env
+    theta = torch.from_numpy(ref.init_params(4).astype(np.float32)).to(dev)
+    seed, n_probe = 0x2304055050, 512
+    for cell, psi, c, t_psi in cells:
+        ng, ni = cell.N_g, cell.n_isdf
+        F = torch.empty((ng, 3), dtype=torch.float32, device=dev)
+        exx.exx_mlp_features(h, c, t_psi, NORM, F)
+        s = torch.empty((ng,), dtype=torch.float32, device=dev)
+        exx.exx_mlp_forward(h, F, theta, s)
+        pts = torch.empty((ni,), dtype=torch.int32, device=dev)
+        used, resid = exx.exx_select_points_mlp(h, c, t_psi, NORM, theta, float("inf"), n_probe, pts)
+        assert not used
+        got = pts.cpu().numpy().astype(np.int64)
+        want = ref.nms_select(cell.L, cell.grid, s.cpu().numpy().astype(np.float64), ni)
+        assert np.array_equal(got, want)
+        probe = splitmix_points(seed, n_probe, ng)
+        assert abs(resid - ref.probe_residual(psi, got, probe)) <= 1e-10 + 1e-6 * resid
+        # a threshold below the residual sends the cell to QRCP
+        q = torch.empty((ni,), dtype=torch.int32, device=dev)
+        npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+        exx.exx_select_points(h, c, t_psi, q, npiv)
+        used, resid2 = exx.exx_select_points_mlp(h, c, t_psi, NORM, theta, 0.5 * resid, n_probe, pts)
+        assert used and resid2 == resid
+        assert np.array_equal(pts.cpu().numpy(), q.cpu().numpy())
+
+
+def test_corrupted_weights_fall_back_to_qrcp(env, gpu):
+    exx, torch, dev, h, cells = env
+    cell, psi, c, t_psi = cells[0]
+    ni, n_probe = cell.n_isdf, 512
+    q = torch.empty((ni,), dtype=torch.int32, device=dev)
+    npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+    exx.exx_select_points(h, c, t_psi, q, npiv)
+    r = torch.empty((1,), dtype=torch.float64, device=dev)
+    exx.exx_mlp_probe(h, c, t_psi, q, n_probe, 0x2304055050, r)
+    tau = 2.0 * float(r.cpu()[0])
+    bad = torch.full((exx.EXX_MLP_NPARAM,), float("nan"), dtype=torch.float32, device=dev)
+    pts = torch.empty((ni,), dtype=torch.int32, device=dev)
+    used, resid = exx.exx_select_points_mlp(h, c, t_psi, NORM, bad, tau, n_probe, pts)
+    assert used and resid > tau
+    assert np.array_equal(pts.cpu().numpy(), q.cpu().numpy())

@@ -1,11 +1,13 @@
 """Pins of the learned-selector reference (oracle/mlp.py): finite-difference
-gradients, the closed-form first Adam step, feature identities, targets and
-the non-maximum-suppression rule checked by brute force."""
+gradients, the closed-form first Adam step, feature identities, targets, the
+non-maximum-suppression rule checked by brute force, and the fit-residual
+probe checked against least squares on the explicit pair matrix and against
+the pivot order of QRCP."""
 
 import numpy as np
 
 import synth
-from oracle import mlp
+from oracle import mlp, select
 
 
 def _data(n=200, seed=1):
@@ -84,7 +86,7 @@ def test_targets_and_nms_rule():
     grid = (10, 12, 14)
     rng = np.random.default_rng(4)
     pts = rng.choice(np.prod(grid), 12, replace=False)
-    t = mlp.targets(L, grid, pts)
+    t = mlp.targets(L, grid, pts, mlp.target_width(L, 12))
     assert np.allclose(t[pts], 1.0)
     assert np.all((t > 0) & (t <= 1.0 + 1e-15))
     scores = rng.standard_normal(np.prod(grid))
@@ -102,3 +104,56 @@ def test_targets_and_nms_rule():
             continue
         assert mlp.min_image_dist2(L, r[i:i + 1], r[sel]).min() < h2
     assert len(set(sel.tolist())) == 12
+
+
+def _small_cell(nk=(2, 1, 1), n_occ=2, grid=(6, 6, 8), seed=(5, 5, 5)):
+    c = synth.make_random_cell((4.0, 4.5, 5.0), 2, grid, nk, n_occ, 6, seed)
+    return synth.orbitals_on_grid(c, synth.orbital_coeffs(c))
+
+
+def _pair_rows(psi):
+    """Explicit pair matrix z[(w, w'), r] = psi_w(r) conj psi_w'(r)."""
+    A = psi.reshape(-1, psi.shape[-1])
+    return (A[:, None, :] * A[None, :, :].conj()).reshape(-1, A.shape[-1])
+
+
+def test_probe_residual_is_least_squares_on_the_pair_matrix():
+    psi = _small_cell()
+    Z = _pair_rows(psi)  # 16 pair functions
+    ng = psi.shape[-1]
+    rng = np.random.default_rng(11)
+    pts = rng.choice(ng, 6, replace=False)
+    for r in rng.choice(np.setdiff1d(np.arange(ng), pts), 12, replace=False):
+        coef, *_ = np.linalg.lstsq(Z[:, pts], Z[:, r], rcond=None)
+        res = np.linalg.norm(Z[:, r] - Z[:, pts] @ coef) ** 2 / np.linalg.norm(Z[:, r]) ** 2
+        got = mlp.probe_residual(psi, pts, [r])
+        assert abs(got - res) <= 1e-10 + 1e-8 * res
+
+
+def test_probe_residual_vanishes_on_the_points_and_decreases_with_more_points():
+    psi = _small_cell(nk=(1, 1, 1), n_occ=3, seed=(6, 6, 6))
+    ng = psi.shape[-1]
+    rng = np.random.default_rng(3)
+    pts = rng.choice(ng, 8, replace=False)
+    assert mlp.probe_residual(psi, pts, pts[:5]) <= 1e-12
+    probe = rng.choice(ng, 40, replace=False)
+    prev = 1.0 + 1e-12
+    for p in range(1, 9):
+        cur = mlp.probe_residual(psi, pts[:p], probe)
+        assert cur <= prev + 1e-12
+        prev = cur
+    # 9 pair functions: 9 well-spread points span them, so nothing is left anywhere
+    full, _ = select.select_points(psi, 9)
+    assert mlp.probe_residual(psi, full, np.arange(ng)) <= 1e-9
+
+
+def test_probe_schur_diagonal_peaks_at_the_next_qrcp_pivot():
+    psi = _small_cell(seed=(7, 7, 7))
+    ng = psi.shape[-1]
+    A = psi.reshape(-1, ng)
+    crr = np.sum(np.abs(A) ** 2, axis=0) ** 2
+    for p in (1, 3, 5):
+        pts, npiv = select.select_points(psi, p + 1)
+        assert npiv == p + 1
+        d = np.array([mlp.probe_residual(psi, pts[:p], [r]) * crr[r] for r in range(ng)])
+        assert int(np.argmax(d)) == int(pts[p])
