@@ -14,7 +14,9 @@ FP32 FFT and Coulomb contraction with FP64 accumulation) and f32 (bulk FP32).
 ~1e-12; with --prec the reported path is forced).
 
 Prints one JSON line. Options: --steps K --warmup W --gpus N (N must be 1)
---prec auto|f64|mixed|f32 --no-cpu.
+--prec auto|f64|mixed|f32 --no-cpu --profile; --workload select-k4 instead times
+the learned and the QRCP point selection at the 4x4x4 ring workload, each
+followed by one FP32 K-build.
 """
 
 from __future__ import annotations
@@ -144,6 +146,100 @@ def cpu_baseline(cell, psi, pts, ao):
     }
 
 
+def bench_select5(args):
+    """Learned vs QRCP point selection at the 4x4x4 ring workload (2s + 2p basis,
+    N 384, n_occ 84, grid 72x90x64, N_ISDF 420), each followed by the FP32 K-build
+    at the chosen points: end-to-end time and the E_x difference."""
+    import torch
+
+    import synth
+    from paper_2304_05505_amd import exx, mlp
+    from synth.fast import orbitals_on_grid_torch
+
+    dev = torch.device("cuda", 0)
+    cell = synth.make_config(5)
+    t0 = time.perf_counter()
+    psi64 = orbitals_on_grid_torch(cell, synth.orbital_coeffs(cell), dev)
+    psi32 = psi64.to(torch.complex64)
+    torch.cuda.synchronize()
+    log(f"[select5] orbitals generated in {time.perf_counter() - t0:.1f} s")
+    nk, no, ng, ni, na = cell.N_k, cell.n_occ, cell.N_g, cell.n_isdf, cell.n_ao
+    h = exx.Handle(0)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, no, na, ni)
+    w = mlp.load_weights()
+    theta = torch.from_numpy(w["theta"]).to(dev)
+
+    def timed(fn, reps):
+        out, ts = None, []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return out, float(np.median(ts))
+
+    def qrcp():
+        pts = torch.empty((ni,), dtype=torch.int32, device=dev)
+        npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+        exx.exx_select_points(h, c, psi64, pts, npiv)
+        return pts
+
+    def learned():
+        pts = torch.empty((ni,), dtype=torch.int32, device=dev)
+        used, resid = exx.exx_select_points_mlp(h, c, psi64, w["norm"], theta, w["tau"],
+                                                int(w["n_probe"]), pts)
+        return pts, used, resid
+
+    learned()
+    (pm, used, resid), t_mlp = timed(learned, 3)
+    log(f"[select5] learned selection {t_mlp * 1e3:.1f} ms (fallback {used}, residual {resid:.4f})")
+    pq, t_qrcp = timed(qrcp, 1)
+    log(f"[select5] QRCP selection {t_qrcp * 1e3:.1f} ms")
+    r = torch.empty((1,), dtype=torch.float64, device=dev)
+    exx.exx_mlp_probe(h, c, psi64, pq, int(w["n_probe"]), int(w["probe_seed"]), r)
+    resid_q = float(r.cpu()[0])
+
+    def build(pts_t):
+        pts = pts_t.cpu().numpy().astype(np.int64)
+        ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(nk)])
+        t_ao = torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev)
+        occ = psi64[:, :, pts_t.long()].permute(0, 2, 1).contiguous()
+        K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+        Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+        rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+
+        def run():
+            exx.exx_build(h, c, exx.EXX_F32, psi32, occ, t_ao, pts_t, K, Ex, rank)
+
+        run()
+        _, t = timed(run, 2)
+        return float(Ex.cpu()[0]), t
+
+    ex_m, tb_m = build(pm)
+    log(f"[select5] K-build (f32) at learned points {tb_m * 1e3:.1f} ms, E_x {ex_m:.8f}")
+    ex_q, tb_q = build(pq)
+    log(f"[select5] K-build (f32) at QRCP points {tb_q * 1e3:.1f} ms, E_x {ex_q:.8f}")
+    out = {
+        "metric": "end-to-end s: point selection + one K-build (all k), learned vs QRCP",
+        "value": t_mlp + tb_m,
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "48-atom four-ring cell, 4x4x4 k-mesh, 2s+2p (N=384), n_occ=84, "
+                               "grid 72x90x64, N_ISDF=420", "N_k": nk, "N_g": ng},
+        "learned": {"select_s": t_mlp, "build_s": tb_m, "Ex": ex_m, "probe_residual": resid,
+                    "fallback": used},
+        "qrcp": {"select_s": t_qrcp, "build_s": tb_q, "Ex": ex_q, "probe_residual": resid_q},
+        "end_to_end_speedup": (t_qrcp + tb_q) / (t_mlp + tb_m),
+        "dEx_learned_vs_qrcp": ex_m - ex_q,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,11 +250,17 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiling target: one build per precision path and a 1 GiB device "
                          "copy, no JSON")
+    ap.add_argument("--workload", choices=("rings-k2", "select-k4"), default="rings-k2",
+                    help="rings-k2: the K-build throughput line (default); select-k4: learned vs "
+                         "QRCP selection + K-build at the 4x4x4 ring workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the build is not sharded "
               "across GPUs", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "select-k4":
+        bench_select5(args)
+        return
 
     import torch
 

@@ -353,69 +353,142 @@ __device__ __forceinline__ bool nms_better(float v, long i, float bv, long bi) {
   return (v > bv) || (v == bv && i < bi);
 }
 
-// One workgroup: greedy selection by score, suppressing alive points within
-// radius h of each pick; if the suppressed grid runs out before k picks, the
-// remaining slots take the unpicked points in score order. alive: [N_g] scratch
-// (1 alive, 0 suppressed, 2 picked). k <= N_g, so every slot is filled.
+// better of (v, i) and (v2, i2) in nms_better order; i < 0 marks "none"
+__device__ __forceinline__ void nms_take(float& v, int& i, float v2, int i2) {
+  if (i2 >= 0 && (i < 0 || nms_better(v2, i2, v, i))) {
+    v = v2;
+    i = i2;
+  }
+}
+
+__device__ __forceinline__ void nms_wave_reduce(float& v, int& i) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float v2 = __shfl_xor(v, off);
+    const int i2 = __shfl_xor(i, off);
+    nms_take(v, i, v2, i2);
+  }
+}
+
+struct NmsBox {
+  int k[3];  // half-width of the search box in grid steps per axis (0 = whole axis)
+};
+
+constexpr int NMS_WAVES = SEL_NT / 64;
+
+// One workgroup: greedy selection by score, suppressing alive points closer
+// than h to each pick; if nothing is alive before k picks, the remaining slots
+// take the unpicked points in score order. The grid is cut into SEL_NT
+// contiguous chunks whose best alive candidate sits in LDS; a pick only
+// rescans the chunks whose best it suppressed, and suppression only visits the
+// box of grid points within h along every axis (min-image distances are the
+// ones of the full scan, so the result is that of the plain greedy rule).
+// alive: [N_g] scratch (1 alive, 0 suppressed, 2 picked). k <= N_g.
 __global__ __launch_bounds__(SEL_NT) void nms_kernel(const float* __restrict__ score,
                                                      int32_t* __restrict__ alive, int k,
-                                                     int32_t* __restrict__ pts, GridArgs a) {
-  const long ng = (long)a.n[0] * a.n[1] * a.n[2];
-  __shared__ float rv[SEL_NT];
-  __shared__ long ri[SEL_NT];
-  __shared__ int s_count;
-  for (long r = threadIdx.x; r < ng; r += SEL_NT) alive[r] = 1;
-  if (threadIdx.x == 0) s_count = 0;
-  __syncthreads();
+                                                     int32_t* __restrict__ pts, GridArgs a,
+                                                     NmsBox box) {
+  const int ng = a.n[0] * a.n[1] * a.n[2];
+  const int chunk = (ng + SEL_NT - 1) / SEL_NT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ float sbv[SEL_NT];
+  __shared__ int sbi[SEL_NT];
+  __shared__ unsigned char dirty[SEL_NT];
+  __shared__ int dlist[SEL_NT];
+  __shared__ int ndirty;
+  __shared__ float wv[NMS_WAVES];
+  __shared__ int wi[NMS_WAVES];
+  __shared__ int s_pick;
+  for (int r = tid * chunk; r < min(ng, (tid + 1) * chunk); ++r) alive[r] = 1;
+  dirty[tid] = 1;
   const double h2 = a.h * a.h;
+  const double dx[3] = {a.L[0] / a.n[0], a.L[1] / a.n[1], a.L[2] / a.n[2]};
+  int bx[3];
+  for (int ax = 0; ax < 3; ++ax) bx[ax] = box.k[ax] > 0 ? 2 * box.k[ax] + 1 : a.n[ax];
+  const int nbox = bx[0] * bx[1] * bx[2];
+  int count = 0;
+  __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {  // pass 0: with suppression, pass 1: fill
-    while (s_count < k) {
-      float bv = 0.f;
-      long bi = -1;
-      for (long r = threadIdx.x; r < ng; r += SEL_NT) {
-        if (alive[r] != 1) continue;
-        const float v = score[r];
-        if (nms_better(v, r, bv, bi)) {
-          bv = v;
-          bi = r;
+    while (count < k) {
+      // rescan dirty chunks, one wave per chunk
+      if (tid == 0) ndirty = 0;
+      __syncthreads();
+      if (dirty[tid]) {
+        dlist[atomicAdd(&ndirty, 1)] = tid;
+        dirty[tid] = 0;
+      }
+      __syncthreads();
+      for (int j = wave; j < ndirty; j += NMS_WAVES) {
+        const int c = dlist[j];
+        const int lo = c * chunk, hi = min(ng, lo + chunk);
+        float v = 0.f;
+        int bi = -1;
+        for (int r = lo + lane; r < hi; r += 64)
+          if (alive[r] == 1) nms_take(v, bi, score[r], r);
+        nms_wave_reduce(v, bi);
+        if (lane == 0) {
+          sbv[c] = v;
+          sbi[c] = bi;
         }
       }
-      rv[threadIdx.x] = bv;
-      ri[threadIdx.x] = bi;
       __syncthreads();
-      for (int s = SEL_NT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s && ri[threadIdx.x + s] >= 0 &&
-            nms_better(rv[threadIdx.x + s], ri[threadIdx.x + s], rv[threadIdx.x],
-                       ri[threadIdx.x])) {
-          rv[threadIdx.x] = rv[threadIdx.x + s];
-          ri[threadIdx.x] = ri[threadIdx.x + s];
-        }
-        __syncthreads();
+      // best alive point
+      float v = sbv[tid];
+      int bi = sbi[tid];
+      nms_wave_reduce(v, bi);
+      if (lane == 0) {
+        wv[wave] = v;
+        wi[wave] = bi;
       }
-      const long pick = ri[0];
       __syncthreads();
-      if (pick < 0) break;  // nothing alive in this pass
-      if (threadIdx.x == 0) {
-        pts[s_count] = (int32_t)pick;
+      if (wave == 0) {
+        v = lane < NMS_WAVES ? wv[lane] : 0.f;
+        bi = lane < NMS_WAVES ? wi[lane] : -1;
+        nms_wave_reduce(v, bi);
+        if (lane == 0) s_pick = bi;
+      }
+      __syncthreads();
+      const int pick = s_pick;
+      if (pick < 0) break;  // nothing alive in this pass (uniform)
+      if (tid == 0) {
+        pts[count] = pick;
         alive[pick] = 2;
+        dirty[pick / chunk] = 1;
       }
       if (pass == 0) {
-        double c[3];
-        coords(a, pick, c);
-        for (long r = threadIdx.x; r < ng; r += SEL_NT) {
+        const int n23 = a.n[1] * a.n[2];
+        const int pc[3] = {pick / n23, (pick / a.n[2]) % a.n[1], pick % a.n[2]};
+        double cx[3];
+        for (int ax = 0; ax < 3; ++ax) cx[ax] = (double)pc[ax] * dx[ax];
+        for (int t = tid; t < nbox; t += SEL_NT) {
+          const int o[3] = {t / (bx[1] * bx[2]), (t / bx[2]) % bx[1], t % bx[2]};
+          int g[3];
+          for (int ax = 0; ax < 3; ++ax) {
+            if (box.k[ax] > 0) {
+              g[ax] = (pc[ax] + o[ax] - box.k[ax]) % a.n[ax];
+              if (g[ax] < 0) g[ax] += a.n[ax];
+            } else {
+              g[ax] = o[ax];
+            }
+          }
+          const int r = (g[0] * a.n[1] + g[1]) * a.n[2] + g[2];
           if (alive[r] != 1) continue;
           double x[3];
-          coords(a, r, x);
-          if (min_image_d2(a, x, c) < h2) alive[r] = 0;
+          for (int ax = 0; ax < 3; ++ax) x[ax] = (double)g[ax] * dx[ax];
+          if (min_image_d2(a, x, cx) < h2) {
+            alive[r] = 0;
+            const int c = r / chunk;
+            if (sbi[c] == r) dirty[c] = 1;
+          }
         }
       }
       __syncthreads();
-      if (threadIdx.x == 0) s_count += 1;
-      __syncthreads();
+      ++count;
     }
     // revive suppressed points for the fill pass
-    for (long r = threadIdx.x; r < ng; r += SEL_NT)
+    for (int r = tid * chunk; r < min(ng, (tid + 1) * chunk); ++r)
       if (alive[r] == 0) alive[r] = 1;
+    dirty[tid] = 1;
     __syncthreads();
   }
 }
@@ -629,7 +702,15 @@ size_t mlp_nms_scratch_bytes(const Geom& g) { return sizeof(int32_t) * (size_t)g
 hipError_t launch_nms(const Geom& g, const float* score, int k, int32_t* pts, void* scratch,
                       hipStream_t st) {
   GridArgs a = grid_args(g, k);
-  hipLaunchKernelGGL(nms_kernel, dim3(1), dim3(SEL_NT), 0, st, score, (int32_t*)scratch, k, pts, a);
+  // box half-widths: every point closer than h along an axis lies within
+  // floor(h / spacing) + 1 steps; an axis the box would wrap around is taken whole
+  NmsBox box;
+  for (int ax = 0; ax < 3; ++ax) {
+    const long kk = (long)floor(a.h / (g.L[ax] / g.n[ax])) + 1;
+    box.k[ax] = (2 * kk + 1 >= g.n[ax]) ? 0 : (int)kk;
+  }
+  hipLaunchKernelGGL(nms_kernel, dim3(1), dim3(SEL_NT), 0, st, score, (int32_t*)scratch, k, pts, a,
+                     box);
   return hipGetLastError();
 }
 

@@ -1,0 +1,121 @@
+"""What the trained selector gains over the method without it (QRCP selection),
+on cells held out from its training set.
+
+* Time: the learned selection (descriptors, network, NMS and the fit-residual
+  probe) against the GPU QRCP selection of the same number of points.
+* Quality, reported and compared with two baselines that use no training (the
+  same network at its initial parameters, and uniformly random points): the
+  probe residual and the exchange energy of the FP64 K-build at the chosen
+  points, against the build at the QRCP points and, on one small cell, against
+  the exact exchange of the direct oracle. The quality of the learned points
+  has no value fixed by the paper (it is parity unpinned); the assertions only
+  require the trained network to beat the untrained baselines.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct
+
+pytestmark = pytest.mark.gpu
+
+HELD_OUT = (187, 188, 192, 199)  # two Gamma-only and two 2x2x2 cells
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2304_05505_amd import exx, mlp
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    w = mlp.load_weights()
+    theta = torch.from_numpy(w["theta"]).to(dev)
+    theta0 = torch.from_numpy(mlp.init_params(0)).to(dev)
+    return torch, exx, mlp, dev, h, w, theta, theta0
+
+
+def _ex(torch, exx, dev, h, cd, pts_t):
+    cell = cd.cell
+    pts = pts_t.cpu().numpy().astype(np.int64)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    t_ao = torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev)
+    occ = cd.psi[:, :, pts_t.long()].permute(0, 2, 1).contiguous()
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, len(pts))
+    K = torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128, device=dev)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((cell.N_k,), dtype=torch.int32, device=dev)
+    exx.exx_build(h, c, exx.EXX_F64, cd.psi, occ, t_ao, pts_t, K, Ex, rank)
+    return float(Ex.cpu()[0])
+
+
+def test_trained_selector_beats_untrained_baselines(env, gpu):
+    torch, exx, mlp, dev, h, w, theta, theta0 = env
+    rows = []
+    for i in HELD_OUT:
+        cd = mlp.CellData(mlp.training_cell(i), dev)
+        ni = cd.cell.n_isdf
+        q = cd.qrcp(h)
+        m, used, r_m = cd.select(h, w["norm"], theta, float("inf"))
+        u, _, r_u = cd.select(h, w["norm"], theta0, float("inf"))
+        rng = np.random.default_rng(1000 + i)
+        rnd = torch.from_numpy(rng.choice(cd.cell.N_g, ni, replace=False).astype(np.int32)).to(dev)
+        row = {"cell": cd.cell.name, "resid": {"qrcp": cd.probe(h, q), "mlp": r_m, "untrained": r_u,
+                                               "random": cd.probe(h, rnd)}}
+        row["Ex"] = {k: _ex(torch, exx, dev, h, cd, p) for k, p in
+                     (("qrcp", q), ("mlp", m), ("untrained", u), ("random", rnd))}
+        rows.append(row)
+        del cd
+    for r in rows:
+        e = r["Ex"]
+        print(f"{r['cell']}: resid qrcp {r['resid']['qrcp']:.4f} mlp {r['resid']['mlp']:.4f} "
+              f"untrained {r['resid']['untrained']:.4f} random {r['resid']['random']:.4f}; "
+              f"E_x qrcp {e['qrcp']:.6f}, mlp-qrcp {e['mlp'] - e['qrcp']:+.2e}, "
+              f"untrained-qrcp {e['untrained'] - e['qrcp']:+.2e}, random-qrcp {e['random'] - e['qrcp']:+.2e}")
+    ratio = lambda k: np.array([r["resid"][k] / r["resid"]["qrcp"] for r in rows])  # noqa: E731
+    dE = lambda k: np.array([abs(r["Ex"][k] - r["Ex"]["qrcp"]) for r in rows])  # noqa: E731
+    assert np.all(ratio("mlp") < ratio("random"))
+    assert np.median(ratio("mlp")) < np.median(ratio("untrained"))
+    assert np.mean(dE("mlp")) < np.mean(dE("random"))
+    assert np.mean(dE("mlp")) < np.mean(dE("untrained"))
+
+
+def test_fitted_exchange_error_against_the_exact_oracle(env, gpu):
+    """Cell 194 (12 atoms, Gamma): E_x of the build at the QRCP and at the learned
+    points against the direct exchange of the occupied orbitals (oracle O1)."""
+    torch, exx, mlp, dev, h, w, theta, theta0 = env
+    cd = mlp.CellData(mlp.training_cell(194), dev)
+    q = cd.qrcp(h)
+    m, _, _ = cd.select(h, w["norm"], theta, float("inf"))
+    e_q, e_m = _ex(torch, exx, dev, h, cd, q), _ex(torch, exx, dev, h, cd, m)
+    psi = cd.psi.cpu().numpy()
+    e_exact = direct.exchange_energy(cd.cell.L, cd.cell.grid, cd.cell.kmesh, psi)
+    print(f"E_x exact {e_exact:.6f}; QRCP points {e_q - e_exact:+.3e}; learned points {e_m - e_exact:+.3e}")
+    assert e_exact < 0
+    # at N_ISDF = 5 n_occ both fits are approximate; the learned one stays within 3x of QRCP's error
+    assert abs(e_m - e_exact) <= 3.0 * abs(e_q - e_exact) + 1e-6 * abs(e_exact)
+
+
+def test_learned_selection_is_faster_than_qrcp(env, gpu):
+    torch, exx, mlp, dev, h, w, theta, theta0 = env
+    cd = mlp.CellData(mlp.training_cell(193), dev)  # 40 atoms, 2x2x2, N_ISDF 350
+    cd.qrcp(h)
+    cd.select(h, w["norm"], theta, w["tau"])
+    torch.cuda.synchronize()
+    tq, tm = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        cd.qrcp(h)
+        torch.cuda.synchronize()
+        tq.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        _, used, _ = cd.select(h, w["norm"], theta, float("inf"))
+        torch.cuda.synchronize()
+        tm.append(time.perf_counter() - t0)
+    print(f"selection time: QRCP {1e3 * np.median(tq):.1f} ms, learned {1e3 * np.median(tm):.1f} ms")
+    assert not used
+    assert np.median(tm) < 0.5 * np.median(tq)
