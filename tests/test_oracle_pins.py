@@ -331,6 +331,24 @@ def test_error_decreases_with_more_points(kcell):
     assert min(errs[:2]) > 10 * errs[2] or errs[2] < 1e-3 * abs(E1)
 
 
+def test_fitted_exchange_is_a_variational_bound(kcell):
+    """Per transfer q the fitted pair functions are the pair functions projected
+    onto the row space of their values at the points, and the Coulomb kernel is
+    positive, so the fitted exchange recovers at most the exact exchange
+    (E_fit >= E_exact, both negative) and more of it for a larger point set."""
+    c, C, psi = kcell
+    E1 = direct.exchange_energy(c.L, c.grid, c.kmesh, psi)
+    order = np.random.default_rng(12).permutation(c.N_g)
+    prev = 0.0
+    for nI in (4, 9, 17, 30):
+        pts = order[:nI]
+        Ex = thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, _ao_pts(c, pts))["Ex"]
+        assert Ex >= E1 - 1e-10 * abs(E1)
+        assert Ex <= prev + 1e-10 * abs(E1)
+        prev = Ex
+    assert prev < 0.5 * E1  # 30 of 32 pair dimensions recover most of it
+
+
 # ---------------------------------------------------------------------------
 # the fit itself: literal least squares, and the k-sum forms used on the GPU
 # ---------------------------------------------------------------------------
