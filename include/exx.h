@@ -336,6 +336,16 @@ exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_batch_item* it
                              exx_prec prec, int32_t flags, hipStream_t stream);
 
 /*
+ * exx_set_refinement -- steps (0, the default, or 1) of iterative refinement
+ * applied by every later fit of this handle (exx_isdf_fit, exx_build,
+ * exx_build_batched): after xi^m = S^+ Z^m, the residual R^m = Z^m - S^m xi^m
+ * and the correction xi^m += S^+ R^m are formed with FP64 arithmetic on the
+ * stored operands (two more grid-sized GEMMs per fit). With the pivot-drop
+ * rule the correction is confined to the retained points like the solve.
+ */
+exx_status exx_set_refinement(exx_handle_t h, int32_t steps);
+
+/*
  * Per-phase timing (instrumentation, not part of the method). When enabled,
  * the library records a pair of HIP events on the call's stream around each
  * phase of every subsequent call. exx_phase_times synchronises on those

@@ -237,6 +237,17 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
                             (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
+  if (h->refine > 0) {
+    // one step of iterative refinement: Z <- Z - S^m xi (the residual, over Z),
+    // then xi <- xi + S^+ Z; both products in FP64 arithmetic
+    PhaseTimer pt(h, PH_SOLVE, st);
+    e = zgemm_nn_grid_acc<TX, TF>(g.ni, g.ng, g.ni, g.nk, S, g.ni, nn, xi, g.ng,
+                                  (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, -1, st);
+    if (e != hipSuccess) return hip_check(h, e, "refinement residual");
+    e = zgemm_nn_grid_acc<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, grid, g.ng,
+                                  (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, 1, st);
+    if (e != hipSuccess) return hip_check(h, e, "refinement update");
+  }
   return EXX_OK;
 }
 
@@ -442,6 +453,14 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   return buildK_impl(h, g, ws, L, ao_pts, occ_pts, V, K, Ex, stream);
 }
 
+exx_status exx_set_refinement(exx_handle_t h, int32_t steps) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (steps < 0 || steps > 1) return fail(h, EXX_ERR_ARG, "exx_set_refinement: steps must be 0 or 1");
+  h->refine = steps;
+  return EXX_OK;
+}
+
 exx_status exx_set_timing(exx_handle_t h, int enable) {
   if (!h) return EXX_ERR_ARG;
   (void)hipSetDevice(h->device);
@@ -629,9 +648,10 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   if (stream == nullptr)
     return fail(h, EXX_ERR_ARG, "EXX_BATCH_GRAPH needs a non-default stream (capture)");
 
-  // signature: precision, workspace base and every item field
+  // signature: precision, refinement, workspace base and every item field
   std::vector<long> sig;
   sig.push_back((long)prec);
+  sig.push_back((long)h->refine);
   sig.push_back((long)(size_t)ws);
   for (int i = 0; i < n; ++i) {
     const exx_batch_item& it = items[i];

@@ -112,6 +112,8 @@ struct exx_context {
   // wave tiles of the grid GEMMs (see zgemm_nn_grid)
   int tile_gamma = 22;
   int tile_solve = 22;
+  // steps of iterative refinement after the fit solve (0 or 1)
+  int refine = 0;
   int ncu = 256;
   // autotuned wave tiles per size class: key (ni, ng, no, nk, prec) -> (gamma, solve)
   struct Tune {
@@ -193,6 +195,13 @@ template <typename TB, typename TC>
 hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                          hipStream_t st, int tile);
+
+// C[b] = C[b] + sign * A[b] * B[b] (sign = +1 or -1), same operands as zgemm_nn_grid
+// (tile 22, no conjugation); used by the iterative refinement of the fit
+template <typename TB, typename TC>
+hipError_t zgemm_nn_grid_acc(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                             const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                             int sign, hipStream_t st);
 
 // Gamma^n(P, r) = sum_i occ[n][P][i] conj psi[n][i][r]  (fit right-hand side factor)
 template <typename T>

@@ -32,7 +32,8 @@ __device__ __forceinline__ long xcd_remap(long bid, long total_padded) {
 }
 
 // Wave tile: WM x WN blocks of 16x16; workgroup = 2 x 2 waves.
-template <typename TB, typename TC, int WM, int WN, int CONJB>
+// ACC = 0: C = A op(B); ACC = +1 / -1: C = C +/- A op(B) (arithmetic in FP64).
+template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC>
 __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nrt, long ntiles,
                                                      long ntiles_pad, const double2* __restrict__ A,
                                                      long lda, long sA,
@@ -129,7 +130,14 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
           const long c = col0 + j * 16 + li;
-          if (c < N) C[(long)r * ldc + c] = mk<TC>(are[i][j][v], aim[i][j][v]);
+          if (c >= N) continue;
+          if constexpr (ACC == 0) {
+            C[(long)r * ldc + c] = mk<TC>(are[i][j][v], aim[i][j][v]);
+          } else {
+            const cplx<TC> o = C[(long)r * ldc + c];
+            C[(long)r * ldc + c] = mk<TC>((double)o.x + ACC * are[i][j][v],
+                                          (double)o.y + ACC * aim[i][j][v]);
+          }
         }
       }
   } else {
@@ -154,23 +162,30 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double xr = sre[v * 64 + lane], xi = sim[v * 64 + lane];
+          double xr = sre[v * 64 + lane], xi = sim[v * 64 + lane];
           const int r = row0 + i * 16 + 4 * v + lk;
           const long c = col0 + j * 16 + li;
-          if (r < M && c < N) C[(long)r * ldc + c] = mk<TC>((TC)xr, (TC)xi);
+          if (r < M && c < N) {
+            if constexpr (ACC != 0) {
+              const cplx<TC> o = C[(long)r * ldc + c];
+              xr = (double)o.x + ACC * xr;
+              xi = (double)o.y + ACC * xi;
+            }
+            C[(long)r * ldc + c] = mk<TC>((TC)xr, (TC)xi);
+          }
         }
       }
   }
 }
 
-template <typename TB, typename TC, int WM, int WN, int CONJB>
+template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC = 0>
 hipError_t run_nn(int M, int N, int K, int batch, const void* A, long lda, long sA, const void* B,
                   long ldb, long sB, void* C, long ldc, long sC, hipStream_t st) {
   const int nrt = (M + 2 * WM * 16 - 1) / (2 * WM * 16);
   const long nct = ((long)N + 2 * WN * 16 - 1) / (2 * WN * 16);
   const long ntiles = nrt * nct;
   const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
-  hipLaunchKernelGGL((zgemm_nn_mfma<TB, TC, WM, WN, CONJB>), dim3((unsigned)pad, batch), dim3(256),
+  hipLaunchKernelGGL((zgemm_nn_mfma<TB, TC, WM, WN, CONJB, ACC>), dim3((unsigned)pad, batch), dim3(256),
                      0, st, M, N, K, nrt, ntiles, pad, (const double2*)A, lda, sA,
                      (const cplx<TB>*)B, ldb, sB, (cplx<TC>*)C, ldc, sC);
   return hipGetLastError();
@@ -204,6 +219,27 @@ hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
     return run_nn_tile<TB, TC, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
   return run_nn_tile<TB, TC, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
 }
+
+template <typename TB, typename TC>
+hipError_t zgemm_nn_grid_acc(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                             const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                             int sign, hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (K <= 0) return hipErrorInvalidValue;
+  if (sign > 0)
+    return run_nn<TB, TC, 2, 2, 0, 1>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+  return run_nn<TB, TC, 2, 2, 0, -1>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+}
+
+#define EXX_ACC_INST(TB, TC)                                                                  \
+  template hipError_t zgemm_nn_grid_acc<TB, TC>(int, int, int, int, const void*, long, long, \
+                                                const void*, long, long, void*, long, long,  \
+                                                int, hipStream_t);
+EXX_ACC_INST(double, double)
+EXX_ACC_INST(float, double)
+EXX_ACC_INST(double, float)
+EXX_ACC_INST(float, float)
+#undef EXX_ACC_INST
 
 template hipError_t zgemm_nn_grid<double, double>(int, int, int, int, const void*, long, long,
                                                   bool, const void*, long, long, void*, long, long,

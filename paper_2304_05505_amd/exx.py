@@ -40,6 +40,7 @@ EXPORTED = (
     "exx_build",
     "exx_select_points",
     "exx_set_timing",
+    "exx_set_refinement",
     "exx_phase_times",
     "exx_build_batched",
     "exx_mlp_features",
@@ -108,6 +109,7 @@ def _load():
         "exx_build": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "exx_select_points": ([vp, cellp, vp, vp, vp, vp], ctypes.c_int),
         "exx_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
+        "exx_set_refinement": ([vp, ctypes.c_int32], ctypes.c_int),
         "exx_build_batched": ([vp, ctypes.c_int32, ctypes.POINTER(ExxBatchItem), ctypes.c_int,
                                ctypes.c_int32, vp], ctypes.c_int),
         "exx_phase_times": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
@@ -214,6 +216,10 @@ class Handle:
     @property
     def raw(self):
         return self._h
+
+    def set_refinement(self, steps: int):
+        """Steps (0 or 1) of iterative refinement after every fit solve of this handle."""
+        self._check(_lib.exx_set_refinement(self._h, int(steps)))
 
     def set_timing(self, enable: bool):
         self._check(_lib.exx_set_timing(self._h, 1 if enable else 0))
