@@ -16,7 +16,8 @@ FP32 FFT and Coulomb contraction with FP64 accumulation) and f32 (bulk FP32).
 Prints one JSON line. Options: --steps K --warmup W --gpus N (N must be 1)
 --prec auto|f64|mixed|f32 --no-cpu --profile; --workload select-k4 instead times
 the learned and the QRCP point selection at the 4x4x4 ring workload, each
-followed by one FP32 K-build.
+followed by one FP32 K-build; --workload batch24 times the 24-cell batched
+build (one graph launch) against 24 sequential FP64 builds.
 """
 
 from __future__ import annotations
@@ -240,6 +241,103 @@ def bench_select5(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_batch24(args):
+    """The 24-cell batch (2 x {8, 16, 24, 48 atoms} x {1, 2, 3}^3 k-meshes): one
+    batched call (hipGraph replay, autotuned tiles) against 24 sequential plain
+    FP64 builds, with the per-cell E_x and K differences."""
+    import torch
+
+    import synth
+    from paper_2304_05505_amd import exx
+    from synth.fast import orbitals_on_grid_torch
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    t0 = time.perf_counter()
+    items64, items_mx, items32 = [], [], []
+    for cell in synth.make_batch_cells():
+        psi = orbitals_on_grid_torch(cell, synth.orbital_coeffs(cell), dev)
+        c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, cell.n_isdf)
+        pts_t = torch.empty((cell.n_isdf,), dtype=torch.int32, device=dev)
+        npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+        exx.exx_select_points(h, c, psi, pts_t, npiv)
+        pts = pts_t.cpu().numpy().astype(np.int64)
+        ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+        t_ao = torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev)
+        occ = psi[:, :, pts_t.long()].permute(0, 2, 1).contiguous()
+        base = {"cell": c, "occ_pts": occ, "ao_pts": t_ao, "pts": pts_t}
+        for lst, p in ((items64, psi), (items_mx, psi), (items32, psi.to(torch.complex64))):
+            lst.append(dict(base, psi_grid=p,
+                            K=torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128,
+                                          device=dev),
+                            Ex=torch.empty((1,), dtype=torch.float64, device=dev),
+                            rank=torch.empty((cell.N_k,), dtype=torch.int32, device=dev)))
+    torch.cuda.synchronize()
+    log(f"[batch24] inputs and QRCP points for 24 cells in {time.perf_counter() - t0:.1f} s")
+
+    def sequential_f64():
+        for it in items64:
+            exx.exx_build(h, it["cell"], exx.EXX_F64, it["psi_grid"], it["occ_pts"], it["ao_pts"],
+                          it["pts"], it["K"], it["Ex"], it["rank"])
+
+    stream = torch.cuda.Stream()
+
+    def batched(prec, items):
+        stream.wait_stream(torch.cuda.current_stream())
+        exx.exx_build_batched(h, items, prec, exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_TUNE,
+                              stream=stream)
+        stream.synchronize()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    reps = max(1, min(args.steps, 3))
+    t_seq = timed(sequential_f64, reps)
+    ex64 = [float(it["Ex"].cpu()[0]) for it in items64]
+    k64 = [it["K"].cpu().numpy() for it in items64]
+    log(f"[batch24] 24 sequential FP64 builds: {t_seq * 1e3:.1f} ms")
+    res = {}
+    for name, prec, items in (("f32", exx.EXX_F32, items32), ("mixed", exx.EXX_MIXED, items_mx),
+                              ("f64", exx.EXX_F64, items64)):
+        t_b = timed(lambda: batched(prec, items), reps)
+        dEs = [abs(float(it["Ex"].cpu()[0]) - e) for it, e in zip(items, ex64)]
+        dKs = [float(np.abs(it["K"].cpu().numpy() - k).max()) for it, k in zip(items, k64)]
+        dE, dK = max(dEs), max(dKs)
+        res[name] = {"seconds": t_b, "builds_per_s": 24.0 / t_b, "speedup_vs_seq_f64": t_seq / t_b,
+                     "max_dEx_vs_f64": dE, "max_dK_vs_f64": dK,
+                     "meets_1e-5_1e-6": bool(dE <= 1e-5 and dK <= 1e-6),
+                     "dEx_per_cell": dEs}
+        log(f"[batch24] batched {name}: {t_b * 1e3:.1f} ms, max|dEx| {dE:.2e}, max|dK| {dK:.2e}")
+    ok = [n for n in res if res[n]["meets_1e-5_1e-6"]]
+    chosen = max(ok, key=lambda n: res[n]["builds_per_s"])
+    out = {
+        "metric": "K-builds/s over a 24-cell batch (one graph launch) vs 24 sequential plain FP64 "
+                  "builds, at |dE_x| <= 1e-5 Ha/cell and max|dK| <= 1e-6",
+        "value": res[chosen]["builds_per_s"],
+        "path": chosen,
+        "unit": "K-builds/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "mixed": "f64+f32", "f32": "f32+f64"}[chosen],
+        "data": "synthetic",
+        "config": {"workload": "24 cells: 2 x {8, 16, 24, 48 atoms} x {1, 2, 3}^3 k-meshes, 4 "
+                               "functions/atom, n_occ = 0.44 N, N_ISDF = 2.2 N, QRCP points"},
+        "sequential_f64_s": t_seq,
+        "batched": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,9 +348,10 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiling target: one build per precision path and a 1 GiB device "
                          "copy, no JSON")
-    ap.add_argument("--workload", choices=("rings-k2", "select-k4"), default="rings-k2",
+    ap.add_argument("--workload", choices=("rings-k2", "select-k4", "batch24"), default="rings-k2",
                     help="rings-k2: the K-build throughput line (default); select-k4: learned vs "
-                         "QRCP selection + K-build at the 4x4x4 ring workload")
+                         "QRCP selection + K-build at the 4x4x4 ring workload; batch24: the "
+                         "24-cell batched build against sequential FP64 builds")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the build is not sharded "
@@ -260,6 +359,9 @@ def main():
         sys.exit(2)
     if args.workload == "select-k4":
         bench_select5(args)
+        return
+    if args.workload == "batch24":
+        bench_batch24(args)
         return
 
     import torch
