@@ -1,9 +1,9 @@
 // Coulomb matrices of the interpolating vectors in reciprocal space:
 //   V^m_PQ = (Omega/N_g^2) sum_g v^m(g) F_P(g) conj F_Q(g),  v^m = 4 pi/|K|^2,
-// as a Hermitian rank-N_g update split over grid chunks. sqrt(v^m(g)) scales
-// both operands while they are staged in LDS; the kernel value is generated
-// on the fly from the K-box rule. A reduction kernel sums the chunks, mirrors
-// the upper triangle and applies the Bloch-gauge phase.
+// as a Hermitian rank-N_g update split over grid chunks on the matrix cores.
+// The kernel values v^m(g) (K-box rule, K = 0 dropped) are tabulated once per
+// call; a reduction kernel sums the chunks, mirrors the upper triangle and
+// applies the Bloch-gauge phase.
 #include <cmath>
 #include <type_traits>
 
@@ -35,8 +35,6 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int MW = 2;       // 16-blocks per wave in each direction (wave tile 32 x 32)
 constexpr int MTILE = 64;   // workgroup tile (2 x 2 waves)
 constexpr int FLUSH = 64;   // FP32 accumulation length before the FP64 flush
-constexpr int TPL = 2;      // consecutive grid values per lane and chunk
-constexpr int CK = 4 * TPL; // grid points per chunk
 
 // Accumulators of one wave tile (MW x MW blocks of 16x16, real and imaginary).
 template <bool F64MMA>
@@ -113,13 +111,40 @@ struct CAcc<false> {  // FP32 matrix cores, FP32 accumulation flushed into FP64
   static __device__ int row(int gq, int v) { return 4 * gq + v; }
 };
 
+// v^m(g) for every transfer m and grid point g: 4 pi/|K|^2 with the K-box
+// representative of each axis, 0 for K = 0
+__global__ __launch_bounds__(256) void coulomb_vtab_kernel(double* __restrict__ vt, CoulArgs a) {
+  const long g = (long)blockIdx.x * 256 + threadIdx.x;
+  const int m = blockIdx.y;
+  if (g >= a.ng) return;
+  const int n23 = a.n[1] * a.n[2];
+  const int gc[3] = {(int)(g / n23), (int)((g / a.n[2]) % a.n[1]), (int)(g % a.n[2])};
+  const int mm[3] = {m / (a.N[1] * a.N[2]), (m / a.N[2]) % a.N[1], m % a.N[2]};
+  double kk = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int kap = wrap_sym(a.N[ax] * gc[ax] + mm[ax], a.N[ax] * a.n[ax]);
+    const double K = kap * (2.0 * M_PI / (a.N[ax] * a.L[ax]));
+    kk += K * K;
+  }
+  vt[(long)m * a.ng + g] = kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
+}
+
 // T: storage of F. F64MMA: FP64 matrix cores (exact products of FP32 inputs, FP64
 // accumulation) even for FP32 storage; otherwise FP32 matrix cores with flushes.
+// Work item w = (transfer m, grid split s, lower-triangle 64x64 tile); the
+// workgroup order is XCD-aware so that the tiles of one (m, s) share an L2.
+// Loads are unconditional with clamped indices (rows past N_ISDF feed outputs
+// that are never stored; grid points past the chunk get v = 0 at use), and
+// NPF chunks are in flight in registers.
 template <typename T, bool F64MMA>
 __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __restrict__ F,
+                                                           const double* __restrict__ vt,
                                                            double2* __restrict__ part, CoulArgs a,
                                                            long nwork, long nwork_pad) {
   using TO = typename std::conditional<F64MMA, double, float>::type;
+  // grid values per lane and chunk: the FP32 path takes twice as many per load
+  constexpr int TPL = F64MMA ? 2 : 4;
+  constexpr int CK = 4 * TPL;
   const long per = nwork_pad / 8;
   const long w = (blockIdx.x % 8) * per + blockIdx.x / 8;  // XCD-contiguous ranges
   if (w >= nwork) return;
@@ -139,83 +164,60 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
   const long g0 = (long)s * a.chunk;
   const long g1 = min((long)a.ng, g0 + a.chunk);
   const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
-  const int m1 = m / (a.N[1] * a.N[2]), m2 = (m / a.N[2]) % a.N[1], m3 = m % a.N[2];
-
-  // per-axis squared components of K for this transfer: |K|^2 = T0[g1] + T1[g2] + T2[g3]
-  __shared__ double sK2[3][128];
-  for (int e = threadIdx.x; e < a.n[0] + a.n[1] + a.n[2]; e += 256) {
-    const int ax = e < a.n[0] ? 0 : (e < a.n[0] + a.n[1] ? 1 : 2);
-    const int gi = e - (ax == 0 ? 0 : (ax == 1 ? a.n[0] : a.n[0] + a.n[1]));
-    const int mi = ax == 0 ? m1 : (ax == 1 ? m2 : m3);
-    const int kap = wrap_sym(a.N[ax] * gi + mi, a.N[ax] * a.n[ax]);
-    const double K = kap * (2.0 * M_PI / (a.N[ax] * a.L[ax]));
-    sK2[ax][gi] = K * K;
-  }
-  __syncthreads();
-  const int n2 = a.n[1], n3 = a.n[2];
-  // v^m at TPL consecutive grid points starting at gb (int32 index arithmetic)
-  auto vchunk = [&](long gb, double* vv) {
-    int g = (int)gb;
-    int q = g / n3;
-    int c3 = g - q * n3;
-    int c1 = q / n2;
-    int c2 = q - c1 * n2;
+  const double* vm = vt + (long)m * a.ng;
+  // row bases (clamped rows only feed unstored outputs)
+  const cplx<T>* xrow[MW];
+  const cplx<T>* yrow[MW];
 #pragma unroll
-    for (int t = 0; t < TPL; ++t) {
-      const double kk = sK2[0][c1] + sK2[1][c2] + sK2[2][c3];
-      vv[t] = (gb + t < g1 && kk > 0.0) ? 4.0 * M_PI / kk : 0.0;
-      if (++c3 == n3) {
-        c3 = 0;
-        if (++c2 == n2) {
-          c2 = 0;
-          if (++c1 == a.n[0]) c1 = 0;
-        }
-      }
-    }
-  };
+  for (int i = 0; i < MW; ++i) {
+    const int P = min(P0 + 16 * i + li, a.ni - 1), Q = min(Q0 + 16 * i + li, a.ni - 1);
+    xrow[i] = Fm + (long)P * a.ng;
+    yrow[i] = Fm + (long)Q * a.ng;
+  }
 
   CAcc<F64MMA> acc;
   acc.init();
-  // double-buffered register pipeline over CK-point grid chunks
-  cplx<T> rx[2][MW][TPL], ry[2][MW][TPL];
-  auto load = [&](long k0, cplx<T> (*xx)[TPL], cplx<T> (*yy)[TPL]) {
+  constexpr int NPF = 2;  // chunks in flight
+  cplx<T> fx[NPF][MW][TPL], fy[NPF][MW][TPL];
+  double fv[NPF][TPL];
+  auto load = [&](long k0, cplx<T> (*xx)[TPL], cplx<T> (*yy)[TPL], double* vv) {
     const long gb = k0 + TPL * gq;
-#pragma unroll
-    for (int i = 0; i < MW; ++i) {
-      const int P = P0 + 16 * i + li;
-      const int Q = Q0 + 16 * i + li;
-#pragma unroll
-      for (int t = 0; t < TPL; ++t) {
-        const bool ok = gb + t < g1;
-        xx[i][t] = (ok && P < a.ni) ? Fm[(long)P * a.ng + gb + t] : mk<T>(0, 0);
-        yy[i][t] = (ok && Q < a.ni) ? Fm[(long)Q * a.ng + gb + t] : mk<T>(0, 0);
-      }
-    }
-  };
-  auto compute = [&](long k0, cplx<T> (*xx)[TPL], cplx<T> (*yy)[TPL]) {
-    const long gb = k0 + TPL * gq;
-    double vd[TPL];
-    vchunk(gb, vd);
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
-      const TO vv = (TO)vd[t];
+      const long g = min(gb + t, (long)a.ng - 1);
+      vv[t] = vm[g];
 #pragma unroll
       for (int i = 0; i < MW; ++i) {
-        const TO xr = (TO)xx[i][t].x * vv, xi = (TO)xx[i][t].y * vv;
-#pragma unroll
-        for (int j = 0; j < MW; ++j) acc.mac(i, j, xr, xi, (TO)yy[j][t].x, (TO)yy[j][t].y);
+        xx[i][t] = xrow[i][g];
+        yy[i][t] = yrow[i][g];
       }
     }
-    acc.chunk_done(CK);
   };
-  // ping-pong between two statically indexed register buffers
-  if (g0 < g1) load(g0, rx[0], ry[0]);
-  for (long k0 = g0; k0 < g1; k0 += 2 * CK) {
-    if (k0 + CK < g1) load(k0 + CK, rx[1], ry[1]);
-    compute(k0, rx[0], ry[0]);
-    if (k0 + CK >= g1) break;
-    if (k0 + 2 * CK < g1) load(k0 + 2 * CK, rx[0], ry[0]);
-    compute(k0 + CK, rx[1], ry[1]);
+  const long nchunk = (g1 - g0 + CK - 1) / CK;
+#pragma unroll
+  for (int sl = 0; sl < NPF; ++sl) load(g0 + (long)sl * CK, fx[sl], fy[sl], fv[sl]);
+  for (long c = 0; c < nchunk; c += NPF) {
+#pragma unroll
+    for (int sl = 0; sl < NPF; ++sl) {
+      const long k0 = g0 + (c + sl) * CK;
+      const long gb = k0 + TPL * gq;
+#pragma unroll
+      for (int t = 0; t < TPL; ++t) {
+        const TO vv = (gb + t < g1) ? (TO)fv[sl][t] : (TO)0;
+#pragma unroll
+        for (int i = 0; i < MW; ++i) {
+          const TO xr = (TO)fx[sl][i][t].x * vv, xi = (TO)fx[sl][i][t].y * vv;
+#pragma unroll
+          for (int j = 0; j < MW; ++j)
+            acc.mac(i, j, xr, xi, (TO)fy[sl][j][t].x, (TO)fy[sl][j][t].y);
+        }
+      }
+      acc.chunk_done(CK);
+      // refill the slot (clamped loads past the end are discarded by v = 0)
+      __builtin_amdgcn_sched_barrier(0);
+      load(k0 + NPF * CK, fx[sl], fy[sl], fv[sl]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
 #pragma unroll
@@ -240,7 +242,7 @@ struct ReduceArgs {
   double scale;
 };
 
-// V[m][P][Q] = scale * e^{-i q_m.(r_P - r_Q)} sum_s part (mirrored for upper tiles)
+// V[m][P][Q] = scale * e^{-i q_m.(r_P - r_Q)} sum_s part (P < Q mirrored from Q > P)
 __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __restrict__ part,
                                                              const int32_t* __restrict__ pts,
                                                              double2* __restrict__ V,
@@ -250,7 +252,7 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __re
   const int m = blockIdx.y;
   if (idx >= nn) return;
   const int P = (int)(idx / a.ni), Q = (int)(idx % a.ni);
-  const bool lower = (P / MTILE) >= (Q / MTILE);
+  const bool lower = P >= Q;
   const long src = lower ? ((long)P * a.ni + Q) : ((long)Q * a.ni + P);
   double sx = 0.0, sy = 0.0;
   for (int s = 0; s < a.nsplit; ++s) {
@@ -298,8 +300,13 @@ int coulomb_nsplit(const Geom& g) {
   return (int)ns;
 }
 
+// partial sums [N_k][nsplit][N_I][N_I] c128, then the kernel table [N_k][N_g] double
+static size_t partial_only(const Geom& g, int nsplit) {
+  return ((size_t)g.nk * nsplit * g.ni * g.ni * sizeof(double2) + 255) / 256 * 256;
+}
+
 size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
-  return (size_t)g.nk * nsplit * g.ni * g.ni * sizeof(double2);
+  return partial_only(g, nsplit) + (size_t)g.nk * g.ng * sizeof(double);
 }
 
 template <typename T>
@@ -320,13 +327,21 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.ntile = nt * (nt + 1) / 2;
   const long nwork = (long)a.ntile * g.nk * nsplit;
   const long pad = (nwork + 7) / 8 * 8;
-  if (f64mma || sizeof(T) == 8)
-    hipLaunchKernelGGL((coulomb_mfma_kernel<T, true>), dim3((unsigned)pad), dim3(256), 0, st,
-                       (const cplx<T>*)F, (double2*)partial, a, nwork, pad);
-  else
-    hipLaunchKernelGGL((coulomb_mfma_kernel<T, false>), dim3((unsigned)pad), dim3(256), 0, st,
-                       (const cplx<T>*)F, (double2*)partial, a, nwork, pad);
+  double* vt = (double*)((char*)partial + partial_only(g, nsplit));
+  hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), g.nk), dim3(256), 0,
+                     st, vt, a);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bool fp64_cores = f64mma;
+  if constexpr (sizeof(T) == 8) fp64_cores = true;  // FP64 storage always uses FP64 cores
+  if (fp64_cores) {
+    hipLaunchKernelGGL((coulomb_mfma_kernel<T, true>), dim3((unsigned)pad), dim3(256), 0, st,
+                       (const cplx<T>*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+  } else if constexpr (sizeof(T) == 4) {
+    hipLaunchKernelGGL((coulomb_mfma_kernel<T, false>), dim3((unsigned)pad), dim3(256), 0, st,
+                       (const cplx<T>*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+  }
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   ReduceArgs r;
   for (int i = 0; i < 3; ++i) {
