@@ -88,9 +88,19 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
   }
 }
 
+// x / d for 0 <= x < 2^22 and d >= 1 from a float reciprocal: the float
+// quotient is off by at most one, which the remainder test corrects
+__device__ __forceinline__ int small_div(int x, int d, float inv) {
+  int q = (int)((float)x * inv);
+  const int r = x - q * d;
+  q += (r >= d) - (r < 0);
+  return q;
+}
+
 // One Stockham stage of radix R on `nlines` lines of length n stored in LDS
 // (element stride es, line stride ls); Ns = product of the radices done so far.
 // With LINE_FAST the butterfly index runs over lines first (use when ls == 1).
+// The index decomposition is done once per butterfly, without integer division.
 template <typename T, int R, int NT, int MAXPTS, bool LINE_FAST>
 __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, int es, int ls,
                                       const cplx<T>* tw) {
@@ -98,35 +108,37 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, i
   const int nb = n / R;
   const int total = nlines * nb;
   const int tid = threadIdx.x;
+  const int dmaj = LINE_FAST ? nlines : nb;  // divisor splitting b into (line, j)
+  const float imaj = 1.0f / (float)dmaj, ins = 1.0f / (float)Ns;
   cplx<T> v[MAXB][R];
+  int src[MAXB], dst[MAXB], stp[MAXB];
 #pragma unroll
   for (int s = 0; s < MAXB; ++s) {
     const int b = tid + s * NT;
     if (b < total) {
-      const int line = LINE_FAST ? b % nlines : b / nb;
-      const int j = LINE_FAST ? b / nlines : b % nb;
-      const cplx<T>* src = buf + line * ls;
+      const int q = small_div(b, dmaj, imaj);
+      const int rem = b - q * dmaj;
+      const int line = LINE_FAST ? rem : q;
+      const int j = LINE_FAST ? q : rem;
+      const int jq = small_div(j, Ns, ins);
+      const int jm = j - jq * Ns;
+      src[s] = line * ls + j * es;
+      dst[s] = line * ls + (jq * Ns * R + jm) * es;
+      stp[s] = jm * (nb / Ns);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[s][r] = src[(j + r * nb) * es];
+      for (int r = 0; r < R; ++r) v[s][r] = buf[src[s] + r * nb * es];
     }
   }
   __syncthreads();
-  const int span = n / R;
 #pragma unroll
   for (int s = 0; s < MAXB; ++s) {
     const int b = tid + s * NT;
     if (b < total) {
-      const int line = LINE_FAST ? b % nlines : b / nb;
-      const int j = LINE_FAST ? b / nlines : b % nb;
-      const int jm = j % Ns;
-      const int step = jm * (span / Ns);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[s][r] = cmul<T>(v[s][r], tw[step * r]);
+      for (int r = 1; r < R; ++r) v[s][r] = cmul<T>(v[s][r], tw[stp[s] * r]);
       dft_small<T, R>(v[s]);
-      const int idxD = (j / Ns) * Ns * R + jm;
-      cplx<T>* dst = buf + line * ls;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[(idxD + r * Ns) * es] = v[s][r];
+      for (int r = 0; r < R; ++r) buf[dst[s] + r * Ns * es] = v[s][r];
     }
   }
   __syncthreads();
