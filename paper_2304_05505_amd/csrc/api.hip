@@ -221,7 +221,8 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
                                         psi, g.ng, (long)g.no * g.ng, grid, g.ng,
                                         (long)g.ni * g.ng, st, h->tile_gamma);
     else
-      e = launch_gamma<TF>(g, occ, psi, grid, st);
+      e = cgemm_nn_grid32(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi, g.ng,
+                          (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
   // a2: Z^m in place

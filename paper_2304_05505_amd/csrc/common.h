@@ -196,6 +196,11 @@ hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                          hipStream_t st, int tile);
 
+// C[b] = A[b] * op(B[b]) on the FP32 matrix cores: A c128 (rounded to FP32), B and C c64
+hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                          hipStream_t st);
+
 // C[b] = C[b] + sign * A[b] * B[b] (sign = +1 or -1), same operands as zgemm_nn_grid
 // (tile 22, no conjugation); used by the iterative refinement of the fit
 template <typename TB, typename TC>

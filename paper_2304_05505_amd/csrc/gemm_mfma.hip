@@ -178,6 +178,101 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
   }
 }
 
+// FP32 matrix-core form for FP32 storage: C = A op(B) with A (c128) rounded to
+// FP32 at load, v_mfma_f32_16x16x4_f32, FP32 accumulation (the products of
+// the FP32 build path; K is short there). Same tiling, pipeline and workgroup
+// order as zgemm_nn_mfma. D layout: register v of a lane holds row
+// 4*(lane/16) + v, column lane%16 of the 16x16 block.
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int WM, int WN, int CONJB>
+__global__ __launch_bounds__(256) void cgemm_nn_mfma32(int M, int N, int K, int nrt, long ntiles,
+                                                       long ntiles_pad,
+                                                       const double2* __restrict__ A, long lda,
+                                                       long sA, const float2* __restrict__ B,
+                                                       long ldb, long sB, float2* __restrict__ C,
+                                                       long ldc, long sC) {
+  const long t = xcd_remap(blockIdx.x, ntiles_pad);
+  if (t >= ntiles) return;
+  const int rt = (int)(t % nrt);
+  const long ct = t / nrt;
+  const long b = blockIdx.y;
+  A += b * sA;
+  B += b * sB;
+  C += b * sC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = rt * (2 * WM * 16) + (wave & 1) * (WM * 16);
+  const long col0 = ct * (2 * WN * 16) + (wave >> 1) * (WN * 16);
+  f4 are[WM][WN], aim[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      are[i][j] = f4{0, 0, 0, 0};
+      aim[i][j] = f4{0, 0, 0, 0};
+    }
+  constexpr int NPF = 3;
+  double2 fa[NPF][WM];
+  float2 fb[NPF][WN];
+  auto load = [&](int k0, double2* xa, float2* xb) {
+    const int k = k0 + lk;
+    const long kc = k < K ? k : K - 1;
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const int r = row0 + i * 16 + li;
+      xa[i] = A[(long)(r < M ? r : M - 1) * lda + kc];
+    }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const long c = col0 + j * 16 + li;
+      xb[j] = B[kc * ldb + (c < N ? c : N - 1)];
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
+  const int niter = (K + 4 * NPF - 1) / (4 * NPF);
+  for (int it = 0; it < niter; ++it) {
+#pragma unroll
+    for (int s = 0; s < NPF; ++s) {
+      const bool kin = 4 * (it * NPF + s) + lk < K;
+      float br[WN], bi[WN];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        br[j] = fb[s][j].x;
+        bi[j] = CONJB ? -fb[s][j].y : fb[s][j].y;
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const float ar = kin ? (float)fa[s][i].x : 0.f, ai = kin ? (float)fa[s][i].y : 0.f;
+        const float nai = -ai;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          are[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[j], are[i][j], 0, 0, 0);
+          are[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bi[j], are[i][j], 0, 0, 0);
+          aim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi[j], aim[i][j], 0, 0, 0);
+          aim[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br[j], aim[i][j], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      load(4 * ((it + 1) * NPF + s), fa[s], fb[s]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + i * 16 + 4 * lk + v;
+      if (r >= M) continue;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const long c = col0 + j * 16 + li;
+        if (c < N) C[(long)r * ldc + c] = make_float2(are[i][j][v], aim[i][j][v]);
+      }
+    }
+}
+
 template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC = 0>
 hipError_t run_nn(int M, int N, int K, int batch, const void* A, long lda, long sA, const void* B,
                   long ldb, long sB, void* C, long ldc, long sC, hipStream_t st) {
@@ -218,6 +313,27 @@ hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
   if (conjB)
     return run_nn_tile<TB, TC, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
   return run_nn_tile<TB, TC, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+}
+
+hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                          hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (K <= 0) return hipErrorInvalidValue;
+  constexpr int WM = 2, WN = 2;
+  const int nrt = (M + 2 * WM * 16 - 1) / (2 * WM * 16);
+  const long nct = ((long)N + 2 * WN * 16 - 1) / (2 * WN * 16);
+  const long ntiles = nrt * nct;
+  const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
+  if (conjB)
+    hipLaunchKernelGGL((cgemm_nn_mfma32<WM, WN, 1>), dim3((unsigned)pad, batch), dim3(256), 0, st, M,
+                       N, K, nrt, ntiles, pad, (const double2*)A, lda, sA, (const float2*)B, ldb,
+                       sB, (float2*)C, ldc, sC);
+  else
+    hipLaunchKernelGGL((cgemm_nn_mfma32<WM, WN, 0>), dim3((unsigned)pad, batch), dim3(256), 0, st, M,
+                       N, K, nrt, ntiles, pad, (const double2*)A, lda, sA, (const float2*)B, ldb,
+                       sB, (float2*)C, ldc, sC);
+  return hipGetLastError();
 }
 
 template <typename TB, typename TC>
