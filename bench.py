@@ -62,28 +62,28 @@ def algorithmic_work(cell, n_isdf, prec):
 
 # HBM traffic of the dominant kernel of each phase at this workload, from two
 # rocprofv3 counter runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; KiB
-# per dispatch). A plain 1 GiB device copy reads 524 313 KiB of FETCH_SIZE and
+# per dispatch). A plain 1 GiB device copy reads 524 315 KiB of FETCH_SIZE and
 # 1 048 576 KiB of WRITE_SIZE on MI355X, so fetch counts are scaled by 2.0 and write
 # counts by 1.0. Each entry names the source file of its kernels and that file's
 # SHA-256 prefix when the counters were taken; a changed file reports null.
-FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524312.8125, 1.0
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524315.4375, 1.0
 TRAFFIC = {
     # (phase, path): (source, sha256[:16], FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("solve", "f64"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 16499298.2, 12757500.0),
-    ("solve", "mixed"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 16195238.8, 6420254.4),
-    ("solve", "f32"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 10106401.2, 6425021.1),
-    ("gamma", "f64"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 1311050.3, 12757500.0),
-    ("gamma", "mixed"): ("gemm_mfma.hip", "a8c1eadde3f05d96", 1311050.3, 12757500.0),
-    ("gamma", "f32"): ("gemm.hip", "04e1ff7ac33225d7", 5041303.9, 6378750.1),
-    ("coulomb", "f64"): ("coulomb.hip", "0ea60aa7eec985c6", 10739856.6, 243689.7),
-    ("coulomb", "mixed"): ("coulomb.hip", "0ea60aa7eec985c6", 4874858.5, 242664.6),
-    ("coulomb", "f32"): ("coulomb.hip", "0ea60aa7eec985c6", 10707815.6, 244540.2),
-    ("fft", "f64"): ("fft.hip", "e70bd9dd61c12049", 6390621.2 + 7579020.8, 12757536.3 + 12757500.0),
-    ("fft", "mixed"): ("fft.hip", "e70bd9dd61c12049", 3200645.2 + 4589710.8, 6381900.0 + 6778800.0),
-    ("fft", "f32"): ("fft.hip", "e70bd9dd61c12049", 3200645.2 + 4589710.8, 6381900.0 + 6778800.0),
-    ("kcorr", "f64"): ("fit.hip", "01c53048f397523a", 6379021.4, 12757500.0),
-    ("kcorr", "mixed"): ("fit.hip", "01c53048f397523a", 6379004.9, 12757500.0),
-    ("kcorr", "f32"): ("fit.hip", "01c53048f397523a", 3189587.6, 6378750.0),
+    ("solve", "f64"): ("gemm_mfma.hip", "56e32a30c5a5588c", 16446904.8, 12757500.0),
+    ("solve", "mixed"): ("gemm_mfma.hip", "56e32a30c5a5588c", 16197055.4, 6420846.6),
+    ("solve", "f32"): ("gemm_mfma.hip", "56e32a30c5a5588c", 10148010.9, 6425589.2),
+    ("gamma", "f64"): ("gemm_mfma.hip", "56e32a30c5a5588c", 1311069.3, 12757500.0),
+    ("gamma", "mixed"): ("gemm_mfma.hip", "56e32a30c5a5588c", 1311069.3, 12757500.0),
+    ("gamma", "f32"): ("gemm_mfma.hip", "56e32a30c5a5588c", 816074.0, 6425531.5),
+    ("kcorr", "f64"): ("fit.hip", "01c53048f397523a", 6378994.6, 12757500.0),
+    ("kcorr", "mixed"): ("fit.hip", "01c53048f397523a", 6378994.6, 12757500.0),
+    ("kcorr", "f32"): ("fit.hip", "01c53048f397523a", 3189577.6, 6378750.0),
+    ("fft", "f64"): ("fft.hip", "f37851e0012f7e0c", 13970475.8, 25515043.8),
+    ("fft", "mixed"): ("fft.hip", "f37851e0012f7e0c", 7790404.2, 13160700.0),
+    ("fft", "f32"): ("fft.hip", "f37851e0012f7e0c", 7790404.2, 13160700.0),
+    ("coulomb", "f64"): ("coulomb.hip", "0be09b85ad4262f0", 25114777.7, 243822.2),
+    ("coulomb", "mixed"): ("coulomb.hip", "0be09b85ad4262f0", 5651119.9, 242763.8),
+    ("coulomb", "f32"): ("coulomb.hip", "0be09b85ad4262f0", 11378013.4, 244838.6),
 }
 
 
