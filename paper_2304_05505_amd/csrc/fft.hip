@@ -24,23 +24,69 @@ struct Plan1 {
   int r[10];
 };
 
-Plan1 plan_for(int n) {
+// Radices of a line of length n (a 2*3*5-smooth n), largest first from the
+// list below so that a line takes as few LDS stages as possible; composite
+// radices run their own small Cooley-Tukey in registers. maxr caps the radix:
+// 16 for FP32, 5 for FP64 (register use).
+Plan1 plan_for(int n, int maxr = 16) {
   Plan1 p{};
   p.n = n;
   int m = n;
-  while (m % 4 == 0 && m != 8 && m / 4 != 2) {
-    p.r[p.ns++] = 4;
-    m /= 4;
+  const int pr[13] = {16, 25, 12, 15, 20, 9, 10, 8, 6, 5, 4, 3, 2};
+  while (m > 1 && p.ns < 10) {
+    int k = 0;
+    while (k < 13 && (pr[k] > maxr || m % pr[k] != 0)) ++k;
+    if (k == 13) break;
+    p.r[p.ns++] = pr[k];
+    m /= pr[k];
   }
-  const int pr[4] = {4, 2, 3, 5};
-  for (int k = 0; k < 4; ++k)
-    while (m % pr[k] == 0) {
-      p.r[p.ns++] = pr[k];
-      m /= pr[k];
-    }
   if (m != 1) p.ns = -1;
   return p;
 }
+
+// cos and sin of 2 pi m / R, evaluated by the compiler: octant reduction and
+// Taylor series on [0, pi/4]
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr void taylor_cs(double x, double& c, double& s) {
+  double t = 1.0, cs = 1.0;
+  double u = x, ss = x;
+  for (int k = 1; k < 14; ++k) {
+    t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    cs += t;
+    u *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    ss += u;
+  }
+  c = cs;
+  s = ss;
+}
+
+constexpr void cs_2pi_frac(int m, int R, double& c, double& s) {
+  const int q = (4 * m) / R, r4 = 4 * m - q * R;  // 2 pi m/R = q pi/2 + (pi/2) r4/R
+  double cc = 0.0, sc = 0.0;
+  if (2 * r4 <= R) {
+    taylor_cs(0.5 * kPi * r4 / R, cc, sc);
+  } else {
+    double c2 = 0.0, s2 = 0.0;
+    taylor_cs(0.5 * kPi * (R - r4) / R, c2, s2);
+    cc = s2;
+    sc = c2;
+  }
+  switch (q & 3) {
+    case 0: c = cc; s = sc; break;
+    case 1: c = -sc; s = cc; break;
+    case 2: c = -cc; s = -sc; break;
+    default: c = sc; s = -cc; break;
+  }
+}
+
+template <int R>
+struct RootsR {
+  double c[R], s[R];
+  constexpr RootsR() : c(), s() {
+    for (int m = 0; m < R; ++m) cs_2pi_frac(m, R, c[m], s[m]);
+  }
+};
 
 template <typename T, int R>
 __device__ __forceinline__ void dft_small(cplx<T>* v) {
@@ -86,6 +132,51 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
     v[2] = mk<T>(m2.x + e2.y, m2.y - e2.x);
     v[3] = mk<T>(m2.x - e2.y, m2.y + e2.x);
   }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_any(cplx<T>* v);
+
+// DFT of length R = R1 R2 in registers (forward, natural order in and out):
+// X[k1 + R1 k2] = sum_j2 W_R2^{j2 k2} W_R^{j2 k1} sum_j1 W_R1^{j1 k1} x[R2 j1 + j2]
+template <typename T, int R1, int R2>
+__device__ __forceinline__ void dft_comp(cplx<T>* v) {
+  constexpr int R = R1 * R2;
+  constexpr RootsR<R> w{};
+  cplx<T> y[R];
+#pragma unroll
+  for (int j2 = 0; j2 < R2; ++j2) {
+    cplx<T> t[R1];
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) t[j1] = v[R2 * j1 + j2];
+    dft_any<T, R1>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      const int m = (j2 * k1) % R;
+      y[j2 * R1 + k1] = m == 0 ? t[k1] : cmul<T>(t[k1], mk<T>((T)w.c[m], (T)-w.s[m]));
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cplx<T> u[R2];
+#pragma unroll
+    for (int j2 = 0; j2 < R2; ++j2) u[j2] = y[j2 * R1 + k1];
+    dft_any<T, R2>(u);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = u[k2];
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_any(cplx<T>* v) {
+  if constexpr (R == 2 || R == 3 || R == 4 || R == 5) dft_small<T, R>(v);
+  else if constexpr (R == 6) dft_comp<T, 2, 3>(v);
+  else if constexpr (R == 8) dft_comp<T, 2, 4>(v);
+  else if constexpr (R == 9) dft_comp<T, 3, 3>(v);
+  else if constexpr (R == 10) dft_comp<T, 2, 5>(v);
+  else if constexpr (R == 12) dft_comp<T, 3, 4>(v);
+  else if constexpr (R == 15) dft_comp<T, 3, 5>(v);
+  else if constexpr (R == 16) dft_comp<T, 4, 4>(v);
 }
 
 // x / d for 0 <= x < 2^22 and d >= 1 from a float reciprocal: the float
@@ -136,7 +227,7 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, i
     if (b < total) {
 #pragma unroll
       for (int r = 1; r < R; ++r) v[s][r] = cmul<T>(v[s][r], tw[stp[s] * r]);
-      dft_small<T, R>(v[s]);
+      dft_any<T, R>(v[s]);
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[dst[s] + r * Ns * es] = v[s][r];
     }
@@ -150,14 +241,24 @@ __device__ void fft_lines(cplx<T>* buf, const Plan1& p, int nlines, int es, int 
   int Ns = 1;
   for (int s = 0; s < p.ns; ++s) {
     const int R = p.r[s];
-    if (R == 4)
-      stage<T, 4, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
-    else if (R == 2)
-      stage<T, 2, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
-    else if (R == 3)
-      stage<T, 3, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
-    else
-      stage<T, 5, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
+#define EXX_STAGE(RR) \
+  if (R == RR) stage<T, RR, NT, MAXPTS, LINE_FAST>(buf, p.n, Ns, nlines, es, ls, tw);
+    EXX_STAGE(2)
+    EXX_STAGE(3)
+    EXX_STAGE(4)
+    EXX_STAGE(5)
+    // composite radices only in the FP32 kernels: in FP64 their registers would
+    // cost the plane kernels occupancy
+    if constexpr (sizeof(T) == 4) {
+      EXX_STAGE(6)
+      EXX_STAGE(8)
+      EXX_STAGE(9)
+      EXX_STAGE(10)
+      EXX_STAGE(12)
+      EXX_STAGE(15)
+      EXX_STAGE(16)
+    }
+#undef EXX_STAGE
     Ns *= R;
   }
 }
@@ -369,7 +470,8 @@ hipError_t fft_prepare(int* ncu) {
 template <typename T>
 hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
                         int ncu, hipStream_t st) {
-  Plan1 px = plan_for(g.n[0]), py = plan_for(g.n[1]), pz = plan_for(g.n[2]);
+  const int maxr = sizeof(T) == 8 ? 5 : 16;
+  Plan1 px = plan_for(g.n[0], maxr), py = plan_for(g.n[1], maxr), pz = plan_for(g.n[2], maxr);
   const int np = g.n[1] * g.n[2];
   size_t lds1 = (size_t)(np + g.n[1] + g.n[2]) * sizeof(cplx<T>);
   size_t lds2 = (size_t)(g.n[0] * FFT_CB + g.n[0]) * sizeof(cplx<T>);
