@@ -71,19 +71,27 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
   constexpr int NPF = 3;
   double2 fa[NPF][WM];
   cplx<TB> fb[NPF][WN];
+  // 32-bit element offsets from the uniform operand bases (the launcher checks
+  // that they fit), so the loads use a scalar base plus a vector offset
+  unsigned aoff[WM], boff[WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    const int r = row0 + i * 16 + li;
+    aoff[i] = (unsigned)((r < M ? r : M - 1) * lda);
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long c = col0 + j * 16 + li;
+    boff[j] = (unsigned)(c < N ? c : N - 1);
+  }
+  const unsigned ldb32 = (unsigned)ldb;
   auto load = [&](int k0, double2* xa, cplx<TB>* xb) {
     const int k = k0 + lk;
-    const long kc = k < K ? k : K - 1;
+    const unsigned kc = (unsigned)(k < K ? k : K - 1);
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-      const int r = row0 + i * 16 + li;
-      xa[i] = A[(long)(r < M ? r : M - 1) * lda + kc];
-    }
+    for (int i = 0; i < WM; ++i) xa[i] = A[aoff[i] + kc];
 #pragma unroll
-    for (int j = 0; j < WN; ++j) {
-      const long c = col0 + j * 16 + li;
-      xb[j] = B[kc * ldb + (c < N ? c : N - 1)];
-    }
+    for (int j = 0; j < WN; ++j) xb[j] = B[kc * ldb32 + boff[j]];
   };
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
@@ -215,19 +223,27 @@ __global__ __launch_bounds__(256) void cgemm_nn_mfma32(int M, int N, int K, int 
   constexpr int NPF = 3;
   double2 fa[NPF][WM];
   float2 fb[NPF][WN];
+  // 32-bit element offsets from the uniform operand bases (the launcher checks
+  // that they fit), so the loads use a scalar base plus a vector offset
+  unsigned aoff[WM], boff[WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    const int r = row0 + i * 16 + li;
+    aoff[i] = (unsigned)((r < M ? r : M - 1) * lda);
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long c = col0 + j * 16 + li;
+    boff[j] = (unsigned)(c < N ? c : N - 1);
+  }
+  const unsigned ldb32 = (unsigned)ldb;
   auto load = [&](int k0, double2* xa, float2* xb) {
     const int k = k0 + lk;
-    const long kc = k < K ? k : K - 1;
+    const unsigned kc = (unsigned)(k < K ? k : K - 1);
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-      const int r = row0 + i * 16 + li;
-      xa[i] = A[(long)(r < M ? r : M - 1) * lda + kc];
-    }
+    for (int i = 0; i < WM; ++i) xa[i] = A[aoff[i] + kc];
 #pragma unroll
-    for (int j = 0; j < WN; ++j) {
-      const long c = col0 + j * 16 + li;
-      xb[j] = B[kc * ldb + (c < N ? c : N - 1)];
-    }
+    for (int j = 0; j < WN; ++j) xb[j] = B[kc * ldb32 + boff[j]];
   };
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
@@ -302,6 +318,13 @@ hipError_t run_nn_tile(int tile, int M, int N, int K, int batch, const void* A, 
   }
 }
 
+// operand offsets of one batch item must fit the kernels' 32-bit arithmetic
+bool offsets_fit(int M, int N, int K, long lda, long ldb) {
+  if (K <= 0) return false;
+  const long lim = 0x7fffffffL;
+  return (long)M * lda < lim && (long)K * ldb < lim && (long)N <= ldb;
+}
+
 }  // namespace
 
 template <typename TB, typename TC>
@@ -309,7 +332,7 @@ hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                          hipStream_t st, int tile) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  if (K <= 0) return hipErrorInvalidValue;
+  if (!offsets_fit(M, N, K, lda, ldb)) return hipErrorInvalidValue;
   if (conjB)
     return run_nn_tile<TB, TC, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
   return run_nn_tile<TB, TC, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
@@ -319,7 +342,7 @@ hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long l
                           bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                           hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  if (K <= 0) return hipErrorInvalidValue;
+  if (!offsets_fit(M, N, K, lda, ldb)) return hipErrorInvalidValue;
   constexpr int WM = 2, WN = 2;
   const int nrt = (M + 2 * WM * 16 - 1) / (2 * WM * 16);
   const long nct = ((long)N + 2 * WN * 16 - 1) / (2 * WN * 16);
@@ -341,7 +364,7 @@ hipError_t zgemm_nn_grid_acc(int M, int N, int K, int batch, const void* A, long
                              const void* B, long ldb, long sB, void* C, long ldc, long sC,
                              int sign, hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  if (K <= 0) return hipErrorInvalidValue;
+  if (!offsets_fit(M, N, K, lda, ldb)) return hipErrorInvalidValue;
   if (sign > 0)
     return run_nn<TB, TC, 2, 2, 0, 1>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
   return run_nn<TB, TC, 2, 2, 0, -1>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
