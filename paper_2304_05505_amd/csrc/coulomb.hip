@@ -165,14 +165,14 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
   const long g1 = min((long)a.ng, g0 + a.chunk);
   const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
   const double* vm = vt + (long)m * a.ng;
-  // row bases (clamped rows only feed unstored outputs)
-  const cplx<T>* xrow[MW];
-  const cplx<T>* yrow[MW];
+  // 32-bit row offsets from the uniform base Fm (N_ISDF N_g < 2^31 is checked by
+  // the launcher); clamped rows only feed unstored outputs
+  unsigned xrow[MW], yrow[MW];
 #pragma unroll
   for (int i = 0; i < MW; ++i) {
     const int P = min(P0 + 16 * i + li, a.ni - 1), Q = min(Q0 + 16 * i + li, a.ni - 1);
-    xrow[i] = Fm + (long)P * a.ng;
-    yrow[i] = Fm + (long)Q * a.ng;
+    xrow[i] = (unsigned)P * (unsigned)a.ng;
+    yrow[i] = (unsigned)Q * (unsigned)a.ng;
   }
 
   CAcc<F64MMA> acc;
@@ -184,12 +184,12 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
     const long gb = k0 + TPL * gq;
 #pragma unroll
     for (int t = 0; t < TPL; ++t) {
-      const long g = min(gb + t, (long)a.ng - 1);
+      const unsigned g = (unsigned)min(gb + t, (long)a.ng - 1);
       vv[t] = vm[g];
 #pragma unroll
       for (int i = 0; i < MW; ++i) {
-        xx[i][t] = xrow[i][g];
-        yy[i][t] = yrow[i][g];
+        xx[i][t] = Fm[xrow[i] + g];
+        yy[i][t] = Fm[yrow[i] + g];
       }
     }
   };
@@ -325,6 +325,7 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.chunk = (int)((((long)g.ng + nsplit - 1) / nsplit + FLUSH - 1) / FLUSH * FLUSH);
   const int nt = (g.ni + MTILE - 1) / MTILE;
   a.ntile = nt * (nt + 1) / 2;
+  if ((long)g.ni * g.ng >= 0x7fffffffL) return hipErrorInvalidValue;
   const long nwork = (long)a.ntile * g.nk * nsplit;
   const long pad = (nwork + 7) / 8 * 8;
   double* vt = (double*)((char*)partial + partial_only(g, nsplit));
