@@ -46,16 +46,25 @@ def log(msg):
 
 
 def algorithmic_work(cell, n_isdf, prec):
-    """Per-launch algorithmic flops / bytes of each phase (one K-build)."""
+    """Per-launch algorithmic flops / bytes of each phase (one K-build).
+
+    Flops count the real multiply-adds of the product form each kernel uses:
+    the FP64-matrix-core products (fit solve, Gamma in FP64 and mixed, the
+    Coulomb contraction in FP64 and mixed) use Gauss's three-product form, 6
+    flops per complex multiply-add; the FP32-matrix-core products (Gamma and
+    Coulomb in FP32) and the small K GEMMs use four real products, 8 flops.
+    The Coulomb contraction forms the lower triangle only (N_ISDF^2/2 pairs).
+    """
     nk, ng, no, na = cell.N_k, cell.N_g, cell.n_occ, cell.n_ao
     ni = n_isdf
     cs = 16 if prec == "f64" else 8
+    cm = 8.0 if prec == "f32" else 6.0  # flops per complex multiply-add, Gamma and Coulomb
     return {
-        "gamma": ("flop", 8.0 * nk * ni * no * ng),
+        "gamma": ("flop", cm * nk * ni * no * ng),
         "kcorr": ("byte", 2.0 * nk * ni * ng * cs),
-        "solve": ("flop", 8.0 * nk * ni * ni * ng),
+        "solve": ("flop", 6.0 * nk * ni * ni * ng),
         "fft": ("byte", 2.0 * nk * ni * ng * cs),
-        "coulomb": ("flop", 4.0 * nk * ni * ni * ng),
+        "coulomb": ("flop", cm / 2 * nk * ni * ni * ng),
         "K": ("flop", 8.0 * nk * (na * ni * ni + na * na * ni)),
     }
 

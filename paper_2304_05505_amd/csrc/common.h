@@ -190,7 +190,8 @@ hipError_t gemm(int M, int N, int K, int batch, OpA oa, const void* A, long lda,
 
 // C[b] = A[b] * op(B[b]) on the matrix cores in FP64: A (M x K) c128, B (K x N) and
 // C (M x N) row-major with storage types TB, TC; op = conj if conjB. `tile` picks the
-// wave tile in 16x16 blocks (22, 24, 42, 44; workgroup = 2 x 2 waves).
+// wave tile in 16x16 blocks (22, 24 or 42; any other value means 24; workgroup =
+// 2 x 2 waves).
 template <typename TB, typename TC>
 hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,

@@ -25,9 +25,13 @@ struct CoulArgs {
 // group gq = lane / 16) loads TPL consecutive grid values of its row, so the k
 // index of MFMA step t is g0 + TPL gq + t for both operands (the k order of a
 // sum is free). X = v(g) F_P (rows P), Y = conj F_Q (rows Q):
-//   Re += Re X Re F_Q + Im X Im F_Q,  Im += Im X Re F_Q - Re X Im F_Q.
-// FP64 storage: v_mfma_f64_16x16x4_f64. FP32 storage: v_mfma_f32_16x16x4_f32
-// whose FP32 accumulators are flushed into FP64 every FLUSH grid points.
+//   Re = sum Re X Re F_Q + Im X Im F_Q,  Im = sum Im X Re F_Q - Re X Im F_Q.
+// FP64 matrix cores (v_mfma_f64_16x16x4_f64) use Gauss's three-product form:
+// T1 = sum Re X Re F_Q, T2 = sum Im X Im F_Q, T3 = sum (Re X + Im X)(Re F_Q -
+// Im F_Q), then Re = T1 + T2 and Im = T3 - T1 + T2 (three MFMAs per complex
+// step). FP32 matrix cores (v_mfma_f32_16x16x4_f32) keep the four-product form
+// (its rounding is the smaller one) and flush their FP32 accumulators into FP64
+// every FLUSH grid points.
 // ---------------------------------------------------------------------------
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -41,24 +45,22 @@ template <bool F64MMA>
 struct CAcc;
 
 template <>
-struct CAcc<true> {  // FP64 matrix cores, FP64 accumulation
-  d4v r[MW][MW], i[MW][MW];
+struct CAcc<true> {  // FP64 matrix cores, FP64 accumulation, three-product form
+  d4v t1[MW][MW], t2[MW][MW], t3[MW][MW];
   __device__ void init() {
 #pragma unroll
     for (int a = 0; a < MW; ++a)
 #pragma unroll
-      for (int b = 0; b < MW; ++b) r[a][b] = i[a][b] = d4v{0, 0, 0, 0};
+      for (int b = 0; b < MW; ++b) t1[a][b] = t2[a][b] = t3[a][b] = d4v{0, 0, 0, 0};
   }
-  // (xr + i xi) * conj(yr + i yi) for block (a, b)
-  __device__ void mac(int a, int b, double xr, double xi, double yr, double yi) {
-    r[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr, r[a][b], 0, 0, 0);
-    r[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi, r[a][b], 0, 0, 0);
-    i[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yr, i[a][b], 0, 0, 0);
-    i[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xr, yi, i[a][b], 0, 0, 0);
+  // (xr + i xi) * conj(yr + i yi) for block (a, b); xs = xr + xi, ys = yr - yi
+  __device__ void mac(int a, int b, double xr, double xi, double xs, double yr, double yi,
+                      double ys) {
+    t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr, t1[a][b], 0, 0, 0);
+    t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi, t2[a][b], 0, 0, 0);
+    t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, ys, t3[a][b], 0, 0, 0);
   }
   __device__ void chunk_done(int) {}
-  __device__ double re(int a, int b, int v) const { return r[a][b][v]; }
-  __device__ double im(int a, int b, int v) const { return i[a][b][v]; }
   // register v of a lane holds row 4 v + lane/16 of the block
   static __device__ int row(int gq, int v) { return 4 * v + gq; }
 };
@@ -79,7 +81,7 @@ struct CAcc<false> {  // FP32 matrix cores, FP32 accumulation flushed into FP64
         for (int v = 0; v < 4; ++v) sr[a][b][v] = si[a][b][v] = 0.0;
       }
   }
-  __device__ void mac(int a, int b, float xr, float xi, float yr, float yi) {
+  __device__ void mac(int a, int b, float xr, float xi, float, float yr, float yi, float) {
     r[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, yr, r[a][b], 0, 0, 0);
     r[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yi, r[a][b], 0, 0, 0);
     i[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yr, i[a][b], 0, 0, 0);
@@ -204,12 +206,19 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
 #pragma unroll
       for (int t = 0; t < TPL; ++t) {
         const TO vv = (gb + t < g1) ? (TO)fv[sl][t] : (TO)0;
+        TO yr[MW], yi[MW], ys[MW];
+#pragma unroll
+        for (int j = 0; j < MW; ++j) {
+          yr[j] = (TO)fy[sl][j][t].x;
+          yi[j] = (TO)fy[sl][j][t].y;
+          ys[j] = yr[j] - yi[j];
+        }
 #pragma unroll
         for (int i = 0; i < MW; ++i) {
           const TO xr = (TO)fx[sl][i][t].x * vv, xi = (TO)fx[sl][i][t].y * vv;
+          const TO xs = xr + xi;
 #pragma unroll
-          for (int j = 0; j < MW; ++j)
-            acc.mac(i, j, xr, xi, (TO)fy[sl][j][t].x, (TO)fy[sl][j][t].y);
+          for (int j = 0; j < MW; ++j) acc.mac(i, j, xr, xi, xs, yr[j], yi[j], ys[j]);
         }
       }
       acc.chunk_done(CK);
@@ -220,18 +229,48 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
     }
   }
   double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
+  if constexpr (F64MMA) {
+    // Combining T1..T3 needs the accumulators in VALU registers: each lane
+    // round-trips its own values through this wave's LDS slice (LDS accesses of
+    // one wave complete in order), which keeps the accumulators in the matrix
+    // registers during the loop.
+    __shared__ double stage[4][3][64 * 4];
+    typedef __attribute__((address_space(3))) volatile double lds_f64;
+    lds_f64* s1 = (lds_f64*)stage[wave][0];
+    lds_f64* s2 = (lds_f64*)stage[wave][1];
+    lds_f64* s3 = (lds_f64*)stage[wave][2];
 #pragma unroll
-  for (int i = 0; i < MW; ++i)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int P = P0 + 16 * i + CAcc<F64MMA>::row(gq, v);
-      if (P >= a.ni) continue;
+    for (int i = 0; i < MW; ++i)
 #pragma unroll
       for (int j = 0; j < MW; ++j) {
-        const int Q = Q0 + 16 * j + li;
-        if (Q < a.ni) out[(long)P * a.ni + Q] = make_double2(acc.re(i, j, v), acc.im(i, j, v));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          s1[v * 64 + lane] = acc.t1[i][j][v];
+          s2[v * 64 + lane] = acc.t2[i][j][v];
+          s3[v * 64 + lane] = acc.t3[i][j][v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double x1 = s1[v * 64 + lane], x2 = s2[v * 64 + lane], x3 = s3[v * 64 + lane];
+          const int P = P0 + 16 * i + CAcc<true>::row(gq, v);
+          const int Q = Q0 + 16 * j + li;
+          if (P < a.ni && Q < a.ni) out[(long)P * a.ni + Q] = make_double2(x1 + x2, x3 - x1 + x2);
+        }
       }
-    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < MW; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int P = P0 + 16 * i + CAcc<false>::row(gq, v);
+        if (P >= a.ni) continue;
+#pragma unroll
+        for (int j = 0; j < MW; ++j) {
+          const int Q = Q0 + 16 * j + li;
+          if (Q < a.ni) out[(long)P * a.ni + Q] = make_double2(acc.re(i, j, v), acc.im(i, j, v));
+        }
+      }
+  }
 }
 
 struct ReduceArgs {

@@ -198,7 +198,11 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, i
   constexpr int MAXB = (MAXPTS / R + NT - 1) / NT;
   const int nb = n / R;
   const int total = nlines * nb;
-  const int tid = threadIdx.x;
+  // an opaque copy of the thread index per stage: without it the compiler
+  // hoists the index arithmetic of every radix out of the stage loop and keeps
+  // it live across all stages (twice the registers, half the occupancy)
+  int tid = threadIdx.x;
+  __asm__ volatile("" : "+v"(tid));
   const int dmaj = LINE_FAST ? nlines : nb;  // divisor splitting b into (line, j)
   const float imaj = 1.0f / (float)dmaj, ins = 1.0f / (float)Ns;
   cplx<T> v[MAXB][R];
@@ -479,7 +483,8 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
   const int nblk = (np + FFT_CB - 1) / FFT_CB;
   hipError_t e;
   if (sizeof(T) == 8) {
-    // FP64 planes fill the register file; they run one plane per workgroup
+    // FP64 planes: a register copy of the next plane would spill, so one plane
+    // per workgroup (two workgroups per CU by LDS)
     hipLaunchKernelGGL(fft_yz1_kernel<T>, dim3((unsigned)nplanes), dim3(NT1), lds1, st,
                        (const cplx<T>*)in, (cplx<T>*)out, py, pz, twp<T>(tb, 1), twp<T>(tb, 2));
     e = hipGetLastError();

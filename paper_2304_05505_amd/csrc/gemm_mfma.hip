@@ -1,5 +1,5 @@
 // Grid-sized complex FP64 GEMMs on the matrix cores (v_mfma_f64_16x16x4_f64),
-// complex products by four real MFMAs (4M).
+// complex products by three real MFMAs (Gauss's 3M form).
 //
 //  * zgemm_nn: C[b] = A[b] * op(B[b]) with A (M x K, c128, small, L2-resident)
 //    and B (K x N) / C (M x N) long row-major panels over the grid (N = N_g).
@@ -53,13 +53,17 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
   const int row0 = rt * (2 * WM * 16) + (wave & 1) * (WM * 16);
   const long col0 = ct * (2 * WN * 16) + (wave >> 1) * (WN * 16);
 
-  d4 are[WM][WN], aim[WM][WN];
+  // Gauss's three-product form of the complex product: T1 = Re A Re B,
+  // T2 = Im A Im B, T3 = (Re A + Im A)(Re B + Im B); then Re C = T1 - T2 and
+  // Im C = T3 - T1 - T2. Three real MFMAs per complex k-step instead of four.
+  d4 t1[WM][WN], t2[WM][WN], t3[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
-      are[i][j] = d4{0, 0, 0, 0};
-      aim[i][j] = d4{0, 0, 0, 0};
+      t1[i][j] = d4{0, 0, 0, 0};
+      t2[i][j] = d4{0, 0, 0, 0};
+      t3[i][j] = d4{0, 0, 0, 0};
     }
 
   // NPF-deep register pipeline: slot s holds the fragments of k-step s (mod NPF).
@@ -100,22 +104,22 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
 #pragma unroll
     for (int s = 0; s < NPF; ++s) {
       const bool kin = 4 * (it * NPF + s) + lk < K;
-      double br[WN], bi[WN];
+      double br[WN], bi[WN], bs[WN];
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         br[j] = (double)fb[s][j].x;
         bi[j] = CONJB ? -(double)fb[s][j].y : (double)fb[s][j].y;
+        bs[j] = br[j] + bi[j];
       }
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
         const double ar = kin ? fa[s][i].x : 0.0, ai = kin ? fa[s][i].y : 0.0;
-        const double nai = -ai;
+        const double as = ar + ai;
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
-          are[i][j] = mfma64(ar, br[j], are[i][j]);
-          are[i][j] = mfma64(nai, bi[j], are[i][j]);
-          aim[i][j] = mfma64(ar, bi[j], aim[i][j]);
-          aim[i][j] = mfma64(ai, br[j], aim[i][j]);
+          t1[i][j] = mfma64(ar, br[j], t1[i][j]);
+          t2[i][j] = mfma64(ai, bi[j], t2[i][j]);
+          t3[i][j] = mfma64(as, bs[j], t3[i][j]);
         }
       }
       // refill the slot with k-step (it + 1) * NPF + s (masked at use past K). The
@@ -127,63 +131,44 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
     }
   }
   // D layout of v_mfma_f64_16x16x4_f64: register v of a lane holds row
-  // 4*v + lane/16, column lane%16 of the 16x16 block
-  if constexpr (sizeof(TC) == sizeof(double)) {
+  // 4*v + lane/16, column lane%16 of the 16x16 block.
+  // Combining T1..T3 needs the accumulators in VALU registers. Each lane
+  // round-trips its own values through this wave's LDS slice (the LDS write
+  // takes matrix registers directly, and LDS accesses of one wave complete in
+  // order); arithmetic on the accumulators themselves makes the compiler carry
+  // them in VALU registers and copy them in and out of the matrix registers on
+  // every iteration.
+  __shared__ double stage[4][3][64 * 4];
+  typedef __attribute__((address_space(3))) volatile double lds_f64;
+  lds_f64* s1 = (lds_f64*)stage[wave][0];
+  lds_f64* s2 = (lds_f64*)stage[wave][1];
+  lds_f64* s3 = (lds_f64*)stage[wave][2];
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        s1[v * 64 + lane] = t1[i][j][v];
+        s2[v * 64 + lane] = t2[i][j][v];
+        s3[v * 64 + lane] = t3[i][j][v];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double x1 = s1[v * 64 + lane], x2 = s2[v * 64 + lane], x3 = s3[v * 64 + lane];
+        double xr = x1 - x2, xi = x3 - x1 - x2;
         const int r = row0 + i * 16 + 4 * v + lk;
-        if (r >= M) continue;
-#pragma unroll
-        for (int j = 0; j < WN; ++j) {
-          const long c = col0 + j * 16 + li;
-          if (c >= N) continue;
-          if constexpr (ACC == 0) {
-            C[(long)r * ldc + c] = mk<TC>(are[i][j][v], aim[i][j][v]);
-          } else {
+        const long c = col0 + j * 16 + li;
+        if (r < M && c < N) {
+          if constexpr (ACC != 0) {
             const cplx<TC> o = C[(long)r * ldc + c];
-            C[(long)r * ldc + c] = mk<TC>((double)o.x + ACC * are[i][j][v],
-                                          (double)o.y + ACC * aim[i][j][v]);
+            xr = (double)o.x + ACC * xr;
+            xi = (double)o.y + ACC * xi;
           }
+          C[(long)r * ldc + c] = mk<TC>((TC)xr, (TC)xi);
         }
       }
-  } else {
-    // Narrowing needs the accumulators in VALU registers. Each lane round-trips
-    // its own values through this wave's LDS slice (the LDS write takes matrix
-    // registers directly, and LDS accesses of one wave complete in order); a
-    // direct conversion makes the compiler carry the accumulators in VALU
-    // registers and copy them in and out of the matrix registers on every
-    // iteration.
-    __shared__ double stage[4][2][64 * 4];
-    typedef __attribute__((address_space(3))) volatile double lds_f64;
-    lds_f64* sre = (lds_f64*)stage[wave][0];
-    lds_f64* sim = (lds_f64*)stage[wave][1];
-#pragma unroll
-    for (int i = 0; i < WM; ++i)
-#pragma unroll
-      for (int j = 0; j < WN; ++j) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          sre[v * 64 + lane] = are[i][j][v];
-          sim[v * 64 + lane] = aim[i][j][v];
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          double xr = sre[v * 64 + lane], xi = sim[v * 64 + lane];
-          const int r = row0 + i * 16 + 4 * v + lk;
-          const long c = col0 + j * 16 + li;
-          if (r < M && c < N) {
-            if constexpr (ACC != 0) {
-              const cplx<TC> o = C[(long)r * ldc + c];
-              xr = (double)o.x + ACC * xr;
-              xi = (double)o.y + ACC * xi;
-            }
-            C[(long)r * ldc + c] = mk<TC>((TC)xr, (TC)xi);
-          }
-        }
-      }
-  }
+    }
 }
 
 // FP32 matrix-core form for FP32 storage: C = A op(B) with A (c128) rounded to
@@ -309,8 +294,6 @@ hipError_t run_nn_tile(int tile, int M, int N, int K, int batch, const void* A, 
   switch (tile) {
     case 22:
       return run_nn<TB, TC, 2, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
-    case 44:
-      return run_nn<TB, TC, 4, 4, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
     case 42:
       return run_nn<TB, TC, 4, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
     default:

@@ -1,0 +1,94 @@
+"""Full-size parity on the 3x3x3 form of the benchmark cell (48-atom four-ring
+cell, N = 192, n_occ = 84, grid 60x75x54, N_ISDF = 420, N_k = 27): the fit metric and
+Bloch-gauge Coulomb matrices of three transfers against stored FP64 oracle values
+(tests/golden/make_golden.py, points chosen by the oracle), then properties of
+the fused build that hold at any size.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+
+from gpu_helpers import from_cplx_list, load_golden
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def full3():
+    import torch
+
+    from paper_2304_05505_amd import exx
+    from synth.fast import orbitals_on_grid_torch
+
+    gold = load_golden("config3.json")
+    cell = synth.make_config(3)
+    dev = torch.device("cuda", 0)
+    psi = orbitals_on_grid_torch(cell, synth.orbital_coeffs(cell), dev)
+    pts = np.asarray(gold["pts"], dtype=np.int64)
+    pts_t = torch.from_numpy(pts.astype(np.int32)).to(dev)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    t = {
+        "psi": psi,
+        "occ": psi[:, :, pts_t.long()].permute(0, 2, 1).contiguous(),
+        "ao": torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+        "pts": pts_t,
+    }
+    h = exx.Handle(0)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, cell.n_isdf)
+    return dict(gold=gold, cell=cell, t=t, h=h, c=c, exx=exx, torch=torch, dev=dev)
+
+
+def test_config3_fit_and_coulomb_match_oracle_samples(full3):
+    gold, cell, t, exx, torch, dev = (full3[k] for k in ("gold", "cell", "t", "exx", "torch", "dev"))
+    nk, ni, ng = cell.N_k, cell.n_isdf, cell.N_g
+    xi = torch.empty((nk, ni, ng), dtype=torch.complex128, device=dev)
+    S = torch.empty((nk, ni, ni), dtype=torch.complex128, device=dev)
+    V = torch.empty((nk, ni, ni), dtype=torch.complex128, device=dev)
+    rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+    exx.exx_isdf_fit(full3["h"], full3["c"], exx.EXX_F64, t["psi"], t["occ"], t["pts"], xi, S, rank)
+    exx.exx_coulomb_V(full3["h"], full3["c"], exx.EXX_F64, xi, t["pts"], V)
+    torch.cuda.synchronize()
+    del xi
+    S = S.cpu().numpy()
+    V = V.cpu().numpy()
+    rank = rank.cpu().numpy()
+    for j, m in enumerate(gold["m"]):
+        assert rank[m] == gold["rank"][j]
+        idx = np.asarray(gold[f"idx_{m}"])
+        tol = max(1e-12, 64 * EPS64 * gold["cond_S"][j])
+        s_ref = from_cplx_list(gold[f"S_{m}"])
+        assert np.abs(S[m][idx[:, 0], idx[:, 1]] - s_ref).max() <= 1e-12 * np.abs(s_ref).max()
+        v_ref = from_cplx_list(gold[f"Vb_{m}"])
+        dv = np.abs(V[m][idx[:, 0], idx[:, 1]] - v_ref).max()
+        dd = np.abs(np.diagonal(V[m]) - from_cplx_list(gold[f"Vbdiag_{m}"])).max()
+        print(f"m={m}: max|dVb| {dv:.2e} (diag {dd:.2e}) vs tol {tol * gold['maxabs_Vb'][j]:.2e}")
+        assert dv <= tol * gold["maxabs_Vb"][j]
+        assert dd <= tol * gold["maxabs_Vb"][j]
+
+
+def _build(full3, prec):
+    exx, torch, cell, t, dev = (full3[k] for k in ("exx", "torch", "cell", "t", "dev"))
+    psi = t["psi"] if prec in ("f64", "mixed") else t["psi"].to(torch.complex64)
+    K = torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128, device=dev)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((cell.N_k,), dtype=torch.int32, device=dev)
+    exx.exx_build(full3["h"], full3["c"], exx.PREC[prec], psi, t["occ"], t["ao"], t["pts"], K, Ex,
+                  rank)
+    torch.cuda.synchronize()
+    return K.cpu().numpy(), float(Ex.cpu()[0])
+
+
+def test_config3_build_properties_and_reduced_precision(full3):
+    K64, E64 = _build(full3, "f64")
+    assert E64 < 0
+    herm = max(np.abs(K64[n] - K64[n].conj().T).max() for n in range(K64.shape[0]))
+    assert herm <= 1e-10 * np.abs(K64).max()
+    Km, Em = _build(full3, "mixed")
+    Kf, Ef = _build(full3, "f32")
+    print(f"E_x f64 {E64:.10f}; mixed dE {Em - E64:+.2e} max|dK| {np.abs(Km - K64).max():.2e}; "
+          f"f32 dE {Ef - E64:+.2e} max|dK| {np.abs(Kf - K64).max():.2e}")
+    assert abs(Em - E64) <= 1e-5
