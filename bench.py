@@ -50,21 +50,21 @@ def algorithmic_work(cell, n_isdf, prec):
 
     Flops count the real multiply-adds of the product form each kernel uses:
     the FP64-matrix-core products (fit solve, Gamma in FP64 and mixed, the
-    Coulomb contraction in FP64 and mixed) use Gauss's three-product form, 6
-    flops per complex multiply-add; the FP32-matrix-core products (Gamma and
-    Coulomb in FP32) and the small K GEMMs use four real products, 8 flops.
-    The Coulomb contraction forms the lower triangle only (N_ISDF^2/2 pairs).
+    Coulomb contraction) use Gauss's three-product form, 6 flops per complex
+    multiply-add; the FP32-matrix-core Gamma of the FP32 path and the small K
+    GEMMs use four real products, 8 flops. The Coulomb contraction forms the
+    lower triangle only (N_ISDF^2/2 pairs).
     """
     nk, ng, no, na = cell.N_k, cell.N_g, cell.n_occ, cell.n_ao
     ni = n_isdf
     cs = 16 if prec == "f64" else 8
-    cm = 8.0 if prec == "f32" else 6.0  # flops per complex multiply-add, Gamma and Coulomb
+    cg = 8.0 if prec == "f32" else 6.0  # flops per complex multiply-add of the Gamma GEMM
     return {
-        "gamma": ("flop", cm * nk * ni * no * ng),
+        "gamma": ("flop", cg * nk * ni * no * ng),
         "kcorr": ("byte", 2.0 * nk * ni * ng * cs),
         "solve": ("flop", 6.0 * nk * ni * ni * ng),
         "fft": ("byte", 2.0 * nk * ni * ng * cs),
-        "coulomb": ("flop", cm / 2 * nk * ni * ni * ng),
+        "coulomb": ("flop", 3.0 * nk * ni * ni * ng),
         "K": ("flop", 8.0 * nk * (na * ni * ni + na * na * ni)),
     }
 
@@ -114,8 +114,9 @@ def traffic_bytes(phase, path):
     return 1024.0 * (fetch_kib * FETCH_SCALE + write_kib * WRITE_SCALE)
 
 
-FP64_PHASES = {"f64": {"gamma", "solve", "coulomb", "K"}, "mixed": {"gamma", "solve", "K"},
-               "f32": {"solve", "K"}}
+FP64_PHASES = {"f64": {"gamma", "solve", "coulomb", "K"},
+               "mixed": {"gamma", "solve", "coulomb", "K"},
+               "f32": {"solve", "coulomb", "K"}}
 
 
 def roofline(phases, work, prec, steps):

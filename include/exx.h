@@ -76,11 +76,11 @@ typedef enum {
  *              FP32; the Coulomb contraction multiplies the FP32-stored
  *              transforms on the FP64 matrix cores (exact products, FP64
  *              accumulation).
- *   EXX_F32    the grid-sized fit GEMM (Gamma^n) and the k-correlation Z^m
- *              in FP32 (psi_grid and xi c64); the fit solve applies the FP64
- *              pseudo-inverse in FP64 arithmetic; FFT in FP32; Coulomb
- *              contraction on FP32 matrix cores with FP32 accumulation
- *              flushed into FP64 every 64 grid points.
+ *   EXX_F32    the grid-sized fit GEMM (Gamma^n, FP32 matrix cores) and the
+ *              k-correlation Z^m in FP32 (psi_grid and xi c64); the fit solve
+ *              applies the FP64 pseudo-inverse in FP64 arithmetic; FFT in
+ *              FP32; the Coulomb contraction as in EXX_MIXED (FP64 matrix
+ *              cores on the FP32-stored transforms).
  *   EXX_BF16   reserved (not built in: EXX_ERR_UNSUPPORTED). */
 typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 } exx_prec;
 

@@ -252,10 +252,10 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   return EXX_OK;
 }
 
-// f64mma: contraction on FP64 matrix cores (exact products of the FP32-stored F)
+// T: storage of xi and F; the contraction runs on the FP64 matrix cores either way
 template <typename T>
 exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
-                        const void* xi, const int32_t* pts, void* V, bool f64mma, hipStream_t st) {
+                        const void* xi, const int32_t* pts, void* V, hipStream_t st) {
   void* F = ws + L.grid;
   hipError_t e;
   {
@@ -265,7 +265,7 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {
     PhaseTimer pt(h, PH_COULOMB, st);
-    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, f64mma, st);
+    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "coulomb");
   return EXX_OK;
@@ -404,8 +404,8 @@ exx_status exx_coulomb_V(exx_handle_t h, const exx_cell* cell, exx_prec prec, co
   char* ws;
   exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
   if (s != EXX_OK) return s;
-  if (prec == EXX_F64) return coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, true, stream);
-  return coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, prec == EXX_MIXED, stream);
+  if (prec == EXX_F64) return coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
+  return coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
 }
 
 exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* ao_pts,
@@ -442,13 +442,13 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   void* V = ws + L.V2;
   if (prec == EXX_F64) {
     s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, true, stream);
+    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
   } else if (prec == EXX_MIXED) {
     s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, true, stream);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
   } else {
     s = fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, false, stream);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
   }
   if (s != EXX_OK) return s;
   return buildK_impl(h, g, ws, L, ao_pts, occ_pts, V, K, Ex, stream);
@@ -512,15 +512,15 @@ exx_status build_one(exx_context* h, const Geom& g, const Tables& tb, char* ws, 
   if (prec == EXX_F64) {
     s = fit_impl<double, double>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
                                  st);
-    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, it.pts, V, true, st);
+    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, it.pts, V, st);
   } else if (prec == EXX_MIXED) {
     s = fit_impl<double, float>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
                                 st);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, it.pts, V, true, st);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, it.pts, V, st);
   } else {
     s = fit_impl<float, float>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
                                st);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, it.pts, V, false, st);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, it.pts, V, st);
   }
   if (s != EXX_OK) return s;
   return buildK_impl(h, g, ws, L, it.ao_pts, it.occ_pts, V, it.K, it.Ex, st);

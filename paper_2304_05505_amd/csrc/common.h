@@ -249,10 +249,10 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
                         int ncu, hipStream_t st);
 bool fft_supported(const Geom& g, bool fp64);
 
-// Coulomb contraction: V^m (Bloch gauge) from F^m; f64mma: FP64 matrix cores for FP32 storage
+// Coulomb contraction: V^m (Bloch gauge) from F^m (storage T) on the FP64 matrix cores
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
-                          void* partial, int nsplit, double2* V, bool f64mma, hipStream_t st);
+                          void* partial, int nsplit, double2* V, hipStream_t st);
 size_t coulomb_partial_bytes(const Geom& g, int nsplit);
 int coulomb_nsplit(const Geom& g);
 

@@ -21,97 +21,21 @@ struct CoulArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Matrix-core version of the partial contraction. A lane (row li = lane % 16,
-// group gq = lane / 16) loads TPL consecutive grid values of its row, so the k
-// index of MFMA step t is g0 + TPL gq + t for both operands (the k order of a
-// sum is free). X = v(g) F_P (rows P), Y = conj F_Q (rows Q):
-//   Re = sum Re X Re F_Q + Im X Im F_Q,  Im = sum Im X Re F_Q - Re X Im F_Q.
-// FP64 matrix cores (v_mfma_f64_16x16x4_f64) use Gauss's three-product form:
-// T1 = sum Re X Re F_Q, T2 = sum Im X Im F_Q, T3 = sum (Re X + Im X)(Re F_Q -
-// Im F_Q), then Re = T1 + T2 and Im = T3 - T1 + T2 (three MFMAs per complex
-// step). FP32 matrix cores (v_mfma_f32_16x16x4_f32) keep the four-product form
-// (its rounding is the smaller one) and flush their FP32 accumulators into FP64
-// every FLUSH grid points.
+// Matrix-core partial contraction. A lane (row li = lane % 16, group
+// gq = lane / 16) loads TPL consecutive grid values of its row, so the k index
+// of MFMA step t is g0 + TPL gq + t for both operands (the k order of a sum is
+// free). X = v(g) F_P (rows P), Y = conj F_Q (rows Q):
+//   Re = sum Re X Re F_Q + Im X Im F_Q,  Im = sum Im X Re F_Q - Re X Im F_Q,
+// on the FP64 matrix cores (v_mfma_f64_16x16x4_f64) in Gauss's three-product
+// form: T1 = sum Re X Re F_Q, T2 = sum Im X Im F_Q, T3 = sum (Re X + Im X)
+// (Re F_Q - Im F_Q), then Re = T1 + T2 and Im = T3 - T1 + T2. FP32-stored F is
+// widened at use, so its products are exact and the accumulation is FP64.
 // ---------------------------------------------------------------------------
 typedef double d4v __attribute__((ext_vector_type(4)));
-typedef float f4v __attribute__((ext_vector_type(4)));
 
-constexpr int MW = 2;       // 16-blocks per wave in each direction (wave tile 32 x 32)
-constexpr int MTILE = 64;   // workgroup tile (2 x 2 waves)
-constexpr int FLUSH = 64;   // FP32 accumulation length before the FP64 flush
-
-// Accumulators of one wave tile (MW x MW blocks of 16x16, real and imaginary).
-template <bool F64MMA>
-struct CAcc;
-
-template <>
-struct CAcc<true> {  // FP64 matrix cores, FP64 accumulation, three-product form
-  d4v t1[MW][MW], t2[MW][MW], t3[MW][MW];
-  __device__ void init() {
-#pragma unroll
-    for (int a = 0; a < MW; ++a)
-#pragma unroll
-      for (int b = 0; b < MW; ++b) t1[a][b] = t2[a][b] = t3[a][b] = d4v{0, 0, 0, 0};
-  }
-  // (xr + i xi) * conj(yr + i yi) for block (a, b); xs = xr + xi, ys = yr - yi
-  __device__ void mac(int a, int b, double xr, double xi, double xs, double yr, double yi,
-                      double ys) {
-    t1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr, t1[a][b], 0, 0, 0);
-    t2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi, t2[a][b], 0, 0, 0);
-    t3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, ys, t3[a][b], 0, 0, 0);
-  }
-  __device__ void chunk_done(int) {}
-  // register v of a lane holds row 4 v + lane/16 of the block
-  static __device__ int row(int gq, int v) { return 4 * v + gq; }
-};
-
-template <>
-struct CAcc<false> {  // FP32 matrix cores, FP32 accumulation flushed into FP64
-  f4v r[MW][MW], i[MW][MW];
-  double sr[MW][MW][4], si[MW][MW][4];
-  int since;
-  __device__ void init() {
-    since = 0;
-#pragma unroll
-    for (int a = 0; a < MW; ++a)
-#pragma unroll
-      for (int b = 0; b < MW; ++b) {
-        r[a][b] = i[a][b] = f4v{0, 0, 0, 0};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) sr[a][b][v] = si[a][b][v] = 0.0;
-      }
-  }
-  __device__ void mac(int a, int b, float xr, float xi, float, float yr, float yi, float) {
-    r[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, yr, r[a][b], 0, 0, 0);
-    r[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yi, r[a][b], 0, 0, 0);
-    i[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, yr, i[a][b], 0, 0, 0);
-    i[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-xr, yi, i[a][b], 0, 0, 0);
-  }
-  __device__ void flush() {
-#pragma unroll
-    for (int a = 0; a < MW; ++a)
-#pragma unroll
-      for (int b = 0; b < MW; ++b) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          sr[a][b][v] += (double)r[a][b][v];
-          si[a][b][v] += (double)i[a][b][v];
-        }
-        r[a][b] = i[a][b] = f4v{0, 0, 0, 0};
-      }
-  }
-  __device__ void chunk_done(int npts) {
-    since += npts;
-    if (since >= FLUSH) {
-      since = 0;
-      flush();
-    }
-  }
-  __device__ double re(int a, int b, int v) const { return sr[a][b][v] + (double)r[a][b][v]; }
-  __device__ double im(int a, int b, int v) const { return si[a][b][v] + (double)i[a][b][v]; }
-  // register v of a lane holds row 4 (lane/16) + v of the block
-  static __device__ int row(int gq, int v) { return 4 * gq + v; }
-};
+constexpr int MW = 2;      // 16-blocks per wave in each direction (wave tile 32 x 32)
+constexpr int MTILE = 64;  // workgroup tile (2 x 2 waves)
+constexpr int CALIGN = 64; // grid chunks of the split start at multiples of this
 
 // v^m(g) for every transfer m and grid point g: 4 pi/|K|^2 with the K-box
 // representative of each axis, 0 for K = 0
@@ -131,21 +55,17 @@ __global__ __launch_bounds__(256) void coulomb_vtab_kernel(double* __restrict__ 
   vt[(long)m * a.ng + g] = kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
 }
 
-// T: storage of F. F64MMA: FP64 matrix cores (exact products of FP32 inputs, FP64
-// accumulation) even for FP32 storage; otherwise FP32 matrix cores with flushes.
-// Work item w = (transfer m, grid split s, lower-triangle 64x64 tile); the
-// workgroup order is XCD-aware so that the tiles of one (m, s) share an L2.
-// Loads are unconditional with clamped indices (rows past N_ISDF feed outputs
-// that are never stored; grid points past the chunk get v = 0 at use), and
-// NPF chunks are in flight in registers.
-template <typename T, bool F64MMA>
+// T: storage of F. Work item w = (transfer m, grid split s, lower-triangle
+// 64x64 tile); the workgroup order is XCD-aware so that the tiles of one (m, s)
+// share an L2. Loads are unconditional with clamped indices (rows past N_ISDF
+// feed outputs that are never stored; grid points past the chunk get v = 0 at
+// use), and NPF chunks are in flight in registers.
+template <typename T>
 __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __restrict__ F,
                                                            const double* __restrict__ vt,
                                                            double2* __restrict__ part, CoulArgs a,
                                                            long nwork, long nwork_pad) {
-  using TO = typename std::conditional<F64MMA, double, float>::type;
-  // grid values per lane and chunk: the FP32 path takes twice as many per load
-  constexpr int TPL = F64MMA ? 2 : 4;
+  constexpr int TPL = 2;  // grid values per lane and MFMA step group
   constexpr int CK = 4 * TPL;
   const long per = nwork_pad / 8;
   const long w = (blockIdx.x % 8) * per + blockIdx.x / 8;  // XCD-contiguous ranges
@@ -177,8 +97,11 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
     yrow[i] = (unsigned)Q * (unsigned)a.ng;
   }
 
-  CAcc<F64MMA> acc;
-  acc.init();
+  d4v t1[MW][MW], t2[MW][MW], t3[MW][MW];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < MW; ++j) t1[i][j] = t2[i][j] = t3[i][j] = d4v{0, 0, 0, 0};
   constexpr int NPF = 2;  // chunks in flight
   cplx<T> fx[NPF][MW][TPL], fy[NPF][MW][TPL];
   double fv[NPF][TPL];
@@ -198,6 +121,10 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
   const long nchunk = (g1 - g0 + CK - 1) / CK;
 #pragma unroll
   for (int sl = 0; sl < NPF; ++sl) load(g0 + (long)sl * CK, fx[sl], fy[sl], fv[sl]);
+  // FP32 storage: let the first loads land before the loop, so that the wait
+  // counts at the loop head see only the loop's own refills (otherwise the
+  // differently ordered prologue forces a full wait there on every iteration)
+  if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_waitcnt(0);
   for (long c = 0; c < nchunk; c += NPF) {
 #pragma unroll
     for (int sl = 0; sl < NPF; ++sl) {
@@ -205,72 +132,61 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
       const long gb = k0 + TPL * gq;
 #pragma unroll
       for (int t = 0; t < TPL; ++t) {
-        const TO vv = (gb + t < g1) ? (TO)fv[sl][t] : (TO)0;
-        TO yr[MW], yi[MW], ys[MW];
+        const double vv = (gb + t < g1) ? fv[sl][t] : 0.0;
+        double yr[MW], yi[MW], ys[MW];
 #pragma unroll
         for (int j = 0; j < MW; ++j) {
-          yr[j] = (TO)fy[sl][j][t].x;
-          yi[j] = (TO)fy[sl][j][t].y;
+          yr[j] = (double)fy[sl][j][t].x;
+          yi[j] = (double)fy[sl][j][t].y;
           ys[j] = yr[j] - yi[j];
         }
 #pragma unroll
         for (int i = 0; i < MW; ++i) {
-          const TO xr = (TO)fx[sl][i][t].x * vv, xi = (TO)fx[sl][i][t].y * vv;
-          const TO xs = xr + xi;
+          const double xr = (double)fx[sl][i][t].x * vv, xi = (double)fx[sl][i][t].y * vv;
+          const double xs = xr + xi;
 #pragma unroll
-          for (int j = 0; j < MW; ++j) acc.mac(i, j, xr, xi, xs, yr[j], yi[j], ys[j]);
+          for (int j = 0; j < MW; ++j) {
+            t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr[j], t1[i][j], 0, 0, 0);
+            t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi[j], t2[i][j], 0, 0, 0);
+            t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, ys[j], t3[i][j], 0, 0, 0);
+          }
         }
       }
-      acc.chunk_done(CK);
       // refill the slot (clamped loads past the end are discarded by v = 0)
       __builtin_amdgcn_sched_barrier(0);
       load(k0 + NPF * CK, fx[sl], fy[sl], fv[sl]);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  // D layout: register v of a lane holds row 4 v + lane/16 of the block.
+  // Combining T1..T3 needs the accumulators in VALU registers: each lane
+  // round-trips its own values through this wave's LDS slice (LDS accesses of
+  // one wave complete in order), which keeps the accumulators in the matrix
+  // registers during the loop.
   double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
-  if constexpr (F64MMA) {
-    // Combining T1..T3 needs the accumulators in VALU registers: each lane
-    // round-trips its own values through this wave's LDS slice (LDS accesses of
-    // one wave complete in order), which keeps the accumulators in the matrix
-    // registers during the loop.
-    __shared__ double stage[4][3][64 * 4];
-    typedef __attribute__((address_space(3))) volatile double lds_f64;
-    lds_f64* s1 = (lds_f64*)stage[wave][0];
-    lds_f64* s2 = (lds_f64*)stage[wave][1];
-    lds_f64* s3 = (lds_f64*)stage[wave][2];
+  __shared__ double stage[4][3][64 * 4];
+  typedef __attribute__((address_space(3))) volatile double lds_f64;
+  lds_f64* s1 = (lds_f64*)stage[wave][0];
+  lds_f64* s2 = (lds_f64*)stage[wave][1];
+  lds_f64* s3 = (lds_f64*)stage[wave][2];
 #pragma unroll
-    for (int i = 0; i < MW; ++i)
+  for (int i = 0; i < MW; ++i)
 #pragma unroll
-      for (int j = 0; j < MW; ++j) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          s1[v * 64 + lane] = acc.t1[i][j][v];
-          s2[v * 64 + lane] = acc.t2[i][j][v];
-          s3[v * 64 + lane] = acc.t3[i][j][v];
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double x1 = s1[v * 64 + lane], x2 = s2[v * 64 + lane], x3 = s3[v * 64 + lane];
-          const int P = P0 + 16 * i + CAcc<true>::row(gq, v);
-          const int Q = Q0 + 16 * j + li;
-          if (P < a.ni && Q < a.ni) out[(long)P * a.ni + Q] = make_double2(x1 + x2, x3 - x1 + x2);
-        }
-      }
-  } else {
-#pragma unroll
-    for (int i = 0; i < MW; ++i)
+    for (int j = 0; j < MW; ++j) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int P = P0 + 16 * i + CAcc<false>::row(gq, v);
-        if (P >= a.ni) continue;
-#pragma unroll
-        for (int j = 0; j < MW; ++j) {
-          const int Q = Q0 + 16 * j + li;
-          if (Q < a.ni) out[(long)P * a.ni + Q] = make_double2(acc.re(i, j, v), acc.im(i, j, v));
-        }
+        s1[v * 64 + lane] = t1[i][j][v];
+        s2[v * 64 + lane] = t2[i][j][v];
+        s3[v * 64 + lane] = t3[i][j][v];
       }
-  }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double x1 = s1[v * 64 + lane], x2 = s2[v * 64 + lane], x3 = s3[v * 64 + lane];
+        const int P = P0 + 16 * i + 4 * v + gq;
+        const int Q = Q0 + 16 * j + li;
+        if (P < a.ni && Q < a.ni) out[(long)P * a.ni + Q] = make_double2(x1 + x2, x3 - x1 + x2);
+      }
+    }
 }
 
 struct ReduceArgs {
@@ -350,7 +266,7 @@ size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
 
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
-                          void* partial, int nsplit, double2* V, bool f64mma, hipStream_t st) {
+                          void* partial, int nsplit, double2* V, hipStream_t st) {
   CoulArgs a;
   for (int i = 0; i < 3; ++i) {
     a.L[i] = g.L[i];
@@ -361,7 +277,7 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.ni = g.ni;
   a.nk = g.nk;
   a.nsplit = nsplit;
-  a.chunk = (int)((((long)g.ng + nsplit - 1) / nsplit + FLUSH - 1) / FLUSH * FLUSH);
+  a.chunk = (int)((((long)g.ng + nsplit - 1) / nsplit + CALIGN - 1) / CALIGN * CALIGN);
   const int nt = (g.ni + MTILE - 1) / MTILE;
   a.ntile = nt * (nt + 1) / 2;
   if ((long)g.ni * g.ng >= 0x7fffffffL) return hipErrorInvalidValue;
@@ -372,15 +288,8 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
                      st, vt, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  bool fp64_cores = f64mma;
-  if constexpr (sizeof(T) == 8) fp64_cores = true;  // FP64 storage always uses FP64 cores
-  if (fp64_cores) {
-    hipLaunchKernelGGL((coulomb_mfma_kernel<T, true>), dim3((unsigned)pad), dim3(256), 0, st,
-                       (const cplx<T>*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
-  } else if constexpr (sizeof(T) == 4) {
-    hipLaunchKernelGGL((coulomb_mfma_kernel<T, false>), dim3((unsigned)pad), dim3(256), 0, st,
-                       (const cplx<T>*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
-  }
+  hipLaunchKernelGGL((coulomb_mfma_kernel<T>), dim3((unsigned)pad), dim3(256), 0, st,
+                     (const cplx<T>*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   ReduceArgs r;
@@ -399,8 +308,8 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
 }
 
 template hipError_t launch_coulomb<double>(const Geom&, const Tables&, const void*, const int32_t*,
-                                           void*, int, double2*, bool, hipStream_t);
+                                           void*, int, double2*, hipStream_t);
 template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void*, const int32_t*,
-                                          void*, int, double2*, bool, hipStream_t);
+                                          void*, int, double2*, hipStream_t);
 
 }  // namespace exx

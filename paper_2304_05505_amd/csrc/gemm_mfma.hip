@@ -99,6 +99,10 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
   };
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
+  // let the first loads land before the loop, so that the wait counts at the
+  // loop head see only the loop's own refills (the differently ordered prologue
+  // otherwise forces a full wait there on every iteration)
+  __builtin_amdgcn_s_waitcnt(0);
   const int niter = (K + 4 * NPF - 1) / (4 * NPF);
   for (int it = 0; it < niter; ++it) {
 #pragma unroll
@@ -232,6 +236,7 @@ __global__ __launch_bounds__(256) void cgemm_nn_mfma32(int M, int N, int K, int 
   };
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
+  __builtin_amdgcn_s_waitcnt(0);  // as in zgemm_nn_mfma
   const int niter = (K + 4 * NPF - 1) / (4 * NPF);
   for (int it = 0; it < niter; ++it) {
 #pragma unroll

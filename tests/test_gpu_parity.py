@@ -94,9 +94,9 @@ def test_fused_build_equals_stages(gpu):
 
 @pytest.mark.parametrize("name", ["gamma-config1", "k444", "k112", "k221"])
 def test_mixed_mode_matches_oracle(name, gpu):
-    """EXX_MIXED: FP64 fit, xi stored in FP32, FP32 FFT and Coulomb contraction with FP64
-    flushes. xi rounding (eps32 relative) and FP32 products bound the error of V at
-    ~1e-6 relative; E_x and K inherit it. K and E_x come out of sums whose terms grow
+    """EXX_MIXED: FP64 fit, xi stored in FP32, FP32 FFT, Coulomb contraction on the FP64
+    matrix cores from the FP32-stored transforms. The FP32 rounding of xi and F
+    (eps32 relative) bounds the error of V at ~1e-6 relative; E_x and K inherit it. K and E_x come out of sums whose terms grow
     with the conditioning of S^m, so the cells here are the well-conditioned ones
     (smallest retained Cholesky pivot >= 1e-5 of the largest diagonal); the
     accuracy target at the benchmark workload is checked in test_gpu_full.py."""
@@ -117,7 +117,8 @@ def test_mixed_mode_matches_oracle(name, gpu):
 
 @pytest.mark.parametrize("name", ["gamma-config1", "k222-ragged", "k333"])
 def test_fp32_mode_error_report(name, gpu):
-    """EXX_F32: bulk FP32 (Gamma, Z, FFT, Coulomb), FP64 solve and E_x. Error reported and bounded."""
+    """EXX_F32: Gamma, Z, xi and the FFT in FP32; FP64 solve arithmetic, FP64-core Coulomb
+    contraction, FP64 E_x. Error reported and bounded."""
     cell = CELLS[name]()
     base = inputs(cell)
     pts, _ = select.select_points(base["psi"], cell.n_isdf)
