@@ -34,7 +34,7 @@ struct CoulArgs {
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 constexpr int MW = 2;      // 16-blocks per wave in each direction (wave tile 32 x 32)
-constexpr int MTILE = 64;  // workgroup tile (2 x 2 waves)
+constexpr int WTILE = MW * 16;  // wave tile
 constexpr int CALIGN = 64; // grid chunks of the split start at multiples of this
 
 // v^m(g) for every transfer m and grid point g: 4 pi/|K|^2 with the K-box
@@ -55,40 +55,31 @@ __global__ __launch_bounds__(256) void coulomb_vtab_kernel(double* __restrict__ 
   vt[(long)m * a.ng + g] = kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
 }
 
-// T: storage of F. Work item w = (transfer m, grid split s, lower-triangle
-// 64x64 tile); the workgroup order is XCD-aware so that the tiles of one (m, s)
-// share an L2. Loads are unconditional with clamped indices (rows past N_ISDF
-// feed outputs that are never stored; grid points past the chunk get v = 0 at
-// use), and NPF chunks are in flight in registers.
-template <typename T>
-__global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __restrict__ F,
-                                                           const double* __restrict__ vt,
-                                                           double2* __restrict__ part, CoulArgs a,
-                                                           long nwork, long nwork_pad) {
+// One wave computes one 32 x 32 wave tile (2 x 2 blocks of 16 x 16) of the
+// lower triangle for one transfer m and one grid chunk [g0, g1). MASK selects
+// the blocks that are computed and stored (bit 2 i + j for block row i, column
+// j). On diagonal tiles without block (0, 1) the row and column operands are
+// the same rows of F and are loaded once. Loads are unconditional with clamped
+// indices (clamped rows only feed outputs that are never stored; grid points
+// past the chunk get v = 0 at use), and NPF chunks are in flight in registers.
+// VEC (FP32 storage, even N_g): a lane's two grid values of a row are one
+// aligned 16-byte load, so a load instruction touches each row's cache line
+// once. stage: this wave's 3 x 256 doubles of LDS (epilogue staging).
+template <typename T, int MASK, bool VEC, int NPF>
+__device__ __forceinline__ void coulomb_wave_tile(const cplx<T>* __restrict__ Fm,
+                                                  const double* __restrict__ vm,
+                                                  double2* __restrict__ out, const CoulArgs& a,
+                                                  int P0, int Q0, long g0, long g1,
+                                                  double* stage) {
   constexpr int TPL = 2;  // grid values per lane and MFMA step group
   constexpr int CK = 4 * TPL;
-  const long per = nwork_pad / 8;
-  const long w = (blockIdx.x % 8) * per + blockIdx.x / 8;  // XCD-contiguous ranges
-  if (w >= nwork) return;
-  int tile = (int)(w % a.ntile);
-  const long ms = w / a.ntile;
-  const int m = (int)(ms / a.nsplit), s = (int)(ms % a.nsplit);
-  int ti = 0;
-  while (tile > ti) {
-    tile -= ti + 1;
-    ++ti;
-  }
-  const int tj = tile;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr bool DIAG = (MASK & 2) == 0;
+  constexpr bool XU[MW] = {(MASK & 3) != 0, (MASK & 12) != 0};
+  constexpr bool YU[MW] = {(MASK & 5) != 0, (MASK & 10) != 0};
+  const int lane = threadIdx.x & 63;
   const int li = lane & 15, gq = lane >> 4;
-  const int P0 = ti * MTILE + (wave & 1) * (MW * 16);
-  const int Q0 = tj * MTILE + (wave >> 1) * (MW * 16);
-  const long g0 = (long)s * a.chunk;
-  const long g1 = min((long)a.ng, g0 + a.chunk);
-  const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
-  const double* vm = vt + (long)m * a.ng;
   // 32-bit row offsets from the uniform base Fm (N_ISDF N_g < 2^31 is checked by
-  // the launcher); clamped rows only feed unstored outputs
+  // the launcher)
   unsigned xrow[MW], yrow[MW];
 #pragma unroll
   for (int i = 0; i < MW; ++i) {
@@ -96,25 +87,44 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
     xrow[i] = (unsigned)P * (unsigned)a.ng;
     yrow[i] = (unsigned)Q * (unsigned)a.ng;
   }
-
   d4v t1[MW][MW], t2[MW][MW], t3[MW][MW];
 #pragma unroll
   for (int i = 0; i < MW; ++i)
 #pragma unroll
     for (int j = 0; j < MW; ++j) t1[i][j] = t2[i][j] = t3[i][j] = d4v{0, 0, 0, 0};
-  constexpr int NPF = 2;  // chunks in flight
   cplx<T> fx[NPF][MW][TPL], fy[NPF][MW][TPL];
   double fv[NPF][TPL];
   auto load = [&](long k0, cplx<T> (*xx)[TPL], cplx<T> (*yy)[TPL], double* vv) {
     const long gb = k0 + TPL * gq;
-#pragma unroll
-    for (int t = 0; t < TPL; ++t) {
-      const unsigned g = (unsigned)min(gb + t, (long)a.ng - 1);
-      vv[t] = vm[g];
+    if constexpr (VEC) {
+      // gb is even; past the end the base is clamped to N_g - 2 (v = 0 at use)
+      const unsigned g = (unsigned)min(gb, (long)a.ng - 2);
+      const double2 v2 = *(const double2*)(vm + g);
+      vv[0] = v2.x;
+      vv[1] = v2.y;
 #pragma unroll
       for (int i = 0; i < MW; ++i) {
-        xx[i][t] = Fm[xrow[i] + g];
-        yy[i][t] = Fm[yrow[i] + g];
+        if (DIAG ? (XU[i] || YU[i]) : XU[i]) {
+          const float4 q = *(const float4*)(Fm + xrow[i] + g);
+          xx[i][0] = mk<T>(q.x, q.y);
+          xx[i][1] = mk<T>(q.z, q.w);
+        }
+        if (!DIAG && YU[i]) {
+          const float4 q = *(const float4*)(Fm + yrow[i] + g);
+          yy[i][0] = mk<T>(q.x, q.y);
+          yy[i][1] = mk<T>(q.z, q.w);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < TPL; ++t) {
+        const unsigned g = (unsigned)min(gb + t, (long)a.ng - 1);
+        vv[t] = vm[g];
+#pragma unroll
+        for (int i = 0; i < MW; ++i) {
+          if (DIAG ? (XU[i] || YU[i]) : XU[i]) xx[i][t] = Fm[xrow[i] + g];
+          if (!DIAG && YU[i]) yy[i][t] = Fm[yrow[i] + g];
+        }
       }
     }
   };
@@ -136,16 +146,20 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
         double yr[MW], yi[MW], ys[MW];
 #pragma unroll
         for (int j = 0; j < MW; ++j) {
-          yr[j] = (double)fy[sl][j][t].x;
-          yi[j] = (double)fy[sl][j][t].y;
+          if (!YU[j]) continue;
+          const cplx<T> y = DIAG ? fx[sl][j][t] : fy[sl][j][t];
+          yr[j] = (double)y.x;
+          yi[j] = (double)y.y;
           ys[j] = yr[j] - yi[j];
         }
 #pragma unroll
         for (int i = 0; i < MW; ++i) {
+          if (!XU[i]) continue;
           const double xr = (double)fx[sl][i][t].x * vv, xi = (double)fx[sl][i][t].y * vv;
           const double xs = xr + xi;
 #pragma unroll
           for (int j = 0; j < MW; ++j) {
+            if (!(MASK & (1 << (2 * i + j)))) continue;
             t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr[j], t1[i][j], 0, 0, 0);
             t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi[j], t2[i][j], 0, 0, 0);
             t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, ys[j], t3[i][j], 0, 0, 0);
@@ -160,19 +174,18 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
   }
   // D layout: register v of a lane holds row 4 v + lane/16 of the block.
   // Combining T1..T3 needs the accumulators in VALU registers: each lane
-  // round-trips its own values through this wave's LDS slice (LDS accesses of
+  // round-trips its own values through its wave's LDS slice (LDS accesses of
   // one wave complete in order), which keeps the accumulators in the matrix
   // registers during the loop.
-  double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
-  __shared__ double stage[4][3][64 * 4];
   typedef __attribute__((address_space(3))) volatile double lds_f64;
-  lds_f64* s1 = (lds_f64*)stage[wave][0];
-  lds_f64* s2 = (lds_f64*)stage[wave][1];
-  lds_f64* s3 = (lds_f64*)stage[wave][2];
+  lds_f64* s1 = (lds_f64*)stage;
+  lds_f64* s2 = s1 + 64 * 4;
+  lds_f64* s3 = s2 + 64 * 4;
 #pragma unroll
   for (int i = 0; i < MW; ++i)
 #pragma unroll
     for (int j = 0; j < MW; ++j) {
+      if (!(MASK & (1 << (2 * i + j)))) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         s1[v * 64 + lane] = t1[i][j][v];
@@ -187,6 +200,80 @@ __global__ __launch_bounds__(256, 2) void coulomb_mfma_kernel(const cplx<T>* __r
         if (P < a.ni && Q < a.ni) out[(long)P * a.ni + Q] = make_double2(x1 + x2, x3 - x1 + x2);
       }
     }
+}
+
+// (transfer m, grid split s, lower-triangle tile t) of work item w; the order of
+// w is XCD-contiguous so that the tiles of one (m, s) share an L2
+__device__ __forceinline__ void coulomb_work(long w, const CoulArgs& a, int& m, int& s, int& ti,
+                                             int& tj) {
+  int tile = (int)(w % a.ntile);
+  const long ms = w / a.ntile;
+  m = (int)(ms / a.nsplit);
+  s = (int)(ms % a.nsplit);
+  ti = 0;
+  while (tile > ti) {
+    tile -= ti + 1;
+    ++ti;
+  }
+  tj = tile;
+}
+
+// FP64 storage: 64 x 64 tiles of 2 x 2 waves, whose waves share the rows of F
+// through L1 (the redundant upper-triangle blocks of diagonal tiles are
+// computed; the reduction reads only P >= Q).
+__global__ __launch_bounds__(256, 2) void coulomb_kernel_f64(const double2* __restrict__ F,
+                                                          const double* __restrict__ vt,
+                                                          double2* __restrict__ part, CoulArgs a,
+                                                          long nwork, long nwork_pad) {
+  const long w = (blockIdx.x % 8) * (nwork_pad / 8) + blockIdx.x / 8;
+  if (w >= nwork) return;
+  int m, s, ti, tj;
+  coulomb_work(w, a, m, s, ti, tj);
+  const int wave = threadIdx.x >> 6;
+  const int P0 = ti * 2 * WTILE + (wave & 1) * WTILE;
+  const int Q0 = tj * 2 * WTILE + (wave >> 1) * WTILE;
+  const long g0 = (long)s * a.chunk;
+  const long g1 = min((long)a.ng, g0 + a.chunk);
+  __shared__ double stage[4 * 3 * 64 * 4];
+  coulomb_wave_tile<double, 0xF, false, 2>(
+      F + (long)m * a.ni * a.ng, vt + (long)m * a.ng,
+      part + ((long)m * a.nsplit + s) * a.ni * a.ni, a, P0, Q0, g0, g1,
+      stage + wave * 3 * 64 * 4);
+}
+
+// FP32 storage: one wave per workgroup and 32 x 32 tiles, so that only the
+// blocks that hold needed entries are computed (the all-upper block of a
+// diagonal tile and block rows past N_ISDF are skipped) without leaving a SIMD
+// of a multi-wave workgroup short of waves.
+template <bool VEC>
+__global__ __launch_bounds__(64) void coulomb_kernel_f32(const float2* __restrict__ F,
+                                                      const double* __restrict__ vt,
+                                                      double2* __restrict__ part, CoulArgs a,
+                                                      long nwork, long nwork_pad) {
+  const long w = (blockIdx.x % 8) * (nwork_pad / 8) + blockIdx.x / 8;
+  if (w >= nwork) return;
+  int m, s, ti, tj;
+  coulomb_work(w, a, m, s, ti, tj);
+  const int P0 = ti * WTILE, Q0 = tj * WTILE;
+  const long g0 = (long)s * a.chunk;
+  const long g1 = min((long)a.ng, g0 + a.chunk);
+  const float2* Fm = F + (long)m * a.ni * a.ng;
+  const double* vm = vt + (long)m * a.ng;
+  double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
+  constexpr int NPF = 4;
+  __shared__ double stage[3 * 64 * 4];
+  const bool row1 = P0 + 16 < a.ni;  // block row 1 holds rows below N_ISDF
+  if (ti != tj) {
+    if (row1)
+      coulomb_wave_tile<float, 0xF, VEC, NPF>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+    else
+      coulomb_wave_tile<float, 0x3, VEC, NPF>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+  } else {
+    if (row1)
+      coulomb_wave_tile<float, 0xD, VEC, NPF>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+    else
+      coulomb_wave_tile<float, 0x1, VEC, NPF>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+  }
 }
 
 struct ReduceArgs {
@@ -246,7 +333,7 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __re
 }  // namespace
 
 int coulomb_nsplit(const Geom& g) {
-  const int nt = (g.ni + MTILE - 1) / MTILE;
+  const int nt = (g.ni + 2 * WTILE - 1) / (2 * WTILE);  // 64-row blocks
   const long tiles = (long)nt * (nt + 1) / 2 * g.nk;
   long ns = (4096 + tiles - 1) / tiles;
   const long maxs = (g.ng + 1023) / 1024;  // keep chunks >= ~1k points
@@ -278,7 +365,9 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.nk = g.nk;
   a.nsplit = nsplit;
   a.chunk = (int)((((long)g.ng + nsplit - 1) / nsplit + CALIGN - 1) / CALIGN * CALIGN);
-  const int nt = (g.ni + MTILE - 1) / MTILE;
+  // FP64 storage: 64 x 64 workgroup tiles; FP32 storage: 32 x 32 wave tiles
+  const int tw = sizeof(T) == 8 ? 2 * WTILE : WTILE;
+  const int nt = (g.ni + tw - 1) / tw;
   a.ntile = nt * (nt + 1) / 2;
   if ((long)g.ni * g.ng >= 0x7fffffffL) return hipErrorInvalidValue;
   const long nwork = (long)a.ntile * g.nk * nsplit;
@@ -288,8 +377,16 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
                      st, vt, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((coulomb_mfma_kernel<T>), dim3((unsigned)pad), dim3(256), 0, st,
-                     (const cplx<T>*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+  if constexpr (sizeof(T) == 8) {
+    hipLaunchKernelGGL(coulomb_kernel_f64, dim3((unsigned)pad), dim3(256), 0, st,
+                       (const double2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+  } else if (g.ng % 2 == 0) {
+    hipLaunchKernelGGL(coulomb_kernel_f32<true>, dim3((unsigned)pad), dim3(64), 0, st,
+                       (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+  } else {
+    hipLaunchKernelGGL(coulomb_kernel_f32<false>, dim3((unsigned)pad), dim3(64), 0, st,
+                       (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   ReduceArgs r;
