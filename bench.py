@@ -78,21 +78,21 @@ def algorithmic_work(cell, n_isdf, prec):
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524315.4375, 1.0
 TRAFFIC = {
     # (phase, path): (source, sha256[:16], FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("solve", "f64"): ("gemm_mfma.hip", "56e32a30c5a5588c", 16446904.8, 12757500.0),
-    ("solve", "mixed"): ("gemm_mfma.hip", "56e32a30c5a5588c", 16197055.4, 6420846.6),
-    ("solve", "f32"): ("gemm_mfma.hip", "56e32a30c5a5588c", 10148010.9, 6425589.2),
-    ("gamma", "f64"): ("gemm_mfma.hip", "56e32a30c5a5588c", 1311069.3, 12757500.0),
-    ("gamma", "mixed"): ("gemm_mfma.hip", "56e32a30c5a5588c", 1311069.3, 12757500.0),
-    ("gamma", "f32"): ("gemm_mfma.hip", "56e32a30c5a5588c", 816074.0, 6425531.5),
-    ("kcorr", "f64"): ("fit.hip", "01c53048f397523a", 6378994.6, 12757500.0),
-    ("kcorr", "mixed"): ("fit.hip", "01c53048f397523a", 6378994.6, 12757500.0),
-    ("kcorr", "f32"): ("fit.hip", "01c53048f397523a", 3189577.6, 6378750.0),
-    ("fft", "f64"): ("fft.hip", "f37851e0012f7e0c", 13970475.8, 25515043.8),
-    ("fft", "mixed"): ("fft.hip", "f37851e0012f7e0c", 7790404.2, 13160700.0),
-    ("fft", "f32"): ("fft.hip", "f37851e0012f7e0c", 7790404.2, 13160700.0),
-    ("coulomb", "f64"): ("coulomb.hip", "0be09b85ad4262f0", 25114777.7, 243822.2),
-    ("coulomb", "mixed"): ("coulomb.hip", "0be09b85ad4262f0", 5651119.9, 242763.8),
-    ("coulomb", "f32"): ("coulomb.hip", "0be09b85ad4262f0", 11378013.4, 244838.6),
+    ("solve", "f64"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 15980730.3, 12757500.0),
+    ("solve", "mixed"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 15917826.1, 6417227.2),
+    ("solve", "f32"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 9040774.4, 6456818.7),
+    ("gamma", "f64"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 1296077.3, 12757500.0),
+    ("gamma", "mixed"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 1296077.3, 12757500.0),
+    ("gamma", "f32"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 656773.1, 6437899.1),
+    ("kcorr", "f64"): ("fit.hip", "01c53048f397523a", 6379036.9, 12757500.0),
+    ("kcorr", "mixed"): ("fit.hip", "01c53048f397523a", 6379036.9, 12757500.0),
+    ("kcorr", "f32"): ("fit.hip", "01c53048f397523a", 3189571.4, 6378750.0),
+    ("fft", "f64"): ("fft.hip", "97cc61b6aef13241", 13969953.2, 25515043.5),
+    ("fft", "mixed"): ("fft.hip", "97cc61b6aef13241", 7790563.8, 13160701.9),
+    ("fft", "f32"): ("fft.hip", "97cc61b6aef13241", 7790563.8, 13160701.9),
+    ("coulomb", "f64"): ("coulomb.hip", "5af2bc2def895dff", 61064667.3, 241537.9),
+    ("coulomb", "mixed"): ("coulomb.hip", "5af2bc2def895dff", 7473337.8, 245680.6),
+    ("coulomb", "f32"): ("coulomb.hip", "5af2bc2def895dff", 7473337.8, 245680.6),
 }
 
 
