@@ -325,7 +325,8 @@ def bench_batch24(args):
         res[name] = {"seconds": t_b, "builds_per_s": 24.0 / t_b, "speedup_vs_seq_f64": t_seq / t_b,
                      "max_dEx_vs_f64": dE, "max_dK_vs_f64": dK,
                      "meets_1e-5_1e-6": bool(dE <= 1e-5 and dK <= 1e-6),
-                     "dEx_per_cell": dEs}
+                     "dEx_per_cell": dEs, "dK_per_cell": dKs,
+                     "maxabs_K_per_cell": [float(np.abs(k).max()) for k in k64]}
         log(f"[batch24] batched {name}: {t_b * 1e3:.1f} ms, max|dEx| {dE:.2e}, max|dK| {dK:.2e}")
     ok = [n for n in res if res[n]["meets_1e-5_1e-6"]]
     chosen = max(ok, key=lambda n: res[n]["builds_per_s"])
