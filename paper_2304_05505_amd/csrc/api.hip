@@ -183,36 +183,57 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   void* grid = ws + L.grid;
   const long nn = (long)g.ni * g.ni;
   hipError_t e;
+  // The point-metric chain (a0, a2 at the points, a3) runs on the handle's
+  // second stream while the grid-sized Gamma and Z run on st; the solve waits
+  // for both. Both streams touch disjoint scratch.
+  hipStream_t ax = h->aux;
+  e = hipEventRecord(h->fork_ev, st);
+  if (e != hipSuccess) return hip_check(h, e, "fork event");
+  e = hipStreamWaitEvent(ax, h->fork_ev, 0);
+  if (e != hipSuccess) return hip_check(h, e, "fork wait");
+  const char* what = nullptr;
   // a0: G^n = Psi^n Psi^n^H (FP64)
   {
-  PhaseTimer pt(h, PH_GRAM, st);
-  e = gemm<double, double, double, double>(g.ni, g.ni, g.no, g.nk, A_N, occ, g.no,
-                                           (long)g.ni * g.no, B_C, occ, g.no, (long)g.ni * g.no, G,
-                                           g.ni, nn, 1.0, false, st);
+    PhaseTimer pt(h, PH_GRAM, ax);
+    e = gemm<double, double, double, double>(g.ni, g.ni, g.no, g.nk, A_N, occ, g.no,
+                                             (long)g.ni * g.no, B_C, occ, g.no,
+                                             (long)g.ni * g.no, G, g.ni, nn, 1.0, false, ax);
   }
-  if (e != hipSuccess) return hip_check(h, e, "G gemm");
+  if (e != hipSuccess) what = "G gemm";
   // a2 at the points: S^m = e^{iq(r_P - r_Q)} sum_n G^n o conj G^{n+m}
-  {
-    PhaseTimer pt(h, PH_METRIC, st);
-    e = launch_kcorr<double>(g, tb, G, S, g.ni, pts, true, st);
+  if (!what) {
+    PhaseTimer pt(h, PH_METRIC, ax);
+    e = launch_kcorr<double>(g, tb, G, S, g.ni, pts, true, ax);
+    if (e != hipSuccess) what = "S kcorr";
   }
-  if (e != hipSuccess) return hip_check(h, e, "S kcorr");
   // a3: Cholesky with drop, inverse factor, S^+ = W^H W
-  {
-    PhaseTimer pt(h, PH_CHOL, st);
-    e = launch_copy(Lf, (const double2*)S, (long)g.nk * nn, st);
-    if (e != hipSuccess) return hip_check(h, e, "copy S");
-    e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, st);
+  if (!what) {
+    PhaseTimer pt(h, PH_CHOL, ax);
+    e = launch_copy(Lf, (const double2*)S, (long)g.nk * nn, ax);
+    if (e != hipSuccess) what = "copy S";
+    if (!what) {
+      e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax);
+      if (e != hipSuccess) what = "cholesky";
+    }
   }
-  if (e != hipSuccess) return hip_check(h, e, "cholesky");
-  {
-    PhaseTimer pt(h, PH_PINV, st);
-    e = launch_tri_inv_blocked(g, Lf, keep, W, (double2*)(ws + L.Tinv), st);
-    if (e != hipSuccess) return hip_check(h, e, "triangular inverse");
-    e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,
-                                             g.ni, nn, Sp, g.ni, nn, 1.0, false, st);
+  if (!what) {
+    PhaseTimer pt(h, PH_PINV, ax);
+    e = launch_tri_inv_blocked(g, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
+    if (e != hipSuccess) what = "triangular inverse";
+    if (!what) {
+      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,
+                                               g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
+      if (e != hipSuccess) what = "S+ gemm";
+    }
   }
-  if (e != hipSuccess) return hip_check(h, e, "S+ gemm");
+  // join back into st even after an error, so that st never runs ahead of the
+  // chain (and a capture stays joined)
+  hipError_t ej = hipEventRecord(h->join_ev, ax);
+  if (what) {
+    if (ej == hipSuccess) (void)hipStreamWaitEvent(st, h->join_ev, 0);
+    return hip_check(h, e, what);
+  }
+  if (ej != hipSuccess) return hip_check(h, ej, "join event");
   // a1: Gamma^n(P, r)
   {
     PhaseTimer pt(h, PH_GAMMA, st);
@@ -224,13 +245,16 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
       e = cgemm_nn_grid32(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi, g.ng,
                           (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, st);
   }
-  if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
+  if (e != hipSuccess) what = "Gamma gemm";
   // a2: Z^m in place
-  {
+  if (!what) {
     PhaseTimer pt(h, PH_KCORR, st);
     e = launch_kcorr<TF>(g, tb, grid, grid, g.ng, pts, false, st);
+    if (e != hipSuccess) what = "Z kcorr";
   }
-  if (e != hipSuccess) return hip_check(h, e, "Z kcorr");
+  hipError_t ew = hipStreamWaitEvent(st, h->join_ev, 0);
+  if (what) return hip_check(h, e, what);
+  if (ew != hipSuccess) return hip_check(h, ew, "join wait");
   // a4: xi^m = S^+ Z^m, FP64 arithmetic
   {
     PhaseTimer pt(h, PH_SOLVE, st);
@@ -315,6 +339,12 @@ exx_status setup(exx_context* h, const exx_cell* cell, exx_prec prec, bool build
   if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  if (!h->aux) {
+    e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_check(h, e, "auxiliary stream");
+  }
   e = fft_prepare(&h->ncu);
   if (e != hipSuccess) return hip_check(h, e, "FFT set-up");
   *g = make_geom(*cell);
@@ -359,6 +389,9 @@ exx_status exx_destroy(exx_handle_t h) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
   delete h;
   return EXX_OK;
 }
@@ -598,6 +631,12 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   if (n == 0) return EXX_OK;
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  if (!h->aux) {
+    e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_check(h, e, "auxiliary stream");
+  }
   e = fft_prepare(&h->ncu);
   if (e != hipSuccess) return hip_check(h, e, "FFT set-up");
   // validate everything and size the scratch before anything is launched

@@ -114,6 +114,10 @@ struct exx_context {
   int tile_solve = 22;
   // steps of iterative refinement after the fit solve (0 or 1)
   int refine = 0;
+  // second stream (default priority) for the point-metric chain of the fit,
+  // which overlaps the grid-sized Gamma and Z; fork/join events
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int ncu = 256;
   // autotuned wave tiles per size class: key (ni, ng, no, nk, prec) -> (gamma, solve)
   struct Tune {
