@@ -289,10 +289,142 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {
     PhaseTimer pt(h, PH_COULOMB, st);
-    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, st);
+    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "coulomb");
   return EXX_OK;
+}
+
+// Fit and Coulomb matrices of the fused build on meshes whose every axis has
+// N_i <= 2 (every transfer self-conjugate, refinement off). There the unphased
+// metric S~ and right-hand side Z~ are real, S^m = D S~ D^H and
+// Z^m = D Z~ e^{-iq.r} with D = diag(e^{iq.r_P}), so xi^m = D eta e^{-iq.r} with
+// the real eta = S~^+ Z~; the Bloch-gauge Vb^m is the real
+// sum_G v(G) Re(H_P conj H_Q) over the pairs G <-> -G - 2q of the twisted
+// transform H = FFT(eta e^{-iq.r}). Same quantities as fit_impl + coulomb_impl,
+// in real arithmetic. TF: Gamma storage, TZ: Z~, TX: eta and the transform.
+template <typename TF, typename TZ, typename TX>
+exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, char* ws,
+                            const Layout& L, const void* psi, const void* occ, const int32_t* pts,
+                            void* S, void* V, int32_t* rank, hipStream_t st) {
+  double2* G = (double2*)(ws + L.G);
+  double2* Lf = (double2*)(ws + L.Lf);
+  double2* W = (double2*)(ws + L.W);
+  double2* Sp = (double2*)(ws + L.Sp);
+  int32_t* keep = (int32_t*)(ws + L.keep);
+  void* grid = ws + L.grid;    // Gamma, then eta
+  void* grid2 = ws + L.grid2;  // Z~, then the half-grid transform
+  const long nn = (long)g.ni * g.ni;
+  hipError_t e;
+  hipStream_t ax = h->aux;
+  e = hipEventRecord(h->fork_ev, st);
+  if (e != hipSuccess) return hip_check(h, e, "fork event");
+  e = hipStreamWaitEvent(ax, h->fork_ev, 0);
+  if (e != hipSuccess) return hip_check(h, e, "fork wait");
+  const char* what = nullptr;
+  {
+    PhaseTimer pt(h, PH_GRAM, ax);
+    e = gemm<double, double, double, double>(g.ni, g.ni, g.no, g.nk, A_N, occ, g.no,
+                                             (long)g.ni * g.no, B_C, occ, g.no,
+                                             (long)g.ni * g.no, G, g.ni, nn, 1.0, false, ax);
+  }
+  if (e != hipSuccess) what = "G gemm";
+  if (!what) {
+    PhaseTimer pt(h, PH_METRIC, ax);
+    e = launch_kcorr_real<double, double2>(g, G, S, g.ni, ax);
+    if (e != hipSuccess) what = "S kcorr";
+  }
+  if (!what) {
+    PhaseTimer pt(h, PH_CHOL, ax);
+    e = launch_copy(Lf, (const double2*)S, (long)g.nk * nn, ax);
+    if (e != hipSuccess) what = "copy S";
+    if (!what) {
+      e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax);
+      if (e != hipSuccess) what = "cholesky";
+    }
+  }
+  if (!what) {
+    PhaseTimer pt(h, PH_PINV, ax);
+    e = launch_tri_inv_blocked(g, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
+    if (e != hipSuccess) what = "triangular inverse";
+    if (!what) {
+      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,
+                                               g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
+      if (e != hipSuccess) what = "S+ gemm";
+    }
+  }
+  hipError_t ej = hipEventRecord(h->join_ev, ax);
+  if (what) {
+    if (ej == hipSuccess) (void)hipStreamWaitEvent(st, h->join_ev, 0);
+    return hip_check(h, e, what);
+  }
+  if (ej != hipSuccess) return hip_check(h, ej, "join event");
+  {
+    PhaseTimer pt(h, PH_GAMMA, st);
+    if (std::is_same<TF, double>::value)
+      e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
+                                        psi, g.ng, (long)g.no * g.ng, grid, g.ng,
+                                        (long)g.ni * g.ng, st, h->tile_gamma);
+    else
+      e = cgemm_nn_grid32(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi, g.ng,
+                          (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, st);
+  }
+  if (e != hipSuccess) what = "Gamma gemm";
+  if (!what) {
+    PhaseTimer pt(h, PH_KCORR, st);
+    e = launch_kcorr_real<TF, TZ>(g, grid, grid2, g.ng, st);
+    if (e != hipSuccess) what = "Z kcorr";
+  }
+  hipError_t ew = hipStreamWaitEvent(st, h->join_ev, 0);
+  if (what) return hip_check(h, e, what);
+  if (ew != hipSuccess) return hip_check(h, ew, "join wait");
+  {
+    PhaseTimer pt(h, PH_SOLVE, st);
+    e = dgemm_nn_grid<TZ, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, grid2, g.ng, (long)g.ni * g.ng,
+                              grid, g.ng, (long)g.ni * g.ng, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "solve gemm");
+  {
+    PhaseTimer pt(h, PH_FFT, st);
+    e = launch_fft3d_half<TX, TX>(g, tb, grid, grid2, (long)g.nk * g.ni, h->ncu, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "fft");
+  {
+    PhaseTimer pt(h, PH_COULOMB, st);
+    e = launch_coulomb<TX>(g, tb, grid2, pts, ws + L.cpart, L.nsplit, (double2*)V, true, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "coulomb");
+  return EXX_OK;
+}
+
+// the fused fit + Coulomb of one build in precision prec
+exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
+                       exx_prec prec, const void* psi, const void* occ, const int32_t* pts,
+                       int32_t* rank, hipStream_t st) {
+  void* xi = ws + L.grid2;
+  void* S = ws + L.S2;
+  void* V = ws + L.V2;
+  exx_status s;
+  if (kcorr_real(g) && h->refine == 0) {
+    if (prec == EXX_F64)
+      return fit_coulomb_real<double, double, double>(h, g, tb, ws, L, psi, occ, pts, S, V, rank,
+                                                      st);
+    if (prec == EXX_MIXED)
+      return fit_coulomb_real<double, double, float>(h, g, tb, ws, L, psi, occ, pts, S, V, rank,
+                                                     st);
+    return fit_coulomb_real<float, float, float>(h, g, tb, ws, L, psi, occ, pts, S, V, rank, st);
+  }
+  if (prec == EXX_F64) {
+    s = fit_impl<double, double>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st);
+    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, st);
+  } else if (prec == EXX_MIXED) {
+    s = fit_impl<double, float>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, st);
+  } else {
+    s = fit_impl<float, float>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, st);
+  }
+  return s;
 }
 
 exx_status buildK_impl(exx_context* h, const Geom& g, char* ws, const Layout& L, const void* ao,
@@ -470,21 +602,9 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   char* ws;
   exx_status s = setup(h, cell, prec, true, &g, &tb, &L, &ws, stream);
   if (s != EXX_OK) return s;
-  void* xi = ws + L.grid2;
-  void* S = ws + L.S2;
-  void* V = ws + L.V2;
-  if (prec == EXX_F64) {
-    s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
-  } else if (prec == EXX_MIXED) {
-    s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
-  } else {
-    s = fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
-  }
+  s = fit_coulomb(h, g, tb, ws, L, prec, psi_grid, occ_pts, pts, rank, stream);
   if (s != EXX_OK) return s;
-  return buildK_impl(h, g, ws, L, ao_pts, occ_pts, V, K, Ex, stream);
+  return buildK_impl(h, g, ws, L, ao_pts, occ_pts, ws + L.V2, K, Ex, stream);
 }
 
 exx_status exx_set_refinement(exx_handle_t h, int32_t steps) {
@@ -538,25 +658,9 @@ namespace {
 
 exx_status build_one(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                      exx_prec prec, const exx_batch_item& it, hipStream_t st) {
-  void* xi = ws + L.grid2;
-  void* S = ws + L.S2;
-  void* V = ws + L.V2;
-  exx_status s;
-  if (prec == EXX_F64) {
-    s = fit_impl<double, double>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
-                                 st);
-    if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, it.pts, V, st);
-  } else if (prec == EXX_MIXED) {
-    s = fit_impl<double, float>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
-                                st);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, it.pts, V, st);
-  } else {
-    s = fit_impl<float, float>(h, g, tb, ws, L, it.psi_grid, it.occ_pts, it.pts, xi, S, it.rank,
-                               st);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, it.pts, V, st);
-  }
+  exx_status s = fit_coulomb(h, g, tb, ws, L, prec, it.psi_grid, it.occ_pts, it.pts, it.rank, st);
   if (s != EXX_OK) return s;
-  return buildK_impl(h, g, ws, L, it.ao_pts, it.occ_pts, V, it.K, it.Ex, st);
+  return buildK_impl(h, g, ws, L, it.ao_pts, it.occ_pts, ws + L.V2, it.K, it.Ex, st);
 }
 
 void tune_key(const Geom& g, exx_prec prec, long* key) {

@@ -206,6 +206,11 @@ hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long l
                           bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                           hipStream_t st);
 
+// real form: C[b] = Re(A[b]) B[b], A (M x K) c128, B (K x N) real TB, C real TC
+template <typename TB, typename TC>
+hipError_t dgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                         const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                         hipStream_t st);
 // C[b] = C[b] + sign * A[b] * B[b] (sign = +1 or -1), same operands as zgemm_nn_grid
 // (tile 22, no conjugation); used by the iterative refinement of the fit
 template <typename TB, typename TC>
@@ -234,6 +239,12 @@ template <typename T>
 hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* out, int ncol,
                         const int32_t* pts, bool cols_are_points, hipStream_t st);
 bool kcorr_supported(const Geom& g);
+// meshes whose every axis has N_i <= 2 (all transfers self-conjugate)
+bool kcorr_real(const Geom& g);
+// unphased real k-correlation: out[m][P][c] = sum_n in[n][P][c] conj in[n+m][P][c]
+// (real there); TO real for grid columns, double2 (imaginary part 0) for points
+template <typename T, typename TO>
+hipError_t launch_kcorr_real(const Geom& g, const void* in, void* out, int ncol, hipStream_t st);
 
 // dst[0:n] = src[0:n] (a kernel, so that captured sequences hold no copy nodes)
 hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st);
@@ -252,11 +263,18 @@ template <typename T>
 hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
                         int ncu, hipStream_t st);
 bool fft_supported(const Geom& g, bool fp64);
+// real path: twisted FFT of the real fit eta (storage TI), keeping the z
+// frequencies below fft_half_z(g) = n3/2 + 1: out [nfun][n1][n2][hz] complex T
+template <typename TI, typename T>
+hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
+                             int ncu, hipStream_t st);
+int fft_half_z(const Geom& g);
 
-// Coulomb contraction: V^m (Bloch gauge) from F^m (storage T) on the FP64 matrix cores
+// Coulomb contraction: V^m (Bloch gauge) from F^m (storage T) on the FP64 matrix cores;
+// half: F is the real path's half-grid transform (launch_fft3d_half)
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
-                          void* partial, int nsplit, double2* V, hipStream_t st);
+                          void* partial, int nsplit, double2* V, bool half, hipStream_t st);
 size_t coulomb_partial_bytes(const Geom& g, int nsplit);
 int coulomb_nsplit(const Geom& g);
 

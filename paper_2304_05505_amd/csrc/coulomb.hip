@@ -55,6 +55,46 @@ __global__ __launch_bounds__(256) void coulomb_vtab_kernel(double* __restrict__ 
   vt[(long)m * a.ng + g] = kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
 }
 
+// Real path: the kernel table over the kept half grid (z index g3 < hz of the
+// [x][y][hz] layout) with the pairing weights of G <-> G' = -G - 2 q_m: 2 where
+// the partner lies outside the kept set or after G, 1 where G' = G, 0 for
+// partners already counted and for z columns past the transfer's half range.
+__global__ __launch_bounds__(256) void coulomb_vtab_half_kernel(double* __restrict__ vt,
+                                                                CoulArgs a, int hz) {
+  const long gh = (long)blockIdx.x * 256 + threadIdx.x;
+  const int m = blockIdx.y;
+  const long ngh = (long)a.n[0] * a.n[1] * hz;
+  if (gh >= ngh) return;
+  const int g1 = (int)(gh / ((long)a.n[1] * hz)), g2 = (int)((gh / hz) % a.n[1]),
+            g3 = (int)(gh % hz);
+  const int mm[3] = {m / (a.N[1] * a.N[2]), (m / a.N[2]) % a.N[1], m % a.N[2]};
+  const int n1 = a.n[0], n2 = a.n[1], n3 = a.n[2];
+  const int h3 = mm[2] == 0 ? n3 / 2 + 1 : (n3 + 1) / 2;
+  int w = 0;
+  if (g3 < h3) {
+    const int p3 = ((-g3 - mm[2]) % n3 + n3) % n3;
+    if (p3 != g3) {
+      w = 2;
+    } else {
+      const int p1 = ((-g1 - mm[0]) % n1 + n1) % n1, p2 = ((-g2 - mm[1]) % n2 + n2) % n2;
+      const long lin = (long)g1 * n2 + g2, plin = (long)p1 * n2 + p2;
+      w = lin < plin ? 2 : (lin == plin ? 1 : 0);
+    }
+  }
+  double v = 0.0;
+  if (w) {
+    const int gc[3] = {g1, g2, g3};
+    double kk = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+      const int kap = wrap_sym(a.N[ax] * gc[ax] + mm[ax], a.N[ax] * a.n[ax]);
+      const double K = kap * (2.0 * M_PI / (a.N[ax] * a.L[ax]));
+      kk += K * K;
+    }
+    v = kk > 0.0 ? w * 4.0 * M_PI / kk : 0.0;
+  }
+  vt[(long)m * ngh + gh] = v;
+}
+
 // One wave computes one 32 x 32 wave tile (2 x 2 blocks of 16 x 16) of the
 // lower triangle for one transfer m and one grid chunk [g0, g1). MASK selects
 // the blocks that are computed and stored (bit 2 i + j for block row i, column
@@ -65,7 +105,9 @@ __global__ __launch_bounds__(256) void coulomb_vtab_kernel(double* __restrict__ 
 // VEC (FP32 storage, even N_g): a lane's two grid values of a row are one
 // aligned 16-byte load, so a load instruction touches each row's cache line
 // once. stage: this wave's 3 x 256 doubles of LDS (epilogue staging).
-template <typename T, int MASK, bool VEC, int NPF>
+// RE: accumulate only Re(X conj Y) = Re X Re Y + Im X Im Y (two MFMAs into one
+// accumulator; the real path, whose Coulomb matrices are real).
+template <typename T, int MASK, bool VEC, int NPF, bool RE = false>
 __device__ __forceinline__ void coulomb_wave_tile(const cplx<T>* __restrict__ Fm,
                                                   const double* __restrict__ vm,
                                                   double2* __restrict__ out, const CoulArgs& a,
@@ -150,19 +192,23 @@ __device__ __forceinline__ void coulomb_wave_tile(const cplx<T>* __restrict__ Fm
           const cplx<T> y = DIAG ? fx[sl][j][t] : fy[sl][j][t];
           yr[j] = (double)y.x;
           yi[j] = (double)y.y;
-          ys[j] = yr[j] - yi[j];
+          if (!RE) ys[j] = yr[j] - yi[j];
         }
 #pragma unroll
         for (int i = 0; i < MW; ++i) {
           if (!XU[i]) continue;
           const double xr = (double)fx[sl][i][t].x * vv, xi = (double)fx[sl][i][t].y * vv;
-          const double xs = xr + xi;
+          const double xs = RE ? 0.0 : xr + xi;
 #pragma unroll
           for (int j = 0; j < MW; ++j) {
             if (!(MASK & (1 << (2 * i + j)))) continue;
             t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr[j], t1[i][j], 0, 0, 0);
-            t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi[j], t2[i][j], 0, 0, 0);
-            t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, ys[j], t3[i][j], 0, 0, 0);
+            if (RE) {
+              t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi[j], t1[i][j], 0, 0, 0);
+            } else {
+              t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi[j], t2[i][j], 0, 0, 0);
+              t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, ys[j], t3[i][j], 0, 0, 0);
+            }
           }
         }
       }
@@ -189,15 +235,22 @@ __device__ __forceinline__ void coulomb_wave_tile(const cplx<T>* __restrict__ Fm
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         s1[v * 64 + lane] = t1[i][j][v];
-        s2[v * 64 + lane] = t2[i][j][v];
-        s3[v * 64 + lane] = t3[i][j][v];
+        if (!RE) {
+          s2[v * 64 + lane] = t2[i][j][v];
+          s3[v * 64 + lane] = t3[i][j][v];
+        }
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double x1 = s1[v * 64 + lane], x2 = s2[v * 64 + lane], x3 = s3[v * 64 + lane];
         const int P = P0 + 16 * i + 4 * v + gq;
         const int Q = Q0 + 16 * j + li;
-        if (P < a.ni && Q < a.ni) out[(long)P * a.ni + Q] = make_double2(x1 + x2, x3 - x1 + x2);
+        const double x1 = s1[v * 64 + lane];
+        if (RE) {
+          if (P < a.ni && Q < a.ni) out[(long)P * a.ni + Q] = make_double2(x1, 0.0);
+        } else {
+          const double x2 = s2[v * 64 + lane], x3 = s3[v * 64 + lane];
+          if (P < a.ni && Q < a.ni) out[(long)P * a.ni + Q] = make_double2(x1 + x2, x3 - x1 + x2);
+        }
       }
     }
 }
@@ -221,6 +274,7 @@ __device__ __forceinline__ void coulomb_work(long w, const CoulArgs& a, int& m, 
 // FP64 storage: 64 x 64 tiles of 2 x 2 waves, whose waves share the rows of F
 // through L1 (the redundant upper-triangle blocks of diagonal tiles are
 // computed; the reduction reads only P >= Q).
+template <bool RE>
 __global__ __launch_bounds__(256, 2) void coulomb_kernel_f64(const double2* __restrict__ F,
                                                           const double* __restrict__ vt,
                                                           double2* __restrict__ part, CoulArgs a,
@@ -235,7 +289,7 @@ __global__ __launch_bounds__(256, 2) void coulomb_kernel_f64(const double2* __re
   const long g0 = (long)s * a.chunk;
   const long g1 = min((long)a.ng, g0 + a.chunk);
   __shared__ double stage[4 * 3 * 64 * 4];
-  coulomb_wave_tile<double, 0xF, false, 2>(
+  coulomb_wave_tile<double, 0xF, false, 2, RE>(
       F + (long)m * a.ni * a.ng, vt + (long)m * a.ng,
       part + ((long)m * a.nsplit + s) * a.ni * a.ni, a, P0, Q0, g0, g1,
       stage + wave * 3 * 64 * 4);
@@ -245,7 +299,7 @@ __global__ __launch_bounds__(256, 2) void coulomb_kernel_f64(const double2* __re
 // blocks that hold needed entries are computed (the all-upper block of a
 // diagonal tile and block rows past N_ISDF are skipped) without leaving a SIMD
 // of a multi-wave workgroup short of waves.
-template <bool VEC>
+template <bool VEC, bool RE>
 __global__ __launch_bounds__(64) void coulomb_kernel_f32(const float2* __restrict__ F,
                                                       const double* __restrict__ vt,
                                                       double2* __restrict__ part, CoulArgs a,
@@ -265,14 +319,14 @@ __global__ __launch_bounds__(64) void coulomb_kernel_f32(const float2* __restric
   const bool row1 = P0 + 16 < a.ni;  // block row 1 holds rows below N_ISDF
   if (ti != tj) {
     if (row1)
-      coulomb_wave_tile<float, 0xF, VEC, NPF>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+      coulomb_wave_tile<float, 0xF, VEC, NPF, RE>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
     else
-      coulomb_wave_tile<float, 0x3, VEC, NPF>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+      coulomb_wave_tile<float, 0x3, VEC, NPF, RE>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
   } else {
     if (row1)
-      coulomb_wave_tile<float, 0xD, VEC, NPF>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+      coulomb_wave_tile<float, 0xD, VEC, NPF, RE>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
     else
-      coulomb_wave_tile<float, 0x1, VEC, NPF>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+      coulomb_wave_tile<float, 0x1, VEC, NPF, RE>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
   }
 }
 
@@ -281,6 +335,7 @@ struct ReduceArgs {
   int n[3];
   int N[3];
   int ni, nsplit;
+  int real;
   double scale;
 };
 
@@ -305,7 +360,9 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __re
   if (!lower) sy = -sy;
   sx *= a.scale;
   sy *= a.scale;
-  if (m) {
+  if (a.real) {
+    sy = 0.0;  // the real path's partials are already the Bloch-gauge matrix
+  } else if (m) {
     const int m1 = m / (a.N[1] * a.N[2]), m2 = (m / a.N[2]) % a.N[1], m3 = m % a.N[2];
     const int n23 = a.n[1] * a.n[2];
     const int gp = pts[P], gq = pts[Q];
@@ -351,42 +408,58 @@ size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
   return partial_only(g, nsplit) + (size_t)g.nk * g.ng * sizeof(double);
 }
 
+// half = false: F is [N_k][N_ISDF][N_g] (complex path). half = true (real
+// path): F is [N_k][N_ISDF][n1 n2 hz] with hz = n3/2 + 1, the contraction takes
+// the real part with the pairing weights, and the reduction applies no phase.
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
-                          void* partial, int nsplit, double2* V, hipStream_t st) {
+                          void* partial, int nsplit, double2* V, bool half, hipStream_t st) {
   CoulArgs a;
   for (int i = 0; i < 3; ++i) {
     a.L[i] = g.L[i];
     a.n[i] = g.n[i];
     a.N[i] = g.N[i];
   }
-  a.ng = g.ng;
+  const int hz = g.n[2] / 2 + 1;
+  a.ng = half ? g.n[0] * g.n[1] * hz : g.ng;
   a.ni = g.ni;
   a.nk = g.nk;
   a.nsplit = nsplit;
-  a.chunk = (int)((((long)g.ng + nsplit - 1) / nsplit + CALIGN - 1) / CALIGN * CALIGN);
+  a.chunk = (int)((((long)a.ng + nsplit - 1) / nsplit + CALIGN - 1) / CALIGN * CALIGN);
   // FP64 storage: 64 x 64 workgroup tiles; FP32 storage: 32 x 32 wave tiles
   const int tw = sizeof(T) == 8 ? 2 * WTILE : WTILE;
   const int nt = (g.ni + tw - 1) / tw;
   a.ntile = nt * (nt + 1) / 2;
-  if ((long)g.ni * g.ng >= 0x7fffffffL) return hipErrorInvalidValue;
+  if ((long)g.ni * a.ng >= 0x7fffffffL) return hipErrorInvalidValue;
   const long nwork = (long)a.ntile * g.nk * nsplit;
   const long pad = (nwork + 7) / 8 * 8;
   double* vt = (double*)((char*)partial + partial_only(g, nsplit));
-  hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), g.nk), dim3(256), 0,
-                     st, vt, a);
+  if (half)
+    hipLaunchKernelGGL(coulomb_vtab_half_kernel, dim3((unsigned)((a.ng + 255) / 256), g.nk),
+                       dim3(256), 0, st, vt, a, hz);
+  else
+    hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), g.nk), dim3(256),
+                       0, st, vt, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if constexpr (sizeof(T) == 8) {
-    hipLaunchKernelGGL(coulomb_kernel_f64, dim3((unsigned)pad), dim3(256), 0, st,
-                       (const double2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
-  } else if (g.ng % 2 == 0) {
-    hipLaunchKernelGGL(coulomb_kernel_f32<true>, dim3((unsigned)pad), dim3(64), 0, st,
-                       (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
-  } else {
-    hipLaunchKernelGGL(coulomb_kernel_f32<false>, dim3((unsigned)pad), dim3(64), 0, st,
-                       (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+  const bool vec = a.ng % 2 == 0;
+#define EXX_COUL(RE)                                                                            \
+  if constexpr (sizeof(T) == 8) {                                                               \
+    hipLaunchKernelGGL(coulomb_kernel_f64<RE>, dim3((unsigned)pad), dim3(256), 0, st,            \
+                       (const double2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);  \
+  } else if (vec) {                                                                             \
+    hipLaunchKernelGGL((coulomb_kernel_f32<true, RE>), dim3((unsigned)pad), dim3(64), 0, st,     \
+                       (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);   \
+  } else {                                                                                      \
+    hipLaunchKernelGGL((coulomb_kernel_f32<false, RE>), dim3((unsigned)pad), dim3(64), 0, st,    \
+                       (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);   \
   }
+  if (half) {
+    EXX_COUL(true)
+  } else {
+    EXX_COUL(false)
+  }
+#undef EXX_COUL
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   ReduceArgs r;
@@ -397,6 +470,7 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   }
   r.ni = g.ni;
   r.nsplit = nsplit;
+  r.real = half ? 1 : 0;
   r.scale = g.omega / ((double)g.ng * (double)g.ng);
   const long nn = (long)g.ni * g.ni;
   hipLaunchKernelGGL(coulomb_reduce_kernel, dim3((unsigned)((nn + 255) / 256), g.nk), dim3(256), 0,
@@ -405,8 +479,8 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
 }
 
 template hipError_t launch_coulomb<double>(const Geom&, const Tables&, const void*, const int32_t*,
-                                           void*, int, double2*, hipStream_t);
+                                           void*, int, double2*, bool, hipStream_t);
 template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void*, const int32_t*,
-                                          void*, int, double2*, hipStream_t);
+                                          void*, int, double2*, bool, hipStream_t);
 
 }  // namespace exx

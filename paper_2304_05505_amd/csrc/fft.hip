@@ -412,6 +412,67 @@ __global__ __launch_bounds__(NT2) void fft_x_kernel(cplx<T>* __restrict__ data, 
   }
 }
 
+// Real path (meshes whose transfers are all self-conjugate): the input is the
+// real fit eta_P(r) of transfer m, the transform wanted is
+// H_P(G) = sum_r eta_P(r) e^{-i (G + q_m).r}, and only the z frequencies
+// g3 < hz = n3/2 + 1 are kept (the others follow from the pairing
+// H(G) = conj H(-G - 2 q_m)). Pass 1 loads a (function, x) plane times the
+// twist e^{-i q_m.r}, transforms all z lines, then the y lines of the first hz
+// z columns only, and writes [function][x][y][hz].
+struct TwistArgs {
+  const double2* root[3];  // e^{-2 pi i t / (N_a n_a)}
+  int n[3], N[3];
+  int ni;
+};
+
+template <typename TI, typename T>
+__global__ __launch_bounds__(NT1) void fft_yz_half_kernel(const TI* __restrict__ in,
+                                                          cplx<T>* __restrict__ out, Plan1 py,
+                                                          Plan1 pz, int hz, TwistArgs ta,
+                                                          const cplx<T>* __restrict__ twy,
+                                                          const cplx<T>* __restrict__ twz) {
+  extern __shared__ char smem_raw[];
+  const int n2 = py.n, n3 = pz.n, np = n2 * n3;
+  cplx<T>* buf = (cplx<T>*)smem_raw;
+  cplx<T>* ty = buf + np;
+  cplx<T>* tz = ty + n2;
+  cplx<T>* ry = tz + n3;
+  cplx<T>* rz = ry + n2;
+  const long p = blockIdx.x;  // plane = function * n1 + x
+  const int n1 = ta.n[0];
+  const long f = p / n1;
+  const int g1 = (int)(p % n1);
+  const int m = (int)(f / ta.ni);
+  const int m1 = m / (ta.N[1] * ta.N[2]), m2 = (m / ta.N[2]) % ta.N[1], m3 = m % ta.N[2];
+  const double2 c0 = ta.root[0][(m1 * g1) % (ta.N[0] * n1)];
+  for (int e = threadIdx.x; e < n2; e += NT1) {
+    ty[e] = twy[e];
+    const double2 r = ta.root[1][(m2 * e) % (ta.N[1] * n2)];
+    ry[e] = mk<T>((T)(c0.x * r.x - c0.y * r.y), (T)(c0.x * r.y + c0.y * r.x));
+  }
+  for (int e = threadIdx.x; e < n3; e += NT1) {
+    tz[e] = twz[e];
+    const double2 r = ta.root[2][(m3 * e) % (ta.N[2] * n3)];
+    rz[e] = mk<T>((T)r.x, (T)r.y);
+  }
+  __syncthreads();
+  const TI* src = in + p * np;
+  for (int e = threadIdx.x; e < np; e += NT1) {
+    const int y = e / n3, z = e - y * n3;
+    const cplx<T> w = cmul<T>(ry[y], rz[z]);
+    const T v = (T)src[e];
+    buf[e] = mk<T>(v * w.x, v * w.y);
+  }
+  __syncthreads();
+  fft_lines<T, NT1, FFT_MAXPTS, false>(buf, pz, n2, 1, n3, tz);
+  fft_lines<T, NT1, FFT_MAXPTS, true>(buf, py, hz, n3, 1, ty);
+  cplx<T>* dst = out + p * ((long)n2 * hz);
+  for (int e = threadIdx.x; e < n2 * hz; e += NT1) {
+    const int y = e / hz, z = e - y * hz;
+    dst[e] = buf[y * n3 + z];
+  }
+}
+
 template <typename T>
 const cplx<T>* twp(const Tables& tb, int a);
 template <>
@@ -436,7 +497,7 @@ bool fft_supported(const Geom& g, bool fp64) {
   return true;
 }
 
-// Raise the dynamic-LDS limit of the four FFT kernels to what grids up to the
+// Raise the dynamic-LDS limit of the FFT plane and line kernels to what grids up to the
 // supported maximum need. Called once per process before any launch (and
 // therefore never inside a captured launch sequence).
 static hipError_t fft_attributes() {
@@ -457,6 +518,14 @@ static hipError_t fft_attributes() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)fft_x_kernel<float>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, l2f);
+  const int lhd = (FFT_MAXPTS + 4 * 128) * (int)sizeof(double2);
+  const int lhf = (FFT_MAXPTS + 4 * 128) * (int)sizeof(float2);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)fft_yz_half_kernel<double, double>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lhd);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)fft_yz_half_kernel<float, float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lhf);
   done = e;
   return e;
 }
@@ -508,6 +577,47 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
                      nwork, px, np, nblk, twp<T>(tb, 0));
   return hipGetLastError();
 }
+
+int fft_half_z(const Geom& g) { return g.n[2] / 2 + 1; }
+
+template <typename TI, typename T>
+hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
+                             int ncu, hipStream_t st) {
+  const int maxr = sizeof(T) == 8 ? 5 : 16;
+  Plan1 px = plan_for(g.n[0], maxr), py = plan_for(g.n[1], maxr), pz = plan_for(g.n[2], maxr);
+  const int hz = fft_half_z(g);
+  const int np = g.n[1] * g.n[2], nph = g.n[1] * hz;
+  const size_t lds1 = (size_t)(np + 2 * g.n[1] + 2 * g.n[2]) * sizeof(cplx<T>);
+  const size_t lds2 = (size_t)(g.n[0] * FFT_CB + g.n[0]) * sizeof(cplx<T>);
+  const long nplanes = nfun * g.n[0];
+  const int nblk = (nph + FFT_CB - 1) / FFT_CB;
+  TwistArgs ta;
+  for (int a = 0; a < 3; ++a) {
+    ta.root[a] = tb.root[a];
+    ta.n[a] = g.n[a];
+    ta.N[a] = g.N[a];
+  }
+  ta.ni = g.ni;
+  hipLaunchKernelGGL((fft_yz_half_kernel<TI, T>), dim3((unsigned)nplanes), dim3(NT1), lds1, st,
+                     (const TI*)in, (cplx<T>*)out, py, pz, hz, ta, twp<T>(tb, 1), twp<T>(tb, 2));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (sizeof(T) == 8) {
+    hipLaunchKernelGGL(fft_x1_kernel<T>, dim3((unsigned)(nfun * nblk)), dim3(NT2), lds2, st,
+                       (cplx<T>*)out, px, nph, nblk, twp<T>(tb, 0));
+    return hipGetLastError();
+  }
+  const long nwork = nfun * nblk;
+  const long wpc2 = std::max<long>(1, (160L * 1024) / (long)lds2);
+  const long grid2 = std::min<long>(nwork, (long)ncu * std::min<long>(wpc2, 8) * 2);
+  hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)grid2), dim3(NT2), lds2, st, (cplx<T>*)out,
+                     nwork, px, nph, nblk, twp<T>(tb, 0));
+  return hipGetLastError();
+}
+template hipError_t launch_fft3d_half<double, double>(const Geom&, const Tables&, const void*,
+                                                      void*, long, int, hipStream_t);
+template hipError_t launch_fft3d_half<float, float>(const Geom&, const Tables&, const void*, void*,
+                                                    long, int, hipStream_t);
 
 template hipError_t launch_fft3d<double>(const Geom&, const Tables&, const void*, void*, long,
                                          int, hipStream_t);

@@ -207,6 +207,39 @@ __global__ __launch_bounds__(256) void kcorr_kernel(const cplx<T>* in, cplx<T>* 
   }
 }
 
+// Meshes whose every axis has N_i <= 2: every transfer m satisfies 2m = 0 on
+// the mesh, so the unphased sums sum_n in[n] o conj in[n+m] are real (the
+// conjugate sum is the same sum with n relabelled n + m). This kernel writes
+// that real value: to a real array (grid columns) or as a complex number with
+// zero imaginary part (point columns, for the metric).
+template <typename T, typename TO, int N1, int N2, int N3>
+__global__ __launch_bounds__(256) void kcorr_real_kernel(const cplx<T>* __restrict__ in,
+                                                         TO* __restrict__ out, int ni, int ncol) {
+  constexpr int NK = N1 * N2 * N3;
+  const long total = (long)ni * ncol;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  cplx<T> a[NK];
+#pragma unroll
+  for (int n = 0; n < NK; ++n) a[n] = in[(long)n * total + idx];
+  if (NK > 1) {
+    kdft3<T, N1, N2, N3>(a);
+#pragma unroll
+    for (int n = 0; n < NK; ++n) a[n] = mk<T>(a[n].x * a[n].x + a[n].y * a[n].y, 0);
+    kdft3<T, N1, N2, N3>(a);
+  } else {
+    a[0] = mk<T>(a[0].x * a[0].x + a[0].y * a[0].y, 0);
+  }
+  const T inv = (T)1 / (T)NK;
+#pragma unroll
+  for (int m = 0; m < NK; ++m) {
+    if constexpr (sizeof(TO) == 2 * sizeof(T))
+      out[(long)m * total + idx] = mk<T>(a[m].x * inv, 0);
+    else
+      out[(long)m * total + idx] = (TO)(a[m].x * inv);
+  }
+}
+
 #define EXX_KMESH_LIST(X) \
   X(1, 1, 1)              \
   X(2, 2, 2)              \
@@ -248,6 +281,36 @@ hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* o
 #undef EXX_KLAUNCH
   return hipErrorInvalidValue;
 }
+bool kcorr_real(const Geom& g) { return g.N[0] <= 2 && g.N[1] <= 2 && g.N[2] <= 2; }
+
+// unphased real k-correlation (meshes with every N_i <= 2): grid columns to a
+// real array of TO, or point columns (ncol = N_ISDF) to a complex matrix
+template <typename T, typename TO>
+hipError_t launch_kcorr_real(const Geom& g, const void* in, void* out, int ncol, hipStream_t st) {
+  long total = (long)g.ni * ncol;
+  dim3 grid((unsigned)((total + 255) / 256));
+#define EXX_KRLAUNCH(a, b, c)                                                                    \
+  if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                               \
+    hipLaunchKernelGGL((kcorr_real_kernel<T, TO, a, b, c>), grid, dim3(256), 0, st,              \
+                       (const cplx<T>*)in, (TO*)out, g.ni, ncol);                                 \
+    return hipGetLastError();                                                                    \
+  }
+  EXX_KRLAUNCH(1, 1, 1)
+  EXX_KRLAUNCH(2, 2, 2)
+  EXX_KRLAUNCH(2, 1, 1)
+  EXX_KRLAUNCH(1, 2, 1)
+  EXX_KRLAUNCH(1, 1, 2)
+  EXX_KRLAUNCH(2, 2, 1)
+#undef EXX_KRLAUNCH
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_kcorr_real<double, double>(const Geom&, const void*, void*, int,
+                                                      hipStream_t);
+template hipError_t launch_kcorr_real<float, float>(const Geom&, const void*, void*, int,
+                                                    hipStream_t);
+template hipError_t launch_kcorr_real<double, double2>(const Geom&, const void*, void*, int,
+                                                       hipStream_t);
+
 template hipError_t launch_kcorr<double>(const Geom&, const Tables&, const void*, void*, int,
                                          const int32_t*, bool, hipStream_t);
 template hipError_t launch_kcorr<float>(const Geom&, const Tables&, const void*, void*, int,

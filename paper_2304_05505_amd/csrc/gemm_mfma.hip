@@ -279,6 +279,102 @@ __global__ __launch_bounds__(256) void cgemm_nn_mfma32(int M, int N, int K, int 
     }
 }
 
+// Real form for the fit solve of meshes whose transfers are all self-conjugate:
+// C[b] = Re(A[b]) B[b] with A (M x K) stored complex (its imaginary part is
+// zero there) and real B (K x N, storage TB) and C (M x N, storage TC). One
+// FP64 MFMA per block and k-step. Wave tile 4 x 4 blocks (64 x 64); the four
+// waves of a workgroup take consecutive column strips of one 64-row band, so
+// they share the A rows through L1. Same register pipeline as zgemm_nn_mfma.
+template <typename TB, typename TC>
+__global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nrt, long ntiles,
+                                                     long ntiles_pad, const double2* __restrict__ A,
+                                                     long lda, long sA, const TB* __restrict__ B,
+                                                     long ldb, long sB, TC* __restrict__ C,
+                                                     long ldc, long sC) {
+  constexpr int WM = 4, WN = 4;
+  const long t = xcd_remap(blockIdx.x, ntiles_pad);
+  if (t >= ntiles) return;
+  const int rt = (int)(t % nrt);
+  const long ct = t / nrt;
+  const long b = blockIdx.y;
+  const double* Ar = (const double*)(A + b * sA);  // real parts at even offsets
+  B += b * sB;
+  C += b * sC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = rt * (WM * 16);
+  const long col0 = ct * (4 * WN * 16) + wave * (WN * 16);
+  d4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  constexpr int NPF = 3;
+  double fa[NPF][WM];
+  TB fb[NPF][WN];
+  unsigned aoff[WM], boff[WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    const int r = row0 + i * 16 + li;
+    aoff[i] = (unsigned)(2 * (r < M ? r : M - 1) * lda);
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long c = col0 + j * 16 + li;
+    boff[j] = (unsigned)(c < N ? c : N - 1);
+  }
+  const unsigned ldb32 = (unsigned)ldb;
+  auto load = [&](int k0, double* xa, TB* xb) {
+    const int k = k0 + lk;
+    const unsigned kc = (unsigned)(k < K ? k : K - 1);
+#pragma unroll
+    for (int i = 0; i < WM; ++i) xa[i] = Ar[aoff[i] + 2 * kc];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) xb[j] = B[kc * ldb32 + boff[j]];
+  };
+#pragma unroll
+  for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
+  __builtin_amdgcn_s_waitcnt(0);  // as in zgemm_nn_mfma
+  const int niter = (K + 4 * NPF - 1) / (4 * NPF);
+  for (int it = 0; it < niter; ++it) {
+#pragma unroll
+    for (int s = 0; s < NPF; ++s) {
+      const bool kin = 4 * (it * NPF + s) + lk < K;
+      double bv[WN];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) bv[j] = (double)fb[s][j];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const double av = kin ? fa[s][i] : 0.0;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = mfma64(av, bv[j], acc[i][j]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      load(4 * ((it + 1) * NPF + s), fa[s], fb[s]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // register v of a lane holds row 4 v + lane/16, column lane%16 of a block;
+  // stored through this wave's LDS slice (see zgemm_nn_mfma)
+  __shared__ double stage[4][64 * 4];
+  typedef __attribute__((address_space(3))) volatile double lds_f64;
+  lds_f64* sv = (lds_f64*)stage[wave];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sv[v * 64 + lane] = acc[i][j][v];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double x = sv[v * 64 + lane];
+        const int r = row0 + i * 16 + 4 * v + lk;
+        const long c = col0 + j * 16 + li;
+        if (r < M && c < N) C[(long)r * ldc + c] = (TC)x;
+      }
+    }
+}
+
 template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC = 0>
 hipError_t run_nn(int M, int N, int K, int batch, const void* A, long lda, long sA, const void* B,
                   long ldb, long sB, void* C, long ldc, long sC, hipStream_t st) {
@@ -346,6 +442,31 @@ hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long l
                        sB, (float2*)C, ldc, sC);
   return hipGetLastError();
 }
+
+template <typename TB, typename TC>
+hipError_t dgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                         const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                         hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (!offsets_fit(M, N, K, 2 * lda, ldb)) return hipErrorInvalidValue;
+  const int nrt = (M + 63) / 64;
+  const long nct = ((long)N + 255) / 256;
+  const long ntiles = nrt * nct;
+  const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
+  hipLaunchKernelGGL((dgemm_nn_mfma<TB, TC>), dim3((unsigned)pad, batch), dim3(256), 0, st, M, N, K,
+                     nrt, ntiles, pad, (const double2*)A, lda, sA, (const TB*)B, ldb, sB, (TC*)C,
+                     ldc, sC);
+  return hipGetLastError();
+}
+template hipError_t dgemm_nn_grid<double, double>(int, int, int, int, const void*, long, long,
+                                                  const void*, long, long, void*, long, long,
+                                                  hipStream_t);
+template hipError_t dgemm_nn_grid<double, float>(int, int, int, int, const void*, long, long,
+                                                 const void*, long, long, void*, long, long,
+                                                 hipStream_t);
+template hipError_t dgemm_nn_grid<float, float>(int, int, int, int, const void*, long, long,
+                                                const void*, long, long, void*, long, long,
+                                                hipStream_t);
 
 template <typename TB, typename TC>
 hipError_t zgemm_nn_grid_acc(int M, int N, int K, int batch, const void* A, long lda, long sA,
