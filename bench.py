@@ -45,28 +45,51 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def real_path(cell):
+    """The fused build's real path runs on meshes whose every axis has N_i <= 2."""
+    return all(n <= 2 for n in cell.kmesh)
+
+
 def algorithmic_work(cell, n_isdf, prec):
     """Per-launch algorithmic flops / bytes of each phase (one K-build).
 
     Flops count the real multiply-adds of the product form each kernel uses:
-    the FP64-matrix-core products (fit solve, Gamma in FP64 and mixed, the
-    Coulomb contraction) use Gauss's three-product form, 6 flops per complex
-    multiply-add; the FP32-matrix-core Gamma of the FP32 path and the small K
-    GEMMs use four real products, 8 flops. The Coulomb contraction forms the
-    lower triangle only (N_ISDF^2/2 pairs).
+    complex products on the FP64 matrix cores use Gauss's three-product form, 6
+    flops per complex multiply-add; the FP32-matrix-core Gamma of the FP32 path
+    and the small K GEMMs use four real products, 8 flops. The Coulomb
+    contraction forms the lower triangle only (N_ISDF^2/2 pairs).
+    On the real path (every k-mesh axis <= 2) the solve is a real GEMM (2 flops
+    per multiply-add), Z~ and eta are real arrays, the FFT writes the kept half
+    grid of n1 n2 (n3/2 + 1) points and the Coulomb contraction takes
+    Re(X conj Y) (two real products, 4 flops) over that half grid.
     """
     nk, ng, no, na = cell.N_k, cell.N_g, cell.n_occ, cell.n_ao
     ni = n_isdf
-    cs = 16 if prec == "f64" else 8
-    cg = 8.0 if prec == "f32" else 6.0  # flops per complex multiply-add of the Gamma GEMM
-    return {
-        "gamma": ("flop", cg * nk * ni * no * ng),
-        "kcorr": ("byte", 2.0 * nk * ni * ng * cs),
-        "solve": ("flop", 6.0 * nk * ni * ni * ng),
-        "fft": ("byte", 2.0 * nk * ni * ng * cs),
-        "coulomb": ("flop", 3.0 * nk * ni * ni * ng),
-        "K": ("flop", 8.0 * nk * (na * ni * ni + na * na * ni)),
-    }
+    cs = 16 if prec == "f64" else 8           # complex Gamma/Z (f64, mixed: Gamma c128)
+    cg = 8.0 if prec == "f32" else 6.0        # flops per complex multiply-add of the Gamma GEMM
+    work = {"gamma": ("flop", cg * nk * ni * no * ng),
+            "K": ("flop", 8.0 * nk * (na * ni * ni + na * na * ni))}
+    if real_path(cell):
+        n1, n2, n3 = cell.grid
+        ngh = n1 * n2 * (n3 // 2 + 1)
+        gam = 8 if prec == "f32" else 16      # Gamma element (complex)
+        zr = 4 if prec == "f32" else 8        # Z~ element (real)
+        xr = 8 if prec == "f64" else 4        # eta element (real)
+        xc = 16 if prec == "f64" else 8       # transform element (complex)
+        work.update({
+            "kcorr": ("byte", nk * ni * ng * (gam + zr)),
+            "solve": ("flop", 2.0 * nk * ni * ni * ng),
+            "fft": ("byte", nk * ni * (ng * xr + ngh * xc)),
+            "coulomb": ("flop", 2.0 * nk * ni * ni * ngh),
+        })
+    else:
+        work.update({
+            "kcorr": ("byte", 2.0 * nk * ni * ng * cs),
+            "solve": ("flop", 6.0 * nk * ni * ni * ng),
+            "fft": ("byte", 2.0 * nk * ni * ng * cs),
+            "coulomb": ("flop", 3.0 * nk * ni * ni * ng),
+        })
+    return work
 
 
 # HBM traffic of the dominant kernel of each phase at this workload, from two

@@ -303,6 +303,9 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
 // sum_G v(G) Re(H_P conj H_Q) over the pairs G <-> -G - 2q of the twisted
 // transform H = FFT(eta e^{-iq.r}). Same quantities as fit_impl + coulomb_impl,
 // in real arithmetic. TF: Gamma storage, TZ: Z~, TX: eta and the transform.
+// The factorisation chain of the metric (many short launches) runs on the
+// caller's stream and the grid-sized Gamma and Z~ on the handle's second
+// stream; the solve waits for both.
 template <typename TF, typename TZ, typename TX>
 exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                             const Layout& L, const void* psi, const void* occ, const int32_t* pts,
@@ -316,10 +319,11 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   void* grid2 = ws + L.grid2;  // Z~, then the half-grid transform
   const long nn = (long)g.ni * g.ni;
   hipError_t e;
-  hipStream_t ax = h->aux;
+  hipStream_t ax = st;           // the factorisation chain stays on the caller's stream
+  hipStream_t gs = h->aux;       // Gamma and Z~ go to the second stream
   e = hipEventRecord(h->fork_ev, st);
   if (e != hipSuccess) return hip_check(h, e, "fork event");
-  e = hipStreamWaitEvent(ax, h->fork_ev, 0);
+  e = hipStreamWaitEvent(gs, h->fork_ev, 0);
   if (e != hipSuccess) return hip_check(h, e, "fork wait");
   const char* what = nullptr;
   {
@@ -353,29 +357,29 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
       if (e != hipSuccess) what = "S+ gemm";
     }
   }
-  hipError_t ej = hipEventRecord(h->join_ev, ax);
   if (what) {
-    if (ej == hipSuccess) (void)hipStreamWaitEvent(st, h->join_ev, 0);
+    (void)hipEventRecord(h->join_ev, gs);
+    (void)hipStreamWaitEvent(st, h->join_ev, 0);
     return hip_check(h, e, what);
   }
-  if (ej != hipSuccess) return hip_check(h, ej, "join event");
   {
-    PhaseTimer pt(h, PH_GAMMA, st);
+    PhaseTimer pt(h, PH_GAMMA, gs);
     if (std::is_same<TF, double>::value)
       e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
                                         psi, g.ng, (long)g.no * g.ng, grid, g.ng,
-                                        (long)g.ni * g.ng, st, h->tile_gamma);
+                                        (long)g.ni * g.ng, gs, h->tile_gamma);
     else
       e = cgemm_nn_grid32(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi, g.ng,
-                          (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, st);
+                          (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, gs);
   }
   if (e != hipSuccess) what = "Gamma gemm";
   if (!what) {
-    PhaseTimer pt(h, PH_KCORR, st);
-    e = launch_kcorr_real<TF, TZ>(g, grid, grid2, g.ng, st);
+    PhaseTimer pt(h, PH_KCORR, gs);
+    e = launch_kcorr_real<TF, TZ>(g, grid, grid2, g.ng, gs);
     if (e != hipSuccess) what = "Z kcorr";
   }
-  hipError_t ew = hipStreamWaitEvent(st, h->join_ev, 0);
+  hipError_t ej = hipEventRecord(h->join_ev, gs);
+  hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
   if (what) return hip_check(h, e, what);
   if (ew != hipSuccess) return hip_check(h, ew, "join wait");
   {
