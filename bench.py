@@ -101,21 +101,21 @@ def algorithmic_work(cell, n_isdf, prec):
 FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524315.4375, 1.0
 TRAFFIC = {
     # (phase, path): (source, sha256[:16], FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("solve", "f64"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 15980730.3, 12757500.0),
-    ("solve", "mixed"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 15917826.1, 6417227.2),
-    ("solve", "f32"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 9040774.4, 6456818.7),
-    ("gamma", "f64"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 1296077.3, 12757500.0),
-    ("gamma", "mixed"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 1296077.3, 12757500.0),
-    ("gamma", "f32"): ("gemm_mfma.hip", "f9af0baeb7cb22fd", 656773.1, 6437899.1),
-    ("kcorr", "f64"): ("fit.hip", "01c53048f397523a", 6379036.9, 12757500.0),
-    ("kcorr", "mixed"): ("fit.hip", "01c53048f397523a", 6379036.9, 12757500.0),
-    ("kcorr", "f32"): ("fit.hip", "01c53048f397523a", 3189571.4, 6378750.0),
-    ("fft", "f64"): ("fft.hip", "97cc61b6aef13241", 13969953.2, 25515043.5),
-    ("fft", "mixed"): ("fft.hip", "97cc61b6aef13241", 7790563.8, 13160701.9),
-    ("fft", "f32"): ("fft.hip", "97cc61b6aef13241", 7790563.8, 13160701.9),
-    ("coulomb", "f64"): ("coulomb.hip", "5af2bc2def895dff", 61064667.3, 241537.9),
-    ("coulomb", "mixed"): ("coulomb.hip", "5af2bc2def895dff", 7473337.8, 245680.6),
-    ("coulomb", "f32"): ("coulomb.hip", "5af2bc2def895dff", 7473337.8, 245680.6),
+    ("solve", "f64"): ("gemm_mfma.hip", "823a24094444ff6d", 7983256.3, 6488644.8),
+    ("solve", "mixed"): ("gemm_mfma.hip", "823a24094444ff6d", 6478133.0, 3296220.9),
+    ("solve", "f32"): ("gemm_mfma.hip", "823a24094444ff6d", 4204795.5, 3207987.6),
+    ("gamma", "f64"): ("gemm_mfma.hip", "823a24094444ff6d", 1299443.3, 12757500.0),
+    ("gamma", "mixed"): ("gemm_mfma.hip", "823a24094444ff6d", 1299443.3, 12757500.0),
+    ("gamma", "f32"): ("gemm_mfma.hip", "823a24094444ff6d", 656774.5, 6435262.1),
+    ("kcorr", "f64"): ("fit.hip", "647e3dc673614016", 6378788.0, 6378750.0),
+    ("kcorr", "mixed"): ("fit.hip", "647e3dc673614016", 6378788.0, 6378750.0),
+    ("kcorr", "f32"): ("fit.hip", "647e3dc673614016", 3189395.9, 3189375.0),
+    ("fft", "f64"): ("fft.hip", "3d4f96af3d2899eb", 6924057.2, 13230000.0),
+    ("fft", "mixed"): ("fft.hip", "3d4f96af3d2899eb", 3884516.4, 6615000.1),
+    ("fft", "f32"): ("fft.hip", "3d4f96af3d2899eb", 3884516.4, 6615000.1),
+    ("coulomb", "f64"): ("coulomb.hip", "2469cbf960cac8b6", 33541806.2, 241658.0),
+    ("coulomb", "mixed"): ("coulomb.hip", "2469cbf960cac8b6", 16654467.2, 218471.5),
+    ("coulomb", "f32"): ("coulomb.hip", "2469cbf960cac8b6", 16654467.2, 218471.5),
 }
 
 

@@ -457,8 +457,9 @@ __global__ __launch_bounds__(NT1) void fft_yz_half_kernel(const TI* __restrict__
   }
   __syncthreads();
   const TI* src = in + p * np;
+  const float in3 = 1.0f / (float)n3, ihz = 1.0f / (float)hz;
   for (int e = threadIdx.x; e < np; e += NT1) {
-    const int y = e / n3, z = e - y * n3;
+    const int y = small_div(e, n3, in3), z = e - y * n3;
     const cplx<T> w = cmul<T>(ry[y], rz[z]);
     const T v = (T)src[e];
     buf[e] = mk<T>(v * w.x, v * w.y);
@@ -468,7 +469,7 @@ __global__ __launch_bounds__(NT1) void fft_yz_half_kernel(const TI* __restrict__
   fft_lines<T, NT1, FFT_MAXPTS, true>(buf, py, hz, n3, 1, ty);
   cplx<T>* dst = out + p * ((long)n2 * hz);
   for (int e = threadIdx.x; e < n2 * hz; e += NT1) {
-    const int y = e / hz, z = e - y * hz;
+    const int y = small_div(e, hz, ihz), z = e - y * hz;
     dst[e] = buf[y * n3 + z];
   }
 }
