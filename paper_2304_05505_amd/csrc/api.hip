@@ -315,7 +315,7 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   double2* W = (double2*)(ws + L.W);
   double2* Sp = (double2*)(ws + L.Sp);
   int32_t* keep = (int32_t*)(ws + L.keep);
-  void* grid = ws + L.grid;    // Gamma, then eta
+  void* grid = ws + L.grid;    // Gamma (FP64), then eta
   void* grid2 = ws + L.grid2;  // Z~, then the half-grid transform
   const long nn = (long)g.ni * g.ni;
   hipError_t e;
@@ -362,21 +362,25 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     (void)hipStreamWaitEvent(st, h->join_ev, 0);
     return hip_check(h, e, what);
   }
-  {
+  if constexpr (std::is_same<TF, float>::value) {
+    // FP32: Gamma^n and the real k-correlation in one pass; only Z~ is written
     PhaseTimer pt(h, PH_GAMMA, gs);
-    if (std::is_same<TF, double>::value)
+    e = launch_gamma_kcorr<float, float>(g, occ, psi, grid2, gs);
+    if (e != hipSuccess) what = "Gamma and Z kcorr";
+  } else {
+    // FP64: the three-product Gamma GEMM, then the real k-correlation
+    {
+      PhaseTimer pt(h, PH_GAMMA, gs);
       e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
                                         psi, g.ng, (long)g.no * g.ng, grid, g.ng,
                                         (long)g.ni * g.ng, gs, h->tile_gamma);
-    else
-      e = cgemm_nn_grid32(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi, g.ng,
-                          (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, gs);
-  }
-  if (e != hipSuccess) what = "Gamma gemm";
-  if (!what) {
-    PhaseTimer pt(h, PH_KCORR, gs);
-    e = launch_kcorr_real<TF, TZ>(g, grid, grid2, g.ng, gs);
-    if (e != hipSuccess) what = "Z kcorr";
+    }
+    if (e != hipSuccess) what = "Gamma gemm";
+    if (!what) {
+      PhaseTimer pt(h, PH_KCORR, gs);
+      e = launch_kcorr_real<TF, TZ>(g, grid, grid2, g.ng, gs);
+      if (e != hipSuccess) what = "Z kcorr";
+    }
   }
   hipError_t ej = hipEventRecord(h->join_ev, gs);
   hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;

@@ -245,6 +245,11 @@ bool kcorr_real(const Geom& g);
 // (real there); TO real for grid columns, double2 (imaginary part 0) for points
 template <typename T, typename TO>
 hipError_t launch_kcorr_real(const Geom& g, const void* in, void* out, int ncol, hipStream_t st);
+// real path, Gamma^n = occ^n conj(psi^n) and the real k-correlation fused:
+// Z~ [N_k][N_ISDF][N_g] (TZ) from occ [N_k][N_ISDF][n_occ] c128 and psi (storage T)
+template <typename T, typename TZ>
+hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, void* Z,
+                              hipStream_t st);
 
 // dst[0:n] = src[0:n] (a kernel, so that captured sequences hold no copy nodes)
 hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st);

@@ -240,6 +240,155 @@ __global__ __launch_bounds__(256) void kcorr_real_kernel(const cplx<T>* __restri
   }
 }
 
+// ---------------------------------------------------------------------------
+// Real path, Gamma and the k-correlation fused: a workgroup (4 waves stacked
+// along P) owns a 64 x (16 WN) tile of (P, r). For every k-point n the product
+// Gamma^n = occ^n conj(psi^n) of that tile accumulates in matrix registers
+// (four real MFMAs per complex step, FP32 or FP64 matrix cores by T); then each
+// lane forms Z~[m] = (1/N_k) DFT_k(|DFT_k Gamma|^2)[m] for its elements, which is
+// real on these meshes, and only Z~ is written. Gamma never reaches memory.
+// ---------------------------------------------------------------------------
+typedef float gk_f4 __attribute__((ext_vector_type(4)));
+typedef double gk_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct GkMma;
+template <>
+struct GkMma<float> {
+  using acc = gk_f4;
+  static __device__ acc zero() { return acc{0, 0, 0, 0}; }
+  static __device__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // register v of a lane holds row 4 (lane/16) + v, column lane % 16
+  static __device__ int row(int lk, int v) { return 4 * lk + v; }
+};
+template <>
+struct GkMma<double> {
+  using acc = gk_d4;
+  static __device__ acc zero() { return acc{0, 0, 0, 0}; }
+  static __device__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // register v of a lane holds row 4 v + lane/16, column lane % 16
+  static __device__ int row(int lk, int v) { return 4 * v + lk; }
+};
+
+template <typename T, typename TZ, int N1, int N2, int N3, int WN>
+__global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no, int nrt,
+                                                          long ntiles, long ntiles_pad,
+                                                          const double2* __restrict__ occ,
+                                                          const cplx<T>* __restrict__ psi,
+                                                          TZ* __restrict__ Z) {
+  using M = GkMma<T>;
+  using acc_t = typename M::acc;
+  constexpr int NK = N1 * N2 * N3;
+  constexpr int NPF = 2;
+  const long per = ntiles_pad / 8;
+  const long t = (blockIdx.x % 8) * per + blockIdx.x / 8;  // XCD-contiguous tile ranges
+  if (t >= ntiles) return;
+  const int rt = (int)(t % nrt);
+  const long ct = t / nrt;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = rt * 64 + wave * 16;
+  const long col0 = ct * (16 * WN);
+  const int ra = min(row0 + li, ni - 1);
+  unsigned boff[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long c = col0 + 16 * j + li;
+    boff[j] = (unsigned)(c < ng ? c : ng - 1);
+  }
+  acc_t are[NK][WN], aim[NK][WN];
+#pragma unroll
+  for (int n = 0; n < NK; ++n)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) are[n][j] = aim[n][j] = M::zero();
+  // k-steps of 4 per k-point, padded to a multiple of the slot count so that
+  // every k-point starts at slot 0; the refills run across k-points (the last
+  // slots of k-point n fetch the first steps of n + 1), so the pipeline fills
+  // once per tile
+  const int nks = ((no + 3) / 4 + NPF - 1) / NPF * NPF;
+  double2 fa[NPF];
+  cplx<T> fb[NPF][WN];
+  auto load = [&](int n, int ks, double2& xa, cplx<T>* xb) {
+    if (ks >= nks) {  // first steps of the next k-point (clamped past the last)
+      ks -= nks;
+      n = n + 1 < NK ? n + 1 : NK - 1;
+    }
+    const int k = 4 * ks + lk;
+    const unsigned kc = (unsigned)(k < no ? k : no - 1);
+    xa = occ[((long)n * ni + ra) * no + kc];
+    const cplx<T>* Bn = psi + (long)n * no * ng + (long)kc * ng;
+#pragma unroll
+    for (int j = 0; j < WN; ++j) xb[j] = Bn[boff[j]];
+  };
+#pragma unroll
+  for (int s = 0; s < NPF; ++s) load(0, s, fa[s], fb[s]);
+  // the first loads land before the loops, so that the wait counts at the loop
+  // heads see only the loops' own refills
+  __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+  for (int n = 0; n < NK; ++n) {
+    for (int it = 0; it < nks; it += NPF) {
+#pragma unroll
+      for (int s = 0; s < NPF; ++s) {
+        const int ks = it + s;
+        const bool kin = 4 * ks + lk < no;
+        // Gamma = A conj(B): Re += ar br + ai bi, Im += ai br - ar bi
+        const T ar = kin ? (T)fa[s].x : (T)0, ai = kin ? (T)fa[s].y : (T)0;
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          const T br = (T)fb[s][j].x, bi = (T)fb[s][j].y;
+          are[n][j] = M::mma(ar, br, are[n][j]);
+          are[n][j] = M::mma(ai, bi, are[n][j]);
+          aim[n][j] = M::mma(ai, br, aim[n][j]);
+          aim[n][j] = M::mma(-ar, bi, aim[n][j]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        load(n, ks + NPF, fa[s], fb[s]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  // each lane round-trips its accumulators through its wave's LDS slice (keeps
+  // them in matrix registers during the loops), then correlates over the mesh
+  __shared__ T stage[4][2 * NK][64];
+  typedef __attribute__((address_space(3))) volatile T lds_t;
+  lds_t* sw = (lds_t*)&stage[wave][0][0];
+  const T inv = (T)1 / (T)NK;
+  const long nz = (long)ni * ng;
+#pragma unroll
+  for (int j = 0; j < WN; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int n = 0; n < NK; ++n) {
+        sw[(2 * n) * 64 + lane] = are[n][j][v];
+        sw[(2 * n + 1) * 64 + lane] = aim[n][j][v];
+      }
+      cplx<T> a[NK];
+#pragma unroll
+      for (int n = 0; n < NK; ++n) a[n] = mk<T>(sw[(2 * n) * 64 + lane], sw[(2 * n + 1) * 64 + lane]);
+      if (NK > 1) {
+        kdft3<T, N1, N2, N3>(a);
+#pragma unroll
+        for (int n = 0; n < NK; ++n) a[n] = mk<T>(a[n].x * a[n].x + a[n].y * a[n].y, 0);
+        kdft3<T, N1, N2, N3>(a);
+      } else {
+        a[0] = mk<T>(a[0].x * a[0].x + a[0].y * a[0].y, 0);
+      }
+      const int r = row0 + M::row(lk, v);
+      const long c = col0 + 16 * j + li;
+      if (r < ni && c < ng) {
+        TZ* dst = Z + (long)r * ng + c;
+#pragma unroll
+        for (int m = 0; m < NK; ++m) dst[(long)m * nz] = (TZ)(a[m].x * inv);
+      }
+    }
+}
+
 #define EXX_KMESH_LIST(X) \
   X(1, 1, 1)              \
   X(2, 2, 2)              \
@@ -310,6 +459,36 @@ template hipError_t launch_kcorr_real<float, float>(const Geom&, const void*, vo
                                                     hipStream_t);
 template hipError_t launch_kcorr_real<double, double2>(const Geom&, const void*, void*, int,
                                                        hipStream_t);
+
+// fused Gamma + real k-correlation of the real path: T is the storage of psi
+// and the matrix-core precision, TZ that of Z~
+template <typename T, typename TZ>
+hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, void* Z,
+                              hipStream_t st) {
+  constexpr int WN = sizeof(T) == 4 ? 2 : 1;
+  const int nrt = (g.ni + 63) / 64;
+  const long nct = ((long)g.ng + 16 * WN - 1) / (16 * WN);
+  const long ntiles = nrt * nct;
+  const long pad = (ntiles + 7) / 8 * 8;
+  if ((long)g.no * g.ng >= 0x7fffffffL) return hipErrorInvalidValue;
+#define EXX_GKLAUNCH(a, b, c)                                                                    \
+  if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                               \
+    hipLaunchKernelGGL((gamma_kcorr_kernel<T, TZ, a, b, c, WN>), dim3((unsigned)pad), dim3(256), \
+                       0, st, g.ni, g.ng, g.no, nrt, ntiles, pad, (const double2*)occ,           \
+                       (const cplx<T>*)psi, (TZ*)Z);                                             \
+    return hipGetLastError();                                                                    \
+  }
+  EXX_GKLAUNCH(1, 1, 1)
+  EXX_GKLAUNCH(2, 2, 2)
+  EXX_GKLAUNCH(2, 1, 1)
+  EXX_GKLAUNCH(1, 2, 1)
+  EXX_GKLAUNCH(1, 1, 2)
+  EXX_GKLAUNCH(2, 2, 1)
+#undef EXX_GKLAUNCH
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_gamma_kcorr<float, float>(const Geom&, const void*, const void*, void*,
+                                                     hipStream_t);
 
 template hipError_t launch_kcorr<double>(const Geom&, const Tables&, const void*, void*, int,
                                          const int32_t*, bool, hipStream_t);
