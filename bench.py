@@ -61,7 +61,8 @@ def algorithmic_work(cell, n_isdf, prec):
     On the real path (every k-mesh axis <= 2) the solve is a real GEMM (2 flops
     per multiply-add), Z~ and eta are real arrays, the FFT writes the kept half
     grid of n1 n2 (n3/2 + 1) points and the Coulomb contraction takes
-    Re(X conj Y) (two real products, 4 flops) over that half grid.
+    Re(X conj Y) (two real products, 4 flops) over that half grid; in FP32 the
+    Gamma GEMM and the k-correlation are one kernel (phase "gamma").
     """
     nk, ng, no, na = cell.N_k, cell.N_g, cell.n_occ, cell.n_ao
     ni = n_isdf
@@ -71,6 +72,10 @@ def algorithmic_work(cell, n_isdf, prec):
             "K": ("flop", 8.0 * nk * (na * ni * ni + na * na * ni))}
     if real_path(cell):
         n1, n2, n3 = cell.grid
+        if prec == "f32":
+            # FP32: one fused kernel forms Gamma^n (four real products) and Z~;
+            # its time is reported under "gamma" and counts the GEMM flops
+            work["gamma"] = ("flop", 8.0 * nk * ni * no * ng)
         ngh = n1 * n2 * (n3 // 2 + 1)
         gam = 8 if prec == "f32" else 16      # Gamma element (complex)
         zr = 4 if prec == "f32" else 8        # Z~ element (real)
