@@ -363,9 +363,12 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     return hip_check(h, e, what);
   }
   if constexpr (std::is_same<TF, float>::value) {
-    // FP32: Gamma^n and the real k-correlation in one pass; only Z~ is written
+    // FP32: Gamma^n and the real k-correlation in one pass; only Z~ is written.
+    // occ is narrowed to c64 first, into the K-build's scratch (free until then)
     PhaseTimer pt(h, PH_GAMMA, gs);
-    e = launch_gamma_kcorr<float, float>(g, occ, psi, grid2, gs);
+    float2* occ32 = (float2*)(ws + L.T);
+    e = launch_narrow((const double2*)occ, occ32, (long)g.nk * g.ni * g.no, gs);
+    if (e == hipSuccess) e = launch_gamma_kcorr<float, float>(g, occ32, psi, grid2, gs);
     if (e != hipSuccess) what = "Gamma and Z kcorr";
   } else {
     // FP64: the three-product Gamma GEMM, then the real k-correlation

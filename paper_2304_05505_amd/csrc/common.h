@@ -245,8 +245,10 @@ bool kcorr_real(const Geom& g);
 // (real there); TO real for grid columns, double2 (imaginary part 0) for points
 template <typename T, typename TO>
 hipError_t launch_kcorr_real(const Geom& g, const void* in, void* out, int ncol, hipStream_t st);
+// c128 -> c64, n elements
+hipError_t launch_narrow(const double2* in, float2* out, long n, hipStream_t st);
 // real path, Gamma^n = occ^n conj(psi^n) and the real k-correlation fused:
-// Z~ [N_k][N_ISDF][N_g] (TZ) from occ [N_k][N_ISDF][n_occ] c128 and psi (storage T)
+// Z~ [N_k][N_ISDF][N_g] (TZ) from occ [N_k][N_ISDF][n_occ] and psi, both storage T
 template <typename T, typename TZ>
 hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, void* Z,
                               hipStream_t st);

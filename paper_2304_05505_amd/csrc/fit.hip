@@ -244,6 +244,7 @@ __global__ __launch_bounds__(256) void kcorr_real_kernel(const cplx<T>* __restri
 // Real path, Gamma and the k-correlation fused: a workgroup (4 waves stacked
 // along P) owns a 64 x (16 WN) tile of (P, r). For every k-point n the product
 // Gamma^n = occ^n conj(psi^n) of that tile accumulates in matrix registers
+// (occ in the storage type T)
 // (four real MFMAs per complex step, FP32 or FP64 matrix cores by T); then each
 // lane forms Z~[m] = (1/N_k) DFT_k(|DFT_k Gamma|^2)[m] for its elements, which is
 // real on these meshes, and only Z~ is written. Gamma never reaches memory.
@@ -277,7 +278,7 @@ struct GkMma<double> {
 template <typename T, typename TZ, int N1, int N2, int N3, int WN>
 __global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no, int nrt,
                                                           long ntiles, long ntiles_pad,
-                                                          const double2* __restrict__ occ,
+                                                          const cplx<T>* __restrict__ occ,
                                                           const cplx<T>* __restrict__ psi,
                                                           TZ* __restrict__ Z) {
   using M = GkMma<T>;
@@ -310,9 +311,9 @@ __global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no
   // slots of k-point n fetch the first steps of n + 1), so the pipeline fills
   // once per tile
   const int nks = ((no + 3) / 4 + NPF - 1) / NPF * NPF;
-  double2 fa[NPF];
+  cplx<T> fa[NPF];
   cplx<T> fb[NPF][WN];
-  auto load = [&](int n, int ks, double2& xa, cplx<T>* xb) {
+  auto load = [&](int n, int ks, cplx<T>& xa, cplx<T>* xb) {
     if (ks >= nks) {  // first steps of the next k-point (clamped past the last)
       ks -= nks;
       n = n + 1 < NK ? n + 1 : NK - 1;
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no
         const int ks = it + s;
         const bool kin = 4 * ks + lk < no;
         // Gamma = A conj(B): Re += ar br + ai bi, Im += ai br - ar bi
-        const T ar = kin ? (T)fa[s].x : (T)0, ai = kin ? (T)fa[s].y : (T)0;
+        const T ar = kin ? fa[s].x : (T)0, ai = kin ? fa[s].y : (T)0;
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
           const T br = (T)fb[s][j].x, bi = (T)fb[s][j].y;
@@ -460,8 +461,21 @@ template hipError_t launch_kcorr_real<float, float>(const Geom&, const void*, vo
 template hipError_t launch_kcorr_real<double, double2>(const Geom&, const void*, void*, int,
                                                        hipStream_t);
 
-// fused Gamma + real k-correlation of the real path: T is the storage of psi
-// and the matrix-core precision, TZ that of Z~
+__global__ __launch_bounds__(256) void narrow_kernel(const double2* __restrict__ in,
+                                                     float2* __restrict__ out, long n) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+hipError_t launch_narrow(const double2* in, float2* out, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out,
+                     n);
+  return hipGetLastError();
+}
+
+// fused Gamma + real k-correlation of the real path: T is the storage of occ
+// and psi and the matrix-core precision, TZ that of Z~
 template <typename T, typename TZ>
 hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, void* Z,
                               hipStream_t st) {
@@ -474,7 +488,7 @@ hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, v
 #define EXX_GKLAUNCH(a, b, c)                                                                    \
   if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                               \
     hipLaunchKernelGGL((gamma_kcorr_kernel<T, TZ, a, b, c, WN>), dim3((unsigned)pad), dim3(256), \
-                       0, st, g.ni, g.ng, g.no, nrt, ntiles, pad, (const double2*)occ,           \
+                       0, st, g.ni, g.ng, g.no, nrt, ntiles, pad, (const cplx<T>*)occ,           \
                        (const cplx<T>*)psi, (TZ*)Z);                                             \
     return hipGetLastError();                                                                    \
   }
