@@ -408,6 +408,136 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   return EXX_OK;
 }
 
+// Transfers m and -m of the mesh: the fitted pair functions of -m are the
+// conjugates of those of m (relabelling n), so Vb^{-m} = conj Vb^m and the
+// Cholesky pivots (hence the ranks) agree. The paired path below fits and
+// contracts one transfer of each pair (rep, slice order), then writes both.
+struct Pairs {
+  int n = 0;
+  int rep[64], bar[64], slot[64];
+};
+
+Pairs make_pairs(const Geom& g) {
+  Pairs p;
+  for (int m = 0; m < 64; ++m) p.slot[m] = -1;
+  for (int m = 0; m < g.nk; ++m) {
+    const int m1 = m / (g.N[1] * g.N[2]), m2 = (m / g.N[2]) % g.N[1], m3 = m % g.N[2];
+    const int b = (((g.N[0] - m1) % g.N[0]) * g.N[1] + (g.N[1] - m2) % g.N[1]) * g.N[2] +
+                  (g.N[2] - m3) % g.N[2];
+    if (m <= b) {
+      p.slot[m] = p.n;
+      p.rep[p.n] = m;
+      p.bar[p.n] = b != m ? b : -1;
+      ++p.n;
+    }
+  }
+  return p;
+}
+
+// The complex path of the fused build with one transfer per pair (meshes with
+// an axis of 3 or more, refinement off): same steps as fit_impl + coulomb_impl
+// over the representative transfers, Vb of the partners by conjugation.
+template <typename TF, typename TX>
+exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, char* ws,
+                             const Layout& L, const Pairs& pr, const void* psi, const void* occ,
+                             const int32_t* pts, void* V, int32_t* rank, hipStream_t st) {
+  double2* G = (double2*)(ws + L.G);
+  double2* Lf = (double2*)(ws + L.Lf);
+  double2* W = (double2*)(ws + L.W);
+  double2* Sp = (double2*)(ws + L.Sp);
+  int32_t* keep = (int32_t*)(ws + L.keep);
+  int32_t* rank_c = (int32_t*)(ws + L.rank2);
+  void* grid = ws + L.grid;    // Gamma, Z (compacted in place), then the transform
+  void* xi = ws + L.grid2;     // xi of the representative transfers
+  Geom gr = g;                 // batch over the representative transfers
+  gr.nk = pr.n;
+  const long nn = (long)g.ni * g.ni;
+  hipError_t e;
+  hipStream_t ax = st;         // factorisation chain on the caller's stream
+  hipStream_t gs = h->aux;     // Gamma and Z on the second stream
+  e = hipEventRecord(h->fork_ev, st);
+  if (e != hipSuccess) return hip_check(h, e, "fork event");
+  e = hipStreamWaitEvent(gs, h->fork_ev, 0);
+  if (e != hipSuccess) return hip_check(h, e, "fork wait");
+  const char* what = nullptr;
+  {
+    PhaseTimer pt(h, PH_GRAM, ax);
+    e = gemm<double, double, double, double>(g.ni, g.ni, g.no, g.nk, A_N, occ, g.no,
+                                             (long)g.ni * g.no, B_C, occ, g.no,
+                                             (long)g.ni * g.no, G, g.ni, nn, 1.0, false, ax);
+  }
+  if (e != hipSuccess) what = "G gemm";
+  if (!what) {
+    // S^m of the representative transfers, straight into the factor buffer
+    PhaseTimer pt(h, PH_METRIC, ax);
+    e = launch_kcorr<double>(g, tb, G, Lf, g.ni, pts, true, ax, pr.slot);
+    if (e != hipSuccess) what = "S kcorr";
+  }
+  if (!what) {
+    PhaseTimer pt(h, PH_CHOL, ax);
+    e = launch_chol_blocked(gr, Lf, keep, rank_c, (double*)(ws + L.tol), 1e-12, ax);
+    if (e != hipSuccess) what = "cholesky";
+  }
+  if (!what) {
+    PhaseTimer pt(h, PH_PINV, ax);
+    e = launch_tri_inv_blocked(gr, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
+    if (e != hipSuccess) what = "triangular inverse";
+    if (!what) {
+      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_C, W, g.ni, nn, B_N, W,
+                                               g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
+      if (e != hipSuccess) what = "S+ gemm";
+    }
+  }
+  if (!what) {
+    e = launch_rank_scatter(rank_c, rank, pr.rep, pr.bar, pr.n, ax);
+    if (e != hipSuccess) what = "rank scatter";
+  }
+  if (what) {
+    (void)hipEventRecord(h->join_ev, gs);
+    (void)hipStreamWaitEvent(st, h->join_ev, 0);
+    return hip_check(h, e, what);
+  }
+  {
+    PhaseTimer pt(h, PH_GAMMA, gs);
+    if (std::is_same<TF, double>::value)
+      e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
+                                        psi, g.ng, (long)g.no * g.ng, grid, g.ng,
+                                        (long)g.ni * g.ng, gs, h->tile_gamma);
+    else
+      e = cgemm_nn_grid32(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi, g.ng,
+                          (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, gs);
+  }
+  if (e != hipSuccess) what = "Gamma gemm";
+  if (!what) {
+    // Z^m of the representative transfers, compacted in place
+    PhaseTimer pt(h, PH_KCORR, gs);
+    e = launch_kcorr<TF>(g, tb, grid, grid, g.ng, pts, false, gs, pr.slot);
+    if (e != hipSuccess) what = "Z kcorr";
+  }
+  hipError_t ej = hipEventRecord(h->join_ev, gs);
+  hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
+  if (what) return hip_check(h, e, what);
+  if (ew != hipSuccess) return hip_check(h, ew, "join wait");
+  {
+    PhaseTimer pt(h, PH_SOLVE, st);
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, gr.nk, Sp, g.ni, nn, false, grid, g.ng,
+                              (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "solve gemm");
+  {
+    PhaseTimer pt(h, PH_FFT, st);
+    e = launch_fft3d<TX>(g, tb, xi, grid, (long)gr.nk * g.ni, h->ncu, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "fft");
+  {
+    PhaseTimer pt(h, PH_COULOMB, st);
+    e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st,
+                           pr.rep, pr.bar, pr.n);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "coulomb");
+  return EXX_OK;
+}
+
 // the fused fit + Coulomb of one build in precision prec
 exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                        exx_prec prec, const void* psi, const void* occ, const int32_t* pts,
@@ -416,6 +546,14 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
   void* S = ws + L.S2;
   void* V = ws + L.V2;
   exx_status s;
+  const Pairs pr = make_pairs(g);
+  if (!kcorr_real(g) && h->refine == 0 && pr.n < g.nk) {
+    if (prec == EXX_F64)
+      return fit_coulomb_pairs<double, double>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
+    if (prec == EXX_MIXED)
+      return fit_coulomb_pairs<double, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
+    return fit_coulomb_pairs<float, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
+  }
   if (kcorr_real(g) && h->refine == 0) {
     if (prec == EXX_F64)
       return fit_coulomb_real<double, double, double>(h, g, tb, ws, L, psi, occ, pts, S, V, rank,

@@ -177,6 +177,32 @@ __global__ __launch_bounds__(PNT) void diag_inv_kernel(const double2* __restrict
 
 }  // namespace
 
+struct RankMap {
+  int rep[64], bar[64];
+  int n;
+};
+
+// rank[rep[s]] = rc[s] and, for a conjugate partner, rank[bar[s]] = rc[s]
+__global__ void rank_scatter_kernel(const int32_t* __restrict__ rc, int32_t* __restrict__ rank,
+                                    RankMap mp) {
+  const int s = threadIdx.x;
+  if (s >= mp.n) return;
+  rank[mp.rep[s]] = rc[s];
+  if (mp.bar[s] >= 0) rank[mp.bar[s]] = rc[s];
+}
+
+hipError_t launch_rank_scatter(const int32_t* rc, int32_t* rank, const int* rep, const int* bar,
+                               int n, hipStream_t st) {
+  RankMap mp;
+  for (int s = 0; s < 64; ++s) {
+    mp.rep[s] = s < n ? rep[s] : 0;
+    mp.bar[s] = s < n ? bar[s] : -1;
+  }
+  mp.n = n;
+  hipLaunchKernelGGL(rank_scatter_kernel, dim3(1), dim3(64), 0, st, rc, rank, mp);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);

@@ -235,9 +235,12 @@ exx_status get_tables(exx_context* h, const Geom& g, Tables* t, hipStream_t st);
 // k-autocorrelation with Bloch phase:
 // out[m][P][c] = e^{i q_m.(r_P - r_c)} sum_n in[n][P][c] conj in[n+m][P][c]
 // columns c are grid points (cols_are_points false) or the points pts[c].
+// slot (64 entries, host): transfer m goes to output slice slot[m] <= m, or is
+// skipped for -1; nullptr writes every m to slice m.
 template <typename T>
 hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* out, int ncol,
-                        const int32_t* pts, bool cols_are_points, hipStream_t st);
+                        const int32_t* pts, bool cols_are_points, hipStream_t st,
+                        const int* slot = nullptr);
 bool kcorr_supported(const Geom& g);
 // meshes whose every axis has N_i <= 2 (all transfers self-conjugate)
 bool kcorr_real(const Geom& g);
@@ -255,6 +258,9 @@ hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, v
 
 // dst[0:n] = src[0:n] (a kernel, so that captured sequences hold no copy nodes)
 hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st);
+// rank[rep[s]] = rc[s], and rank[bar[s]] = rc[s] where bar[s] >= 0 (host lists, n <= 64)
+hipError_t launch_rank_scatter(const int32_t* rc, int32_t* rank, const int* rep, const int* bar,
+                               int n, hipStream_t st);
 
 // Blocked Cholesky with pivot drop (A: S^m in, L in the lower triangle out;
 // tol: [N_k] scratch) and blocked inverse W = L^{-1} (T: [N_k][32][N_I] scratch)
@@ -279,9 +285,13 @@ int fft_half_z(const Geom& g);
 
 // Coulomb contraction: V^m (Bloch gauge) from F^m (storage T) on the FP64 matrix cores;
 // half: F is the real path's half-grid transform (launch_fft3d_half)
+// rep/bar/nslice (host arrays): F holds nslice transfers, slice s being transfer
+// rep[s]; V[rep[s]] is written and, where bar[s] >= 0, V[bar[s]] = conj V[rep[s]]
+// (bar[s] = -rep[s] on the mesh). rep == nullptr: slice m is transfer m.
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
-                          void* partial, int nsplit, double2* V, bool half, hipStream_t st);
+                          void* partial, int nsplit, double2* V, bool half, hipStream_t st,
+                          const int* rep = nullptr, const int* bar = nullptr, int nslice = 0);
 size_t coulomb_partial_bytes(const Geom& g, int nsplit);
 int coulomb_nsplit(const Geom& g);
 

@@ -18,6 +18,7 @@ struct CoulArgs {
   int n[3];
   int N[3];
   int ng, ni, nk, nsplit, chunk, ntile;
+  int rep[64];  // transfer of each slice (slices may hold a subset of the transfers)
 };
 
 // ---------------------------------------------------------------------------
@@ -41,7 +42,7 @@ constexpr int CALIGN = 64; // grid chunks of the split start at multiples of thi
 // representative of each axis, 0 for K = 0
 __global__ __launch_bounds__(256) void coulomb_vtab_kernel(double* __restrict__ vt, CoulArgs a) {
   const long g = (long)blockIdx.x * 256 + threadIdx.x;
-  const int m = blockIdx.y;
+  const int sl = blockIdx.y, m = a.rep[sl];
   if (g >= a.ng) return;
   const int n23 = a.n[1] * a.n[2];
   const int gc[3] = {(int)(g / n23), (int)((g / a.n[2]) % a.n[1]), (int)(g % a.n[2])};
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(256) void coulomb_vtab_kernel(double* __restrict__ 
     const double K = kap * (2.0 * M_PI / (a.N[ax] * a.L[ax]));
     kk += K * K;
   }
-  vt[(long)m * a.ng + g] = kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
+  vt[(long)sl * a.ng + g] = kk > 0.0 ? 4.0 * M_PI / kk : 0.0;
 }
 
 // Real path: the kernel table over the kept half grid (z index g3 < hz of the
@@ -337,23 +338,26 @@ struct ReduceArgs {
   int ni, nsplit;
   int real;
   double scale;
+  int rep[64];  // transfer of each slice
+  int bar[64];  // its conjugate partner -m, written as conj(Vb^m); -1: none
 };
 
-// V[m][P][Q] = scale * e^{-i q_m.(r_P - r_Q)} sum_s part (P < Q mirrored from Q > P)
+// V[m][P][Q] = scale * e^{-i q_m.(r_P - r_Q)} sum_s part (P < Q mirrored from Q > P),
+// m = rep[slice]; also V[-m] = conj V[m] where bar[slice] names -m
 __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __restrict__ part,
                                                              const int32_t* __restrict__ pts,
                                                              double2* __restrict__ V,
                                                              ReduceArgs a) {
   const long nn = (long)a.ni * a.ni;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int m = blockIdx.y;
+  const int sl = blockIdx.y, m = a.rep[sl];
   if (idx >= nn) return;
   const int P = (int)(idx / a.ni), Q = (int)(idx % a.ni);
   const bool lower = P >= Q;
   const long src = lower ? ((long)P * a.ni + Q) : ((long)Q * a.ni + P);
   double sx = 0.0, sy = 0.0;
   for (int s = 0; s < a.nsplit; ++s) {
-    const double2 v = part[((long)m * a.nsplit + s) * nn + src];
+    const double2 v = part[((long)sl * a.nsplit + s) * nn + src];
     sx += v.x;
     sy += v.y;
   }
@@ -385,6 +389,8 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __re
     sx = vx;
   }
   V[(long)m * nn + idx] = make_double2(sx, sy);
+  // Vb^{-m} = conj Vb^m
+  if (a.bar[sl] >= 0) V[(long)a.bar[sl] * nn + idx] = make_double2(sx, -sy);
 }
 
 }  // namespace
@@ -413,8 +419,11 @@ size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
 // the real part with the pairing weights, and the reduction applies no phase.
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
-                          void* partial, int nsplit, double2* V, bool half, hipStream_t st) {
+                          void* partial, int nsplit, double2* V, bool half, hipStream_t st,
+                          const int* rep, const int* bar, int nslice) {
   CoulArgs a;
+  const int ns = rep ? nslice : g.nk;
+  for (int m = 0; m < 64; ++m) a.rep[m] = rep && m < ns ? rep[m] : m;
   for (int i = 0; i < 3; ++i) {
     a.L[i] = g.L[i];
     a.n[i] = g.n[i];
@@ -423,7 +432,7 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   const int hz = g.n[2] / 2 + 1;
   a.ng = half ? g.n[0] * g.n[1] * hz : g.ng;
   a.ni = g.ni;
-  a.nk = g.nk;
+  a.nk = ns;
   a.nsplit = nsplit;
   a.chunk = (int)((((long)a.ng + nsplit - 1) / nsplit + CALIGN - 1) / CALIGN * CALIGN);
   // FP64 storage: 64 x 64 workgroup tiles; FP32 storage: 32 x 32 wave tiles
@@ -431,14 +440,14 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   const int nt = (g.ni + tw - 1) / tw;
   a.ntile = nt * (nt + 1) / 2;
   if ((long)g.ni * a.ng >= 0x7fffffffL) return hipErrorInvalidValue;
-  const long nwork = (long)a.ntile * g.nk * nsplit;
+  const long nwork = (long)a.ntile * ns * nsplit;
   const long pad = (nwork + 7) / 8 * 8;
   double* vt = (double*)((char*)partial + partial_only(g, nsplit));
   if (half)
     hipLaunchKernelGGL(coulomb_vtab_half_kernel, dim3((unsigned)((a.ng + 255) / 256), g.nk),
                        dim3(256), 0, st, vt, a, hz);
   else
-    hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), g.nk), dim3(256),
+    hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), ns), dim3(256),
                        0, st, vt, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -472,15 +481,21 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   r.nsplit = nsplit;
   r.real = half ? 1 : 0;
   r.scale = g.omega / ((double)g.ng * (double)g.ng);
+  for (int m = 0; m < 64; ++m) {
+    r.rep[m] = a.rep[m];
+    r.bar[m] = bar && m < ns ? bar[m] : -1;
+  }
   const long nn = (long)g.ni * g.ni;
-  hipLaunchKernelGGL(coulomb_reduce_kernel, dim3((unsigned)((nn + 255) / 256), g.nk), dim3(256), 0,
+  hipLaunchKernelGGL(coulomb_reduce_kernel, dim3((unsigned)((nn + 255) / 256), ns), dim3(256), 0,
                      st, (const double2*)partial, pts, V, r);
   return hipGetLastError();
 }
 
 template hipError_t launch_coulomb<double>(const Geom&, const Tables&, const void*, const int32_t*,
-                                           void*, int, double2*, bool, hipStream_t);
+                                           void*, int, double2*, bool, hipStream_t, const int*,
+                                           const int*, int);
 template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void*, const int32_t*,
-                                          void*, int, double2*, bool, hipStream_t);
+                                          void*, int, double2*, bool, hipStream_t, const int*,
+                                          const int*, int);
 
 }  // namespace exx

@@ -158,13 +158,16 @@ struct KcorrArgs {
   const double2* root[3];
   int n[3];
   int N[3];
+  // output slice of transfer m, or -1 to skip it (compacted output); slot[m] <= m
+  int slot[64];
 };
 
 // out[m][P][c] = e^{i q_m.(r_P - r_c)} (1/N_k) DFT_k(|DFT_k in|^2)[m]
 //             = e^{i q_m.(r_P - r_c)} sum_n in[n][P][c] conj in[n+m][P][c]
 template <typename T, int N1, int N2, int N3>
 // `in` and `out` may alias (in place): each thread reads all of its inputs
-// before it writes.
+// before it writes, and writes only its own element of each slice (slices may
+// be compacted: transfer m goes to slice slot[m] <= m, or nowhere).
 __global__ __launch_bounds__(256) void kcorr_kernel(const cplx<T>* in, cplx<T>* out, int ni, int ncol,
                                                     const int32_t* __restrict__ pts,
                                                     int cols_are_points, KcorrArgs ka) {
@@ -203,7 +206,8 @@ __global__ __launch_bounds__(256) void kcorr_kernel(const cplx<T>* in, cplx<T>* 
       double2 ph = make_double2(fp.x * fc.x + fp.y * fc.y, fp.x * fc.y - fp.y * fc.x);
       v = cmul<T>(v, mk<T>((T)ph.x, (T)ph.y));
     }
-    out[(long)m * total + idx] = v;
+    const int sm = ka.slot[m];
+    if (sm >= 0) out[(long)sm * total + idx] = v;
   }
 }
 
@@ -412,13 +416,15 @@ bool kcorr_supported(const Geom& g) {
 
 template <typename T>
 hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* out, int ncol,
-                        const int32_t* pts, bool cols_are_points, hipStream_t st) {
+                        const int32_t* pts, bool cols_are_points, hipStream_t st,
+                        const int* slot) {
   KcorrArgs ka;
   for (int a = 0; a < 3; ++a) {
     ka.root[a] = tb.root[a];
     ka.n[a] = g.n[a];
     ka.N[a] = g.N[a];
   }
+  for (int m = 0; m < 64; ++m) ka.slot[m] = slot ? slot[m] : m;
   long total = (long)g.ni * ncol;
   dim3 grid((unsigned)((total + 255) / 256));
 #define EXX_KLAUNCH(a, b, c)                                                                    \
@@ -505,8 +511,8 @@ template hipError_t launch_gamma_kcorr<float, float>(const Geom&, const void*, c
                                                      hipStream_t);
 
 template hipError_t launch_kcorr<double>(const Geom&, const Tables&, const void*, void*, int,
-                                         const int32_t*, bool, hipStream_t);
+                                         const int32_t*, bool, hipStream_t, const int*);
 template hipError_t launch_kcorr<float>(const Geom&, const Tables&, const void*, void*, int,
-                                        const int32_t*, bool, hipStream_t);
+                                        const int32_t*, bool, hipStream_t, const int*);
 
 }  // namespace exx

@@ -95,3 +95,35 @@ def test_config3_build_properties_and_reduced_precision(full3):
     for E, K in ((Em, Km), (Ef, Kf)):
         assert abs(E - E64) <= 1e-5
         assert np.abs(K - K64).max() <= 1e-6
+
+
+def test_config3_fused_build_matches_stages(full3):
+    """On the 3x3x3 mesh the fused build fits and contracts one transfer of each
+    pair (m, -m) and writes Vb^{-m} = conj Vb^m; the stage-wise calls compute
+    every transfer. K, E_x and the ranks agree to the FP64 parity tolerance."""
+    gold, cell, t, exx, torch, dev = (full3[k] for k in ("gold", "cell", "t", "exx", "torch", "dev"))
+    h, c = full3["h"], full3["c"]
+    nk, ni, ng, na = cell.N_k, cell.n_isdf, cell.N_g, cell.n_ao
+    K_f, E_f = _build(full3, "f64")
+    rank_f = torch.empty((nk,), dtype=torch.int32, device=dev)
+    K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    exx.exx_build(h, c, exx.EXX_F64, t["psi"], t["occ"], t["ao"], t["pts"], K, Ex, rank_f)
+    xi = torch.empty((nk, ni, ng), dtype=torch.complex128, device=dev)
+    S = torch.empty((nk, ni, ni), dtype=torch.complex128, device=dev)
+    V = torch.empty((nk, ni, ni), dtype=torch.complex128, device=dev)
+    rank_s = torch.empty((nk,), dtype=torch.int32, device=dev)
+    exx.exx_isdf_fit(h, c, exx.EXX_F64, t["psi"], t["occ"], t["pts"], xi, S, rank_s)
+    exx.exx_coulomb_V(h, c, exx.EXX_F64, xi, t["pts"], V)
+    del xi
+    K_s = torch.empty_like(K)
+    E_s = torch.empty_like(Ex)
+    exx.exx_build_K(h, c, exx.EXX_F64, t["ao"], t["occ"], V, K_s, E_s)
+    torch.cuda.synchronize()
+    tol = max(1e-12, 64 * EPS64 * max(gold["cond_S"]))
+    dK = float(np.abs(K_f - K_s.cpu().numpy()).max() / np.abs(K_s.cpu().numpy()).max())
+    dE = abs(E_f - float(E_s.cpu()[0])) / abs(float(E_s.cpu()[0]))
+    print(f"fused (paired) vs stage-wise: rel dK {dK:.2e}, rel dE {dE:.2e} (tol {tol:.2e})")
+    assert rank_f.cpu().tolist() == rank_s.cpu().tolist()
+    assert dK <= 2 * tol and dE <= 2 * tol
+
