@@ -151,7 +151,7 @@ def roofline(phases, work, prec, steps):
     """Roofline entry for the phase with the largest time."""
     best = max((p for p in phases if p in work), key=lambda p: phases[p][0])
     ms, calls = phases[best]
-    avg_s = ms / max(calls, 1) / 1e3
+    avg_s = ms / steps / 1e3  # per build (a phase may run as several launches per build)
     kind, amount = work[best]
     traffic = traffic_bytes(best, prec)
     if kind == "byte":
@@ -476,8 +476,8 @@ def main():
         el = time.perf_counter() - t0
         phases = h.phase_times()
         h.set_timing(False)
-        log(f"[{prec}] {args.steps} steps in {el:.3f} s; phases(ms/call): " +
-            ", ".join(f"{k}={v[0] / max(v[1], 1):.2f}" for k, v in phases.items()))
+        log(f"[{prec}] {args.steps} steps in {el:.3f} s; phases(ms/build): " +
+            ", ".join(f"{k}={v[0] / args.steps:.2f}" for k, v in phases.items()))
         results[prec] = {
             "value": args.steps / el,
             "ms_per_step": el / args.steps * 1e3,
@@ -534,7 +534,7 @@ def main():
         "roofline": dict(roof, kernel=dom),
         "paths": paths,
         "oracle_points": gold is not None,
-        "phases_ms": {k: v[0] / max(v[1], 1) for k, v in sel["phases"].items()},
+        "phases_ms": {k: v[0] / args.steps for k, v in sel["phases"].items()},
     }
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")

@@ -397,7 +397,7 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
   {
     PhaseTimer pt(h, PH_FFT, st);
-    e = launch_fft3d_half<TX, TX>(g, tb, grid, grid2, (long)g.nk * g.ni, h->ncu, st);
+    e = launch_fft3d_half<TX, TX>(g, tb, grid, grid2, (long)g.nk * g.ni, 0, h->ncu, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {

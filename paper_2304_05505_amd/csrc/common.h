@@ -277,10 +277,11 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
                         int ncu, hipStream_t st);
 bool fft_supported(const Geom& g, bool fp64);
 // real path: twisted FFT of the real fit eta (storage TI), keeping the z
-// frequencies below fft_half_z(g) = n3/2 + 1: out [nfun][n1][n2][hz] complex T
+// frequencies below fft_half_z(g) = n3/2 + 1: out [nfun][n1][n2][hz] complex T;
+// function f belongs to transfer m0 + f / N_ISDF
 template <typename TI, typename T>
 hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
-                             int ncu, hipStream_t st);
+                             int m0, int ncu, hipStream_t st);
 int fft_half_z(const Geom& g);
 
 // Coulomb contraction: V^m (Bloch gauge) from F^m (storage T) on the FP64 matrix cores;

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void coulomb_vtab_kernel(double* __restrict__ 
 __global__ __launch_bounds__(256) void coulomb_vtab_half_kernel(double* __restrict__ vt,
                                                                 CoulArgs a, int hz) {
   const long gh = (long)blockIdx.x * 256 + threadIdx.x;
-  const int m = blockIdx.y;
+  const int sl = blockIdx.y, m = a.rep[sl];
   const long ngh = (long)a.n[0] * a.n[1] * hz;
   if (gh >= ngh) return;
   const int g1 = (int)(gh / ((long)a.n[1] * hz)), g2 = (int)((gh / hz) % a.n[1]),
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void coulomb_vtab_half_kernel(double* __restri
     }
     v = kk > 0.0 ? w * 4.0 * M_PI / kk : 0.0;
   }
-  vt[(long)m * ngh + gh] = v;
+  vt[(long)sl * ngh + gh] = v;
 }
 
 // One wave computes one 32 x 32 wave tile (2 x 2 blocks of 16 x 16) of the
@@ -405,13 +405,15 @@ int coulomb_nsplit(const Geom& g) {
   return (int)ns;
 }
 
-// partial sums [N_k][nsplit][N_I][N_I] c128, then the kernel table [N_k][N_g] double
-static size_t partial_only(const Geom& g, int nsplit) {
-  return ((size_t)g.nk * nsplit * g.ni * g.ni * sizeof(double2) + 255) / 256 * 256;
+// partial sums [slices][nsplit][N_I][N_I] c128, then the kernel table [slices][N_g] double
+static size_t partial_only(const Geom& g, int nslice, int nsplit) {
+  return ((size_t)nslice * nsplit * g.ni * g.ni * sizeof(double2) + 255) / 256 * 256;
 }
 
+// scratch of a launch over all N_k transfers with nsplit splits; a launch over
+// fewer slices may use proportionally more splits in the same bytes
 size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
-  return partial_only(g, nsplit) + (size_t)g.nk * g.ng * sizeof(double);
+  return partial_only(g, g.nk, nsplit) + (size_t)g.nk * g.ng * sizeof(double);
 }
 
 // half = false: F is [N_k][N_ISDF][N_g] (complex path). half = true (real
@@ -442,9 +444,9 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   if ((long)g.ni * a.ng >= 0x7fffffffL) return hipErrorInvalidValue;
   const long nwork = (long)a.ntile * ns * nsplit;
   const long pad = (nwork + 7) / 8 * 8;
-  double* vt = (double*)((char*)partial + partial_only(g, nsplit));
+  double* vt = (double*)((char*)partial + partial_only(g, ns, nsplit));
   if (half)
-    hipLaunchKernelGGL(coulomb_vtab_half_kernel, dim3((unsigned)((a.ng + 255) / 256), g.nk),
+    hipLaunchKernelGGL(coulomb_vtab_half_kernel, dim3((unsigned)((a.ng + 255) / 256), ns),
                        dim3(256), 0, st, vt, a, hz);
   else
     hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), ns), dim3(256),

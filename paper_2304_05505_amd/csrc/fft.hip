@@ -423,6 +423,7 @@ struct TwistArgs {
   const double2* root[3];  // e^{-2 pi i t / (N_a n_a)}
   int n[3], N[3];
   int ni;
+  int m0;  // transfer of the first function (functions are N_ISDF per transfer)
 };
 
 template <typename TI, typename T>
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(NT1) void fft_yz_half_kernel(const TI* __restrict__
   const int n1 = ta.n[0];
   const long f = p / n1;
   const int g1 = (int)(p % n1);
-  const int m = (int)(f / ta.ni);
+  const int m = ta.m0 + (int)(f / ta.ni);
   const int m1 = m / (ta.N[1] * ta.N[2]), m2 = (m / ta.N[2]) % ta.N[1], m3 = m % ta.N[2];
   const double2 c0 = ta.root[0][(m1 * g1) % (ta.N[0] * n1)];
   for (int e = threadIdx.x; e < n2; e += NT1) {
@@ -583,7 +584,7 @@ int fft_half_z(const Geom& g) { return g.n[2] / 2 + 1; }
 
 template <typename TI, typename T>
 hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
-                             int ncu, hipStream_t st) {
+                             int m0, int ncu, hipStream_t st) {
   const int maxr = sizeof(T) == 8 ? 5 : 16;
   Plan1 px = plan_for(g.n[0], maxr), py = plan_for(g.n[1], maxr), pz = plan_for(g.n[2], maxr);
   const int hz = fft_half_z(g);
@@ -599,6 +600,7 @@ hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, vo
     ta.N[a] = g.N[a];
   }
   ta.ni = g.ni;
+  ta.m0 = m0;
   hipLaunchKernelGGL((fft_yz_half_kernel<TI, T>), dim3((unsigned)nplanes), dim3(NT1), lds1, st,
                      (const TI*)in, (cplx<T>*)out, py, pz, hz, ta, twp<T>(tb, 1), twp<T>(tb, 2));
   hipError_t e = hipGetLastError();
@@ -616,9 +618,9 @@ hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, vo
   return hipGetLastError();
 }
 template hipError_t launch_fft3d_half<double, double>(const Geom&, const Tables&, const void*,
-                                                      void*, long, int, hipStream_t);
+                                                      void*, long, int, int, hipStream_t);
 template hipError_t launch_fft3d_half<float, float>(const Geom&, const Tables&, const void*, void*,
-                                                    long, int, hipStream_t);
+                                                    long, int, int, hipStream_t);
 
 template hipError_t launch_fft3d<double>(const Geom&, const Tables&, const void*, void*, long,
                                          int, hipStream_t);
