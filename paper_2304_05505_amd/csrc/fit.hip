@@ -317,17 +317,21 @@ __global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no
   const int nks = ((no + 3) / 4 + NPF - 1) / NPF * NPF;
   cplx<T> fa[NPF];
   cplx<T> fb[NPF][WN];
+  // k-point bases are wave-uniform (scalar registers); lane offsets are 32-bit
+  // (the launcher checks N_ISDF n_occ and n_occ N_g against 2^31)
+  const unsigned aoff = (unsigned)ra * (unsigned)no, ng32 = (unsigned)ng;
   auto load = [&](int n, int ks, cplx<T>& xa, cplx<T>* xb) {
     if (ks >= nks) {  // first steps of the next k-point (clamped past the last)
       ks -= nks;
       n = n + 1 < NK ? n + 1 : NK - 1;
     }
+    const cplx<T>* An = occ + (long)n * ni * no;
+    const cplx<T>* Bn = psi + (long)n * no * ng;
     const int k = 4 * ks + lk;
     const unsigned kc = (unsigned)(k < no ? k : no - 1);
-    xa = occ[((long)n * ni + ra) * no + kc];
-    const cplx<T>* Bn = psi + (long)n * no * ng + (long)kc * ng;
+    xa = An[aoff + kc];
 #pragma unroll
-    for (int j = 0; j < WN; ++j) xb[j] = Bn[boff[j]];
+    for (int j = 0; j < WN; ++j) xb[j] = Bn[kc * ng32 + boff[j]];
   };
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(0, s, fa[s], fb[s]);
@@ -490,7 +494,8 @@ hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, v
   const long nct = ((long)g.ng + 16 * WN - 1) / (16 * WN);
   const long ntiles = nrt * nct;
   const long pad = (ntiles + 7) / 8 * 8;
-  if ((long)g.no * g.ng >= 0x7fffffffL) return hipErrorInvalidValue;
+  if ((long)g.no * g.ng >= 0x7fffffffL || (long)g.ni * g.no >= 0x7fffffffL)
+    return hipErrorInvalidValue;
 #define EXX_GKLAUNCH(a, b, c)                                                                    \
   if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                               \
     hipLaunchKernelGGL((gamma_kcorr_kernel<T, TZ, a, b, c, WN>), dim3((unsigned)pad), dim3(256), \
