@@ -306,6 +306,17 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
 // The factorisation chain of the metric (many short launches) runs on the
 // caller's stream and the grid-sized Gamma and Z~ on the handle's second
 // stream; the solve waits for both.
+//
+// When Z~ and the transform share one storage type (FP64, FP32) the solve is
+// split at the factor: with S~^+ = W^T W (W the inverted Cholesky factor, lower
+// triangular in point order) the grid-sized product is Y = W Z~, half the
+// multiply-adds of S~^+ Z~; Y is transformed and contracted like eta, giving
+// Vy = sum_G v Re(HY_P conj HY_Q), and Vb = W^T Vy W by two small products.
+// Rounding of Y, of its transform and of Vy reaches Vb amplified by the norm of
+// W on each side, i.e. by cond(S~) once, as rounding of Z~ does in the eta
+// form. With Z~ in FP64 and eta stored in FP32 (MIXED) the eta form is kept:
+// there FP32 storage of Y would add a sqrt(cond) amplification that the
+// FP32 storage of eta does not have.
 template <typename TF, typename TZ, typename TX>
 exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                             const Layout& L, const void* psi, const void* occ, const int32_t* pts,
@@ -347,11 +358,12 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
       if (e != hipSuccess) what = "cholesky";
     }
   }
+  constexpr bool split = std::is_same<TZ, TX>::value;  // Y = W Z~ (see above)
   if (!what) {
     PhaseTimer pt(h, PH_PINV, ax);
     e = launch_tri_inv_blocked(g, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
     if (e != hipSuccess) what = "triangular inverse";
-    if (!what) {
+    if (!what && !split) {
       e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,
                                                g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
       if (e != hipSuccess) what = "S+ gemm";
@@ -391,8 +403,8 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   if (ew != hipSuccess) return hip_check(h, ew, "join wait");
   {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = dgemm_nn_grid<TZ, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, grid2, g.ng, (long)g.ni * g.ng,
-                              grid, g.ng, (long)g.ni * g.ng, st);
+    e = dgemm_nn_grid<TZ, TX>(g.ni, g.ng, g.ni, g.nk, split ? W : Sp, g.ni, nn, grid2, g.ng,
+                              (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, st, split);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
   {
@@ -403,6 +415,17 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   {
     PhaseTimer pt(h, PH_COULOMB, st);
     e = launch_coulomb<TX>(g, tb, grid2, pts, ws + L.cpart, L.nsplit, (double2*)V, true, st);
+    if (e == hipSuccess && split) {
+      // Vb = W^T Vy W: T = Vy W (real, in the S~^+ scratch), then Vb = W^T T
+      const int n = g.ni;
+      double* T = (double*)Sp;
+      StridedGemm p1{2 * nn, 2 * nn, nn, 2 * n, 2, 2 * n, 2, n, 1, n, n, n};
+      e = dgemm_strided(p1, g.nk, (const double*)V, (const double*)W, T, false, st);
+      if (e == hipSuccess) {
+        StridedGemm p2{2 * nn, nn, 2 * nn, 2, 2 * n, n, 1, 2 * n, 2, n, n, n};
+        e = dgemm_strided(p2, g.nk, (const double*)W, T, (double*)V, true, st);
+      }
+    }
   }
   if (e != hipSuccess) return hip_check(h, e, "coulomb");
   return EXX_OK;

@@ -206,11 +206,26 @@ hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long l
                           bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                           hipStream_t st);
 
-// real form: C[b] = Re(A[b]) B[b], A (M x K) c128, B (K x N) real TB, C real TC
+// real form: C[b] = Re(A[b]) B[b], A (M x K) c128, B (K x N) real TB, C real TC;
+// lower: A is lower triangular (each 64-row band stops at its diagonal)
 template <typename TB, typename TC>
 hipError_t dgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          const void* B, long ldb, long sB, void* C, long ldc, long sC,
-                         hipStream_t st);
+                         hipStream_t st, bool lower = false);
+
+// Small real FP64 product C[b] = A[b] B[b] (M x K times K x N) with operands given
+// by element strides in doubles: A(r, k) = A[b sA + r ar + k ak], B(k, c) =
+// B[b sB + k bk + c bc], C(r, c) = C[b sC + r cr + c cc]. Strided views cover
+// transposes and the real parts of complex storage. cplx_out: C is complex
+// storage (cr, cc, sC even) and gets (x, 0). Offsets within one batch item are
+// 32-bit. Invalid strides return hipErrorInvalidValue.
+struct StridedGemm {
+  long sA, sB, sC;
+  int ar, ak, bk, bc, cr, cc;
+  int M, N, K;
+};
+hipError_t dgemm_strided(const StridedGemm& s, int batch, const double* A, const double* B,
+                         double* C, bool cplx_out, hipStream_t st);
 // C[b] = C[b] + sign * A[b] * B[b] (sign = +1 or -1), same operands as zgemm_nn_grid
 // (tile 22, no conjugation); used by the iterative refinement of the fit
 template <typename TB, typename TC>

@@ -285,7 +285,9 @@ __global__ __launch_bounds__(256) void cgemm_nn_mfma32(int M, int N, int K, int 
 // FP64 MFMA per block and k-step. Wave tile 4 x 4 blocks (64 x 64); the four
 // waves of a workgroup take consecutive column strips of one 64-row band, so
 // they share the A rows through L1. Same register pipeline as zgemm_nn_mfma.
-template <typename TB, typename TC>
+// LOWER: A is lower triangular (zero above its diagonal), so the band of rows
+// [r0, r0 + 64) stops its k loop at r0 + 64.
+template <typename TB, typename TC, int LOWER>
 __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nrt, long ntiles,
                                                      long ntiles_pad, const double2* __restrict__ A,
                                                      long lda, long sA, const TB* __restrict__ B,
@@ -304,6 +306,7 @@ __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nr
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = rt * (WM * 16);
   const long col0 = ct * (4 * WN * 16) + wave * (WN * 16);
+  const int Kb = LOWER ? min(K, row0 + WM * 16) : K;
   d4 acc[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
@@ -335,11 +338,11 @@ __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nr
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
   __builtin_amdgcn_s_waitcnt(0);  // as in zgemm_nn_mfma
-  const int niter = (K + 4 * NPF - 1) / (4 * NPF);
+  const int niter = (Kb + 4 * NPF - 1) / (4 * NPF);
   for (int it = 0; it < niter; ++it) {
 #pragma unroll
     for (int s = 0; s < NPF; ++s) {
-      const bool kin = 4 * (it * NPF + s) + lk < K;
+      const bool kin = 4 * (it * NPF + s) + lk < Kb;
       double bv[WN];
 #pragma unroll
       for (int j = 0; j < WN; ++j) bv[j] = (double)fb[s][j];
@@ -446,27 +449,119 @@ hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long l
 template <typename TB, typename TC>
 hipError_t dgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          const void* B, long ldb, long sB, void* C, long ldc, long sC,
-                         hipStream_t st) {
+                         hipStream_t st, bool lower) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (!offsets_fit(M, N, K, 2 * lda, ldb)) return hipErrorInvalidValue;
   const int nrt = (M + 63) / 64;
   const long nct = ((long)N + 255) / 256;
   const long ntiles = nrt * nct;
   const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
-  hipLaunchKernelGGL((dgemm_nn_mfma<TB, TC>), dim3((unsigned)pad, batch), dim3(256), 0, st, M, N, K,
-                     nrt, ntiles, pad, (const double2*)A, lda, sA, (const TB*)B, ldb, sB, (TC*)C,
-                     ldc, sC);
+  if (lower)
+    hipLaunchKernelGGL((dgemm_nn_mfma<TB, TC, 1>), dim3((unsigned)pad, batch), dim3(256), 0, st, M,
+                       N, K, nrt, ntiles, pad, (const double2*)A, lda, sA, (const TB*)B, ldb, sB,
+                       (TC*)C, ldc, sC);
+  else
+    hipLaunchKernelGGL((dgemm_nn_mfma<TB, TC, 0>), dim3((unsigned)pad, batch), dim3(256), 0, st, M,
+                       N, K, nrt, ntiles, pad, (const double2*)A, lda, sA, (const TB*)B, ldb, sB,
+                       (TC*)C, ldc, sC);
   return hipGetLastError();
 }
 template hipError_t dgemm_nn_grid<double, double>(int, int, int, int, const void*, long, long,
                                                   const void*, long, long, void*, long, long,
-                                                  hipStream_t);
+                                                  hipStream_t, bool);
 template hipError_t dgemm_nn_grid<double, float>(int, int, int, int, const void*, long, long,
                                                  const void*, long, long, void*, long, long,
-                                                 hipStream_t);
+                                                 hipStream_t, bool);
 template hipError_t dgemm_nn_grid<float, float>(int, int, int, int, const void*, long, long,
                                                 const void*, long, long, void*, long, long,
-                                                hipStream_t);
+                                                hipStream_t, bool);
+
+namespace {
+
+// Small real FP64 products C[b] = A[b] B[b] with every operand addressed by
+// element strides (a view may be the real parts of complex storage or a
+// transpose). Workgroup tile 64 x 64 of four 32 x 32 wave tiles; operands are
+// read from global memory (they are small and stay in L2), four k-steps in
+// flight per wave. CPLX: C is complex storage and gets (x, 0).
+template <int CPLX>
+__global__ __launch_bounds__(256) void dgemm_strided_kernel(const double* __restrict__ A,
+                                                            const double* __restrict__ B,
+                                                            double* __restrict__ C,
+                                                            StridedGemm s) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int col0 = blockIdx.x * 64 + (wave & 1) * 32;
+  const long b = blockIdx.z;
+  A += b * s.sA;
+  B += b * s.sB;
+  C += b * s.sC;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < s.K; k0 += 16) {
+    double a[4][2], bv[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + lk;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = row0 + i * 16 + li;
+        a[u][i] = (r < s.M && k < s.K) ? A[r * s.ar + k * s.ak] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = col0 + j * 16 + li;
+        bv[u][j] = (c < s.N && k < s.K) ? B[k * s.bk + c * s.bc] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma64(a[u][i], bv[u][j], acc[i][j]);
+  }
+  // register v of a lane holds row 4 v + lane/16, column lane%16 of a block
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + i * 16 + 4 * v + lk;
+        const int c = col0 + j * 16 + li;
+        if (r >= s.M || c >= s.N) continue;
+        const long o = r * s.cr + c * s.cc;
+        if (CPLX)
+          *(double2*)(C + o) = make_double2(acc[i][j][v], 0.0);
+        else
+          C[o] = acc[i][j][v];
+      }
+}
+
+}  // namespace
+
+hipError_t dgemm_strided(const StridedGemm& s, int batch, const double* A, const double* B,
+                         double* C, bool cplx_out, hipStream_t st) {
+  if (s.M <= 0 || s.N <= 0 || batch <= 0) return hipSuccess;
+  if (s.K <= 0 || (cplx_out && ((s.cr | s.cc | s.sC) & 1))) return hipErrorInvalidValue;
+  if (s.ar < 0 || s.ak < 0 || s.bk < 0 || s.bc < 0 || s.cr < 0 || s.cc < 0)
+    return hipErrorInvalidValue;
+  const long lim = 0x7fffffffL;
+  if ((long)(s.M - 1) * s.ar + (long)(s.K - 1) * s.ak >= lim ||
+      (long)(s.K - 1) * s.bk + (long)(s.N - 1) * s.bc >= lim ||
+      (long)(s.M - 1) * s.cr + (long)(s.N - 1) * s.cc + 1 >= lim)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((s.N + 63) / 64), (unsigned)((s.M + 63) / 64), (unsigned)batch);
+  if (cplx_out)
+    hipLaunchKernelGGL(dgemm_strided_kernel<1>, grid, dim3(256), 0, st, A, B, C, s);
+  else
+    hipLaunchKernelGGL(dgemm_strided_kernel<0>, grid, dim3(256), 0, st, A, B, C, s);
+  return hipGetLastError();
+}
 
 template <typename TB, typename TC>
 hipError_t zgemm_nn_grid_acc(int M, int N, int K, int batch, const void* A, long lda, long sA,
