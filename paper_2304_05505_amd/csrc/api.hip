@@ -435,6 +435,9 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
 // conjugates of those of m (relabelling n), so Vb^{-m} = conj Vb^m and the
 // Cholesky pivots (hence the ranks) agree. The paired path below fits and
 // contracts one transfer of each pair (rep, slice order), then writes both.
+// In FP64 and FP32 it splits the solve at the factor as the real path does:
+// Y = W Z on the grid (W lower triangular), the contraction of the transform of
+// Y gives Vy, and V^m = W^H Vy W before the Bloch phases are applied.
 struct Pairs {
   int n = 0;
   int rep[64], bar[64], slot[64];
@@ -501,11 +504,12 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
     e = launch_chol_blocked(gr, Lf, keep, rank_c, (double*)(ws + L.tol), 1e-12, ax);
     if (e != hipSuccess) what = "cholesky";
   }
+  constexpr bool split = std::is_same<TF, TX>::value;  // Y = W Z (as on the real path)
   if (!what) {
     PhaseTimer pt(h, PH_PINV, ax);
     e = launch_tri_inv_blocked(gr, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
     if (e != hipSuccess) what = "triangular inverse";
-    if (!what) {
+    if (!what && !split) {
       e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_C, W, g.ni, nn, B_N, W,
                                                g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
       if (e != hipSuccess) what = "S+ gemm";
@@ -543,8 +547,9 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   if (ew != hipSuccess) return hip_check(h, ew, "join wait");
   {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, gr.nk, Sp, g.ni, nn, false, grid, g.ng,
-                              (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve);
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, gr.nk, split ? W : Sp, g.ni, nn, false, grid,
+                              g.ng, (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st,
+                              h->tile_solve, split);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
   {
@@ -554,8 +559,27 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {
     PhaseTimer pt(h, PH_COULOMB, st);
-    e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st,
-                           pr.rep, pr.bar, pr.n);
+    if (!split) {
+      e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st,
+                             pr.rep, pr.bar, pr.n);
+    } else {
+      // Vy (unphased, slice order) into V, then V^m = W^H Vy W with T = Vy W in the
+      // S^+ scratch and the product in the consumed partial sums, then the phases
+      // and the conjugate partners
+      double2* Vy = (double2*)V;
+      double2* T = Sp;
+      double2* U = (double2*)(ws + L.cpart);
+      e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, Vy, false, st, pr.rep,
+                             pr.bar, pr.n, true);
+      if (e == hipSuccess)
+        e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_N, Vy, g.ni, nn, B_N,
+                                                 W, g.ni, nn, T, g.ni, nn, 1.0, false, st);
+      if (e == hipSuccess)
+        e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_C, W, g.ni, nn, B_N,
+                                                 T, g.ni, nn, U, g.ni, nn, 1.0, false, st);
+      if (e == hipSuccess)
+        e = launch_coulomb_phase(g, tb, pts, U, (double2*)V, pr.rep, pr.bar, pr.n, st);
+    }
   }
   if (e != hipSuccess) return hip_check(h, e, "coulomb");
   return EXX_OK;

@@ -195,11 +195,11 @@ hipError_t gemm(int M, int N, int K, int batch, OpA oa, const void* A, long lda,
 // C[b] = A[b] * op(B[b]) on the matrix cores in FP64: A (M x K) c128, B (K x N) and
 // C (M x N) row-major with storage types TB, TC; op = conj if conjB. `tile` picks the
 // wave tile in 16x16 blocks (22, 24 or 42; any other value means 24; workgroup =
-// 2 x 2 waves).
+// 2 x 2 waves). lower: A is lower triangular (each wave's rows stop at the diagonal).
 template <typename TB, typename TC>
 hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
-                         hipStream_t st, int tile);
+                         hipStream_t st, int tile, bool lower = false);
 
 // C[b] = A[b] * op(B[b]) on the FP32 matrix cores: A c128 (rounded to FP32), B and C c64
 hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long lda, long sA,
@@ -304,10 +304,19 @@ int fft_half_z(const Geom& g);
 // rep/bar/nslice (host arrays): F holds nslice transfers, slice s being transfer
 // rep[s]; V[rep[s]] is written and, where bar[s] >= 0, V[bar[s]] = conj V[rep[s]]
 // (bar[s] = -rep[s] on the mesh). rep == nullptr: slice m is transfer m.
+// raw: V[s] = the scaled sum of slice s, unphased (lower triangle mirrored), and
+// nothing else is written (the factor-split build applies W^H (.) W and then
+// launch_coulomb_phase).
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
                           void* partial, int nsplit, double2* V, bool half, hipStream_t st,
-                          const int* rep = nullptr, const int* bar = nullptr, int nslice = 0);
+                          const int* rep = nullptr, const int* bar = nullptr, int nslice = 0,
+                          bool raw = false);
+// V[rep[s]] = e^{-i q_m.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and, where
+// bar[s] >= 0, V[bar[s]] = conj of that; U holds nslice (<= 64) matrices
+hipError_t launch_coulomb_phase(const Geom& g, const Tables& tb, const int32_t* pts,
+                                const double2* U, double2* V, const int* rep, const int* bar,
+                                int nslice, hipStream_t st);
 size_t coulomb_partial_bytes(const Geom& g, int nsplit);
 int coulomb_nsplit(const Geom& g);
 

@@ -337,6 +337,7 @@ struct ReduceArgs {
   int N[3];
   int ni, nsplit;
   int real;
+  int raw;  // write the slice's scaled sum, unphased, to V[slice] and nothing else
   double scale;
   int rep[64];  // transfer of each slice
   int bar[64];  // its conjugate partner -m, written as conj(Vb^m); -1: none
@@ -364,6 +365,10 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __re
   if (!lower) sy = -sy;
   sx *= a.scale;
   sy *= a.scale;
+  if (a.raw) {
+    V[(long)sl * nn + idx] = make_double2(sx, sy);
+    return;
+  }
   if (a.real) {
     sy = 0.0;  // the real path's partials are already the Bloch-gauge matrix
   } else if (m) {
@@ -422,7 +427,7 @@ size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
                           void* partial, int nsplit, double2* V, bool half, hipStream_t st,
-                          const int* rep, const int* bar, int nslice) {
+                          const int* rep, const int* bar, int nslice, bool raw) {
   CoulArgs a;
   const int ns = rep ? nslice : g.nk;
   for (int m = 0; m < 64; ++m) a.rep[m] = rep && m < ns ? rep[m] : m;
@@ -482,6 +487,7 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   r.ni = g.ni;
   r.nsplit = nsplit;
   r.real = half ? 1 : 0;
+  r.raw = raw ? 1 : 0;
   r.scale = g.omega / ((double)g.ng * (double)g.ng);
   for (int m = 0; m < 64; ++m) {
     r.rep[m] = a.rep[m];
@@ -495,9 +501,36 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
 
 template hipError_t launch_coulomb<double>(const Geom&, const Tables&, const void*, const int32_t*,
                                            void*, int, double2*, bool, hipStream_t, const int*,
-                                           const int*, int);
+                                           const int*, int, bool);
 template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void*, const int32_t*,
                                           void*, int, double2*, bool, hipStream_t, const int*,
-                                          const int*, int);
+                                          const int*, int, bool);
+
+// V[rep[s]] = e^{-i q.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and
+// V[bar[s]] = conj of that, for the nslice unphased matrices U
+hipError_t launch_coulomb_phase(const Geom& g, const Tables& tb, const int32_t* pts,
+                                const double2* U, double2* V, const int* rep, const int* bar,
+                                int nslice, hipStream_t st) {
+  if (nslice <= 0 || nslice > 64) return hipErrorInvalidValue;
+  ReduceArgs r;
+  for (int i = 0; i < 3; ++i) {
+    r.root[i] = tb.root[i];
+    r.n[i] = g.n[i];
+    r.N[i] = g.N[i];
+  }
+  r.ni = g.ni;
+  r.nsplit = 1;
+  r.real = 0;
+  r.raw = 0;
+  r.scale = 1.0;
+  for (int m = 0; m < 64; ++m) {
+    r.rep[m] = m < nslice ? rep[m] : 0;
+    r.bar[m] = m < nslice ? bar[m] : -1;
+  }
+  const long nn = (long)g.ni * g.ni;
+  hipLaunchKernelGGL(coulomb_reduce_kernel, dim3((unsigned)((nn + 255) / 256), nslice), dim3(256),
+                     0, st, U, pts, V, r);
+  return hipGetLastError();
+}
 
 }  // namespace exx

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
                                                      long lda, long sA,
                                                      const cplx<TB>* __restrict__ B, long ldb,
                                                      long sB, cplx<TC>* __restrict__ C, long ldc,
-                                                     long sC) {
+                                                     long sC, int lower) {
   const long t = xcd_remap(blockIdx.x, ntiles_pad);
   if (t >= ntiles) return;
   const int rt = (int)(t % nrt);
@@ -52,6 +52,8 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = rt * (2 * WM * 16) + (wave & 1) * (WM * 16);
   const long col0 = ct * (2 * WN * 16) + (wave >> 1) * (WN * 16);
+  // lower: A is lower triangular, so this wave's rows need k < row0 + WM * 16
+  const int Kb = lower ? min(K, row0 + WM * 16) : K;
 
   // Gauss's three-product form of the complex product: T1 = Re A Re B,
   // T2 = Im A Im B, T3 = (Re A + Im A)(Re B + Im B); then Re C = T1 - T2 and
@@ -103,11 +105,11 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
   // loop head see only the loop's own refills (the differently ordered prologue
   // otherwise forces a full wait there on every iteration)
   __builtin_amdgcn_s_waitcnt(0);
-  const int niter = (K + 4 * NPF - 1) / (4 * NPF);
+  const int niter = (Kb + 4 * NPF - 1) / (4 * NPF);
   for (int it = 0; it < niter; ++it) {
 #pragma unroll
     for (int s = 0; s < NPF; ++s) {
-      const bool kin = 4 * (it * NPF + s) + lk < K;
+      const bool kin = 4 * (it * NPF + s) + lk < Kb;
       double br[WN], bi[WN], bs[WN];
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
@@ -380,28 +382,32 @@ __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nr
 
 template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC = 0>
 hipError_t run_nn(int M, int N, int K, int batch, const void* A, long lda, long sA, const void* B,
-                  long ldb, long sB, void* C, long ldc, long sC, hipStream_t st) {
+                  long ldb, long sB, void* C, long ldc, long sC, hipStream_t st,
+                  bool lower = false) {
   const int nrt = (M + 2 * WM * 16 - 1) / (2 * WM * 16);
   const long nct = ((long)N + 2 * WN * 16 - 1) / (2 * WN * 16);
   const long ntiles = nrt * nct;
   const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
   hipLaunchKernelGGL((zgemm_nn_mfma<TB, TC, WM, WN, CONJB, ACC>), dim3((unsigned)pad, batch), dim3(256),
                      0, st, M, N, K, nrt, ntiles, pad, (const double2*)A, lda, sA,
-                     (const cplx<TB>*)B, ldb, sB, (cplx<TC>*)C, ldc, sC);
+                     (const cplx<TB>*)B, ldb, sB, (cplx<TC>*)C, ldc, sC, lower ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename TB, typename TC, int CONJB>
 hipError_t run_nn_tile(int tile, int M, int N, int K, int batch, const void* A, long lda, long sA,
                        const void* B, long ldb, long sB, void* C, long ldc, long sC,
-                       hipStream_t st) {
+                       hipStream_t st, bool lower) {
   switch (tile) {
     case 22:
-      return run_nn<TB, TC, 2, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+      return run_nn<TB, TC, 2, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
+                                         lower);
     case 42:
-      return run_nn<TB, TC, 4, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+      return run_nn<TB, TC, 4, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
+                                         lower);
     default:
-      return run_nn<TB, TC, 2, 4, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+      return run_nn<TB, TC, 2, 4, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
+                                         lower);
   }
 }
 
@@ -417,12 +423,14 @@ bool offsets_fit(int M, int N, int K, long lda, long ldb) {
 template <typename TB, typename TC>
 hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
-                         hipStream_t st, int tile) {
+                         hipStream_t st, int tile, bool lower) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (!offsets_fit(M, N, K, lda, ldb)) return hipErrorInvalidValue;
   if (conjB)
-    return run_nn_tile<TB, TC, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
-  return run_nn_tile<TB, TC, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+    return run_nn_tile<TB, TC, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
+                                  lower);
+  return run_nn_tile<TB, TC, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
+                                lower);
 }
 
 hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long lda, long sA,
@@ -586,12 +594,12 @@ EXX_ACC_INST(float, float)
 
 template hipError_t zgemm_nn_grid<double, double>(int, int, int, int, const void*, long, long,
                                                   bool, const void*, long, long, void*, long, long,
-                                                  hipStream_t, int);
+                                                  hipStream_t, int, bool);
 template hipError_t zgemm_nn_grid<float, float>(int, int, int, int, const void*, long, long, bool,
                                                 const void*, long, long, void*, long, long,
-                                                hipStream_t, int);
+                                                hipStream_t, int, bool);
 template hipError_t zgemm_nn_grid<double, float>(int, int, int, int, const void*, long, long, bool,
                                                  const void*, long, long, void*, long, long,
-                                                 hipStream_t, int);
+                                                 hipStream_t, int, bool);
 
 }  // namespace exx
