@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no
   using M = GkMma<T>;
   using acc_t = typename M::acc;
   constexpr int NK = N1 * N2 * N3;
-  constexpr int NPF = 2;
+  constexpr int NPF = 3;
   const long per = ntiles_pad / 8;
   const long t = (blockIdx.x % 8) * per + blockIdx.x / 8;  // XCD-contiguous tile ranges
   if (t >= ntiles) return;
@@ -318,20 +318,22 @@ __global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no
   cplx<T> fa[NPF];
   cplx<T> fb[NPF][WN];
   // k-point bases are wave-uniform (scalar registers); lane offsets are 32-bit
-  // (the launcher checks N_ISDF n_occ and n_occ N_g against 2^31)
+  // byte offsets (the launcher checks the bytes of one k-point's occ and psi
+  // against 2^32), so the loads take a scalar base plus a vector offset
   const unsigned aoff = (unsigned)ra * (unsigned)no, ng32 = (unsigned)ng;
   auto load = [&](int n, int ks, cplx<T>& xa, cplx<T>* xb) {
     if (ks >= nks) {  // first steps of the next k-point (clamped past the last)
       ks -= nks;
       n = n + 1 < NK ? n + 1 : NK - 1;
     }
-    const cplx<T>* An = occ + (long)n * ni * no;
-    const cplx<T>* Bn = psi + (long)n * no * ng;
+    const char* An = (const char*)(occ + (long)n * ni * no);
+    const char* Bn = (const char*)(psi + (long)n * no * ng);
     const int k = 4 * ks + lk;
     const unsigned kc = (unsigned)(k < no ? k : no - 1);
-    xa = An[aoff + kc];
+    constexpr unsigned es = sizeof(cplx<T>);
+    xa = *(const cplx<T>*)(An + (aoff + kc) * es);
 #pragma unroll
-    for (int j = 0; j < WN; ++j) xb[j] = Bn[kc * ng32 + boff[j]];
+    for (int j = 0; j < WN; ++j) xb[j] = *(const cplx<T>*)(Bn + (kc * ng32 + boff[j]) * es);
   };
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(0, s, fa[s], fb[s]);
@@ -494,7 +496,8 @@ hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, v
   const long nct = ((long)g.ng + 16 * WN - 1) / (16 * WN);
   const long ntiles = nrt * nct;
   const long pad = (ntiles + 7) / 8 * 8;
-  if ((long)g.no * g.ng >= 0x7fffffffL || (long)g.ni * g.no >= 0x7fffffffL)
+  const long es = (long)sizeof(cplx<T>);
+  if ((long)g.no * g.ng * es >= 0xffffffffL || (long)g.ni * g.no * es >= 0xffffffffL)
     return hipErrorInvalidValue;
 #define EXX_GKLAUNCH(a, b, c)                                                                    \
   if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                               \
