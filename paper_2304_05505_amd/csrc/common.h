@@ -195,7 +195,8 @@ hipError_t gemm(int M, int N, int K, int batch, OpA oa, const void* A, long lda,
 // C[b] = A[b] * op(B[b]) on the matrix cores in FP64: A (M x K) c128, B (K x N) and
 // C (M x N) row-major with storage types TB, TC; op = conj if conjB. `tile` picks the
 // wave tile in 16x16 blocks (22, 24 or 42; any other value means 24; workgroup =
-// 2 x 2 waves). lower: A is lower triangular (each wave's rows stop at the diagonal).
+// 2 x 2 waves). lower: A is lower triangular (each wave's rows stop at the
+// diagonal); lower with conjB returns hipErrorInvalidValue.
 template <typename TB, typename TC>
 hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
@@ -207,7 +208,8 @@ hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long l
                           hipStream_t st);
 
 // real form: C[b] = Re(A[b]) B[b], A (M x K) c128, B (K x N) real TB, C real TC;
-// lower: A is lower triangular (each 64-row band stops at its diagonal)
+// lower: A is lower triangular (each 64-row band stops at its diagonal and skips
+// the 16-row blocks a k-step cannot reach)
 template <typename TB, typename TC>
 hipError_t dgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda, long sA,
                          const void* B, long ldb, long sB, void* C, long ldc, long sC,

@@ -33,13 +33,13 @@ __device__ __forceinline__ long xcd_remap(long bid, long total_padded) {
 
 // Wave tile: WM x WN blocks of 16x16; workgroup = 2 x 2 waves.
 // ACC = 0: C = A op(B); ACC = +1 / -1: C = C +/- A op(B) (arithmetic in FP64).
-template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC>
+template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC, int LOWER>
 __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nrt, long ntiles,
                                                      long ntiles_pad, const double2* __restrict__ A,
                                                      long lda, long sA,
                                                      const cplx<TB>* __restrict__ B, long ldb,
                                                      long sB, cplx<TC>* __restrict__ C, long ldc,
-                                                     long sC, int lower) {
+                                                     long sC) {
   const long t = xcd_remap(blockIdx.x, ntiles_pad);
   if (t >= ntiles) return;
   const int rt = (int)(t % nrt);
@@ -52,8 +52,10 @@ __global__ __launch_bounds__(256) void zgemm_nn_mfma(int M, int N, int K, int nr
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = rt * (2 * WM * 16) + (wave & 1) * (WM * 16);
   const long col0 = ct * (2 * WN * 16) + (wave >> 1) * (WN * 16);
-  // lower: A is lower triangular, so this wave's rows need k < row0 + WM * 16
-  const int Kb = lower ? min(K, row0 + WM * 16) : K;
+  // LOWER: A is lower triangular, so this wave's rows need k < row0 + WM * 16
+  // (skipping the blocks above the diagonal within that range was measured
+  // slower here: the branches cost more than the three-product MFMAs they save)
+  const int Kb = LOWER ? min(K, row0 + WM * 16) : K;
 
   // Gauss's three-product form of the complex product: T1 = Re A Re B,
   // T2 = Im A Im B, T3 = (Re A + Im A)(Re B + Im B); then Re C = T1 - T2 and
@@ -288,7 +290,8 @@ __global__ __launch_bounds__(256) void cgemm_nn_mfma32(int M, int N, int K, int 
 // waves of a workgroup take consecutive column strips of one 64-row band, so
 // they share the A rows through L1. Same register pipeline as zgemm_nn_mfma.
 // LOWER: A is lower triangular (zero above its diagonal), so the band of rows
-// [r0, r0 + 64) stops its k loop at r0 + 64.
+// [r0, r0 + 64) stops its k loop at r0 + 64 and skips the 16-row blocks that a
+// k-step cannot reach (above the diagonal, or past M).
 template <typename TB, typename TC, int LOWER>
 __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nrt, long ntiles,
                                                      long ntiles_pad, const double2* __restrict__ A,
@@ -348,8 +351,14 @@ __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nr
       double bv[WN];
 #pragma unroll
       for (int j = 0; j < WN; ++j) bv[j] = (double)fb[s][j];
+      const int kb = 4 * (it * NPF + s);  // this k-step's first column (wave-uniform)
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
+        // LOWER: a row block past M, or one whose rows all lie above this
+        // k-step's columns, contributes nothing; its MFMAs are skipped by a
+        // wave-uniform branch (the full product keeps its branch-free loop)
+        const int rb = row0 + i * 16;
+        if (LOWER && (rb >= M || kb > rb + 15)) continue;
         const double av = kin ? fa[s][i] : 0.0;
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = mfma64(av, bv[j], acc[i][j]);
@@ -380,34 +389,34 @@ __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nr
     }
 }
 
-template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC = 0>
+template <typename TB, typename TC, int WM, int WN, int CONJB, int ACC = 0, int LOWER = 0>
 hipError_t run_nn(int M, int N, int K, int batch, const void* A, long lda, long sA, const void* B,
-                  long ldb, long sB, void* C, long ldc, long sC, hipStream_t st,
-                  bool lower = false) {
+                  long ldb, long sB, void* C, long ldc, long sC, hipStream_t st) {
   const int nrt = (M + 2 * WM * 16 - 1) / (2 * WM * 16);
   const long nct = ((long)N + 2 * WN * 16 - 1) / (2 * WN * 16);
   const long ntiles = nrt * nct;
   const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
-  hipLaunchKernelGGL((zgemm_nn_mfma<TB, TC, WM, WN, CONJB, ACC>), dim3((unsigned)pad, batch), dim3(256),
+  hipLaunchKernelGGL((zgemm_nn_mfma<TB, TC, WM, WN, CONJB, ACC, LOWER>), dim3((unsigned)pad, batch),
+                     dim3(256),
                      0, st, M, N, K, nrt, ntiles, pad, (const double2*)A, lda, sA,
-                     (const cplx<TB>*)B, ldb, sB, (cplx<TC>*)C, ldc, sC, lower ? 1 : 0);
+                     (const cplx<TB>*)B, ldb, sB, (cplx<TC>*)C, ldc, sC);
   return hipGetLastError();
 }
 
-template <typename TB, typename TC, int CONJB>
+template <typename TB, typename TC, int CONJB, int LOWER>
 hipError_t run_nn_tile(int tile, int M, int N, int K, int batch, const void* A, long lda, long sA,
                        const void* B, long ldb, long sB, void* C, long ldc, long sC,
-                       hipStream_t st, bool lower) {
+                       hipStream_t st) {
   switch (tile) {
     case 22:
-      return run_nn<TB, TC, 2, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
-                                         lower);
+      return run_nn<TB, TC, 2, 2, CONJB, 0, LOWER>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc,
+                                                   sC, st);
     case 42:
-      return run_nn<TB, TC, 4, 2, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
-                                         lower);
+      return run_nn<TB, TC, 4, 2, CONJB, 0, LOWER>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc,
+                                                   sC, st);
     default:
-      return run_nn<TB, TC, 2, 4, CONJB>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
-                                         lower);
+      return run_nn<TB, TC, 2, 4, CONJB, 0, LOWER>(M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc,
+                                                   sC, st);
   }
 }
 
@@ -426,11 +435,12 @@ hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
                          hipStream_t st, int tile, bool lower) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (!offsets_fit(M, N, K, lda, ldb)) return hipErrorInvalidValue;
+  if (conjB && lower) return hipErrorInvalidValue;  // not instantiated
   if (conjB)
-    return run_nn_tile<TB, TC, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
-                                  lower);
-  return run_nn_tile<TB, TC, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st,
-                                lower);
+    return run_nn_tile<TB, TC, 1, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+  if (lower)
+    return run_nn_tile<TB, TC, 0, 1>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
+  return run_nn_tile<TB, TC, 0, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
 }
 
 hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long lda, long sA,
