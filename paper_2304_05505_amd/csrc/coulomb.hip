@@ -331,6 +331,146 @@ __global__ __launch_bounds__(64) void coulomb_kernel_f32(const float2* __restric
   }
 }
 
+// Real path, FP32-stored half-grid transform with an even number of points: one
+// wave per 64 x 64 tile (4 x 4 blocks of 16 x 16) of the lower triangle, which
+// halves the operand loads per MFMA and the re-reads of F against 32 x 32
+// tiles. NR: block rows that hold rows below N_ISDF (1..4); DIAG: a diagonal
+// tile, whose column operand rows are its row operand rows and whose blocks
+// above the diagonal are skipped. Accumulates Re(X conj Y) = Re X Re Y +
+// Im X Im Y in FP64 (two MFMAs per block and k-step); a lane loads two
+// consecutive grid values of a row as one 16-byte load.
+template <int NR, bool DIAG>
+__device__ __forceinline__ void coulomb_tile64_re(const float2* __restrict__ Fm,
+                                                  const double* __restrict__ vm,
+                                                  double2* __restrict__ out, const CoulArgs& a,
+                                                  int P0, int Q0, long g0, long g1,
+                                                  double* stage) {
+  constexpr int NPF = 2, TPL = 2, CK = 4 * TPL;
+  constexpr int NC = DIAG ? NR : 4;  // column blocks read
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, gq = lane >> 4;
+  unsigned xrow[NR], yrow[NC];
+#pragma unroll
+  for (int i = 0; i < NR; ++i)
+    xrow[i] = (unsigned)min(P0 + 16 * i + li, a.ni - 1) * (unsigned)a.ng;
+#pragma unroll
+  for (int j = 0; j < NC; ++j)
+    yrow[j] = (unsigned)min(Q0 + 16 * j + li, a.ni - 1) * (unsigned)a.ng;
+  d4v acc[NR][NC];
+#pragma unroll
+  for (int i = 0; i < NR; ++i)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[i][j] = d4v{0, 0, 0, 0};
+  float4 fx[NPF][NR], fy[NPF][DIAG ? 1 : NC];
+  double2 fv[NPF];
+  auto load = [&](long k0, float4* xx, float4* yy, double2& vv) {
+    // the lane's grid index is even; past the end the base is clamped to
+    // N_g - 2 and the values are discarded (v = 0 at use)
+    const unsigned g = (unsigned)min(k0 + TPL * gq, (long)a.ng - 2);
+    vv = *(const double2*)(vm + g);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) xx[i] = *(const float4*)(Fm + xrow[i] + g);
+    if constexpr (!DIAG) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) yy[j] = *(const float4*)(Fm + yrow[j] + g);
+    }
+  };
+  const long nchunk = (g1 - g0 + CK - 1) / CK;
+#pragma unroll
+  for (int sl = 0; sl < NPF; ++sl) load(g0 + (long)sl * CK, fx[sl], fy[sl], fv[sl]);
+  __builtin_amdgcn_s_waitcnt(0);  // as in coulomb_wave_tile
+  for (long c = 0; c < nchunk; c += NPF) {
+#pragma unroll
+    for (int sl = 0; sl < NPF; ++sl) {
+      const long k0 = g0 + (c + sl) * CK;
+      const long gb = k0 + TPL * gq;
+#pragma unroll
+      for (int t = 0; t < TPL; ++t) {
+        const double vv = (gb + t < g1) ? (t ? fv[sl].y : fv[sl].x) : 0.0;
+        double yr[NC], yi[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float4 q = DIAG ? fx[sl][j] : fy[sl][DIAG ? 0 : j];
+          yr[j] = (double)(t ? q.z : q.x);
+          yi[j] = (double)(t ? q.w : q.y);
+        }
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          const float4 q = fx[sl][i];
+          const double xr = (double)(t ? q.z : q.x) * vv, xi = (double)(t ? q.w : q.y) * vv;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            if (DIAG && j > i) continue;
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yi[j], acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      load(k0 + NPF * CK, fx[sl], fy[sl], fv[sl]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // register v of a lane holds row 4 v + lane/16 of a block; each lane
+  // round-trips its own values through the wave's LDS slice (keeps the
+  // accumulators in matrix registers during the loop)
+  typedef __attribute__((address_space(3))) volatile double lds_f64;
+  lds_f64* s1 = (lds_f64*)stage;
+#pragma unroll
+  for (int i = 0; i < NR; ++i)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      if (DIAG && j > i) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) s1[v * 64 + lane] = acc[i][j][v];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int P = P0 + 16 * i + 4 * v + gq;
+        const int Q = Q0 + 16 * j + li;
+        const double x = s1[v * 64 + lane];
+        if (P < a.ni && Q < a.ni) out[(long)P * a.ni + Q] = make_double2(x, 0.0);
+      }
+    }
+}
+
+// one wave per (transfer, grid split, 64 x 64 lower-triangle tile)
+__global__ __launch_bounds__(64) void coulomb_kernel_f32_t64(const float2* __restrict__ F,
+                                                             const double* __restrict__ vt,
+                                                             double2* __restrict__ part,
+                                                             CoulArgs a, long nwork,
+                                                             long nwork_pad) {
+  const long w = (blockIdx.x % 8) * (nwork_pad / 8) + blockIdx.x / 8;
+  if (w >= nwork) return;
+  int m, s, ti, tj;
+  coulomb_work(w, a, m, s, ti, tj);
+  const int P0 = ti * 64, Q0 = tj * 64;
+  const long g0 = (long)s * a.chunk;
+  const long g1 = min((long)a.ng, g0 + a.chunk);
+  const float2* Fm = F + (long)m * a.ni * a.ng;
+  const double* vm = vt + (long)m * a.ng;
+  double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
+  __shared__ double stage[64 * 4];
+  const int nr = min(4, (a.ni - P0 + 15) / 16);
+#define EXX_T64(R)                                                                 \
+  case R:                                                                          \
+    if (ti == tj)                                                                  \
+      coulomb_tile64_re<R, true>(Fm, vm, out, a, P0, Q0, g0, g1, stage);           \
+    else                                                                           \
+      coulomb_tile64_re<R, false>(Fm, vm, out, a, P0, Q0, g0, g1, stage);          \
+    break;
+  switch (nr) {
+    EXX_T64(1)
+    EXX_T64(2)
+    EXX_T64(3)
+    default:
+      if (ti == tj)
+        coulomb_tile64_re<4, true>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+      else
+        coulomb_tile64_re<4, false>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+  }
+#undef EXX_T64
+}
+
 struct ReduceArgs {
   const double2* root[3];
   int n[3];
@@ -442,8 +582,11 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.nk = ns;
   a.nsplit = nsplit;
   a.chunk = (int)((((long)a.ng + nsplit - 1) / nsplit + CALIGN - 1) / CALIGN * CALIGN);
-  // FP64 storage: 64 x 64 workgroup tiles; FP32 storage: 32 x 32 wave tiles
-  const int tw = sizeof(T) == 8 ? 2 * WTILE : WTILE;
+  const bool vec = a.ng % 2 == 0;
+  // FP64 storage: 64 x 64 workgroup tiles; FP32 storage: 32 x 32 wave tiles, or
+  // 64 x 64 wave tiles on the real path with an even half grid
+  const bool t64 = sizeof(T) == 4 && half && vec;
+  const int tw = (sizeof(T) == 8 || t64) ? 2 * WTILE : WTILE;
   const int nt = (g.ni + tw - 1) / tw;
   a.ntile = nt * (nt + 1) / 2;
   if ((long)g.ni * a.ng >= 0x7fffffffL) return hipErrorInvalidValue;
@@ -458,7 +601,6 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
                        0, st, vt, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const bool vec = a.ng % 2 == 0;
 #define EXX_COUL(RE)                                                                            \
   if constexpr (sizeof(T) == 8) {                                                               \
     hipLaunchKernelGGL(coulomb_kernel_f64<RE>, dim3((unsigned)pad), dim3(256), 0, st,            \
@@ -470,7 +612,10 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
     hipLaunchKernelGGL((coulomb_kernel_f32<false, RE>), dim3((unsigned)pad), dim3(64), 0, st,    \
                        (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);   \
   }
-  if (half) {
+  if (t64) {
+    hipLaunchKernelGGL(coulomb_kernel_f32_t64, dim3((unsigned)pad), dim3(64), 0, st,
+                       (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+  } else if (half) {
     EXX_COUL(true)
   } else {
     EXX_COUL(false)
