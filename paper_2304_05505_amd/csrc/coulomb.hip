@@ -580,8 +580,6 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.ng = half ? g.n[0] * g.n[1] * hz : g.ng;
   a.ni = g.ni;
   a.nk = ns;
-  a.nsplit = nsplit;
-  a.chunk = (int)((((long)a.ng + nsplit - 1) / nsplit + CALIGN - 1) / CALIGN * CALIGN);
   const bool vec = a.ng % 2 == 0;
   // FP64 storage: 64 x 64 workgroup tiles; FP32 storage: 32 x 32 wave tiles, or
   // 64 x 64 wave tiles on the real path with an even half grid
@@ -589,6 +587,44 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   const int tw = (sizeof(T) == 8 || t64) ? 2 * WTILE : WTILE;
   const int nt = (g.ni + tw - 1) / tw;
   a.ntile = nt * (nt + 1) / 2;
+  // Grid splits: whole rounds of the kernel's resident workgroups (a work item
+  // runs for its whole chunk, so a last round that is mostly empty costs as
+  // much as a full one), within the scratch capacity (nsplit splits over N_k
+  // slices) and with chunks of at least ~1k points.
+  {
+    const void* kfn;
+    int threads = 64;
+    if (sizeof(T) == 8) {
+      kfn = half ? (const void*)coulomb_kernel_f64<true> : (const void*)coulomb_kernel_f64<false>;
+      threads = 256;
+    } else if (t64) {
+      kfn = (const void*)coulomb_kernel_f32_t64;
+    } else if (half) {
+      kfn = vec ? (const void*)coulomb_kernel_f32<true, true>
+                : (const void*)coulomb_kernel_f32<false, true>;
+    } else {
+      kfn = vec ? (const void*)coulomb_kernel_f32<true, false>
+                : (const void*)coulomb_kernel_f32<false, false>;
+    }
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, 0) == hipSuccess &&
+        ncu > 0 && per_cu > 0) {
+      const long slots = (long)ncu * per_cu;
+      const long per_split = (long)a.ntile * ns;
+      long cap = (long)nsplit * g.nk / ns;
+      const long maxs = ((long)a.ng + 1023) / 1024;
+      if (cap > maxs) cap = maxs;
+      const long rounds = cap * per_split / slots;
+      if (rounds >= 1) {
+        const long want = rounds * slots / per_split;
+        nsplit = (int)(want < 1 ? 1 : want);
+      }
+    }
+  }
+  a.nsplit = nsplit;
+  a.chunk = (int)((((long)a.ng + nsplit - 1) / nsplit + CALIGN - 1) / CALIGN * CALIGN);
   if ((long)g.ni * a.ng >= 0x7fffffffL) return hipErrorInvalidValue;
   const long nwork = (long)a.ntile * ns * nsplit;
   const long pad = (nwork + 7) / 8 * 8;
