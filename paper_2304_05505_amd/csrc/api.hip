@@ -354,14 +354,14 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     e = launch_copy(Lf, (const double2*)S, (long)g.nk * nn, ax);
     if (e != hipSuccess) what = "copy S";
     if (!what) {
-      e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax);
+      e = launch_chol_blocked_real(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax);
       if (e != hipSuccess) what = "cholesky";
     }
   }
   constexpr bool split = std::is_same<TZ, TX>::value;  // Y = W Z~ (see above)
   if (!what) {
     PhaseTimer pt(h, PH_PINV, ax);
-    e = launch_tri_inv_blocked(g, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
+    e = launch_tri_inv_real(g, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
     if (e != hipSuccess) what = "triangular inverse";
     if (!what && !split) {
       e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,

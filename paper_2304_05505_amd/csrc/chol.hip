@@ -260,4 +260,64 @@ hipError_t launch_tri_inv_blocked(const Geom& g, const double2* Lf, const int32_
   return hipSuccess;
 }
 
+// Real-path forms (the metric S~ is real, stored complex with a zero imaginary
+// part): the trailing updates and the off-diagonal blocks of the inverse run on
+// the real parts through the strided FP64 matrix-core product; the panel and
+// diagonal-block kernels are the complex ones, exact on real data.
+hipError_t launch_chol_blocked_real(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
+                                   double* tol, double rel_tol, hipStream_t st) {
+  const int n = g.ni;
+  const long nn = (long)n * n;
+  hipLaunchKernelGGL(chol_init_kernel, dim3(g.nk), dim3(PNT), 0, st, A, n, rel_tol, tol, rank);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double* Ad = (double*)A;
+  for (int c0 = 0; c0 < n; c0 += NB) {
+    const int w = n - c0 < NB ? n - c0 : NB;
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(g.nk), dim3(PNT), 0, st, A, n, c0, tol, keep, rank);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int r = n - c0 - w;
+    if (r <= 0) break;
+    // A22 -= L21 L21^T: L21(i, k) at row c0 + w + i, column c0 + k
+    const double* L21 = Ad + 2 * ((long)(c0 + w) * n + c0);
+    StridedGemm p{2 * nn, 2 * nn, 2 * nn, 2 * n, 2, 2, 2 * n, 2 * n, 2, r, r, w};
+    e = dgemm_strided(p, g.nk, L21, L21, Ad + 2 * ((long)(c0 + w) * n + c0 + w), true, st, -1.0,
+                      true);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_tri_inv_real(const Geom& g, const double2* Lf, const int32_t* keep, double2* W,
+                               double2* T, hipStream_t st) {
+  const int n = g.ni;
+  const long nn = (long)n * n;
+  const long total = (long)g.nk * nn;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, W, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nb = (n + NB - 1) / NB;
+  hipLaunchKernelGGL(diag_inv_kernel, dim3(nb, g.nk), dim3(PNT), 0, st, Lf, n, keep, W);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double* Ld = (const double*)Lf;
+  double* Wd = (double*)W;
+  double* Td = (double*)T;  // w x ci real per transfer, NB n doubles apart
+  for (int b = 1; b < nb; ++b) {
+    const int ci = b * NB;
+    const int w = n - ci < NB ? n - ci : NB;
+    // T = L[ci:ci+w, 0:ci] W[0:ci, 0:ci]
+    StridedGemm p1{2 * nn, 2 * nn, (long)NB * n, 2 * n, 2, 2 * n, 2, ci, 1, w, ci, ci};
+    e = dgemm_strided(p1, g.nk, Ld + 2 * (long)ci * n, Wd, Td, false, st);
+    if (e != hipSuccess) return e;
+    // W[ci:ci+w, 0:ci] = -W[ci:ci+w, ci:ci+w] T
+    StridedGemm p2{2 * nn, (long)NB * n, 2 * nn, 2 * n, 2, ci, 1, 2 * n, 2, w, ci, w};
+    e = dgemm_strided(p2, g.nk, Wd + 2 * ((long)ci * n + ci), Td, Wd + 2 * (long)ci * n, true, st,
+                      -1.0, false);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace exx

@@ -215,19 +215,21 @@ hipError_t dgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
                          const void* B, long ldb, long sB, void* C, long ldc, long sC,
                          hipStream_t st, bool lower = false);
 
-// Small real FP64 product C[b] = A[b] B[b] (M x K times K x N) with operands given
-// by element strides in doubles: A(r, k) = A[b sA + r ar + k ak], B(k, c) =
-// B[b sB + k bk + c bc], C(r, c) = C[b sC + r cr + c cc]. Strided views cover
-// transposes and the real parts of complex storage. cplx_out: C is complex
-// storage (cr, cc, sC even) and gets (x, 0). Offsets within one batch item are
-// 32-bit. Invalid strides return hipErrorInvalidValue.
+// Small real FP64 product C[b] = alpha A[b] B[b] (+ C[b] if acc), M x K times
+// K x N, with operands given by element strides in doubles: A(r, k) =
+// A[b sA + r ar + k ak], B(k, c) = B[b sB + k bk + c bc], C(r, c) =
+// C[b sC + r cr + c cc]. Strided views cover transposes and the real parts of
+// complex storage. cplx_out: C is complex storage (cr, cc, sC even) and gets
+// (x, 0). Offsets within one batch item are 32-bit. Invalid strides return
+// hipErrorInvalidValue.
 struct StridedGemm {
   long sA, sB, sC;
   int ar, ak, bk, bc, cr, cc;
   int M, N, K;
 };
 hipError_t dgemm_strided(const StridedGemm& s, int batch, const double* A, const double* B,
-                         double* C, bool cplx_out, hipStream_t st);
+                         double* C, bool cplx_out, hipStream_t st, double alpha = 1.0,
+                         bool acc = false);
 // C[b] = C[b] + sign * A[b] * B[b] (sign = +1 or -1), same operands as zgemm_nn_grid
 // (tile 22, no conjugation); used by the iterative refinement of the fit
 template <typename TB, typename TC>
@@ -283,6 +285,13 @@ hipError_t launch_rank_scatter(const int32_t* rc, int32_t* rank, const int* rep,
 // tol: [N_k] scratch) and blocked inverse W = L^{-1} (T: [N_k][32][N_I] scratch)
 hipError_t launch_chol_blocked(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
                                double* tol, double rel_tol, hipStream_t st);
+// real-path forms of launch_chol_blocked and launch_tri_inv_blocked (S~ real,
+// complex storage): same results, with the GEMMs on the real parts (strided FP64
+// matrix-core product)
+hipError_t launch_chol_blocked_real(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
+                                   double* tol, double rel_tol, hipStream_t st);
+hipError_t launch_tri_inv_real(const Geom& g, const double2* Lf, const int32_t* keep, double2* W,
+                               double2* T, hipStream_t st);
 hipError_t launch_tri_inv_blocked(const Geom& g, const double2* Lf, const int32_t* keep,
                                   double2* W, double2* T, hipStream_t st);
 

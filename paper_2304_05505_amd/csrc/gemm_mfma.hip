@@ -496,16 +496,16 @@ template hipError_t dgemm_nn_grid<float, float>(int, int, int, int, const void*,
 
 namespace {
 
-// Small real FP64 products C[b] = A[b] B[b] with every operand addressed by
-// element strides (a view may be the real parts of complex storage or a
-// transpose). Workgroup tile 64 x 64 of four 32 x 32 wave tiles; operands are
-// read from global memory (they are small and stay in L2), four k-steps in
-// flight per wave. CPLX: C is complex storage and gets (x, 0).
-template <int CPLX>
+// Small real FP64 products C[b] = alpha A[b] B[b] (+ C[b] with ACC) with every
+// operand addressed by element strides (a view may be the real parts of complex
+// storage or a transpose). Workgroup tile 64 x 64 of four 32 x 32 wave tiles;
+// operands are read from global memory (they are small and stay in L2), four
+// k-steps in flight per wave. CPLX: C is complex storage and gets (x, 0).
+template <int CPLX, int ACC>
 __global__ __launch_bounds__(256) void dgemm_strided_kernel(const double* __restrict__ A,
                                                             const double* __restrict__ B,
                                                             double* __restrict__ C,
-                                                            StridedGemm s) {
+                                                            StridedGemm s, double alpha) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = blockIdx.y * 64 + (wave >> 1) * 32;
@@ -553,17 +553,18 @@ __global__ __launch_bounds__(256) void dgemm_strided_kernel(const double* __rest
         const int c = col0 + j * 16 + li;
         if (r >= s.M || c >= s.N) continue;
         const long o = r * s.cr + c * s.cc;
+        const double x = alpha * acc[i][j][v] + (ACC ? C[o] : 0.0);
         if (CPLX)
-          *(double2*)(C + o) = make_double2(acc[i][j][v], 0.0);
+          *(double2*)(C + o) = make_double2(x, 0.0);
         else
-          C[o] = acc[i][j][v];
+          C[o] = x;
       }
 }
 
 }  // namespace
 
 hipError_t dgemm_strided(const StridedGemm& s, int batch, const double* A, const double* B,
-                         double* C, bool cplx_out, hipStream_t st) {
+                         double* C, bool cplx_out, hipStream_t st, double alpha, bool acc) {
   if (s.M <= 0 || s.N <= 0 || batch <= 0) return hipSuccess;
   if (s.K <= 0 || (cplx_out && ((s.cr | s.cc | s.sC) & 1))) return hipErrorInvalidValue;
   if (s.ar < 0 || s.ak < 0 || s.bk < 0 || s.bc < 0 || s.cr < 0 || s.cc < 0)
@@ -574,10 +575,20 @@ hipError_t dgemm_strided(const StridedGemm& s, int batch, const double* A, const
       (long)(s.M - 1) * s.cr + (long)(s.N - 1) * s.cc + 1 >= lim)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)((s.N + 63) / 64), (unsigned)((s.M + 63) / 64), (unsigned)batch);
-  if (cplx_out)
-    hipLaunchKernelGGL(dgemm_strided_kernel<1>, grid, dim3(256), 0, st, A, B, C, s);
-  else
-    hipLaunchKernelGGL(dgemm_strided_kernel<0>, grid, dim3(256), 0, st, A, B, C, s);
+#define EXX_STRIDED(CX, AC)                                                                  \
+  hipLaunchKernelGGL((dgemm_strided_kernel<CX, AC>), grid, dim3(256), 0, st, A, B, C, s, alpha)
+  if (cplx_out) {
+    if (acc)
+      EXX_STRIDED(1, 1);
+    else
+      EXX_STRIDED(1, 0);
+  } else {
+    if (acc)
+      EXX_STRIDED(0, 1);
+    else
+      EXX_STRIDED(0, 0);
+  }
+#undef EXX_STRIDED
   return hipGetLastError();
 }
 
