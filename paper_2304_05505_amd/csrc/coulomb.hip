@@ -331,22 +331,24 @@ __global__ __launch_bounds__(64) void coulomb_kernel_f32(const float2* __restric
   }
 }
 
-// Real path, FP32-stored half-grid transform with an even number of points: one
-// wave per 64 x 64 tile (4 x 4 blocks of 16 x 16) of the lower triangle, which
-// halves the operand loads per MFMA and the re-reads of F against 32 x 32
-// tiles. NR: block rows that hold rows below N_ISDF (1..4); DIAG: a diagonal
-// tile, whose column operand rows are its row operand rows and whose blocks
-// above the diagonal are skipped. Accumulates Re(X conj Y) = Re X Re Y +
-// Im X Im Y in FP64 (two MFMAs per block and k-step); a lane loads two
-// consecutive grid values of a row as one 16-byte load.
-template <int NR, bool DIAG>
-__device__ __forceinline__ void coulomb_tile64_re(const float2* __restrict__ Fm,
+// Real path: one wave per 64 x 64 tile (4 x 4 blocks of 16 x 16) of the lower
+// triangle, which halves the operand loads per MFMA and the re-reads of F
+// against 32 x 32 tiles. T: storage of the half-grid transform; a lane loads 16
+// bytes of a row per k-step (two consecutive FP32 values, which needs an even
+// number of points, or one FP64 value). NR: block rows that hold rows below
+// N_ISDF (1..4); DIAG: a diagonal tile, whose column operand rows are its row
+// operand rows and whose blocks above the diagonal are skipped. Accumulates
+// Re(X conj Y) = Re X Re Y + Im X Im Y in FP64 (two MFMAs per block and value).
+template <typename T, int NR, bool DIAG>
+__device__ __forceinline__ void coulomb_tile64_re(const cplx<T>* __restrict__ Fm,
                                                   const double* __restrict__ vm,
                                                   double2* __restrict__ out, const CoulArgs& a,
                                                   int P0, int Q0, long g0, long g1,
                                                   double* stage) {
-  constexpr int NPF = 2, TPL = 2, CK = 4 * TPL;
+  constexpr int TPL = 16 / sizeof(cplx<T>);  // grid values per lane and k-step
+  constexpr int NPF = 2, CK = 4 * TPL;
   constexpr int NC = DIAG ? NR : 4;  // column blocks read
+  using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, gq = lane >> 4;
   unsigned xrow[NR], yrow[NC];
@@ -361,19 +363,34 @@ __device__ __forceinline__ void coulomb_tile64_re(const float2* __restrict__ Fm,
   for (int i = 0; i < NR; ++i)
 #pragma unroll
     for (int j = 0; j < NC; ++j) acc[i][j] = d4v{0, 0, 0, 0};
-  float4 fx[NPF][NR], fy[NPF][DIAG ? 1 : NC];
-  double2 fv[NPF];
-  auto load = [&](long k0, float4* xx, float4* yy, double2& vv) {
-    // the lane's grid index is even; past the end the base is clamped to
-    // N_g - 2 and the values are discarded (v = 0 at use)
-    const unsigned g = (unsigned)min(k0 + TPL * gq, (long)a.ng - 2);
-    vv = *(const double2*)(vm + g);
+  V fx[NPF][NR], fy[NPF][DIAG ? 1 : NC];
+  double fv[NPF][TPL];
+  // the lane's first grid index; past the end the base is clamped to N_g - TPL
+  // and the values are discarded (v = 0 at use)
+  auto load = [&](long k0, V* xx, V* yy, double* vv) {
+    const unsigned g = (unsigned)min(k0 + TPL * gq, (long)a.ng - TPL);
+    if constexpr (TPL == 2) {
+      const double2 v2 = *(const double2*)(vm + g);
+      vv[0] = v2.x;
+      vv[1] = v2.y;
+    } else {
+      vv[0] = vm[g];
+    }
 #pragma unroll
-    for (int i = 0; i < NR; ++i) xx[i] = *(const float4*)(Fm + xrow[i] + g);
+    for (int i = 0; i < NR; ++i) xx[i] = *(const V*)(Fm + xrow[i] + g);
     if constexpr (!DIAG) {
 #pragma unroll
-      for (int j = 0; j < NC; ++j) yy[j] = *(const float4*)(Fm + yrow[j] + g);
+      for (int j = 0; j < NC; ++j) yy[j] = *(const V*)(Fm + yrow[j] + g);
     }
+  };
+  // value t of a lane's 16 bytes as (re, im) in FP64
+  auto re = [](const V& q, int t) -> double {
+    if constexpr (sizeof(T) == 4) return (double)(t ? q.z : q.x);
+    else return q.x;
+  };
+  auto im = [](const V& q, int t) -> double {
+    if constexpr (sizeof(T) == 4) return (double)(t ? q.w : q.y);
+    else return q.y;
   };
   const long nchunk = (g1 - g0 + CK - 1) / CK;
 #pragma unroll
@@ -386,18 +403,17 @@ __device__ __forceinline__ void coulomb_tile64_re(const float2* __restrict__ Fm,
       const long gb = k0 + TPL * gq;
 #pragma unroll
       for (int t = 0; t < TPL; ++t) {
-        const double vv = (gb + t < g1) ? (t ? fv[sl].y : fv[sl].x) : 0.0;
+        const double vv = (gb + t < g1) ? fv[sl][t] : 0.0;
         double yr[NC], yi[NC];
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const float4 q = DIAG ? fx[sl][j] : fy[sl][DIAG ? 0 : j];
-          yr[j] = (double)(t ? q.z : q.x);
-          yi[j] = (double)(t ? q.w : q.y);
+          const V& q = DIAG ? fx[sl][j] : fy[sl][DIAG ? 0 : j];
+          yr[j] = re(q, t);
+          yi[j] = im(q, t);
         }
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-          const float4 q = fx[sl][i];
-          const double xr = (double)(t ? q.z : q.x) * vv, xi = (double)(t ? q.w : q.y) * vv;
+          const double xr = re(fx[sl][i], t) * vv, xi = im(fx[sl][i], t) * vv;
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
             if (DIAG && j > i) continue;
@@ -434,11 +450,11 @@ __device__ __forceinline__ void coulomb_tile64_re(const float2* __restrict__ Fm,
 }
 
 // one wave per (transfer, grid split, 64 x 64 lower-triangle tile)
-__global__ __launch_bounds__(64) void coulomb_kernel_f32_t64(const float2* __restrict__ F,
-                                                             const double* __restrict__ vt,
-                                                             double2* __restrict__ part,
-                                                             CoulArgs a, long nwork,
-                                                             long nwork_pad) {
+template <typename T>
+__global__ __launch_bounds__(64) void coulomb_kernel_t64(const cplx<T>* __restrict__ F,
+                                                         const double* __restrict__ vt,
+                                                         double2* __restrict__ part, CoulArgs a,
+                                                         long nwork, long nwork_pad) {
   const long w = (blockIdx.x % 8) * (nwork_pad / 8) + blockIdx.x / 8;
   if (w >= nwork) return;
   int m, s, ti, tj;
@@ -446,7 +462,7 @@ __global__ __launch_bounds__(64) void coulomb_kernel_f32_t64(const float2* __res
   const int P0 = ti * 64, Q0 = tj * 64;
   const long g0 = (long)s * a.chunk;
   const long g1 = min((long)a.ng, g0 + a.chunk);
-  const float2* Fm = F + (long)m * a.ni * a.ng;
+  const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
   const double* vm = vt + (long)m * a.ng;
   double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
   __shared__ double stage[64 * 4];
@@ -454,9 +470,9 @@ __global__ __launch_bounds__(64) void coulomb_kernel_f32_t64(const float2* __res
 #define EXX_T64(R)                                                                 \
   case R:                                                                          \
     if (ti == tj)                                                                  \
-      coulomb_tile64_re<R, true>(Fm, vm, out, a, P0, Q0, g0, g1, stage);           \
+      coulomb_tile64_re<T, R, true>(Fm, vm, out, a, P0, Q0, g0, g1, stage);        \
     else                                                                           \
-      coulomb_tile64_re<R, false>(Fm, vm, out, a, P0, Q0, g0, g1, stage);          \
+      coulomb_tile64_re<T, R, false>(Fm, vm, out, a, P0, Q0, g0, g1, stage);       \
     break;
   switch (nr) {
     EXX_T64(1)
@@ -464,9 +480,9 @@ __global__ __launch_bounds__(64) void coulomb_kernel_f32_t64(const float2* __res
     EXX_T64(3)
     default:
       if (ti == tj)
-        coulomb_tile64_re<4, true>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+        coulomb_tile64_re<T, 4, true>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
       else
-        coulomb_tile64_re<4, false>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
+        coulomb_tile64_re<T, 4, false>(Fm, vm, out, a, P0, Q0, g0, g1, stage);
   }
 #undef EXX_T64
 }
@@ -581,9 +597,10 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.ni = g.ni;
   a.nk = ns;
   const bool vec = a.ng % 2 == 0;
-  // FP64 storage: 64 x 64 workgroup tiles; FP32 storage: 32 x 32 wave tiles, or
-  // 64 x 64 wave tiles on the real path with an even half grid
-  const bool t64 = sizeof(T) == 4 && half && vec;
+  // complex path: FP64 storage on 64 x 64 workgroup tiles, FP32 storage on
+  // 32 x 32 wave tiles; real path: 64 x 64 wave tiles (FP32 storage needs an even
+  // half grid for its 16-byte loads, else 32 x 32 wave tiles)
+  const bool t64 = half && (sizeof(T) == 8 || vec);
   const int tw = (sizeof(T) == 8 || t64) ? 2 * WTILE : WTILE;
   const int nt = (g.ni + tw - 1) / tw;
   a.ntile = nt * (nt + 1) / 2;
@@ -594,11 +611,11 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   {
     const void* kfn;
     int threads = 64;
-    if (sizeof(T) == 8) {
+    if (t64) {
+      kfn = (const void*)coulomb_kernel_t64<T>;
+    } else if (sizeof(T) == 8) {
       kfn = half ? (const void*)coulomb_kernel_f64<true> : (const void*)coulomb_kernel_f64<false>;
       threads = 256;
-    } else if (t64) {
-      kfn = (const void*)coulomb_kernel_f32_t64;
     } else if (half) {
       kfn = vec ? (const void*)coulomb_kernel_f32<true, true>
                 : (const void*)coulomb_kernel_f32<false, true>;
@@ -649,8 +666,8 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
                        (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);   \
   }
   if (t64) {
-    hipLaunchKernelGGL(coulomb_kernel_f32_t64, dim3((unsigned)pad), dim3(64), 0, st,
-                       (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
+    hipLaunchKernelGGL(coulomb_kernel_t64<T>, dim3((unsigned)pad), dim3(64), 0, st,
+                       (const cplx<T>*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
   } else if (half) {
     EXX_COUL(true)
   } else {
