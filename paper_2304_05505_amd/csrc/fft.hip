@@ -225,12 +225,15 @@ __device__ __forceinline__ void stage(cplx<T>* buf, int n, int Ns, int nlines, i
     }
   }
   __syncthreads();
+  const bool first = Ns == 1;  // the first stage's twiddles are all 1 (uniform branch)
 #pragma unroll
   for (int s = 0; s < MAXB; ++s) {
     const int b = tid + s * NT;
     if (b < total) {
+      if (!first) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[s][r] = cmul<T>(v[s][r], tw[stp[s] * r]);
+        for (int r = 1; r < R; ++r) v[s][r] = cmul<T>(v[s][r], tw[stp[s] * r]);
+      }
       dft_any<T, R>(v[s]);
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[dst[s] + r * Ns * es] = v[s][r];
