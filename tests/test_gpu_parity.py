@@ -55,6 +55,10 @@ CELLS = {
                                            (11, 8, 1)),
     "k123": lambda: synth.make_random_cell((5.0, 5.0, 6.0), 2, (10, 10, 12), (1, 2, 3), 2, 45,
                                            (11, 9, 1)),
+    # odd n3 with a k-point along z, and an odd number of kept half-grid points
+    # (15 * 15 * 5): the FP32 real path falls back to 32 x 32 Coulomb tiles
+    "k112-odd": lambda: synth.make_random_cell((5.0, 5.0, 6.0), 2, (15, 15, 9), (1, 1, 2), 3, 33,
+                                               (11, 10, 1)),
 }
 
 
@@ -99,7 +103,8 @@ def test_fused_build_matches_stages(gpu):
 
 
 # meshes with every N_i <= 2 (the fused build's real path) and two that are not
-FUSED = ["gamma-config1", "k222-ragged", "k211", "k121", "k112", "k221", "k321", "k333"]
+FUSED = ["gamma-config1", "k222-ragged", "k211", "k121", "k112", "k221", "k112-odd", "k321",
+         "k333"]
 
 
 @pytest.mark.parametrize("name", FUSED)
@@ -124,7 +129,7 @@ def test_fp64_fused_build_matches_oracle(name, gpu):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "f32"])
-@pytest.mark.parametrize("name", ["gamma-config1", "k112", "k221"])
+@pytest.mark.parametrize("name", ["gamma-config1", "k112", "k221", "k112-odd"])
 def test_reduced_precision_fused_build(name, prec, gpu):
     """The fused build in MIXED and F32 on well-conditioned cells of the real path,
     against the oracle, to the bounds of the stage-wise reduced-precision tests."""
