@@ -505,24 +505,27 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __re
                                                              const int32_t* __restrict__ pts,
                                                              double2* __restrict__ V,
                                                              ReduceArgs a) {
+  // one thread per lower-triangle entry (P >= Q; the others exit), so that the
+  // partial sums are read once and along rows; (Q, P) is written as the
+  // conjugate (V^m is Hermitian)
   const long nn = (long)a.ni * a.ni;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int sl = blockIdx.y, m = a.rep[sl];
   if (idx >= nn) return;
   const int P = (int)(idx / a.ni), Q = (int)(idx % a.ni);
-  const bool lower = P >= Q;
-  const long src = lower ? ((long)P * a.ni + Q) : ((long)Q * a.ni + P);
+  if (P < Q) return;
+  const long up = (long)Q * a.ni + P;
   double sx = 0.0, sy = 0.0;
   for (int s = 0; s < a.nsplit; ++s) {
-    const double2 v = part[((long)sl * a.nsplit + s) * nn + src];
+    const double2 v = part[((long)sl * a.nsplit + s) * nn + idx];
     sx += v.x;
     sy += v.y;
   }
-  if (!lower) sy = -sy;
   sx *= a.scale;
   sy *= a.scale;
   if (a.raw) {
     V[(long)sl * nn + idx] = make_double2(sx, sy);
+    if (P != Q) V[(long)sl * nn + up] = make_double2(sx, -sy);
     return;
   }
   if (a.real) {
@@ -549,9 +552,15 @@ __global__ __launch_bounds__(256) void coulomb_reduce_kernel(const double2* __re
     sy = sx * py + sy * px;
     sx = vx;
   }
-  V[(long)m * nn + idx] = make_double2(sx, sy);
+  double2* Vm = V + (long)m * nn;
+  Vm[idx] = make_double2(sx, sy);
+  if (P != Q) Vm[up] = make_double2(sx, -sy);
   // Vb^{-m} = conj Vb^m
-  if (a.bar[sl] >= 0) V[(long)a.bar[sl] * nn + idx] = make_double2(sx, -sy);
+  if (a.bar[sl] >= 0) {
+    double2* Vb = V + (long)a.bar[sl] * nn;
+    Vb[idx] = make_double2(sx, -sy);
+    if (P != Q) Vb[up] = make_double2(sx, sy);
+  }
 }
 
 }  // namespace
