@@ -623,14 +623,17 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
   return s;
 }
 
+// have_G: the point Gram G^n is already in the scratch (the fused build's fit
+// formed it from the same occ and nothing since has written that region)
 exx_status buildK_impl(exx_context* h, const Geom& g, char* ws, const Layout& L, const void* ao,
-                       const void* occ, const void* V, void* K, double* Ex, hipStream_t st) {
+                       const void* occ, const void* V, void* K, double* Ex, hipStream_t st,
+                       bool have_G = false) {
   double2* G = (double2*)(ws + L.G);
   double2* Y = (double2*)(ws + L.Y);
   double2* T = (double2*)(ws + L.T);
   const long nn = (long)g.ni * g.ni;
-  hipError_t e;
-  {
+  hipError_t e = hipSuccess;
+  if (!have_G) {
     PhaseTimer pt(h, PH_GRAM, st);
     e = gemm<double, double, double, double>(g.ni, g.ni, g.no, g.nk, A_N, occ, g.no,
                                              (long)g.ni * g.no, B_C, occ, g.no, (long)g.ni * g.no,
@@ -800,7 +803,7 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   if (s != EXX_OK) return s;
   s = fit_coulomb(h, g, tb, ws, L, prec, psi_grid, occ_pts, pts, rank, stream);
   if (s != EXX_OK) return s;
-  return buildK_impl(h, g, ws, L, ao_pts, occ_pts, ws + L.V2, K, Ex, stream);
+  return buildK_impl(h, g, ws, L, ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
 }
 
 exx_status exx_set_refinement(exx_handle_t h, int32_t steps) {
@@ -856,7 +859,7 @@ exx_status build_one(exx_context* h, const Geom& g, const Tables& tb, char* ws, 
                      exx_prec prec, const exx_batch_item& it, hipStream_t st) {
   exx_status s = fit_coulomb(h, g, tb, ws, L, prec, it.psi_grid, it.occ_pts, it.pts, it.rank, st);
   if (s != EXX_OK) return s;
-  return buildK_impl(h, g, ws, L, it.ao_pts, it.occ_pts, ws + L.V2, it.K, it.Ex, st);
+  return buildK_impl(h, g, ws, L, it.ao_pts, it.occ_pts, ws + L.V2, it.K, it.Ex, st, true);
 }
 
 void tune_key(const Geom& g, exx_prec prec, long* key) {
