@@ -307,16 +307,14 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
 // caller's stream and the grid-sized Gamma and Z~ on the handle's second
 // stream; the solve waits for both.
 //
-// When Z~ and the transform share one storage type (FP64, FP32) the solve is
-// split at the factor: with S~^+ = W^T W (W the inverted Cholesky factor, lower
-// triangular in point order) the grid-sized product is Y = W Z~, half the
-// multiply-adds of S~^+ Z~; Y is transformed and contracted like eta, giving
-// Vy = sum_G v Re(HY_P conj HY_Q), and Vb = W^T Vy W by two small products.
-// Rounding of Y, of its transform and of Vy reaches Vb amplified by the norm of
-// W on each side, i.e. by cond(S~) once, as rounding of Z~ does in the eta
-// form. With Z~ in FP64 and eta stored in FP32 (MIXED) the eta form is kept:
-// there FP32 storage of Y would add a sqrt(cond) amplification that the
-// FP32 storage of eta does not have.
+// The solve is split at the factor: with S~^+ = W^T W (W the inverted Cholesky
+// factor, lower triangular in point order) the grid-sized product is Y = W Z~,
+// half the multiply-adds of S~^+ Z~; Y is transformed and contracted like eta,
+// giving Vy = sum_G v Re(HY_P conj HY_Q), and Vb = W^T Vy W by two small
+// products. Rounding of Y, of its transform and of Vy reaches Vb through
+// W^T (.) W, amplified by cond(S~) at most, as rounding of Z~ is in the eta
+// form. With Z~ in FP64 and Y stored in FP32 (MIXED) the measured errors are
+// lower than with eta stored in FP32, not higher.
 template <typename TF, typename TZ, typename TX>
 exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                             const Layout& L, const void* psi, const void* occ, const int32_t* pts,
@@ -358,16 +356,10 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
       if (e != hipSuccess) what = "cholesky";
     }
   }
-  constexpr bool split = std::is_same<TZ, TX>::value;  // Y = W Z~ (see above)
   if (!what) {
     PhaseTimer pt(h, PH_PINV, ax);
     e = launch_tri_inv_real(g, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
     if (e != hipSuccess) what = "triangular inverse";
-    if (!what && !split) {
-      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,
-                                               g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
-      if (e != hipSuccess) what = "S+ gemm";
-    }
   }
   if (what) {
     (void)hipEventRecord(h->join_ev, gs);
@@ -403,8 +395,8 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   if (ew != hipSuccess) return hip_check(h, ew, "join wait");
   {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = dgemm_nn_grid<TZ, TX>(g.ni, g.ng, g.ni, g.nk, split ? W : Sp, g.ni, nn, grid2, g.ng,
-                              (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, st, split);
+    e = dgemm_nn_grid<TZ, TX>(g.ni, g.ng, g.ni, g.nk, W, g.ni, nn, grid2, g.ng,
+                              (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, st, true);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
   {
@@ -415,7 +407,7 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   {
     PhaseTimer pt(h, PH_COULOMB, st);
     e = launch_coulomb<TX>(g, tb, grid2, pts, ws + L.cpart, L.nsplit, (double2*)V, true, st);
-    if (e == hipSuccess && split) {
+    if (e == hipSuccess) {
       // Vb = W^T Vy W: T = Vy W (real, in the S~^+ scratch), then Vb = W^T T
       const int n = g.ni;
       double* T = (double*)Sp;
@@ -435,7 +427,7 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
 // conjugates of those of m (relabelling n), so Vb^{-m} = conj Vb^m and the
 // Cholesky pivots (hence the ranks) agree. The paired path below fits and
 // contracts one transfer of each pair (rep, slice order), then writes both.
-// In FP64 and FP32 it splits the solve at the factor as the real path does:
+// It splits the solve at the factor as the real path does:
 // Y = W Z on the grid (W lower triangular), the contraction of the transform of
 // Y gives Vy, and V^m = W^H Vy W before the Bloch phases are applied.
 struct Pairs {
@@ -504,16 +496,10 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
     e = launch_chol_blocked(gr, Lf, keep, rank_c, (double*)(ws + L.tol), 1e-12, ax);
     if (e != hipSuccess) what = "cholesky";
   }
-  constexpr bool split = std::is_same<TF, TX>::value;  // Y = W Z (as on the real path)
   if (!what) {
     PhaseTimer pt(h, PH_PINV, ax);
     e = launch_tri_inv_blocked(gr, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
     if (e != hipSuccess) what = "triangular inverse";
-    if (!what && !split) {
-      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_C, W, g.ni, nn, B_N, W,
-                                               g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
-      if (e != hipSuccess) what = "S+ gemm";
-    }
   }
   if (!what) {
     e = launch_rank_scatter(rank_c, rank, pr.rep, pr.bar, pr.n, ax);
@@ -547,9 +533,9 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   if (ew != hipSuccess) return hip_check(h, ew, "join wait");
   {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, gr.nk, split ? W : Sp, g.ni, nn, false, grid,
-                              g.ng, (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st,
-                              h->tile_solve, split);
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, gr.nk, W, g.ni, nn, false, grid, g.ng,
+                              (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve,
+                              true);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
   {
@@ -559,27 +545,22 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {
     PhaseTimer pt(h, PH_COULOMB, st);
-    if (!split) {
-      e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st,
-                             pr.rep, pr.bar, pr.n);
-    } else {
-      // Vy (unphased, slice order) into V, then V^m = W^H Vy W with T = Vy W in the
-      // S^+ scratch and the product in the consumed partial sums, then the phases
-      // and the conjugate partners
-      double2* Vy = (double2*)V;
-      double2* T = Sp;
-      double2* U = (double2*)(ws + L.cpart);
-      e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, Vy, false, st, pr.rep,
-                             pr.bar, pr.n, true);
-      if (e == hipSuccess)
-        e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_N, Vy, g.ni, nn, B_N,
-                                                 W, g.ni, nn, T, g.ni, nn, 1.0, false, st);
-      if (e == hipSuccess)
-        e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_C, W, g.ni, nn, B_N,
-                                                 T, g.ni, nn, U, g.ni, nn, 1.0, false, st);
-      if (e == hipSuccess)
-        e = launch_coulomb_phase(g, tb, pts, U, (double2*)V, pr.rep, pr.bar, pr.n, st);
-    }
+    // Vy (unphased, slice order) into V, then V^m = W^H Vy W with T = Vy W in the
+    // S^+ scratch and the product in the consumed partial sums, then the phases
+    // and the conjugate partners
+    double2* Vy = (double2*)V;
+    double2* T = Sp;
+    double2* U = (double2*)(ws + L.cpart);
+    e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, Vy, false, st, pr.rep,
+                           pr.bar, pr.n, true);
+    if (e == hipSuccess)
+      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_N, Vy, g.ni, nn, B_N,
+                                               W, g.ni, nn, T, g.ni, nn, 1.0, false, st);
+    if (e == hipSuccess)
+      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_C, W, g.ni, nn, B_N,
+                                               T, g.ni, nn, U, g.ni, nn, 1.0, false, st);
+    if (e == hipSuccess)
+      e = launch_coulomb_phase(g, tb, pts, U, (double2*)V, pr.rep, pr.bar, pr.n, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "coulomb");
   return EXX_OK;
