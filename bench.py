@@ -63,9 +63,9 @@ def algorithmic_work(cell, n_isdf, prec):
     grid of n1 n2 (n3/2 + 1) points and the Coulomb contraction takes
     Re(X conj Y) (two real products, 4 flops) over that half grid; in FP32 the
     Gamma GEMM and the k-correlation are one kernel (phase "gamma"). There the
-    F64 and F32 solves multiply by the triangular inverse Cholesky factor and
-    count its N_I (N_I + 1) / 2 multiply-adds per grid point (the kernel rounds
-    each 64-row band up to its diagonal block).
+    solve multiplies by the triangular inverse Cholesky factor and counts its
+    N_I (N_I + 1) / 2 multiply-adds per grid point (the kernel rounds each
+    16-row block up to the diagonal).
     """
     nk, ng, no, na = cell.N_k, cell.N_g, cell.n_occ, cell.n_ao
     ni = n_isdf
@@ -86,9 +86,9 @@ def algorithmic_work(cell, n_isdf, prec):
         xc = 16 if prec == "f64" else 8       # transform element (complex)
         work.update({
             "kcorr": ("byte", nk * ni * ng * (gam + zr)),
-            # F64 and F32 apply the lower-triangular inverse factor W (S~^+ = W^T W):
-            # N_I (N_I + 1) / 2 multiply-adds per grid point; MIXED applies S~^+
-            "solve": ("flop", (1.0 * ni * (ni + 1) if prec != "mixed" else 2.0 * ni * ni) * nk * ng),
+            # the lower-triangular inverse factor W (S~^+ = W^T W): N_I (N_I + 1) / 2
+            # multiply-adds per grid point
+            "solve": ("flop", 1.0 * ni * (ni + 1) * nk * ng),
             "fft": ("byte", nk * ni * (ng * xr + ngh * xc)),
             "coulomb": ("flop", 2.0 * nk * ni * ni * ngh),
         })
