@@ -160,9 +160,16 @@ exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec,
                        void* K, double* Ex, hipStream_t stream);
 
 /*
- * exx_build -- one whole K-build: exx_isdf_fit, exx_coulomb_V and
- * exx_build_K back to back on one stream, with xi, S and V kept in the
- * handle's scratch. Arguments as above.
+ * exx_build -- one whole K-build (Algorithm 2: fit, Coulomb matrices, K and
+ * E_x) with the results of exx_isdf_fit, exx_coulomb_V and exx_build_K called
+ * in turn, to rounding; xi, S and V stay in the handle's scratch. It reaches
+ * them by identities of the method instead of forming xi: on meshes whose
+ * every axis has N_i <= 2 it works in the unphased gauge in real arithmetic,
+ * elsewhere it fits and contracts one transfer of each pair (m, -m); both
+ * apply the triangular inverse Cholesky factor W (S^+ = W^H W) to the grid
+ * and form Vb = W^H Vy W from the contraction of its transform. It forks a
+ * second stream of the handle and joins it back into `stream` before
+ * returning. Arguments as above; error behaviour as above.
  */
 exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec,
                      const void* psi_grid, const void* occ_pts, const void* ao_pts,
