@@ -167,7 +167,8 @@ exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec,
  * every axis has N_i <= 2 it works in the unphased gauge in real arithmetic,
  * elsewhere it fits and contracts one transfer of each pair (m, -m); both
  * apply the triangular inverse Cholesky factor W (S^+ = W^H W) to the grid
- * and form Vb = W^H Vy W from the contraction of its transform. It forks a
+ * and form Vb = W^H Vy W from the contraction of its transform (with
+ * refinement on, exx_set_refinement, it runs the stage-wise form). It forks a
  * second stream of the handle and joins it back into `stream` before
  * returning. Arguments as above; error behaviour as above.
  */
