@@ -26,8 +26,8 @@ struct Plan1 {
 
 // Radices of a line of length n (a 2*3*5-smooth n), largest first from the
 // list below so that a line takes as few LDS stages as possible; composite
-// radices run their own small Cooley-Tukey in registers. maxr caps the radix:
-// 16 for FP32, 5 for FP64 (register use).
+// radices run their own small Cooley-Tukey in registers. maxr caps the radix
+// (16 in every kernel).
 Plan1 plan_for(int n, int maxr = 16) {
   Plan1 p{};
   p.n = n;
@@ -254,9 +254,9 @@ __device__ void fft_lines(cplx<T>* buf, const Plan1& p, int nlines, int es, int 
     EXX_STAGE(3)
     EXX_STAGE(4)
     EXX_STAGE(5)
-    // composite radices only in the FP32 kernels: in FP64 their registers would
-    // cost the plane kernels occupancy
-    if constexpr (sizeof(T) == 4) {
+    // composite radices in both precisions: the FP64 plane kernels are held to
+    // two workgroups per CU by LDS, so their extra registers cost no occupancy
+    {
       EXX_STAGE(6)
       EXX_STAGE(8)
       EXX_STAGE(9)
@@ -548,7 +548,7 @@ hipError_t fft_prepare(int* ncu) {
 template <typename T>
 hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
                         int ncu, hipStream_t st) {
-  const int maxr = sizeof(T) == 8 ? 5 : 16;
+  const int maxr = 16;
   Plan1 px = plan_for(g.n[0], maxr), py = plan_for(g.n[1], maxr), pz = plan_for(g.n[2], maxr);
   const int np = g.n[1] * g.n[2];
   size_t lds1 = (size_t)(np + g.n[1] + g.n[2]) * sizeof(cplx<T>);
@@ -556,7 +556,7 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
   const long nplanes = nfun * g.n[0];
   const int nblk = (np + FFT_CB - 1) / FFT_CB;
   hipError_t e;
-  if (sizeof(T) == 8) {
+  if constexpr (sizeof(T) == 8) {
     // FP64 planes: a register copy of the next plane would spill, so one plane
     // per workgroup (two workgroups per CU by LDS)
     hipLaunchKernelGGL(fft_yz1_kernel<T>, dim3((unsigned)nplanes), dim3(NT1), lds1, st,
@@ -566,21 +566,22 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
     hipLaunchKernelGGL(fft_x1_kernel<T>, dim3((unsigned)(nfun * nblk)), dim3(NT2), lds2, st,
                        (cplx<T>*)out, px, np, nblk, twp<T>(tb, 0));
     return hipGetLastError();
+  } else {
+    // FP32 planes: persistent workgroups that prefetch the next plane
+    const long wpc1 = std::max<long>(1, (160L * 1024) / (long)lds1);
+    const long grid1 = std::min<long>(nplanes, (long)ncu * std::min<long>(wpc1, 4) * 2);
+    hipLaunchKernelGGL(fft_yz_kernel<T>, dim3((unsigned)grid1), dim3(NT1), lds1, st,
+                       (const cplx<T>*)in, (cplx<T>*)out, nplanes, py, pz, twp<T>(tb, 1),
+                       twp<T>(tb, 2));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long nwork = nfun * nblk;
+    const long wpc2 = std::max<long>(1, (160L * 1024) / (long)lds2);
+    const long grid2 = std::min<long>(nwork, (long)ncu * std::min<long>(wpc2, 8) * 2);
+    hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)grid2), dim3(NT2), lds2, st,
+                       (cplx<T>*)out, nwork, px, np, nblk, twp<T>(tb, 0));
+    return hipGetLastError();
   }
-  // FP32 planes: persistent workgroups that prefetch the next plane
-  const long wpc1 = std::max<long>(1, (160L * 1024) / (long)lds1);
-  const long grid1 = std::min<long>(nplanes, (long)ncu * std::min<long>(wpc1, 4) * 2);
-  hipLaunchKernelGGL(fft_yz_kernel<T>, dim3((unsigned)grid1), dim3(NT1), lds1, st,
-                     (const cplx<T>*)in, (cplx<T>*)out, nplanes, py, pz, twp<T>(tb, 1),
-                     twp<T>(tb, 2));
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const long nwork = nfun * nblk;
-  const long wpc2 = std::max<long>(1, (160L * 1024) / (long)lds2);
-  const long grid2 = std::min<long>(nwork, (long)ncu * std::min<long>(wpc2, 8) * 2);
-  hipLaunchKernelGGL(fft_x_kernel<T>, dim3((unsigned)grid2), dim3(NT2), lds2, st, (cplx<T>*)out,
-                     nwork, px, np, nblk, twp<T>(tb, 0));
-  return hipGetLastError();
 }
 
 int fft_half_z(const Geom& g) { return g.n[2] / 2 + 1; }
@@ -588,7 +589,7 @@ int fft_half_z(const Geom& g) { return g.n[2] / 2 + 1; }
 template <typename TI, typename T>
 hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, void* out, long nfun,
                              int m0, int ncu, hipStream_t st) {
-  const int maxr = sizeof(T) == 8 ? 5 : 16;
+  const int maxr = 16;
   Plan1 px = plan_for(g.n[0], maxr), py = plan_for(g.n[1], maxr), pz = plan_for(g.n[2], maxr);
   const int hz = fft_half_z(g);
   const int np = g.n[1] * g.n[2], nph = g.n[1] * hz;
