@@ -332,13 +332,19 @@ __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nr
     boff[j] = (unsigned)(c < N ? c : N - 1);
   }
   const unsigned ldb32 = (unsigned)ldb;
+  // 32-bit byte offsets from the uniform bases (the launcher checks that the
+  // bytes of one batch item's operands fit), so the loads take a scalar base
+  // plus a vector offset
+  const char* Ab = (const char*)Ar;
+  const char* Bb = (const char*)B;
   auto load = [&](int k0, double* xa, TB* xb) {
     const int k = k0 + lk;
     const unsigned kc = (unsigned)(k < K ? k : K - 1);
 #pragma unroll
-    for (int i = 0; i < WM; ++i) xa[i] = Ar[aoff[i] + 2 * kc];
+    for (int i = 0; i < WM; ++i) xa[i] = *(const double*)(Ab + (aoff[i] + 2 * kc) * 8u);
 #pragma unroll
-    for (int j = 0; j < WN; ++j) xb[j] = B[kc * ldb32 + boff[j]];
+    for (int j = 0; j < WN; ++j)
+      xb[j] = *(const TB*)(Bb + (kc * ldb32 + boff[j]) * (unsigned)sizeof(TB));
   };
 #pragma unroll
   for (int s = 0; s < NPF; ++s) load(4 * s, fa[s], fb[s]);
@@ -470,6 +476,8 @@ hipError_t dgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
                          hipStream_t st, bool lower) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (!offsets_fit(M, N, K, 2 * lda, ldb)) return hipErrorInvalidValue;
+  if ((long)M * 2 * lda * 8 >= 0xffffffffL || (long)K * ldb * (long)sizeof(TB) >= 0xffffffffL)
+    return hipErrorInvalidValue;
   const int nrt = (M + 63) / 64;
   const long nct = ((long)N + 255) / 256;
   const long ntiles = nrt * nct;
