@@ -629,14 +629,29 @@ exx_status buildK_impl(exx_context* h, const Geom& g, char* ws, const Layout& L,
   if (e != hipSuccess) return hip_check(h, e, "k-convolution");
   // c2: K^n = (1/N_k) A^H (Y A)
   PhaseTimer ptk(h, PH_KMAT, st);
-  e = gemm<double, double, double, double>(g.ni, g.nao, g.ni, g.nk, A_N, Y, g.ni, nn, B_N, ao,
-                                           g.nao, (long)g.ni * g.nao, T, g.nao,
-                                           (long)g.ni * g.nao, 1.0, false, st);
-  if (e != hipSuccess) return hip_check(h, e, "Y A gemm");
-  e = gemm<double, double, double, double>(g.nao, g.nao, g.ni, g.nk, A_C, ao, g.nao,
-                                           (long)g.ni * g.nao, B_N, T, g.nao, (long)g.ni * g.nao, K,
-                                           g.nao, (long)g.nao * g.nao, 1.0 / g.nk, false, st);
-  if (e != hipSuccess) return hip_check(h, e, "A^H T gemm");
+  const long na_i = (long)g.ni * g.nao;
+  if (g.nao <= g.ni) {
+    // both products on the FP64 matrix cores: T = Y A, then K = ((1/N_k) A^H) T
+    // with A^H written once into the S^+ scratch (free here; it holds
+    // N_k N_ISDF^2 >= N_k n_ao N_ISDF entries)
+    double2* AH = (double2*)(ws + L.Sp);
+    e = zgemm_nn_grid<double, double>(g.ni, g.nao, g.ni, g.nk, Y, g.ni, nn, false, ao, g.nao,
+                                      na_i, T, g.nao, na_i, st, 22);
+    if (e != hipSuccess) return hip_check(h, e, "Y A gemm");
+    e = launch_conj_transpose((const double2*)ao, AH, g.ni, g.nao, g.nk, 1.0 / g.nk, st);
+    if (e != hipSuccess) return hip_check(h, e, "A^H");
+    e = zgemm_nn_grid<double, double>(g.nao, g.nao, g.ni, g.nk, AH, g.ni, na_i, false, T, g.nao,
+                                      na_i, K, g.nao, (long)g.nao * g.nao, st, 22);
+    if (e != hipSuccess) return hip_check(h, e, "A^H T gemm");
+  } else {
+    e = gemm<double, double, double, double>(g.ni, g.nao, g.ni, g.nk, A_N, Y, g.ni, nn, B_N, ao,
+                                             g.nao, na_i, T, g.nao, na_i, 1.0, false, st);
+    if (e != hipSuccess) return hip_check(h, e, "Y A gemm");
+    e = gemm<double, double, double, double>(g.nao, g.nao, g.ni, g.nk, A_C, ao, g.nao, na_i, B_N,
+                                             T, g.nao, na_i, K, g.nao, (long)g.nao * g.nao,
+                                             1.0 / g.nk, false, st);
+    if (e != hipSuccess) return hip_check(h, e, "A^H T gemm");
+  }
   // c3: E_x
   PhaseTimer pte(h, PH_ENERGY, st);
   e = launch_energy(g, Y, G, (double*)(ws + L.epart), Ex, st);

@@ -215,6 +215,10 @@ hipError_t dgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
                          const void* B, long ldb, long sB, void* C, long ldc, long sC,
                          hipStream_t st, bool lower = false);
 
+// AH[b] = s * A[b]^H for (rows x cols) complex matrices, batch items contiguous
+hipError_t launch_conj_transpose(const double2* A, double2* AH, int rows, int cols, int batch,
+                                 double s, hipStream_t st);
+
 // Small real FP64 product C[b] = alpha A[b] B[b] (+ C[b] if acc), M x K times
 // K x N, with operands given by element strides in doubles: A(r, k) =
 // A[b sA + r ar + k ak], B(k, c) = B[b sB + k bk + c bc], C(r, c) =

@@ -36,6 +36,19 @@ __global__ __launch_bounds__(256) void kconv_kernel(const double2* __restrict__ 
   Y[(long)n * a.nn + e] = make_double2(sx, sy);
 }
 
+// AH[b][c][r] = s * conj(A[b][r][c]) for an (rows x cols) matrix per batch item
+__global__ __launch_bounds__(256) void conj_transpose_kernel(const double2* __restrict__ A,
+                                                             double2* __restrict__ AH, int rows,
+                                                             int cols, double s) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long n = (long)rows * cols;
+  if (e >= n) return;
+  const long b = blockIdx.y;
+  const int c = (int)(e / rows), r = (int)(e % rows);  // output order: consecutive r
+  const double2 v = A[b * n + (long)r * cols + c];
+  AH[b * n + e] = make_double2(s * v.x, -s * v.y);
+}
+
 constexpr int EN_NT = 256;
 
 // partial[b] = sum over block b of Re(Y conj G)
@@ -95,6 +108,15 @@ hipError_t launch_energy(const Geom& g, const double2* Y, const double2* G, doub
   if (e != hipSuccess) return e;
   const double scale = -1.0 / ((double)g.nk * (double)g.nk);
   hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(EN_NT), 0, st, partial, nb, scale, Ex);
+  return hipGetLastError();
+}
+
+hipError_t launch_conj_transpose(const double2* A, double2* AH, int rows, int cols, int batch,
+                                 double s, hipStream_t st) {
+  const long n = (long)rows * cols;
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(conj_transpose_kernel, dim3((unsigned)((n + 255) / 256), batch), dim3(256), 0,
+                     st, A, AH, rows, cols, s);
   return hipGetLastError();
 }
 
