@@ -87,7 +87,10 @@ typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 } exx_prec;
 typedef struct {
   double L[3];       /* orthorhombic cell edges, bohr */
   int32_t grid[3];   /* n1, n2, n3: each 2..128, 2*3*5-smooth, n2*n3 <= 6144 */
-  int32_t kmesh[3];  /* N1, N2, N3: each 1..8, N_k = N1*N2*N3 <= 64 */
+  int32_t kmesh[3];  /* N1, N2, N3: one of the shapes whose k-correlation is
+                        compiled in -- 1x1x1, 2x2x2, 3x3x3, 4x4x4, 2x1x1, 1x2x1,
+                        1x1x2, 2x2x1, 3x1x1, 3x2x1, 1x2x3; any other shape
+                        returns EXX_ERR_UNSUPPORTED */
   int32_t n_occ;     /* occupied orbitals per k, 1..512 */
   int32_t n_ao;      /* basis functions per k, 1..4096 */
   int32_t n_isdf;    /* interpolation points, 1..2048 */

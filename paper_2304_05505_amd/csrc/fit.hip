@@ -409,6 +409,7 @@ __global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no
   X(1, 2, 1)              \
   X(1, 1, 2)              \
   X(2, 2, 1)              \
+  X(3, 1, 1)              \
   X(3, 2, 1)              \
   X(1, 2, 3)
 

@@ -59,6 +59,10 @@ CELLS = {
     # (15 * 15 * 5): the FP32 real path falls back to 32 x 32 Coulomb tiles
     "k112-odd": lambda: synth.make_random_cell((5.0, 5.0, 6.0), 2, (15, 15, 9), (1, 1, 2), 3, 33,
                                                (11, 10, 1)),
+    # a well-conditioned cell on a mesh with an axis of 3: the fused build's
+    # paired complex path (transfers 0 and {1, 2})
+    "k311": lambda: synth.make_random_cell((6.0, 5.0, 5.0), 2, (12, 10, 10), (3, 1, 1), 2, 24,
+                                           (11, 13, 1)),
 }
 
 
@@ -103,8 +107,8 @@ def test_fused_build_matches_stages(gpu):
 
 
 # meshes with every N_i <= 2 (the fused build's real path) and two that are not
-FUSED = ["gamma-config1", "k222-ragged", "k211", "k121", "k112", "k221", "k112-odd", "k321",
-         "k333"]
+FUSED = ["gamma-config1", "k222-ragged", "k211", "k121", "k112", "k221", "k112-odd", "k311",
+         "k321", "k333"]
 
 
 @pytest.mark.parametrize("name", FUSED)
@@ -129,10 +133,11 @@ def test_fp64_fused_build_matches_oracle(name, gpu):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "f32"])
-@pytest.mark.parametrize("name", ["gamma-config1", "k112", "k221", "k112-odd"])
+@pytest.mark.parametrize("name", ["gamma-config1", "k112", "k221", "k112-odd", "k311"])
 def test_reduced_precision_fused_build(name, prec, gpu):
-    """The fused build in MIXED and F32 on well-conditioned cells of the real path,
-    against the oracle, to the bounds of the stage-wise reduced-precision tests."""
+    """The fused build in MIXED and F32 on well-conditioned cells (the real path,
+    and the paired complex path on the 3x1x1 mesh), against the oracle, to the
+    bounds of the stage-wise reduced-precision tests."""
     cell = CELLS[name]()
     base = inputs(cell)
     pts, _ = select.select_points(base["psi"], cell.n_isdf)
