@@ -63,6 +63,12 @@ CELLS = {
     # paired complex path (transfers 0 and {1, 2})
     "k311": lambda: synth.make_random_cell((6.0, 5.0, 5.0), 2, (12, 10, 10), (3, 1, 1), 2, 24,
                                            (11, 13, 1)),
+    # tiny point sets: fewer rows than one 16-row block; on the 2x2x2 cell n_ao
+    # exceeds N_ISDF (the K contraction's tiled form)
+    "tiny-k211": lambda: synth.make_random_cell((5.0, 5.0, 5.0), 1, (8, 8, 8), (2, 1, 1), 1, 5,
+                                                (11, 15, 1)),
+    "tiny-k222": lambda: synth.make_random_cell((5.0, 5.0, 5.0), 2, (8, 8, 10), (2, 2, 2), 1, 6,
+                                                (11, 16, 1)),
 }
 
 
@@ -108,7 +114,7 @@ def test_fused_build_matches_stages(gpu):
 
 # meshes with every N_i <= 2 (the fused build's real path) and two that are not
 FUSED = ["gamma-config1", "k222-ragged", "k211", "k121", "k112", "k221", "k112-odd", "k311",
-         "k321", "k333"]
+         "k321", "k333", "tiny-k211", "tiny-k222"]
 
 
 @pytest.mark.parametrize("name", FUSED)
@@ -133,7 +139,8 @@ def test_fp64_fused_build_matches_oracle(name, gpu):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "f32"])
-@pytest.mark.parametrize("name", ["gamma-config1", "k112", "k221", "k112-odd", "k311"])
+@pytest.mark.parametrize("name", ["gamma-config1", "k112", "k221", "k112-odd", "k311",
+                                  "tiny-k211", "tiny-k222"])
 def test_reduced_precision_fused_build(name, prec, gpu):
     """The fused build in MIXED and F32 on well-conditioned cells (the real path,
     and the paired complex path on the 3x1x1 mesh), against the oracle, to the
