@@ -72,7 +72,7 @@ def _single(h, exx, it, prec):
     return K.cpu().numpy(), float(Ex.cpu()[0]), rank.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("prec", ["f64", "mixed", "f32"])
 @pytest.mark.parametrize("flags", [0, 2, 1, 3])
 def test_batched_equals_single_builds(batch, prec, flags, gpu):
     import torch
@@ -107,7 +107,8 @@ def test_batched_equals_single_builds(batch, prec, flags, gpu):
             assert abs(Ex - Es) <= 1e-13 * abs(Es), f"rep {rep}"
             assert np.array_equal(rs, ref["rank"])
             # same tolerance rule as the parity tests: 64 eps64 cond(S_RR) relative (FP64);
-            # the mixed mode adds FP32 storage of xi (eps32 relative, amplified like the solve)
+            # the mixed and F32 modes store FP32 data (eps32 relative, amplified like the
+            # solve)
             conds = []
             for m in range(ref["S"].shape[0]):
                 R = np.flatnonzero(ref["keep"][m])
