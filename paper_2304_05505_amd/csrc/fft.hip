@@ -429,6 +429,96 @@ struct TwistArgs {
   int m0;  // transfer of the first function (functions are N_ISDF per transfer)
 };
 
+// Real path, two real lines per complex transform: the twisted input of a
+// plane is v(y, z) ry[y] rz[z] with real v, and the y (and x) phase ry[y] is
+// constant along z, so it is applied after the z transform. Lines a = 2q and
+// b = 2q + 1 are packed as c(z) = (v_a(z) + i v_b(z)) rz[z]; with the z twist
+// rz[z] = e^{-i pi d z / n3} (d = 2 m3 / N3, 0 or 1 on the real path), the
+// transform X of a real line obeys conj X(g) = X((-g - d) mod n3), so
+//   X_a(g) = (C(g) + conj C(g')) / 2,  X_b(g) = (C(g) - conj C(g')) / (2i),
+// g' = (-g - d) mod n3, for the kept g < hz. Half the z work and half the LDS
+// of fft_yz_half_kernel, so twice the planes per CU with 256-thread workgroups.
+constexpr int NTH = 256;            // threads of the paired plane pass
+constexpr int FFT_MAXPTS_H = 3200;  // points of the paired z lines or of the kept half plane
+constexpr int SEP_MAX = 8;          // separated (pair, g) entries per thread
+
+template <typename TI, typename T>
+__global__ __launch_bounds__(NTH) void fft_yz_half2_kernel(const TI* __restrict__ in,
+                                                           cplx<T>* __restrict__ out, Plan1 py,
+                                                           Plan1 pz, int hz, TwistArgs ta,
+                                                           const cplx<T>* __restrict__ twy,
+                                                           const cplx<T>* __restrict__ twz) {
+  extern __shared__ char smem_raw[];
+  const int n2 = py.n, n3 = pz.n, n2p = (n2 + 1) / 2;
+  const int nbuf = max(n2p * n3, n2 * hz);
+  cplx<T>* buf = (cplx<T>*)smem_raw;
+  cplx<T>* ty = buf + nbuf;
+  cplx<T>* tz = ty + n2;
+  cplx<T>* ry = tz + n3;
+  cplx<T>* rz = ry + n2;
+  const long p = blockIdx.x;  // plane = function * n1 + x
+  const int n1 = ta.n[0];
+  const long f = p / n1;
+  const int g1 = (int)(p % n1);
+  const int m = ta.m0 + (int)(f / ta.ni);
+  const int m1 = m / (ta.N[1] * ta.N[2]), m2 = (m / ta.N[2]) % ta.N[1], m3 = m % ta.N[2];
+  const int d = (2 * m3) / ta.N[2];
+  const double2 c0 = ta.root[0][(m1 * g1) % (ta.N[0] * n1)];
+  for (int e = threadIdx.x; e < n2; e += NTH) {
+    ty[e] = twy[e];
+    const double2 r = ta.root[1][(m2 * e) % (ta.N[1] * n2)];
+    ry[e] = mk<T>((T)(c0.x * r.x - c0.y * r.y), (T)(c0.x * r.y + c0.y * r.x));
+  }
+  for (int e = threadIdx.x; e < n3; e += NTH) {
+    tz[e] = twz[e];
+    const double2 r = ta.root[2][(m3 * e) % (ta.N[2] * n3)];
+    rz[e] = mk<T>((T)r.x, (T)r.y);
+  }
+  __syncthreads();
+  const TI* src = in + p * (long)(n2 * n3);
+  const float in3 = 1.0f / (float)n3, ihz = 1.0f / (float)hz;
+  for (int e = threadIdx.x; e < n2p * n3; e += NTH) {
+    const int q = small_div(e, n3, in3), z = e - q * n3;
+    const T va = (T)src[(2 * q) * n3 + z];
+    const T vb = 2 * q + 1 < n2 ? (T)src[(2 * q + 1) * n3 + z] : (T)0;
+    const cplx<T> w = rz[z];
+    buf[e] = mk<T>(va * w.x - vb * w.y, va * w.y + vb * w.x);
+  }
+  __syncthreads();
+  fft_lines<T, NTH, FFT_MAXPTS_H, false>(buf, pz, n2p, 1, n3, tz);
+  // separate the pairs (all reads into registers, then the [y][hz] layout is
+  // written over the same LDS)
+  cplx<T> za[SEP_MAX], zb[SEP_MAX];
+  const T half = (T)0.5;
+#pragma unroll
+  for (int s = 0; s < SEP_MAX; ++s) {
+    const int e = threadIdx.x + s * NTH;
+    if (e < n2p * hz) {
+      const int q = small_div(e, hz, ihz), g = e - q * hz;
+      const int gp = (2 * n3 - g - d) % n3;
+      const cplx<T> c = buf[q * n3 + g], cp = buf[q * n3 + gp];
+      const cplx<T> xa = mk<T>(half * (c.x + cp.x), half * (c.y - cp.y));
+      const cplx<T> xb = mk<T>(half * (c.y + cp.y), half * (cp.x - c.x));
+      za[s] = cmul<T>(ry[2 * q], xa);
+      zb[s] = 2 * q + 1 < n2 ? cmul<T>(ry[2 * q + 1], xb) : mk<T>((T)0, (T)0);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SEP_MAX; ++s) {
+    const int e = threadIdx.x + s * NTH;
+    if (e < n2p * hz) {
+      const int q = small_div(e, hz, ihz), g = e - q * hz;
+      buf[(2 * q) * hz + g] = za[s];
+      if (2 * q + 1 < n2) buf[(2 * q + 1) * hz + g] = zb[s];
+    }
+  }
+  __syncthreads();
+  fft_lines<T, NTH, FFT_MAXPTS_H, true>(buf, py, hz, hz, 1, ty);
+  cplx<T>* dst = out + p * ((long)n2 * hz);
+  for (int e = threadIdx.x; e < n2 * hz; e += NTH) dst[e] = buf[e];
+}
+
 template <typename TI, typename T>
 __global__ __launch_bounds__(NT1) void fft_yz_half_kernel(const TI* __restrict__ in,
                                                           cplx<T>* __restrict__ out, Plan1 py,
@@ -605,8 +695,20 @@ hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, vo
   }
   ta.ni = g.ni;
   ta.m0 = m0;
-  hipLaunchKernelGGL((fft_yz_half_kernel<TI, T>), dim3((unsigned)nplanes), dim3(NT1), lds1, st,
-                     (const TI*)in, (cplx<T>*)out, py, pz, hz, ta, twp<T>(tb, 1), twp<T>(tb, 2));
+  const int n2p = (g.n[1] + 1) / 2;
+  const bool paired = n2p * g.n[2] <= FFT_MAXPTS_H && nph <= FFT_MAXPTS_H &&
+                      n2p * hz <= SEP_MAX * NTH;
+  if (paired) {
+    const size_t ldsp =
+        (size_t)(std::max(n2p * g.n[2], nph) + 2 * g.n[1] + 2 * g.n[2]) * sizeof(cplx<T>);
+    hipLaunchKernelGGL((fft_yz_half2_kernel<TI, T>), dim3((unsigned)nplanes), dim3(NTH), ldsp, st,
+                       (const TI*)in, (cplx<T>*)out, py, pz, hz, ta, twp<T>(tb, 1),
+                       twp<T>(tb, 2));
+  } else {
+    hipLaunchKernelGGL((fft_yz_half_kernel<TI, T>), dim3((unsigned)nplanes), dim3(NT1), lds1, st,
+                       (const TI*)in, (cplx<T>*)out, py, pz, hz, ta, twp<T>(tb, 1),
+                       twp<T>(tb, 2));
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (sizeof(T) == 8) {
