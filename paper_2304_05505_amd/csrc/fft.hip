@@ -15,7 +15,11 @@ namespace {
 constexpr int NT1 = 512;          // threads of the plane pass
 constexpr int NT2 = 256;          // threads of the x pass
 constexpr int FFT_MAXPTS = 6144;  // largest (y, z) plane held in LDS by one workgroup
-constexpr int FFT_CB = 32;        // (y, z) columns per workgroup in pass 2
+constexpr int FFT_CB = 32;        // largest (y, z) column block per workgroup in pass 2
+// (y, z) columns per workgroup in pass 2: 32 in FP32; 16 in FP64, where the
+// smaller block halves the stage registers (measured faster)
+template <typename T>
+constexpr int fft_cb = sizeof(T) == 8 ? 16 : 32;
 constexpr int FFT_MAXX = 128;     // longest x line
 
 struct Plan1 {
@@ -291,27 +295,27 @@ __global__ __launch_bounds__(NT1) void fft_yz1_kernel(const cplx<T>* __restrict_
   for (int e = threadIdx.x; e < np; e += NT1) out[off + e] = buf[e];
 }
 
-// pass 2: x lines of FFT_CB contiguous (y, z) columns of one function
+// pass 2: x lines of fft_cb<T> contiguous (y, z) columns of one function
 template <typename T>
 __global__ __launch_bounds__(NT2) void fft_x1_kernel(cplx<T>* __restrict__ data, Plan1 px, int np,
                                                     int nblk, const cplx<T>* __restrict__ twx) {
   extern __shared__ char smem_raw[];
   const int n1 = px.n;
   cplx<T>* buf = (cplx<T>*)smem_raw;
-  cplx<T>* tx = buf + n1 * FFT_CB;
+  cplx<T>* tx = buf + n1 * fft_cb<T>;
   const long f = blockIdx.x / nblk;
-  const int c0 = (blockIdx.x % nblk) * FFT_CB;
-  const int cw = min(FFT_CB, np - c0);
+  const int c0 = (blockIdx.x % nblk) * fft_cb<T>;
+  const int cw = min(fft_cb<T>, np - c0);
   cplx<T>* base = data + f * (long)n1 * np + c0;
-  for (int e = threadIdx.x; e < n1 * FFT_CB; e += NT2) {
-    const int x = e / FFT_CB, c = e % FFT_CB;
+  for (int e = threadIdx.x; e < n1 * fft_cb<T>; e += NT2) {
+    const int x = e / fft_cb<T>, c = e % fft_cb<T>;
     buf[e] = (c < cw) ? base[(long)x * np + c] : mk<T>(0, 0);
   }
   for (int e = threadIdx.x; e < n1; e += NT2) tx[e] = twx[e];
   __syncthreads();
-  fft_lines<T, NT2, FFT_CB * FFT_MAXX, true>(buf, px, FFT_CB, FFT_CB, 1, tx);
-  for (int e = threadIdx.x; e < n1 * FFT_CB; e += NT2) {
-    const int x = e / FFT_CB, c = e % FFT_CB;
+  fft_lines<T, NT2, fft_cb<T> * FFT_MAXX, true>(buf, px, fft_cb<T>, fft_cb<T>, 1, tx);
+  for (int e = threadIdx.x; e < n1 * fft_cb<T>; e += NT2) {
+    const int x = e / fft_cb<T>, c = e % fft_cb<T>;
     if (c < cw) base[(long)x * np + c] = buf[e];
   }
 }
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(NT1) void fft_yz_kernel(const cplx<T>* __restrict__
   }
 }
 
-// pass 2: x lines of FFT_CB contiguous (y, z) columns; workgroups loop over
+// pass 2: x lines of fft_cb<T> contiguous (y, z) columns; workgroups loop over
 // column blocks with a register prefetch of the next block.
 constexpr int PRE2 = (FFT_CB * FFT_MAXX + NT2 - 1) / NT2;
 template <typename T>
@@ -374,20 +378,20 @@ __global__ __launch_bounds__(NT2) void fft_x_kernel(cplx<T>* __restrict__ data, 
   extern __shared__ char smem_raw[];
   const int n1 = px.n;
   cplx<T>* buf = (cplx<T>*)smem_raw;
-  cplx<T>* tx = buf + n1 * FFT_CB;
+  cplx<T>* tx = buf + n1 * fft_cb<T>;
   for (int e = threadIdx.x; e < n1; e += NT2) tx[e] = twx[e];
-  const int npts = n1 * FFT_CB;
+  const int npts = n1 * fft_cb<T>;
   cplx<T> pre[PRE2];
   auto fetch = [&](long w) {
     const long f = w / nblk;
-    const int c0 = (int)(w % nblk) * FFT_CB;
-    const int cw = min(FFT_CB, np - c0);
+    const int c0 = (int)(w % nblk) * fft_cb<T>;
+    const int cw = min(fft_cb<T>, np - c0);
     const cplx<T>* base = data + f * (long)n1 * np + c0;
 #pragma unroll
     for (int k = 0; k < PRE2; ++k) {
       const int e = threadIdx.x + k * NT2;
       if (e < npts) {
-        const int x = e / FFT_CB, c = e % FFT_CB;
+        const int x = e / fft_cb<T>, c = e % fft_cb<T>;
         pre[k] = (c < cw) ? base[(long)x * np + c] : mk<T>(0, 0);
       }
     }
@@ -402,13 +406,13 @@ __global__ __launch_bounds__(NT2) void fft_x_kernel(cplx<T>* __restrict__ data, 
     }
     __syncthreads();
     if (w + gridDim.x < nwork) fetch(w + gridDim.x);
-    fft_lines<T, NT2, FFT_CB * FFT_MAXX, true>(buf, px, FFT_CB, FFT_CB, 1, tx);
+    fft_lines<T, NT2, fft_cb<T> * FFT_MAXX, true>(buf, px, fft_cb<T>, fft_cb<T>, 1, tx);
     const long f = w / nblk;
-    const int c0 = (int)(w % nblk) * FFT_CB;
-    const int cw = min(FFT_CB, np - c0);
+    const int c0 = (int)(w % nblk) * fft_cb<T>;
+    const int cw = min(fft_cb<T>, np - c0);
     cplx<T>* base = data + f * (long)n1 * np + c0;
     for (int e = threadIdx.x; e < npts; e += NT2) {
-      const int x = e / FFT_CB, c = e % FFT_CB;
+      const int x = e / fft_cb<T>, c = e % fft_cb<T>;
       if (c < cw) base[(long)x * np + c] = buf[e];
     }
     __syncthreads();
@@ -642,9 +646,9 @@ hipError_t launch_fft3d(const Geom& g, const Tables& tb, const void* in, void* o
   Plan1 px = plan_for(g.n[0], maxr), py = plan_for(g.n[1], maxr), pz = plan_for(g.n[2], maxr);
   const int np = g.n[1] * g.n[2];
   size_t lds1 = (size_t)(np + g.n[1] + g.n[2]) * sizeof(cplx<T>);
-  size_t lds2 = (size_t)(g.n[0] * FFT_CB + g.n[0]) * sizeof(cplx<T>);
+  size_t lds2 = (size_t)(g.n[0] * fft_cb<T> + g.n[0]) * sizeof(cplx<T>);
   const long nplanes = nfun * g.n[0];
-  const int nblk = (np + FFT_CB - 1) / FFT_CB;
+  const int nblk = (np + fft_cb<T> - 1) / fft_cb<T>;
   hipError_t e;
   if constexpr (sizeof(T) == 8) {
     // FP64 planes: a register copy of the next plane would spill, so one plane
@@ -684,9 +688,9 @@ hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, vo
   const int hz = fft_half_z(g);
   const int np = g.n[1] * g.n[2], nph = g.n[1] * hz;
   const size_t lds1 = (size_t)(np + 2 * g.n[1] + 2 * g.n[2]) * sizeof(cplx<T>);
-  const size_t lds2 = (size_t)(g.n[0] * FFT_CB + g.n[0]) * sizeof(cplx<T>);
+  const size_t lds2 = (size_t)(g.n[0] * fft_cb<T> + g.n[0]) * sizeof(cplx<T>);
   const long nplanes = nfun * g.n[0];
-  const int nblk = (nph + FFT_CB - 1) / FFT_CB;
+  const int nblk = (nph + fft_cb<T> - 1) / fft_cb<T>;
   TwistArgs ta;
   for (int a = 0; a < 3; ++a) {
     ta.root[a] = tb.root[a];
