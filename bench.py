@@ -104,27 +104,27 @@ def algorithmic_work(cell, n_isdf, prec):
 
 # HBM traffic of the dominant kernel of each phase at this workload, from two
 # rocprofv3 counter runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; KiB
-# per dispatch). A plain 1 GiB device copy reads 524 312 KiB of FETCH_SIZE and
+# per dispatch). A plain 1 GiB device copy reads 524 311 KiB of FETCH_SIZE and
 # 1 048 576 KiB of WRITE_SIZE on MI355X, so fetch counts are scaled by 2.0 and write
 # counts by 1.0. Each entry names the source file of its kernels and that file's
 # SHA-256 prefix when the counters were taken; a changed file reports null.
-FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524312.0625, 1.0
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524311.1250, 1.0
 TRAFFIC = {
     # (phase, path): (source, sha256[:16], FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("solve", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 8033111.7, 6468851.2),
-    ("solve", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 7515140.1, 3303554.2),
-    ("solve", "f32"): ("gemm_mfma.hip", "b285ff3ab7358f19", 3060142.2, 3263628.8),
-    ("gamma", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299448.7, 12757500.0),
-    ("gamma", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299448.7, 12757500.0),
-    ("gamma", "f32"): ("fit.hip", "fa8c9af02b7f561a", 1305200.4, 4510312.8),
-    ("kcorr", "f64"): ("fit.hip", "fa8c9af02b7f561a", 6378788.2, 6378750.0),
-    ("kcorr", "mixed"): ("fit.hip", "fa8c9af02b7f561a", 6378788.2, 6378750.0),
-    ("fft", "f64"): ("fft.hip", "25226941ab7950b6", 6924180.2, 13230000.3),
-    ("fft", "mixed"): ("fft.hip", "25226941ab7950b6", 3884469.4, 6615000.1),
-    ("fft", "f32"): ("fft.hip", "25226941ab7950b6", 3884469.4, 6615000.1),
-    ("coulomb", "f64"): ("coulomb.hip", "e5d3729797beb400", 23727292.1, 207554.2),
-    ("coulomb", "mixed"): ("coulomb.hip", "e5d3729797beb400", 8996177.5, 206326.9),
-    ("coulomb", "f32"): ("coulomb.hip", "e5d3729797beb400", 8996177.5, 206326.9),
+    ("solve", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 8044630.9, 6469185.9),
+    ("solve", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 7479915.4, 3302715.3),
+    ("solve", "f32"): ("gemm_mfma.hip", "b285ff3ab7358f19", 3052322.9, 3263711.6),
+    ("gamma", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299539.4, 12757500.0),
+    ("gamma", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299539.4, 12757500.0),
+    ("gamma", "f32"): ("fit.hip", "fa8c9af02b7f561a", 1377861.8, 4467408.1),
+    ("kcorr", "f64"): ("fit.hip", "fa8c9af02b7f561a", 6378788.3, 6378750.0),
+    ("kcorr", "mixed"): ("fit.hip", "fa8c9af02b7f561a", 6378788.3, 6378750.0),
+    ("fft", "f64"): ("fft.hip", "05376b4f2156bb5c", 7340649.5, 13230000.2),
+    ("fft", "mixed"): ("fft.hip", "05376b4f2156bb5c", 3884785.5, 6615000.2),
+    ("fft", "f32"): ("fft.hip", "05376b4f2156bb5c", 3884785.5, 6615000.2),
+    ("coulomb", "f64"): ("coulomb.hip", "e5d3729797beb400", 23759214.6, 207539.6),
+    ("coulomb", "mixed"): ("coulomb.hip", "e5d3729797beb400", 9014701.9, 206309.1),
+    ("coulomb", "f32"): ("coulomb.hip", "e5d3729797beb400", 9014701.9, 206309.1),
 }
 
 
