@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <optional>
 #include <type_traits>
 
 #include "common.h"
@@ -399,15 +400,56 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
                               (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, st, true);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
-  {
-    PhaseTimer pt(h, PH_FFT, st);
-    e = launch_fft3d_half<TX, TX>(g, tb, grid, grid2, (long)g.nk * g.ni, 0, h->ncu, st);
-  }
-  if (e != hipSuccess) return hip_check(h, e, "fft");
-  {
+  // FP64 storage: the transfers go in four chunks, the transform of each chunk
+  // on the caller's stream and its contraction on the second stream, so that
+  // the transform of one chunk runs beside the contraction of the one before
+  // (the FP64 transform is latency bound, the contraction matrix-core bound).
+  // With FP32 storage the two contend for the CUs and nothing is gained, so
+  // that path keeps one transform and one contraction. The timed phases of the
+  // chunked form overlap.
+  const int nchunk = sizeof(TX) == 8 ? std::min(4, g.nk) : 1;
+  if (nchunk == 1) {
+    {
+      PhaseTimer pt(h, PH_FFT, st);
+      e = launch_fft3d_half<TX, TX>(g, tb, grid, grid2, (long)g.nk * g.ni, 0, h->ncu, st);
+    }
+    if (e != hipSuccess) return hip_check(h, e, "fft");
     PhaseTimer pt(h, PH_COULOMB, st);
     e = launch_coulomb<TX>(g, tb, grid2, pts, ws + L.cpart, L.nsplit, (double2*)V, true, st);
-    if (e == hipSuccess) {
+    if (e != hipSuccess) return hip_check(h, e, "coulomb");
+  } else {
+    const int per = (g.nk + nchunk - 1) / nchunk;
+    const size_t fin = (size_t)g.ni * g.ng * sizeof(TX);  // solved functions per transfer
+    const size_t fout = (size_t)g.ni * g.n[0] * g.n[1] * (g.n[2] / 2 + 1) * sizeof(cplx<TX>);
+    std::optional<PhaseTimer> tc;
+    {
+      PhaseTimer pt(h, PH_FFT, st);
+      for (int c0 = 0; c0 < g.nk && !what; c0 += per) {
+        const int cn = std::min(per, g.nk - c0);
+        e = launch_fft3d_half<TX, TX>(g, tb, (const char*)grid + c0 * fin,
+                                      (char*)grid2 + c0 * fout, (long)cn * g.ni, c0, h->ncu, st);
+        if (e != hipSuccess) what = "fft";
+        if (!what) e = hipEventRecord(h->fork_ev, st);
+        if (!what && e == hipSuccess) e = hipStreamWaitEvent(gs, h->fork_ev, 0);
+        if (!what && e != hipSuccess) what = "chunk fork";
+        if (!what && !tc) tc.emplace(h, PH_COULOMB, gs);
+        int rep[64];
+        for (int m = 0; m < cn; ++m) rep[m] = c0 + m;
+        if (!what)
+          e = launch_coulomb<TX>(g, tb, (const char*)grid2 + c0 * fout, pts, ws + L.cpart,
+                                 L.nsplit, (double2*)V, true, gs, rep, nullptr, cn, false);
+        if (!what && e != hipSuccess) what = "coulomb";
+      }
+    }
+    tc.reset();
+    ej = hipEventRecord(h->join_ev, gs);
+    ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
+    if (what) return hip_check(h, e, what);
+    if (ew != hipSuccess) return hip_check(h, ew, "join wait");
+  }
+  {
+    PhaseTimer pt(h, PH_COULOMB, st);
+    {
       // Vb = W^T Vy W: T = Vy W (real, in the S~^+ scratch), then Vb = W^T T
       const int n = g.ni;
       double* T = (double*)Sp;
