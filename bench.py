@@ -104,27 +104,28 @@ def algorithmic_work(cell, n_isdf, prec):
 
 # HBM traffic of the dominant kernel of each phase at this workload, from two
 # rocprofv3 counter runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; KiB
-# per dispatch). A plain 1 GiB device copy reads 524 311 KiB of FETCH_SIZE and
-# 1 048 576 KiB of WRITE_SIZE on MI355X, so fetch counts are scaled by 2.0 and write
-# counts by 1.0. Each entry names the source file of its kernels and that file's
+# per dispatch; the FP64 transform and contraction run in four chunks of transfers,
+# so their entries cover a quarter of the build). A plain 1 GiB device copy reads
+# 524 312 KiB of FETCH_SIZE and 1 048 576 KiB of WRITE_SIZE on MI355X, so fetch
+# counts are scaled by 2.0 and write counts by 1.0. Each entry names the source file of its kernels and that file's
 # SHA-256 prefix when the counters were taken; a changed file reports null.
-FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524311.1250, 1.0
+FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524312.2, 1.0
 TRAFFIC = {
     # (phase, path): (source, sha256[:16], FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("solve", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 8044630.9, 6469185.9),
-    ("solve", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 7479915.4, 3302715.3),
-    ("solve", "f32"): ("gemm_mfma.hip", "b285ff3ab7358f19", 3052322.9, 3263711.6),
-    ("gamma", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299539.4, 12757500.0),
-    ("gamma", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299539.4, 12757500.0),
-    ("gamma", "f32"): ("fit.hip", "fa8c9af02b7f561a", 1377861.8, 4467408.1),
-    ("kcorr", "f64"): ("fit.hip", "fa8c9af02b7f561a", 6378788.3, 6378750.0),
-    ("kcorr", "mixed"): ("fit.hip", "fa8c9af02b7f561a", 6378788.3, 6378750.0),
-    ("fft", "f64"): ("fft.hip", "05376b4f2156bb5c", 7340649.5, 13230000.2),
-    ("fft", "mixed"): ("fft.hip", "05376b4f2156bb5c", 3884785.5, 6615000.2),
-    ("fft", "f32"): ("fft.hip", "05376b4f2156bb5c", 3884785.5, 6615000.2),
-    ("coulomb", "f64"): ("coulomb.hip", "e5d3729797beb400", 23759214.6, 207539.6),
-    ("coulomb", "mixed"): ("coulomb.hip", "e5d3729797beb400", 9014701.9, 206309.1),
-    ("coulomb", "f32"): ("coulomb.hip", "e5d3729797beb400", 9014701.9, 206309.1),
+    ("solve", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 8087716.2, 6469594.8),
+    ("solve", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 7483829.7, 3303541.6),
+    ("solve", "f32"): ("gemm_mfma.hip", "b285ff3ab7358f19", 3051883.4, 3263706.8),
+    ("gamma", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299417.4, 12757500.0),
+    ("gamma", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299417.4, 12757500.0),
+    ("gamma", "f32"): ("fit.hip", "fa8c9af02b7f561a", 1355649.1, 4503349.7),
+    ("kcorr", "f64"): ("fit.hip", "fa8c9af02b7f561a", 6378788.6, 6378750.0),
+    ("kcorr", "mixed"): ("fit.hip", "fa8c9af02b7f561a", 6378788.6, 6378750.0),
+    ("fft", "f64"): ("fft.hip", "05376b4f2156bb5c", 1835594.0, 3307500.8),
+    ("fft", "mixed"): ("fft.hip", "05376b4f2156bb5c", 3884780.6, 6615000.5),
+    ("fft", "f32"): ("fft.hip", "05376b4f2156bb5c", 3884780.6, 6615000.5),
+    ("coulomb", "f64"): ("coulomb.hip", "e5d3729797beb400", 4980022.1, 210761.8),
+    ("coulomb", "mixed"): ("coulomb.hip", "e5d3729797beb400", 8965173.4, 206327.3),
+    ("coulomb", "f32"): ("coulomb.hip", "e5d3729797beb400", 8965173.4, 206327.3),
 }
 
 
