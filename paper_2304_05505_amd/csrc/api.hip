@@ -580,21 +580,55 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
                               true);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
-  {
-    PhaseTimer pt(h, PH_FFT, st);
-    e = launch_fft3d<TX>(g, tb, xi, grid, (long)gr.nk * g.ni, h->ncu, st);
-  }
-  if (e != hipSuccess) return hip_check(h, e, "fft");
-  {
+  // Vy (unphased, slice order) into V. FP64 storage: the slices go in four
+  // chunks, the transform of each on the caller's stream and its contraction
+  // on the second stream, as in the real path (the timed phases then overlap)
+  double2* Vy = (double2*)V;
+  const int nchunk = sizeof(TX) == 8 ? std::min(4, gr.nk) : 1;
+  if (nchunk == 1) {
+    {
+      PhaseTimer pt(h, PH_FFT, st);
+      e = launch_fft3d<TX>(g, tb, xi, grid, (long)gr.nk * g.ni, h->ncu, st);
+    }
+    if (e != hipSuccess) return hip_check(h, e, "fft");
     PhaseTimer pt(h, PH_COULOMB, st);
-    // Vy (unphased, slice order) into V, then V^m = W^H Vy W with T = Vy W in the
-    // S^+ scratch and the product in the consumed partial sums, then the phases
-    // and the conjugate partners
-    double2* Vy = (double2*)V;
-    double2* T = Sp;
-    double2* U = (double2*)(ws + L.cpart);
     e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, Vy, false, st, pr.rep,
                            pr.bar, pr.n, true);
+    if (e != hipSuccess) return hip_check(h, e, "coulomb");
+  } else {
+    const int per = (gr.nk + nchunk - 1) / nchunk;
+    const size_t fb = (size_t)g.ni * g.ng * sizeof(cplx<TX>);  // functions of one slice
+    std::optional<PhaseTimer> tc;
+    {
+      PhaseTimer pt(h, PH_FFT, st);
+      for (int s0 = 0; s0 < gr.nk && !what; s0 += per) {
+        const int cn = std::min(per, gr.nk - s0);
+        e = launch_fft3d<TX>(g, tb, (const char*)xi + s0 * fb, (char*)grid + s0 * fb,
+                             (long)cn * g.ni, h->ncu, st);
+        if (e != hipSuccess) what = "fft";
+        if (!what) e = hipEventRecord(h->fork_ev, st);
+        if (!what && e == hipSuccess) e = hipStreamWaitEvent(gs, h->fork_ev, 0);
+        if (!what && e != hipSuccess) what = "chunk fork";
+        if (!what && !tc) tc.emplace(h, PH_COULOMB, gs);
+        if (!what)
+          e = launch_coulomb<TX>(g, tb, (const char*)grid + s0 * fb, pts, ws + L.cpart, L.nsplit,
+                                 Vy + (long)s0 * nn, false, gs, pr.rep + s0, pr.bar + s0, cn,
+                                 true);
+        if (!what && e != hipSuccess) what = "coulomb";
+      }
+    }
+    tc.reset();
+    ej = hipEventRecord(h->join_ev, gs);
+    ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
+    if (what) return hip_check(h, e, what);
+    if (ew != hipSuccess) return hip_check(h, ew, "join wait");
+  }
+  {
+    PhaseTimer pt(h, PH_COULOMB, st);
+    // V^m = W^H Vy W with T = Vy W in the S^+ scratch and the product in the
+    // consumed partial sums, then the phases and the conjugate partners
+    double2* T = Sp;
+    double2* U = (double2*)(ws + L.cpart);
     if (e == hipSuccess)
       e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_N, Vy, g.ni, nn, B_N,
                                                W, g.ni, nn, T, g.ni, nn, 1.0, false, st);
