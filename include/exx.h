@@ -172,9 +172,10 @@ exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec,
  * apply the triangular inverse Cholesky factor W (S^+ = W^H W) to the grid
  * and form Vb = W^H Vy W from the contraction of its transform (with
  * refinement on, exx_set_refinement, it runs the stage-wise form). It forks a
- * second stream of the handle (the Gamma fit beside the factorisation; in
- * EXX_F64 also the contraction of each chunk of transfers beside the transform
- * of the next) and joins it back into `stream` before returning, so work
+ * second stream of the handle (the Gamma fit beside the factorisation; on the
+ * paired path, and in EXX_F64 on the real path, also the contraction of each
+ * chunk of transfers beside the transform of the next) and joins it back into
+ * `stream` before returning, so work
  * ordered on `stream` before and after the call stays ordered. Arguments as
  * above; error behaviour as above.
  */

@@ -580,11 +580,13 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
                               true);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
-  // Vy (unphased, slice order) into V. FP64 storage: the slices go in four
-  // chunks, the transform of each on the caller's stream and its contraction
-  // on the second stream, as in the real path (the timed phases then overlap)
+  // Vy (unphased, slice order) into V. The slices go in four chunks, the
+  // transform of each on the caller's stream and its contraction on the second
+  // stream (the timed phases then overlap). Unlike the real path this pays in
+  // every precision here: the complex transform and the 32 x 32 contraction
+  // tiles of FP32 storage leave each other room on the CUs
   double2* Vy = (double2*)V;
-  const int nchunk = sizeof(TX) == 8 ? std::min(4, gr.nk) : 1;
+  const int nchunk = std::min(4, gr.nk);
   if (nchunk == 1) {
     {
       PhaseTimer pt(h, PH_FFT, st);
