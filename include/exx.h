@@ -38,7 +38,8 @@
  * --------------------
  * Every array argument is caller-owned DEVICE memory unless marked "host";
  * the library never frees caller memory. Scratch memory belongs to the handle
- * (allocated on first use, grown on demand, released by exx_destroy). Calls
+ * (allocated on first use, grown on demand, released by exx_destroy) unless
+ * the caller provides it (exx_set_workspace). Calls
  * are asynchronous on the given stream (0 = default stream) and return a
  * status; no C++ exception crosses the ABI. Shape and argument checks happen
  * before any launch; on error nothing is launched and exx_last_error(h)
@@ -63,8 +64,8 @@ typedef enum {
   EXX_ERR_ARG = -1,         /* null pointer, bad enum, bad handle */
   EXX_ERR_SHAPE = -2,       /* sizes out of the supported range */
   EXX_ERR_NOMEM = -3,       /* scratch allocation failed */
-  EXX_ERR_NOT_PD = -4,      /* reserved: fit metric not positive definite */
-  EXX_ERR_NONFINITE = -5,   /* reserved: non-finite input detected */
+  EXX_ERR_NOT_PD = -4,      /* a fit metric lost a pivot (EXX_STRICT_PD only) */
+  EXX_ERR_NONFINITE = -5,   /* a non-finite value reached a checked array */
   EXX_ERR_DEVICE = -6,      /* a HIP runtime call failed */
   EXX_ERR_UNSUPPORTED = -7  /* precision or size not built in */
 } exx_status;
@@ -106,6 +107,59 @@ exx_status exx_destroy(exx_handle_t h);
 const char* exx_last_error(exx_handle_t h);
 /* Bytes of scratch the handle currently holds. */
 exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes);
+
+/*
+ * Caller-owned scratch. exx_workspace_size returns the scratch bytes that one
+ * kind of call needs for this cell (and precision, for the K-build calls):
+ *   EXX_CALL_BUILD       exx_isdf_fit, exx_coulomb_V, exx_build_K, exx_build and
+ *                        an exx_build_batched item (the largest of them)
+ *   EXX_CALL_SELECT      exx_select_points
+ *   EXX_CALL_SELECT_MLP  exx_select_points_mlp (n_probe up to 8192)
+ * exx_set_workspace hands the handle a device buffer (256-byte aligned, caller
+ * owned, e.g. a torch tensor) that every later call uses as its scratch; the
+ * library then allocates no scratch of its own and releases what it held. A
+ * call needing more than `bytes` fails with EXX_ERR_NOMEM before any launch.
+ * dev = NULL returns to library-owned scratch. The call synchronises the device
+ * first. The buffer must stay valid until it is replaced or the handle is
+ * destroyed, and calls sharing it must be ordered. The handle still keeps a
+ * few small tables of its own (FFT twiddles and Bloch phases per grid shape,
+ * the status word).
+ */
+#define EXX_CALL_BUILD 0
+#define EXX_CALL_SELECT 1
+#define EXX_CALL_SELECT_MLP 2
+exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec prec, int32_t call,
+                              size_t* bytes);
+exx_status exx_set_workspace(exx_handle_t h, void* dev, size_t bytes);
+
+/*
+ * Run-time checks (failure detection). The K-build calls report into a device
+ * status word of the handle; kernels set its bits and the host reads them with
+ * exx_get_status, so the checks never stall the stream.
+ *   EXX_CHECK_FINITE  (default on) scan the small inputs occ_pts and ao_pts, the
+ *                     Coulomb matrices given to or returned by the stage-wise
+ *                     calls, and the outputs K and E_x for NaN or Inf; the
+ *                     Cholesky factorisation reports a non-finite pivot. A
+ *                     non-finite psi_grid reaches V, K and E_x and is reported
+ *                     there (exx_isdf_fit alone does not scan xi).
+ *   EXX_STRICT_PD     the drop rule (a Schur pivot below 1e-12 max_P S_PP) still
+ *                     applies, but a dropped pivot is reported as EXX_ERR_NOT_PD
+ *                     with the lowest transfer index m whose metric lost one.
+ *   EXX_CHECK_SYNC    every K-build call synchronises its stream at the end and
+ *                     returns the status (EXX_ERR_NONFINITE before
+ *                     EXX_ERR_NOT_PD) instead of EXX_OK.
+ * exx_get_status synchronises `stream`, reads and clears the status word and
+ * returns EXX_OK, EXX_ERR_NONFINITE or EXX_ERR_NOT_PD. info (host, may be NULL):
+ * info[0] = the first transfer that lost a pivot under EXX_STRICT_PD (-1 if
+ * none), info[1] = where the first non-finite value was seen (0 none, 1 occ_pts,
+ * 2 ao_pts, 3 fit metric, 4 Coulomb matrices, 5 K or E_x). The status word
+ * accumulates over calls until it is read.
+ */
+#define EXX_CHECK_FINITE 1
+#define EXX_STRICT_PD 2
+#define EXX_CHECK_SYNC 4
+exx_status exx_set_checks(exx_handle_t h, int32_t flags);
+exx_status exx_get_status(exx_handle_t h, hipStream_t stream, int32_t* info);
 
 /*
  * exx_isdf_fit -- occupied-pair ISDF fit per transfer q (Sec. 2.2-2.3,

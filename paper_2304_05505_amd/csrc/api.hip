@@ -41,6 +41,13 @@ exx_status hip_check(exx_context* h, hipError_t e, const char* what) {
 
 void* ws_get(exx_context* h, size_t bytes, exx_status* st) {
   *st = EXX_OK;
+  if (h->user_ws) {
+    if (bytes <= h->user_ws_bytes) return h->user_ws;
+    *st = fail(h, EXX_ERR_NOMEM,
+               "the workspace set by exx_set_workspace holds " + std::to_string(h->user_ws_bytes) +
+                   " bytes; this call needs " + std::to_string(bytes));
+    return nullptr;
+  }
   if (h->ws.cap >= bytes) return h->ws.base;
   if (h->ws.base) {
     hipError_t e = hipDeviceSynchronize();
@@ -127,7 +134,12 @@ struct Layout {
   int nsplit;
 };
 
-Layout layout(const Geom& g, exx_prec prec, bool build) {
+// what a call needs besides the point-sized matrices
+enum Need { NEED_FIT = 1, NEED_COULOMB = 2, NEED_K = 4, NEED_BUILD = 8 };
+
+Layout layout(const Geom& g, exx_prec prec, int need) {
+  const bool build = (need & NEED_BUILD) != 0;
+  const bool grid = (need & (NEED_FIT | NEED_COULOMB | NEED_BUILD)) != 0;
   Layout L;
   const size_t mat = al(sizeof(double2) * (size_t)g.nk * g.ni * g.ni);
   // Gamma/Z (and F) buffer: FP64 unless the fit itself runs in FP32; xi: FP64 only in EXX_F64
@@ -152,7 +164,7 @@ Layout layout(const Geom& g, exx_prec prec, bool build) {
   o += al(sizeof(double) * 1024);
   L.nsplit = coulomb_nsplit(g);
   L.cpart = o;
-  o += al(coulomb_partial_bytes(g, L.nsplit));
+  o += grid ? al(coulomb_partial_bytes(g, L.nsplit)) : 0;
   L.S2 = o;
   o += build ? mat : 0;
   L.V2 = o;
@@ -164,11 +176,53 @@ Layout layout(const Geom& g, exx_prec prec, bool build) {
   L.Tinv = o;
   o += al(sizeof(double2) * (size_t)g.nk * 32 * g.ni);
   L.grid = o;
-  o += al(cs * (size_t)g.nk * g.ni * g.ng);
+  o += grid ? al(cs * (size_t)g.nk * g.ni * g.ng) : 0;
   L.grid2 = o;
   o += build ? al(cx * (size_t)g.nk * g.ni * g.ng) : 0;
   L.total = o;
   return L;
+}
+
+// status word for the kernels' reports (null when no check is enabled)
+int32_t* stat_ptr(exx_context* h) {
+  return (h->checks & (EXX_CHECK_FINITE | EXX_STRICT_PD)) ? h->dstat : nullptr;
+}
+bool strict_pd(exx_context* h) { return (h->checks & EXX_STRICT_PD) != 0; }
+
+// non-finite scans of a call's small inputs and outputs (EXX_CHECK_FINITE)
+exx_status scan(exx_context* h, const void* p, long n_doubles, int site, hipStream_t st) {
+  if (!(h->checks & EXX_CHECK_FINITE) || !p) return EXX_OK;
+  return hip_check(h, launch_check_finite((const double*)p, n_doubles, h->dstat, site, st),
+                   "finite check");
+}
+
+// read and clear the status word after synchronising st
+exx_status read_status(exx_context* h, hipStream_t st, int32_t* info) {
+  int32_t v[3] = {0, INT_MAX, INT_MAX};
+  hipError_t e = hipMemcpyAsync(v, h->dstat, sizeof(v), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = launch_status_reset(h->dstat, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_check(h, e, "status read");
+  if (info) {
+    info[0] = (v[0] & ST_NOT_PD) ? v[1] : -1;
+    info[1] = (v[0] & ST_NONFINITE) ? v[2] : 0;
+  }
+  if (v[0] & ST_NONFINITE)
+    return fail(h, EXX_ERR_NONFINITE, "non-finite value (site " + std::to_string(v[2]) +
+                                          ": 1 occ_pts, 2 ao_pts, 3 fit metric, 4 Coulomb "
+                                          "matrices, 5 K or E_x)");
+  if (v[0] & ST_NOT_PD)
+    return fail(h, EXX_ERR_NOT_PD, "fit metric of transfer " + std::to_string(v[1]) +
+                                       " lost a pivot to the drop rule (EXX_STRICT_PD)");
+  return EXX_OK;
+}
+
+// end of a K-build call: with EXX_CHECK_SYNC the call waits for its work and
+// returns the status word
+exx_status finish(exx_context* h, hipStream_t st) {
+  if (!(h->checks & EXX_CHECK_SYNC)) return EXX_OK;
+  return read_status(h, st, nullptr);
 }
 
 // TF: type of Gamma^n / Z^m (and of psi_grid); TX: storage type of xi
@@ -213,7 +267,8 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
     e = launch_copy(Lf, (const double2*)S, (long)g.nk * nn, ax);
     if (e != hipSuccess) what = "copy S";
     if (!what) {
-      e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax);
+      e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax, stat_ptr(h),
+                              strict_pd(h));
       if (e != hipSuccess) what = "cholesky";
     }
   }
@@ -353,7 +408,8 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     e = launch_copy(Lf, (const double2*)S, (long)g.nk * nn, ax);
     if (e != hipSuccess) what = "copy S";
     if (!what) {
-      e = launch_chol_blocked_real(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax);
+      e = launch_chol_blocked_real(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax,
+                                   stat_ptr(h), strict_pd(h));
       if (e != hipSuccess) what = "cholesky";
     }
   }
@@ -535,7 +591,10 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   }
   if (!what) {
     PhaseTimer pt(h, PH_CHOL, ax);
-    e = launch_chol_blocked(gr, Lf, keep, rank_c, (double*)(ws + L.tol), 1e-12, ax);
+    QLabel lab;
+    for (int k = 0; k < 64; ++k) lab.q[k] = k < pr.n ? pr.rep[k] : 0;
+    e = launch_chol_blocked(gr, Lf, keep, rank_c, (double*)(ws + L.tol), 1e-12, ax, stat_ptr(h),
+                            strict_pd(h), &lab);
     if (e != hipSuccess) what = "cholesky";
   }
   if (!what) {
@@ -682,14 +741,27 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
   return s;
 }
 
-// have_G: the point Gram G^n is already in the scratch (the fused build's fit
-// formed it from the same occ and nothing since has written that region)
-exx_status buildK_impl(exx_context* h, const Geom& g, char* ws, const Layout& L, const void* ao,
+// scratch of the exchange contraction: G^n and Y^n [N_k][N_ISDF][N_ISDF],
+// T [N_k][N_ISDF][n_ao], AH [N_k][n_ao][N_ISDF] (used when n_ao <= N_ISDF),
+// epart [1024] doubles
+struct KScratch {
+  double2 *G, *Y, *T, *AH;
+  double* epart;
+};
+
+KScratch kscratch(char* ws, const Layout& L) {
+  return {(double2*)(ws + L.G), (double2*)(ws + L.Y), (double2*)(ws + L.T), (double2*)(ws + L.Sp),
+          (double*)(ws + L.epart)};
+}
+
+// have_G: the point Gram G^n is already in ks.G (the fused build's fit formed it
+// from the same occ and nothing since has written that region)
+exx_status buildK_impl(exx_context* h, const Geom& g, const KScratch& ks, const void* ao,
                        const void* occ, const void* V, void* K, double* Ex, hipStream_t st,
                        bool have_G = false) {
-  double2* G = (double2*)(ws + L.G);
-  double2* Y = (double2*)(ws + L.Y);
-  double2* T = (double2*)(ws + L.T);
+  double2* G = ks.G;
+  double2* Y = ks.Y;
+  double2* T = ks.T;
   const long nn = (long)g.ni * g.ni;
   hipError_t e = hipSuccess;
   if (!have_G) {
@@ -710,9 +782,8 @@ exx_status buildK_impl(exx_context* h, const Geom& g, char* ws, const Layout& L,
   const long na_i = (long)g.ni * g.nao;
   if (g.nao <= g.ni) {
     // both products on the FP64 matrix cores: T = Y A, then K = ((1/N_k) A^H) T
-    // with A^H written once into the S^+ scratch (free here; it holds
-    // N_k N_ISDF^2 >= N_k n_ao N_ISDF entries)
-    double2* AH = (double2*)(ws + L.Sp);
+    // with A^H written once
+    double2* AH = ks.AH;
     e = zgemm_nn_grid<double, double>(g.ni, g.nao, g.ni, g.nk, Y, g.ni, nn, false, ao, g.nao,
                                       na_i, T, g.nao, na_i, st, 22);
     if (e != hipSuccess) return hip_check(h, e, "Y A gemm");
@@ -732,12 +803,14 @@ exx_status buildK_impl(exx_context* h, const Geom& g, char* ws, const Layout& L,
   }
   // c3: E_x
   PhaseTimer pte(h, PH_ENERGY, st);
-  e = launch_energy(g, Y, G, (double*)(ws + L.epart), Ex, st);
+  e = launch_energy(g, Y, G, ks.epart, Ex, st);
   if (e != hipSuccess) return hip_check(h, e, "energy");
-  return EXX_OK;
+  exx_status s = scan(h, K, 2L * g.nk * g.nao * g.nao, SITE_OUTPUT, st);
+  if (s == EXX_OK) s = scan(h, Ex, 1, SITE_OUTPUT, st);
+  return s;
 }
 
-exx_status setup(exx_context* h, const exx_cell* cell, exx_prec prec, bool build, Geom* g,
+exx_status setup(exx_context* h, const exx_cell* cell, exx_prec prec, int need, Geom* g,
                  Tables* tb, Layout* L, char** ws, hipStream_t st) {
   exx_status s = check_cell(h, cell, prec);
   if (s != EXX_OK) return s;
@@ -753,7 +826,7 @@ exx_status setup(exx_context* h, const exx_cell* cell, exx_prec prec, bool build
   e = fft_prepare(&h->ncu);
   if (e != hipSuccess) return hip_check(h, e, "FFT set-up");
   *g = make_geom(*cell);
-  *L = layout(*g, prec, build);
+  *L = layout(*g, prec, need);
   *ws = (char*)ws_get(h, L->total, &s);
   if (s != EXX_OK) return s;
   return get_tables(h, *g, tb, st);
@@ -774,6 +847,16 @@ exx_status exx_create(exx_handle_t* h, int device) {
   exx_context* c = new (std::nothrow) exx_context();
   if (!c) return EXX_ERR_NOMEM;
   c->device = device;
+  // the device status word, cleared once here and after every exx_get_status
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->dstat, 4 * sizeof(int32_t));
+  if (e == hipSuccess) e = launch_status_reset(c->dstat, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    if (c->dstat) (void)hipFree(c->dstat);
+    delete c;
+    return EXX_ERR_DEVICE;
+  }
   // wave tiles of the grid GEMMs (16x16 blocks); EXX_TILE_GAMMA / EXX_TILE_SOLVE override
   if (const char* v = getenv("EXX_TILE_GAMMA")) c->tile_gamma = atoi(v);
   if (const char* v = getenv("EXX_TILE_SOLVE")) c->tile_solve = atoi(v);
@@ -789,6 +872,7 @@ exx_status exx_destroy(exx_handle_t h) {
   for (auto& te : h->tabs) (void)hipFree(te.buf);
   for (auto& ge : h->graphs) (void)hipGraphExecDestroy(ge.exec);
   if (h->small) (void)hipFree(h->small);
+  if (h->dstat) (void)hipFree(h->dstat);
   for (auto& r : h->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -822,13 +906,17 @@ exx_status exx_isdf_fit(exx_handle_t h, const exx_cell* cell, exx_prec prec, con
   Tables tb;
   Layout L;
   char* ws;
-  exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
+  exx_status s = setup(h, cell, prec, NEED_FIT, &g, &tb, &L, &ws, stream);
+  if (s != EXX_OK) return s;
+  s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
   if (s != EXX_OK) return s;
   if (prec == EXX_F64)
-    return fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-  if (prec == EXX_MIXED)
-    return fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
-  return fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+    s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+  else if (prec == EXX_MIXED)
+    s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+  else
+    s = fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+  return s == EXX_OK ? finish(h, stream) : s;
 }
 
 exx_status exx_coulomb_V(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* xi,
@@ -840,10 +928,14 @@ exx_status exx_coulomb_V(exx_handle_t h, const exx_cell* cell, exx_prec prec, co
   Tables tb;
   Layout L;
   char* ws;
-  exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
+  exx_status s = setup(h, cell, prec, NEED_COULOMB, &g, &tb, &L, &ws, stream);
   if (s != EXX_OK) return s;
-  if (prec == EXX_F64) return coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
-  return coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
+  if (prec == EXX_F64)
+    s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
+  else
+    s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
+  if (s == EXX_OK) s = scan(h, V, 2L * g.nk * g.ni * g.ni, SITE_COULOMB, stream);
+  return s == EXX_OK ? finish(h, stream) : s;
 }
 
 exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* ao_pts,
@@ -857,9 +949,13 @@ exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec, cons
   Tables tb;
   Layout L;
   char* ws;
-  exx_status s = setup(h, cell, prec, false, &g, &tb, &L, &ws, stream);
+  exx_status s = setup(h, cell, prec, NEED_K, &g, &tb, &L, &ws, stream);
   if (s != EXX_OK) return s;
-  return buildK_impl(h, g, ws, L, ao_pts, occ_pts, V, K, Ex, stream);
+  s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
+  if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
+  if (s == EXX_OK) s = scan(h, V, 2L * g.nk * g.ni * g.ni, SITE_COULOMB, stream);
+  if (s == EXX_OK) s = buildK_impl(h, g, kscratch(ws, L), ao_pts, occ_pts, V, K, Ex, stream);
+  return s == EXX_OK ? finish(h, stream) : s;
 }
 
 exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const void* psi_grid,
@@ -873,11 +969,83 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   Tables tb;
   Layout L;
   char* ws;
-  exx_status s = setup(h, cell, prec, true, &g, &tb, &L, &ws, stream);
+  exx_status s = setup(h, cell, prec, NEED_BUILD, &g, &tb, &L, &ws, stream);
   if (s != EXX_OK) return s;
-  s = fit_coulomb(h, g, tb, ws, L, prec, psi_grid, occ_pts, pts, rank, stream);
+  s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
+  if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
+  if (s == EXX_OK) s = fit_coulomb(h, g, tb, ws, L, prec, psi_grid, occ_pts, pts, rank, stream);
+  if (s == EXX_OK)
+    s = buildK_impl(h, g, kscratch(ws, L), ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
+  return s == EXX_OK ? finish(h, stream) : s;
+}
+
+exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec prec, int32_t call,
+                              size_t* bytes) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!bytes) return fail(h, EXX_ERR_ARG, "exx_workspace_size: bytes is NULL");
+  exx_status s = check_cell(h, cell, call == EXX_CALL_BUILD ? prec : EXX_F64);
   if (s != EXX_OK) return s;
-  return buildK_impl(h, g, ws, L, ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
+  const Geom g = make_geom(*cell);
+  if (call == EXX_CALL_BUILD) {
+    if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
+    size_t b = layout(g, prec, NEED_BUILD).total;
+    b = std::max(b, layout(g, prec, NEED_FIT | NEED_COULOMB | NEED_K).total);
+    *bytes = b;
+    return EXX_OK;
+  }
+  if (call == EXX_CALL_SELECT) {
+    *bytes = select_scratch_bytes(g);
+    return EXX_OK;
+  }
+  if (call == EXX_CALL_SELECT_MLP) {
+    size_t inner = mlp_feature_scratch_bytes(g);
+    inner = std::max(inner, mlp_nms_scratch_bytes(g));
+    inner = std::max(inner, mlp_probe_scratch_bytes(g, 8192));
+    inner = std::max(inner, select_scratch_bytes(g));
+    *bytes = al(sizeof(float) * 3 * (size_t)g.ng) + al(sizeof(float) * (size_t)g.ng) +
+             al(sizeof(double)) + inner;
+    return EXX_OK;
+  }
+  return fail(h, EXX_ERR_ARG, "exx_workspace_size: unknown call");
+}
+
+exx_status exx_set_workspace(exx_handle_t h, void* dev, size_t bytes) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (dev && ((uintptr_t)dev % 256 != 0))
+    return fail(h, EXX_ERR_ARG, "exx_set_workspace: the workspace must be 256-byte aligned");
+  if (dev && bytes == 0) return fail(h, EXX_ERR_ARG, "exx_set_workspace: zero bytes");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  // work queued on the old scratch must finish before it is released or replaced
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_check(h, e, "hipDeviceSynchronize");
+  if (h->ws.base) {
+    (void)hipFree(h->ws.base);
+    h->ws.base = nullptr;
+    h->ws.cap = 0;
+  }
+  h->user_ws = (char*)dev;
+  h->user_ws_bytes = dev ? bytes : 0;
+  return EXX_OK;
+}
+
+exx_status exx_set_checks(exx_handle_t h, int32_t flags) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (flags & ~(EXX_CHECK_FINITE | EXX_STRICT_PD | EXX_CHECK_SYNC))
+    return fail(h, EXX_ERR_ARG, "exx_set_checks: unknown flag");
+  h->checks = flags;
+  return EXX_OK;
+}
+
+exx_status exx_get_status(exx_handle_t h, hipStream_t stream, int32_t* info) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  return read_status(h, stream, info);
 }
 
 exx_status exx_set_refinement(exx_handle_t h, int32_t steps) {
@@ -931,9 +1099,13 @@ namespace {
 
 exx_status build_one(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                      exx_prec prec, const exx_batch_item& it, hipStream_t st) {
-  exx_status s = fit_coulomb(h, g, tb, ws, L, prec, it.psi_grid, it.occ_pts, it.pts, it.rank, st);
+  exx_status s = scan(h, it.occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, st);
+  if (s == EXX_OK) s = scan(h, it.ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, st);
+  if (s == EXX_OK)
+    s = fit_coulomb(h, g, tb, ws, L, prec, it.psi_grid, it.occ_pts, it.pts, it.rank, st);
   if (s != EXX_OK) return s;
-  return buildK_impl(h, g, ws, L, it.ao_pts, it.occ_pts, ws + L.V2, it.K, it.Ex, st, true);
+  return buildK_impl(h, g, kscratch(ws, L), it.ao_pts, it.occ_pts, ws + L.V2, it.K, it.Ex, st,
+                     true);
 }
 
 void tune_key(const Geom& g, exx_prec prec, long* key) {
@@ -1029,7 +1201,7 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
     if (!it.psi_grid || !it.occ_pts || !it.ao_pts || !it.pts || !it.K || !it.Ex || !it.rank)
       return fail(h, EXX_ERR_ARG, "item " + std::to_string(i) + ": null array");
     geo[i] = make_geom(it.cell);
-    lay[i] = layout(geo[i], prec, true);
+    lay[i] = layout(geo[i], prec, NEED_BUILD);
     need = lay[i].total > need ? lay[i].total : need;
   }
   exx_status s;
@@ -1061,7 +1233,10 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
     }
     return EXX_OK;
   };
-  if (!(flags & EXX_BATCH_GRAPH)) return run_all();
+  if (!(flags & EXX_BATCH_GRAPH)) {
+    s = run_all();
+    return s == EXX_OK ? finish(h, stream) : s;
+  }
   if (stream == nullptr)
     return fail(h, EXX_ERR_ARG, "EXX_BATCH_GRAPH needs a non-default stream (capture)");
 
@@ -1082,8 +1257,12 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
     const exx_context::Tune* t = find_tune(h, key);
     sig.push_back(t ? t->gamma * 100 + t->solve : 0);
   }
+  sig.push_back((long)h->checks);
   for (const auto& ge : h->graphs)
-    if (ge.sig == sig) return hip_check(h, hipGraphLaunch(ge.exec, stream), "hipGraphLaunch");
+    if (ge.sig == sig) {
+      s = hip_check(h, hipGraphLaunch(ge.exec, stream), "hipGraphLaunch");
+      return s == EXX_OK ? finish(h, stream) : s;
+    }
   const bool timing = h->timing;
   h->timing = false;  // no event records inside the captured sequence
   e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
@@ -1105,7 +1284,8 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return hip_check(h, e, "hipGraphInstantiate");
   h->graphs.push_back({sig, exec});
-  return hip_check(h, hipGraphLaunch(exec, stream), "hipGraphLaunch");
+  s = hip_check(h, hipGraphLaunch(exec, stream), "hipGraphLaunch");
+  return s == EXX_OK ? finish(h, stream) : s;
 }
 
 namespace {

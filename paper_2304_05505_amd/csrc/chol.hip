@@ -8,6 +8,9 @@
 // rel_tol * max_P S^m_PP is dropped: its column of L is zero, it does not
 // update later columns, and its row and column of L^{-1} are zero. The
 // retained block then satisfies S_RR = L_RR L_RR^H.
+#include <algorithm>
+#include <climits>
+
 #include "common.h"
 
 namespace exx {
@@ -39,10 +42,15 @@ __global__ __launch_bounds__(PNT) void chol_init_kernel(const double2* __restric
 }
 
 // Factorise the diagonal block at c0 (width w) and solve the rows below it.
+// status (may be null): a non-finite pivot sets ST_NONFINITE with site
+// SITE_METRIC; with strict, a pivot dropped by the rule sets ST_NOT_PD and
+// lowers status[1] to the transfer label of this metric.
 __global__ __launch_bounds__(PNT) void chol_panel_kernel(double2* __restrict__ A, int n, int c0,
                                                          const double* __restrict__ tol,
                                                          int32_t* __restrict__ keep,
-                                                         int32_t* __restrict__ rank) {
+                                                         int32_t* __restrict__ rank,
+                                                         int32_t* __restrict__ status, int strict,
+                                                         QLabel lab) {
   const int m = blockIdx.x;
   double2* Am = A + (long)m * n * n;
   int32_t* km = keep + (long)m * n;
@@ -72,6 +80,15 @@ __global__ __launch_bounds__(PNT) void chol_panel_kernel(double2* __restrict__ A
     if (tid == 0) {
       kp[p] = ok ? 1 : 0;
       s_kept += ok ? 1 : 0;
+      if (!ok && status) {
+        if (!isfinite(d)) {
+          atomicOr(status, (int)ST_NONFINITE);
+          atomicMin(status + 2, (int)SITE_METRIC);
+        } else if (strict) {
+          atomicOr(status, (int)ST_NOT_PD);
+          atomicMin(status + 1, lab.q[m]);
+        }
+      }
     }
     __syncthreads();
     if (ok) {
@@ -118,6 +135,18 @@ __global__ __launch_bounds__(PNT) void chol_panel_kernel(double2* __restrict__ A
 #pragma unroll
     for (int p = 0; p < NB; ++p)
       if (p < w) row[p] = x[p];
+  }
+}
+
+// status[0] |= ST_NONFINITE, status[2] = min(status[2], site) if any value is not finite
+__global__ __launch_bounds__(256) void check_finite_kernel(const double* __restrict__ p, long n,
+                                                           int32_t* __restrict__ status, int site) {
+  bool bad = false;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256)
+    bad |= !isfinite(p[e]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) {
+    atomicOr(status, (int)ST_NONFINITE);
+    atomicMin(status + 2, site);
   }
 }
 
@@ -203,22 +232,54 @@ hipError_t launch_rank_scatter(const int32_t* rc, int32_t* rank, const int* rep,
   return hipGetLastError();
 }
 
+__global__ void status_reset_kernel(int32_t* __restrict__ status) {
+  if (threadIdx.x == 0) {
+    status[0] = 0;
+    status[1] = INT_MAX;
+    status[2] = INT_MAX;
+    status[3] = 0;
+  }
+}
+
+hipError_t launch_status_reset(int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(status_reset_kernel, dim3(1), dim3(64), 0, st, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* p, long n, int32_t* status, int site,
+                               hipStream_t st) {
+  if (n <= 0 || !status) return hipSuccess;
+  const long blocks = std::min<long>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, status,
+                     site);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 
+static QLabel labels(const QLabel* lab) {
+  QLabel l;
+  for (int s = 0; s < 64; ++s) l.q[s] = lab ? lab->q[s] : s;
+  return l;
+}
+
 hipError_t launch_chol_blocked(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
-                               double* tol, double rel_tol, hipStream_t st) {
+                               double* tol, double rel_tol, hipStream_t st, int32_t* status,
+                               bool strict, const QLabel* lab) {
   const int n = g.ni;
   const long nn = (long)n * n;
+  const QLabel ql = labels(lab);
   hipLaunchKernelGGL(chol_init_kernel, dim3(g.nk), dim3(PNT), 0, st, A, n, rel_tol, tol, rank);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int c0 = 0; c0 < n; c0 += NB) {
     const int w = n - c0 < NB ? n - c0 : NB;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(g.nk), dim3(PNT), 0, st, A, n, c0, tol, keep, rank);
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(g.nk), dim3(PNT), 0, st, A, n, c0, tol, keep, rank,
+                       status, strict ? 1 : 0, ql);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int r = n - c0 - w;
@@ -265,16 +326,19 @@ hipError_t launch_tri_inv_blocked(const Geom& g, const double2* Lf, const int32_
 // the real parts through the strided FP64 matrix-core product; the panel and
 // diagonal-block kernels are the complex ones, exact on real data.
 hipError_t launch_chol_blocked_real(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
-                                   double* tol, double rel_tol, hipStream_t st) {
+                                   double* tol, double rel_tol, hipStream_t st, int32_t* status,
+                                   bool strict) {
   const int n = g.ni;
   const long nn = (long)n * n;
+  const QLabel ql = labels(nullptr);
   hipLaunchKernelGGL(chol_init_kernel, dim3(g.nk), dim3(PNT), 0, st, A, n, rel_tol, tol, rank);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double* Ad = (double*)A;
   for (int c0 = 0; c0 < n; c0 += NB) {
     const int w = n - c0 < NB ? n - c0 : NB;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(g.nk), dim3(PNT), 0, st, A, n, c0, tol, keep, rank);
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(g.nk), dim3(PNT), 0, st, A, n, c0, tol, keep, rank,
+                       status, strict ? 1 : 0, ql);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int r = n - c0 - w;

@@ -98,6 +98,14 @@ struct exx_context {
   int device = 0;
   std::string err;
   exx::Arena ws;            // grid-sized scratch + small matrices
+  // caller-owned workspace (exx_set_workspace): when set, every scratch request
+  // is served from it and the library allocates no scratch of its own
+  char* user_ws = nullptr;
+  size_t user_ws_bytes = 0;
+  // device status words (exx_get_status): [0] flag bits, [1] first transfer
+  // whose metric lost a pivot under EXX_STRICT_PD, [2] first non-finite site
+  int32_t* dstat = nullptr;
+  int checks = 1;           // EXX_CHECK_* flags
   // per-axis root tables e^{-2 pi i t / (N_i n_i)} for the Bloch phases and
   // twiddle tables for the FFT, one device buffer per (grid, k-mesh) shape
   struct TabEntry {
@@ -145,6 +153,20 @@ namespace exx {
 
 // status helpers
 exx_status fail(exx_context* h, exx_status s, const std::string& msg);
+// bits of the device status word
+enum StatusBits { ST_NONFINITE = 1, ST_NOT_PD = 2 };
+// sites of the first non-finite value (status word [2])
+enum FiniteSite { SITE_OCC = 1, SITE_AO = 2, SITE_METRIC = 3, SITE_COULOMB = 4, SITE_OUTPUT = 5 };
+// transfer label of each factorised metric (slot s of the batch is transfer q[s])
+struct QLabel {
+  int q[64];
+};
+// status[0] |= ST_NONFINITE and status[2] = min(status[2], site) if any of the n
+// doubles at p is not finite
+hipError_t launch_check_finite(const double* p, long n, int32_t* status, int site,
+                               hipStream_t st);
+// status = {0, INT_MAX, INT_MAX, 0} (a kernel, so that it can be captured)
+hipError_t launch_status_reset(int32_t* status, hipStream_t st);
 exx_status hip_check(exx_context* h, hipError_t e, const char* what);
 
 // scratch: returns pointer to >= bytes of workspace (grown on demand)
@@ -287,13 +309,19 @@ hipError_t launch_rank_scatter(const int32_t* rc, int32_t* rank, const int* rep,
 
 // Blocked Cholesky with pivot drop (A: S^m in, L in the lower triangle out;
 // tol: [N_k] scratch) and blocked inverse W = L^{-1} (T: [N_k][32][N_I] scratch)
+// status/strict: a non-finite pivot sets ST_NONFINITE (site SITE_METRIC); with
+// strict, a dropped pivot sets ST_NOT_PD and status[1] = min(status[1], lab.q[m])
+// (status may be nullptr: no reporting). lab == nullptr labels slot m as m.
 hipError_t launch_chol_blocked(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
-                               double* tol, double rel_tol, hipStream_t st);
+                               double* tol, double rel_tol, hipStream_t st,
+                               int32_t* status = nullptr, bool strict = false,
+                               const QLabel* lab = nullptr);
 // real-path forms of launch_chol_blocked and launch_tri_inv_blocked (S~ real,
 // complex storage): same results, with the GEMMs on the real parts (strided FP64
 // matrix-core product)
 hipError_t launch_chol_blocked_real(const Geom& g, double2* A, int32_t* keep, int32_t* rank,
-                                   double* tol, double rel_tol, hipStream_t st);
+                                   double* tol, double rel_tol, hipStream_t st,
+                                   int32_t* status = nullptr, bool strict = false);
 hipError_t launch_tri_inv_real(const Geom& g, const double2* Lf, const int32_t* keep, double2* W,
                                double2* T, hipStream_t st);
 hipError_t launch_tri_inv_blocked(const Geom& g, const double2* Lf, const int32_t* keep,

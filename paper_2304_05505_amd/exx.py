@@ -51,9 +51,16 @@ EXPORTED = (
     "exx_mlp_nms",
     "exx_mlp_probe",
     "exx_select_points_mlp",
+    "exx_workspace_size",
+    "exx_set_workspace",
+    "exx_set_checks",
+    "exx_get_status",
 )
 
 EXX_BATCH_GRAPH, EXX_BATCH_TUNE = 1, 2
+EXX_CALL_BUILD, EXX_CALL_SELECT, EXX_CALL_SELECT_MLP = 0, 1, 2
+EXX_CHECK_FINITE, EXX_STRICT_PD, EXX_CHECK_SYNC = 1, 2, 4
+EXX_ERR_NOT_PD, EXX_ERR_NONFINITE = -4, -5
 EXX_MLP_NPARAM = 4481
 
 PHASES = ("G", "S", "cholesky", "pinv", "gamma", "kcorr", "solve", "fft", "coulomb",
@@ -128,6 +135,11 @@ def _load():
         "exx_select_points_mlp": ([vp, cellp, vp, ctypes.POINTER(ctypes.c_double), vp,
                                    ctypes.c_double, ctypes.c_int32, vp, i32p,
                                    ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
+        "exx_workspace_size": ([vp, cellp, ctypes.c_int, ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "exx_set_workspace": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
+        "exx_set_checks": ([vp, ctypes.c_int32], ctypes.c_int),
+        "exx_get_status": ([vp, vp, i32p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +248,39 @@ class Handle:
         b = ctypes.c_size_t()
         self._check(_lib.exx_scratch_bytes(self._h, ctypes.byref(b)))
         return b.value
+
+    def workspace_size(self, cell: ExxCell, prec: int, call: int = EXX_CALL_BUILD) -> int:
+        """Scratch bytes one kind of call needs for this cell (exx_workspace_size)."""
+        b = ctypes.c_size_t()
+        self._check(_lib.exx_workspace_size(self._h, ctypes.byref(cell), int(prec), int(call),
+                                            ctypes.byref(b)))
+        return b.value
+
+    def set_workspace(self, buf):
+        """Use a caller-owned device buffer (a uint8 torch tensor on this device) as the
+        handle's scratch; None returns to library-owned scratch. The handle keeps a
+        reference to the tensor while it is in use."""
+        if buf is None:
+            self._check(_lib.exx_set_workspace(self._h, None, 0))
+            self._ws = None
+            return
+        if not isinstance(buf, torch.Tensor) or buf.device != self.device or not buf.is_contiguous():
+            raise ValueError("workspace must be a contiguous tensor on the handle's device")
+        self._check(_lib.exx_set_workspace(self._h, buf.data_ptr(),
+                                           buf.numel() * buf.element_size()))
+        self._ws = buf
+
+    def set_checks(self, flags: int):
+        self._check(_lib.exx_set_checks(self._h, int(flags)))
+
+    def status(self, stream=None):
+        """exx_get_status on `stream` (current stream by default): returns
+        (status code, first transfer that lost a pivot or -1, non-finite site or 0)
+        without raising."""
+        info = (ctypes.c_int32 * 2)()
+        st = (stream.cuda_stream if stream is not None else _stream(self.device))
+        code = _lib.exx_get_status(self._h, st, info)
+        return code, info[0], info[1]
 
 
 def exx_isdf_fit(h: Handle, cell: ExxCell, prec: int, psi_grid, occ_pts, pts, xi, S, rank):

@@ -2,17 +2,23 @@
 
 Runs only the FP64 oracle (``oracle/``) on the seeded inputs from ``synth``:
 
-* ``config2.json``: the 48-atom four-ring cell on the 2x2x2 mesh (N = 192,
-  n_occ = 84, grid 60x75x54, N_ISDF = 420). Points chosen by the oracle's
-  pivoted-Cholesky selection; E_x, ranks, cond(S^m) and seeded samples of
-  K^k, Vb^m and S^m.
-* ``config3.json``: the same cell on the 3x3x3 mesh. Points by the oracle's
-  selection; the fit and Coulomb steps for three of the 27 transfers
-  (m = 0, 13, 26): ranks, cond(S^m) and seeded samples of S^m and of the
-  Bloch-gauge Coulomb matrix Vb^m.
+* ``config2.json`` + ``config2_K.npz``: the 48-atom four-ring cell on the
+  2x2x2 mesh (N = 192, n_occ = 84, grid 60x75x54, N_ISDF = 420). Points chosen
+  by the oracle's pivoted-Cholesky selection; E_x (three forms), ranks,
+  cond(S^m), seeded samples of Vb^m and S^m, and the whole K^k.
+* ``config3.json`` + ``config3_K.npz``: the same cell on the 3x3x3 mesh, all
+  27 transfers: E_x (three forms), ranks and cond(S^m) of every transfer,
+  seeded samples of S^m and Vb^m for m = 0, 13, 26, and the whole K^k.
+* ``config4.json`` + ``config4_K.npz``: the 24 cells of the batched workload
+  (2 x {8, 16, 24, 48 atoms} x {1^3, 2^3, 3^3}), each with its own oracle
+  points: E_x (two forms), ranks, cond(S^m), the diagonal of every K^k and
+  2000 seeded entries of K.
 
-Usage: ``python tests/golden/make_golden.py [config2|config3]`` (config2 about
-three minutes and ~25 GB RAM, config3 a few minutes and ~30 GB).
+Each ``.npz`` holds plain complex128 arrays (no pickled objects).
+
+Usage: ``python tests/golden/make_golden.py [config2] [config3] [config4]``.
+Wall times on 8 cores: config2 a few minutes (~25 GB RAM), config3 about
+twenty minutes (~30 GB), config4 about an hour (~30 GB).
 """
 
 from __future__ import annotations
@@ -36,6 +42,15 @@ def cl(a):
     return [[float(x.real), float(x.imag)] for x in a]
 
 
+def _conds(o, nk):
+    """cond(S^m) over the retained points of each transfer."""
+    out = []
+    for m in range(nk):
+        R = np.flatnonzero(o["keep"][m])
+        out.append(float(np.linalg.cond(o["S"][m][np.ix_(R, R)])))
+    return out
+
+
 def make_config2(path):
     t0 = time.time()
     c = synth.make_config(2)
@@ -52,7 +67,6 @@ def make_config2(path):
     vm = rng.integers(0, nk, 1000)
     vp = rng.integers(0, ni, 1000)
     vq = rng.integers(0, ni, 1000)
-    conds = [float(np.linalg.cond(o["S"][m])) for m in range(nk)]
     out = {
         "workload": "48-atom four-ring cell, 2x2x2 mesh, N=192, n_occ=84, grid 60x75x54, N_ISDF=420",
         "seed": list(c.seed),
@@ -62,7 +76,7 @@ def make_config2(path):
         "Ex_trVS": o["Ex_trVS"],
         "Ex_fromK": direct.energy_from_K(o["K"], C),
         "rank": [int(x) for x in o["rank"]],
-        "cond_S": conds,
+        "cond_S": _conds(o, nk),
         "maxabs_K": float(np.abs(o["K"]).max()),
         "maxabs_Vb": float(np.abs(o["Vb"]).max()),
         "K_idx": [[int(a), int(b), int(d)] for a, b, d in zip(kn, kmu, knu)],
@@ -75,7 +89,8 @@ def make_config2(path):
     }
     with open(path, "w") as f:
         json.dump(out, f)
-    print(f"wrote {path}: Ex={o['Ex']:.12f} in {out['seconds']:.0f} s")
+    np.savez_compressed(path.replace(".json", "_K.npz"), K=o["K"])
+    print(f"wrote {path}: Ex={o['Ex']:.12f} in {out['seconds']:.0f} s", flush=True)
 
 
 M3 = (0, 13, 26)
@@ -89,14 +104,20 @@ def make_config3(path):
     pts, npiv = select.select_points(psi, c.n_isdf)
     print(f"config3: points selected ({npiv} pivots) in {time.time() - t0:.0f} s", flush=True)
     ao = np.stack([synth.ao_at_points(c, n, pts) for n in range(c.N_k)])
-    o = thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao, m_subset=list(M3))
+    o = thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao)
     rng = np.random.default_rng(20230406)
-    ni = c.n_isdf
+    ni, nk = c.n_isdf, c.N_k
     out = {
         "workload": "48-atom four-ring cell, 3x3x3 mesh, N=192, n_occ=84, grid 60x75x54, N_ISDF=420",
         "seed": list(c.seed),
         "pts": [int(x) for x in pts],
         "n_pivot": int(npiv),
+        "Ex": o["Ex"],
+        "Ex_trVS": o["Ex_trVS"],
+        "Ex_fromK": direct.energy_from_K(o["K"], C),
+        "rank_all": [int(x) for x in o["rank"]],
+        "cond_S_all": _conds(o, nk),
+        "maxabs_K": float(np.abs(o["K"]).max()),
         "m": list(M3),
         "rank": [int(o["rank"][m]) for m in M3],
         "cond_S": [float(np.linalg.cond(o["S"][m])) for m in M3],
@@ -113,12 +134,63 @@ def make_config3(path):
     out["seconds"] = time.time() - t0
     with open(path, "w") as f:
         json.dump(out, f)
-    print(f"wrote {path} in {out['seconds']:.0f} s")
+    np.savez_compressed(path.replace(".json", "_K.npz"), K=o["K"])
+    print(f"wrote {path}: Ex={o['Ex']:.12f} in {out['seconds']:.0f} s", flush=True)
+
+
+def make_config4(path):
+    cells = synth.make_batch_cells()
+    rng = np.random.default_rng(20230407)
+    meta, arrays = [], {}
+    for i, c in enumerate(cells):
+        t0 = time.time()
+        C = synth.orbital_coeffs(c)
+        psi = synth.orbitals_on_grid(c, C)
+        pts, npiv = select.select_points(psi, c.n_isdf)
+        ao = np.stack([synth.ao_at_points(c, n, pts) for n in range(c.N_k)])
+        t1 = time.time()
+        o = thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao)
+        t_build = time.time() - t1
+        nk, na = c.N_k, c.n_ao
+        kn = rng.integers(0, nk, 2000)
+        kmu = rng.integers(0, na, 2000)
+        knu = rng.integers(0, na, 2000)
+        meta.append({
+            "name": c.name,
+            "seed": list(c.seed),
+            "kmesh": list(c.kmesh),
+            "grid": list(c.grid),
+            "n_occ": c.n_occ,
+            "n_ao": c.n_ao,
+            "n_isdf": c.n_isdf,
+            "pts": [int(x) for x in pts],
+            "n_pivot": int(npiv),
+            "Ex": o["Ex"],
+            "Ex_trVS": o["Ex_trVS"],
+            "rank": [int(x) for x in o["rank"]],
+            "cond_S": _conds(o, nk),
+            "maxabs_K": float(np.abs(o["K"]).max()),
+            "oracle_build_s": t_build,
+        })
+        arrays[f"idx_{i}"] = np.stack([kn, kmu, knu], axis=1).astype(np.int32)
+        arrays[f"val_{i}"] = o["K"][kn, kmu, knu]
+        arrays[f"diag_{i}"] = np.stack([np.diagonal(o["K"][n]) for n in range(nk)])
+        print(f"config4 cell {i} ({c.name}): Ex={o['Ex']:.12f}, selection {t1 - t0:.0f} s, "
+              f"oracle build {t_build:.0f} s", flush=True)
+        del psi, o
+    with open(path, "w") as f:
+        json.dump({"workload": "24 cells: 2 x {8, 16, 24, 48 atoms} x {1, 2, 3}^3 k-meshes, "
+                               "4 functions/atom, n_occ = 0.44 N, N_ISDF = 2.2 N, oracle points",
+                   "cells": meta}, f)
+    np.savez_compressed(path.replace(".json", "_K.npz"), **arrays)
+    print(f"wrote {path}", flush=True)
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config2", "config3"]
+    which = sys.argv[1:] or ["config2", "config3", "config4"]
     if "config2" in which:
         make_config2(os.path.join(HERE, "config2.json"))
     if "config3" in which:
         make_config3(os.path.join(HERE, "config3.json"))
+    if "config4" in which:
+        make_config4(os.path.join(HERE, "config4.json"))

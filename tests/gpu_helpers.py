@@ -65,6 +65,12 @@ def load_golden(name):
         return json.load(f)
 
 
+def load_golden_arrays(name):
+    """Arrays stored beside a golden JSON file (plain numeric .npz, no pickles)."""
+    with np.load(os.path.join(GOLDEN, name), allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
 def cplx_list(a):
     a = np.asarray(a)
     return [[float(x.real), float(x.imag)] for x in a.reshape(-1)]

@@ -1,12 +1,25 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-FP64 tolerance. Both sides compute the same quantities in FP64 but solve the
-fit differently (GPU: explicit pseudo-inverse from the inverted Cholesky
-factor; oracle: two triangular solves) and sum in different orders. The
-forward error of either solve is bounded by ~cond(S^m) * eps64 relative, so
-every comparison uses  tol = 64 * eps64 * max_m cond(S^m_RR)  relative to the
-largest entry of the compared array (floor 1e-12); E_x is compared relative
-to |E_x|. Integer outputs (ranks) must match exactly.
+Tolerances (relative to the largest entry of the compared array; E_x relative
+to |E_x|; ranks must match exactly):
+
+* FP64, stage-wise calls and fused build, on cells whose retained fit metric
+  has cond(S^m_RR) <= 1e8: tol = min(1e-8, max(1e-12, 64 eps64 cond)). Both
+  sides solve the same least-squares problem in FP64 by different routes
+  (GPU: explicit inverse Cholesky factor; oracle: two triangular solves), so
+  they differ by rounding amplified at most by cond(S); the cap keeps the test
+  able to fail at every cell.
+* FP64 on the ill-conditioned cells (cond 4e8 .. 2e10): the stage-wise xi, V
+  and K are determined only to ~eps64 cond by any FP64 solve, so they get
+  tol = min(1e-5, 4 eps64 cond) while the determined quantities, E_x and the
+  occupied block C^H K C, keep fixed tolerances (1e-8, 1e-7). The fused build
+  keeps min(1e-8, ...) on K there as well.
+* The numerically singular 1x2x1 cell (cond 3e17: the drop rule keeps a pivot
+  at rounding level) determines only E_x and the occupied block; those are
+  compared at fixed tolerances, the AO block of K is not.
+* Reduced precision (fused build): MIXED rel E_x <= 3e-7 and rel K <= 3e-7 on
+  every determined cell; F32 rel E_x <= 1e-6 and rel K <= 8 eps32 sqrt(cond)
+  (FP32 rounding of Gamma, Z and xi amplified by the metric).
 """
 
 import numpy as np
@@ -20,18 +33,28 @@ from gpu_helpers import inputs, run_gpu
 pytestmark = pytest.mark.gpu
 
 EPS64 = np.finfo(np.float64).eps
+EPS32 = np.finfo(np.float32).eps
 
 
-def _tol(o):
+def _cond(o):
     conds = []
     for m in range(o["S"].shape[0]):
         R = np.flatnonzero(o["keep"][m])
         conds.append(np.linalg.cond(o["S"][m][np.ix_(R, R)]))
-    return max(1e-12, 64 * EPS64 * max(conds))
+    return float(max(conds))
+
+
+def _tol(o):
+    return min(1e-8, max(1e-12, 64 * EPS64 * _cond(o)))
 
 
 def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _occ_block(K, C):
+    """C^H K C per k: the block of K that E_x and the fit's pair space fix."""
+    return np.stack([C[n].conj().T @ K[n] @ C[n] for n in range(K.shape[0])])
 
 
 CELLS = {
@@ -47,8 +70,12 @@ CELLS = {
                                            (11, 4, 1)),
     "k211": lambda: synth.make_random_cell((6.0, 5.0, 5.0), 2, (12, 10, 10), (2, 1, 1), 3, 33,
                                            (11, 5, 1)),
-    "k121": lambda: synth.make_random_cell((5.0, 6.0, 5.0), 2, (10, 12, 10), (1, 2, 1), 3, 33,
+    "k121": lambda: synth.make_random_cell((5.0, 6.0, 5.0), 2, (10, 12, 10), (1, 2, 1), 3, 16,
                                            (11, 6, 1)),
+    # more points than the pair space has dimensions (N_k n_occ^2 = 18): the drop
+    # rule keeps a rounding-level pivot on one transfer (rank 19, cond 3e17)
+    "k121-singular": lambda: synth.make_random_cell((5.0, 6.0, 5.0), 2, (10, 12, 10), (1, 2, 1),
+                                                    3, 33, (11, 6, 1)),
     "k112": lambda: synth.make_random_cell((5.0, 5.0, 6.0), 2, (10, 10, 12), (1, 1, 2), 3, 33,
                                            (11, 7, 1)),
     "k221": lambda: synth.make_random_cell((5.0, 5.0, 6.0), 2, (10, 10, 12), (2, 2, 1), 3, 20,
@@ -76,45 +103,77 @@ def _oracle(cell, psi, pts, ao):
     return thc.thc_oo_k(cell.L, cell.grid, cell.kmesh, psi, pts, ao, keep_intermediates=("xi",))
 
 
-@pytest.mark.parametrize("name", list(CELLS))
-def test_fp64_stages_match_oracle(name, gpu):
+def _case(name, prec, stages):
     cell = CELLS[name]()
     base = inputs(cell)
     pts, _ = select.select_points(base["psi"], cell.n_isdf)
     ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
     o = _oracle(cell, base["psi"], pts, ao)
-    g = run_gpu(cell, base["psi"], pts, ao, "f64")
-    tol = _tol(o)
-    print(f"{name}: tol {tol:.2e}")
+    g = run_gpu(cell, base["psi"], pts, ao, prec, stages=stages)
+    return cell, base, o, g
+
+
+WELL = ["gamma-config1", "k444", "k211", "k121", "k112", "k221", "k112-odd", "k311", "tiny-k211",
+        "tiny-k222"]
+ILL = ["k222-ragged", "k321", "k333", "k123"]
+
+
+@pytest.mark.parametrize("name", WELL)
+def test_fp64_stages_match_oracle(name, gpu):
+    """Stage-wise calls (exx_isdf_fit, exx_coulomb_V, exx_build_K) in FP64 against
+    the oracle on cells with cond(S^m_RR) <= 1e8."""
+    cell, base, o, g = _case(name, "f64", True)
+    cond, tol = _cond(o), _tol(o)
+    errs = dict(xi=_rel(g["xi"], o["xi"]), V=_rel(g["V"], o["Vb"]), K=_rel(g["K"], o["K"]),
+                E=abs(g["Ex"] - o["Ex"]) / abs(o["Ex"]), S=_rel(g["S"], o["S"]))
+    print(f"{name}: cond {cond:.2e} tol {tol:.2e} " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert cond <= 1e8
+    assert np.array_equal(g["rank"], o["rank"])
+    assert errs["S"] <= 1e-13
+    for k in ("xi", "V", "K", "E"):
+        assert errs[k] <= tol, k
+
+
+@pytest.mark.parametrize("name", ILL)
+def test_fp64_stages_ill_conditioned(name, gpu):
+    """Stage-wise FP64 on cells with cond(S^m_RR) 4e8 .. 2e10: E_x and the occupied
+    block at fixed tolerances, xi, V and K to the conditioning limit."""
+    cell, base, o, g = _case(name, "f64", True)
+    cond = _cond(o)
+    tol = min(1e-5, 4 * EPS64 * cond)
+    errs = dict(xi=_rel(g["xi"], o["xi"]), V=_rel(g["V"], o["Vb"]), K=_rel(g["K"], o["K"]))
+    dE = abs(g["Ex"] - o["Ex"]) / abs(o["Ex"])
+    dO = _rel(_occ_block(g["K"], base["C"]), _occ_block(o["K"], base["C"]))
+    print(f"{name}: cond {cond:.2e} tol {tol:.2e} E {dE:.2e} occ {dO:.2e} " +
+          " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert 1e8 < cond < 1e11
     assert np.array_equal(g["rank"], o["rank"])
     assert _rel(g["S"], o["S"]) <= 1e-13
-    assert _rel(g["xi"], o["xi"]) <= tol
-    assert _rel(g["V"], o["Vb"]) <= tol
-    assert _rel(g["K"], o["K"]) <= tol
-    assert abs(g["Ex"] - o["Ex"]) <= tol * abs(o["Ex"])
+    assert dE <= 1e-8
+    assert dO <= 1e-7
+    for k, v in errs.items():
+        assert v <= tol, k
 
 
 def test_fused_build_matches_stages(gpu):
     """The fused build against the stage-wise calls on a 2x2x2 cell: the fused
     build takes the real path there (every transfer self-conjugate), the stage-wise
-    calls the general complex path; both stay within the parity tolerance of the
-    oracle and of each other, and the ranks agree exactly."""
+    calls the general complex path; E_x agrees to 1e-9 and K to 1e-8 relative, and
+    the ranks exactly."""
     cell = CELLS["k222-ragged"]()
     base = inputs(cell)
     pts, _ = select.select_points(base["psi"], cell.n_isdf)
     ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
-    o = _oracle(cell, base["psi"], pts, ao)
-    tol = _tol(o)
     a = run_gpu(cell, base["psi"], pts, ao, "f64", stages=True)
     b = run_gpu(cell, base["psi"], pts, ao, "f64", stages=False)
     assert np.array_equal(a["rank"], b["rank"])
-    assert _rel(b["K"], a["K"]) <= 2 * tol
-    assert abs(b["Ex"] - a["Ex"]) <= 2 * tol * abs(a["Ex"])
+    assert _rel(b["K"], a["K"]) <= 1e-8
+    assert abs(b["Ex"] - a["Ex"]) <= 1e-9 * abs(a["Ex"])
 
 
-# meshes with every N_i <= 2 (the fused build's real path) and two that are not
+# meshes with every N_i <= 2 (the fused build's real path) and others (paired path)
 FUSED = ["gamma-config1", "k222-ragged", "k211", "k121", "k112", "k221", "k112-odd", "k311",
-         "k321", "k333", "tiny-k211", "tiny-k222"]
+         "k321", "k333", "k444", "k123", "tiny-k211", "tiny-k222"]
 
 
 @pytest.mark.parametrize("name", FUSED)
@@ -122,86 +181,76 @@ def test_fp64_fused_build_matches_oracle(name, gpu):
     """The fused build (exx_build) in FP64 against the oracle: K, E_x and the ranks.
     On meshes with every N_i <= 2 it computes the unphased metric and right-hand
     side as real arrays, solves in real arithmetic and forms the real Bloch-gauge
-    Coulomb matrices from half of the grid transform; elsewhere it runs the same
-    complex path as the stage-wise calls."""
-    cell = CELLS[name]()
-    base = inputs(cell)
-    pts, _ = select.select_points(base["psi"], cell.n_isdf)
-    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
-    o = _oracle(cell, base["psi"], pts, ao)
-    g = run_gpu(cell, base["psi"], pts, ao, "f64", stages=False)
-    tol = _tol(o)
-    print(f"{name}: fused f64 rel dK {_rel(g['K'], o['K']):.2e}, "
-          f"rel dE {abs(g['Ex'] - o['Ex']) / abs(o['Ex']):.2e} (tol {tol:.2e})")
+    Coulomb matrices from half of the grid transform; elsewhere it fits and
+    contracts one transfer of each conjugate pair. Both apply the inverse Cholesky
+    factor to the grid and its adjoint to the Coulomb matrix, which keeps K within
+    1e-8 of the oracle even where cond(S) reaches 2e10."""
+    cell, base, o, g = _case(name, "f64", False)
+    cond, tol = _cond(o), _tol(o)
+    dK = _rel(g["K"], o["K"])
+    dE = abs(g["Ex"] - o["Ex"]) / abs(o["Ex"])
+    print(f"{name}: fused f64 cond {cond:.2e} rel dK {dK:.2e}, rel dE {dE:.2e} (tol {tol:.2e})")
     assert np.array_equal(g["rank"], o["rank"])
-    assert _rel(g["K"], o["K"]) <= tol
-    assert abs(g["Ex"] - o["Ex"]) <= tol * abs(o["Ex"])
+    assert dK <= tol
+    assert dE <= min(tol, 1e-10)
+
+
+def test_fp64_fused_build_singular_metric(gpu):
+    """On the numerically singular 1x2x1 cell (cond 3e17) the fit leaves the AO
+    block of K undetermined, but E_x and the occupied block C^H K C are fixed by
+    the pair space; the fused build reproduces both, and the ranks."""
+    cell, base, o, g = _case("k121-singular", "f64", False)
+    dE = abs(g["Ex"] - o["Ex"]) / abs(o["Ex"])
+    dO = _rel(_occ_block(g["K"], base["C"]), _occ_block(o["K"], base["C"]))
+    print(f"k121-singular: cond {_cond(o):.2e} rel dE {dE:.2e} occ {dO:.2e}")
+    assert _cond(o) > 1e15
+    assert np.array_equal(g["rank"], o["rank"])
+    assert dE <= 1e-10
+    assert dO <= 1e-9
 
 
 @pytest.mark.parametrize("prec", ["mixed", "f32"])
-@pytest.mark.parametrize("name", ["gamma-config1", "k112", "k221", "k112-odd", "k311",
-                                  "tiny-k211", "tiny-k222"])
+@pytest.mark.parametrize("name", FUSED)
 def test_reduced_precision_fused_build(name, prec, gpu):
-    """The fused build in MIXED and F32 on well-conditioned cells (the real path,
-    and the paired complex path on the 3x1x1 mesh), against the oracle, to the
-    bounds of the stage-wise reduced-precision tests."""
-    cell = CELLS[name]()
-    base = inputs(cell)
-    pts, _ = select.select_points(base["psi"], cell.n_isdf)
-    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
-    o = _oracle(cell, base["psi"], pts, ao)
-    g = run_gpu(cell, base["psi"], pts, ao, prec, stages=False)
-    dE = abs(g["Ex"] - o["Ex"])
-    dK = float(np.abs(g["K"] - o["K"]).max())
-    print(f"{name}: fused {prec} |dEx| {dE:.3e} (rel {dE / abs(o['Ex']):.2e}) max|dK| {dK:.3e}")
+    """The fused build in MIXED and F32 against the FP64 oracle (bounds in the
+    module docstring)."""
+    cell, base, o, g = _case(name, prec, False)
+    cond = _cond(o)
+    dE = abs(g["Ex"] - o["Ex"]) / abs(o["Ex"])
+    dK = _rel(g["K"], o["K"])
+    print(f"{name}: fused {prec} cond {cond:.2e} rel dE {dE:.2e} rel dK {dK:.2e} "
+          f"(|dEx| {abs(g['Ex'] - o['Ex']):.2e} Ha, max|dK| {np.abs(g['K'] - o['K']).max():.2e})")
     assert np.array_equal(g["rank"], o["rank"])
     if prec == "mixed":
-        assert dE <= 1e-6 * abs(o["Ex"])
-        assert dK <= 1e-5 * np.abs(o["K"]).max()
+        assert dE <= 3e-7
+        assert dK <= 3e-7
     else:
-        cond_tol = _tol(o) / (64 * EPS64) * 1e-6
-        assert dE <= max(1e-5, cond_tol) * abs(o["Ex"])
-        assert dK <= max(1e-4, cond_tol) * np.abs(o["K"]).max()
+        assert dE <= 1e-6
+        assert dK <= 8 * EPS32 * np.sqrt(cond)
 
 
-@pytest.mark.parametrize("name", ["gamma-config1", "k444", "k112", "k221"])
-def test_mixed_mode_matches_oracle(name, gpu):
-    """EXX_MIXED: FP64 fit, xi stored in FP32, FP32 FFT, Coulomb contraction on the FP64
-    matrix cores from the FP32-stored transforms. The FP32 rounding of xi and F
-    (eps32 relative) bounds the error of V at ~1e-6 relative; E_x and K inherit it. K and E_x come out of sums whose terms grow
-    with the conditioning of S^m, so the cells here are the well-conditioned ones
-    (smallest retained Cholesky pivot >= 1e-5 of the largest diagonal); the
-    accuracy target at the benchmark workload is checked in test_gpu_full.py."""
-    cell = CELLS[name]()
-    base = inputs(cell)
-    pts, _ = select.select_points(base["psi"], cell.n_isdf)
-    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
-    o = _oracle(cell, base["psi"], pts, ao)
-    g = run_gpu(cell, base["psi"], pts, ao, "mixed")
-    dE = abs(g["Ex"] - o["Ex"])
-    dK = float(np.abs(g["K"] - o["K"]).max())
-    print(f"{name}: mixed |dEx| {dE:.3e} (rel {dE / abs(o['Ex']):.2e}) max|dK| {dK:.3e}")
+def test_mixed_fused_build_singular_metric(gpu):
+    """MIXED on the numerically singular cell: E_x and the occupied block."""
+    cell, base, o, g = _case("k121-singular", "mixed", False)
+    dE = abs(g["Ex"] - o["Ex"]) / abs(o["Ex"])
+    dO = _rel(_occ_block(g["K"], base["C"]), _occ_block(o["K"], base["C"]))
+    print(f"k121-singular mixed: rel dE {dE:.2e} occ {dO:.2e}")
+    assert dE <= 3e-7 and dO <= 3e-7
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f32"])
+@pytest.mark.parametrize("name", ["gamma-config1", "k444", "k112", "k221", "k311"])
+def test_reduced_precision_stages(name, prec, gpu):
+    """The stage-wise calls in MIXED and F32 (xi stored in FP32, FP32 FFT, Coulomb
+    contraction on the FP64 matrix cores from FP32-stored transforms) against the
+    oracle on well-conditioned cells."""
+    cell, base, o, g = _case(name, prec, True)
+    dE = abs(g["Ex"] - o["Ex"]) / abs(o["Ex"])
+    dK = _rel(g["K"], o["K"])
+    dV = _rel(g["V"], o["Vb"])
+    print(f"{name}: stages {prec} cond {_cond(o):.2e} rel dE {dE:.2e} dK {dK:.2e} dV {dV:.2e}")
     assert np.array_equal(g["rank"], o["rank"])
-    assert _rel(g["V"], o["Vb"]) <= 1e-5
-    assert dE <= 1e-6 * abs(o["Ex"])
-    assert dK <= 1e-5 * np.abs(o["K"]).max()
-
-
-@pytest.mark.parametrize("name", ["gamma-config1", "k222-ragged", "k333"])
-def test_fp32_mode_error_report(name, gpu):
-    """EXX_F32: Gamma, Z, xi and the FFT in FP32; FP64 solve arithmetic, FP64-core Coulomb
-    contraction, FP64 E_x. Error reported and bounded."""
-    cell = CELLS[name]()
-    base = inputs(cell)
-    pts, _ = select.select_points(base["psi"], cell.n_isdf)
-    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
-    o = _oracle(cell, base["psi"], pts, ao)
-    g = run_gpu(cell, base["psi"], pts, ao, "f32")
-    dE = abs(g["Ex"] - o["Ex"])
-    dK = float(np.abs(g["K"] - o["K"]).max())
-    print(f"{name}: f32 |dEx| {dE:.3e} (rel {dE / abs(o['Ex']):.2e}) max|dK| {dK:.3e}")
-    assert np.array_equal(g["rank"], o["rank"])
-    # FP32 data carries ~1e-7 relative error, amplified at most by cond(S)
-    cond_tol = _tol(o) / (64 * EPS64) * 1e-6
-    assert dE <= max(1e-5, cond_tol) * abs(o["Ex"])
-    assert dK <= max(1e-4, cond_tol) * np.abs(o["K"]).max()
+    if prec == "mixed":
+        assert dV <= 1e-6 and dE <= 1e-6 and dK <= 3e-6
+    else:
+        assert dV <= 1e-4 and dE <= 1e-6 and dK <= 8 * EPS32 * np.sqrt(_cond(o))
