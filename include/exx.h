@@ -217,6 +217,25 @@ exx_status exx_build_K(exx_handle_t h, const exx_cell* cell, exx_prec prec,
                        void* K, double* Ex, hipStream_t stream);
 
 /*
+ * exx_build_K_noalloc -- exx_build_K for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, results and checks as exx_build_K; it
+ * calls no hipMalloc, hipFree or allocating library routine. Its scratch
+ * (G^n, Y^n, the contraction intermediates) lives in a fixed device array of
+ * EXX_NOALLOC_MAX_BYTES per GPU, reserved when the library's code is loaded on
+ * that GPU and held until the process ends; its address is looked up in
+ * exx_create. A cell needing more, 2 N_k N_ISDF^2 + 2 N_k N_ISDF n_ao complex128
+ * values plus 8 KiB (the second N_k N_ISDF n_ao term only when n_ao <= N_ISDF),
+ * returns EXX_ERR_SHAPE before any launch. Every call on a GPU shares that GPU's
+ * array, whatever its handle: calls that overlap in time on one GPU (two
+ * streams, two host threads) race and must be ordered by the caller.
+ */
+#define EXX_NOALLOC_MAX_BYTES (256u << 20)
+exx_status exx_build_K_noalloc(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                               const void* ao_pts, const void* occ_pts, const void* V, void* K,
+                               double* Ex, hipStream_t stream);
+
+/*
  * exx_build -- one whole K-build (Algorithm 2: fit, Coulomb matrices, K and
  * E_x) with the results of exx_isdf_fit, exx_coulomb_V and exx_build_K called
  * in turn, to rounding; xi, S and V stay in the handle's scratch. It reaches

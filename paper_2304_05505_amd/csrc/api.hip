@@ -5,11 +5,43 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <optional>
 #include <type_traits>
 
 #include "common.h"
+
+// Scratch of the allocation-free exchange contraction (exx_build_K_noalloc):
+// one copy per GPU, placed by the loader with the code object and held until
+// the process ends. Host code never uses this name as an address; it uses the
+// device address from hipGetSymbolAddress, kept per device in noalloc_ptr.
+static __device__ __align__(256) char scratch[EXX_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+char* noalloc_ptr[MAX_DEVICES] = {};
+
+// With `device` current: the device address of its copy of `scratch`, looked
+// up once per device.
+hipError_t noalloc_setup(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (noalloc_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  noalloc_ptr[device] = (char*)p;
+  return hipSuccess;
+}
+
+char* noalloc_base(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  return noalloc_ptr[device];
+}
+}  // namespace
 
 namespace exx {
 
@@ -849,6 +881,7 @@ exx_status exx_create(exx_handle_t* h, int device) {
   c->device = device;
   // the device status word, cleared once here and after every exx_get_status
   hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = noalloc_setup(device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->dstat, 4 * sizeof(int32_t));
   if (e == hipSuccess) e = launch_status_reset(c->dstat, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -1046,6 +1079,46 @@ exx_status exx_get_status(exx_handle_t h, hipStream_t stream, int32_t* info) {
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
   return read_status(h, stream, info);
+}
+
+exx_status exx_build_K_noalloc(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                               const void* ao_pts, const void* occ_pts, const void* V, void* K,
+                               double* Ex, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!ao_pts || !occ_pts || !V || !K || !Ex)
+    return fail(h, EXX_ERR_ARG, "exx_build_K_noalloc: null array argument");
+  exx_status s = check_cell(h, cell, prec);
+  if (s != EXX_OK) return s;
+  if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
+  const Geom g = make_geom(*cell);
+  // G, Y [N_k][N_ISDF][N_ISDF], T [N_k][N_ISDF][n_ao], A^H (n_ao <= N_ISDF), partial sums
+  const size_t mat = al(sizeof(double2) * (size_t)g.nk * g.ni * g.ni);
+  const size_t tb = al(sizeof(double2) * (size_t)g.nk * g.ni * g.nao);
+  const size_t need = 2 * mat + tb + (g.nao <= g.ni ? tb : 0) + al(sizeof(double) * 1024);
+  if (need > (size_t)EXX_NOALLOC_MAX_BYTES)
+    return fail(h, EXX_ERR_SHAPE, "exx_build_K_noalloc: this cell needs " + std::to_string(need) +
+                                      " bytes of scratch; the allocation-free scratch holds " +
+                                      std::to_string((size_t)EXX_NOALLOC_MAX_BYTES));
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  char* base = noalloc_base(h->device);
+  if (!base) return fail(h, EXX_ERR_DEVICE, "exx_build_K_noalloc: scratch address not set up");
+  KScratch ks;
+  ks.G = (double2*)base;
+  ks.Y = (double2*)(base + mat);
+  ks.T = (double2*)(base + 2 * mat);
+  ks.AH = g.nao <= g.ni ? (double2*)(base + 2 * mat + tb) : nullptr;
+  ks.epart = (double*)(base + 2 * mat + tb + (g.nao <= g.ni ? tb : 0));
+  // no phase events here: taking one may create it
+  const bool timing = h->timing;
+  h->timing = false;
+  s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
+  if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
+  if (s == EXX_OK) s = scan(h, V, 2L * g.nk * g.ni * g.ni, SITE_COULOMB, stream);
+  if (s == EXX_OK) s = buildK_impl(h, g, ks, ao_pts, occ_pts, V, K, Ex, stream);
+  h->timing = timing;
+  return s == EXX_OK ? finish(h, stream) : s;
 }
 
 exx_status exx_set_refinement(exx_handle_t h, int32_t steps) {

@@ -55,6 +55,7 @@ EXPORTED = (
     "exx_set_workspace",
     "exx_set_checks",
     "exx_get_status",
+    "exx_build_K_noalloc",
 )
 
 EXX_BATCH_GRAPH, EXX_BATCH_TUNE = 1, 2
@@ -140,6 +141,7 @@ def _load():
         "exx_set_workspace": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "exx_set_checks": ([vp, ctypes.c_int32], ctypes.c_int),
         "exx_get_status": ([vp, vp, i32p], ctypes.c_int),
+        "exx_build_K_noalloc": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -319,6 +321,20 @@ def exx_build_K(h: Handle, cell: ExxCell, prec: int, ao_pts, occ_pts, V, K, Ex):
         _ptr(Ex, "Ex", torch.float64, (1,), d),
     )
     h._check(_lib.exx_build_K(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
+
+
+def exx_build_K_noalloc(h: Handle, cell: ExxCell, prec: int, ao_pts, occ_pts, V, K, Ex):
+    """exx_build_K on the library's fixed per-GPU scratch (no device allocation)."""
+    nk, ni, no, na = _nk(cell), cell.n_isdf, cell.n_occ, cell.n_ao
+    d = h.device
+    args = (
+        _ptr(ao_pts, "ao_pts", torch.complex128, (nk, ni, na), d),
+        _ptr(occ_pts, "occ_pts", torch.complex128, (nk, ni, no), d),
+        _ptr(V, "V", torch.complex128, (nk, ni, ni), d),
+        _ptr(K, "K", torch.complex128, (nk, na, na), d),
+        _ptr(Ex, "Ex", torch.float64, (1,), d),
+    )
+    h._check(_lib.exx_build_K_noalloc(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
 
 
 def exx_build(h: Handle, cell: ExxCell, prec: int, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank):
