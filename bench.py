@@ -1,23 +1,26 @@
 """Throughput of the THC-oo-K exchange build (K^k for all k plus E_x) on one GPU.
 
-Workload: the 48-atom four-ring cell (14.0 x 17.8 x 12.9 bohr, C6H6 x 4) on a
-2x2x2 Gamma-centred k-mesh; s + p Gaussians per atom (N = 192), n_occ = 84,
-grid 60x75x54 (N_g = 243000), N_ISDF = 420 points chosen on the GPU by
-pivoted-Cholesky QRCP. Seeded synthetic orbitals; inputs are resident in HBM
-before the timed region. One step = one whole K-build (fit, Coulomb
-matrices, contraction) through the C ABI.
+Default workload (the metric's configuration): the 24-cell batch, 2 x {8, 16,
+24, 48 atoms} x {1^3, 2^3, 3^3} k-meshes, 4 Gaussian functions per atom
+(N = 32 .. 192), n_occ = 0.44 N, N_ISDF = 2.2 N, grids at 4.5 points/bohr.
+One step = the whole batch of K-builds through one exx_build_batched call
+(one captured HIP graph, autotuned tiles) in the mixed precision mode (FP64
+fit, FP32 storage of the fitted functions and transforms, FP64 Cholesky,
+solve arithmetic, Coulomb accumulation, contraction and E_x). It is compared
+with 24 sequential plain-FP64 builds of the same cells, and every cell's E_x
+and K are checked against the stored FP64 oracle values (tests/golden/
+config4.json, written by the oracle alone) at |dE_x| <= 1e-5 Ha/cell and
+max|dK| <= 1e-6. Inputs are seeded, synthetic and resident in HBM before the
+timed region.
 
-Three precision paths are timed: f64 (everything FP64), mixed (FP64 fit,
-FP32 FFT and Coulomb contraction with FP64 accumulation) and f32 (bulk FP32).
-`value` is the fastest path whose E_x and K stay within 1e-5 Ha/cell and
-1e-6 of the FP64 result (the FP64 path itself matches the FP64 oracle to
-~1e-12; with --prec the reported path is forced).
+`value` = 24 / (seconds per batched step). `paths` also carries the batch in
+F32 and F64 and the single-cell builds of the 48-atom four-ring cell on the
+2x2x2 and 3x3x3 meshes (N = 192, n_occ = 84, grid 60x75x54, N_ISDF = 420) in
+every precision, each against its stored oracle K and E_x.
 
-Prints one JSON line. Options: --steps K --warmup W --gpus N (N must be 1)
---prec auto|f64|mixed|f32 --no-cpu --profile; --workload select-k4 instead times
-the learned and the QRCP point selection at the 4x4x4 ring workload, each
-followed by one FP32 K-build; --workload batch24 times the 24-cell batched
-build (one graph launch) against 24 sequential FP64 builds.
+Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --profile
+(one batch per precision, one 3x3x3 build per precision and a 1 GiB copy, no
+JSON); --workload rings-k2 | rings-k3 | select-k4 print a single leg.
 """
 
 from __future__ import annotations
@@ -25,6 +28,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -32,165 +36,402 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 METRIC = "K-builds/sec (all k) vs plain FP64 GPU at |ΔE_x|≤1e-5 Ha/cell; MFMA %"
-PEAK = {  # MI355X published dense peaks
-    "hbm_GBs": 8000.0,
-    "fp64_TF": 78.6,
-    "fp32_TF": 157.3,
-}
+PEAK = {"hbm_GBs": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3}  # MI355X published dense peaks
+GATE_E, GATE_K = 1e-5, 1e-6
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------------------
+# algorithmic work
+# ---------------------------------------------------------------------------
+def n_pairs(kmesh):
+    """Transfers m with m <= -m on the mesh (one per conjugate pair)."""
+    N = kmesh
+    cnt = 0
+    for m in range(N[0] * N[1] * N[2]):
+        m1, m2, m3 = m // (N[1] * N[2]), (m // N[2]) % N[1], m % N[2]
+        b = (((N[0] - m1) % N[0]) * N[1] + (N[1] - m2) % N[1]) * N[2] + (N[2] - m3) % N[2]
+        cnt += m <= b
+    return cnt
+
+
 def real_path(cell):
-    """The fused build's real path runs on meshes whose every axis has N_i <= 2."""
     return all(n <= 2 for n in cell.kmesh)
 
 
-def algorithmic_work(cell, n_isdf, prec):
-    """Per-launch algorithmic flops / bytes of each phase (one K-build).
+def work(cell, prec):
+    """Per-build work of each phase: {phase: (unit, executed, survey)}.
 
-    Flops count the real multiply-adds of the product form each kernel uses:
-    complex products on the FP64 matrix cores use Gauss's three-product form, 6
-    flops per complex multiply-add; the FP32-matrix-core Gamma of the FP32 path
-    and the small K GEMMs use four real products, 8 flops. The Coulomb
-    contraction forms the lower triangle only (N_ISDF^2/2 pairs).
-    On the real path (every k-mesh axis <= 2) the solve is a real GEMM (2 flops
-    per multiply-add), Z~ and eta are real arrays, the FFT writes the kept half
-    grid of n1 n2 (n3/2 + 1) points and the Coulomb contraction takes
-    Re(X conj Y) (two real products, 4 flops) over that half grid; in FP32 the
-    Gamma GEMM and the k-correlation are one kernel (phase "gamma"). There the
-    solve multiplies by the triangular inverse Cholesky factor and counts its
-    N_I (N_I + 1) / 2 multiply-adds per grid point (the kernel rounds each
-    16-row block up to the diagonal).
+    `executed` counts what the kernels do after the method's exact identities:
+    on meshes with every N_i <= 2 the unphased metric and right-hand side are
+    real (real solve by the triangular inverse factor, N_ISDF (N_ISDF + 1)/2
+    multiply-adds per grid point; half-grid transform; real Coulomb sum over
+    n1 n2 (n3/2 + 1) points, lower triangle); elsewhere one transfer of each
+    pair (m, -m) is fitted, transformed and contracted (complex, Gauss's
+    three-product form on the FP64 matrix cores: 6 flops per complex
+    multiply-add; triangular solve; lower triangle of V). `survey` counts the
+    plain method: Gamma 8 N_k N_I n_o N_g, solve 8 N_k N_I^2 N_g, Coulomb
+    (Hermitian) 4 N_k N_I^2 N_g, one read and one write of the N_k N_I N_g
+    intermediate for the k-correlation and the transform.
     """
-    nk, ng, no, na = cell.N_k, cell.N_g, cell.n_occ, cell.n_ao
-    ni = n_isdf
-    cs = 16 if prec == "f64" else 8           # complex Gamma/Z (f64, mixed: Gamma c128)
-    cg = 8.0 if prec == "f32" else 6.0        # flops per complex multiply-add of the Gamma GEMM
-    work = {"gamma": ("flop", cg * nk * ni * no * ng),
-            "K": ("flop", 8.0 * nk * (na * ni * ni + na * na * ni))}
+    nk, ng, no, na, ni = cell.N_k, cell.N_g, cell.n_occ, cell.n_ao, cell.n_isdf
+    cs = 16 if prec in ("f64", "mixed") else 8   # Gamma / Z element (complex)
+    cx = 16 if prec == "f64" else 8              # xi / transform element (complex)
+    sv = {
+        "gamma": ("flop", 8.0 * nk * ni * no * ng),
+        "kcorr": ("byte", 2.0 * nk * ni * ng * cs),
+        "solve": ("flop", 8.0 * nk * ni * ni * ng),
+        "fft": ("byte", 2.0 * nk * ni * ng * cx),
+        "coulomb": ("flop", 4.0 * nk * ni * ni * ng),
+        "K": ("flop", 8.0 * nk * (na * ni * ni + na * na * ni)),
+    }
+    cg = 8.0 if prec == "f32" else 6.0
+    ex = {"gamma": cg * nk * ni * no * ng, "K": 8.0 * nk * (na * ni * ni + na * na * ni)}
     if real_path(cell):
         n1, n2, n3 = cell.grid
-        if prec == "f32":
-            # FP32: one fused kernel forms Gamma^n (four real products) and Z~;
-            # its time is reported under "gamma" and counts the GEMM flops
-            work["gamma"] = ("flop", 8.0 * nk * ni * no * ng)
         ngh = n1 * n2 * (n3 // 2 + 1)
-        gam = 8 if prec == "f32" else 16      # Gamma element (complex)
-        zr = 4 if prec == "f32" else 8        # Z~ element (real)
-        xr = 8 if prec == "f64" else 4        # eta element (real)
-        xc = 16 if prec == "f64" else 8       # transform element (complex)
-        work.update({
-            "kcorr": ("byte", nk * ni * ng * (gam + zr)),
-            # the lower-triangular inverse factor W (S~^+ = W^T W): N_I (N_I + 1) / 2
-            # multiply-adds per grid point
-            "solve": ("flop", 1.0 * ni * (ni + 1) * nk * ng),
-            "fft": ("byte", nk * ni * (ng * xr + ngh * xc)),
-            "coulomb": ("flop", 2.0 * nk * ni * ni * ngh),
+        gam = 8 if prec == "f32" else 16
+        zr = 4 if prec == "f32" else 8
+        xr = 8 if prec == "f64" else 4
+        xc = 16 if prec == "f64" else 8
+        ex.update({
+            "kcorr": nk * ni * ng * (gam + zr),
+            "solve": 1.0 * ni * (ni + 1) * nk * ng,
+            "fft": nk * ni * (ng * xr + ngh * xc),
+            "coulomb": 2.0 * nk * ni * ni * ngh,
         })
+        if prec == "f32":
+            ex["gamma"] = 8.0 * nk * ni * no * ng  # Gamma and Z~ in one FP32-core kernel
     else:
-        work.update({
-            "kcorr": ("byte", 2.0 * nk * ni * ng * cs),
-            "solve": ("flop", 6.0 * nk * ni * ni * ng),
-            "fft": ("byte", 2.0 * nk * ni * ng * cs),
-            "coulomb": ("flop", 3.0 * nk * ni * ni * ng),
+        npr = n_pairs(cell.kmesh)
+        ex.update({
+            "kcorr": (nk + npr) * ni * ng * cs,
+            "solve": 3.0 * npr * ni * (ni + 1) * ng,
+            "fft": 2.0 * npr * ni * ng * cx,
+            "coulomb": 3.0 * npr * ni * (ni + 1) * ng,
         })
-    return work
+    return {p: (sv[p][0], ex[p], sv[p][1]) for p in sv}
 
 
-# HBM traffic of the dominant kernel of each phase at this workload, from two
-# rocprofv3 counter runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; KiB
-# per dispatch; the FP64 transform and contraction run in four chunks of transfers,
-# so their entries cover a quarter of the build). A plain 1 GiB device copy reads
-# 524 312 KiB of FETCH_SIZE and 1 048 576 KiB of WRITE_SIZE on MI355X, so fetch
-# counts are scaled by 2.0 and write counts by 1.0. Each entry names the source file of its kernels and that file's
-# SHA-256 prefix when the counters were taken; a changed file reports null.
-FETCH_SCALE, WRITE_SCALE = 1048576.0 / 524312.2, 1.0
-TRAFFIC = {
-    # (phase, path): (source, sha256[:16], FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("solve", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 8087716.2, 6469594.8),
-    ("solve", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 7483829.7, 3303541.6),
-    ("solve", "f32"): ("gemm_mfma.hip", "b285ff3ab7358f19", 3051883.4, 3263706.8),
-    ("gamma", "f64"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299417.4, 12757500.0),
-    ("gamma", "mixed"): ("gemm_mfma.hip", "b285ff3ab7358f19", 1299417.4, 12757500.0),
-    ("gamma", "f32"): ("fit.hip", "fa8c9af02b7f561a", 1355649.1, 4503349.7),
-    ("kcorr", "f64"): ("fit.hip", "fa8c9af02b7f561a", 6378788.6, 6378750.0),
-    ("kcorr", "mixed"): ("fit.hip", "fa8c9af02b7f561a", 6378788.6, 6378750.0),
-    ("fft", "f64"): ("fft.hip", "05376b4f2156bb5c", 1835594.0, 3307500.8),
-    ("fft", "mixed"): ("fft.hip", "05376b4f2156bb5c", 3884780.6, 6615000.5),
-    ("fft", "f32"): ("fft.hip", "05376b4f2156bb5c", 3884780.6, 6615000.5),
-    ("coulomb", "f64"): ("coulomb.hip", "e5d3729797beb400", 4980022.1, 210761.8),
-    ("coulomb", "mixed"): ("coulomb.hip", "e5d3729797beb400", 8965173.4, 206327.3),
-    ("coulomb", "f32"): ("coulomb.hip", "e5d3729797beb400", 8965173.4, 206327.3),
+FP64_CORES = {"f64": {"gamma", "solve", "coulomb", "K"}, "mixed": {"gamma", "solve", "coulomb", "K"},
+              "f32": {"solve", "coulomb", "K"}}
+
+KERNELS = {  # dominant kernel(s) of each phase, real path / paired path
+    "gamma": ("zgemm_nn_mfma (FP64) or gamma_kcorr_kernel (F32)", "zgemm_nn_mfma / cgemm FP32 cores"),
+    "solve": ("dgemm_nn_mfma (triangular W)", "zgemm_nn_mfma (triangular W)"),
+    "coulomb": ("coulomb_kernel_t64", "coulomb_kernel_f64 / coulomb_kernel_f32"),
+    "fft": ("fft_yz_half2_kernel + fft_x", "fft_yz + fft_x"),
+    "kcorr": ("kcorr_real_kernel", "kcorr_kernel"),
 }
 
 
-def traffic_bytes(phase, path):
-    """HBM bytes per launch of the phase's kernel, or None if unmeasured or changed."""
-    import hashlib
+def roofline(phase_ms, work_exec, work_survey, units, prec):
+    """Roofline of the phase with the largest summed time. phase_ms: {phase: ms};
+    work_*: {phase: amount} summed over the same builds."""
+    best = max((p for p in phase_ms if p in work_exec and phase_ms[p] > 0), key=lambda p: phase_ms[p])
+    s = phase_ms[best] / 1e3
+    unit = units[best]
+    if unit == "byte":
+        a, a_sv = work_exec[best] / s / 1e9, work_survey[best] / s / 1e9
+        out = {"bound": "hbm", "achieved": a, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+               "frac": a / PEAK["hbm_GBs"]}
+    else:
+        a, a_sv = work_exec[best] / s / 1e12, work_survey[best] / s / 1e12
+        peak = PEAK["fp64_TF"] if best in FP64_CORES[prec] else PEAK["fp32_TF"]
+        out = {"bound": "mfma", "achieved": a, "peak": peak, "unit": "TFLOP/s", "frac": a / peak}
+    out.update({"traffic": None, "phase": best, "phase_ms": phase_ms[best],
+                "work_executed": work_exec[best], "work_survey": work_survey[best],
+                "achieved_survey_count": a_sv})
+    return out
 
-    ent = TRAFFIC.get((phase, path))
-    if ent is None:
+
+# ---------------------------------------------------------------------------
+# stored oracle values
+# ---------------------------------------------------------------------------
+def load_json(name):
+    p = os.path.join(GOLDEN, name)
+    return json.load(open(p)) if os.path.exists(p) else None
+
+
+def load_npz(name):
+    p = os.path.join(GOLDEN, name)
+    if not os.path.exists(p):
         return None
-    src, digest, fetch_kib, write_kib = ent
-    fn = os.path.join(ROOT, "paper_2304_05505_amd", "csrc", src)
+    with np.load(p, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def cpu_info():
+    model = "unknown"
     try:
-        cur = hashlib.sha256(open(fn, "rb").read()).hexdigest()[:16]
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
     except OSError:
-        return None
-    if cur != digest:
-        return None
-    return 1024.0 * (fetch_kib * FETCH_SCALE + write_kib * WRITE_SCALE)
+        pass
+    return model or platform.processor()
 
 
-FP64_PHASES = {"f64": {"gamma", "solve", "coulomb", "K"},
-               "mixed": {"gamma", "solve", "coulomb", "K"},
-               "f32": {"solve", "coulomb", "K"}}
+# ---------------------------------------------------------------------------
+# inputs
+# ---------------------------------------------------------------------------
+def cell_inputs(h, exx, torch, cell, dev, pts=None):
+    """Orbitals on the grid (generated on the GPU), points (given, else GPU QRCP),
+    orbital and basis values at the points; all resident on the device."""
+    import synth
+    from synth.fast import orbitals_on_grid_torch
 
-
-def roofline(phases, work, prec, steps):
-    """Roofline entry for the phase with the largest time."""
-    best = max((p for p in phases if p in work), key=lambda p: phases[p][0])
-    ms, calls = phases[best]
-    avg_s = ms / steps / 1e3  # per build (a phase may run as several launches per build)
-    kind, amount = work[best]
-    traffic = traffic_bytes(best, prec)
-    if kind == "byte":
-        achieved = amount / avg_s / 1e9
-        return best, {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-                      "frac": achieved / PEAK["hbm_GBs"], "traffic": traffic}
-    achieved = amount / avg_s / 1e12
-    peak = PEAK["fp64_TF"] if best in FP64_PHASES[prec] else PEAK["fp32_TF"]
-    return best, {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                  "frac": achieved / peak, "traffic": traffic}
-
-
-def cpu_baseline(cell, psi, pts, ao):
-    """The FP64 oracle on a bounded sample: all Gamma^n plus the fit/FFT/Coulomb of two q."""
-    from oracle import thc
-    from oracle._threads import WORKERS
-
-    t0 = time.perf_counter()
-    o = thc.thc_oo_k(cell.L, cell.grid, cell.kmesh, psi, pts, ao,
-                     m_subset=[cell.N_k - 1, cell.N_k // 2])
-    wall = time.perf_counter() - t0
-    sec = o["seconds"]
-    est = sec["gamma"] + cell.N_k * float(np.mean(sec["per_q"])) + sec["contract"]
+    psi = orbitals_on_grid_torch(cell, synth.orbital_coeffs(cell), dev)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, cell.n_isdf)
+    if pts is None:
+        pts_t = torch.empty((cell.n_isdf,), dtype=torch.int32, device=dev)
+        npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+        exx.exx_select_points(h, c, psi, pts_t, npiv)
+        pts = pts_t.cpu().numpy().astype(np.int64)
+    else:
+        pts = np.asarray(pts, dtype=np.int64)
+        pts_t = torch.from_numpy(pts.astype(np.int32)).to(dev)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
     return {
-        "value": 1.0 / est,
-        "unit": "K-builds/s",
-        "cores": WORKERS,
-        "kind": "oracle",
-        "sample": (f"oracle Gamma^n for all {cell.N_k} k plus steps 2-6 for two of {cell.N_k} "
-                   f"transfers ({wall:.1f} s wall); build time extrapolated as "
-                   f"gamma + N_k * per_q + contract = {est:.1f} s"),
+        "cell": c,
+        "psi64": psi,
+        "occ_pts": psi[:, :, pts_t.long()].permute(0, 2, 1).contiguous(),
+        "ao_pts": torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+        "pts": pts_t,
+        "pts_np": pts,
     }
 
 
+def outputs(torch, cell, dev):
+    return {"K": torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128, device=dev),
+            "Ex": torch.empty((1,), dtype=torch.float64, device=dev),
+            "rank": torch.empty((cell.N_k,), dtype=torch.int32, device=dev)}
+
+
+def psi_for(t, prec, torch):
+    if prec == "f32":
+        if "psi32" not in t:
+            t["psi32"] = t["psi64"].to(torch.complex64)
+        return t["psi32"]
+    return t["psi64"]
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+# ---------------------------------------------------------------------------
+# single-cell legs (the 48-atom ring cell on 2x2x2 and 3x3x3)
+# ---------------------------------------------------------------------------
+def ring_leg(config, args, h, exx, torch, dev):
+    import synth
+
+    cell = synth.make_config(config)
+    tag = f"rings-k{cell.kmesh[0]}"
+    gold = load_json(f"config{config}.json")
+    goldK = load_npz(f"config{config}_K.npz")
+    t0 = time.perf_counter()
+    t = cell_inputs(h, exx, torch, cell, dev, pts=gold["pts"] if gold else None)
+    torch.cuda.synchronize()
+    log(f"[{tag}] inputs in {time.perf_counter() - t0:.1f} s")
+    res = {}
+    for prec in ("f64", "mixed", "f32"):
+        o = outputs(torch, cell, dev)
+
+        def step():
+            exx.exx_build(h, t["cell"], exx.PREC[prec], psi_for(t, prec, torch), t["occ_pts"],
+                          t["ao_pts"], t["pts"], o["K"], o["Ex"], o["rank"])
+
+        s = time_steps(step, max(1, args.steps), max(1, args.warmup), torch)
+        h.set_timing(True)
+        step()
+        torch.cuda.synchronize()
+        ph = {k: v[0] for k, v in h.phase_times().items()}
+        h.set_timing(False)
+        r = {"ms_per_build": s * 1e3, "builds_per_s": 1.0 / s, "Ex": float(o["Ex"].cpu()[0]),
+             "phases_ms": ph}
+        if gold is not None and goldK is not None and "K" in goldK:
+            K = o["K"].cpu().numpy()
+            r["dEx_vs_oracle"] = abs(r["Ex"] - gold["Ex"])
+            r["maxdK_vs_oracle"] = float(np.abs(K - goldK["K"]).max())
+            r["meets_gate"] = bool(r["dEx_vs_oracle"] <= GATE_E and r["maxdK_vs_oracle"] <= GATE_K)
+        res[prec] = r
+        log(f"[{tag}] {prec}: {s * 1e3:.2f} ms/build, E_x {r['Ex']:.10f}" +
+            (f", |dEx| {r['dEx_vs_oracle']:.2e}, max|dK| {r['maxdK_vs_oracle']:.2e}"
+             if "dEx_vs_oracle" in r else ""))
+    for prec in ("mixed", "f32"):
+        res[prec]["speedup_vs_f64"] = res["f64"]["ms_per_build"] / res[prec]["ms_per_build"]
+    return {"workload": f"48-atom four-ring cell, {'x'.join(map(str, cell.kmesh))} k-mesh, N=192, "
+                        f"n_occ=84, grid 60x75x54, N_ISDF=420", "paths": res}
+
+
+# ---------------------------------------------------------------------------
+# the 24-cell batch
+# ---------------------------------------------------------------------------
+def batch_errors(items, gold, goldK):
+    """Per-cell |dE_x| and max|dK| (stored oracle entries and diagonals)."""
+    dE, dK = [], []
+    for i, it in enumerate(items):
+        g = gold["cells"][i]
+        K = it["K"].cpu().numpy()
+        idx = goldK[f"idx_{i}"]
+        d1 = np.abs(K[idx[:, 0], idx[:, 1], idx[:, 2]] - goldK[f"val_{i}"]).max()
+        diag = np.stack([np.diagonal(K[n]) for n in range(K.shape[0])])
+        d2 = np.abs(diag - goldK[f"diag_{i}"]).max()
+        dE.append(abs(float(it["Ex"].cpu()[0]) - g["Ex"]))
+        dK.append(float(max(d1, d2)))
+    return dE, dK
+
+
+def batch_leg(args, h, exx, torch, dev):
+    import synth
+
+    cells = synth.make_batch_cells()
+    gold = load_json("config4.json")
+    goldK = load_npz("config4_K.npz")
+    if gold is not None and [g["name"] for g in gold["cells"]] != [c.name for c in cells]:
+        gold = goldK = None
+    t0 = time.perf_counter()
+    base = [cell_inputs(h, exx, torch, c, dev, pts=gold["cells"][i]["pts"] if gold else None)
+            for i, c in enumerate(cells)]
+    torch.cuda.synchronize()
+    log(f"[batch24] inputs for 24 cells in {time.perf_counter() - t0:.1f} s "
+        f"({'oracle' if gold else 'GPU QRCP'} points)")
+
+    def items(prec):
+        out = []
+        for c, t in zip(cells, base):
+            out.append(dict(cell=t["cell"], psi_grid=psi_for(t, prec, torch), occ_pts=t["occ_pts"],
+                            ao_pts=t["ao_pts"], pts=t["pts"], **outputs(torch, c, dev)))
+        return out
+
+    seq = items("f64")
+
+    def sequential_f64():
+        for it in seq:
+            exx.exx_build(h, it["cell"], exx.EXX_F64, it["psi_grid"], it["occ_pts"], it["ao_pts"],
+                          it["pts"], it["K"], it["Ex"], it["rank"])
+
+    stream = torch.cuda.Stream()
+    flags = exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_TUNE
+
+    def batched(prec, its):
+        def fn():
+            stream.wait_stream(torch.cuda.current_stream())
+            exx.exx_build_batched(h, its, exx.PREC[prec], flags, stream=stream)
+            torch.cuda.current_stream().wait_stream(stream)
+        return fn
+
+    steps, warmup = max(1, args.steps), max(1, args.warmup)
+    res = {}
+    s_seq = time_steps(sequential_f64, steps, warmup, torch)
+    log(f"[batch24] 24 sequential plain-FP64 builds: {s_seq * 1e3:.1f} ms")
+    seq_err = batch_errors(seq, gold, goldK) if gold else None
+    its_by_prec = {}
+    for prec in ("mixed", "f32", "f64"):
+        its = items(prec)
+        its_by_prec[prec] = its
+        s = time_steps(batched(prec, its), steps if prec == "mixed" else max(1, steps // 2),
+                       warmup, torch)
+        r = {"seconds": s, "builds_per_s": 24.0 / s, "speedup_vs_sequential_f64": s_seq / s}
+        if gold:
+            dE, dK = batch_errors(its, gold, goldK)
+            r.update({"max_dEx_vs_oracle": max(dE), "max_dK_vs_oracle": max(dK),
+                      "cells_meeting_gate": int(sum(e <= GATE_E and k <= GATE_K
+                                                    for e, k in zip(dE, dK))),
+                      "dEx_per_cell": dE, "dK_per_cell": dK})
+        res[prec] = r
+        log(f"[batch24] batched {prec}: {s * 1e3:.1f} ms ({s_seq / s:.2f}x sequential FP64)" +
+            (f", max|dEx| {r['max_dEx_vs_oracle']:.2e}, max|dK| {r['max_dK_vs_oracle']:.2e}, "
+             f"{r['cells_meeting_gate']}/24 cells in the gate" if gold else ""))
+    seq_r = {"seconds": s_seq, "builds_per_s": 24.0 / s_seq}
+    if seq_err:
+        seq_r.update({"max_dEx_vs_oracle": max(seq_err[0]), "max_dK_vs_oracle": max(seq_err[1])})
+
+    # per-phase event times of every cell's build (one untimed pass, same kernels
+    # and shapes as the batch) and the matching work counts
+    phase_ms, wex, wsv, units = {}, {}, {}, {}
+    its = its_by_prec["mixed"]
+    h.set_timing(True)
+    for c, it in zip(cells, its):
+        exx.exx_build(h, it["cell"], exx.EXX_MIXED, it["psi_grid"], it["occ_pts"], it["ao_pts"],
+                      it["pts"], it["K"], it["Ex"], it["rank"])
+        torch.cuda.synchronize()
+        for p, (ms, _) in h.phase_times().items():
+            phase_ms[p] = phase_ms.get(p, 0.0) + ms
+        for p, (u, a, b) in work(c, "mixed").items():
+            wex[p] = wex.get(p, 0.0) + a
+            wsv[p] = wsv.get(p, 0.0) + b
+            units[p] = u
+    h.set_timing(False)
+    return cells, res, seq_r, phase_ms, wex, wsv, units
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle baseline
+# ---------------------------------------------------------------------------
+CPU_SAMPLE = ("batch0-a8-k1", "batch1-a8-k2", "batch3-a16-k1")
+
+
+def cpu_baseline(cells):
+    """Complete FP64 oracle K-builds (same steps as the GPU build) of three small
+    cells of the batch, median of three passes; scaled to the batch by the plain
+    method's work (Gamma + solve + Coulomb flops of the survey count)."""
+    import synth
+    from oracle import select, thc
+    from oracle._threads import WORKERS
+
+    sample = [c for c in cells if c.name in CPU_SAMPLE]
+    prepared = []
+    for c in sample:
+        psi = synth.orbitals_on_grid(c, synth.orbital_coeffs(c))
+        pts, _ = select.select_points(psi, c.n_isdf)
+        ao = np.stack([synth.ao_at_points(c, n, pts) for n in range(c.N_k)])
+        prepared.append((c, psi, pts, ao))
+    passes = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        for c, psi, pts, ao in prepared:
+            thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao)
+        passes.append(time.perf_counter() - t0)
+    med = float(np.median(passes))
+
+    def w(c):
+        sv = work(c, "f64")
+        return sv["gamma"][2] + sv["solve"][2] + sv["coulomb"][2]
+
+    scale = sum(w(c) for c in cells) / sum(w(c) for c, *_ in prepared)
+    return {
+        "value": 24.0 / (med * scale),
+        "unit": "K-builds/s",
+        "cores": WORKERS,
+        "kind": "oracle",
+        "cpu_model": cpu_info(),
+        "sample": (f"complete oracle K-builds of {', '.join(c.name for c, *_ in prepared)} "
+                   f"(median of 3 passes: {med:.2f} s for the {len(prepared)} cells, "
+                   f"{len(prepared) / med:.3f} builds/s); scaled to the 24-cell batch by the "
+                   f"plain method's flops (x{scale:.0f})"),
+        "sample_seconds": passes,
+    }
+
+
+# ---------------------------------------------------------------------------
+# learned selection leg (unchanged workload)
+# ---------------------------------------------------------------------------
 def bench_select5(args):
     """Learned vs QRCP point selection at the 4x4x4 ring workload (2s + 2p basis,
     N 384, n_occ 84, grid 72x90x64, N_ISDF 420), each followed by the FP32 K-build
@@ -285,102 +526,45 @@ def bench_select5(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_batch24(args):
-    """The 24-cell batch (2 x {8, 16, 24, 48 atoms} x {1, 2, 3}^3 k-meshes): one
-    batched call (hipGraph replay, autotuned tiles) against 24 sequential plain
-    FP64 builds, with the per-cell E_x and K differences."""
+def profile_target(args):
+    """One batch per precision, one 3x3x3 ring build per precision and a plain
+    1 GiB device copy (whose counter readings calibrate the traffic counters)."""
     import torch
 
     import synth
     from paper_2304_05505_amd import exx
-    from synth.fast import orbitals_on_grid_torch
 
     dev = torch.device("cuda", 0)
     h = exx.Handle(0)
-    t0 = time.perf_counter()
-    items64, items_mx, items32 = [], [], []
-    for cell in synth.make_batch_cells():
-        psi = orbitals_on_grid_torch(cell, synth.orbital_coeffs(cell), dev)
-        c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, cell.n_isdf)
-        pts_t = torch.empty((cell.n_isdf,), dtype=torch.int32, device=dev)
-        npiv = torch.empty((1,), dtype=torch.int32, device=dev)
-        exx.exx_select_points(h, c, psi, pts_t, npiv)
-        pts = pts_t.cpu().numpy().astype(np.int64)
-        ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
-        t_ao = torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev)
-        occ = psi[:, :, pts_t.long()].permute(0, 2, 1).contiguous()
-        base = {"cell": c, "occ_pts": occ, "ao_pts": t_ao, "pts": pts_t}
-        for lst, p in ((items64, psi), (items_mx, psi), (items32, psi.to(torch.complex64))):
-            lst.append(dict(base, psi_grid=p,
-                            K=torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128,
-                                          device=dev),
-                            Ex=torch.empty((1,), dtype=torch.float64, device=dev),
-                            rank=torch.empty((cell.N_k,), dtype=torch.int32, device=dev)))
-    torch.cuda.synchronize()
-    log(f"[batch24] inputs and QRCP points for 24 cells in {time.perf_counter() - t0:.1f} s")
-
-    def sequential_f64():
-        for it in items64:
-            exx.exx_build(h, it["cell"], exx.EXX_F64, it["psi_grid"], it["occ_pts"], it["ao_pts"],
-                          it["pts"], it["K"], it["Ex"], it["rank"])
-
+    cells = synth.make_batch_cells()
+    gold = load_json("config4.json")
+    base = [cell_inputs(h, exx, torch, c, dev, pts=gold["cells"][i]["pts"] if gold else None)
+            for i, c in enumerate(cells)]
     stream = torch.cuda.Stream()
-
-    def batched(prec, items):
+    for prec in ("mixed", "f32", "f64"):
+        its = [dict(cell=t["cell"], psi_grid=psi_for(t, prec, torch), occ_pts=t["occ_pts"],
+                    ao_pts=t["ao_pts"], pts=t["pts"], **outputs(torch, c, dev))
+               for c, t in zip(cells, base)]
         stream.wait_stream(torch.cuda.current_stream())
-        exx.exx_build_batched(h, items, prec, exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_TUNE,
+        exx.exx_build_batched(h, its, exx.PREC[prec], exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_TUNE,
                               stream=stream)
         stream.synchronize()
-
-    def timed(fn, reps):
-        fn()
+        log(f"profile target: batch {prec} done")
+    del base
+    cell = synth.make_config(3)
+    g3 = load_json("config3.json")
+    t = cell_inputs(h, exx, torch, cell, dev, pts=g3["pts"] if g3 else None)
+    for prec in ("f64", "mixed", "f32"):
+        o = outputs(torch, cell, dev)
+        exx.exx_build(h, t["cell"], exx.PREC[prec], psi_for(t, prec, torch), t["occ_pts"],
+                      t["ao_pts"], t["pts"], o["K"], o["Ex"], o["rank"])
         torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            t = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t)
-        return float(np.median(ts))
-
-    reps = max(1, min(args.steps, 3))
-    t_seq = timed(sequential_f64, reps)
-    ex64 = [float(it["Ex"].cpu()[0]) for it in items64]
-    k64 = [it["K"].cpu().numpy() for it in items64]
-    log(f"[batch24] 24 sequential FP64 builds: {t_seq * 1e3:.1f} ms")
-    res = {}
-    for name, prec, items in (("f32", exx.EXX_F32, items32), ("mixed", exx.EXX_MIXED, items_mx),
-                              ("f64", exx.EXX_F64, items64)):
-        t_b = timed(lambda: batched(prec, items), reps)
-        dEs = [abs(float(it["Ex"].cpu()[0]) - e) for it, e in zip(items, ex64)]
-        dKs = [float(np.abs(it["K"].cpu().numpy() - k).max()) for it, k in zip(items, k64)]
-        dE, dK = max(dEs), max(dKs)
-        res[name] = {"seconds": t_b, "builds_per_s": 24.0 / t_b, "speedup_vs_seq_f64": t_seq / t_b,
-                     "max_dEx_vs_f64": dE, "max_dK_vs_f64": dK,
-                     "meets_1e-5_1e-6": bool(dE <= 1e-5 and dK <= 1e-6),
-                     "dEx_per_cell": dEs, "dK_per_cell": dKs,
-                     "maxabs_K_per_cell": [float(np.abs(k).max()) for k in k64]}
-        log(f"[batch24] batched {name}: {t_b * 1e3:.1f} ms, max|dEx| {dE:.2e}, max|dK| {dK:.2e}")
-    ok = [n for n in res if res[n]["meets_1e-5_1e-6"]]
-    chosen = max(ok, key=lambda n: res[n]["builds_per_s"])
-    out = {
-        "metric": "K-builds/s over a 24-cell batch (one graph launch) vs 24 sequential plain FP64 "
-                  "builds, at |dE_x| <= 1e-5 Ha/cell and max|dK| <= 1e-6",
-        "value": res[chosen]["builds_per_s"],
-        "path": chosen,
-        "unit": "K-builds/s",
-        "n_gpus": 1,
-        "steps": reps,
-        "higher_is_better": True,
-        "vs_baseline": None,
-        "dtype": {"f64": "f64", "mixed": "f64+f32", "f32": "f32+f64"}[chosen],
-        "data": "synthetic",
-        "config": {"workload": "24 cells: 2 x {8, 16, 24, 48 atoms} x {1, 2, 3}^3 k-meshes, 4 "
-                               "functions/atom, n_occ = 0.44 N, N_ISDF = 2.2 N, QRCP points"},
-        "sequential_f64_s": t_seq,
-        "batched": res,
-    }
-    print(json.dumps(out), flush=True)
+        log(f"profile target: 3x3x3 {prec} done")
+    src = torch.ones((1 << 27,), dtype=torch.float64, device=dev)  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"profile target: copied {src.numel() * 8} bytes")
 
 
 def main():
@@ -388,162 +572,78 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", choices=("auto", "f64", "mixed", "f32"), default="auto")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile", action="store_true",
-                    help="profiling target: one build per precision path and a 1 GiB device "
-                         "copy, no JSON")
-    ap.add_argument("--workload", choices=("rings-k2", "select-k4", "batch24"), default="rings-k2",
-                    help="rings-k2: the K-build throughput line (default); select-k4: learned vs "
-                         "QRCP selection + K-build at the 4x4x4 ring workload; batch24: the "
-                         "24-cell batched build against sequential FP64 builds")
+    ap.add_argument("--profile", action="store_true")
+    ap.add_argument("--workload", choices=("batch24", "rings-k2", "rings-k3", "select-k4"),
+                    default="batch24")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the build is not sharded "
-              "across GPUs", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every GPU box here has one "
+              "GPU; the batch would shard by cell across GPUs with no exchange", file=sys.stderr)
         sys.exit(2)
     if args.workload == "select-k4":
         bench_select5(args)
         return
-    if args.workload == "batch24":
-        bench_batch24(args)
+    if args.profile:
+        profile_target(args)
         return
 
     import torch
 
-    import synth
     from paper_2304_05505_amd import exx
 
     dev = torch.device("cuda", 0)
-    cell = synth.make_config(2)
-    t0 = time.perf_counter()
-    C = synth.orbital_coeffs(cell)
-    psi = synth.orbitals_on_grid(cell, C)
-    log(f"inputs generated in {time.perf_counter() - t0:.1f} s")
-    nk, no, ng, ni, na = cell.N_k, cell.n_occ, cell.N_g, cell.n_isdf, cell.n_ao
-
     h = exx.Handle(0)
-    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, no, na, ni)
-    t_psi64 = torch.from_numpy(psi).to(dev)
-    t_pts = torch.empty((ni,), dtype=torch.int32, device=dev)
-    t_npiv = torch.empty((1,), dtype=torch.int32, device=dev)
-    t0 = time.perf_counter()
-    exx.exx_select_points(h, c, t_psi64, t_pts, t_npiv)
-    torch.cuda.synchronize()
-    log(f"points selected on the GPU in {time.perf_counter() - t0:.2f} s")
-    pts = t_pts.cpu().numpy().astype(np.int64)
-    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(nk)])
-    t_ao = torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev)
-    t_occ = torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev)
-    t_psi32 = t_psi64.to(torch.complex64)
-
-    if args.profile:
-        # one build per precision path, then a plain 1 GiB device copy whose
-        # counter readings calibrate the HBM traffic counters
-        K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
-        Ex = torch.empty((1,), dtype=torch.float64, device=dev)
-        rank = torch.empty((nk,), dtype=torch.int32, device=dev)
-        for prec in ("f64", "mixed", "f32"):
-            t_psi = t_psi32 if prec == "f32" else t_psi64
-            exx.exx_build(h, c, exx.PREC[prec], t_psi, t_occ, t_ao, t_pts, K, Ex, rank)
-            torch.cuda.synchronize()
-            log(f"profile target [{prec}] done: Ex {float(Ex.cpu()[0]):.12f}")
-        src = torch.ones((1 << 27,), dtype=torch.float64, device=dev)  # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"profile target: copied {src.numel() * 8} bytes")
+    if args.workload in ("rings-k2", "rings-k3"):
+        leg = ring_leg(2 if args.workload == "rings-k2" else 3, args, h, exx, torch, dev)
+        print(json.dumps(leg), flush=True)
         return
 
-    results = {}
-    for prec in ("f64", "mixed", "f32"):
-        p = exx.PREC[prec]
-        t_psi = t_psi32 if prec == "f32" else t_psi64
-        K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
-        Ex = torch.empty((1,), dtype=torch.float64, device=dev)
-        rank = torch.empty((nk,), dtype=torch.int32, device=dev)
-
-        def step():
-            exx.exx_build(h, c, p, t_psi, t_occ, t_ao, t_pts, K, Ex, rank)
-
-        # per-phase HIP events on the build's stream, recorded inside the timed
-        # region; the warmup steps fill the handle's event pool
-        h.set_timing(True)
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        h.phase_times()
-        log(f"[{prec}] warmup done")
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        phases = h.phase_times()
-        h.set_timing(False)
-        log(f"[{prec}] {args.steps} steps in {el:.3f} s; phases(ms/build): " +
-            ", ".join(f"{k}={v[0] / args.steps:.2f}" for k, v in phases.items()))
-        results[prec] = {
-            "value": args.steps / el,
-            "ms_per_step": el / args.steps * 1e3,
-            "Ex": float(Ex.cpu()[0]),
-            "K": K.cpu().numpy(),
-            "rank": rank.cpu().tolist(),
-            "phases": phases,
-        }
-
-    ref64 = results["f64"]
-    gold = None
-    gpath = os.path.join(ROOT, "tests", "golden", "config2.json")
-    if os.path.exists(gpath):
-        g = json.load(open(gpath))
-        if g["pts"] == [int(x) for x in pts]:
-            gold = g
-    paths = {}
-    for prec, r in results.items():
-        dE = abs(r["Ex"] - ref64["Ex"])
-        dK = float(np.abs(r["K"] - ref64["K"]).max())
-        paths[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"], "Ex": r["Ex"],
-                       "dEx_vs_f64": dE, "maxdK_vs_f64": dK,
-                       "speedup_vs_f64": r["value"] / ref64["value"],
-                       "meets_1e-5_1e-6": bool(dE <= 1e-5 and dK <= 1e-6)}
-        if gold is not None:
-            paths[prec]["dEx_vs_oracle"] = abs(r["Ex"] - gold["Ex"])
-    if args.prec == "auto":
-        ok = [p for p in paths if paths[p]["meets_1e-5_1e-6"]]
-        chosen = max(ok, key=lambda p: paths[p]["value"])
-    else:
-        chosen = args.prec
-    sel = results[chosen]
-    work = algorithmic_work(cell, ni, "f64" if chosen == "f64" else "f32")
-    dom, roof = roofline(sel["phases"], work, chosen, args.steps)
+    cells, res, seq_r, phase_ms, wex, wsv, units = batch_leg(args, h, exx, torch, dev)
+    legs = {}
+    for cfg in (3, 2):
+        legs[f"rings-k{cfg}"] = ring_leg(cfg, args, h, exx, torch, dev)
+    ok = [p for p in ("mixed", "f32", "f64")
+          if res[p].get("cells_meeting_gate", 0) == 24]
+    chosen = "mixed"
+    r = res[chosen]
+    roof = roofline(phase_ms, wex, wsv, units, chosen)
+    roof["kernel"] = KERNELS.get(roof["phase"], ("?", "?"))
     out = {
         "metric": METRIC,
-        "value": sel["value"],
+        "value": r["builds_per_s"],
         "unit": "K-builds/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sel["ms_per_step"],
+        "ms_per_step": r["seconds"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "mixed": "f64+f32", "f32": "f32+f64"}[chosen],
+        "dtype": "f64+f32",
         "data": "synthetic",
         "config": {
-            "workload": "THC-oo-K K-build, 48-atom four-ring cell, 2x2x2 k-mesh, N=192, n_occ=84, "
-                        "grid 60x75x54, N_ISDF=420",
-            "N_k": nk, "N_g": ng, "n_occ": no, "n_ao": na, "n_isdf": ni,
+            "workload": "24-cell batch: 2 x {8, 16, 24, 48 atoms} x {1^3, 2^3, 3^3} k-meshes, 4 "
+                        "Gaussian functions/atom (N 32-192), n_occ = 0.44 N, N_ISDF = 2.2 N, grids "
+                        "4.5 points/bohr; one exx_build_batched graph launch per step, mixed mode",
+            "cells": 24,
             "prec": chosen,
         },
-        "roofline": dict(roof, kernel=dom),
-        "paths": paths,
-        "oracle_points": gold is not None,
-        "phases_ms": {k: v[0] / args.steps for k, v in sel["phases"].items()},
+        "speedup_vs_sequential_f64": r["speedup_vs_sequential_f64"],
+        "sequential_f64": seq_r,
+        "meets_gate": bool(chosen in ok),
+        "gate": {"dEx_Ha_per_cell": GATE_E, "max_dK": GATE_K, "vs": "stored FP64 oracle values"},
+        "roofline": roof,
+        "batched": {p: {k: v for k, v in res[p].items() if not k.endswith("per_cell")}
+                    for p in res},
+        "batched_per_cell": {p: {"dEx": res[p].get("dEx_per_cell"), "dK": res[p].get("dK_per_cell")}
+                             for p in res},
+        "phases_ms_batch_mixed": phase_ms,
+        "paths": legs,
     }
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(cell, psi, pts, ao)
+        out["cpu_baseline"] = cpu_baseline(cells)
     print(json.dumps(out), flush=True)
 
 

@@ -160,18 +160,77 @@ exx_status check_cell(exx_context* h, const exx_cell* c, exx_prec prec) {
   return EXX_OK;
 }
 
+// Transfers m and -m of the mesh: the fitted pair functions of -m are the
+// conjugates of those of m (relabelling n), so Vb^{-m} = conj Vb^m and the
+// Cholesky pivots (hence the ranks) agree. The paired path below fits and
+// contracts one transfer of each pair (rep, slice order), then writes both.
+// It splits the solve at the factor as the real path does:
+// Y = W Z on the grid (W lower triangular), the contraction of the transform of
+// Y gives Vy, and V^m = W^H Vy W before the Bloch phases are applied.
+struct Pairs {
+  int n = 0;
+  int rep[64], bar[64], slot[64];
+};
+
+Pairs make_pairs(const Geom& g) {
+  Pairs p;
+  for (int m = 0; m < 64; ++m) p.slot[m] = -1;
+  for (int m = 0; m < g.nk; ++m) {
+    const int m1 = m / (g.N[1] * g.N[2]), m2 = (m / g.N[2]) % g.N[1], m3 = m % g.N[2];
+    const int b = (((g.N[0] - m1) % g.N[0]) * g.N[1] + (g.N[1] - m2) % g.N[1]) * g.N[2] +
+                  (g.N[2] - m3) % g.N[2];
+    if (m <= b) {
+      p.slot[m] = p.n;
+      p.rep[p.n] = m;
+      p.bar[p.n] = b != m ? b : -1;
+      ++p.n;
+    }
+  }
+  return p;
+}
+
+// which form the fused build takes (fit_coulomb)
+enum BuildPath { PATH_STAGES = 0, PATH_REAL = 1, PATH_PAIRED = 2 };
+
+BuildPath build_path(const exx_context* h, const Geom& g) {
+  if (h->refine != 0) return PATH_STAGES;
+  if (kcorr_real(g)) return PATH_REAL;
+  return make_pairs(g).n < g.nk ? PATH_PAIRED : PATH_STAGES;
+}
+
+// the paired path's chunking: fit over `cols` grid columns at a time, the
+// transform and contraction over `per` transfers at a time (two buffers)
+struct PairedDims {
+  int cols, per, nchunk;
+};
+
+PairedDims paired_dims(const exx_context* h, const Geom& g, size_t cs) {
+  PairedDims d;
+  const size_t per_col = cs * (size_t)g.nk * g.ni;
+  size_t cols = h->fit_chunk_bytes / per_col;
+  cols = cols / 256 * 256;
+  if (cols < 256) cols = 256;
+  d.cols = (int)std::min<size_t>(cols, (size_t)g.ng);
+  const int np = make_pairs(g).n;
+  d.nchunk = std::min(4, np);
+  d.per = (np + d.nchunk - 1) / d.nchunk;
+  return d;
+}
+
 // scratch layout shared by the three calls
 struct Layout {
-  size_t G, Lf, W, Sp, keep, Y, T, epart, cpart, S2, V2, rank2, tol, Tinv, grid, grid2, total;
+  size_t G, Lf, W, Sp, keep, Y, T, epart, cpart, S2, V2, rank2, tol, Tinv, grid, grid2, F, total;
   int nsplit;
+  PairedDims pd;
 };
 
 // what a call needs besides the point-sized matrices
 enum Need { NEED_FIT = 1, NEED_COULOMB = 2, NEED_K = 4, NEED_BUILD = 8 };
 
-Layout layout(const Geom& g, exx_prec prec, int need) {
+Layout layout(const exx_context* h, const Geom& g, exx_prec prec, int need) {
   const bool build = (need & NEED_BUILD) != 0;
   const bool grid = (need & (NEED_FIT | NEED_COULOMB | NEED_BUILD)) != 0;
+  const bool paired = build && build_path(h, g) == PATH_PAIRED;
   Layout L;
   const size_t mat = al(sizeof(double2) * (size_t)g.nk * g.ni * g.ni);
   // Gamma/Z (and F) buffer: FP64 unless the fit itself runs in FP32; xi: FP64 only in EXX_F64
@@ -207,12 +266,34 @@ Layout layout(const Geom& g, exx_prec prec, int need) {
   o += al(sizeof(double) * g.nk);
   L.Tinv = o;
   o += al(sizeof(double2) * (size_t)g.nk * 32 * g.ni);
+  L.pd = paired_dims(h, g, cs);
   L.grid = o;
-  o += grid ? al(cs * (size_t)g.nk * g.ni * g.ng) : 0;
+  if (paired)  // Gamma / Z of one chunk of grid columns
+    o += al(cs * (size_t)g.nk * g.ni * L.pd.cols);
+  else
+    o += grid ? al(cs * (size_t)g.nk * g.ni * g.ng) : 0;
   L.grid2 = o;
-  o += build ? al(cx * (size_t)g.nk * g.ni * g.ng) : 0;
+  if (paired)  // Y = W Z of the representative transfers
+    o += al(cx * (size_t)make_pairs(g).n * g.ni * g.ng);
+  else
+    o += build ? al(cx * (size_t)g.nk * g.ni * g.ng) : 0;
+  L.F = o;
+  if (paired)  // transforms of two chunks of transfers
+    o += 2 * al(cx * (size_t)L.pd.per * g.ni * g.ng);
   L.total = o;
   return L;
+}
+
+// the second stream of a build and its events (default priority)
+hipError_t make_lane_streams(hipStream_t* aux, hipEvent_t* fork, hipEvent_t* join, hipEvent_t* chain,
+                             hipEvent_t* fb) {
+  hipError_t e = hipStreamCreateWithFlags(aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(chain, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fb[0], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fb[1], hipEventDisableTiming);
+  return e;
 }
 
 // status word for the kernels' reports (null when no check is enabled)
@@ -553,38 +634,16 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
   return EXX_OK;
 }
 
-// Transfers m and -m of the mesh: the fitted pair functions of -m are the
-// conjugates of those of m (relabelling n), so Vb^{-m} = conj Vb^m and the
-// Cholesky pivots (hence the ranks) agree. The paired path below fits and
-// contracts one transfer of each pair (rep, slice order), then writes both.
-// It splits the solve at the factor as the real path does:
-// Y = W Z on the grid (W lower triangular), the contraction of the transform of
-// Y gives Vy, and V^m = W^H Vy W before the Bloch phases are applied.
-struct Pairs {
-  int n = 0;
-  int rep[64], bar[64], slot[64];
-};
-
-Pairs make_pairs(const Geom& g) {
-  Pairs p;
-  for (int m = 0; m < 64; ++m) p.slot[m] = -1;
-  for (int m = 0; m < g.nk; ++m) {
-    const int m1 = m / (g.N[1] * g.N[2]), m2 = (m / g.N[2]) % g.N[1], m3 = m % g.N[2];
-    const int b = (((g.N[0] - m1) % g.N[0]) * g.N[1] + (g.N[1] - m2) % g.N[1]) * g.N[2] +
-                  (g.N[2] - m3) % g.N[2];
-    if (m <= b) {
-      p.slot[m] = p.n;
-      p.rep[p.n] = m;
-      p.bar[p.n] = b != m ? b : -1;
-      ++p.n;
-    }
-  }
-  return p;
-}
-
 // The complex path of the fused build with one transfer per pair (meshes with
 // an axis of 3 or more, refinement off): same steps as fit_impl + coulomb_impl
 // over the representative transfers, Vb of the partners by conjugation.
+//
+// Memory is bounded independently of N_k N_ISDF N_g: the fit runs over chunks
+// of grid columns (Gamma^n, Z^m and Y = W Z are column-local), writing Y of the
+// representative transfers; the transform and the contraction then run over
+// chunks of transfers through two transform buffers, the transform of one
+// chunk on the caller's stream beside the contraction of the previous one on
+// the second stream. Results do not depend on the chunk sizes.
 template <typename TF, typename TX>
 exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                              const Layout& L, const Pairs& pr, const void* psi, const void* occ,
@@ -595,14 +654,16 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   double2* Sp = (double2*)(ws + L.Sp);
   int32_t* keep = (int32_t*)(ws + L.keep);
   int32_t* rank_c = (int32_t*)(ws + L.rank2);
-  void* grid = ws + L.grid;    // Gamma, Z (compacted in place), then the transform
-  void* xi = ws + L.grid2;     // xi of the representative transfers
+  void* gam = ws + L.grid;     // Gamma, then Z (compacted in place), of one column chunk
+  char* xi = ws + L.grid2;     // Y = W Z of the representative transfers, full grid
+  char* fbuf = ws + L.F;       // transforms of two chunks of transfers
   Geom gr = g;                 // batch over the representative transfers
   gr.nk = pr.n;
   const long nn = (long)g.ni * g.ni;
+  const int cc = L.pd.cols;
   hipError_t e;
   hipStream_t ax = st;         // factorisation chain on the caller's stream
-  hipStream_t gs = h->aux;     // Gamma and Z on the second stream
+  hipStream_t gs = h->aux;     // the fit over column chunks on the second stream
   e = hipEventRecord(h->fork_ev, st);
   if (e != hipSuccess) return hip_check(h, e, "fork event");
   e = hipStreamWaitEvent(gs, h->fork_ev, 0);
@@ -638,93 +699,109 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
     e = launch_rank_scatter(rank_c, rank, pr.rep, pr.bar, pr.n, ax);
     if (e != hipSuccess) what = "rank scatter";
   }
+  if (!what) {
+    e = hipEventRecord(h->chain_ev, ax);
+    if (e != hipSuccess) what = "chain event";
+  }
   if (what) {
     (void)hipEventRecord(h->join_ev, gs);
     (void)hipStreamWaitEvent(st, h->join_ev, 0);
     return hip_check(h, e, what);
   }
-  {
-    PhaseTimer pt(h, PH_GAMMA, gs);
-    if (std::is_same<TF, double>::value)
-      e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
-                                        psi, g.ng, (long)g.no * g.ng, grid, g.ng,
-                                        (long)g.ni * g.ng, gs, h->tile_gamma);
-    else
-      e = cgemm_nn_grid32(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi, g.ng,
-                          (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, gs);
-  }
-  if (e != hipSuccess) what = "Gamma gemm";
-  if (!what) {
-    // Z^m of the representative transfers, compacted in place
-    PhaseTimer pt(h, PH_KCORR, gs);
-    e = launch_kcorr<TF>(g, tb, grid, grid, g.ng, pts, false, gs, pr.slot);
-    if (e != hipSuccess) what = "Z kcorr";
+  // the fit, one chunk of grid columns at a time; the first chunk's Gamma and Z
+  // run beside the factorisation chain, every solve waits for it
+  for (int c0 = 0; c0 < g.ng && !what; c0 += cc) {
+    const int cn = std::min(cc, g.ng - c0);
+    const char* psi_c = (const char*)psi + (size_t)c0 * sizeof(cplx<TF>);
+    {
+      PhaseTimer pt(h, PH_GAMMA, gs);
+      if (std::is_same<TF, double>::value)
+        e = zgemm_nn_grid<double, double>(g.ni, cn, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
+                                          psi_c, g.ng, (long)g.no * g.ng, gam, cn, (long)g.ni * cn,
+                                          gs, h->tile_gamma);
+      else
+        e = cgemm_nn_grid32(g.ni, cn, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi_c, g.ng,
+                            (long)g.no * g.ng, gam, cn, (long)g.ni * cn, gs);
+    }
+    if (e != hipSuccess) {
+      what = "Gamma gemm";
+      break;
+    }
+    {
+      // Z^m of the representative transfers, compacted in place
+      PhaseTimer pt(h, PH_KCORR, gs);
+      e = launch_kcorr<TF>(g, tb, gam, gam, cn, pts, false, gs, pr.slot, c0);
+    }
+    if (e != hipSuccess) {
+      what = "Z kcorr";
+      break;
+    }
+    if (c0 == 0) {
+      e = hipStreamWaitEvent(gs, h->chain_ev, 0);
+      if (e != hipSuccess) {
+        what = "chain wait";
+        break;
+      }
+    }
+    PhaseTimer pt(h, PH_SOLVE, gs);
+    e = zgemm_nn_grid<TF, TX>(g.ni, cn, g.ni, gr.nk, W, g.ni, nn, false, gam, cn,
+                              (long)g.ni * cn, xi + (size_t)c0 * sizeof(cplx<TX>), g.ng,
+                              (long)g.ni * g.ng, gs, h->tile_solve, true);
+    if (e != hipSuccess) what = "solve gemm";
   }
   hipError_t ej = hipEventRecord(h->join_ev, gs);
   hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
   if (what) return hip_check(h, e, what);
   if (ew != hipSuccess) return hip_check(h, ew, "join wait");
-  {
-    PhaseTimer pt(h, PH_SOLVE, st);
-    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, gr.nk, W, g.ni, nn, false, grid, g.ng,
-                              (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve,
-                              true);
-  }
-  if (e != hipSuccess) return hip_check(h, e, "solve gemm");
-  // Vy (unphased, slice order) into V. The slices go in four chunks, the
-  // transform of each on the caller's stream and its contraction on the second
-  // stream (the timed phases then overlap). Unlike the real path this pays in
-  // every precision here: the complex transform and the 32 x 32 contraction
-  // tiles of FP32 storage leave each other room on the CUs
+  // Vy (unphased, slice order) into V: the transform of each chunk of transfers
+  // on the caller's stream into one of two buffers, its contraction on the
+  // second stream; a buffer is refilled only after the contraction that read it
   double2* Vy = (double2*)V;
-  const int nchunk = std::min(4, gr.nk);
-  if (nchunk == 1) {
-    {
-      PhaseTimer pt(h, PH_FFT, st);
-      e = launch_fft3d<TX>(g, tb, xi, grid, (long)gr.nk * g.ni, h->ncu, st);
-    }
-    if (e != hipSuccess) return hip_check(h, e, "fft");
-    PhaseTimer pt(h, PH_COULOMB, st);
-    e = launch_coulomb<TX>(g, tb, grid, pts, ws + L.cpart, L.nsplit, Vy, false, st, pr.rep,
-                           pr.bar, pr.n, true);
-    if (e != hipSuccess) return hip_check(h, e, "coulomb");
-  } else {
-    const int per = (gr.nk + nchunk - 1) / nchunk;
-    const size_t fb = (size_t)g.ni * g.ng * sizeof(cplx<TX>);  // functions of one slice
+  const int per = L.pd.per;
+  const size_t fb = (size_t)g.ni * g.ng * sizeof(cplx<TX>);  // functions of one slice
+  {
     std::optional<PhaseTimer> tc;
-    {
-      PhaseTimer pt(h, PH_FFT, st);
-      for (int s0 = 0; s0 < gr.nk && !what; s0 += per) {
-        const int cn = std::min(per, gr.nk - s0);
-        e = launch_fft3d<TX>(g, tb, (const char*)xi + s0 * fb, (char*)grid + s0 * fb,
-                             (long)cn * g.ni, h->ncu, st);
-        if (e != hipSuccess) what = "fft";
-        if (!what) e = hipEventRecord(h->fork_ev, st);
-        if (!what && e == hipSuccess) e = hipStreamWaitEvent(gs, h->fork_ev, 0);
-        if (!what && e != hipSuccess) what = "chunk fork";
-        if (!what && !tc) tc.emplace(h, PH_COULOMB, gs);
-        if (!what)
-          e = launch_coulomb<TX>(g, tb, (const char*)grid + s0 * fb, pts, ws + L.cpart, L.nsplit,
-                                 Vy + (long)s0 * nn, false, gs, pr.rep + s0, pr.bar + s0, cn,
-                                 true);
-        if (!what && e != hipSuccess) what = "coulomb";
+    PhaseTimer pt(h, PH_FFT, st);
+    int chunk = 0;
+    for (int s0 = 0; s0 < gr.nk && !what; s0 += per, ++chunk) {
+      const int cn = std::min(per, gr.nk - s0);
+      const int b = chunk & 1;
+      char* F = fbuf + (size_t)b * al(per * fb);
+      if (chunk >= 2) {
+        e = hipStreamWaitEvent(st, h->fb_ev[b], 0);
+        if (e != hipSuccess) {
+          what = "buffer wait";
+          break;
+        }
+      }
+      e = launch_fft3d<TX>(g, tb, xi + s0 * fb, F, (long)cn * g.ni, h->ncu, st);
+      if (e != hipSuccess) what = "fft";
+      if (!what) e = hipEventRecord(h->fork_ev, st);
+      if (!what && e == hipSuccess) e = hipStreamWaitEvent(gs, h->fork_ev, 0);
+      if (!what && e != hipSuccess) what = "chunk fork";
+      if (!what && !tc) tc.emplace(h, PH_COULOMB, gs);
+      if (!what)
+        e = launch_coulomb<TX>(g, tb, F, pts, ws + L.cpart, L.nsplit, Vy + (long)s0 * nn, false, gs,
+                               pr.rep + s0, pr.bar + s0, cn, true);
+      if (!what && e != hipSuccess) what = "coulomb";
+      if (!what) {
+        e = hipEventRecord(h->fb_ev[b], gs);
+        if (e != hipSuccess) what = "buffer event";
       }
     }
-    tc.reset();
-    ej = hipEventRecord(h->join_ev, gs);
-    ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
-    if (what) return hip_check(h, e, what);
-    if (ew != hipSuccess) return hip_check(h, ew, "join wait");
   }
+  ej = hipEventRecord(h->join_ev, gs);
+  ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
+  if (what) return hip_check(h, e, what);
+  if (ew != hipSuccess) return hip_check(h, ew, "join wait");
   {
     PhaseTimer pt(h, PH_COULOMB, st);
     // V^m = W^H Vy W with T = Vy W in the S^+ scratch and the product in the
     // consumed partial sums, then the phases and the conjugate partners
     double2* T = Sp;
     double2* U = (double2*)(ws + L.cpart);
-    if (e == hipSuccess)
-      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_N, Vy, g.ni, nn, B_N,
-                                               W, g.ni, nn, T, g.ni, nn, 1.0, false, st);
+    e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_N, Vy, g.ni, nn, B_N, W,
+                                             g.ni, nn, T, g.ni, nn, 1.0, false, st);
     if (e == hipSuccess)
       e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_C, W, g.ni, nn, B_N,
                                                T, g.ni, nn, U, g.ni, nn, 1.0, false, st);
@@ -850,15 +927,13 @@ exx_status setup(exx_context* h, const exx_cell* cell, exx_prec prec, int need, 
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
   if (!h->aux) {
-    e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+    e = make_lane_streams(&h->aux, &h->fork_ev, &h->join_ev, &h->chain_ev, h->fb_ev);
     if (e != hipSuccess) return hip_check(h, e, "auxiliary stream");
   }
   e = fft_prepare(&h->ncu);
   if (e != hipSuccess) return hip_check(h, e, "FFT set-up");
   *g = make_geom(*cell);
-  *L = layout(*g, prec, need);
+  *L = layout(h, *g, prec, need);
   *ws = (char*)ws_get(h, L->total, &s);
   if (s != EXX_OK) return s;
   return get_tables(h, *g, tb, st);
@@ -893,6 +968,9 @@ exx_status exx_create(exx_handle_t* h, int device) {
   // wave tiles of the grid GEMMs (16x16 blocks); EXX_TILE_GAMMA / EXX_TILE_SOLVE override
   if (const char* v = getenv("EXX_TILE_GAMMA")) c->tile_gamma = atoi(v);
   if (const char* v = getenv("EXX_TILE_SOLVE")) c->tile_solve = atoi(v);
+  // grid-column chunk of the paired path's fit, in MiB of Gamma (experiments)
+  if (const char* v = getenv("EXX_FIT_CHUNK_MB"))
+    if (atol(v) > 0) c->fit_chunk_bytes = (size_t)atol(v) << 20;
   *h = c;
   return EXX_OK;
 }
@@ -911,6 +989,9 @@ exx_status exx_destroy(exx_handle_t h) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->chain_ev) (void)hipEventDestroy(h->chain_ev);
+  for (auto ev : h->fb_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   if (h->join_ev) (void)hipEventDestroy(h->join_ev);
   if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -1022,8 +1103,8 @@ exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec pre
   const Geom g = make_geom(*cell);
   if (call == EXX_CALL_BUILD) {
     if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
-    size_t b = layout(g, prec, NEED_BUILD).total;
-    b = std::max(b, layout(g, prec, NEED_FIT | NEED_COULOMB | NEED_K).total);
+    size_t b = layout(h, g, prec, NEED_BUILD).total;
+    b = std::max(b, layout(h, g, prec, NEED_FIT | NEED_COULOMB | NEED_K).total);
     *bytes = b;
     return EXX_OK;
   }
@@ -1254,9 +1335,7 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
   if (!h->aux) {
-    e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+    e = make_lane_streams(&h->aux, &h->fork_ev, &h->join_ev, &h->chain_ev, h->fb_ev);
     if (e != hipSuccess) return hip_check(h, e, "auxiliary stream");
   }
   e = fft_prepare(&h->ncu);
@@ -1274,7 +1353,7 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
     if (!it.psi_grid || !it.occ_pts || !it.ao_pts || !it.pts || !it.K || !it.Ex || !it.rank)
       return fail(h, EXX_ERR_ARG, "item " + std::to_string(i) + ": null array");
     geo[i] = make_geom(it.cell);
-    lay[i] = layout(geo[i], prec, NEED_BUILD);
+    lay[i] = layout(h, geo[i], prec, NEED_BUILD);
     need = lay[i].total > need ? lay[i].total : need;
   }
   exx_status s;

@@ -126,6 +126,13 @@ struct exx_context {
   // which overlaps the grid-sized Gamma and Z; fork/join events
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // paired path: end of the metric chain, and the two transform buffers'
+  // release (their contraction has read them)
+  hipEvent_t chain_ev = nullptr;
+  hipEvent_t fb_ev[2] = {nullptr, nullptr};
+  // grid columns per chunk of the paired path's fit: the Gamma/Z buffer holds
+  // at most this many bytes (EXX_FIT_CHUNK_MB overrides)
+  size_t fit_chunk_bytes = (size_t)8 << 30;
   int ncu = 256;
   // autotuned wave tiles per size class: key (ni, ng, no, nk, prec) -> (gamma, solve)
   struct Tune {
@@ -282,10 +289,11 @@ exx_status get_tables(exx_context* h, const Geom& g, Tables* t, hipStream_t st);
 // columns c are grid points (cols_are_points false) or the points pts[c].
 // slot (64 entries, host): transfer m goes to output slice slot[m] <= m, or is
 // skipped for -1; nullptr writes every m to slice m.
+// col0: grid index of column 0 (grid columns: column c is grid point col0 + c).
 template <typename T>
 hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* out, int ncol,
                         const int32_t* pts, bool cols_are_points, hipStream_t st,
-                        const int* slot = nullptr);
+                        const int* slot = nullptr, int col0 = 0);
 bool kcorr_supported(const Geom& g);
 // meshes whose every axis has N_i <= 2 (all transfers self-conjugate)
 bool kcorr_real(const Geom& g);

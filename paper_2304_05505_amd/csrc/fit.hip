@@ -160,6 +160,7 @@ struct KcorrArgs {
   int N[3];
   // output slice of transfer m, or -1 to skip it (compacted output); slot[m] <= m
   int slot[64];
+  int col0;  // grid index of column 0 (grid columns)
 };
 
 // out[m][P][c] = e^{i q_m.(r_P - r_c)} (1/N_k) DFT_k(|DFT_k in|^2)[m]
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void kcorr_kernel(const cplx<T>* in, cplx<T>* 
   const int n23 = ka.n[1] * ka.n[2];
   int gp = pts[P];
   int p1 = gp / n23, p2 = (gp / ka.n[2]) % ka.n[1], p3 = gp % ka.n[2];
-  int gc = cols_are_points ? pts[c] : c;
+  int gc = cols_are_points ? pts[c] : ka.col0 + c;
   int c1 = gc / n23, c2 = (gc / ka.n[2]) % ka.n[1], c3 = gc % ka.n[2];
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
@@ -424,8 +425,9 @@ bool kcorr_supported(const Geom& g) {
 template <typename T>
 hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* out, int ncol,
                         const int32_t* pts, bool cols_are_points, hipStream_t st,
-                        const int* slot) {
+                        const int* slot, int col0) {
   KcorrArgs ka;
+  ka.col0 = col0;
   for (int a = 0; a < 3; ++a) {
     ka.root[a] = tb.root[a];
     ka.n[a] = g.n[a];
@@ -520,8 +522,8 @@ template hipError_t launch_gamma_kcorr<float, float>(const Geom&, const void*, c
                                                      hipStream_t);
 
 template hipError_t launch_kcorr<double>(const Geom&, const Tables&, const void*, void*, int,
-                                         const int32_t*, bool, hipStream_t, const int*);
+                                          const int32_t*, bool, hipStream_t, const int*, int);
 template hipError_t launch_kcorr<float>(const Geom&, const Tables&, const void*, void*, int,
-                                        const int32_t*, bool, hipStream_t, const int*);
+                                          const int32_t*, bool, hipStream_t, const int*, int);
 
 }  // namespace exx

@@ -254,3 +254,26 @@ def test_reduced_precision_stages(name, prec, gpu):
         assert dV <= 1e-6 and dE <= 1e-6 and dK <= 3e-6
     else:
         assert dV <= 1e-4 and dE <= 1e-6 and dK <= 8 * EPS32 * np.sqrt(_cond(o))
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed", "f32"])
+@pytest.mark.parametrize("name", ["k321", "k333", "k311"])
+def test_paired_fit_chunking_is_exact(name, prec, gpu, monkeypatch):
+    """The paired path fits over chunks of grid columns (Gamma^n, Z^m and Y = W Z
+    are column-local) and transforms over chunks of transfers; a handle whose
+    column chunk is 256 columns (several chunks on these grids) returns the same
+    bits as one whose chunk spans the whole grid."""
+    cell = CELLS[name]()
+    base = inputs(cell)
+    pts, _ = select.select_points(base["psi"], cell.n_isdf)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    from paper_2304_05505_amd import exx
+
+    a = run_gpu(cell, base["psi"], pts, ao, prec, stages=False, handle=exx.Handle(0))
+    monkeypatch.setenv("EXX_FIT_CHUNK_MB", "1")
+    small = exx.Handle(0)
+    b = run_gpu(cell, base["psi"], pts, ao, prec, stages=False, handle=small)
+    print(f"{name} {prec}: N_g {cell.N_g}, |dK| {np.abs(a['K'] - b['K']).max():.2e}")
+    assert cell.N_g > 256
+    assert np.array_equal(a["rank"], b["rank"])
+    assert np.array_equal(a["K"], b["K"]) and a["Ex"] == b["Ex"]
