@@ -327,9 +327,12 @@ def batch_leg(args, h, exx, torch, dev):
                           it["pts"], it["K"], it["Ex"], it["rank"])
 
     stream = torch.cuda.Stream()
-    flags = exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_TUNE
+    modes = {"graph": exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_TUNE,
+             "lanes": exx.EXX_BATCH_CONCURRENT | exx.EXX_BATCH_TUNE}
 
-    def batched(prec, its):
+    def batched(prec, its, mode):
+        flags = modes[mode]
+
         def fn():
             stream.wait_stream(torch.cuda.current_stream())
             exx.exx_build_batched(h, its, exx.PREC[prec], flags, stream=stream)
@@ -345,9 +348,17 @@ def batch_leg(args, h, exx, torch, dev):
     for prec in ("mixed", "f32", "f64"):
         its = items(prec)
         its_by_prec[prec] = its
-        s = time_steps(batched(prec, its), steps if prec == "mixed" else max(1, steps // 2),
-                       warmup, torch)
-        r = {"seconds": s, "builds_per_s": 24.0 / s, "speedup_vs_sequential_f64": s_seq / s}
+        t_mode = {}
+        for mode in modes:
+            t_mode[mode] = time_steps(batched(prec, its, mode),
+                                      steps if prec == "mixed" else max(1, steps // 2), warmup, torch)
+            log(f"[batch24] batched {prec} ({mode}): {t_mode[mode] * 1e3:.1f} ms")
+        mode = min(t_mode, key=t_mode.get)
+        batched(prec, its, mode)()  # the outputs checked below come from the reported mode
+        torch.cuda.synchronize()
+        s = t_mode[mode]
+        r = {"seconds": s, "builds_per_s": 24.0 / s, "speedup_vs_sequential_f64": s_seq / s,
+             "mode": mode, "seconds_by_mode": t_mode}
         if gold:
             dE, dK = batch_errors(its, gold, goldK)
             r.update({"max_dEx_vs_oracle": max(dE), "max_dK_vs_oracle": max(dK),
@@ -625,7 +636,9 @@ def main():
         "config": {
             "workload": "24-cell batch: 2 x {8, 16, 24, 48 atoms} x {1^3, 2^3, 3^3} k-meshes, 4 "
                         "Gaussian functions/atom (N 32-192), n_occ = 0.44 N, N_ISDF = 2.2 N, grids "
-                        "4.5 points/bohr; one exx_build_batched graph launch per step, mixed mode",
+                        "4.5 points/bohr; one exx_build_batched call per step (captured graph or "
+                        "concurrent lanes, the faster), mixed mode",
+            "batch_mode": r["mode"],
             "cells": 24,
             "prec": chosen,
         },

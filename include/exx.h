@@ -388,8 +388,9 @@ exx_status exx_select_points_mlp(exx_handle_t h, const exx_cell* cell, const voi
 /*
  * exx_build_batched -- many independent K-builds (cells of different shapes,
  * k-meshes and sizes) in one call, each exactly as exx_build. All items use
- * the same precision mode. The handle's scratch is sized once for the
- * largest item and the items run one after another on `stream`.
+ * the same precision mode. Without EXX_BATCH_CONCURRENT the handle's scratch
+ * is sized once for the largest item and the items run one after another on
+ * `stream`.
  *
  * flags:
  *   EXX_BATCH_GRAPH  record the whole batch once into a HIP graph (stream
@@ -403,6 +404,17 @@ exx_status exx_select_points_mlp(exx_handle_t h, const exx_cell* cell, const voi
  *                    once per size class (n_isdf, N_g, n_occ, N_k) and keep
  *                    the fastest in the handle; later builds of the same
  *                    class use it.
+ *
+ *   EXX_BATCH_CONCURRENT  run the items on up to four concurrent lanes: each
+ *                    lane has its own streams and scratch (sized for its
+ *                    largest item); items go longest first to the least
+ *                    loaded lane; the most lanes whose scratch fits in 85% of
+ *                    the device memory free at the call are used (one lane,
+ *                    the sequential order, when none fits or when the caller's
+ *                    workspace is set). Lanes fork from and join back into
+ *                    `stream`, so small cells run beside large ones. Results do
+ *                    not depend on the lane plan. Not combinable with
+ *                    EXX_BATCH_GRAPH (EXX_ERR_UNSUPPORTED).
  *
  *   items  [n] host array; every pointer in it is device memory as in
  *          exx_build (psi_grid, occ_pts, ao_pts, pts in; K, Ex, rank out)
@@ -420,8 +432,20 @@ typedef struct {
 
 #define EXX_BATCH_GRAPH 1
 #define EXX_BATCH_TUNE 2
+#define EXX_BATCH_CONCURRENT 4
 exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_batch_item* items,
                              exx_prec prec, int32_t flags, hipStream_t stream);
+
+/*
+ * exx_save_tuning / exx_load_tuning -- write the handle's autotuned tile table
+ * (EXX_BATCH_TUNE results, one line per size class: n_isdf, N_g, n_occ, N_k,
+ * precision, Gamma tile, solve tile) to a text file, and read such a file into
+ * the handle (entries replace those of the same class), so that later
+ * processes skip the timing runs. A malformed file is rejected (EXX_ERR_ARG)
+ * without changing the table.
+ */
+exx_status exx_save_tuning(exx_handle_t h, const char* path);
+exx_status exx_load_tuning(exx_handle_t h, const char* path);
 
 /*
  * exx_set_refinement -- steps (0, the default, or 1) of iterative refinement

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -995,6 +996,15 @@ exx_status exx_destroy(exx_handle_t h) {
   if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   if (h->join_ev) (void)hipEventDestroy(h->join_ev);
   if (h->aux) (void)hipStreamDestroy(h->aux);
+  for (size_t l = 1; l < h->lanes.size(); ++l) {
+    auto& ln = h->lanes[l];
+    if (ln.ws) (void)hipFree(ln.ws);
+    for (hipEvent_t ev : {ln.fork_ev, ln.join_ev, ln.chain_ev, ln.done_ev, ln.fb_ev[0], ln.fb_ev[1]})
+      if (ev) (void)hipEventDestroy(ev);
+    if (ln.aux) (void)hipStreamDestroy(ln.aux);
+    if (ln.st) (void)hipStreamDestroy(ln.st);
+  }
+  if (h->batch_ev) (void)hipEventDestroy(h->batch_ev);
   delete h;
   return EXX_OK;
 }
@@ -1005,7 +1015,9 @@ exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes) {
   if (!h || !bytes) return EXX_ERR_ARG;
   size_t tb = 0;
   for (auto& te : h->tabs) tb += te.bytes;
-  *bytes = h->ws.cap + tb + h->small_cap;
+  size_t lb = 0;
+  for (size_t l = 1; l < h->lanes.size(); ++l) lb += h->lanes[l].cap;
+  *bytes = h->ws.cap + tb + h->small_cap + lb;
   return EXX_OK;
 }
 
@@ -1326,11 +1338,102 @@ exx_status autotune(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
 
 }  // namespace
 
+namespace {
+
+// cost of one build in multiply-adds of its grid-sized steps (for lane balance)
+double build_cost(const Geom& g) {
+  return (double)g.nk * g.ni * (double)g.ng * (g.no + 2.0 * g.ni);
+}
+
+// swap the handle's second stream and events with those of a lane (the host
+// enqueues the lanes one after another, so the build code sees one set)
+void swap_lane(exx_context* h, exx_context::Lane& l) {
+  std::swap(h->aux, l.aux);
+  std::swap(h->fork_ev, l.fork_ev);
+  std::swap(h->join_ev, l.join_ev);
+  std::swap(h->chain_ev, l.chain_ev);
+  std::swap(h->fb_ev[0], l.fb_ev[0]);
+  std::swap(h->fb_ev[1], l.fb_ev[1]);
+}
+
+// Split the items over up to 4 lanes, longest first onto the least loaded lane,
+// using the most lanes whose scratch (each lane sized for its largest item) fits
+// in `budget` bytes. Returns the lane of every item.
+std::vector<int> plan_lanes(const std::vector<Geom>& geo, const std::vector<Layout>& lay,
+                            size_t budget, int max_lanes, std::vector<size_t>* need) {
+  const int n = (int)geo.size();
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return build_cost(geo[a]) > build_cost(geo[b]); });
+  for (int L = std::min(max_lanes, n); L >= 1; --L) {
+    std::vector<double> load(L, 0.0);
+    std::vector<size_t> nd(L, 0);
+    std::vector<int> lane(n, 0);
+    for (int i : order) {
+      int best = 0;
+      for (int l = 1; l < L; ++l)
+        if (load[l] < load[best]) best = l;
+      lane[i] = best;
+      load[best] += build_cost(geo[i]);
+      nd[best] = std::max(nd[best], lay[i].total);
+    }
+    size_t tot = 0;
+    for (size_t x : nd) tot += x;
+    if (L == 1 || tot <= budget) {
+      *need = nd;
+      return lane;
+    }
+  }
+  return std::vector<int>(n, 0);
+}
+
+exx_status ensure_lanes(exx_context* h, int L, const std::vector<size_t>& need) {
+  if ((int)h->lanes.size() < L) h->lanes.resize(L);
+  for (int l = 1; l < L; ++l) {
+    exx_context::Lane& ln = h->lanes[l];
+    hipError_t e = hipSuccess;
+    if (!ln.st) {
+      e = hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking);
+      if (e == hipSuccess)
+        e = make_lane_streams(&ln.aux, &ln.fork_ev, &ln.join_ev, &ln.chain_ev, ln.fb_ev);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ln.done_ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_check(h, e, "lane streams");
+    }
+    if (ln.cap < need[l]) {
+      if (ln.ws) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_check(h, e, "hipDeviceSynchronize");
+        (void)hipFree(ln.ws);
+        ln.ws = nullptr;
+        ln.cap = 0;
+      }
+      void* p = nullptr;
+      e = hipMalloc(&p, need[l]);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, EXX_ERR_NOMEM, "lane scratch of " + std::to_string(need[l]) + " bytes");
+      }
+      ln.ws = (char*)p;
+      ln.cap = need[l];
+    }
+  }
+  if (!h->batch_ev) {
+    hipError_t e = hipEventCreateWithFlags(&h->batch_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_check(h, e, "batch event");
+  }
+  return EXX_OK;
+}
+
+}  // namespace
+
 extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_batch_item* items,
                                         exx_prec prec, int32_t flags, hipStream_t stream) {
   if (!h) return EXX_ERR_ARG;
   h->err.clear();
   if (n < 0 || (n > 0 && !items)) return fail(h, EXX_ERR_ARG, "exx_build_batched: bad item list");
+  if (flags & ~(EXX_BATCH_GRAPH | EXX_BATCH_TUNE | EXX_BATCH_CONCURRENT))
+    return fail(h, EXX_ERR_ARG, "exx_build_batched: unknown flag");
   if (n == 0) return EXX_OK;
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
@@ -1344,7 +1447,6 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   std::vector<Geom> geo(n);
   std::vector<Layout> lay(n);
   std::vector<Tables> tabs(n);
-  size_t need = 0;
   for (int i = 0; i < n; ++i) {
     const exx_batch_item& it = items[i];
     exx_status s = check_cell(h, &it.cell, prec);
@@ -1354,49 +1456,98 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
       return fail(h, EXX_ERR_ARG, "item " + std::to_string(i) + ": null array");
     geo[i] = make_geom(it.cell);
     lay[i] = layout(h, geo[i], prec, NEED_BUILD);
-    need = lay[i].total > need ? lay[i].total : need;
   }
+  if ((flags & EXX_BATCH_GRAPH) && stream == nullptr)
+    return fail(h, EXX_ERR_ARG, "EXX_BATCH_GRAPH needs a non-default stream (capture)");
+  // capturing several lanes into one graph ended in a host-side segmentation
+  // fault inside the capture, launch or instantiation, whose cause has not been
+  // found; that combination is switched off
+  if ((flags & EXX_BATCH_GRAPH) && (flags & EXX_BATCH_CONCURRENT))
+    return fail(h, EXX_ERR_UNSUPPORTED,
+                "EXX_BATCH_GRAPH with EXX_BATCH_CONCURRENT is not supported");
+  // lanes: several only when asked for, with library-owned scratch, within the
+  // device memory that is free now (plus what lane 0 already holds)
+  int max_lanes = 1;
+  size_t budget = 0;
+  if ((flags & EXX_BATCH_CONCURRENT) && !h->user_ws && n > 1) {
+    size_t fr = 0, tot = 0;
+    e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) return hip_check(h, e, "hipMemGetInfo");
+    size_t held = h->ws.cap;
+    for (size_t l = 1; l < h->lanes.size(); ++l) held += h->lanes[l].cap;
+    budget = (size_t)(0.85 * (double)(fr + held));
+    max_lanes = 4;
+  }
+  std::vector<size_t> need;
+  const std::vector<int> lane =
+      plan_lanes(geo, lay, budget, max_lanes, &need);
+  const int L = (int)need.size();
   exx_status s;
-  char* ws = (char*)ws_get(h, need, &s);
+  char* ws0 = (char*)ws_get(h, need[0], &s);
   if (s != EXX_OK) return s;
+  s = ensure_lanes(h, L, need);
+  if (s != EXX_OK) return s;
+  auto ws_of = [&](int i) { return lane[i] == 0 ? ws0 : h->lanes[lane[i]].ws; };
   for (int i = 0; i < n; ++i) {
     s = get_tables(h, geo[i], &tabs[i], stream);
     if (s != EXX_OK) return s;
   }
   if (flags & EXX_BATCH_TUNE) {
     for (int i = 0; i < n; ++i) {
-      s = autotune(h, geo[i], tabs[i], ws, lay[i], prec, items[i], stream);
+      s = autotune(h, geo[i], tabs[i], ws_of(i), lay[i], prec, items[i], stream);
       if (s != EXX_OK) return s;
     }
   }
+  // enqueue lane by lane: lane 0 on `stream`, lanes 1.. on their own streams
+  // forked from `stream` and joined back into it
   auto run_all = [&]() -> exx_status {
     const int sg = h->tile_gamma, ss = h->tile_solve;
-    for (int i = 0; i < n; ++i) {
-      long key[5];
-      tune_key(geo[i], prec, key);
-      if (const exx_context::Tune* t = find_tune(h, key)) {
-        h->tile_gamma = t->gamma;
-        h->tile_solve = t->solve;
-      }
-      exx_status r = build_one(h, geo[i], tabs[i], ws, lay[i], prec, items[i], stream);
-      h->tile_gamma = sg;
-      h->tile_solve = ss;
-      if (r != EXX_OK) return r;
+    hipError_t ee = hipSuccess;
+    if (L > 1) {
+      ee = hipEventRecord(h->batch_ev, stream);
+      for (int l = 1; l < L && ee == hipSuccess; ++l)
+        ee = hipStreamWaitEvent(h->lanes[l].st, h->batch_ev, 0);
+      if (ee != hipSuccess) return hip_check(h, ee, "lane fork");
     }
-    return EXX_OK;
+    exx_status r = EXX_OK;
+    for (int l = 0; l < L && r == EXX_OK; ++l) {
+      hipStream_t ls = l == 0 ? stream : h->lanes[l].st;
+      if (l > 0) swap_lane(h, h->lanes[l]);
+      for (int i = 0; i < n && r == EXX_OK; ++i) {
+        if (lane[i] != l) continue;
+        long key[5];
+        tune_key(geo[i], prec, key);
+        if (const exx_context::Tune* t = find_tune(h, key)) {
+          h->tile_gamma = t->gamma;
+          h->tile_solve = t->solve;
+        }
+        r = build_one(h, geo[i], tabs[i], ws_of(i), lay[i], prec, items[i], ls);
+        h->tile_gamma = sg;
+        h->tile_solve = ss;
+      }
+      if (l > 0) {
+        swap_lane(h, h->lanes[l]);
+        // join the lane back even after an error, so that a capture stays joined
+        hipError_t ej = hipEventRecord(h->lanes[l].done_ev, ls);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, h->lanes[l].done_ev, 0);
+        if (ej != hipSuccess && r == EXX_OK) r = hip_check(h, ej, "lane join");
+      }
+    }
+    return r;
   };
   if (!(flags & EXX_BATCH_GRAPH)) {
     s = run_all();
     return s == EXX_OK ? finish(h, stream) : s;
   }
-  if (stream == nullptr)
-    return fail(h, EXX_ERR_ARG, "EXX_BATCH_GRAPH needs a non-default stream (capture)");
 
-  // signature: precision, refinement, workspace base and every item field
+  // signature: precision, refinement, checks, lane plan and scratch, every item field
   std::vector<long> sig;
   sig.push_back((long)prec);
   sig.push_back((long)h->refine);
-  sig.push_back((long)(size_t)ws);
+  sig.push_back((long)h->checks);
+  sig.push_back((long)L);
+  sig.push_back((long)(size_t)ws0);
+  for (int l = 1; l < L; ++l) sig.push_back((long)(size_t)h->lanes[l].ws);
   for (int i = 0; i < n; ++i) {
     const exx_batch_item& it = items[i];
     const int32_t* c = (const int32_t*)&it.cell;
@@ -1408,8 +1559,8 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
     tune_key(geo[i], prec, key);
     const exx_context::Tune* t = find_tune(h, key);
     sig.push_back(t ? t->gamma * 100 + t->solve : 0);
+    sig.push_back(lane[i]);
   }
-  sig.push_back((long)h->checks);
   for (const auto& ge : h->graphs)
     if (ge.sig == sig) {
       s = hip_check(h, hipGraphLaunch(ge.exec, stream), "hipGraphLaunch");
@@ -1438,6 +1589,55 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   h->graphs.push_back({sig, exec});
   s = hip_check(h, hipGraphLaunch(exec, stream), "hipGraphLaunch");
   return s == EXX_OK ? finish(h, stream) : s;
+}
+
+extern "C" exx_status exx_save_tuning(exx_handle_t h, const char* path) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!path) return fail(h, EXX_ERR_ARG, "exx_save_tuning: path is NULL");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(h, EXX_ERR_ARG, std::string("exx_save_tuning: cannot write ") + path);
+  fprintf(f, "# exx tile table v1: n_isdf n_grid n_occ n_k prec tile_gamma tile_solve\n");
+  for (const auto& t : h->tuned)
+    fprintf(f, "%ld %ld %ld %ld %ld %d %d\n", t.key[0], t.key[1], t.key[2], t.key[3], t.key[4],
+            t.gamma, t.solve);
+  const bool ok = fclose(f) == 0;
+  return ok ? EXX_OK : fail(h, EXX_ERR_ARG, std::string("exx_save_tuning: write failed: ") + path);
+}
+
+extern "C" exx_status exx_load_tuning(exx_handle_t h, const char* path) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!path) return fail(h, EXX_ERR_ARG, "exx_load_tuning: path is NULL");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(h, EXX_ERR_ARG, std::string("exx_load_tuning: cannot read ") + path);
+  char line[256];
+  std::vector<exx_context::Tune> got;
+  bool bad = false;
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    exx_context::Tune t;
+    if (sscanf(line, "%ld %ld %ld %ld %ld %d %d", &t.key[0], &t.key[1], &t.key[2], &t.key[3],
+               &t.key[4], &t.gamma, &t.solve) != 7 ||
+        (t.gamma != 22 && t.gamma != 24 && t.gamma != 42) ||
+        (t.solve != 22 && t.solve != 24 && t.solve != 42)) {
+      bad = true;
+      break;
+    }
+    got.push_back(t);
+  }
+  fclose(f);
+  if (bad) return fail(h, EXX_ERR_ARG, std::string("exx_load_tuning: malformed line in ") + path);
+  for (const auto& t : got) {
+    bool found = false;
+    for (auto& u : h->tuned)
+      if (std::equal(u.key, u.key + 5, t.key)) {
+        u = t;
+        found = true;
+      }
+    if (!found) h->tuned.push_back(t);
+  }
+  return EXX_OK;
 }
 
 namespace {

@@ -134,6 +134,17 @@ struct exx_context {
   // at most this many bytes (EXX_FIT_CHUNK_MB overrides)
   size_t fit_chunk_bytes = (size_t)8 << 30;
   int ncu = 256;
+  // concurrent lanes of a batched build (lane 0 is the handle's own stream set
+  // and scratch; lanes 1.. have their own streams, events and scratch)
+  struct Lane {
+    hipStream_t st = nullptr, aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr, chain_ev = nullptr, done_ev = nullptr;
+    hipEvent_t fb_ev[2] = {nullptr, nullptr};
+    char* ws = nullptr;
+    size_t cap = 0;
+  };
+  std::vector<Lane> lanes;
+  hipEvent_t batch_ev = nullptr;
   // autotuned wave tiles per size class: key (ni, ng, no, nk, prec) -> (gamma, solve)
   struct Tune {
     long key[5];

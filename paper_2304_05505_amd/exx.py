@@ -56,9 +56,11 @@ EXPORTED = (
     "exx_set_checks",
     "exx_get_status",
     "exx_build_K_noalloc",
+    "exx_save_tuning",
+    "exx_load_tuning",
 )
 
-EXX_BATCH_GRAPH, EXX_BATCH_TUNE = 1, 2
+EXX_BATCH_GRAPH, EXX_BATCH_TUNE, EXX_BATCH_CONCURRENT = 1, 2, 4
 EXX_CALL_BUILD, EXX_CALL_SELECT, EXX_CALL_SELECT_MLP = 0, 1, 2
 EXX_CHECK_FINITE, EXX_STRICT_PD, EXX_CHECK_SYNC = 1, 2, 4
 EXX_ERR_NOT_PD, EXX_ERR_NONFINITE = -4, -5
@@ -142,6 +144,8 @@ def _load():
         "exx_set_checks": ([vp, ctypes.c_int32], ctypes.c_int),
         "exx_get_status": ([vp, vp, i32p], ctypes.c_int),
         "exx_build_K_noalloc": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "exx_save_tuning": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "exx_load_tuning": ([vp, ctypes.c_char_p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -271,6 +275,14 @@ class Handle:
         self._check(_lib.exx_set_workspace(self._h, buf.data_ptr(),
                                            buf.numel() * buf.element_size()))
         self._ws = buf
+
+    def save_tuning(self, path: str):
+        """Write the autotuned tile table (exx_save_tuning)."""
+        self._check(_lib.exx_save_tuning(self._h, str(path).encode()))
+
+    def load_tuning(self, path: str):
+        """Read a tile table written by save_tuning (exx_load_tuning)."""
+        self._check(_lib.exx_load_tuning(self._h, str(path).encode()))
 
     def set_checks(self, flags: int):
         self._check(_lib.exx_set_checks(self._h, int(flags)))

@@ -73,7 +73,7 @@ def _single(h, exx, it, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "mixed", "f32"])
-@pytest.mark.parametrize("flags", [0, 2, 1, 3])
+@pytest.mark.parametrize("flags", [0, 2, 1, 3, 4, 6])
 def test_batched_equals_single_builds(batch, prec, flags, gpu):
     import torch
 
@@ -106,16 +106,55 @@ def test_batched_equals_single_builds(batch, prec, flags, gpu):
             assert np.abs(K - Ks).max() <= 1e-13 * np.abs(Ks).max(), f"rep {rep}"
             assert abs(Ex - Es) <= 1e-13 * abs(Es), f"rep {rep}"
             assert np.array_equal(rs, ref["rank"])
-            # same tolerance rule as the parity tests: 64 eps64 cond(S_RR) relative (FP64);
-            # the mixed and F32 modes store FP32 data (eps32 relative, amplified like the
-            # solve)
+            # the parity tests' bounds against the oracle, for E_x and the whole K
             conds = []
             for m in range(ref["S"].shape[0]):
                 R = np.flatnonzero(ref["keep"][m])
                 conds.append(np.linalg.cond(ref["S"][m][np.ix_(R, R)]))
-            eps = np.finfo(np.float64).eps if prec == "f64" else np.finfo(np.float32).eps
-            tol = max(1e-12, 64 * eps * max(conds))
-            assert abs(Ex - ref["Ex"]) <= tol * abs(ref["Ex"])
+            cond = max(conds)
+            dE = abs(Ex - ref["Ex"]) / abs(ref["Ex"])
+            dK = np.abs(K - ref["K"]).max() / np.abs(ref["K"]).max()
+            # beyond cond 1e10 FP64 itself fixes K only to ~eps64 cond (either side)
+            floor = min(1e-5, 4 * np.finfo(np.float64).eps * cond) if cond > 1e10 else 0.0
+            msg = f"{cell.name} {prec}: cond {cond:.2e} rel dE {dE:.2e} rel dK {dK:.2e}"
+            if prec == "f64":
+                tol = min(1e-8, max(1e-12, 64 * np.finfo(np.float64).eps * cond))
+                assert dE <= tol and dK <= max(tol, floor), msg
+            elif prec == "mixed":
+                assert dE <= 3e-7 and dK <= max(3e-7, floor), msg
+            elif cond <= 1e10:
+                # F32 data is amplified by the metric: beyond cond 1e10 (the 3x2x1
+                # cell here, 6e12) its result is not compared with the oracle
+                assert dE <= 1e-6, msg
+                assert dK <= 8 * np.finfo(np.float32).eps * np.sqrt(cond), msg
+
+
+@pytest.mark.skip(reason="capturing concurrent lanes into one graph (EXX_BATCH_GRAPH | "
+                  "EXX_BATCH_CONCURRENT) ended in a host segmentation fault whose cause is not "
+                  "found; the library rejects the combination, and this case stays off the GPU")
+def test_graph_with_concurrent_lanes(batch, gpu):
+    from paper_2304_05505_amd import exx
+    import torch
+
+    h = exx.Handle(0)
+    items = _items(batch, "f64")
+    exx.exx_build_batched(h, items, exx.EXX_F64, exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_CONCURRENT,
+                          stream=torch.cuda.Stream())
+
+
+def test_graph_and_lanes_is_rejected_before_launch(batch, gpu):
+    """The switched-off combination returns EXX_ERR_UNSUPPORTED before anything runs."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    h = exx.Handle(0)
+    items = _items(batch, "f64")
+    with pytest.raises(exx.ExxError) as ei:
+        exx.exx_build_batched(h, items, exx.EXX_F64,
+                              exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_CONCURRENT,
+                              stream=torch.cuda.Stream())
+    assert ei.value.status == -7
 
 
 def test_graph_requires_a_stream(batch, gpu):
@@ -125,3 +164,35 @@ def test_graph_requires_a_stream(batch, gpu):
     items = _items(batch, "f64")
     with pytest.raises(ValueError):
         exx.exx_build_batched(h, items, exx.EXX_F64, exx.EXX_BATCH_GRAPH)
+
+
+def test_tuning_table_round_trip(batch, gpu, tmp_path):
+    """The autotuned tile table saved to a file and loaded into a fresh handle
+    gives the same table (and the same batched results without re-tuning); a
+    malformed file is rejected."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    h = exx.Handle(0)
+    items = _items(batch, "f64")
+    exx.exx_build_batched(h, items, exx.EXX_F64, exx.EXX_BATCH_TUNE)
+    torch.cuda.synchronize()
+    K0 = [it["K"].clone() for it in items]
+    path = tmp_path / "tiles.txt"
+    h.save_tuning(str(path))
+    lines = [ln for ln in path.read_text().splitlines() if not ln.startswith("#")]
+    assert len(lines) == len({(c.n_isdf, c.N_g, c.n_occ, c.N_k) for c, _, _ in batch})
+    h2 = exx.Handle(0)
+    h2.load_tuning(str(path))
+    path2 = tmp_path / "tiles2.txt"
+    h2.save_tuning(str(path2))
+    assert path2.read_text() == path.read_text()
+    exx.exx_build_batched(h2, items, exx.EXX_F64, 0)
+    torch.cuda.synchronize()
+    for it, k in zip(items, K0):
+        assert torch.equal(it["K"], k)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("420 243000 84 8 0 22\n")
+    with pytest.raises(exx.ExxError):
+        h2.load_tuning(str(bad))
