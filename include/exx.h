@@ -244,7 +244,8 @@ exx_status exx_build_K_noalloc(exx_handle_t h, const exx_cell* cell, exx_prec pr
  * elsewhere it fits and contracts one transfer of each pair (m, -m); both
  * apply the triangular inverse Cholesky factor W (S^+ = W^H W) to the grid
  * and form Vb = W^H Vy W from the contraction of its transform (with
- * refinement on, exx_set_refinement, it runs the stage-wise form). It forks a
+ * refinement on, exx_set_refinement, Y is refined in the factor form:
+ * R = Z - L Y, Y += W R). It forks a
  * second stream of the handle (the Gamma fit beside the factorisation; on the
  * paired path, and in EXX_F64 on the real path, also the contraction of each
  * chunk of transfers beside the transform of the next) and joins it back into
@@ -449,11 +450,13 @@ exx_status exx_load_tuning(exx_handle_t h, const char* path);
 
 /*
  * exx_set_refinement -- steps (0, the default, or 1) of iterative refinement
- * applied by every later fit of this handle (exx_isdf_fit, exx_build,
- * exx_build_batched): after xi^m = S^+ Z^m, the residual R^m = Z^m - S^m xi^m
- * and the correction xi^m += S^+ R^m are formed with FP64 arithmetic on the
- * stored operands (two more grid-sized GEMMs per fit). With the pivot-drop
- * rule the correction is confined to the retained points like the solve.
+ * applied by every later fit of this handle. exx_isdf_fit: after
+ * xi^m = S^+ Z^m, the residual R^m = Z^m - S^m xi^m and the correction
+ * xi^m += S^+ R^m. exx_build and exx_build_batched (which keep Y = W Z, W the
+ * inverse Cholesky factor, S = L L^H on the retained points): R = Z - L Y and
+ * Y += W R. Either way two more grid-sized GEMMs per fit, formed with FP64
+ * sums on the stored operands; with the pivot-drop rule the correction is
+ * confined to the retained points like the solve.
  */
 exx_status exx_set_refinement(exx_handle_t h, int32_t steps);
 

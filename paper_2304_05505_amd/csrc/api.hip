@@ -194,7 +194,7 @@ Pairs make_pairs(const Geom& g) {
 enum BuildPath { PATH_STAGES = 0, PATH_REAL = 1, PATH_PAIRED = 2 };
 
 BuildPath build_path(const exx_context* h, const Geom& g) {
-  if (h->refine != 0) return PATH_STAGES;
+  (void)h;
   if (kcorr_real(g)) return PATH_REAL;
   return make_pairs(g).n < g.nk ? PATH_PAIRED : PATH_STAGES;
 }
@@ -531,6 +531,12 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     PhaseTimer pt(h, PH_PINV, ax);
     e = launch_tri_inv_real(g, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
     if (e != hipSuccess) what = "triangular inverse";
+    // the refinement multiplies by L itself: clear what the factorisation left
+    // above its diagonal
+    if (!what && h->refine > 0) {
+      e = launch_zero_upper(Lf, g.ni, g.nk, ax);
+      if (e != hipSuccess) what = "factor";
+    }
   }
   if (what) {
     (void)hipEventRecord(h->join_ev, gs);
@@ -570,6 +576,18 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
                               (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, st, true);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
+  if (h->refine > 0) {
+    // one step of iterative refinement in the factor form: with S~ = L L^T on the
+    // retained points, the residual of eta = W^T Y is L (W Z~ - Y), so
+    // R = Z~ - L Y (over Z~) and Y += W R, both sums in FP64
+    PhaseTimer pt(h, PH_SOLVE, st);
+    e = dgemm_nn_grid_acc<TX, TZ>(g.ni, g.ng, g.ni, g.nk, Lf, g.ni, nn, grid, g.ng,
+                                  (long)g.ni * g.ng, grid2, g.ng, (long)g.ni * g.ng, -1, st, true);
+    if (e == hipSuccess)
+      e = dgemm_nn_grid_acc<TZ, TX>(g.ni, g.ng, g.ni, g.nk, W, g.ni, nn, grid2, g.ng,
+                                    (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, 1, st, true);
+    if (e != hipSuccess) return hip_check(h, e, "refinement");
+  }
   // FP64 storage: the transfers go in four chunks, the transform of each chunk
   // on the caller's stream and its contraction on the second stream, so that
   // the transform of one chunk runs beside the contraction of the one before
@@ -700,6 +718,10 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
     e = launch_rank_scatter(rank_c, rank, pr.rep, pr.bar, pr.n, ax);
     if (e != hipSuccess) what = "rank scatter";
   }
+  if (!what && h->refine > 0) {
+    e = launch_zero_upper(Lf, g.ni, gr.nk, ax);
+    if (e != hipSuccess) what = "factor";
+  }
   if (!what) {
     e = hipEventRecord(h->chain_ev, ax);
     if (e != hipSuccess) what = "chain event";
@@ -745,10 +767,19 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
       }
     }
     PhaseTimer pt(h, PH_SOLVE, gs);
+    char* y = xi + (size_t)c0 * sizeof(cplx<TX>);
     e = zgemm_nn_grid<TF, TX>(g.ni, cn, g.ni, gr.nk, W, g.ni, nn, false, gam, cn,
-                              (long)g.ni * cn, xi + (size_t)c0 * sizeof(cplx<TX>), g.ng,
-                              (long)g.ni * g.ng, gs, h->tile_solve, true);
+                              (long)g.ni * cn, y, g.ng, (long)g.ni * g.ng, gs, h->tile_solve, true);
     if (e != hipSuccess) what = "solve gemm";
+    if (!what && h->refine > 0) {
+      // refinement in the factor form: R = Z - L Y (over Z), Y += W R (FP64 sums)
+      e = zgemm_nn_grid_acc<TX, TF>(g.ni, cn, g.ni, gr.nk, Lf, g.ni, nn, y, g.ng,
+                                    (long)g.ni * g.ng, gam, cn, (long)g.ni * cn, -1, gs);
+      if (e == hipSuccess)
+        e = zgemm_nn_grid_acc<TF, TX>(g.ni, cn, g.ni, gr.nk, W, g.ni, nn, gam, cn,
+                                      (long)g.ni * cn, y, g.ng, (long)g.ni * g.ng, 1, gs);
+      if (e != hipSuccess) what = "refinement";
+    }
   }
   hipError_t ej = hipEventRecord(h->join_ev, gs);
   hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
@@ -822,14 +853,14 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
   void* V = ws + L.V2;
   exx_status s;
   const Pairs pr = make_pairs(g);
-  if (!kcorr_real(g) && h->refine == 0 && pr.n < g.nk) {
+  if (!kcorr_real(g) && pr.n < g.nk) {
     if (prec == EXX_F64)
       return fit_coulomb_pairs<double, double>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
     if (prec == EXX_MIXED)
       return fit_coulomb_pairs<double, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
     return fit_coulomb_pairs<float, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
   }
-  if (kcorr_real(g) && h->refine == 0) {
+  if (kcorr_real(g)) {
     if (prec == EXX_F64)
       return fit_coulomb_real<double, double, double>(h, g, tb, ws, L, psi, occ, pts, S, V, rank,
                                                       st);

@@ -241,6 +241,21 @@ __global__ void status_reset_kernel(int32_t* __restrict__ status) {
   }
 }
 
+__global__ void zero_upper_kernel(double2* __restrict__ A, int n, long total) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const long w = e % ((long)n * n);
+  if (w % n > w / n) A[e] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_zero_upper(double2* A, int n, int batch, hipStream_t st) {
+  const long total = (long)batch * n * n;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, A,
+                     n, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_status_reset(int32_t* status, hipStream_t st) {
   hipLaunchKernelGGL(status_reset_kernel, dim3(1), dim3(64), 0, st, status);
   return hipGetLastError();

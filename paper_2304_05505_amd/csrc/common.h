@@ -274,6 +274,14 @@ struct StridedGemm {
 hipError_t dgemm_strided(const StridedGemm& s, int batch, const double* A, const double* B,
                          double* C, bool cplx_out, hipStream_t st, double alpha = 1.0,
                          bool acc = false);
+// real form of the accumulating product: C[b] = C[b] + sign Re(A[b]) B[b]
+// (sign = +1 or -1, sum in FP64), same operands as dgemm_nn_grid
+template <typename TB, typename TC>
+hipError_t dgemm_nn_grid_acc(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                             const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                             int sign, hipStream_t st, bool lower = false);
+// zero the strict upper triangle of N_k complex n x n matrices
+hipError_t launch_zero_upper(double2* A, int n, int batch, hipStream_t st);
 // C[b] = C[b] + sign * A[b] * B[b] (sign = +1 or -1), same operands as zgemm_nn_grid
 // (tile 22, no conjugation); used by the iterative refinement of the fit
 template <typename TB, typename TC>

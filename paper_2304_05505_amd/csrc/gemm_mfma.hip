@@ -292,7 +292,8 @@ __global__ __launch_bounds__(256) void cgemm_nn_mfma32(int M, int N, int K, int 
 // LOWER: A is lower triangular (zero above its diagonal), so the band of rows
 // [r0, r0 + 64) stops its k loop at r0 + 64 and skips the 16-row blocks that a
 // k-step cannot reach (above the diagonal, or past M).
-template <typename TB, typename TC, int LOWER>
+// ACC = 0: C = A B; ACC = +1 / -1: C = C +/- A B (sum formed in FP64).
+template <typename TB, typename TC, int LOWER, int ACC = 0>
 __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nrt, long ntiles,
                                                      long ntiles_pad, const double2* __restrict__ A,
                                                      long lda, long sA, const TB* __restrict__ B,
@@ -390,7 +391,10 @@ __global__ __launch_bounds__(256) void dgemm_nn_mfma(int M, int N, int K, int nr
         const double x = sv[v * 64 + lane];
         const int r = row0 + i * 16 + 4 * v + lk;
         const long c = col0 + j * 16 + li;
-        if (r < M && c < N) C[(long)r * ldc + c] = (TC)x;
+        if (r < M && c < N) {
+          TC* dst = C + (long)r * ldc + c;
+          *dst = ACC ? (TC)((double)*dst + (double)ACC * x) : (TC)x;
+        }
       }
     }
 }
@@ -501,6 +505,44 @@ template hipError_t dgemm_nn_grid<double, float>(int, int, int, int, const void*
 template hipError_t dgemm_nn_grid<float, float>(int, int, int, int, const void*, long, long,
                                                 const void*, long, long, void*, long, long,
                                                 hipStream_t, bool);
+
+template <typename TB, typename TC>
+hipError_t dgemm_nn_grid_acc(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                             const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                             int sign, hipStream_t st, bool lower) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (!offsets_fit(M, N, K, 2 * lda, ldb)) return hipErrorInvalidValue;
+  if ((long)M * 2 * lda * 8 >= 0xffffffffL || (long)K * ldb * (long)sizeof(TB) >= 0xffffffffL)
+    return hipErrorInvalidValue;
+  if (sign != 1 && sign != -1) return hipErrorInvalidValue;
+  const int nrt = (M + 63) / 64;
+  const long nct = ((long)N + 255) / 256;
+  const long ntiles = nrt * nct;
+  const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
+#define EXX_DACC(LW, SG)                                                                      \
+  hipLaunchKernelGGL((dgemm_nn_mfma<TB, TC, LW, SG>), dim3((unsigned)pad, batch), dim3(256), 0, \
+                     st, M, N, K, nrt, ntiles, pad, (const double2*)A, lda, sA, (const TB*)B,  \
+                     ldb, sB, (TC*)C, ldc, sC)
+  if (lower && sign > 0)
+    EXX_DACC(1, 1);
+  else if (lower)
+    EXX_DACC(1, -1);
+  else if (sign > 0)
+    EXX_DACC(0, 1);
+  else
+    EXX_DACC(0, -1);
+#undef EXX_DACC
+  return hipGetLastError();
+}
+#define EXX_DACC_INST(TB, TC)                                                                 \
+  template hipError_t dgemm_nn_grid_acc<TB, TC>(int, int, int, int, const void*, long, long, \
+                                                const void*, long, long, void*, long, long,  \
+                                                int, hipStream_t, bool);
+EXX_DACC_INST(double, double)
+EXX_DACC_INST(float, double)
+EXX_DACC_INST(double, float)
+EXX_DACC_INST(float, float)
+#undef EXX_DACC_INST
 
 namespace {
 
