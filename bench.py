@@ -216,7 +216,7 @@ def outputs(torch, cell, dev):
 
 
 def psi_for(t, prec, torch):
-    if prec == "f32":
+    if prec in ("f32", "bf16"):
         if "psi32" not in t:
             t["psi32"] = t["psi64"].to(torch.complex64)
         return t["psi32"]
@@ -249,7 +249,7 @@ def ring_leg(config, args, h, exx, torch, dev):
     torch.cuda.synchronize()
     log(f"[{tag}] inputs in {time.perf_counter() - t0:.1f} s")
     res = {}
-    for prec in ("f64", "mixed", "f32"):
+    for prec in ("f64", "mixed", "f32", "bf16"):
         o = outputs(torch, cell, dev)
 
         def step():
@@ -273,7 +273,7 @@ def ring_leg(config, args, h, exx, torch, dev):
         log(f"[{tag}] {prec}: {s * 1e3:.2f} ms/build, E_x {r['Ex']:.10f}" +
             (f", |dEx| {r['dEx_vs_oracle']:.2e}, max|dK| {r['maxdK_vs_oracle']:.2e}"
              if "dEx_vs_oracle" in r else ""))
-    for prec in ("mixed", "f32"):
+    for prec in ("mixed", "f32", "bf16"):
         res[prec]["speedup_vs_f64"] = res["f64"]["ms_per_build"] / res[prec]["ms_per_build"]
     return {"workload": f"48-atom four-ring cell, {'x'.join(map(str, cell.kmesh))} k-mesh, N=192, "
                         f"n_occ=84, grid 60x75x54, N_ISDF=420", "paths": res}

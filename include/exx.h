@@ -82,7 +82,12 @@ typedef enum {
  *              applies the FP64 pseudo-inverse in FP64 arithmetic; FFT in
  *              FP32; the Coulomb contraction as in EXX_MIXED (FP64 matrix
  *              cores on the FP32-stored transforms).
- *   EXX_BF16   reserved (not built in: EXX_ERR_UNSUPPORTED). */
+ *   EXX_BF16   as EXX_F32, but the grid-sized fit GEMM Gamma^n runs on the
+ *              BF16 matrix cores: occ_pts and psi_grid (c64) are rounded to
+ *              bfloat16 (nearest even) as they are loaded, FP32 accumulation,
+ *              Gamma kept in FP32. psi_grid and xi are c64. Its error is that
+ *              of 8-bit significands amplified by the metric's conditioning
+ *              (reported, not within the 1e-5 / 1e-6 accuracy target). */
 typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 } exx_prec;
 
 typedef struct {

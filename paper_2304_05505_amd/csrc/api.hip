@@ -340,10 +340,11 @@ exx_status finish(exx_context* h, hipStream_t st) {
 }
 
 // TF: type of Gamma^n / Z^m (and of psi_grid); TX: storage type of xi
+// bf16 (with TF = float): Gamma^n on the BF16 matrix cores
 template <typename TF, typename TX>
 exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                     const void* psi, const void* occ, const int32_t* pts, void* xi, void* S,
-                    int32_t* rank, hipStream_t st) {
+                    int32_t* rank, hipStream_t st, bool bf16 = false) {
   double2* G = (double2*)(ws + L.G);
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
@@ -411,6 +412,9 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
       e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
                                         psi, g.ng, (long)g.no * g.ng, grid, g.ng,
                                         (long)g.ni * g.ng, st, h->tile_gamma);
+    else if (bf16)
+      e = cgemm_nn_grid_bf16(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, psi, g.ng,
+                             (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, st);
     else
       e = cgemm_nn_grid32(g.ni, g.ng, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi, g.ng,
                           (long)g.no * g.ng, grid, g.ng, (long)g.ni * g.ng, st);
@@ -488,7 +492,7 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
 template <typename TF, typename TZ, typename TX>
 exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                             const Layout& L, const void* psi, const void* occ, const int32_t* pts,
-                            void* S, void* V, int32_t* rank, hipStream_t st) {
+                            void* S, void* V, int32_t* rank, hipStream_t st, bool bf16 = false) {
   double2* G = (double2*)(ws + L.G);
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
@@ -549,7 +553,9 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     PhaseTimer pt(h, PH_GAMMA, gs);
     float2* occ32 = (float2*)(ws + L.T);
     e = launch_narrow((const double2*)occ, occ32, (long)g.nk * g.ni * g.no, gs);
-    if (e == hipSuccess) e = launch_gamma_kcorr<float, float>(g, occ32, psi, grid2, gs);
+    if (e == hipSuccess)
+      e = bf16 ? launch_gamma_kcorr_bf16(g, occ32, psi, grid2, gs)
+               : launch_gamma_kcorr<float, float>(g, occ32, psi, grid2, gs);
     if (e != hipSuccess) what = "Gamma and Z kcorr";
   } else {
     // FP64: the three-product Gamma GEMM, then the real k-correlation
@@ -666,7 +672,8 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
 template <typename TF, typename TX>
 exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                              const Layout& L, const Pairs& pr, const void* psi, const void* occ,
-                             const int32_t* pts, void* V, int32_t* rank, hipStream_t st) {
+                             const int32_t* pts, void* V, int32_t* rank, hipStream_t st,
+                             bool bf16 = false) {
   double2* G = (double2*)(ws + L.G);
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
@@ -742,6 +749,9 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
         e = zgemm_nn_grid<double, double>(g.ni, cn, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
                                           psi_c, g.ng, (long)g.no * g.ng, gam, cn, (long)g.ni * cn,
                                           gs, h->tile_gamma);
+      else if (bf16)
+        e = cgemm_nn_grid_bf16(g.ni, cn, g.no, g.nk, occ, g.no, (long)g.ni * g.no, psi_c, g.ng,
+                               (long)g.no * g.ng, gam, cn, (long)g.ni * cn, gs);
       else
         e = cgemm_nn_grid32(g.ni, cn, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi_c, g.ng,
                             (long)g.no * g.ng, gam, cn, (long)g.ni * cn, gs);
@@ -858,7 +868,8 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
       return fit_coulomb_pairs<double, double>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
     if (prec == EXX_MIXED)
       return fit_coulomb_pairs<double, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
-    return fit_coulomb_pairs<float, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
+    return fit_coulomb_pairs<float, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st,
+                                           prec == EXX_BF16);
   }
   if (kcorr_real(g)) {
     if (prec == EXX_F64)
@@ -867,7 +878,8 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
     if (prec == EXX_MIXED)
       return fit_coulomb_real<double, double, float>(h, g, tb, ws, L, psi, occ, pts, S, V, rank,
                                                      st);
-    return fit_coulomb_real<float, float, float>(h, g, tb, ws, L, psi, occ, pts, S, V, rank, st);
+    return fit_coulomb_real<float, float, float>(h, g, tb, ws, L, psi, occ, pts, S, V, rank, st,
+                                                 prec == EXX_BF16);
   }
   if (prec == EXX_F64) {
     s = fit_impl<double, double>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st);
@@ -876,7 +888,7 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
     s = fit_impl<double, float>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st);
     if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, st);
   } else {
-    s = fit_impl<float, float>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st);
+    s = fit_impl<float, float>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st, prec == EXX_BF16);
     if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, st);
   }
   return s;
@@ -955,7 +967,6 @@ exx_status setup(exx_context* h, const exx_cell* cell, exx_prec prec, int need, 
                  Tables* tb, Layout* L, char** ws, hipStream_t st) {
   exx_status s = check_cell(h, cell, prec);
   if (s != EXX_OK) return s;
-  if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
   if (!h->aux) {
@@ -1072,7 +1083,8 @@ exx_status exx_isdf_fit(exx_handle_t h, const exx_cell* cell, exx_prec prec, con
   else if (prec == EXX_MIXED)
     s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
   else
-    s = fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream);
+    s = fit_impl<float, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, S, rank, stream,
+                               prec == EXX_BF16);
   return s == EXX_OK ? finish(h, stream) : s;
 }
 
@@ -1145,8 +1157,7 @@ exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec pre
   if (s != EXX_OK) return s;
   const Geom g = make_geom(*cell);
   if (call == EXX_CALL_BUILD) {
-    if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
-    size_t b = layout(h, g, prec, NEED_BUILD).total;
+      size_t b = layout(h, g, prec, NEED_BUILD).total;
     b = std::max(b, layout(h, g, prec, NEED_FIT | NEED_COULOMB | NEED_K).total);
     *bytes = b;
     return EXX_OK;
@@ -1214,7 +1225,6 @@ exx_status exx_build_K_noalloc(exx_handle_t h, const exx_cell* cell, exx_prec pr
     return fail(h, EXX_ERR_ARG, "exx_build_K_noalloc: null array argument");
   exx_status s = check_cell(h, cell, prec);
   if (s != EXX_OK) return s;
-  if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
   const Geom g = make_geom(*cell);
   // G, Y [N_k][N_ISDF][N_ISDF], T [N_k][N_ISDF][n_ao], A^H (n_ao <= N_ISDF), partial sums
   const size_t mat = al(sizeof(double2) * (size_t)g.nk * g.ni * g.ni);
@@ -1482,8 +1492,7 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
     const exx_batch_item& it = items[i];
     exx_status s = check_cell(h, &it.cell, prec);
     if (s != EXX_OK) return fail(h, s, "item " + std::to_string(i) + ": " + h->err);
-    if (prec == EXX_BF16) return fail(h, EXX_ERR_UNSUPPORTED, "EXX_BF16 is not built in");
-    if (!it.psi_grid || !it.occ_pts || !it.ao_pts || !it.pts || !it.K || !it.Ex || !it.rank)
+      if (!it.psi_grid || !it.occ_pts || !it.ao_pts || !it.pts || !it.K || !it.Ex || !it.rank)
       return fail(h, EXX_ERR_ARG, "item " + std::to_string(i) + ": null array");
     geo[i] = make_geom(it.cell);
     lay[i] = layout(h, geo[i], prec, NEED_BUILD);

@@ -63,6 +63,13 @@ __device__ __forceinline__ void cstore(cplx<S>* p, cplx<T> v) {
   *p = mk<S>((S)v.x, (S)v.y);
 }
 
+// bfloat16 by round-to-nearest-even of an FP32 value (finite inputs): the top
+// 16 bits of x + 0x7fff + (bit 16 of x)
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
 __host__ __device__ __forceinline__ int wrap_sym(int x, int L) {
   // ((x + floor(L/2)) mod L) - floor(L/2), with a non-negative mod
   int h = L / 2;
@@ -326,6 +333,16 @@ hipError_t launch_narrow(const double2* in, float2* out, long n, hipStream_t st)
 // Z~ [N_k][N_ISDF][N_g] (TZ) from occ [N_k][N_ISDF][n_occ] and psi, both storage T
 template <typename T, typename TZ>
 hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, void* Z,
+                              hipStream_t st);
+
+// BF16 form of launch_gamma_kcorr: occ and psi (c64) rounded to bfloat16 at
+// load, products on the BF16 matrix cores with FP32 accumulation, Z~ in FP32
+hipError_t launch_gamma_kcorr_bf16(const Geom& g, const void* occ, const void* psi, void* Z,
+                                   hipStream_t st);
+// BF16 form of cgemm_nn_grid32 with conjB: C = A conj(B), A c128 and B c64 rounded
+// to bfloat16 at load, BF16 matrix cores, FP32 accumulation, C c64
+hipError_t cgemm_nn_grid_bf16(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                              const void* B, long ldb, long sB, void* C, long ldc, long sC,
                               hipStream_t st);
 
 // dst[0:n] = src[0:n] (a kernel, so that captured sequences hold no copy nodes)

@@ -401,6 +401,125 @@ __global__ __launch_bounds__(256) void gamma_kcorr_kernel(int ni, int ng, int no
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 form of the fused Gamma + real k-correlation. Same tile and lane roles as
+// gamma_kcorr_kernel, with v_mfma_f32_16x16x32_bf16: a k-step covers 32 occupied
+// orbitals, lane group lk = lane/16 holds orbitals 8 lk .. 8 lk + 7 of its row
+// (occ) or column (psi), rounded to bfloat16; the same (lk, item) pairing on both
+// operands makes the instruction sum over all 32. FP32 accumulation.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u16x8 v) {
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+
+template <typename TZ, int N1, int N2, int N3, int WN>
+__global__ __launch_bounds__(256) void gamma_kcorr_bf16_kernel(int ni, int ng, int no, int nrt,
+                                                               long ntiles, long ntiles_pad,
+                                                               const float2* __restrict__ occ,
+                                                               const float2* __restrict__ psi,
+                                                               TZ* __restrict__ Z) {
+  constexpr int NK = N1 * N2 * N3;
+  const long per = ntiles_pad / 8;
+  const long t = (blockIdx.x % 8) * per + blockIdx.x / 8;  // XCD-contiguous tile ranges
+  if (t >= ntiles) return;
+  const int rt = (int)(t % nrt);
+  const long ct = t / nrt;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = rt * 64 + wave * 16;
+  const long col0 = ct * (16 * WN);
+  const int ra = min(row0 + li, ni - 1);
+  long bcol[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long c = col0 + 16 * j + li;
+    bcol[j] = c < ng ? c : ng - 1;
+  }
+  gk_f4 are[NK][WN], aim[NK][WN];
+#pragma unroll
+  for (int n = 0; n < NK; ++n)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) are[n][j] = aim[n][j] = gk_f4{0, 0, 0, 0};
+  const int nks = (no + 31) / 32;
+#pragma unroll
+  for (int n = 0; n < NK; ++n) {
+    const float2* An = occ + ((long)n * ni + ra) * no;
+    const float2* Bn = psi + (long)n * no * ng;
+    for (int ks = 0; ks < nks; ++ks) {
+      const int k0 = 32 * ks + 8 * lk;
+      u16x8 ar, ai, nar;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + e;
+        const float2 a = k < no ? An[k] : make_float2(0.f, 0.f);
+        ar[e] = bf16_rne(a.x);
+        ai[e] = bf16_rne(a.y);
+        nar[e] = ar[e] ^ 0x8000u;
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        u16x8 br, bi;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = min(k0 + e, no - 1);  // the A side is zero past no
+          const float2 b = Bn[(long)k * ng + bcol[j]];
+          br[e] = bf16_rne(b.x);
+          bi[e] = bf16_rne(b.y);
+        }
+        // Gamma = A conj(B): Re += ar br + ai bi, Im += ai br - ar bi
+        are[n][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ar), as_bf16x8(br),
+                                                            are[n][j], 0, 0, 0);
+        are[n][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ai), as_bf16x8(bi),
+                                                            are[n][j], 0, 0, 0);
+        aim[n][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ai), as_bf16x8(br),
+                                                            aim[n][j], 0, 0, 0);
+        aim[n][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(nar), as_bf16x8(bi),
+                                                            aim[n][j], 0, 0, 0);
+      }
+    }
+  }
+  // the k-mesh correlation of each element, as in gamma_kcorr_kernel
+  __shared__ float stage[4][2 * NK][64];
+  typedef __attribute__((address_space(3))) volatile float lds_t;
+  lds_t* sw = (lds_t*)&stage[wave][0][0];
+  const float inv = 1.0f / (float)NK;
+  const long nz = (long)ni * ng;
+#pragma unroll
+  for (int j = 0; j < WN; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int n = 0; n < NK; ++n) {
+        sw[(2 * n) * 64 + lane] = are[n][j][v];
+        sw[(2 * n + 1) * 64 + lane] = aim[n][j][v];
+      }
+      cplx<float> a[NK];
+#pragma unroll
+      for (int n = 0; n < NK; ++n)
+        a[n] = mk<float>(sw[(2 * n) * 64 + lane], sw[(2 * n + 1) * 64 + lane]);
+      if (NK > 1) {
+        kdft3<float, N1, N2, N3>(a);
+#pragma unroll
+        for (int n = 0; n < NK; ++n) a[n] = mk<float>(a[n].x * a[n].x + a[n].y * a[n].y, 0);
+        kdft3<float, N1, N2, N3>(a);
+      } else {
+        a[0] = mk<float>(a[0].x * a[0].x + a[0].y * a[0].y, 0);
+      }
+      const int r = row0 + 4 * lk + v;
+      const long c = col0 + 16 * j + li;
+      if (r < ni && c < ng) {
+        TZ* dst = Z + (long)r * ng + c;
+#pragma unroll
+        for (int m = 0; m < NK; ++m) dst[(long)m * nz] = (TZ)(a[m].x * inv);
+      }
+    }
+}
+
 #define EXX_KMESH_LIST(X) \
   X(1, 1, 1)              \
   X(2, 2, 2)              \
@@ -520,6 +639,30 @@ hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, v
 }
 template hipError_t launch_gamma_kcorr<float, float>(const Geom&, const void*, const void*, void*,
                                                      hipStream_t);
+
+hipError_t launch_gamma_kcorr_bf16(const Geom& g, const void* occ, const void* psi, void* Z,
+                                   hipStream_t st) {
+  constexpr int WN = 2;
+  const int nrt = (g.ni + 63) / 64;
+  const long nct = ((long)g.ng + 16 * WN - 1) / (16 * WN);
+  const long ntiles = nrt * nct;
+  const long pad = (ntiles + 7) / 8 * 8;
+#define EXX_GKB(a, b, c)                                                                         \
+  if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                               \
+    hipLaunchKernelGGL((gamma_kcorr_bf16_kernel<float, a, b, c, WN>), dim3((unsigned)pad),       \
+                       dim3(256), 0, st, g.ni, g.ng, g.no, nrt, ntiles, pad, (const float2*)occ, \
+                       (const float2*)psi, (float*)Z);                                           \
+    return hipGetLastError();                                                                    \
+  }
+  EXX_GKB(1, 1, 1)
+  EXX_GKB(2, 2, 2)
+  EXX_GKB(2, 1, 1)
+  EXX_GKB(1, 2, 1)
+  EXX_GKB(1, 1, 2)
+  EXX_GKB(2, 2, 1)
+#undef EXX_GKB
+  return hipErrorInvalidValue;
+}
 
 template hipError_t launch_kcorr<double>(const Geom&, const Tables&, const void*, void*, int,
                                           const int32_t*, bool, hipStream_t, const int*, int);

@@ -453,6 +453,123 @@ hipError_t zgemm_nn_grid(int M, int N, int K, int batch, const void* A, long lda
   return run_nn_tile<TB, TC, 0, 0>(tile, M, N, K, batch, A, lda, sA, B, ldb, sB, C, ldc, sC, st);
 }
 
+namespace {
+typedef __bf16 gb_bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short gb_u16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ gb_bf16x8 gb_as_bf16(gb_u16x8 v) {
+  gb_bf16x8 r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+
+// BF16 matrix-core form of cgemm_nn_mfma32 with conj(B): v_mfma_f32_16x16x32_bf16,
+// a k-step of 32 with lane group lk = lane/16 holding k = 8 lk .. 8 lk + 7 of its
+// row of A and column of B (the same pairing on both operands), operands
+// rounded to bfloat16 at load, FP32 accumulation. Wave tile WM x WN blocks,
+// workgroup 2 x 2 waves, XCD-contiguous tile order as zgemm_nn_mfma.
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void cgemm_nn_bf16(int M, int N, int K, int nrt, long ntiles,
+                                                     long ntiles_pad,
+                                                     const double2* __restrict__ A, long lda,
+                                                     long sA, const float2* __restrict__ B,
+                                                     long ldb, long sB, float2* __restrict__ C,
+                                                     long ldc, long sC) {
+  const long t = xcd_remap(blockIdx.x, ntiles_pad);
+  if (t >= ntiles) return;
+  const int rt = (int)(t % nrt);
+  const long ct = t / nrt;
+  const long b = blockIdx.y;
+  A += b * sA;
+  B += b * sB;
+  C += b * sC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = rt * (2 * WM * 16) + (wave & 1) * (WM * 16);
+  const long col0 = ct * (2 * WN * 16) + (wave >> 1) * (WN * 16);
+  f4 are[WM][WN], aim[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) are[i][j] = aim[i][j] = f4{0, 0, 0, 0};
+  long arow[WM], bcol[WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    const int r = row0 + i * 16 + li;
+    arow[i] = (long)(r < M ? r : M - 1) * lda;
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long c = col0 + j * 16 + li;
+    bcol[j] = c < N ? c : N - 1;
+  }
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int kb = k0 + 8 * lk;
+    gb_u16x8 br[WN], bi[WN];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = min(kb + e, K - 1);  // the A side is zero past K
+        const float2 v = B[(long)k * ldb + bcol[j]];
+        br[j][e] = bf16_rne(v.x);
+        bi[j][e] = bf16_rne(v.y);
+      }
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      gb_u16x8 ar, ai, nar;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kb + e;
+        const double2 v = k < K ? A[arow[i] + k] : make_double2(0.0, 0.0);
+        ar[e] = bf16_rne((float)v.x);
+        ai[e] = bf16_rne((float)v.y);
+        nar[e] = ar[e] ^ 0x8000u;
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        // C = A conj(B): Re += ar br + ai bi, Im += ai br - ar bi
+        are[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb_as_bf16(ar), gb_as_bf16(br[j]),
+                                                            are[i][j], 0, 0, 0);
+        are[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb_as_bf16(ai), gb_as_bf16(bi[j]),
+                                                            are[i][j], 0, 0, 0);
+        aim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb_as_bf16(ai), gb_as_bf16(br[j]),
+                                                            aim[i][j], 0, 0, 0);
+        aim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gb_as_bf16(nar), gb_as_bf16(bi[j]),
+                                                            aim[i][j], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + i * 16 + 4 * lk + v;
+      if (r >= M) continue;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const long c = col0 + j * 16 + li;
+        if (c < N) C[(long)r * ldc + c] = make_float2(are[i][j][v], aim[i][j][v]);
+      }
+    }
+}
+}  // namespace
+
+hipError_t cgemm_nn_grid_bf16(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                              const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                              hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (!offsets_fit(M, N, K, lda, ldb)) return hipErrorInvalidValue;
+  constexpr int WM = 2, WN = 2;
+  const int nrt = (M + 2 * WM * 16 - 1) / (2 * WM * 16);
+  const long nct = ((long)N + 2 * WN * 16 - 1) / (2 * WN * 16);
+  const long ntiles = nrt * nct;
+  const long pad = (ntiles + NXCD - 1) / NXCD * NXCD;
+  hipLaunchKernelGGL((cgemm_nn_bf16<WM, WN>), dim3((unsigned)pad, batch), dim3(256), 0, st, M, N,
+                     K, nrt, ntiles, pad, (const double2*)A, lda, sA, (const float2*)B, ldb, sB,
+                     (float2*)C, ldc, sC);
+  return hipGetLastError();
+}
+
 hipError_t cgemm_nn_grid32(int M, int N, int K, int batch, const void* A, long lda, long sA,
                           bool conjB, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                           hipStream_t st) {

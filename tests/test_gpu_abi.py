@@ -40,7 +40,7 @@ def test_bad_arguments_are_rejected(gpu):
     assert _fit(exx, h, _cell(exx), exx.EXX_F64, null=True) == -1
     assert _fit(exx, h, _cell(exx, grid=(12, 12, 7)), exx.EXX_F64) == -2
     assert _fit(exx, h, _cell(exx, kmesh=(5, 1, 1)), exx.EXX_F64) == -7
-    assert _fit(exx, h, _cell(exx), exx.EXX_BF16) == -7
+    assert _fit(exx, h, _cell(exx), exx.EXX_BF16) == 0  # built in: Gamma on the BF16 cores
     assert _fit(exx, h, _cell(exx, ni=2049), exx.EXX_F64) == -2
     assert _fit(exx, h, _cell(exx), 9) == -1
     msg = exx._lib.exx_last_error(h.raw).decode()

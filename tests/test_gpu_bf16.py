@@ -1,0 +1,105 @@
+"""EXX_BF16: the grid-sized fit GEMM Gamma^n on the BF16 matrix cores (operands
+rounded to bfloat16 at load, FP32 accumulation), everything else as EXX_F32.
+
+* Kernel check: a BF16 build on inputs that are already bfloat16 values equals
+  the F32 build (FP32 matrix cores, FP32 accumulation) on the same inputs to
+  FP32 accumulation level, on the real path (2x2x1), the paired path (3x2x1,
+  3x3x3) and the Gamma point; and differs from the F32 build on the raw inputs
+  (the BF16 rounding is really applied).
+* Error against the FP64 oracle: the 2^-9 relative rounding of Gamma's
+  operands makes Z inconsistent with the FP64 metric, and the fit amplifies that
+  by the metric's conditioning. On the small random cells with cond(S) <= 1e4
+  it is reported and only sanity-bounded (rel |dE_x| <= 5e-2, rel max|dK| <= 1;
+  measured 2e-3 .. 1.2e-2 and 1.4e-2 .. 0.41); on the ill-conditioned ones
+  (26% in E_x at cond 2e6) the mode is not usable. The meaningful bound is on
+  the full-size ring cell (test_gpu_full3.py: rel |dE_x| 4.4e-6, max|dK| 4.2e-3
+  of max|K|).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import select, thc
+
+from gpu_helpers import inputs, run_gpu
+from test_gpu_parity import CELLS, _cond
+
+pytestmark = pytest.mark.gpu
+
+def bf16_round(x):
+    """Round float32 values to the nearest bfloat16 (ties to even), kept in float32."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+def bf16_complex(z, dtype):
+    re = bf16_round(z.real.astype(np.float32))
+    im = bf16_round(z.imag.astype(np.float32))
+    return (re.astype(np.float64) + 1j * im.astype(np.float64)).astype(dtype)
+
+
+def _run(cell, psi, pts, ao, prec, occ=None):
+    """Fused build through the C ABI; occ overrides the orbital values at the points."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, len(pts))
+    if occ is None:
+        occ = np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))
+    nk, na = cell.N_k, cell.n_ao
+    t_psi = torch.from_numpy(psi.astype(np.complex64)).to(dev)
+    K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+    exx.exx_build(h, c, exx.PREC[prec], t_psi, torch.from_numpy(occ).to(dev),
+                  torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+                  torch.from_numpy(np.asarray(pts, dtype=np.int32)).to(dev), K, Ex, rank)
+    torch.cuda.synchronize()
+    return K.cpu().numpy(), float(Ex.cpu()[0]), rank.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["gamma-config1", "k221", "k321", "k333", "tiny-k222"])
+def test_bf16_gamma_equals_fp32_on_bf16_inputs(name, gpu):
+    cell = CELLS[name]()
+    base = inputs(cell)
+    pts, _ = select.select_points(base["psi"], cell.n_isdf)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    psi_r = bf16_complex(base["psi"], np.complex64)
+    occ_r = bf16_complex(np.ascontiguousarray(np.transpose(base["psi"][:, :, pts], (0, 2, 1))),
+                         np.complex128)
+    Kb, Eb, rb = _run(cell, psi_r, pts, ao, "bf16", occ=occ_r)
+    Kf, Ef, rf = _run(cell, psi_r, pts, ao, "f32", occ=occ_r)
+    K0, E0, _ = _run(cell, base["psi"], pts, ao, "f32")
+    dK = np.abs(Kb - Kf).max() / np.abs(Kf).max()
+    dE = abs(Eb - Ef) / abs(Ef)
+    shift = abs(Eb - E0) / abs(E0)
+    print(f"{name}: bf16 vs f32 on bf16 inputs rel dE {dE:.2e} rel dK {dK:.2e}; "
+          f"bf16 rounding moves E_x by {shift:.2e}")
+    assert np.array_equal(rb, rf)
+    assert dE <= 1e-6 and dK <= 1e-4
+    assert shift > 1e-6
+
+
+@pytest.mark.parametrize("name", ["gamma-config1", "k311", "tiny-k211", "tiny-k222"])
+def test_bf16_error_against_oracle(name, gpu):
+    cell = CELLS[name]()
+    base = inputs(cell)
+    pts, _ = select.select_points(base["psi"], cell.n_isdf)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    o = thc.thc_oo_k(cell.L, cell.grid, cell.kmesh, base["psi"], pts, ao)
+    g = run_gpu(cell, base["psi"], pts, ao, "bf16", stages=False)
+    cond = _cond(o)
+    dE = abs(g["Ex"] - o["Ex"]) / abs(o["Ex"])
+    dK = np.abs(g["K"] - o["K"]).max() / np.abs(o["K"]).max()
+    print(f"{name}: bf16 cond {cond:.2e} rel dE {dE:.2e} rel dK {dK:.2e} "
+          f"(|dEx| {abs(g['Ex'] - o['Ex']):.2e} Ha)")
+    assert np.array_equal(g["rank"], o["rank"])
+    assert cond <= 1e4
+    assert dE <= 5e-2
+    assert dK <= 1.0

@@ -137,3 +137,19 @@ def test_config3_fused_build_matches_stages(full3):
     assert rank_f.cpu().tolist() == rank_s.cpu().tolist()
     assert dK <= 2 * tol and dE <= 2 * tol
 
+
+
+def test_config3_bf16_error_report(full3):
+    """EXX_BF16 (Gamma on the BF16 matrix cores) at full size against the oracle:
+    the error is reported and bounded (about five times the measured values); it
+    is not within the 1e-5 / 1e-6 target, which EXX_MIXED and EXX_F32 meet."""
+    gold = full3["gold"]
+    K, E = _build(full3, "bf16")
+    Kref = gold["K"]
+    dK = float(np.abs(K - Kref).max())
+    dE = abs(E - gold["Ex"])
+    print(f"config3 bf16: |dEx| {dE:.3e} Ha/cell (rel {dE / abs(gold['Ex']):.2e}) max|dK| {dK:.3e} "
+          f"(rel {dK / np.abs(Kref).max():.2e})")
+    # measured: rel |dE_x| 4.4e-6, rel max|dK| 4.2e-3
+    assert dE <= 2e-5 * abs(gold["Ex"])
+    assert dK <= 2e-2 * np.abs(Kref).max()
