@@ -482,15 +482,22 @@ def bench_select5(args):
         exx.exx_select_points(h, c, psi64, pts, npiv)
         return pts
 
-    def learned():
+    # the fallback threshold for the 1e-5 Ha/cell fitted-exchange target, from
+    # the calibration of the probe residual against the fitted-exchange error
+    tau = mlp.tau_for(w, no)
+
+    def learned(tau=tau):
         pts = torch.empty((ni,), dtype=torch.int32, device=dev)
-        used, resid = exx.exx_select_points_mlp(h, c, psi64, w["norm"], theta, w["tau"],
+        used, resid = exx.exx_select_points_mlp(h, c, psi64, w["norm"], theta, tau,
                                                 int(w["n_probe"]), pts)
         return pts, used, resid
 
     learned()
     (pm, used, resid), t_mlp = timed(learned, 3)
-    log(f"[select5] learned selection {t_mlp * 1e3:.1f} ms (fallback {used}, residual {resid:.4f})")
+    log(f"[select5] learned selection at the 1e-5 Ha/cell target (tau {tau:.2e}): "
+        f"{t_mlp * 1e3:.1f} ms (fallback {used}, residual {resid:.4f})")
+    # the network's own points (no fallback), for the comparison below
+    (pn, _, resid_n), t_net = timed(lambda: learned(float("inf")), 3)
     pq, t_qrcp = timed(qrcp, 1)
     log(f"[select5] QRCP selection {t_qrcp * 1e3:.1f} ms")
     r = torch.empty((1,), dtype=torch.float64, device=dev)
@@ -514,9 +521,13 @@ def bench_select5(args):
         return float(Ex.cpu()[0]), t
 
     ex_m, tb_m = build(pm)
-    log(f"[select5] K-build (f32) at learned points {tb_m * 1e3:.1f} ms, E_x {ex_m:.8f}")
+    log(f"[select5] K-build (f32) at the selected points {tb_m * 1e3:.1f} ms, E_x {ex_m:.8f}")
+    ex_n, tb_n = build(pn)
+    log(f"[select5] K-build (f32) at the network's points {tb_n * 1e3:.1f} ms, E_x {ex_n:.8f}")
     ex_q, tb_q = build(pq)
     log(f"[select5] K-build (f32) at QRCP points {tb_q * 1e3:.1f} ms, E_x {ex_q:.8f}")
+    pred_n = mlp.predicted_dex(w, no, resid_n)
+    pred_q = mlp.predicted_dex(w, no, resid_q)
     out = {
         "metric": "end-to-end s: point selection + one K-build (all k), learned vs QRCP",
         "value": t_mlp + tb_m,
@@ -528,11 +539,18 @@ def bench_select5(args):
         "data": "synthetic",
         "config": {"workload": "48-atom four-ring cell, 4x4x4 k-mesh, 2s+2p (N=384), n_occ=84, "
                                "grid 72x90x64, N_ISDF=420", "N_k": nk, "N_g": ng},
+        "target_dEx_Ha_per_cell": mlp.TARGET_DEX,
+        "tau": tau,
         "learned": {"select_s": t_mlp, "build_s": tb_m, "Ex": ex_m, "probe_residual": resid,
                     "fallback": used},
-        "qrcp": {"select_s": t_qrcp, "build_s": tb_q, "Ex": ex_q, "probe_residual": resid_q},
+        "network_points": {"select_s": t_net, "build_s": tb_n, "Ex": ex_n,
+                           "probe_residual": resid_n, "predicted_dEx": pred_n,
+                           "meets_target": bool(pred_n <= mlp.TARGET_DEX)},
+        "qrcp": {"select_s": t_qrcp, "build_s": tb_q, "Ex": ex_q, "probe_residual": resid_q,
+                 "predicted_dEx": pred_q, "meets_target": bool(pred_q <= mlp.TARGET_DEX)},
         "end_to_end_speedup": (t_qrcp + tb_q) / (t_mlp + tb_m),
-        "dEx_learned_vs_qrcp": ex_m - ex_q,
+        "end_to_end_speedup_network_points": (t_qrcp + tb_q) / (t_net + tb_n),
+        "dEx_network_vs_qrcp": ex_n - ex_q,
     }
     print(json.dumps(out), flush=True)
 

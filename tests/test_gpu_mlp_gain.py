@@ -104,7 +104,7 @@ def test_learned_selection_is_faster_than_qrcp(env, gpu):
     torch, exx, mlp, dev, h, w, theta, theta0 = env
     cd = mlp.CellData(mlp.training_cell(193), dev)  # 40 atoms, 2x2x2, N_ISDF 350
     cd.qrcp(h)
-    cd.select(h, w["norm"], theta, w["tau"])
+    cd.select(h, w["norm"], theta, float("inf"))
     torch.cuda.synchronize()
     tq, tm = [], []
     for _ in range(3):
@@ -119,3 +119,42 @@ def test_learned_selection_is_faster_than_qrcp(env, gpu):
     print(f"selection time: QRCP {1e3 * np.median(tq):.1f} ms, learned {1e3 * np.median(tm):.1f} ms")
     assert not used
     assert np.median(tm) < 0.5 * np.median(tq)
+
+
+def test_calibration_predicts_the_fitted_exchange_error(env, gpu):
+    """The fallback's calibration dE / n_occ = a r^b (fitted on other cells)
+    predicts the fitted-exchange error of the QRCP and the learned points on two
+    unseen Gamma cells within a factor 3, with the error measured against the
+    full-pair-rank build of the same cell (exact exchange)."""
+    torch, exx, mlp, dev, h, w, theta, theta0 = env
+    for i in (228, 232):
+        assert i not in mlp.CAL_CELLS
+        base = mlp.CellData(mlp.training_cell(i), dev)
+        no = base.cell.n_occ
+        full = base.resized(no * no)
+        e_full = full.exchange_energy(h, full.qrcp(h))
+        for tag, pts in (("qrcp", base.qrcp(h)),
+                         ("learned", base.select(h, w["norm"], theta, float("inf"))[0])):
+            r = base.probe(h, pts)
+            de = base.exchange_energy(h, pts) - e_full
+            pred = mlp.predicted_dex(w, no, r)
+            print(f"cell {i} {tag}: resid {r:.4e}, dE_x {de:.4e} Ha, predicted {pred:.4e} Ha")
+            assert de > 0  # the fit is variational: it never overshoots exact exchange
+            assert pred / 3.0 <= de <= 3.0 * pred
+
+
+def test_fallback_fires_at_the_accuracy_target(env, gpu):
+    """At the 1e-5 Ha/cell fitted-exchange target the calibrated threshold is far
+    below any residual reachable with N_ISDF = 5 n_occ, so the selector falls back
+    to QRCP and returns exactly the QRCP points; with an infinite threshold it
+    keeps its own."""
+    torch, exx, mlp, dev, h, w, theta, theta0 = env
+    cd = mlp.CellData(mlp.training_cell(192), dev)
+    tau = mlp.tau_for(w, cd.cell.n_occ)
+    q = cd.qrcp(h)
+    pts, used, resid = cd.select(h, w["norm"], theta, tau)
+    print(f"tau(1e-5 Ha/cell, n_occ {cd.cell.n_occ}) = {tau:.3e}; learned residual {resid:.3e}")
+    assert used and resid > tau
+    assert torch.equal(pts, q)
+    pts2, used2, _ = cd.select(h, w["norm"], theta, float("inf"))
+    assert not used2 and not torch.equal(pts2, q)
