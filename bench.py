@@ -257,7 +257,7 @@ def ring_leg(config, args, h, exx, torch, dev):
                           t["ao_pts"], t["pts"], o["K"], o["Ex"], o["rank"])
 
         s = time_steps(step, max(1, args.steps), max(1, args.warmup), torch)
-        h.set_timing(True)
+        h.set_timing(True, serial=True)
         step()
         torch.cuda.synchronize()
         ph = {k: v[0] for k, v in h.phase_times().items()}
@@ -374,10 +374,11 @@ def batch_leg(args, h, exx, torch, dev):
         seq_r.update({"max_dEx_vs_oracle": max(seq_err[0]), "max_dK_vs_oracle": max(seq_err[1])})
 
     # per-phase event times of every cell's build (one untimed pass, same kernels
-    # and shapes as the batch) and the matching work counts
+    # and shapes as the batch, the normally overlapping phases run one after
+    # another so that each interval covers its own kernels) and the work counts
     phase_ms, wex, wsv, units = {}, {}, {}, {}
     its = its_by_prec["mixed"]
-    h.set_timing(True)
+    h.set_timing(True, serial=True)
     for c, it in zip(cells, its):
         exx.exx_build(h, it["cell"], exx.EXX_MIXED, it["psi_grid"], it["occ_pts"], it["ao_pts"],
                       it["pts"], it["K"], it["Ex"], it["rank"])

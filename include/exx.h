@@ -93,10 +93,11 @@ typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 } exx_prec;
 typedef struct {
   double L[3];       /* orthorhombic cell edges, bohr */
   int32_t grid[3];   /* n1, n2, n3: each 2..128, 2*3*5-smooth, n2*n3 <= 6144 */
-  int32_t kmesh[3];  /* N1, N2, N3: one of the shapes whose k-correlation is
-                        compiled in -- 1x1x1, 2x2x2, 3x3x3, 4x4x4, 2x1x1, 1x2x1,
-                        1x1x2, 2x2x1, 3x1x1, 3x2x1, 1x2x3; any other shape
-                        returns EXX_ERR_UNSUPPORTED */
+  int32_t kmesh[3];  /* N1, N2, N3: each 1..8, N1 N2 N3 <= 64. The k-correlation
+                        of 1x1x1, 2x2x2, 3x3x3, 4x4x4, 2x1x1, 1x2x1, 1x1x2,
+                        2x2x1, 2x1x2, 1x2x2, 3x1x1, 3x2x1 and 1x2x3 runs on
+                        register-resident k-mesh DFTs; other meshes take a
+                        direct-sum kernel (same results, slower) */
   int32_t n_occ;     /* occupied orbitals per k, 1..512 */
   int32_t n_ao;      /* basis functions per k, 1..4096 */
   int32_t n_isdf;    /* interpolation points, 1..2048 */
@@ -472,6 +473,11 @@ exx_status exx_set_refinement(exx_handle_t h, int32_t steps);
  * events and returns, per phase, the summed elapsed milliseconds and the
  * number of recorded intervals since timing was enabled or last read, then
  * resets the counters.
+ *
+ * enable = 2 also runs the phases that normally overlap on the build's two
+ * streams (the factorisation chain beside Gamma, each chunk's transform beside
+ * the previous chunk's contraction) one after another, so that every phase's
+ * interval covers its own kernels only (slower builds; for per-kernel rates).
  *
  * Phases: 0 G^n, 1 S^m, 2 Cholesky, 3 S^+ (triangular inverse and W^H W),
  * 4 Gamma^n, 5 Z^m k-correlation, 6 fit solve, 7 grid FFT, 8 Coulomb

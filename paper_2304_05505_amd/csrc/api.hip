@@ -155,7 +155,7 @@ exx_status check_cell(exx_context* h, const exx_cell* c, exx_prec prec) {
   if (c->n_isdf < 1 || c->n_isdf > 2048) return fail(h, EXX_ERR_SHAPE, "n_isdf must be 1..2048");
   Geom g = make_geom(*c);
   if (g.ni > g.ng) return fail(h, EXX_ERR_SHAPE, "n_isdf exceeds the number of grid points");
-  if (!kcorr_supported(g)) return fail(h, EXX_ERR_UNSUPPORTED, "k-mesh shape not built in");
+  if (!kcorr_supported(g)) return fail(h, EXX_ERR_SHAPE, "the k-mesh may hold at most 64 points");
   if (!fft_supported(g, prec == EXX_F64))
     return fail(h, EXX_ERR_UNSUPPORTED, "grid shape not supported by the FFT (n2*n3 <= 6144)");
   return EXX_OK;
@@ -297,6 +297,15 @@ hipError_t make_lane_streams(hipStream_t* aux, hipEvent_t* fork, hipEvent_t* joi
   return e;
 }
 
+// serial timing (exx_set_timing(h, 2)): `after` waits for everything queued so
+// far on `before`, so that two phases on different streams do not overlap
+hipError_t serialize(exx_context* h, hipStream_t before, hipStream_t after) {
+  if (!(h->timing && h->serial)) return hipSuccess;
+  hipError_t e = hipEventRecord(h->join_ev, before);
+  if (e == hipSuccess) e = hipStreamWaitEvent(after, h->join_ev, 0);
+  return e;
+}
+
 // status word for the kernels' reports (null when no check is enabled)
 int32_t* stat_ptr(exx_context* h) {
   return (h->checks & (EXX_CHECK_FINITE | EXX_STRICT_PD)) ? h->dstat : nullptr;
@@ -349,6 +358,7 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
   double2* Sp = (double2*)(ws + L.Sp);
+  double2* WH = (double2*)(ws + L.Y);  // W^H (the K-build's Y region is free during a fit)
   int32_t* keep = (int32_t*)(ws + L.keep);
   void* grid = ws + L.grid;
   const long nn = (long)g.ni * g.ni;
@@ -396,6 +406,10 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
                                                g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
       if (e != hipSuccess) what = "S+ gemm";
     }
+    if (!what) {
+      e = launch_conj_transpose(W, WH, g.ni, g.ni, g.nk, 1.0, ax);
+      if (e != hipSuccess) what = "W^H";
+    }
   }
   // join back into st even after an error, so that st never runs ahead of the
   // chain (and a capture stays joined)
@@ -429,7 +443,27 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   hipError_t ew = hipStreamWaitEvent(st, h->join_ev, 0);
   if (what) return hip_check(h, e, what);
   if (ew != hipSuccess) return hip_check(h, ew, "join wait");
-  // a4: xi^m = S^+ Z^m, FP64 arithmetic
+  // a4: xi^m = S^+ Z^m in FP64 arithmetic. Without refinement it is applied in
+  // the factor form xi = W^H (W Z) (S^+ = W^H W): Y = W Z into xi, then W^H Y
+  // into the Z buffer and back into xi. Applying the explicitly formed S^+
+  // instead squares the metric's conditioning in the rounding error, which
+  // loses every digit where Z lies close to the range of a metric with
+  // cond 1e9 (a fit at full pair rank). With refinement the explicit S^+ is
+  // applied and then refined below.
+  if (h->refine == 0) {
+    PhaseTimer pt(h, PH_SOLVE, st);
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, W, g.ni, nn, false, grid, g.ng,
+                              (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve,
+                              true);
+    if (e == hipSuccess)
+      e = zgemm_nn_grid<TX, TF>(g.ni, g.ng, g.ni, g.nk, WH, g.ni, nn, false, xi, g.ng,
+                                (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, st,
+                                h->tile_solve);
+    if (e == hipSuccess)
+      e = launch_convert<TF, TX>(grid, xi, (long)g.nk * g.ni * g.ng, st);
+    if (e != hipSuccess) return hip_check(h, e, "solve gemm");
+    return EXX_OK;
+  }
   {
     PhaseTimer pt(h, PH_SOLVE, st);
     e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, false, grid, g.ng,
@@ -547,6 +581,8 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     (void)hipStreamWaitEvent(st, h->join_ev, 0);
     return hip_check(h, e, what);
   }
+  e = serialize(h, ax, gs);
+  if (e != hipSuccess) return hip_check(h, e, "serial timing");
   if constexpr (std::is_same<TF, float>::value) {
     // FP32: Gamma^n and the real k-correlation in one pass; only Z~ is written.
     // occ is narrowed to c64 first, into the K-build's scratch (free until then)
@@ -633,6 +669,7 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
           e = launch_coulomb<TX>(g, tb, (const char*)grid2 + c0 * fout, pts, ws + L.cpart,
                                  L.nsplit, (double2*)V, true, gs, rep, nullptr, cn, false);
         if (!what && e != hipSuccess) what = "coulomb";
+        if (!what && serialize(h, gs, st) != hipSuccess) what = "serial timing";
       }
     }
     tc.reset();
@@ -740,6 +777,10 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   }
   // the fit, one chunk of grid columns at a time; the first chunk's Gamma and Z
   // run beside the factorisation chain, every solve waits for it
+  if (h->timing && h->serial) {
+    e = hipStreamWaitEvent(gs, h->chain_ev, 0);
+    if (e != hipSuccess) what = "serial timing";
+  }
   for (int c0 = 0; c0 < g.ng && !what; c0 += cc) {
     const int cn = std::min(cc, g.ng - c0);
     const char* psi_c = (const char*)psi + (size_t)c0 * sizeof(cplx<TF>);
@@ -829,6 +870,10 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
       if (!what) {
         e = hipEventRecord(h->fb_ev[b], gs);
         if (e != hipSuccess) what = "buffer event";
+      }
+      if (!what && h->timing && h->serial) {
+        e = hipStreamWaitEvent(st, h->fb_ev[b], 0);
+        if (e != hipSuccess) what = "serial timing";
       }
     }
   }
@@ -1273,6 +1318,7 @@ exx_status exx_set_timing(exx_handle_t h, int enable) {
   }
   h->recs.clear();
   h->timing = enable != 0;
+  h->serial = enable == 2;
   return EXX_OK;
 }
 

@@ -270,6 +270,24 @@ hipError_t launch_check_finite(const double* p, long n, int32_t* status, int sit
   return hipGetLastError();
 }
 
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void convert_kernel(const cplx<TS>* __restrict__ src,
+                                                      cplx<TD>* __restrict__ dst, long n) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) dst[e] = mk<TD>((TD)src[e].x, (TD)src[e].y);
+}
+
+template <typename TS, typename TD>
+hipError_t launch_convert(const void* src, void* dst, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((convert_kernel<TS, TD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (const cplx<TS>*)src, (cplx<TD>*)dst, n);
+  return hipGetLastError();
+}
+template hipError_t launch_convert<double, double>(const void*, void*, long, hipStream_t);
+template hipError_t launch_convert<double, float>(const void*, void*, long, hipStream_t);
+template hipError_t launch_convert<float, float>(const void*, void*, long, hipStream_t);
+
 hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, src, n);

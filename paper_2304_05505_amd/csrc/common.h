@@ -166,6 +166,10 @@ struct exx_context {
   std::vector<GraphEntry> graphs;
   // per-phase timing: recorded (phase, start, stop) events and a free pool
   bool timing = false;
+  // with timing: run the phases that normally overlap (factorisation chain and
+  // Gamma; transform and contraction chunks) one after another, so that each
+  // phase's events bracket its own kernels only
+  bool serial = false;
   struct Rec {
     int phase;
     hipEvent_t a, b;
@@ -347,6 +351,9 @@ hipError_t cgemm_nn_grid_bf16(int M, int N, int K, int batch, const void* A, lon
 
 // dst[0:n] = src[0:n] (a kernel, so that captured sequences hold no copy nodes)
 hipError_t launch_copy(double2* dst, const double2* src, long n, hipStream_t st);
+// dst[0:n] = src[0:n] for complex arrays, converting storage TS to TD
+template <typename TS, typename TD>
+hipError_t launch_convert(const void* src, void* dst, long n, hipStream_t st);
 // rank[rep[s]] = rc[s], and rank[bar[s]] = rc[s] where bar[s] >= 0 (host lists, n <= 64)
 hipError_t launch_rank_scatter(const int32_t* rc, int32_t* rank, const int* rep, const int* bar,
                                int n, hipStream_t st);

@@ -533,12 +533,58 @@ __global__ __launch_bounds__(256) void gamma_kcorr_bf16_kernel(int ni, int ng, i
   X(3, 2, 1)              \
   X(1, 2, 3)
 
-bool kcorr_supported(const Geom& g) {
+// meshes with a compile-time kernel (register-resident k-mesh DFTs); any other
+// mesh of at most 64 points takes kcorr_direct_kernel
+static bool kcorr_compiled(const Geom& g) {
 #define EXX_KSUP(a, b, c) \
   if (g.N[0] == a && g.N[1] == b && g.N[2] == c) return true;
   EXX_KMESH_LIST(EXX_KSUP)
 #undef EXX_KSUP
   return false;
+}
+
+bool kcorr_supported(const Geom& g) { return g.nk >= 1 && g.nk <= 64; }
+
+// Any mesh of at most 64 points: the k-correlation by its direct sum,
+// out[slot[m]][P][c] = e^{i q_m.(r_P - r_c)} sum_n in[n][P][c] conj in[n+m][P][c]
+// (n + m per axis mod N). Each thread first copies its element of every slice
+// (in and out may alias, as in kcorr_kernel), then forms the N_k sums.
+template <typename T>
+__global__ __launch_bounds__(256) void kcorr_direct_kernel(const cplx<T>* in, cplx<T>* out, int ni,
+                                                           int ncol, const int32_t* __restrict__ pts,
+                                                           int cols_are_points, KcorrArgs ka) {
+  const int N1 = ka.N[0], N2 = ka.N[1], N3 = ka.N[2];
+  const int nk = N1 * N2 * N3;
+  const long total = (long)ni * ncol;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int P = (int)(idx / ncol);
+  const int c = (int)(idx % ncol);
+  cplx<T> a[64];
+  for (int n = 0; n < nk; ++n) a[n] = in[(long)n * total + idx];
+  const int n23 = ka.n[1] * ka.n[2];
+  const int gp = pts[P];
+  const int p1 = gp / n23, p2 = (gp / ka.n[2]) % ka.n[1], p3 = gp % ka.n[2];
+  const int gc = cols_are_points ? pts[c] : ka.col0 + c;
+  const int c1 = gc / n23, c2 = (gc / ka.n[2]) % ka.n[1], c3 = gc % ka.n[2];
+  for (int m = 0; m < nk; ++m) {
+    const int sm = ka.slot[m];
+    if (sm < 0) continue;
+    const int m1 = m / (N2 * N3), m2 = (m / N3) % N2, m3 = m % N3;
+    cplx<T> v = mk<T>(0, 0);
+    for (int n = 0; n < nk; ++n) {
+      const int n1 = n / (N2 * N3), n2 = (n / N3) % N2, n3 = n % N3;
+      const int q = (((n1 + m1) % N1) * N2 + (n2 + m2) % N2) * N3 + (n3 + m3) % N3;
+      v = cadd<T>(v, cmulc<T>(a[n], a[q]));
+    }
+    if (m) {
+      double2 fp = bloch(ka.root, ka.n, ka.N, m1, m2, m3, p1, p2, p3);  // e^{-iq.r_P}
+      double2 fc = bloch(ka.root, ka.n, ka.N, m1, m2, m3, c1, c2, c3);  // e^{-iq.r_c}
+      double2 ph = make_double2(fp.x * fc.x + fp.y * fc.y, fp.x * fc.y - fp.y * fc.x);
+      v = cmul<T>(v, mk<T>((T)ph.x, (T)ph.y));
+    }
+    out[(long)sm * total + idx] = v;
+  }
 }
 
 template <typename T>
@@ -563,6 +609,11 @@ hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* o
   }
   EXX_KMESH_LIST(EXX_KLAUNCH)
 #undef EXX_KLAUNCH
+  if (!kcorr_compiled(g) && kcorr_supported(g)) {
+    hipLaunchKernelGGL((kcorr_direct_kernel<T>), grid, dim3(256), 0, st, (const cplx<T>*)in,
+                       (cplx<T>*)out, g.ni, ncol, pts, cols_are_points ? 1 : 0, ka);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 bool kcorr_real(const Geom& g) { return g.N[0] <= 2 && g.N[1] <= 2 && g.N[2] <= 2; }
@@ -585,6 +636,8 @@ hipError_t launch_kcorr_real(const Geom& g, const void* in, void* out, int ncol,
   EXX_KRLAUNCH(1, 2, 1)
   EXX_KRLAUNCH(1, 1, 2)
   EXX_KRLAUNCH(2, 2, 1)
+  EXX_KRLAUNCH(2, 1, 2)
+  EXX_KRLAUNCH(1, 2, 2)
 #undef EXX_KRLAUNCH
   return hipErrorInvalidValue;
 }
@@ -634,6 +687,8 @@ hipError_t launch_gamma_kcorr(const Geom& g, const void* occ, const void* psi, v
   EXX_GKLAUNCH(1, 2, 1)
   EXX_GKLAUNCH(1, 1, 2)
   EXX_GKLAUNCH(2, 2, 1)
+  EXX_GKLAUNCH(2, 1, 2)
+  EXX_GKLAUNCH(1, 2, 2)
 #undef EXX_GKLAUNCH
   return hipErrorInvalidValue;
 }
@@ -660,6 +715,8 @@ hipError_t launch_gamma_kcorr_bf16(const Geom& g, const void* occ, const void* p
   EXX_GKB(1, 2, 1)
   EXX_GKB(1, 1, 2)
   EXX_GKB(2, 2, 1)
+  EXX_GKB(2, 1, 2)
+  EXX_GKB(1, 2, 2)
 #undef EXX_GKB
   return hipErrorInvalidValue;
 }

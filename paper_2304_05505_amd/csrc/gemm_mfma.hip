@@ -789,5 +789,8 @@ template hipError_t zgemm_nn_grid<float, float>(int, int, int, int, const void*,
 template hipError_t zgemm_nn_grid<double, float>(int, int, int, int, const void*, long, long, bool,
                                                  const void*, long, long, void*, long, long,
                                                  hipStream_t, int, bool);
+template hipError_t zgemm_nn_grid<float, double>(int, int, int, int, const void*, long, long, bool,
+                                                 const void*, long, long, void*, long, long,
+                                                 hipStream_t, int, bool);
 
 }  // namespace exx

@@ -239,8 +239,10 @@ class Handle:
         """Steps (0 or 1) of iterative refinement after every fit solve of this handle."""
         self._check(_lib.exx_set_refinement(self._h, int(steps)))
 
-    def set_timing(self, enable: bool):
-        self._check(_lib.exx_set_timing(self._h, 1 if enable else 0))
+    def set_timing(self, enable: bool, serial: bool = False):
+        """Per-phase HIP events; serial also runs the normally overlapping phases one
+        after another (exx_set_timing(h, 2))."""
+        self._check(_lib.exx_set_timing(self._h, (2 if serial else 1) if enable else 0))
 
     def phase_times(self) -> dict:
         """{phase: (total_ms, calls)} since timing was enabled or last read."""

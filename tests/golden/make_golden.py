@@ -9,6 +9,9 @@ Runs only the FP64 oracle (``oracle/``) on the seeded inputs from ``synth``:
 * ``config3.json`` + ``config3_K.npz``: the same cell on the 3x3x3 mesh, all
   27 transfers: E_x (three forms), ranks and cond(S^m) of every transfer,
   seeded samples of S^m and Vb^m for m = 0, 13, 26, and the whole K^k.
+* ``config5.json`` + ``config5_K.npz``: the 4x4x4 ring cell with 2s + 2p per atom
+  (N = 384, n_occ = 84, grid 72x90x64, N_ISDF = 420), all 64 transfers: E_x,
+  ranks, cond(S^m), every diagonal of K and 4000 seeded entries.
 * ``config4.json`` + ``config4_K.npz``: the 24 cells of the batched workload
   (2 x {8, 16, 24, 48 atoms} x {1^3, 2^3, 3^3}), each with its own oracle
   points: E_x (two forms), ranks, cond(S^m), the diagonal of every K^k and
@@ -16,9 +19,10 @@ Runs only the FP64 oracle (``oracle/``) on the seeded inputs from ``synth``:
 
 Each ``.npz`` holds plain complex128 arrays (no pickled objects).
 
-Usage: ``python tests/golden/make_golden.py [config2] [config3] [config4]``.
+Usage: ``python tests/golden/make_golden.py [config2] [config3] [config4] [config5]``.
 Wall times on 8 cores: config2 a few minutes (~25 GB RAM), config3 about
-twenty minutes (~30 GB), config4 about an hour (~30 GB).
+half an hour (~30 GB), config4 about an hour (~30 GB), config5 a few hours
+(~50 GB).
 """
 
 from __future__ import annotations
@@ -186,11 +190,54 @@ def make_config4(path):
     print(f"wrote {path}", flush=True)
 
 
+def make_config5(path):
+    """The 4x4x4 ring cell with the 2s + 2p basis (N = 384, n_occ = 84, grid
+    72x90x64, N_ISDF = 420): oracle points, E_x (two forms), ranks, cond(S^m),
+    the diagonal of every K^k and 4000 seeded entries of K."""
+    t0 = time.time()
+    c = synth.make_config(5)
+    C = synth.orbital_coeffs(c)
+    psi = synth.orbitals_on_grid(c, C)
+    pts, npiv = select.select_points(psi, c.n_isdf)
+    print(f"config5: points selected ({npiv} pivots) in {time.time() - t0:.0f} s", flush=True)
+    ao = np.stack([synth.ao_at_points(c, n, pts) for n in range(c.N_k)])
+    t1 = time.time()
+    o = thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao)
+    t_build = time.time() - t1
+    rng = np.random.default_rng(20230408)
+    nk, na = c.N_k, c.n_ao
+    kn = rng.integers(0, nk, 4000)
+    kmu = rng.integers(0, na, 4000)
+    knu = rng.integers(0, na, 4000)
+    out = {
+        "workload": "48-atom four-ring cell, 4x4x4 mesh, 2s+2p basis N=384, n_occ=84, grid "
+                    "72x90x64, N_ISDF=420",
+        "seed": list(c.seed),
+        "pts": [int(x) for x in pts],
+        "n_pivot": int(npiv),
+        "Ex": o["Ex"],
+        "Ex_trVS": o["Ex_trVS"],
+        "rank": [int(x) for x in o["rank"]],
+        "cond_S": _conds(o, nk),
+        "maxabs_K": float(np.abs(o["K"]).max()),
+        "oracle_build_s": t_build,
+    }
+    with open(path, "w") as f:
+        json.dump(out, f)
+    np.savez_compressed(path.replace(".json", "_K.npz"),
+                        idx=np.stack([kn, kmu, knu], axis=1).astype(np.int32),
+                        val=o["K"][kn, kmu, knu],
+                        diag=np.stack([np.diagonal(o["K"][n]) for n in range(nk)]))
+    print(f"wrote {path}: Ex={o['Ex']:.12f}, oracle build {t_build:.0f} s", flush=True)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["config2", "config3", "config4"]
+    which = sys.argv[1:] or ["config2", "config3", "config4", "config5"]
     if "config2" in which:
         make_config2(os.path.join(HERE, "config2.json"))
     if "config3" in which:
         make_config3(os.path.join(HERE, "config3.json"))
     if "config4" in which:
         make_config4(os.path.join(HERE, "config4.json"))
+    if "config5" in which:
+        make_config5(os.path.join(HERE, "config5.json"))

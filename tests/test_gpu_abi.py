@@ -39,7 +39,7 @@ def test_bad_arguments_are_rejected(gpu):
     h = exx.Handle(0)
     assert _fit(exx, h, _cell(exx), exx.EXX_F64, null=True) == -1
     assert _fit(exx, h, _cell(exx, grid=(12, 12, 7)), exx.EXX_F64) == -2
-    assert _fit(exx, h, _cell(exx, kmesh=(5, 1, 1)), exx.EXX_F64) == -7
+    assert _fit(exx, h, _cell(exx, kmesh=(8, 8, 2)), exx.EXX_F64) == -2  # 128 k-points
     assert _fit(exx, h, _cell(exx), exx.EXX_BF16) == 0  # built in: Gamma on the BF16 cores
     assert _fit(exx, h, _cell(exx, ni=2049), exx.EXX_F64) == -2
     assert _fit(exx, h, _cell(exx), 9) == -1
