@@ -19,8 +19,8 @@ F32 and F64 and the single-cell builds of the 48-atom four-ring cell on the
 every precision, each against its stored oracle K and E_x.
 
 Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --profile
-(one batch per precision, one 3x3x3 build per precision and a 1 GiB copy, no
-JSON); --workload rings-k2 | rings-k3 | select-k4 print a single leg.
+(the mixed batch twice and a 1 GiB copy, no JSON: the profiler's target);
+--workload rings-k2 | rings-k3 | select-k4 print a single leg.
 """
 
 from __future__ import annotations
@@ -557,8 +557,10 @@ def bench_select5(args):
 
 
 def profile_target(args):
-    """One batch per precision, one 3x3x3 ring build per precision and a plain
-    1 GiB device copy (whose counter readings calibrate the traffic counters)."""
+    """The headline step for a profiler: the 24-cell batch in the mixed mode on
+    concurrent lanes (after one untimed warm-up batch, which also tunes the tiles),
+    then a plain 1 GiB device copy whose counter readings calibrate the traffic
+    counters."""
     import torch
 
     import synth
@@ -570,26 +572,14 @@ def profile_target(args):
     gold = load_json("config4.json")
     base = [cell_inputs(h, exx, torch, c, dev, pts=gold["cells"][i]["pts"] if gold else None)
             for i, c in enumerate(cells)]
-    stream = torch.cuda.Stream()
-    for prec in ("mixed", "f32", "f64"):
-        its = [dict(cell=t["cell"], psi_grid=psi_for(t, prec, torch), occ_pts=t["occ_pts"],
-                    ao_pts=t["ao_pts"], pts=t["pts"], **outputs(torch, c, dev))
-               for c, t in zip(cells, base)]
-        stream.wait_stream(torch.cuda.current_stream())
-        exx.exx_build_batched(h, its, exx.PREC[prec], exx.EXX_BATCH_GRAPH | exx.EXX_BATCH_TUNE,
-                              stream=stream)
-        stream.synchronize()
-        log(f"profile target: batch {prec} done")
-    del base
-    cell = synth.make_config(3)
-    g3 = load_json("config3.json")
-    t = cell_inputs(h, exx, torch, cell, dev, pts=g3["pts"] if g3 else None)
-    for prec in ("f64", "mixed", "f32"):
-        o = outputs(torch, cell, dev)
-        exx.exx_build(h, t["cell"], exx.PREC[prec], psi_for(t, prec, torch), t["occ_pts"],
-                      t["ao_pts"], t["pts"], o["K"], o["Ex"], o["rank"])
+    its = [dict(cell=t["cell"], psi_grid=psi_for(t, "mixed", torch), occ_pts=t["occ_pts"],
+                ao_pts=t["ao_pts"], pts=t["pts"], **outputs(torch, c, dev))
+           for c, t in zip(cells, base)]
+    for rep in range(2):
+        exx.exx_build_batched(h, its, exx.EXX_MIXED,
+                              exx.EXX_BATCH_CONCURRENT | exx.EXX_BATCH_TUNE)
         torch.cuda.synchronize()
-        log(f"profile target: 3x3x3 {prec} done")
+        log(f"profile target: mixed batch {rep} done")
     src = torch.ones((1 << 27,), dtype=torch.float64, device=dev)  # 1 GiB
     dst = torch.empty_like(src)
     dst.copy_(src)

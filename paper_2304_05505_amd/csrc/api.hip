@@ -651,28 +651,28 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     const int per = (g.nk + nchunk - 1) / nchunk;
     const size_t fin = (size_t)g.ni * g.ng * sizeof(TX);  // solved functions per transfer
     const size_t fout = (size_t)g.ni * g.n[0] * g.n[1] * (g.n[2] / 2 + 1) * sizeof(cplx<TX>);
-    std::optional<PhaseTimer> tc;
-    {
-      PhaseTimer pt(h, PH_FFT, st);
-      for (int c0 = 0; c0 < g.nk && !what; c0 += per) {
-        const int cn = std::min(per, g.nk - c0);
+    // timed per launch, so that serial timing gives each phase its own kernels
+    for (int c0 = 0; c0 < g.nk && !what; c0 += per) {
+      const int cn = std::min(per, g.nk - c0);
+      {
+        PhaseTimer pt(h, PH_FFT, st);
         e = launch_fft3d_half<TX, TX>(g, tb, (const char*)grid + c0 * fin,
                                       (char*)grid2 + c0 * fout, (long)cn * g.ni, c0, h->ncu, st);
-        if (e != hipSuccess) what = "fft";
-        if (!what) e = hipEventRecord(h->fork_ev, st);
-        if (!what && e == hipSuccess) e = hipStreamWaitEvent(gs, h->fork_ev, 0);
-        if (!what && e != hipSuccess) what = "chunk fork";
-        if (!what && !tc) tc.emplace(h, PH_COULOMB, gs);
-        int rep[64];
-        for (int m = 0; m < cn; ++m) rep[m] = c0 + m;
-        if (!what)
-          e = launch_coulomb<TX>(g, tb, (const char*)grid2 + c0 * fout, pts, ws + L.cpart,
-                                 L.nsplit, (double2*)V, true, gs, rep, nullptr, cn, false);
-        if (!what && e != hipSuccess) what = "coulomb";
-        if (!what && serialize(h, gs, st) != hipSuccess) what = "serial timing";
       }
+      if (e != hipSuccess) what = "fft";
+      if (!what) e = hipEventRecord(h->fork_ev, st);
+      if (!what && e == hipSuccess) e = hipStreamWaitEvent(gs, h->fork_ev, 0);
+      if (!what && e != hipSuccess) what = "chunk fork";
+      int rep[64];
+      for (int m = 0; m < cn; ++m) rep[m] = c0 + m;
+      if (!what) {
+        PhaseTimer pt(h, PH_COULOMB, gs);
+        e = launch_coulomb<TX>(g, tb, (const char*)grid2 + c0 * fout, pts, ws + L.cpart,
+                               L.nsplit, (double2*)V, true, gs, rep, nullptr, cn, false);
+      }
+      if (!what && e != hipSuccess) what = "coulomb";
+      if (!what && serialize(h, gs, st) != hipSuccess) what = "serial timing";
     }
-    tc.reset();
     ej = hipEventRecord(h->join_ev, gs);
     ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
     if (what) return hip_check(h, e, what);
@@ -843,8 +843,7 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   const int per = L.pd.per;
   const size_t fb = (size_t)g.ni * g.ng * sizeof(cplx<TX>);  // functions of one slice
   {
-    std::optional<PhaseTimer> tc;
-    PhaseTimer pt(h, PH_FFT, st);
+    // timed per launch, so that serial timing gives each phase its own kernels
     int chunk = 0;
     for (int s0 = 0; s0 < gr.nk && !what; s0 += per, ++chunk) {
       const int cn = std::min(per, gr.nk - s0);
@@ -857,15 +856,19 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
           break;
         }
       }
-      e = launch_fft3d<TX>(g, tb, xi + s0 * fb, F, (long)cn * g.ni, h->ncu, st);
+      {
+        PhaseTimer pt(h, PH_FFT, st);
+        e = launch_fft3d<TX>(g, tb, xi + s0 * fb, F, (long)cn * g.ni, h->ncu, st);
+      }
       if (e != hipSuccess) what = "fft";
       if (!what) e = hipEventRecord(h->fork_ev, st);
       if (!what && e == hipSuccess) e = hipStreamWaitEvent(gs, h->fork_ev, 0);
       if (!what && e != hipSuccess) what = "chunk fork";
-      if (!what && !tc) tc.emplace(h, PH_COULOMB, gs);
-      if (!what)
+      if (!what) {
+        PhaseTimer pt(h, PH_COULOMB, gs);
         e = launch_coulomb<TX>(g, tb, F, pts, ws + L.cpart, L.nsplit, Vy + (long)s0 * nn, false, gs,
                                pr.rep + s0, pr.bar + s0, cn, true);
+      }
       if (!what && e != hipSuccess) what = "coulomb";
       if (!what) {
         e = hipEventRecord(h->fb_ev[b], gs);

@@ -144,14 +144,23 @@ __device__ __forceinline__ void kdft3(cplx<T>* a) {
   kdft_axis<T, N1, N2, N3, 0>(a);
 }
 
-// e^{-i q_m . r} for grid coordinates (g1, g2, g3), transfer (m1, m2, m3)
-__device__ __forceinline__ double2 bloch(const double2* const* root, const int* nn, const int* NN,
-                                         int m1, int m2, int m3, int g1, int g2, int g3) {
-  double2 p = root[0][(m1 * g1) % (NN[0] * nn[0])];
-  double2 b = root[1][(m2 * g2) % (NN[1] * nn[1])];
-  double2 c = root[2][(m3 * g3) % (NN[2] * nn[2])];
-  double2 pb = make_double2(p.x * b.x - p.y * b.y, p.x * b.y + p.y * b.x);
-  return make_double2(pb.x * c.x - pb.y * c.y, pb.x * c.y + pb.y * c.x);
+// the Bloch phases of a (point, column) element for every transfer of an
+// N1 x N2 x N3 mesh: e^{i q_m.(r_P - r_c)} = prod_a w_a^{m_a} with
+// w_a = conj(root_a[p_a]) root_a[c_a] (root_a[t] = e^{-2 pi i t/(N_a n_a)}, so
+// root_a[m_a t mod N_a n_a] = root_a[t]^{m_a}); pw[a][j] = w_a^j, j < N_a.
+// Three table reads per position instead of three per transfer.
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <int NMAX>
+__device__ __forceinline__ void axis_powers(const double2* root, int pa, int ca, int Na, double2* pw) {
+  const double2 rp = root[pa], rc = root[ca];
+  const double2 w = make_double2(rp.x * rc.x + rp.y * rc.y, rp.x * rc.y - rp.y * rc.x);
+  pw[0] = make_double2(1.0, 0.0);
+#pragma unroll
+  for (int j = 1; j < NMAX; ++j)
+    if (j < Na) pw[j] = zmul(pw[j - 1], w);
 }
 
 struct KcorrArgs {
@@ -196,19 +205,21 @@ __global__ __launch_bounds__(256) void kcorr_kernel(const cplx<T>* in, cplx<T>* 
   int p1 = gp / n23, p2 = (gp / ka.n[2]) % ka.n[1], p3 = gp % ka.n[2];
   int gc = cols_are_points ? pts[c] : ka.col0 + c;
   int c1 = gc / n23, c2 = (gc / ka.n[2]) % ka.n[1], c3 = gc % ka.n[2];
+  double2 w1[N1], w2[N2], w3[N3];
+  axis_powers<N1>(ka.root[0], p1, c1, N1, w1);
+  axis_powers<N2>(ka.root[1], p2, c2, N2, w2);
+  axis_powers<N3>(ka.root[2], p3, c3, N3, w3);
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
     const int m1 = m / (N2 * N3), m2 = (m / N3) % N2, m3 = m % N3;
+    const int sm = ka.slot[m];
+    if (sm < 0) continue;
     cplx<T> v = cscale<T>(a[m], inv);
     if (m) {
-      double2 fp = bloch(ka.root, ka.n, ka.N, m1, m2, m3, p1, p2, p3);  // e^{-iq.r_P}
-      double2 fc = bloch(ka.root, ka.n, ka.N, m1, m2, m3, c1, c2, c3);  // e^{-iq.r_c}
-      // e^{iq.(r_P - r_c)} = conj(fp) * fc
-      double2 ph = make_double2(fp.x * fc.x + fp.y * fc.y, fp.x * fc.y - fp.y * fc.x);
+      const double2 ph = zmul(zmul(w1[m1], w2[m2]), w3[m3]);  // e^{iq.(r_P - r_c)}
       v = cmul<T>(v, mk<T>((T)ph.x, (T)ph.y));
     }
-    const int sm = ka.slot[m];
-    if (sm >= 0) out[(long)sm * total + idx] = v;
+    out[(long)sm * total + idx] = v;
   }
 }
 
@@ -567,6 +578,10 @@ __global__ __launch_bounds__(256) void kcorr_direct_kernel(const cplx<T>* in, cp
   const int p1 = gp / n23, p2 = (gp / ka.n[2]) % ka.n[1], p3 = gp % ka.n[2];
   const int gc = cols_are_points ? pts[c] : ka.col0 + c;
   const int c1 = gc / n23, c2 = (gc / ka.n[2]) % ka.n[1], c3 = gc % ka.n[2];
+  double2 w1[8], w2[8], w3[8];  // mesh axes are at most 8 points long
+  axis_powers<8>(ka.root[0], p1, c1, N1, w1);
+  axis_powers<8>(ka.root[1], p2, c2, N2, w2);
+  axis_powers<8>(ka.root[2], p3, c3, N3, w3);
   for (int m = 0; m < nk; ++m) {
     const int sm = ka.slot[m];
     if (sm < 0) continue;
@@ -578,9 +593,7 @@ __global__ __launch_bounds__(256) void kcorr_direct_kernel(const cplx<T>* in, cp
       v = cadd<T>(v, cmulc<T>(a[n], a[q]));
     }
     if (m) {
-      double2 fp = bloch(ka.root, ka.n, ka.N, m1, m2, m3, p1, p2, p3);  // e^{-iq.r_P}
-      double2 fc = bloch(ka.root, ka.n, ka.N, m1, m2, m3, c1, c2, c3);  // e^{-iq.r_c}
-      double2 ph = make_double2(fp.x * fc.x + fp.y * fc.y, fp.x * fc.y - fp.y * fc.x);
+      const double2 ph = zmul(zmul(w1[m1], w2[m2]), w3[m3]);  // e^{iq.(r_P - r_c)}
       v = cmul<T>(v, mk<T>((T)ph.x, (T)ph.y));
     }
     out[(long)sm * total + idx] = v;
