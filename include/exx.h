@@ -85,9 +85,11 @@ typedef enum {
  *   EXX_BF16   as EXX_F32, but the grid-sized fit GEMM Gamma^n runs on the
  *              BF16 matrix cores: occ_pts and psi_grid (c64) are rounded to
  *              bfloat16 (nearest even) as they are loaded, FP32 accumulation,
- *              Gamma kept in FP32. psi_grid and xi are c64. Its error is that
- *              of 8-bit significands amplified by the metric's conditioning
- *              (reported, not within the 1e-5 / 1e-6 accuracy target). */
+ *              Gamma kept in FP32; and the Coulomb contraction runs on the
+ *              BF16 matrix cores (EXX_CONTRACT_BF16, exx_set_contraction).
+ *              psi_grid and xi are c64. Its error is that of 8-bit
+ *              significands amplified by the metric's conditioning (reported,
+ *              not within the 1e-5 / 1e-6 accuracy target). */
 typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 } exx_prec;
 
 typedef struct {
@@ -465,6 +467,32 @@ exx_status exx_load_tuning(exx_handle_t h, const char* path);
  * confined to the retained points like the solve.
  */
 exx_status exx_set_refinement(exx_handle_t h, int32_t steps);
+
+/*
+ * exx_set_contraction -- arithmetic of the Coulomb contraction
+ *   V^m_PQ = (Omega/N_g^2) sum_g v^m(g) F_P(g) conj F_Q(g)
+ * (Sec. 2.2, Eq. 15; the step the paper finds rate-limiting) in every later
+ * build and exx_coulomb_V call of this handle whose transforms F are stored in
+ * FP32 (EXX_MIXED, EXX_F32, EXX_BF16):
+ *   EXX_CONTRACT_AUTO    (default) EXX_CONTRACT_BF16 in EXX_BF16, else
+ *                        EXX_CONTRACT_F64;
+ *   EXX_CONTRACT_F64     FP64 matrix cores, FP32 operands widened exactly,
+ *                        FP64 accumulation;
+ *   EXX_CONTRACT_BF16    BF16 matrix cores: v F_P formed in FP32, both operands
+ *                        rounded to bfloat16 (nearest even), FP32 accumulation
+ *                        over at most 256 grid points, added into FP64;
+ *   EXX_CONTRACT_BF16X3  BF16 matrix cores on split operands x = hi + lo
+ *                        (hi = bf16(x), lo = bf16(x - hi), 16 significant
+ *                        bits), three products hi hi + hi lo + lo hi per term,
+ *                        accumulation as EXX_CONTRACT_BF16.
+ * EXX_F64 builds (FP64-stored transforms) return EXX_ERR_UNSUPPORTED while a
+ * BF16 form is set. Returns EXX_ERR_ARG for an unknown form.
+ */
+#define EXX_CONTRACT_AUTO 0
+#define EXX_CONTRACT_F64 1
+#define EXX_CONTRACT_BF16 2
+#define EXX_CONTRACT_BF16X3 3
+exx_status exx_set_contraction(exx_handle_t h, int32_t form);
 
 /*
  * Per-phase timing (instrumentation, not part of the method). When enabled,

@@ -140,6 +140,23 @@ bool smooth235(int n) {
   return n == 1;
 }
 
+// the contraction form of a call in precision prec (COUL_*), or -1 where the
+// handle asks for a BF16 form on FP64-stored transforms
+int coul_form(const exx_context* h, exx_prec prec) {
+  int f = h->contract;
+  if (f == EXX_CONTRACT_AUTO) f = prec == EXX_BF16 ? EXX_CONTRACT_BF16 : EXX_CONTRACT_F64;
+  if (f == EXX_CONTRACT_F64) return COUL_F64;
+  if (prec == EXX_F64) return -1;
+  return f == EXX_CONTRACT_BF16 ? COUL_BF16 : COUL_BF16X3;
+}
+
+exx_status check_form(exx_context* h, exx_prec prec) {
+  if (coul_form(h, prec) < 0)
+    return fail(h, EXX_ERR_UNSUPPORTED,
+                "a BF16 contraction form needs FP32-stored transforms (not EXX_F64)");
+  return EXX_OK;
+}
+
 exx_status check_cell(exx_context* h, const exx_cell* c, exx_prec prec) {
   if (!c) return fail(h, EXX_ERR_ARG, "cell is NULL");
   if (prec != EXX_F64 && prec != EXX_F32 && prec != EXX_BF16 && prec != EXX_MIXED)
@@ -484,10 +501,11 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   return EXX_OK;
 }
 
-// T: storage of xi and F; the contraction runs on the FP64 matrix cores either way
+// T: storage of xi and F; cform: the contraction's form (COUL_*; FP32 storage only)
 template <typename T>
 exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
-                        const void* xi, const int32_t* pts, void* V, hipStream_t st) {
+                        const void* xi, const int32_t* pts, void* V, hipStream_t st,
+                        int cform = COUL_F64) {
   void* F = ws + L.grid;
   hipError_t e;
   {
@@ -497,7 +515,8 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {
     PhaseTimer pt(h, PH_COULOMB, st);
-    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st);
+    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st, nullptr,
+                          nullptr, 0, false, cform);
   }
   if (e != hipSuccess) return hip_check(h, e, "coulomb");
   return EXX_OK;
@@ -526,7 +545,8 @@ exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* w
 template <typename TF, typename TZ, typename TX>
 exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                             const Layout& L, const void* psi, const void* occ, const int32_t* pts,
-                            void* S, void* V, int32_t* rank, hipStream_t st, bool bf16 = false) {
+                            void* S, void* V, int32_t* rank, hipStream_t st, bool bf16 = false,
+                            int cform = COUL_F64) {
   double2* G = (double2*)(ws + L.G);
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
@@ -645,7 +665,8 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
     }
     if (e != hipSuccess) return hip_check(h, e, "fft");
     PhaseTimer pt(h, PH_COULOMB, st);
-    e = launch_coulomb<TX>(g, tb, grid2, pts, ws + L.cpart, L.nsplit, (double2*)V, true, st);
+    e = launch_coulomb<TX>(g, tb, grid2, pts, ws + L.cpart, L.nsplit, (double2*)V, true, st,
+                           nullptr, nullptr, 0, false, cform);
     if (e != hipSuccess) return hip_check(h, e, "coulomb");
   } else {
     const int per = (g.nk + nchunk - 1) / nchunk;
@@ -668,7 +689,7 @@ exx_status fit_coulomb_real(exx_context* h, const Geom& g, const Tables& tb, cha
       if (!what) {
         PhaseTimer pt(h, PH_COULOMB, gs);
         e = launch_coulomb<TX>(g, tb, (const char*)grid2 + c0 * fout, pts, ws + L.cpart,
-                               L.nsplit, (double2*)V, true, gs, rep, nullptr, cn, false);
+                               L.nsplit, (double2*)V, true, gs, rep, nullptr, cn, false, cform);
       }
       if (!what && e != hipSuccess) what = "coulomb";
       if (!what && serialize(h, gs, st) != hipSuccess) what = "serial timing";
@@ -710,7 +731,7 @@ template <typename TF, typename TX>
 exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                              const Layout& L, const Pairs& pr, const void* psi, const void* occ,
                              const int32_t* pts, void* V, int32_t* rank, hipStream_t st,
-                             bool bf16 = false) {
+                             bool bf16 = false, int cform = COUL_F64) {
   double2* G = (double2*)(ws + L.G);
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
@@ -867,7 +888,7 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
       if (!what) {
         PhaseTimer pt(h, PH_COULOMB, gs);
         e = launch_coulomb<TX>(g, tb, F, pts, ws + L.cpart, L.nsplit, Vy + (long)s0 * nn, false, gs,
-                               pr.rep + s0, pr.bar + s0, cn, true);
+                               pr.rep + s0, pr.bar + s0, cn, true, cform);
       }
       if (!what && e != hipSuccess) what = "coulomb";
       if (!what) {
@@ -911,13 +932,17 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
   void* V = ws + L.V2;
   exx_status s;
   const Pairs pr = make_pairs(g);
+  const int cf = coul_form(h, prec);
+  if (cf < 0) return check_form(h, prec);
+  const bool bf = prec == EXX_BF16;
   if (!kcorr_real(g) && pr.n < g.nk) {
     if (prec == EXX_F64)
       return fit_coulomb_pairs<double, double>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
     if (prec == EXX_MIXED)
-      return fit_coulomb_pairs<double, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
-    return fit_coulomb_pairs<float, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st,
-                                           prec == EXX_BF16);
+      return fit_coulomb_pairs<double, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st,
+                                              false, cf);
+    return fit_coulomb_pairs<float, float>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st, bf,
+                                           cf);
   }
   if (kcorr_real(g)) {
     if (prec == EXX_F64)
@@ -925,19 +950,19 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
                                                       st);
     if (prec == EXX_MIXED)
       return fit_coulomb_real<double, double, float>(h, g, tb, ws, L, psi, occ, pts, S, V, rank,
-                                                     st);
+                                                     st, false, cf);
     return fit_coulomb_real<float, float, float>(h, g, tb, ws, L, psi, occ, pts, S, V, rank, st,
-                                                 prec == EXX_BF16);
+                                                 bf, cf);
   }
   if (prec == EXX_F64) {
     s = fit_impl<double, double>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st);
     if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, st);
   } else if (prec == EXX_MIXED) {
     s = fit_impl<double, float>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, st);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, st, cf);
   } else {
-    s = fit_impl<float, float>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st, prec == EXX_BF16);
-    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, st);
+    s = fit_impl<float, float>(h, g, tb, ws, L, psi, occ, pts, xi, S, rank, st, bf);
+    if (s == EXX_OK) s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, st, cf);
   }
   return s;
 }
@@ -1145,12 +1170,13 @@ exx_status exx_coulomb_V(exx_handle_t h, const exx_cell* cell, exx_prec prec, co
   Tables tb;
   Layout L;
   char* ws;
+  if (cell && check_form(h, prec) != EXX_OK) return EXX_ERR_UNSUPPORTED;
   exx_status s = setup(h, cell, prec, NEED_COULOMB, &g, &tb, &L, &ws, stream);
   if (s != EXX_OK) return s;
   if (prec == EXX_F64)
     s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, V, stream);
   else
-    s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream);
+    s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, V, stream, coul_form(h, prec));
   if (s == EXX_OK) s = scan(h, V, 2L * g.nk * g.ni * g.ni, SITE_COULOMB, stream);
   return s == EXX_OK ? finish(h, stream) : s;
 }
@@ -1182,6 +1208,7 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   h->err.clear();
   if (!psi_grid || !occ_pts || !ao_pts || !pts || !K || !Ex || !rank)
     return fail(h, EXX_ERR_ARG, "exx_build: null array argument");
+  if (cell && check_form(h, prec) != EXX_OK) return EXX_ERR_UNSUPPORTED;
   Geom g;
   Tables tb;
   Layout L;
@@ -1308,6 +1335,15 @@ exx_status exx_set_refinement(exx_handle_t h, int32_t steps) {
   h->err.clear();
   if (steps < 0 || steps > 1) return fail(h, EXX_ERR_ARG, "exx_set_refinement: steps must be 0 or 1");
   h->refine = steps;
+  return EXX_OK;
+}
+
+exx_status exx_set_contraction(exx_handle_t h, int32_t form) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (form < EXX_CONTRACT_AUTO || form > EXX_CONTRACT_BF16X3)
+    return fail(h, EXX_ERR_ARG, "exx_set_contraction: unknown form");
+  h->contract = form;
   return EXX_OK;
 }
 
@@ -1525,6 +1561,7 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   if (flags & ~(EXX_BATCH_GRAPH | EXX_BATCH_TUNE | EXX_BATCH_CONCURRENT))
     return fail(h, EXX_ERR_ARG, "exx_build_batched: unknown flag");
   if (n == 0) return EXX_OK;
+  if (check_form(h, prec) != EXX_OK) return EXX_ERR_UNSUPPORTED;
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
   if (!h->aux) {
@@ -1629,10 +1666,11 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
     return s == EXX_OK ? finish(h, stream) : s;
   }
 
-  // signature: precision, refinement, checks, lane plan and scratch, every item field
+  // signature: precision, refinement, contraction form, checks, lane plan and scratch, every item field
   std::vector<long> sig;
   sig.push_back((long)prec);
   sig.push_back((long)h->refine);
+  sig.push_back((long)h->contract);
   sig.push_back((long)h->checks);
   sig.push_back((long)L);
   sig.push_back((long)(size_t)ws0);

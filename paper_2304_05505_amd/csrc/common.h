@@ -129,6 +129,7 @@ struct exx_context {
   int tile_solve = 22;
   // steps of iterative refinement after the fit solve (0 or 1)
   int refine = 0;
+  int contract = 0;  // EXX_CONTRACT_* of the Coulomb contraction
   // second stream (default priority) for the point-metric chain of the fit,
   // which overlaps the grid-sized Gamma and Z; fork/join events
   hipStream_t aux = nullptr;
@@ -393,7 +394,10 @@ hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, vo
                              int m0, int ncu, hipStream_t st);
 int fft_half_z(const Geom& g);
 
-// Coulomb contraction: V^m (Bloch gauge) from F^m (storage T) on the FP64 matrix cores;
+// Coulomb contraction: V^m (Bloch gauge) from F^m (storage T) on the FP64 matrix cores,
+// or with FP32 storage on the BF16 matrix cores (form COUL_BF16: operands rounded to
+// bfloat16; COUL_BF16X3: split hi + lo operands, three products), FP32 accumulation
+// over at most 256 points added into FP64;
 // half: F is the real path's half-grid transform (launch_fft3d_half)
 // rep/bar/nslice (host arrays): F holds nslice transfers, slice s being transfer
 // rep[s]; V[rep[s]] is written and, where bar[s] >= 0, V[bar[s]] = conj V[rep[s]]
@@ -405,7 +409,8 @@ template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
                           void* partial, int nsplit, double2* V, bool half, hipStream_t st,
                           const int* rep = nullptr, const int* bar = nullptr, int nslice = 0,
-                          bool raw = false);
+                          bool raw = false, int form = 0);
+enum { COUL_F64 = 0, COUL_BF16 = 1, COUL_BF16X3 = 2 };
 // V[rep[s]] = e^{-i q_m.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and, where
 // bar[s] >= 0, V[bar[s]] = conj of that; U holds nslice (<= 64) matrices
 hipError_t launch_coulomb_phase(const Geom& g, const Tables& tb, const int32_t* pts,

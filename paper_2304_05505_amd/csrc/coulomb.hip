@@ -487,6 +487,266 @@ __global__ __launch_bounds__(64) void coulomb_kernel_t64(const cplx<T>* __restri
 #undef EXX_T64
 }
 
+// ---------------------------------------------------------------------------
+// BF16 matrix-core forms (FP32-stored transforms). v_mfma_f32_16x16x32_bf16: a
+// k-step covers 16 complex grid points; lane group lk = lane / 16 holds points
+// g0 + 4 lk .. g0 + 4 lk + 3 of its row as k values (Re, Im, Re, Im, ...), the
+// same pairing on both operands, so that with X = v(g) F_P and Y = F_Q
+//   sum_k X_k Y_k   = sum_g Re X Re Y + Im X Im Y = Re(X conj Y),
+// and with the column operand rearranged per point to (-Im Y, Re Y)
+//   sum_k X_k Y'_k  = sum_g Im X Re Y - Re X Im Y = Im(X conj Y).
+// X is formed in FP32 and rounded to bfloat16 (ties to even). SPLIT: every
+// operand is carried as hi + lo with hi = bf16(x), lo = bf16(x - hi) (16
+// significant bits), and a product is hi hi + hi lo + lo hi (the dropped lo lo
+// term is ~2^-16 relative). The FP32 matrix accumulators are added into FP64
+// registers every BF_FLUSH k-steps (256 points) and zeroed, so no FP32 sum runs
+// over more than 256 points; the partial sums leave the kernel in FP64.
+// ---------------------------------------------------------------------------
+typedef __bf16 cb_bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short cb_u16x8 __attribute__((ext_vector_type(8)));
+typedef float cb_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ cb_bf16x8 cb_as_bf16(cb_u16x8 v) {
+  cb_bf16x8 r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+
+// x = hi + lo to 16 significant bits
+__device__ __forceinline__ void cb_split(float x, unsigned short& hi, unsigned short& lo) {
+  hi = bf16_rne(x);
+  lo = bf16_rne(x - __uint_as_float((unsigned)hi << 16));
+}
+
+constexpr int BF_FLUSH = 16;  // k-steps (of 16 points) per FP32 accumulation
+constexpr int BF_NPF = 2;     // k-steps of operands in flight in registers
+
+// lower-triangle 32 x 32 wave tile (MASK as coulomb_wave_tile) of transfer m and
+// grid chunk [g0, g1). VEC: N_g % 4 == 0, so a lane's four points of a row are
+// two aligned 16-byte loads, and a lane group's points are all inside or all
+// outside a chunk (chunks start at multiples of 64). Loads past the end of the
+// grid are clamped and their points get v = 0. RE: Re(X conj Y) only.
+template <int MASK, bool VEC, bool SPLIT, bool RE>
+__device__ __forceinline__ void coulomb_tile_bf16(const float2* __restrict__ Fm,
+                                                  const double* __restrict__ vm,
+                                                  double2* __restrict__ out, const CoulArgs& a,
+                                                  int P0, int Q0, long g0, long g1) {
+  constexpr bool DIAG = (MASK & 2) == 0;
+  constexpr bool XU[MW] = {(MASK & 3) != 0, (MASK & 12) != 0};
+  constexpr bool YU[MW] = {(MASK & 5) != 0, (MASK & 10) != 0};
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  unsigned xrow[MW], yrow[MW];
+#pragma unroll
+  for (int i = 0; i < MW; ++i) {
+    const int P = min(P0 + 16 * i + li, a.ni - 1), Q = min(Q0 + 16 * i + li, a.ni - 1);
+    xrow[i] = (unsigned)P * (unsigned)a.ng;
+    yrow[i] = (unsigned)Q * (unsigned)a.ng;
+  }
+  cb_f4 cre[MW][MW], cim[MW][MW];
+  double dre[MW][MW][4], dim[MW][MW][4];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+      cre[i][j] = cim[i][j] = cb_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dre[i][j][v] = dim[i][j][v] = 0.0;
+    }
+  float2 fx[BF_NPF][MW][4], fy[BF_NPF][MW][4];
+  double fv[BF_NPF][4];
+  auto load = [&](long k0, float2 (*xx)[4], float2 (*yy)[4], double* vv) {
+    const long gb = k0 + 4 * lk;
+    if constexpr (VEC) {
+      const unsigned g = (unsigned)min(gb, (long)a.ng - 4);
+      const double2 va = *(const double2*)(vm + g), vb = *(const double2*)(vm + g + 2);
+      vv[0] = va.x;
+      vv[1] = va.y;
+      vv[2] = vb.x;
+      vv[3] = vb.y;
+#pragma unroll
+      for (int i = 0; i < MW; ++i) {
+        if (DIAG ? (XU[i] || YU[i]) : XU[i]) {
+          const float4 q0 = *(const float4*)(Fm + xrow[i] + g);
+          const float4 q1 = *(const float4*)(Fm + xrow[i] + g + 2);
+          xx[i][0] = make_float2(q0.x, q0.y);
+          xx[i][1] = make_float2(q0.z, q0.w);
+          xx[i][2] = make_float2(q1.x, q1.y);
+          xx[i][3] = make_float2(q1.z, q1.w);
+        }
+        if (!DIAG && YU[i]) {
+          const float4 q0 = *(const float4*)(Fm + yrow[i] + g);
+          const float4 q1 = *(const float4*)(Fm + yrow[i] + g + 2);
+          yy[i][0] = make_float2(q0.x, q0.y);
+          yy[i][1] = make_float2(q0.z, q0.w);
+          yy[i][2] = make_float2(q1.x, q1.y);
+          yy[i][3] = make_float2(q1.z, q1.w);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const unsigned g = (unsigned)min(gb + t, (long)a.ng - 1);
+        vv[t] = vm[g];
+#pragma unroll
+        for (int i = 0; i < MW; ++i) {
+          if (DIAG ? (XU[i] || YU[i]) : XU[i]) xx[i][t] = Fm[xrow[i] + g];
+          if (!DIAG && YU[i]) yy[i][t] = Fm[yrow[i] + g];
+        }
+      }
+    }
+  };
+  auto step = [&](float2 (*xx)[4], float2 (*yy)[4], const double* vv, long gb) {
+    float w[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) w[t] = (gb + t < g1) ? (float)vv[t] : 0.f;
+    cb_u16x8 yh[MW], yl[MW], yhi[MW], yli[MW];
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+      if (!YU[j]) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float2 y = DIAG ? xx[j][t] : yy[j][t];
+        unsigned short rh, rl = 0, ih, il = 0;
+        if (SPLIT) {
+          cb_split(y.x, rh, rl);
+          cb_split(y.y, ih, il);
+        } else {
+          rh = bf16_rne(y.x);
+          ih = bf16_rne(y.y);
+        }
+        yh[j][2 * t] = rh;
+        yh[j][2 * t + 1] = ih;
+        yhi[j][2 * t] = ih ^ 0x8000u;
+        yhi[j][2 * t + 1] = rh;
+        if (SPLIT) {
+          yl[j][2 * t] = rl;
+          yl[j][2 * t + 1] = il;
+          yli[j][2 * t] = il ^ 0x8000u;
+          yli[j][2 * t + 1] = rl;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < MW; ++i) {
+      if (!XU[i]) continue;
+      cb_u16x8 xh, xl;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float xr = xx[i][t].x * w[t], xi = xx[i][t].y * w[t];
+        if (SPLIT) {
+          unsigned short h0, l0, h1, l1;
+          cb_split(xr, h0, l0);
+          cb_split(xi, h1, l1);
+          xh[2 * t] = h0;
+          xh[2 * t + 1] = h1;
+          xl[2 * t] = l0;
+          xl[2 * t + 1] = l1;
+        } else {
+          xh[2 * t] = bf16_rne(xr);
+          xh[2 * t + 1] = bf16_rne(xi);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < MW; ++j) {
+        if (!(MASK & (1 << (2 * i + j)))) continue;
+        cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cb_as_bf16(xh), cb_as_bf16(yh[j]),
+                                                            cre[i][j], 0, 0, 0);
+        if (SPLIT) {
+          cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cb_as_bf16(xh), cb_as_bf16(yl[j]),
+                                                              cre[i][j], 0, 0, 0);
+          cre[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cb_as_bf16(xl), cb_as_bf16(yh[j]),
+                                                              cre[i][j], 0, 0, 0);
+        }
+        if (!RE) {
+          cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cb_as_bf16(xh), cb_as_bf16(yhi[j]),
+                                                              cim[i][j], 0, 0, 0);
+          if (SPLIT) {
+            cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                cb_as_bf16(xh), cb_as_bf16(yli[j]), cim[i][j], 0, 0, 0);
+            cim[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                cb_as_bf16(xl), cb_as_bf16(yhi[j]), cim[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < MW; ++i)
+#pragma unroll
+      for (int j = 0; j < MW; ++j) {
+        if (!(MASK & (1 << (2 * i + j)))) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          dre[i][j][v] += (double)cre[i][j][v];
+          if (!RE) dim[i][j][v] += (double)cim[i][j][v];
+        }
+        cre[i][j] = cim[i][j] = cb_f4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  const long nstep = (g1 - g0 + 15) / 16;
+#pragma unroll
+  for (int sl = 0; sl < BF_NPF; ++sl) load(g0 + (long)sl * 16, fx[sl], fy[sl], fv[sl]);
+  for (long c = 0; c < nstep; c += BF_NPF) {
+#pragma unroll
+    for (int sl = 0; sl < BF_NPF; ++sl) {
+      const long k0 = g0 + (c + sl) * 16;
+      step(fx[sl], fy[sl], fv[sl], k0 + 4 * lk);
+      // refill the slot (clamped loads past the end are discarded by v = 0)
+      __builtin_amdgcn_sched_barrier(0);
+      load(k0 + BF_NPF * 16, fx[sl], fy[sl], fv[sl]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if ((c + BF_NPF) % BF_FLUSH == 0) flush();
+  }
+  flush();
+  // D layout: register v of a lane holds row 4 lk + v, column li of the block
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < MW; ++j) {
+      if (!(MASK & (1 << (2 * i + j)))) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int P = P0 + 16 * i + 4 * lk + v;
+        const int Q = Q0 + 16 * j + li;
+        if (P < a.ni && Q < a.ni)
+          out[(long)P * a.ni + Q] = make_double2(dre[i][j][v], RE ? 0.0 : dim[i][j][v]);
+      }
+    }
+}
+
+// one wave per 32 x 32 lower-triangle tile, as coulomb_kernel_f32
+template <bool VEC, bool SPLIT, bool RE>
+__global__ __launch_bounds__(64) void coulomb_kernel_bf16(const float2* __restrict__ F,
+                                                       const double* __restrict__ vt,
+                                                       double2* __restrict__ part, CoulArgs a,
+                                                       long nwork, long nwork_pad) {
+  const long w = (blockIdx.x % 8) * (nwork_pad / 8) + blockIdx.x / 8;
+  if (w >= nwork) return;
+  int m, s, ti, tj;
+  coulomb_work(w, a, m, s, ti, tj);
+  const int P0 = ti * WTILE, Q0 = tj * WTILE;
+  const long g0 = (long)s * a.chunk;
+  const long g1 = min((long)a.ng, g0 + a.chunk);
+  const float2* Fm = F + (long)m * a.ni * a.ng;
+  const double* vm = vt + (long)m * a.ng;
+  double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
+  const bool row1 = P0 + 16 < a.ni;
+  if (ti != tj) {
+    if (row1)
+      coulomb_tile_bf16<0xF, VEC, SPLIT, RE>(Fm, vm, out, a, P0, Q0, g0, g1);
+    else
+      coulomb_tile_bf16<0x3, VEC, SPLIT, RE>(Fm, vm, out, a, P0, Q0, g0, g1);
+  } else {
+    if (row1)
+      coulomb_tile_bf16<0xD, VEC, SPLIT, RE>(Fm, vm, out, a, P0, Q0, g0, g1);
+    else
+      coulomb_tile_bf16<0x1, VEC, SPLIT, RE>(Fm, vm, out, a, P0, Q0, g0, g1);
+  }
+}
+
 struct ReduceArgs {
   const double2* root[3];
   int n[3];
@@ -589,10 +849,12 @@ size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
 // half = false: F is [N_k][N_ISDF][N_g] (complex path). half = true (real
 // path): F is [N_k][N_ISDF][n1 n2 hz] with hz = n3/2 + 1, the contraction takes
 // the real part with the pairing weights, and the reduction applies no phase.
+// form (FP32 storage only): COUL_F64 on the FP64 matrix cores, COUL_BF16 or
+// COUL_BF16X3 on the BF16 matrix cores (coulomb_tile_bf16).
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
                           void* partial, int nsplit, double2* V, bool half, hipStream_t st,
-                          const int* rep, const int* bar, int nslice, bool raw) {
+                          const int* rep, const int* bar, int nslice, bool raw, int form) {
   CoulArgs a;
   const int ns = rep ? nslice : g.nk;
   for (int m = 0; m < 64; ++m) a.rep[m] = rep && m < ns ? rep[m] : m;
@@ -606,10 +868,14 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.ni = g.ni;
   a.nk = ns;
   const bool vec = a.ng % 2 == 0;
+  const bool bf = sizeof(T) == 4 && form != COUL_F64;
+  const bool split = form == COUL_BF16X3;
+  const bool vec4 = a.ng % 4 == 0;
   // complex path: FP64 storage on 64 x 64 workgroup tiles, FP32 storage on
   // 32 x 32 wave tiles; real path: 64 x 64 wave tiles (FP32 storage needs an even
-  // half grid for its 16-byte loads, else 32 x 32 wave tiles)
-  const bool t64 = half && (sizeof(T) == 8 || vec);
+  // half grid for its 16-byte loads, else 32 x 32 wave tiles); BF16 forms: 32 x 32
+  // wave tiles
+  const bool t64 = !bf && half && (sizeof(T) == 8 || vec);
   const int tw = (sizeof(T) == 8 || t64) ? 2 * WTILE : WTILE;
   const int nt = (g.ni + tw - 1) / tw;
   a.ntile = nt * (nt + 1) / 2;
@@ -620,7 +886,14 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   {
     const void* kfn;
     int threads = 64;
-    if (t64) {
+    if (bf) {
+#define EXX_BFK(V, S, R) (const void*)coulomb_kernel_bf16<V, S, R>
+      kfn = vec4 ? (split ? (half ? EXX_BFK(true, true, true) : EXX_BFK(true, true, false))
+                          : (half ? EXX_BFK(true, false, true) : EXX_BFK(true, false, false)))
+                 : (split ? (half ? EXX_BFK(false, true, true) : EXX_BFK(false, true, false))
+                          : (half ? EXX_BFK(false, false, true) : EXX_BFK(false, false, false)));
+#undef EXX_BFK
+    } else if (t64) {
       kfn = (const void*)coulomb_kernel_t64<T>;
     } else if (sizeof(T) == 8) {
       kfn = half ? (const void*)coulomb_kernel_f64<true> : (const void*)coulomb_kernel_f64<false>;
@@ -674,7 +947,29 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
     hipLaunchKernelGGL((coulomb_kernel_f32<false, RE>), dim3((unsigned)pad), dim3(64), 0, st,    \
                        (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad);   \
   }
-  if (t64) {
+#define EXX_BFL(V, S, R)                                                                   \
+  hipLaunchKernelGGL((coulomb_kernel_bf16<V, S, R>), dim3((unsigned)pad), dim3(64), 0, st,  \
+                     (const float2*)F, (const double*)vt, (double2*)partial, a, nwork, pad)
+#define EXX_BFL2(V, S) \
+  if (half)            \
+    EXX_BFL(V, S, true); \
+  else                 \
+    EXX_BFL(V, S, false);
+  if (bf) {
+    if (vec4) {
+      if (split) {
+        EXX_BFL2(true, true)
+      } else {
+        EXX_BFL2(true, false)
+      }
+    } else {
+      if (split) {
+        EXX_BFL2(false, true)
+      } else {
+        EXX_BFL2(false, false)
+      }
+    }
+  } else if (t64) {
     hipLaunchKernelGGL(coulomb_kernel_t64<T>, dim3((unsigned)pad), dim3(64), 0, st,
                        (const cplx<T>*)F, (const double*)vt, (double2*)partial, a, nwork, pad);
   } else if (half) {
@@ -683,6 +978,8 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
     EXX_COUL(false)
   }
 #undef EXX_COUL
+#undef EXX_BFL2
+#undef EXX_BFL
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   ReduceArgs r;
@@ -708,10 +1005,10 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
 
 template hipError_t launch_coulomb<double>(const Geom&, const Tables&, const void*, const int32_t*,
                                            void*, int, double2*, bool, hipStream_t, const int*,
-                                           const int*, int, bool);
+                                           const int*, int, bool, int);
 template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void*, const int32_t*,
                                           void*, int, double2*, bool, hipStream_t, const int*,
-                                          const int*, int, bool);
+                                          const int*, int, bool, int);
 
 // V[rep[s]] = e^{-i q.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and
 // V[bar[s]] = conj of that, for the nslice unphased matrices U

@@ -58,12 +58,14 @@ EXPORTED = (
     "exx_build_K_noalloc",
     "exx_save_tuning",
     "exx_load_tuning",
+    "exx_set_contraction",
 )
 
 EXX_BATCH_GRAPH, EXX_BATCH_TUNE, EXX_BATCH_CONCURRENT = 1, 2, 4
 EXX_CALL_BUILD, EXX_CALL_SELECT, EXX_CALL_SELECT_MLP = 0, 1, 2
 EXX_CHECK_FINITE, EXX_STRICT_PD, EXX_CHECK_SYNC = 1, 2, 4
 EXX_ERR_NOT_PD, EXX_ERR_NONFINITE = -4, -5
+EXX_CONTRACT_AUTO, EXX_CONTRACT_F64, EXX_CONTRACT_BF16, EXX_CONTRACT_BF16X3 = 0, 1, 2, 3
 EXX_MLP_NPARAM = 4481
 
 PHASES = ("G", "S", "cholesky", "pinv", "gamma", "kcorr", "solve", "fft", "coulomb",
@@ -142,6 +144,7 @@ def _load():
                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "exx_set_workspace": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "exx_set_checks": ([vp, ctypes.c_int32], ctypes.c_int),
+        "exx_set_contraction": ([vp, ctypes.c_int32], ctypes.c_int),
         "exx_get_status": ([vp, vp, i32p], ctypes.c_int),
         "exx_build_K_noalloc": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "exx_save_tuning": ([vp, ctypes.c_char_p], ctypes.c_int),
@@ -238,6 +241,11 @@ class Handle:
     def set_refinement(self, steps: int):
         """Steps (0 or 1) of iterative refinement after every fit solve of this handle."""
         self._check(_lib.exx_set_refinement(self._h, int(steps)))
+
+    def set_contraction(self, form: int):
+        """Arithmetic of the Coulomb contraction on FP32-stored transforms
+        (EXX_CONTRACT_AUTO, _F64, _BF16, _BF16X3)."""
+        self._check(_lib.exx_set_contraction(self._h, int(form)))
 
     def set_timing(self, enable: bool, serial: bool = False):
         """Per-phase HIP events; serial also runs the normally overlapping phases one

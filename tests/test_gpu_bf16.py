@@ -1,7 +1,10 @@
 """EXX_BF16: the grid-sized fit GEMM Gamma^n on the BF16 matrix cores (operands
-rounded to bfloat16 at load, FP32 accumulation), everything else as EXX_F32.
+rounded to bfloat16 at load, FP32 accumulation) and, by default, the Coulomb
+contraction on the BF16 matrix cores too (its own test: test_gpu_contract.py);
+everything else as EXX_F32.
 
-* Kernel check: a BF16 build on inputs that are already bfloat16 values equals
+* Kernel check (contraction on the FP64 cores in both builds, so that only
+  Gamma differs): a BF16 build on inputs that are already bfloat16 values equals
   the F32 build (FP32 matrix cores, FP32 accumulation) on the same inputs to
   FP32 accumulation level, on the real path (2x2x1), the paired path (3x2x1,
   3x3x3) and the Gamma point; and differs from the F32 build on the raw inputs
@@ -49,6 +52,7 @@ def _run(cell, psi, pts, ao, prec, occ=None):
 
     dev = torch.device("cuda", 0)
     h = exx.Handle(0)
+    h.set_contraction(exx.EXX_CONTRACT_F64)
     c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, len(pts))
     if occ is None:
         occ = np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))
