@@ -1,0 +1,115 @@
+"""The 4x4x4 form of the ring cell with the larger basis (2s + 2p per atom,
+N = 384, n_occ = 84, grid 72x90x64, N_ISDF = 420, N_k = 64): the fused build in
+every precision. The paired path fits 36 representative transfers in chunks of
+grid columns (the Gamma/Z buffer holds at most 8 GiB), so the FP64 build's
+scratch is dominated by xi itself (36 x 420 x 414 720 c128, 100 GB).
+
+* Across precisions: MIXED and F32 against the FP64 build, |dE_x| <= 1e-5
+  Ha/cell and max|dK| <= 1e-6; ranks equal.
+* Against the stored FP64 oracle values (tests/golden/config5.json, when
+  written by make_golden.py): E_x, ranks, the diagonal of every K^k and 4000
+  seeded entries; FP64 to min(1e-8, 64 eps64 cond) relative, MIXED and F32 to
+  the accuracy target.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+from gpu_helpers import GOLDEN, load_golden, load_golden_arrays
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+GATE_E, GATE_K = 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module")
+def c5():
+    import torch
+
+    from paper_2304_05505_amd import exx
+    from synth.fast import orbitals_on_grid_torch
+
+    cell = synth.make_config(5)
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, cell.n_isdf)
+    psi = orbitals_on_grid_torch(cell, synth.orbital_coeffs(cell), dev)
+    gold = goldK = None
+    if os.path.exists(os.path.join(GOLDEN, "config5.json")):
+        gold = load_golden("config5.json")
+        goldK = load_golden_arrays("config5_K.npz")
+        pts = np.asarray(gold["pts"], dtype=np.int64)
+    else:
+        pts_t = torch.empty((cell.n_isdf,), dtype=torch.int32, device=dev)
+        npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+        exx.exx_select_points(h, c, psi, pts_t, npiv)
+        pts = pts_t.cpu().numpy().astype(np.int64)
+    pts_t = torch.from_numpy(pts.astype(np.int32)).to(dev)
+    ao = np.stack([synth.ao_at_points(cell, n, pts) for n in range(cell.N_k)])
+    t = {"psi": psi,
+         "occ": psi[:, :, pts_t.long()].permute(0, 2, 1).contiguous(),
+         "ao": torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+         "pts": pts_t}
+    out = dict(cell=cell, h=h, c=c, t=t, exx=exx, torch=torch, dev=dev, gold=gold, goldK=goldK,
+               res={})
+    yield out
+    # release the 4x4x4 cell's orbitals and the handle's scratch for later modules
+    out.clear()
+    del psi, t, h
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _build(c5, prec):
+    if prec in c5["res"]:
+        return c5["res"][prec]
+    exx, torch, cell, t, dev = (c5[k] for k in ("exx", "torch", "cell", "t", "dev"))
+    psi = t["psi"] if prec in ("f64", "mixed") else t["psi"].to(torch.complex64)
+    K = torch.empty((cell.N_k, cell.n_ao, cell.n_ao), dtype=torch.complex128, device=dev)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((cell.N_k,), dtype=torch.int32, device=dev)
+    exx.exx_build(c5["h"], c5["c"], exx.PREC[prec], psi, t["occ"], t["ao"], t["pts"], K, Ex, rank)
+    torch.cuda.synchronize()
+    del psi
+    r = (K.cpu().numpy(), float(Ex.cpu()[0]), rank.cpu().numpy())
+    print(f"config5 {prec}: E_x {r[1]:.10f}, scratch {c5['h'].scratch_bytes() / 2**30:.1f} GiB")
+    c5["res"][prec] = r
+    return r
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f32"])
+def test_config5_precisions_agree_with_fp64(c5, prec):
+    K0, E0, r0 = _build(c5, "f64")
+    K, E, r = _build(c5, prec)
+    dE = abs(E - E0)
+    dK = float(np.abs(K - K0).max())
+    print(f"config5 {prec} vs f64: |dEx| {dE:.2e} Ha/cell max|dK| {dK:.2e}")
+    assert np.array_equal(r, r0)
+    assert dE <= GATE_E and dK <= GATE_K
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed", "f32"])
+def test_config5_against_oracle(c5, prec):
+    gold, goldK = c5["gold"], c5["goldK"]
+    if gold is None:
+        pytest.skip("stored oracle values of the 4x4x4 cell not written")
+    K, E, r = _build(c5, prec)
+    idx = goldK["idx"]
+    d1 = np.abs(K[idx[:, 0], idx[:, 1], idx[:, 2]] - goldK["val"]).max()
+    diag = np.stack([np.diagonal(K[n]) for n in range(K.shape[0])])
+    dK = float(max(d1, np.abs(diag - goldK["diag"]).max()))
+    dE = abs(E - gold["Ex"])
+    cond = max(gold["cond_S"])
+    print(f"config5 {prec} vs oracle: cond {cond:.2e} |dEx| {dE:.2e} Ha/cell max|dK| {dK:.2e}")
+    assert np.array_equal(r, gold["rank"])
+    if prec == "f64":
+        tol = min(1e-8, max(1e-12, 64 * EPS64 * cond))
+        assert dE <= tol * abs(gold["Ex"])
+        assert dK <= tol * gold["maxabs_K"]
+    else:
+        assert dE <= GATE_E and dK <= GATE_K
