@@ -488,6 +488,31 @@ exx_status exx_set_refinement(exx_handle_t h, int32_t steps);
  * EXX_F64 builds (FP64-stored transforms) return EXX_ERR_UNSUPPORTED while a
  * BF16 form is set. Returns EXX_ERR_ARG for an unknown form.
  */
+/*
+ * exx_set_fit -- the ISDF fit of every later exx_build and exx_build_batched
+ * call of this handle (exx_isdf_fit always fits per transfer):
+ *   EXX_FIT_PER_Q   (default) one fit per transfer q (Sec. 2.3, Eq. 16):
+ *                   S^m xi^m = Z^m for every m;
+ *   EXX_FIT_SHARED  one fit for all transfers: the k-point fit of Sec. 2.2
+ *                   (Eq. 13) restricted to occupied pairs, i.e. the least-
+ *                   squares problem over the pairs of every transfer,
+ *                   (sum_m S^m) xi = sum_m Z^m in the cell-periodic gauge of the
+ *                   per-transfer fit. One factorisation, one grid-sized solve and
+ *                   one 3-D FFT per point serve every transfer; the Coulomb
+ *                   matrices V^m_PQ = (Omega/N_g^2) sum_g v^m(g) F_P conj F_Q
+ *                   differ only in the kernel v^m, then the Bloch phases. Less
+ *                   accurate than the per-transfer fit at the same N_ISDF (one
+ *                   set of functions spans the pairs of every transfer). rank[m]
+ *                   is the shared metric's rank for every m; with
+ *                   EXX_STRICT_PD a lost pivot reports transfer 0. Scratch: Gamma
+ *                   and Z of one chunk of grid columns, Y = W Z and its
+ *                   transform (N_ISDF N_g each) instead of one per transfer.
+ * Returns EXX_ERR_ARG for an unknown mode.
+ */
+#define EXX_FIT_PER_Q 0
+#define EXX_FIT_SHARED 1
+exx_status exx_set_fit(exx_handle_t h, int32_t mode);
+
 #define EXX_CONTRACT_AUTO 0
 #define EXX_CONTRACT_F64 1
 #define EXX_CONTRACT_BF16 2

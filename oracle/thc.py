@@ -214,3 +214,56 @@ def thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol=1e-12, keep_intermediates
                     seconds={"gamma": t_gamma, "per_q": t_m, "contract": t_contract}))
     out.update(kept)
     return out
+
+
+def thc_oo_k_shared(L, grid, kmesh, psi, pts, ao_pts, rel_tol=1e-12, chunk=1 << 15):
+    """THC-oo-K with one fit shared by every transfer (Sec. 2.2, Eq. 13: the
+    k-point least-squares fit, here over the occupied pairs of Eq. 16).
+
+    The pairs of all transfers enter one least-squares problem for a single set
+    of interpolating vectors xi_P(r) (cell-periodic gauge, as the per-transfer
+    fit): with the pair matrices B_m and right-hand sides of steps 2-3, the
+    normal equations are (sum_m B_m^H B_m) xi = sum_m B_m^H A_m, i.e.
+    S = sum_m S^m and Z = sum_m Z^m. One Cholesky-with-drop of S, one solve,
+    then per transfer the Coulomb matrix of the same xi with the kernel v^m
+    (steps 5-6) and steps 7-9 unchanged. Returns K, Ex, Ex_trVS (with the
+    shared S), V, Vb, S (shared), rank (shared, one value), xi.
+    """
+    L = np.asarray(L, dtype=np.float64)
+    grid = tuple(int(x) for x in grid)
+    kmesh = tuple(int(x) for x in kmesh)
+    pts = np.asarray(pts, dtype=np.int64)
+    nk, no, ng = psi.shape
+    nI = len(pts)
+    Psi, X, G = gather(psi, pts, ao_pts)
+    rP = coulomb.positions(L, grid, pts)
+    r_all = coulomb.positions(L, grid)
+    S = np.zeros((nI, nI), dtype=np.complex128)
+    Z = np.zeros((nI, ng), dtype=np.complex128)
+    for m in range(nk):
+        q = coulomb.qvec(L, kmesh, m)
+        ph_P = np.exp(-1j * (rP @ q))
+        B = pair_rows(Psi, kmesh, m, ph_P)
+        S += B.conj().T @ B
+        del B
+        for c0 in range(0, ng, chunk):
+            c1 = min(ng, c0 + chunk)
+            Zc = np.zeros((nI, c1 - c0), dtype=np.complex128)
+            for n in range(nk):
+                n2 = coulomb.add_index(kmesh, n, m)
+                Zc += _gamma(Psi[n], psi[n][:, c0:c1]) * _gamma(Psi[n2], psi[n2][:, c0:c1]).conj()
+            ph_r = np.exp(-1j * (r_all[c0:c1] @ q))
+            Z[:, c0:c1] += Zc * (ph_P.conj()[:, None] * ph_r[None, :])
+    Lc, keep = cholesky_drop(S, rel_tol)
+    xi = solve_drop(Lc, keep, Z)
+    V_all = np.stack([coulomb_matrix(L, grid, kmesh, m, xi) for m in range(nk)])
+    Vb_all = np.stack([bloch_gauge(L, grid, kmesh, m, pts, V_all[m]) for m in range(nk)])
+    Y, K, Ex = contract(kmesh, G, X, Vb_all)
+    # the per-transfer metrics S^m weight V^m in the trace form of E_x
+    Sm = np.stack([pair_rows(Psi, kmesh, m, np.exp(-1j * (rP @ coulomb.qvec(L, kmesh, m))))
+                   for m in range(nk)])
+    Ex_trVS = -float(sum(np.trace(V_all[m] @ (Sm[m].conj().T @ Sm[m])).real
+                         for m in range(nk))) / nk ** 2
+    return dict(K=K, Ex=Ex, Ex_trVS=Ex_trVS, V=V_all, Vb=Vb_all, S=S, G=G, Y=Y,
+                rank=int(keep.sum()), keep=keep, xi=xi)
+

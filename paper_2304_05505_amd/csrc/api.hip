@@ -208,10 +208,10 @@ Pairs make_pairs(const Geom& g) {
 }
 
 // which form the fused build takes (fit_coulomb)
-enum BuildPath { PATH_STAGES = 0, PATH_REAL = 1, PATH_PAIRED = 2 };
+enum BuildPath { PATH_STAGES = 0, PATH_REAL = 1, PATH_PAIRED = 2, PATH_SHARED = 3 };
 
 BuildPath build_path(const exx_context* h, const Geom& g) {
-  (void)h;
+  if (h->fit_mode == EXX_FIT_SHARED) return PATH_SHARED;
   if (kcorr_real(g)) return PATH_REAL;
   return make_pairs(g).n < g.nk ? PATH_PAIRED : PATH_STAGES;
 }
@@ -249,6 +249,7 @@ Layout layout(const exx_context* h, const Geom& g, exx_prec prec, int need) {
   const bool build = (need & NEED_BUILD) != 0;
   const bool grid = (need & (NEED_FIT | NEED_COULOMB | NEED_BUILD)) != 0;
   const bool paired = build && build_path(h, g) == PATH_PAIRED;
+  const bool shared = build && build_path(h, g) == PATH_SHARED;
   Layout L;
   const size_t mat = al(sizeof(double2) * (size_t)g.nk * g.ni * g.ni);
   // Gamma/Z (and F) buffer: FP64 unless the fit itself runs in FP32; xi: FP64 only in EXX_F64
@@ -286,18 +287,22 @@ Layout layout(const exx_context* h, const Geom& g, exx_prec prec, int need) {
   o += al(sizeof(double2) * (size_t)g.nk * 32 * g.ni);
   L.pd = paired_dims(h, g, cs);
   L.grid = o;
-  if (paired)  // Gamma / Z of one chunk of grid columns
+  if (paired || shared)  // Gamma / Z of one chunk of grid columns
     o += al(cs * (size_t)g.nk * g.ni * L.pd.cols);
   else
     o += grid ? al(cs * (size_t)g.nk * g.ni * g.ng) : 0;
   L.grid2 = o;
   if (paired)  // Y = W Z of the representative transfers
     o += al(cx * (size_t)make_pairs(g).n * g.ni * g.ng);
+  else if (shared)  // Y = W Z of the shared fit
+    o += al(cx * (size_t)g.ni * g.ng);
   else
     o += build ? al(cx * (size_t)g.nk * g.ni * g.ng) : 0;
   L.F = o;
   if (paired)  // transforms of two chunks of transfers
     o += 2 * al(cx * (size_t)L.pd.per * g.ni * g.ng);
+  else if (shared)  // the one transform
+    o += al(cx * (size_t)g.ni * g.ng);
   L.total = o;
   return L;
 }
@@ -923,6 +928,180 @@ exx_status fit_coulomb_pairs(exx_context* h, const Geom& g, const Tables& tb, ch
   return EXX_OK;
 }
 
+// One fit shared by all transfers (the k-point fit of Sec. 2.2, Eq. 13, on
+// occupied pairs): the least-squares problem over the pairs of every transfer
+// has the metric S = sum_m S^m and the right-hand side Z = sum_m Z^m (each in
+// the cell-periodic gauge of the per-transfer fit), so one Cholesky factor
+// S = L L^H, W = L^{-1} and one grid-sized product Y = W Z serve every
+// transfer, and one transform F_Y = FFT(Y). The transfer enters only through
+// the kernel: Vy^m = (Omega/N_g^2) sum_g v^m(g) F_Y,P conj F_Y,Q, then
+// V^m = W^H Vy^m W and the Bloch phases. The fit runs over chunks of grid
+// columns (Gamma^n, Z^m, their sum over m and Y are column-local); the
+// factorisation chain runs on the caller's stream beside it.
+template <typename TF, typename TX>
+exx_status fit_coulomb_shared(exx_context* h, const Geom& g, const Tables& tb, char* ws,
+                              const Layout& L, const void* psi, const void* occ,
+                              const int32_t* pts, void* V, int32_t* rank, hipStream_t st,
+                              bool bf16 = false, int cform = COUL_F64) {
+  double2* G = (double2*)(ws + L.G);
+  double2* Lf = (double2*)(ws + L.Lf);
+  double2* W = (double2*)(ws + L.W);
+  double2* Sall = (double2*)(ws + L.S2);
+  int32_t* keep = (int32_t*)(ws + L.keep);
+  int32_t* rank_c = (int32_t*)(ws + L.rank2);
+  void* gam = ws + L.grid;   // Gamma, then Z^m, then sum_m Z^m (slice 0), of one column chunk
+  char* y = ws + L.grid2;    // Y = W Z, full grid
+  char* F = ws + L.F;        // its transform
+  Geom g1 = g;               // the one shared metric
+  g1.nk = 1;
+  const long nn = (long)g.ni * g.ni;
+  const int cc = L.pd.cols;
+  hipError_t e;
+  hipStream_t ax = st;
+  hipStream_t gs = h->aux;
+  e = hipEventRecord(h->fork_ev, st);
+  if (e != hipSuccess) return hip_check(h, e, "fork event");
+  e = hipStreamWaitEvent(gs, h->fork_ev, 0);
+  if (e != hipSuccess) return hip_check(h, e, "fork wait");
+  const char* what = nullptr;
+  {
+    PhaseTimer pt(h, PH_GRAM, ax);
+    e = gemm<double, double, double, double>(g.ni, g.ni, g.no, g.nk, A_N, occ, g.no,
+                                             (long)g.ni * g.no, B_C, occ, g.no,
+                                             (long)g.ni * g.no, G, g.ni, nn, 1.0, false, ax);
+  }
+  if (e != hipSuccess) what = "G gemm";
+  if (!what) {
+    // S^m of every transfer, then S = sum_m S^m into the factor buffer
+    PhaseTimer pt(h, PH_METRIC, ax);
+    e = launch_kcorr<double>(g, tb, G, Sall, g.ni, pts, true, ax);
+    if (e == hipSuccess) e = launch_sum_slices<double>(Sall, Lf, nn, g.nk, nn, ax);
+    if (e != hipSuccess) what = "S kcorr";
+  }
+  if (!what) {
+    PhaseTimer pt(h, PH_CHOL, ax);
+    QLabel lab;
+    for (int k = 0; k < 64; ++k) lab.q[k] = 0;
+    e = launch_chol_blocked(g1, Lf, keep, rank_c, (double*)(ws + L.tol), 1e-12, ax, stat_ptr(h),
+                            strict_pd(h), &lab);
+    if (e != hipSuccess) what = "cholesky";
+  }
+  if (!what) {
+    PhaseTimer pt(h, PH_PINV, ax);
+    e = launch_tri_inv_blocked(g1, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
+    if (e != hipSuccess) what = "triangular inverse";
+  }
+  if (!what) {
+    e = launch_rank_broadcast(rank_c, rank, g.nk, ax);
+    if (e != hipSuccess) what = "rank broadcast";
+  }
+  if (!what && h->refine > 0) {
+    e = launch_zero_upper(Lf, g.ni, 1, ax);
+    if (e != hipSuccess) what = "factor";
+  }
+  if (!what) {
+    e = hipEventRecord(h->chain_ev, ax);
+    if (e != hipSuccess) what = "chain event";
+  }
+  if (what) {
+    (void)hipEventRecord(h->join_ev, gs);
+    (void)hipStreamWaitEvent(st, h->join_ev, 0);
+    return hip_check(h, e, what);
+  }
+  if (h->timing && h->serial) {
+    e = hipStreamWaitEvent(gs, h->chain_ev, 0);
+    if (e != hipSuccess) what = "serial timing";
+  }
+  for (int c0 = 0; c0 < g.ng && !what; c0 += cc) {
+    const int cn = std::min(cc, g.ng - c0);
+    const char* psi_c = (const char*)psi + (size_t)c0 * sizeof(cplx<TF>);
+    {
+      PhaseTimer pt(h, PH_GAMMA, gs);
+      if (std::is_same<TF, double>::value)
+        e = zgemm_nn_grid<double, double>(g.ni, cn, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true,
+                                          psi_c, g.ng, (long)g.no * g.ng, gam, cn, (long)g.ni * cn,
+                                          gs, h->tile_gamma);
+      else if (bf16)
+        e = cgemm_nn_grid_bf16(g.ni, cn, g.no, g.nk, occ, g.no, (long)g.ni * g.no, psi_c, g.ng,
+                               (long)g.no * g.ng, gam, cn, (long)g.ni * cn, gs);
+      else
+        e = cgemm_nn_grid32(g.ni, cn, g.no, g.nk, occ, g.no, (long)g.ni * g.no, true, psi_c, g.ng,
+                            (long)g.no * g.ng, gam, cn, (long)g.ni * cn, gs);
+    }
+    if (e != hipSuccess) {
+      what = "Gamma gemm";
+      break;
+    }
+    {
+      // Z^m of every transfer in place, then their sum into slice 0
+      PhaseTimer pt(h, PH_KCORR, gs);
+      e = launch_kcorr<TF>(g, tb, gam, gam, cn, pts, false, gs, nullptr, c0);
+      if (e == hipSuccess)
+        e = launch_sum_slices<TF>(gam, gam, (long)g.ni * cn, g.nk, (long)g.ni * cn, gs);
+    }
+    if (e != hipSuccess) {
+      what = "Z kcorr";
+      break;
+    }
+    if (c0 == 0) {
+      e = hipStreamWaitEvent(gs, h->chain_ev, 0);
+      if (e != hipSuccess) {
+        what = "chain wait";
+        break;
+      }
+    }
+    PhaseTimer pt(h, PH_SOLVE, gs);
+    char* yc = y + (size_t)c0 * sizeof(cplx<TX>);
+    e = zgemm_nn_grid<TF, TX>(g.ni, cn, g.ni, 1, W, g.ni, nn, false, gam, cn, (long)g.ni * cn, yc,
+                              g.ng, (long)g.ni * g.ng, gs, h->tile_solve, true);
+    if (e != hipSuccess) what = "solve gemm";
+    if (!what && h->refine > 0) {
+      // refinement in the factor form: R = Z - L Y (over Z), Y += W R (FP64 sums)
+      e = zgemm_nn_grid_acc<TX, TF>(g.ni, cn, g.ni, 1, Lf, g.ni, nn, yc, g.ng, (long)g.ni * g.ng,
+                                    gam, cn, (long)g.ni * cn, -1, gs);
+      if (e == hipSuccess)
+        e = zgemm_nn_grid_acc<TF, TX>(g.ni, cn, g.ni, 1, W, g.ni, nn, gam, cn, (long)g.ni * cn, yc,
+                                      g.ng, (long)g.ni * g.ng, 1, gs);
+      if (e != hipSuccess) what = "refinement";
+    }
+  }
+  hipError_t ej = hipEventRecord(h->join_ev, gs);
+  hipError_t ew = ej == hipSuccess ? hipStreamWaitEvent(st, h->join_ev, 0) : ej;
+  if (what) return hip_check(h, e, what);
+  if (ew != hipSuccess) return hip_check(h, ew, "join wait");
+  {
+    PhaseTimer pt(h, PH_FFT, st);
+    e = launch_fft3d<TX>(g, tb, y, F, g.ni, h->ncu, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "fft");
+  int rep[64], bar[64];
+  for (int m = 0; m < 64; ++m) {
+    rep[m] = m < g.nk ? m : 0;
+    bar[m] = -1;
+  }
+  double2* Vy = (double2*)V;
+  {
+    PhaseTimer pt(h, PH_COULOMB, st);
+    e = launch_coulomb<TX>(g, tb, F, pts, ws + L.cpart, L.nsplit, Vy, false, st, rep, bar, g.nk,
+                           true, cform, true);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "coulomb");
+  {
+    PhaseTimer pt(h, PH_COULOMB, st);
+    // V^m = W^H Vy^m W (W shared: stride 0), then the phases
+    double2* T = (double2*)(ws + L.Sp);
+    double2* U = (double2*)(ws + L.cpart);
+    e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_N, Vy, g.ni, nn, B_N, W,
+                                             g.ni, 0, T, g.ni, nn, 1.0, false, st);
+    if (e == hipSuccess)
+      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, 0, B_N, T,
+                                               g.ni, nn, U, g.ni, nn, 1.0, false, st);
+    if (e == hipSuccess) e = launch_coulomb_phase(g, tb, pts, U, (double2*)V, rep, bar, g.nk, st);
+  }
+  if (e != hipSuccess) return hip_check(h, e, "Coulomb products");
+  return EXX_OK;
+}
+
 // the fused fit + Coulomb of one build in precision prec
 exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                        exx_prec prec, const void* psi, const void* occ, const int32_t* pts,
@@ -935,6 +1114,14 @@ exx_status fit_coulomb(exx_context* h, const Geom& g, const Tables& tb, char* ws
   const int cf = coul_form(h, prec);
   if (cf < 0) return check_form(h, prec);
   const bool bf = prec == EXX_BF16;
+  if (build_path(h, g) == PATH_SHARED) {
+    if (prec == EXX_F64)
+      return fit_coulomb_shared<double, double>(h, g, tb, ws, L, psi, occ, pts, V, rank, st);
+    if (prec == EXX_MIXED)
+      return fit_coulomb_shared<double, float>(h, g, tb, ws, L, psi, occ, pts, V, rank, st, false,
+                                               cf);
+    return fit_coulomb_shared<float, float>(h, g, tb, ws, L, psi, occ, pts, V, rank, st, bf, cf);
+  }
   if (!kcorr_real(g) && pr.n < g.nk) {
     if (prec == EXX_F64)
       return fit_coulomb_pairs<double, double>(h, g, tb, ws, L, pr, psi, occ, pts, V, rank, st);
@@ -1338,6 +1525,15 @@ exx_status exx_set_refinement(exx_handle_t h, int32_t steps) {
   return EXX_OK;
 }
 
+exx_status exx_set_fit(exx_handle_t h, int32_t mode) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (mode != EXX_FIT_PER_Q && mode != EXX_FIT_SHARED)
+    return fail(h, EXX_ERR_ARG, "exx_set_fit: unknown mode");
+  h->fit_mode = mode;
+  return EXX_OK;
+}
+
 exx_status exx_set_contraction(exx_handle_t h, int32_t form) {
   if (!h) return EXX_ERR_ARG;
   h->err.clear();
@@ -1671,6 +1867,7 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
   sig.push_back((long)prec);
   sig.push_back((long)h->refine);
   sig.push_back((long)h->contract);
+  sig.push_back((long)h->fit_mode);
   sig.push_back((long)h->checks);
   sig.push_back((long)L);
   sig.push_back((long)(size_t)ws0);

@@ -232,6 +232,19 @@ hipError_t launch_rank_scatter(const int32_t* rc, int32_t* rank, const int* rep,
   return hipGetLastError();
 }
 
+// rank[m] = rc[0] for every transfer (one fit shared by all transfers)
+__global__ void rank_broadcast_kernel(const int32_t* __restrict__ rc, int32_t* __restrict__ rank,
+                                      int nk) {
+  const int m = threadIdx.x;
+  if (m < nk) rank[m] = rc[0];
+}
+
+hipError_t launch_rank_broadcast(const int32_t* rc, int32_t* rank, int nk, hipStream_t st) {
+  if (nk <= 0 || nk > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rank_broadcast_kernel, dim3(1), dim3(64), 0, st, rc, rank, nk);
+  return hipGetLastError();
+}
+
 __global__ void status_reset_kernel(int32_t* __restrict__ status) {
   if (threadIdx.x == 0) {
     status[0] = 0;

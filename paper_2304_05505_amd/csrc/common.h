@@ -130,6 +130,7 @@ struct exx_context {
   // steps of iterative refinement after the fit solve (0 or 1)
   int refine = 0;
   int contract = 0;  // EXX_CONTRACT_* of the Coulomb contraction
+  int fit_mode = 0;  // EXX_FIT_* of the fused builds
   // second stream (default priority) for the point-metric chain of the fit,
   // which overlaps the grid-sized Gamma and Z; fork/join events
   hipStream_t aux = nullptr;
@@ -358,6 +359,13 @@ hipError_t launch_convert(const void* src, void* dst, long n, hipStream_t st);
 // rank[rep[s]] = rc[s], and rank[bar[s]] = rc[s] where bar[s] >= 0 (host lists, n <= 64)
 hipError_t launch_rank_scatter(const int32_t* rc, int32_t* rank, const int* rep, const int* bar,
                                int n, hipStream_t st);
+// rank[m] = rc[0], m < nk (<= 64)
+hipError_t launch_rank_broadcast(const int32_t* rc, int32_t* rank, int nk, hipStream_t st);
+// out[e] = sum_s in[s * stride + e] over nslice slices, e < n (complex T; out may
+// be slice 0 of in)
+template <typename T>
+hipError_t launch_sum_slices(const void* in, void* out, long n, int nslice, long stride,
+                             hipStream_t st);
 
 // Blocked Cholesky with pivot drop (A: S^m in, L in the lower triangle out;
 // tol: [N_k] scratch) and blocked inverse W = L^{-1} (T: [N_k][32][N_I] scratch)
@@ -394,6 +402,8 @@ hipError_t launch_fft3d_half(const Geom& g, const Tables& tb, const void* in, vo
                              int m0, int ncu, hipStream_t st);
 int fft_half_z(const Geom& g);
 
+// shared_f: every slice contracts the same transforms F (one fit shared by all
+// transfers; the transfer enters only through the kernel table v^m).
 // Coulomb contraction: V^m (Bloch gauge) from F^m (storage T) on the FP64 matrix cores,
 // or with FP32 storage on the BF16 matrix cores (form COUL_BF16: operands rounded to
 // bfloat16; COUL_BF16X3: split hi + lo operands, three products), FP32 accumulation
@@ -409,7 +419,7 @@ template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
                           void* partial, int nsplit, double2* V, bool half, hipStream_t st,
                           const int* rep = nullptr, const int* bar = nullptr, int nslice = 0,
-                          bool raw = false, int form = 0);
+                          bool raw = false, int form = 0, bool shared_f = false);
 enum { COUL_F64 = 0, COUL_BF16 = 1, COUL_BF16X3 = 2 };
 // V[rep[s]] = e^{-i q_m.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and, where
 // bar[s] >= 0, V[bar[s]] = conj of that; U holds nslice (<= 64) matrices

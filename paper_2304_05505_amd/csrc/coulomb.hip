@@ -18,7 +18,8 @@ struct CoulArgs {
   int n[3];
   int N[3];
   int ng, ni, nk, nsplit, chunk, ntile;
-  int rep[64];  // transfer of each slice (slices may hold a subset of the transfers)
+  long fstride;  // elements of F per slice (0: every slice reads the same F)
+  int rep[64];   // transfer of each slice (slices may hold a subset of the transfers)
 };
 
 // ---------------------------------------------------------------------------
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void coulomb_kernel_f64(const double2* __re
   const long g1 = min((long)a.ng, g0 + a.chunk);
   __shared__ double stage[4 * 3 * 64 * 4];
   coulomb_wave_tile<double, 0xF, false, 2, RE>(
-      F + (long)m * a.ni * a.ng, vt + (long)m * a.ng,
+      F + (long)m * a.fstride, vt + (long)m * a.ng,
       part + ((long)m * a.nsplit + s) * a.ni * a.ni, a, P0, Q0, g0, g1,
       stage + wave * 3 * 64 * 4);
 }
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(64) void coulomb_kernel_f32(const float2* __restric
   const int P0 = ti * WTILE, Q0 = tj * WTILE;
   const long g0 = (long)s * a.chunk;
   const long g1 = min((long)a.ng, g0 + a.chunk);
-  const float2* Fm = F + (long)m * a.ni * a.ng;
+  const float2* Fm = F + (long)m * a.fstride;
   const double* vm = vt + (long)m * a.ng;
   double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
   constexpr int NPF = 4;
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(64) void coulomb_kernel_t64(const cplx<T>* __restri
   const int P0 = ti * 64, Q0 = tj * 64;
   const long g0 = (long)s * a.chunk;
   const long g1 = min((long)a.ng, g0 + a.chunk);
-  const cplx<T>* Fm = F + (long)m * a.ni * a.ng;
+  const cplx<T>* Fm = F + (long)m * a.fstride;
   const double* vm = vt + (long)m * a.ng;
   double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
   __shared__ double stage[64 * 4];
@@ -730,7 +731,7 @@ __global__ __launch_bounds__(64) void coulomb_kernel_bf16(const float2* __restri
   const int P0 = ti * WTILE, Q0 = tj * WTILE;
   const long g0 = (long)s * a.chunk;
   const long g1 = min((long)a.ng, g0 + a.chunk);
-  const float2* Fm = F + (long)m * a.ni * a.ng;
+  const float2* Fm = F + (long)m * a.fstride;
   const double* vm = vt + (long)m * a.ng;
   double2* out = part + ((long)m * a.nsplit + s) * a.ni * a.ni;
   const bool row1 = P0 + 16 < a.ni;
@@ -854,7 +855,8 @@ size_t coulomb_partial_bytes(const Geom& g, int nsplit) {
 template <typename T>
 hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const int32_t* pts,
                           void* partial, int nsplit, double2* V, bool half, hipStream_t st,
-                          const int* rep, const int* bar, int nslice, bool raw, int form) {
+                          const int* rep, const int* bar, int nslice, bool raw, int form,
+                          bool shared_f) {
   CoulArgs a;
   const int ns = rep ? nslice : g.nk;
   for (int m = 0; m < 64; ++m) a.rep[m] = rep && m < ns ? rep[m] : m;
@@ -867,6 +869,7 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
   a.ng = half ? g.n[0] * g.n[1] * hz : g.ng;
   a.ni = g.ni;
   a.nk = ns;
+  a.fstride = shared_f ? 0 : (long)a.ni * a.ng;
   const bool vec = a.ng % 2 == 0;
   const bool bf = sizeof(T) == 4 && form != COUL_F64;
   const bool split = form == COUL_BF16X3;
@@ -1005,10 +1008,10 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
 
 template hipError_t launch_coulomb<double>(const Geom&, const Tables&, const void*, const int32_t*,
                                            void*, int, double2*, bool, hipStream_t, const int*,
-                                           const int*, int, bool, int);
+                                           const int*, int, bool, int, bool);
 template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void*, const int32_t*,
                                           void*, int, double2*, bool, hipStream_t, const int*,
-                                          const int*, int, bool, int);
+                                          const int*, int, bool, int, bool);
 
 // V[rep[s]] = e^{-i q.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and
 // V[bar[s]] = conj of that, for the nslice unphased matrices U

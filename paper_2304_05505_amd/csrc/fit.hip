@@ -739,4 +739,31 @@ template hipError_t launch_kcorr<double>(const Geom&, const Tables&, const void*
 template hipError_t launch_kcorr<float>(const Geom&, const Tables&, const void*, void*, int,
                                           const int32_t*, bool, hipStream_t, const int*, int);
 
+// out[e] = sum_s in[s * stride + e], e < n (out may be slice 0 of in: each
+// element is read for every slice before it is written)
+template <typename T>
+__global__ __launch_bounds__(256) void sum_slices_kernel(const cplx<T>* in, cplx<T>* out, long n,
+                                                         int nslice, long stride) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  T re = 0, im = 0;
+  for (int s = 0; s < nslice; ++s) {
+    const cplx<T> v = in[(long)s * stride + e];
+    re += v.x;
+    im += v.y;
+  }
+  out[e] = mk<T>(re, im);
+}
+
+template <typename T>
+hipError_t launch_sum_slices(const void* in, void* out, long n, int nslice, long stride,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_slices_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (const cplx<T>*)in, (cplx<T>*)out, n, nslice, stride);
+  return hipGetLastError();
+}
+template hipError_t launch_sum_slices<double>(const void*, void*, long, int, long, hipStream_t);
+template hipError_t launch_sum_slices<float>(const void*, void*, long, int, long, hipStream_t);
+
 }  // namespace exx

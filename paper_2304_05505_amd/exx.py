@@ -59,6 +59,7 @@ EXPORTED = (
     "exx_save_tuning",
     "exx_load_tuning",
     "exx_set_contraction",
+    "exx_set_fit",
 )
 
 EXX_BATCH_GRAPH, EXX_BATCH_TUNE, EXX_BATCH_CONCURRENT = 1, 2, 4
@@ -66,6 +67,7 @@ EXX_CALL_BUILD, EXX_CALL_SELECT, EXX_CALL_SELECT_MLP = 0, 1, 2
 EXX_CHECK_FINITE, EXX_STRICT_PD, EXX_CHECK_SYNC = 1, 2, 4
 EXX_ERR_NOT_PD, EXX_ERR_NONFINITE = -4, -5
 EXX_CONTRACT_AUTO, EXX_CONTRACT_F64, EXX_CONTRACT_BF16, EXX_CONTRACT_BF16X3 = 0, 1, 2, 3
+EXX_FIT_PER_Q, EXX_FIT_SHARED = 0, 1
 EXX_MLP_NPARAM = 4481
 
 PHASES = ("G", "S", "cholesky", "pinv", "gamma", "kcorr", "solve", "fft", "coulomb",
@@ -145,6 +147,7 @@ def _load():
         "exx_set_workspace": ([vp, vp, ctypes.c_size_t], ctypes.c_int),
         "exx_set_checks": ([vp, ctypes.c_int32], ctypes.c_int),
         "exx_set_contraction": ([vp, ctypes.c_int32], ctypes.c_int),
+        "exx_set_fit": ([vp, ctypes.c_int32], ctypes.c_int),
         "exx_get_status": ([vp, vp, i32p], ctypes.c_int),
         "exx_build_K_noalloc": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "exx_save_tuning": ([vp, ctypes.c_char_p], ctypes.c_int),
@@ -246,6 +249,10 @@ class Handle:
         """Arithmetic of the Coulomb contraction on FP32-stored transforms
         (EXX_CONTRACT_AUTO, _F64, _BF16, _BF16X3)."""
         self._check(_lib.exx_set_contraction(self._h, int(form)))
+
+    def set_fit(self, mode: int):
+        """ISDF fit of the fused builds: EXX_FIT_PER_Q (default) or EXX_FIT_SHARED."""
+        self._check(_lib.exx_set_fit(self._h, int(mode)))
 
     def set_timing(self, enable: bool, serial: bool = False):
         """Per-phase HIP events; serial also runs the normally overlapping phases one
