@@ -267,3 +267,26 @@ def thc_oo_k_shared(L, grid, kmesh, psi, pts, ao_pts, rel_tol=1e-12, chunk=1 << 
     return dict(K=K, Ex=Ex, Ex_trVS=Ex_trVS, V=V_all, Vb=Vb_all, S=S, G=G, Y=Y,
                 rank=int(keep.sum()), keep=keep, xi=xi)
 
+
+def thc_ao_k(L, grid, kmesh, phi, psi, pts, rel_tol=1e-12):
+    """THC-AO-K (Algorithm 1): the ISDF fit of the AO pair products
+    conj phi_mu^k(r) phi_nu^{k+q}(r) per transfer (Eqs. 7-9 and 13), done once,
+    and the K-build from the occupied density at the points (Eq. 14).
+
+    The fit of the AO pairs is the fit of steps 1-6 with the AO functions phi^k
+    (N per k) in place of the occupied orbitals, so it is taken from thc_oo_k
+    called on phi: its Bloch-gauge Coulomb matrices are M^q of the AO fit. The
+    contraction (steps 7-9) then uses the occupied G^n_PQ = sum_i
+    psi_in(r_P) conj psi_in(r_Q) and X^n_{mu P} = conj phi_mu^n(r_P):
+    Y^n = sum_m Vb^m o G^{n+m}, K^n = (1/N_k) X^n Y^n X^n^H, E_x from Y and G.
+    Returns K, Ex, Vb (of the AO fit), rank (per transfer), the AO-pair metrics S
+    and the retained points keep.
+    """
+    pts = np.asarray(pts, dtype=np.int64)
+    nk = phi.shape[0]
+    ao_pts = np.stack([phi[n][:, pts] for n in range(nk)])
+    fit = thc_oo_k(L, grid, kmesh, phi, pts, ao_pts, rel_tol)
+    Psi, X, G = gather(psi, pts, ao_pts)
+    Y, K, Ex = contract(tuple(int(x) for x in kmesh), G, X, fit["Vb"])
+    return dict(K=K, Ex=Ex, Vb=fit["Vb"], rank=fit["rank"], Y=Y, S=fit["S"], keep=fit["keep"])
+

@@ -9,6 +9,11 @@ itself:
   direct exchange (O1) for E_x and the occupied block of K;
 * the k-convolution form of E_x equals the trace form with the per-transfer
   metrics, and E_x from K (the contraction is the same as the per-q one).
+
+And of the THC-AO-K composition (thc.thc_ao_k: the AO-pair fit done once, the
+K-build from the occupied density): exact at full AO pair rank (every entry of
+K against direct exchange), and below it E_x from its own K, Hermitian K, and a
+fit that does not depend on the occupied orbitals.
 """
 
 import numpy as np
@@ -99,3 +104,49 @@ def test_shared_fit_at_full_pair_rank_reproduces_direct_exchange():
         oo2 = C[n].conj().T @ o["K"][n] @ C[n]
         oo1 = C[n].conj().T @ K1[n] @ C[n]
         assert np.abs(oo2 - oo1).max() <= 1e-9 * np.abs(oo1).max()
+
+
+# ---------------------------------------------------------------------------
+# THC-AO-K (the AO-pair fit, done once, and the K-build from the occupied density)
+# ---------------------------------------------------------------------------
+
+def test_thc_ao_k_at_full_pair_rank_is_direct_exchange():
+    """2x1x1 mesh, one atom (4 AO functions): the AO pairs of a transfer span at
+    most N_k N^2 = 32 functions (fewer independent ones on this grid); with every
+    grid point offered in QRCP order the fit spans them all and is exact, so K
+    (every AO entry, not only the occupied block) and E_x equal direct exchange.
+    (In flat grid order the point-order Cholesky keeps nearly dependent points
+    of the AO pair space, whose conditioning then ruins the fit: the points are
+    an input, and QRCP is the selection this fit needs.)"""
+    c = synth.make_random_cell((4.0, 4.5, 5.0), 1, (6, 6, 8), (2, 1, 1), 2, 288, (9, 9, 9))
+    C, psi = _orbitals(c)
+    phi = _phi(c)
+    pts, _ = select.select_points(phi, c.N_g)
+    o = thc.thc_ao_k(c.L, c.grid, c.kmesh, phi, psi, pts)
+    assert np.all(o["rank"] <= c.N_k * c.n_ao ** 2)
+    K1 = direct.exchange_matrix(c.L, c.grid, c.kmesh, psi, phi)
+    assert np.abs(o["K"] - K1).max() <= 1e-10 * np.abs(K1).max()
+    E1 = direct.exchange_energy(c.L, c.grid, c.kmesh, psi)
+    assert abs(o["Ex"] - E1) <= 1e-12 * abs(E1)
+
+
+def test_thc_ao_k_below_full_rank_identities():
+    """Below full rank: E_x equals the energy of its own K, K is Hermitian, and
+    the fit is independent of the occupied orbitals (a second orbital set reuses
+    M^q unchanged, as Algorithm 1 does inside the SCF loop)."""
+    c = synth.make_random_cell((5.0, 5.0, 6.0), 2, (10, 10, 12), (2, 2, 1), 3, 80, (4, 4, 4))
+    C, psi = _orbitals(c)
+    phi = _phi(c)
+    pts, _ = select.select_points(phi, c.n_isdf)
+    o = thc.thc_ao_k(c.L, c.grid, c.kmesh, phi, psi, pts)
+    assert abs(o["Ex"] - direct.energy_from_K(o["K"], C)) <= 1e-10 * abs(o["Ex"])
+    # Hermitian to the rounding of the AO pair metric's solve (that metric is far
+    # worse conditioned than the occupied one)
+    for n in range(c.N_k):
+        assert np.abs(o["K"][n] - o["K"][n].conj().T).max() <= 1e-9 * np.abs(o["K"]).max()
+    C2 = synth.orbital_coeffs(synth.make_random_cell((5.0, 5.0, 6.0), 2, (10, 10, 12), (2, 2, 1),
+                                                     3, 80, (4, 4, 5)))
+    psi2 = synth.orbitals_on_grid(c, C2)
+    o2 = thc.thc_ao_k(c.L, c.grid, c.kmesh, phi, psi2, pts)
+    assert np.array_equal(o2["Vb"], o["Vb"])
+    assert abs(o2["Ex"] - direct.energy_from_K(o2["K"], C2)) <= 1e-10 * abs(o2["Ex"])
