@@ -4,9 +4,10 @@ Default workload (the metric's configuration): the 24-cell batch, 2 x {8, 16,
 24, 48 atoms} x {1^3, 2^3, 3^3} k-meshes, 4 Gaussian functions per atom
 (N = 32 .. 192), n_occ = 0.44 N, N_ISDF = 2.2 N, grids at 4.5 points/bohr.
 One step = the whole batch of K-builds through one exx_build_batched call
-(one captured HIP graph, autotuned tiles) in the mixed precision mode (FP64
-fit, FP32 storage of the fitted functions and transforms, FP64 Cholesky,
-solve arithmetic, Coulomb accumulation, contraction and E_x). It is compared
+(a captured HIP graph or concurrent lanes, whichever is faster; autotuned
+tiles) in the mixed precision mode (FP64 fit, FP32 storage of the fitted
+functions and transforms, FP64 Cholesky, solve arithmetic, Coulomb
+contraction on the FP64 matrix cores, FP64 K and E_x; no refinement step). It is compared
 with 24 sequential plain-FP64 builds of the same cells, and every cell's E_x
 and K are checked against the stored FP64 oracle values (tests/golden/
 config4.json, written by the oracle alone) at |dE_x| <= 1e-5 Ha/cell and
@@ -16,7 +17,9 @@ timed region.
 `value` = 24 / (seconds per batched step). `paths` also carries the batch in
 F32 and F64 and the single-cell builds of the 48-atom four-ring cell on the
 2x2x2 and 3x3x3 meshes (N = 192, n_occ = 84, grid 60x75x54, N_ISDF = 420) in
-every precision, each against its stored oracle K and E_x.
+every precision, with the split-BF16 contraction in MIXED and F32, each
+against its stored oracle K and E_x, and the shared-xi fit (timed; its E_x
+against the per-transfer oracle's shows the fit's own error).
 
 Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --profile
 (the mixed batch twice and a 1 GiB copy, no JSON: the profiler's target);
@@ -147,7 +150,7 @@ def roofline(phase_ms, work_exec, work_survey, units, prec):
         out = {"bound": "mfma", "achieved": a, "peak": peak, "unit": "TFLOP/s", "frac": a / peak}
     out.update({"traffic": None, "phase": best, "phase_ms": phase_ms[best],
                 "work_executed": work_exec[best], "work_survey": work_survey[best],
-                "achieved_survey_count": a_sv})
+                "achieved_survey_count": a_sv, "frac_survey_count": a_sv / out["peak"]})
     return out
 
 
@@ -237,6 +240,14 @@ def time_steps(fn, steps, warmup, torch):
 # ---------------------------------------------------------------------------
 # single-cell legs (the 48-atom ring cell on 2x2x2 and 3x3x3)
 # ---------------------------------------------------------------------------
+# (label, precision, contraction form, fit) of the single-cell legs
+VARIANTS = (("f64", "f64", 0, 0), ("mixed", "mixed", 0, 0), ("f32", "f32", 0, 0),
+            ("bf16", "bf16", 0, 0), ("mixed+bf16x3", "mixed", 3, 0), ("f32+bf16x3", "f32", 3, 0),
+            ("f64-shared", "f64", 0, 1), ("mixed-shared", "mixed", 0, 1))
+CONTRACTION_NAMES = {0: "auto (FP64 matrix cores; BF16 in bf16)", 1: "FP64 matrix cores",
+                     2: "BF16 matrix cores", 3: "split BF16 (three products)"}
+
+
 def ring_leg(config, args, h, exx, torch, dev):
     import synth
 
@@ -249,8 +260,10 @@ def ring_leg(config, args, h, exx, torch, dev):
     torch.cuda.synchronize()
     log(f"[{tag}] inputs in {time.perf_counter() - t0:.1f} s")
     res = {}
-    for prec in ("f64", "mixed", "f32", "bf16"):
+    for label, prec, form, fit in VARIANTS:
         o = outputs(torch, cell, dev)
+        h.set_contraction(form)
+        h.set_fit(fit)
 
         def step():
             exx.exx_build(h, t["cell"], exx.PREC[prec], psi_for(t, prec, torch), t["occ_pts"],
@@ -262,19 +275,28 @@ def ring_leg(config, args, h, exx, torch, dev):
         torch.cuda.synchronize()
         ph = {k: v[0] for k, v in h.phase_times().items()}
         h.set_timing(False)
+        h.set_contraction(exx.EXX_CONTRACT_AUTO)
+        h.set_fit(exx.EXX_FIT_PER_Q)
         r = {"ms_per_build": s * 1e3, "builds_per_s": 1.0 / s, "Ex": float(o["Ex"].cpu()[0]),
-             "phases_ms": ph}
+             "precision": prec, "contraction": CONTRACTION_NAMES[form],
+             "fit": "shared" if fit else "per transfer", "phases_ms": ph}
         if gold is not None and goldK is not None and "K" in goldK:
             K = o["K"].cpu().numpy()
-            r["dEx_vs_oracle"] = abs(r["Ex"] - gold["Ex"])
-            r["maxdK_vs_oracle"] = float(np.abs(K - goldK["K"]).max())
-            r["meets_gate"] = bool(r["dEx_vs_oracle"] <= GATE_E and r["maxdK_vs_oracle"] <= GATE_K)
-        res[prec] = r
-        log(f"[{tag}] {prec}: {s * 1e3:.2f} ms/build, E_x {r['Ex']:.10f}" +
+            if fit:
+                # the shared fit is another approximation: its distance from the
+                # per-transfer oracle is the fit's own error, not a parity figure
+                r["Ex_minus_per_transfer_oracle"] = r["Ex"] - gold["Ex"]
+            else:
+                r["dEx_vs_oracle"] = abs(r["Ex"] - gold["Ex"])
+                r["maxdK_vs_oracle"] = float(np.abs(K - goldK["K"]).max())
+                r["meets_gate"] = bool(r["dEx_vs_oracle"] <= GATE_E
+                                       and r["maxdK_vs_oracle"] <= GATE_K)
+        res[label] = r
+        log(f"[{tag}] {label}: {s * 1e3:.2f} ms/build, E_x {r['Ex']:.10f}" +
             (f", |dEx| {r['dEx_vs_oracle']:.2e}, max|dK| {r['maxdK_vs_oracle']:.2e}"
              if "dEx_vs_oracle" in r else ""))
-    for prec in ("mixed", "f32", "bf16"):
-        res[prec]["speedup_vs_f64"] = res["f64"]["ms_per_build"] / res[prec]["ms_per_build"]
+    for label in res:
+        res[label]["speedup_vs_f64"] = res["f64"]["ms_per_build"] / res[label]["ms_per_build"]
     return {"workload": f"48-atom four-ring cell, {'x'.join(map(str, cell.kmesh))} k-mesh, N=192, "
                         f"n_occ=84, grid 60x75x54, N_ISDF=420", "paths": res}
 
@@ -655,6 +677,8 @@ def main():
         "sequential_f64": seq_r,
         "meets_gate": bool(chosen in ok),
         "gate": {"dEx_Ha_per_cell": GATE_E, "max_dK": GATE_K, "vs": "stored FP64 oracle values"},
+        "settings": {"refinement_steps": 0, "contraction": "FP64 matrix cores",
+                     "fit": "one per transfer"},
         "roofline": roof,
         "batched": {p: {k: v for k, v in res[p].items() if not k.endswith("per_cell")}
                     for p in res},

@@ -314,6 +314,17 @@ exx_status exx_mlp_features(exx_handle_t h, const exx_cell* cell, const void* ps
                             const double* norm, float* feat, hipStream_t stream);
 
 /*
+ * exx_mlp_moments -- the standardisation constants' raw moments (the training
+ * driver accumulates them over cells before exx_mlp_features is called with
+ * the resulting means and scales): sums[j] += sum_i feat[i][j] and
+ * sums[3 + j] += sum_i feat[i][j]^2, j < 3, in FP64 with a fixed summation
+ * order (deterministic); what sums holds is added to.
+ *   feat [n][3] float32 (n >= 0);  sums in/out [6] double (device)
+ */
+exx_status exx_mlp_moments(exx_handle_t h, int64_t n, const float* feat, double* sums,
+                           hipStream_t stream);
+
+/*
  * exx_mlp_forward -- score[i] = network logit of feat[i], i < n (n >= 0).
  *   feat [n][3] float32, theta [EXX_MLP_NPARAM] float32, score out [n] float32
  */

@@ -2050,6 +2050,20 @@ exx_status exx_mlp_backward(exx_handle_t h, int64_t n, const int32_t* idx, int64
                    "backward");
 }
 
+exx_status exx_mlp_moments(exx_handle_t h, int64_t n, const float* feat, double* sums,
+                           hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (n < 0) return fail(h, EXX_ERR_SHAPE, "exx_mlp_moments: n < 0");
+  if ((n > 0 && !feat) || !sums) return fail(h, EXX_ERR_ARG, "exx_mlp_moments: null argument");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_check(h, e, "hipSetDevice");
+  exx_status s;
+  void* ws = ws_get(h, mlp_moments_scratch_bytes((long)n), &s);
+  if (s != EXX_OK) return s;
+  return hip_check(h, launch_mlp_moments((long)n, feat, sums, ws, stream), "moments");
+}
+
 exx_status exx_mlp_adam(exx_handle_t h, int32_t np, float* theta, const float* grad, float* m,
                         float* v, int32_t step, float lr, float beta1, float beta2, float eps,
                         hipStream_t stream) {

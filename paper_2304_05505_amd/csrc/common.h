@@ -451,6 +451,10 @@ hipError_t launch_mlp_grad(long n, const int32_t* idx, long rows, const float* f
                            const float* tgt, float wpos, const float* theta, float* grad,
                            double* loss, void* scratch, hipStream_t st);
 size_t mlp_grad_scratch_bytes(long n);
+// sums[0..2] += column sums, sums[3..5] += column sums of squares of feat [n][3]
+hipError_t launch_mlp_moments(long n, const float* feat, double* sums, void* scratch,
+                              hipStream_t st);
+size_t mlp_moments_scratch_bytes(long n);
 hipError_t launch_adam(int np, float* theta, const float* g, float* m, float* v, int step, float lr,
                        float b1, float b2, float eps, hipStream_t st);
 hipError_t launch_targets(const Geom& g, const int32_t* pts, int npts, double sigma, float* t,

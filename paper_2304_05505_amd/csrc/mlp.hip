@@ -625,6 +625,44 @@ ProbeLayout probe_layout(const Geom& g, int nr) {
   return L;
 }
 
+// column sums and sums of squares of feat [n][3] in FP64: block b sums the
+// rows b, b + gridDim.x, ... (a fixed assignment), a fixed-order tree in LDS
+constexpr int MOM_WG = 512;
+__global__ __launch_bounds__(MNT) void mlp_moments_kernel(long n, const float* __restrict__ feat,
+                                                         double* __restrict__ part) {
+  __shared__ double red[6][MNT];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long i = (long)blockIdx.x * MNT + threadIdx.x; i < n; i += (long)gridDim.x * MNT) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double f = (double)feat[3 * i + j];
+      acc[j] += f;
+      acc[3 + j] += f * f;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = acc[j];
+  __syncthreads();
+  for (int w = MNT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[(long)blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// sums[j] += sum over the blocks' partial sums, in block order
+__global__ void mlp_moments_reduce_kernel(const double* __restrict__ part, int nblk,
+                                          double* __restrict__ sums) {
+  const int j = threadIdx.x;
+  if (j >= 6) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(long)b * 6 + j];
+  sums[j] += s;
+}
+
 }  // namespace
 
 size_t mlp_feature_scratch_bytes(const Geom& g) {
@@ -759,6 +797,24 @@ hipError_t launch_mlp_probe(const Geom& g, const double2* psi, const int32_t* pt
                                            1.0, false, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(probe_residual_kernel, dim3(1), dim3(1024), 0, st, Y, crr, np, nr, resid);
+  return hipGetLastError();
+}
+
+static int moment_workgroups(long n) {
+  const long nb = (n + MNT - 1) / MNT;
+  return (int)(nb < MOM_WG ? (nb < 1 ? 1 : nb) : MOM_WG);
+}
+
+size_t mlp_moments_scratch_bytes(long n) { return sizeof(double) * 6 * (size_t)moment_workgroups(n); }
+
+hipError_t launch_mlp_moments(long n, const float* feat, double* sums, void* scratch,
+                              hipStream_t st) {
+  const int nblk = moment_workgroups(n);
+  hipLaunchKernelGGL(mlp_moments_kernel, dim3(nblk), dim3(MNT), 0, st, n, feat, (double*)scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mlp_moments_reduce_kernel, dim3(1), dim3(64), 0, st, (const double*)scratch,
+                     nblk, sums);
   return hipGetLastError();
 }
 

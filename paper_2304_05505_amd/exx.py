@@ -60,6 +60,7 @@ EXPORTED = (
     "exx_load_tuning",
     "exx_set_contraction",
     "exx_set_fit",
+    "exx_mlp_moments",
 )
 
 EXX_BATCH_GRAPH, EXX_BATCH_TUNE, EXX_BATCH_CONCURRENT = 1, 2, 4
@@ -148,6 +149,7 @@ def _load():
         "exx_set_checks": ([vp, ctypes.c_int32], ctypes.c_int),
         "exx_set_contraction": ([vp, ctypes.c_int32], ctypes.c_int),
         "exx_set_fit": ([vp, ctypes.c_int32], ctypes.c_int),
+        "exx_mlp_moments": ([vp, ctypes.c_int64, vp, vp, vp], ctypes.c_int),
         "exx_get_status": ([vp, vp, i32p], ctypes.c_int),
         "exx_build_K_noalloc": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "exx_save_tuning": ([vp, ctypes.c_char_p], ctypes.c_int),
@@ -443,6 +445,15 @@ def exx_mlp_forward(h: Handle, feat, theta, score):
             _ptr(theta, "theta", torch.float32, (EXX_MLP_NPARAM,), d),
             _ptr(score, "score", torch.float32, (n,), d))
     h._check(_lib.exx_mlp_forward(h.raw, n, *args, _stream(d)))
+
+
+def exx_mlp_moments(h: Handle, feat, sums):
+    """sums[:3] += column sums, sums[3:] += column sums of squares of feat (n, 3)."""
+    d = h.device
+    n = feat.shape[0]
+    args = (_ptr(feat, "feat", torch.float32, (n, 3), d),
+            _ptr(sums, "sums", torch.float64, (6,), d))
+    h._check(_lib.exx_mlp_moments(h.raw, n, *args, _stream(d)))
 
 
 def exx_mlp_backward(h: Handle, feat, target, wpos: float, theta, grad, loss, idx=None):

@@ -249,18 +249,17 @@ def train(n_cells=200, n_val=20, steps=4000, batch=65536, lr=3e-3, wpos=20.0, se
     ident = (0.0, 1.0, 0.0, 1.0, 0.0, 1.0)
     t0 = time.perf_counter()
     # 1. standardisation constants from the raw descriptors of the first cells
-    s1 = torch.zeros(3, dtype=torch.float64, device=dev)
-    s2 = torch.zeros(3, dtype=torch.float64, device=dev)
+    sums = torch.zeros(6, dtype=torch.float64, device=dev)
     cnt = 0
     for i in range(n_norm):
         cd = CellData(training_cell(i), dev)
-        F = cd.features(h, ident).double()
-        s1 += F.sum(0)
-        s2 += (F * F).sum(0)
+        F = cd.features(h, ident)
+        exx.exx_mlp_moments(h, F, sums)
         cnt += F.shape[0]
         del cd, F
-    mean = (s1 / cnt).cpu().numpy()
-    std = np.sqrt(np.maximum((s2 / cnt).cpu().numpy() - mean * mean, 1e-30))
+    mom = sums.cpu().numpy() / cnt
+    mean = mom[:3]
+    std = np.sqrt(np.maximum(mom[3:] - mean * mean, 1e-30))
     norm = tuple(float(x) for pair in zip(mean, std) for x in pair)
     log(f"[mlp] norm {norm} from {n_norm} cells ({time.perf_counter() - t0:.1f} s)")
     # 2. descriptors and QRCP targets of the training cells; QRCP residuals of the held-out cells

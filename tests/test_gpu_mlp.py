@@ -249,3 +249,29 @@ def test_corrupted_weights_fall_back_to_qrcp(env, gpu):
     used, resid = exx.exx_select_points_mlp(h, c, t_psi, NORM, bad, tau, n_probe, pts)
     assert used and resid > tau
     assert np.array_equal(pts.cpu().numpy(), q.cpu().numpy())
+
+
+@pytest.mark.parametrize("n", [0, 1, 1000, 300007])
+def test_moments_match_numpy_and_are_deterministic(gpu, n):
+    """exx_mlp_moments: column sums and sums of squares of the descriptors in
+    FP64 (the training driver's standardisation constants), added to what the
+    output holds; two calls give the same bits."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    rng = np.random.default_rng(n + 11)
+    F = (rng.standard_normal((n, 3)) * [1.0, 3.0, 0.2] + [0.5, -2.0, 0.1]).astype(np.float32)
+    start = np.array([1.0, -2.0, 0.5, 3.0, 4.0, 5.0])
+    outs = []
+    for _ in range(2):
+        sums = torch.from_numpy(start.copy()).to(dev)
+        exx.exx_mlp_moments(h, torch.from_numpy(F).to(dev), sums)
+        torch.cuda.synchronize()
+        outs.append(sums.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    F64 = F.astype(np.float64)
+    ref_s = start + np.concatenate([F64.sum(0), (F64 * F64).sum(0)])
+    assert np.abs(outs[0] - ref_s).max() <= 1e-12 * max(1.0, np.abs(ref_s).max())
