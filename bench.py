@@ -580,9 +580,10 @@ def bench_select5(args):
 
 def profile_target(args):
     """The headline step for a profiler: the 24-cell batch in the mixed mode on
-    concurrent lanes (after one untimed warm-up batch, which also tunes the tiles),
-    then a plain 1 GiB device copy whose counter readings calibrate the traffic
-    counters."""
+    concurrent lanes (after one untimed warm-up batch, which also tunes the tiles,
+    and a one-row exx_mlp_moments dispatch that marks where the measured batch
+    starts), then a plain 1 GiB device copy whose counter readings calibrate the
+    traffic counters."""
     import torch
 
     import synth
@@ -598,6 +599,11 @@ def profile_target(args):
                 ao_pts=t["ao_pts"], pts=t["pts"], **outputs(torch, c, dev))
            for c, t in zip(cells, base)]
     for rep in range(2):
+        if rep == 1:
+            # a marker dispatch between the tuning batch and the measured one
+            exx.exx_mlp_moments(h, torch.zeros((1, 3), dtype=torch.float32, device=dev),
+                                torch.zeros((6,), dtype=torch.float64, device=dev))
+            torch.cuda.synchronize()
         exx.exx_build_batched(h, its, exx.EXX_MIXED,
                               exx.EXX_BATCH_CONCURRENT | exx.EXX_BATCH_TUNE)
         torch.cuda.synchronize()

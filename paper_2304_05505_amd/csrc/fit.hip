@@ -112,6 +112,21 @@ __device__ __forceinline__ cplx<T> kroot(int t) {
   return mk<T>((T)cs, (T)sn);
 }
 
+// v e^{-2 pi i t / N} for a compile-time root: the roots 1, -1 and -+i are
+// applied as exact swaps and sign changes (a multiply by 0 or 1 is not folded
+// away in IEEE arithmetic, and would cost instructions and registers)
+template <typename T, int N>
+__device__ __forceinline__ cplx<T> cmul_kroot(cplx<T> v, int t) {
+  if (t == 0) return v;
+  if (N == 2) return mk<T>(-v.x, -v.y);
+  if (N == 4) {
+    if (t == 1) return mk<T>(v.y, -v.x);   // * (-i)
+    if (t == 2) return mk<T>(-v.x, -v.y);  // * (-1)
+    return mk<T>(-v.y, v.x);               // * (+i)
+  }
+  return cmul<T>(v, kroot<T, N>(t));
+}
+
 // forward DFT along one axis of an N1 x N2 x N3 register array
 template <typename T, int N1, int N2, int N3, int AX>
 __device__ __forceinline__ void kdft_axis(cplx<T>* a) {
@@ -131,7 +146,7 @@ __device__ __forceinline__ void kdft_axis(cplx<T>* a) {
     for (int s = 0; s < NA; ++s) {
       cplx<T> acc = tmp[0];
 #pragma unroll
-      for (int t = 1; t < NA; ++t) acc = cadd<T>(acc, cmul<T>(tmp[t], kroot<T, NA>((s * t) % NA)));
+      for (int t = 1; t < NA; ++t) acc = cadd<T>(acc, cmul_kroot<T, NA>(tmp[t], (s * t) % NA));
       a[base + s * ST] = acc;
     }
   }
@@ -600,6 +615,110 @@ __global__ __launch_bounds__(256) void kcorr_direct_kernel(const cplx<T>* in, cp
   }
 }
 
+// ---------------------------------------------------------------------------
+// 4 x 4 x 4 meshes: one element's 64 values span a lane quad. Lane q of the
+// quad holds the 16 values of first-axis index q; the DFTs along the other two
+// axes run in the lane, the one along the first axis across the quad with DPP
+// broadcasts (quad_perm [j, j, j, j] reads lane j of each quad). A thread then
+// holds 16 values instead of 64, so the FP64 form stays within the register
+// file (the one-thread form spills there). Same results as kcorr_kernel; in and
+// out may alias: a quad's lanes are in one wavefront, and every store depends
+// on values exchanged after all four lanes' loads.
+// ---------------------------------------------------------------------------
+template <int J>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), J * 0x55, 0xF, 0xF,
+                                                    false));
+}
+template <int J>
+__device__ __forceinline__ double quad_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), J * 0x55, 0xF, 0xF,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), J * 0x55, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// v (-i)^r for a run-time r in 0..3, without branches: odd r swaps the parts,
+// and the real (imaginary) part changes sign for r = 2, 3 (r = 1, 2)
+template <typename T>
+__device__ __forceinline__ cplx<T> mul_mi_pow(cplx<T> v, int r) {
+  const bool odd = (r & 1) != 0;
+  const T re = odd ? v.y : v.x, im = odd ? v.x : v.y;
+  return mk<T>(r >= 2 ? -re : re, (r == 1 || r == 2) ? -im : im);
+}
+
+// X_q = sum_j x_j e^{-2 pi i j q / 4} across the quad, for lane q
+template <typename T>
+__device__ __forceinline__ cplx<T> quad_dft(cplx<T> x, int q) {
+  const cplx<T> x0 = mk<T>(quad_bcast<0>(x.x), quad_bcast<0>(x.y));
+  const cplx<T> x1 = mk<T>(quad_bcast<1>(x.x), quad_bcast<1>(x.y));
+  const cplx<T> x2 = mk<T>(quad_bcast<2>(x.x), quad_bcast<2>(x.y));
+  const cplx<T> x3 = mk<T>(quad_bcast<3>(x.x), quad_bcast<3>(x.y));
+  cplx<T> acc = cadd<T>(x0, mul_mi_pow<T>(x1, q & 3));
+  acc = cadd<T>(acc, mul_mi_pow<T>(x2, (2 * q) & 3));
+  return cadd<T>(acc, mul_mi_pow<T>(x3, (3 * q) & 3));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kcorr_quad_kernel(const cplx<T>* in, cplx<T>* out, int ni,
+                                                         int ncol, const int32_t* __restrict__ pts,
+                                                         int cols_are_points, KcorrArgs ka) {
+  constexpr int NL = 16;  // values per lane (second and third axes)
+  const long total = (long)ni * ncol;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long idx = tid >> 2;  // element (all four lanes of a quad share it)
+  const int q = (int)(tid & 3);
+  if (idx >= total) return;
+  const int P = (int)(idx / ncol);
+  const int c = (int)(idx % ncol);
+  cplx<T> a[NL];
+#pragma unroll
+  for (int p = 0; p < NL; ++p) a[p] = in[(long)(q * NL + p) * total + idx];
+  kdft_axis<T, 1, 4, 4, 2>(a);
+  kdft_axis<T, 1, 4, 4, 1>(a);
+  // one position at a time across the quad (the barriers keep the scheduler
+  // from hoisting all 64 broadcasts, whose temporaries would fill the registers)
+#pragma unroll
+  for (int p = 0; p < NL; ++p) {
+    a[p] = quad_dft<T>(a[p], q);
+    a[p] = mk<T>(a[p].x * a[p].x + a[p].y * a[p].y, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int p = 0; p < NL; ++p) {
+    a[p] = quad_dft<T>(a[p], q);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  kdft_axis<T, 1, 4, 4, 2>(a);
+  kdft_axis<T, 1, 4, 4, 1>(a);
+  const T inv = (T)1 / (T)64;
+  const int n23 = ka.n[1] * ka.n[2];
+  const int gp = pts[P];
+  const int p1 = gp / n23, p2 = (gp / ka.n[2]) % ka.n[1], p3 = gp % ka.n[2];
+  const int gc = cols_are_points ? pts[c] : ka.col0 + c;
+  const int c1 = gc / n23, c2 = (gc / ka.n[2]) % ka.n[1], c3 = gc % ka.n[2];
+  double2 w1[4], w2[4], w3[4];
+  axis_powers<4>(ka.root[0], p1, c1, 4, w1);
+  axis_powers<4>(ka.root[1], p2, c2, 4, w2);
+  axis_powers<4>(ka.root[2], p3, c3, 4, w3);
+  // this lane's first-axis factor w1^q without indexing the array by q
+  double2 f1 = w1[0];
+#pragma unroll
+  for (int j = 1; j < 4; ++j)
+    if (j == q) f1 = w1[j];
+#pragma unroll
+  for (int p = 0; p < NL; ++p) {
+    const int m = q * NL + p;
+    const int sm = ka.slot[m];
+    if (sm < 0) continue;
+    cplx<T> v = cscale<T>(a[p], inv);
+    const double2 ph = zmul(zmul(f1, w2[p / 4]), w3[p % 4]);  // e^{iq.(r_P - r_c)}
+    v = cmul<T>(v, mk<T>((T)ph.x, (T)ph.y));
+    out[(long)sm * total + idx] = v;
+  }
+}
+
 template <typename T>
 hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* out, int ncol,
                         const int32_t* pts, bool cols_are_points, hipStream_t st,
@@ -614,6 +733,12 @@ hipError_t launch_kcorr(const Geom& g, const Tables& tb, const void* in, void* o
   for (int m = 0; m < 64; ++m) ka.slot[m] = slot ? slot[m] : m;
   long total = (long)g.ni * ncol;
   dim3 grid((unsigned)((total + 255) / 256));
+  if (g.N[0] == 4 && g.N[1] == 4 && g.N[2] == 4) {
+    hipLaunchKernelGGL(kcorr_quad_kernel<T>, dim3((unsigned)((4 * total + 255) / 256)), dim3(256),
+                       0, st, (const cplx<T>*)in, (cplx<T>*)out, g.ni, ncol, pts,
+                       cols_are_points ? 1 : 0, ka);
+    return hipGetLastError();
+  }
 #define EXX_KLAUNCH(a, b, c)                                                                    \
   if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                              \
     hipLaunchKernelGGL((kcorr_kernel<T, a, b, c>), grid, dim3(256), 0, st, (const cplx<T>*)in,  \
