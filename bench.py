@@ -22,8 +22,9 @@ against its stored oracle K and E_x, and the shared-xi fit (timed; its E_x
 against the per-transfer oracle's shows the fit's own error).
 
 Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --profile
-(the mixed batch twice and a 1 GiB copy, no JSON: the profiler's target);
---workload rings-k2 | rings-k3 | select-k4 print a single leg.
+(the profiler's target, no JSON: the mixed batch twice and a 1 GiB copy; with
+--workload rings-k2 | rings-k3, two builds per precision of that cell and the
+copy); --workload rings-k2 | rings-k3 | select-k4 print a single leg.
 """
 
 from __future__ import annotations
@@ -134,23 +135,57 @@ KERNELS = {  # dominant kernel(s) of each phase, real path / paired path
 }
 
 
+# HBM bytes the dominant phase's kernels moved in one 24-cell MIXED batch, from
+# the rocprofv3 FETCH_SIZE and WRITE_SIZE runs of `bench.py --profile` (scaled by
+# the counters' reading for a plain 1 GiB copy; profiles/hbm_traffic_batch24_mixed.md).
+# Valid only while the kernels' source file is unchanged (SHA-256 below).
+TRAFFIC = {
+    "solve": {"source": "paper_2304_05505_amd/csrc/gemm_mfma.hip",
+              "sha256": "20b9f74537d768698d899cf87c6d402ee90c1e5f49d29311f9b3873cd09a23ef",
+              "bytes": 344.24e9, "launches": 38,
+              "kernels": ["zgemm_nn_mfma<double, float, 2, 2, 0, 0, 1>",
+                          "dgemm_nn_mfma<double, float, 1, 0>"]},
+}
+
+
+def traffic_for(phase):
+    import hashlib
+
+    t = TRAFFIC.get(phase)
+    if not t:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    return {"bytes_per_batch": t["bytes"], "launches": t["launches"],
+            "bytes_per_launch": t["bytes"] / t["launches"], "kernels": t["kernels"],
+            "counted": "FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (1 GiB copy calibration); includes "
+                       "lines served by the last-level cache"}
+
+
+def phase_rate(p, phase_ms, work_exec, work_survey, units, prec):
+    """Achieved rate of phase p (executed and survey work counts) over its summed time."""
+    s = phase_ms[p] / 1e3
+    if units[p] == "byte":
+        a, a_sv = work_exec[p] / s / 1e9, work_survey[p] / s / 1e9
+        out = {"bound": "hbm", "achieved": a, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+               "frac": a / PEAK["hbm_GBs"]}
+    else:
+        a, a_sv = work_exec[p] / s / 1e12, work_survey[p] / s / 1e12
+        peak = PEAK["fp64_TF"] if p in FP64_CORES[prec] else PEAK["fp32_TF"]
+        out = {"bound": "mfma", "achieved": a, "peak": peak, "unit": "TFLOP/s", "frac": a / peak}
+    out.update({"phase_ms": phase_ms[p], "work_executed": work_exec[p],
+                "work_survey": work_survey[p], "achieved_survey_count": a_sv,
+                "frac_survey_count": a_sv / out["peak"]})
+    return out
+
+
 def roofline(phase_ms, work_exec, work_survey, units, prec):
     """Roofline of the phase with the largest summed time. phase_ms: {phase: ms};
     work_*: {phase: amount} summed over the same builds."""
     best = max((p for p in phase_ms if p in work_exec and phase_ms[p] > 0), key=lambda p: phase_ms[p])
-    s = phase_ms[best] / 1e3
-    unit = units[best]
-    if unit == "byte":
-        a, a_sv = work_exec[best] / s / 1e9, work_survey[best] / s / 1e9
-        out = {"bound": "hbm", "achieved": a, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-               "frac": a / PEAK["hbm_GBs"]}
-    else:
-        a, a_sv = work_exec[best] / s / 1e12, work_survey[best] / s / 1e12
-        peak = PEAK["fp64_TF"] if best in FP64_CORES[prec] else PEAK["fp32_TF"]
-        out = {"bound": "mfma", "achieved": a, "peak": peak, "unit": "TFLOP/s", "frac": a / peak}
-    out.update({"traffic": None, "phase": best, "phase_ms": phase_ms[best],
-                "work_executed": work_exec[best], "work_survey": work_survey[best],
-                "achieved_survey_count": a_sv, "frac_survey_count": a_sv / out["peak"]})
+    out = phase_rate(best, phase_ms, work_exec, work_survey, units, prec)
+    out.update({"traffic": traffic_for(best), "phase": best})
     return out
 
 
@@ -578,6 +613,39 @@ def bench_select5(args):
     print(json.dumps(out), flush=True)
 
 
+def profile_target_ring(args, config):
+    """A profiler's target for one ring cell: one untimed build per precision
+    (F64, MIXED, F32), a marker dispatch (one-row exx_mlp_moments), one build per
+    precision again (the measured ones), then a plain 1 GiB device copy whose
+    counter readings calibrate the traffic counters."""
+    import torch
+
+    import synth
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    cell = synth.make_config(config)
+    gold = load_json(f"config{config}.json")
+    t = cell_inputs(h, exx, torch, cell, dev, pts=gold["pts"] if gold else None)
+    o = outputs(torch, cell, dev)
+    for rep in range(2):
+        if rep == 1:
+            exx.exx_mlp_moments(h, torch.zeros((1, 3), dtype=torch.float32, device=dev),
+                                torch.zeros((6,), dtype=torch.float64, device=dev))
+            torch.cuda.synchronize()
+        for prec in ("f64", "mixed", "f32"):
+            exx.exx_build(h, t["cell"], exx.PREC[prec], psi_for(t, prec, torch), t["occ_pts"],
+                          t["ao_pts"], t["pts"], o["K"], o["Ex"], o["rank"])
+            torch.cuda.synchronize()
+        log(f"profile target: ring cell {config}, pass {rep} done")
+    src = torch.ones((1 << 27,), dtype=torch.float64, device=dev)  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"profile target: copied {src.numel() * 8} bytes")
+
+
 def profile_target(args):
     """The headline step for a profiler: the 24-cell batch in the mixed mode on
     concurrent lanes (after one untimed warm-up batch, which also tunes the tiles,
@@ -633,7 +701,10 @@ def main():
         bench_select5(args)
         return
     if args.profile:
-        profile_target(args)
+        if args.workload in ("rings-k2", "rings-k3"):
+            profile_target_ring(args, 2 if args.workload == "rings-k2" else 3)
+        else:
+            profile_target(args)
         return
 
     import torch
@@ -691,6 +762,8 @@ def main():
         "batched_per_cell": {p: {"dEx": res[p].get("dEx_per_cell"), "dK": res[p].get("dK_per_cell")}
                              for p in res},
         "phases_ms_batch_mixed": phase_ms,
+        "phase_rates_batch_mixed": {p: phase_rate(p, phase_ms, wex, wsv, units, chosen)
+                                    for p in wex if phase_ms.get(p, 0) > 0},
         "paths": legs,
     }
     if not args.no_cpu:
