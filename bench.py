@@ -400,6 +400,16 @@ def batch_leg(args, h, exx, torch, dev):
     res = {}
     s_seq = time_steps(sequential_f64, steps, warmup, torch)
     log(f"[batch24] 24 sequential plain-FP64 builds: {s_seq * 1e3:.1f} ms")
+    seq_mixed = items("mixed")
+
+    def sequential_mixed():
+        for it in seq_mixed:
+            exx.exx_build(h, it["cell"], exx.EXX_MIXED, it["psi_grid"], it["occ_pts"],
+                          it["ao_pts"], it["pts"], it["K"], it["Ex"], it["rank"])
+
+    s_seq_mixed = time_steps(sequential_mixed, steps, warmup, torch)
+    del seq_mixed
+    log(f"[batch24] 24 sequential MIXED builds: {s_seq_mixed * 1e3:.1f} ms")
     seq_err = batch_errors(seq, gold, goldK) if gold else None
     its_by_prec = {}
     for prec in ("mixed", "f32", "f64"):
@@ -416,6 +426,8 @@ def batch_leg(args, h, exx, torch, dev):
         s = t_mode[mode]
         r = {"seconds": s, "builds_per_s": 24.0 / s, "speedup_vs_sequential_f64": s_seq / s,
              "mode": mode, "seconds_by_mode": t_mode}
+        if prec == "mixed":
+            r["speedup_vs_sequential_same_precision"] = s_seq_mixed / s
         if gold:
             dE, dK = batch_errors(its, gold, goldK)
             r.update({"max_dEx_vs_oracle": max(dE), "max_dK_vs_oracle": max(dK),
@@ -426,7 +438,8 @@ def batch_leg(args, h, exx, torch, dev):
         log(f"[batch24] batched {prec}: {s * 1e3:.1f} ms ({s_seq / s:.2f}x sequential FP64)" +
             (f", max|dEx| {r['max_dEx_vs_oracle']:.2e}, max|dK| {r['max_dK_vs_oracle']:.2e}, "
              f"{r['cells_meeting_gate']}/24 cells in the gate" if gold else ""))
-    seq_r = {"seconds": s_seq, "builds_per_s": 24.0 / s_seq}
+    seq_r = {"seconds": s_seq, "builds_per_s": 24.0 / s_seq,
+             "sequential_mixed_seconds": s_seq_mixed}
     if seq_err:
         seq_r.update({"max_dEx_vs_oracle": max(seq_err[0]), "max_dK_vs_oracle": max(seq_err[1])})
 

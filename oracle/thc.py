@@ -290,3 +290,65 @@ def thc_ao_k(L, grid, kmesh, phi, psi, pts, rel_tol=1e-12):
     Y, K, Ex = contract(tuple(int(x) for x in kmesh), G, X, fit["Vb"])
     return dict(K=K, Ex=Ex, Vb=fit["Vb"], rank=fit["rank"], Y=Y, S=fit["S"], keep=fit["keep"])
 
+
+def thc_oo_k_gradient(L, grid, kmesh, psi, phi, pts, rel_tol=1e-12):
+    """The derivative of the fitted exchange energy in the AO density matrices:
+    the full exchange matrix whose occupied-virtual block is the orbital
+    gradient of Sec. 2.3 (Eq. 19; the dM/dtheta step of Algorithm 2).
+
+    With the per-transfer fit xi^m = (S^m)^{-1} Z^m (on the retained points) and
+    V^m = xi^m Vop xi^m^H (Vop the Coulomb operator of steps 5-6), the energy of
+    step 9 is E = -(1/N_k^2) sum_m Tr(V^m S^m) = -(1/N_k^2) sum_m Tr((S^m)^{-1}
+    Z^m Vop Z^m^H), so that
+      dE = (1/N_k^2) sum_m [Tr(V^m dS^m) - 2 Re sum_{P,r} dZ^m(P,r) conj Phi^m_P(r)],
+      Phi^m_P(r) = (Omega/N_g^2) sum_g e^{i g.r} v^m(g) F^m_P(g)  (the potential of xi^m_P).
+    S^m and Z^m depend on the density through G^n and Gamma^n (steps 1-3), and
+    those on the AO density matrices D^n = C^n C^n^H through
+    Gamma^n(P,r) = sum_{mu,nu} phi_mu^n(r_P) D^n_{mu nu} conj phi_nu^n(r). Collecting
+    the coefficient of dD gives dE = Re sum_n sum_{mu nu} dD^n_{mu nu} A^n_{mu nu}
+    and, for Hermitian dD, dE = -(2/N_k) sum_n Tr(Kgrad^n dD^n) with
+    Kgrad^n = -(N_k/4) (A^n + A^n^H)^T. (Holding V^m fixed instead gives the K of
+    steps 7-8 in the same normalisation.) Both terms of each product rule are
+    written out (no symmetry between m and -m is used).
+
+    phi: AO functions on the grid (N_k, N, N_g). Returns K, Kgrad, Ex, rank.
+    """
+    L = np.asarray(L, dtype=np.float64)
+    grid = tuple(int(x) for x in grid)
+    kmesh = tuple(int(x) for x in kmesh)
+    pts = np.asarray(pts, dtype=np.int64)
+    nk, no, ng = psi.shape
+    nI = len(pts)
+    omega = float(np.prod(L))
+    ao_pts = np.stack([phi[n][:, pts] for n in range(nk)])
+    o = thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol, keep_intermediates=("xi",))
+    Psi, X, G = gather(psi, pts, ao_pts)
+    rP = coulomb.positions(L, grid, pts)
+    r_all = coulomb.positions(L, grid)
+    Gam = np.stack([_gamma(Psi[n], psi[n]) for n in range(nk)])
+    # Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r) and U^m_PQ = V^m_QP e^{i q_m.(r_P - r_Q)}
+    Pw = np.empty((nk, nI, ng), dtype=np.complex128)
+    U = np.empty((nk, nI, nI), dtype=np.complex128)
+    for m in range(nk):
+        q = coulomb.qvec(L, kmesh, m)
+        F = sfft.fftn(o["xi"][m].reshape((nI,) + grid), axes=(1, 2, 3), workers=WORKERS)
+        v = coulomb.kernel(L, grid, kmesh, m)
+        Phi = (omega / ng) * sfft.ifftn(F * v[None], axes=(1, 2, 3), workers=WORKERS).reshape(nI, ng)
+        eP = np.exp(1j * (rP @ q))
+        Pw[m] = eP[:, None] * np.exp(-1j * (r_all @ q))[None, :] * Phi.conj()
+        U[m] = o["V"][m].T * (eP[:, None] * eP.conj()[None, :])
+    Kgrad = np.empty_like(o["K"])
+    for n in range(nk):
+        CS = np.zeros((nI, nI), dtype=np.complex128)
+        CZ = np.zeros((nI, ng), dtype=np.complex128)
+        for m in range(nk):
+            up = coulomb.add_index(kmesh, n, m)                       # n + m
+            dn = [k for k in range(nk) if coulomb.add_index(kmesh, k, m) == n][0]  # n - m
+            CS += U[m] * G[up].conj() + U[m].conj() * G[dn].conj()
+            CZ += Pw[m] * Gam[up].conj() + Pw[m].conj() * Gam[dn].conj()
+        NS = ao_pts[n] @ CS @ ao_pts[n].conj().T
+        NZ = ao_pts[n] @ CZ @ phi[n].conj().T
+        A = (NS - 2.0 * NZ) / nk ** 2
+        Kgrad[n] = -(nk / 4.0) * (A + A.conj().T).T
+    return dict(K=o["K"], Kgrad=Kgrad, Ex=o["Ex"], rank=o["rank"])
+

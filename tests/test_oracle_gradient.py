@@ -1,0 +1,69 @@
+"""Pins of the gradient oracle (thc.thc_oo_k_gradient: the derivative of the fitted
+exchange energy in the AO density matrices, whose occupied-virtual block is the
+orbital gradient of Eq. 19) against facts other than itself:
+
+* central finite differences of the oracle's fitted energy E(C + eps dC) along
+  random complex directions of the orbital coefficients (so every AO entry,
+  occupied-virtual included, is exercised), at two step sizes whose error
+  ratio shows the second-order convergence of the difference quotient;
+* Euler's identity for the energy, homogeneous of degree two in the density:
+  -(1/N_k) sum_n Tr(Kgrad^n D^n) = E_x;
+* the gradient is not the fixed-V exchange matrix K: along the same directions
+  K's directional derivative differs (the fit's own dependence on the
+  orbitals matters), and the test requires the two to differ.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import select, thc
+
+
+def _cell(kind):
+    if kind == "k211":
+        return synth.make_random_cell((5.0, 5.5, 6.0), 2, (10, 10, 12), (2, 1, 1), 2, 14, (7, 7, 7))
+    if kind == "k211-low":  # N_ISDF 12 below the pair rank N_k n_occ^2 = 18: an approximate fit
+        return synth.make_random_cell((5.0, 5.5, 6.0), 2, (10, 10, 12), (2, 1, 1), 3, 12, (7, 7, 6))
+    if kind == "k311":
+        return synth.make_random_cell((6.0, 5.0, 5.0), 2, (12, 10, 10), (3, 1, 1), 2, 16, (7, 7, 8))
+    return synth.make_random_cell((6.0, 6.0, 6.0), 3, (12, 12, 12), (1, 1, 1), 3, 12, (7, 7, 9))
+
+
+def _directional(Kg, C, dC, nk):
+    return sum(-(2.0 / nk) * np.trace(Kg[n] @ (dC[n] @ C[n].conj().T + C[n] @ dC[n].conj().T)).real
+               for n in range(nk))
+
+
+@pytest.mark.parametrize("kind", ["k211", "k211-low", "k311", "gamma"])
+def test_gradient_matches_finite_differences(kind):
+    c = _cell(kind)
+    C = synth.orbital_coeffs(c)
+    psi = synth.orbitals_on_grid(c, C)
+    phi = np.stack([synth.ao_on_grid(c, n) for n in range(c.N_k)])
+    pts, _ = select.select_points(psi, c.n_isdf)
+    g = thc.thc_oo_k_gradient(c.L, c.grid, c.kmesh, psi, phi, pts)
+    ao = np.stack([phi[n][:, pts] for n in range(c.N_k)])
+    rng = np.random.default_rng([len(kind), c.N_k, 5])
+    dC = [rng.standard_normal(Cn.shape) + 1j * rng.standard_normal(Cn.shape) for Cn in C]
+
+    def energy(eps):
+        Cp = [Cn + eps * d for Cn, d in zip(C, dC)]
+        return thc.thc_oo_k(c.L, c.grid, c.kmesh, synth.orbitals_on_grid(c, Cp), pts, ao)["Ex"]
+
+    an = _directional(g["Kgrad"], C, dC, c.N_k)
+    errs = []
+    for eps in (1e-3, 1e-4):
+        fd = (energy(eps) - energy(-eps)) / (2 * eps)
+        errs.append(abs(fd - an) / abs(fd))
+    print(f"{kind}: rank {g['rank']}, analytic {an:.10f}, rel errors {errs[0]:.2e}, {errs[1]:.2e}")
+    assert errs[1] <= 5e-6
+    assert errs[1] <= errs[0] / 30          # O(eps^2): a factor 100 for a factor 10 in eps
+    fixed_v = _directional(g["K"], C, dC, c.N_k)
+    assert abs(fixed_v - an) > 1e-3 * abs(an)
+    # Euler (degree two) and Hermiticity
+    D = [Cn @ Cn.conj().T for Cn in C]
+    e_euler = -(1.0 / c.N_k) * sum(np.trace(g["Kgrad"][n] @ D[n]).real for n in range(c.N_k))
+    assert abs(e_euler - g["Ex"]) <= 1e-10 * abs(g["Ex"])
+    for n in range(c.N_k):
+        assert np.abs(g["Kgrad"][n] - g["Kgrad"][n].conj().T).max() <= 1e-12 * np.abs(g["Kgrad"]).max()
