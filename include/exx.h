@@ -123,6 +123,7 @@ exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes);
  *                        an exx_build_batched item (the largest of them)
  *   EXX_CALL_SELECT      exx_select_points
  *   EXX_CALL_SELECT_MLP  exx_select_points_mlp (n_probe up to 8192)
+ *   EXX_CALL_GRADIENT    exx_exchange_gradient (prec ignored: FP64)
  * exx_set_workspace hands the handle a device buffer (256-byte aligned, caller
  * owned, e.g. a torch tensor) that every later call uses as its scratch; the
  * library then allocates no scratch of its own and releases what it held. A
@@ -136,6 +137,7 @@ exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes);
 #define EXX_CALL_BUILD 0
 #define EXX_CALL_SELECT 1
 #define EXX_CALL_SELECT_MLP 2
+#define EXX_CALL_GRADIENT 3
 exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec prec, int32_t call,
                               size_t* bytes);
 exx_status exx_set_workspace(exx_handle_t h, void* dev, size_t bytes);
@@ -265,6 +267,38 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec,
                      const void* psi_grid, const void* occ_pts, const void* ao_pts,
                      const int32_t* pts, void* K, double* Ex, int32_t* rank,
                      hipStream_t stream);
+
+/*
+ * exx_exchange_gradient -- the derivative of the fitted exchange energy in the
+ * AO density matrices (Sec. 2.3, Eq. 19: its occupied-virtual block C_v^H Kgrad
+ * C_o is the orbital gradient of the exchange energy), together with the
+ * K-build of exx_build. The fit xi^m and the Coulomb matrices depend on the
+ * density through G^n and Gamma^n, so the derivative of
+ * E_x = -(1/N_k^2) sum_m Tr((S^m)^+ Z^m Vop Z^m^H) has, besides the fixed-fit
+ * term that gives K, the terms of dS^m and dZ^m:
+ *   dE_x = (1/N_k^2) sum_m [Tr(V^m dS^m) - 2 Re sum_{P,r} dZ^m(P,r) conj Phi^m_P(r)],
+ *   Phi^m_P(r) = (Omega/N_g^2) sum_g e^{i g.r} v^m(g) F^m_P(g)
+ * (the potential of xi^m_P, F^m_P its transform). With A^n the coefficient of
+ * dD^n in dE_x = Re sum_n sum_{mu nu} dD^n_{mu nu} A^n_{mu nu}, the output is
+ *   Kgrad^n = -(N_k/4) (A^n + A^n^H)^T,
+ * normalised like K (dE_x = -(2/N_k) sum_n Tr(Kgrad^n dD^n) for Hermitian dD^n,
+ * E_x = -(1/N_k) sum_n Tr(Kgrad^n D^n)); holding V^m fixed instead gives K.
+ * A reference path: the per-transfer fit, every array in FP64, the
+ * potentials by one more forward transform of conj(v^m F^m), the k-mesh sums
+ * by plain kernels and the AO contractions on the FP64 matrix cores.
+ *
+ *   psi_grid, occ_pts, ao_pts, pts, K, Ex, rank as in exx_build (EXX_F64)
+ *   ao_grid  [N_k][n_ao][N_g] c128: the AO functions phi^n_mu on the grid
+ *   Kgrad    out [N_k][n_ao][n_ao] c128, Hermitian
+ * prec must be EXX_F64 (else EXX_ERR_UNSUPPORTED). Scratch: three grid-sized
+ * complex128 arrays [N_k][N_ISDF][N_g] plus the build's point-sized ones
+ * (exx_workspace_size with EXX_CALL_GRADIENT). Ordered on `stream` like
+ * exx_build; error behaviour as above.
+ */
+exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                                 const void* psi_grid, const void* occ_pts, const void* ao_pts,
+                                 const void* ao_grid, const int32_t* pts, void* K, void* Kgrad,
+                                 double* Ex, int32_t* rank, hipStream_t stream);
 
 /*
  * exx_select_points -- interpolation points by QR with column pivoting

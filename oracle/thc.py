@@ -311,7 +311,8 @@ def thc_oo_k_gradient(L, grid, kmesh, psi, phi, pts, rel_tol=1e-12):
     steps 7-8 in the same normalisation.) Both terms of each product rule are
     written out (no symmetry between m and -m is used).
 
-    phi: AO functions on the grid (N_k, N, N_g). Returns K, Kgrad, Ex, rank.
+    phi: AO functions on the grid (N_k, N, N_g). Returns K, Kgrad, Ex, rank (and
+    the metrics S with their retained points keep).
     """
     L = np.asarray(L, dtype=np.float64)
     grid = tuple(int(x) for x in grid)
@@ -350,5 +351,5 @@ def thc_oo_k_gradient(L, grid, kmesh, psi, phi, pts, rel_tol=1e-12):
         NZ = ao_pts[n] @ CZ @ phi[n].conj().T
         A = (NS - 2.0 * NZ) / nk ** 2
         Kgrad[n] = -(nk / 4.0) * (A + A.conj().T).T
-    return dict(K=o["K"], Kgrad=Kgrad, Ex=o["Ex"], rank=o["rank"])
+    return dict(K=o["K"], Kgrad=Kgrad, Ex=o["Ex"], rank=o["rank"], S=o["S"], keep=o["keep"])
 

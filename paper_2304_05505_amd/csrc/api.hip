@@ -238,18 +238,22 @@ PairedDims paired_dims(const exx_context* h, const Geom& g, size_t cs) {
 // scratch layout shared by the three calls
 struct Layout {
   size_t G, Lf, W, Sp, keep, Y, T, epart, cpart, S2, V2, rank2, tol, Tinv, grid, grid2, F, total;
+  // the exchange gradient's buffers: a third grid-sized array, the kernel table,
+  // the point-sized correlation and the AO-sized products
+  size_t g3, gvt, gCS, gT, gA;
   int nsplit;
   PairedDims pd;
 };
 
 // what a call needs besides the point-sized matrices
-enum Need { NEED_FIT = 1, NEED_COULOMB = 2, NEED_K = 4, NEED_BUILD = 8 };
+enum Need { NEED_FIT = 1, NEED_COULOMB = 2, NEED_K = 4, NEED_BUILD = 8, NEED_GRAD = 16 };
 
 Layout layout(const exx_context* h, const Geom& g, exx_prec prec, int need) {
-  const bool build = (need & NEED_BUILD) != 0;
-  const bool grid = (need & (NEED_FIT | NEED_COULOMB | NEED_BUILD)) != 0;
-  const bool paired = build && build_path(h, g) == PATH_PAIRED;
-  const bool shared = build && build_path(h, g) == PATH_SHARED;
+  const bool grad = (need & NEED_GRAD) != 0;
+  const bool build = (need & NEED_BUILD) != 0 || grad;
+  const bool grid = (need & (NEED_FIT | NEED_COULOMB | NEED_BUILD | NEED_GRAD)) != 0;
+  const bool paired = !grad && build && build_path(h, g) == PATH_PAIRED;
+  const bool shared = !grad && build && build_path(h, g) == PATH_SHARED;
   Layout L;
   const size_t mat = al(sizeof(double2) * (size_t)g.nk * g.ni * g.ni);
   // Gamma/Z (and F) buffer: FP64 unless the fit itself runs in FP32; xi: FP64 only in EXX_F64
@@ -303,6 +307,19 @@ Layout layout(const exx_context* h, const Geom& g, exx_prec prec, int need) {
     o += 2 * al(cx * (size_t)L.pd.per * g.ni * g.ng);
   else if (shared)  // the one transform
     o += al(cx * (size_t)g.ni * g.ng);
+  L.g3 = L.gvt = L.gCS = L.gT = L.gA = o;
+  if (grad) {
+    L.g3 = o;
+    o += al(sizeof(double2) * (size_t)g.nk * g.ni * g.ng);
+    L.gvt = o;
+    o += al(sizeof(double) * (size_t)g.nk * g.ng);
+    L.gCS = o;
+    o += mat;
+    L.gT = o;
+    o += al(sizeof(double2) * (size_t)g.nk * g.ni * g.nao);
+    L.gA = o;
+    o += al(sizeof(double2) * (size_t)g.nk * g.nao * g.nao);
+  }
   L.total = o;
   return L;
 }
@@ -1410,6 +1427,77 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   return s == EXX_OK ? finish(h, stream) : s;
 }
 
+exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                                 const void* psi_grid, const void* occ_pts, const void* ao_pts,
+                                 const void* ao_grid, const int32_t* pts, void* K, void* Kgrad,
+                                 double* Ex, int32_t* rank, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  if (!psi_grid || !occ_pts || !ao_pts || !ao_grid || !pts || !K || !Kgrad || !Ex || !rank)
+    return fail(h, EXX_ERR_ARG, "exx_exchange_gradient: null array argument");
+  if (cell && prec != EXX_F64)
+    return fail(h, EXX_ERR_UNSUPPORTED, "exx_exchange_gradient: FP64 (EXX_F64) only");
+  Geom g;
+  Tables tb;
+  Layout L;
+  char* ws;
+  exx_status s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
+  if (s != EXX_OK) return s;
+  s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
+  if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
+  if (s != EXX_OK) return s;
+  // the fit (xi into grid2, S into S2), V^m (Bloch gauge, into V2; the transforms
+  // F^m stay in grid), K and E_x with the fit's G^n
+  void* xi = ws + L.grid2;
+  s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, ws + L.S2, rank,
+                               stream);
+  if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream);
+  if (s == EXX_OK)
+    s = buildK_impl(h, g, kscratch(ws, L), ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
+  if (s != EXX_OK) return s;
+  const long nn = (long)g.ni * g.ni, na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
+  double* vt = (double*)(ws + L.gvt);
+  hipError_t e = launch_kernel_table(g, vt, stream);
+  if (e != hipSuccess) return hip_check(h, e, "kernel table");
+  // conj Phi^m scaled by N_g^2 / Omega: the forward transform of conj(v^m F^m)
+  // (xi is no longer needed: grid2 takes the potentials)
+  e = launch_kernel_scale_conj(g, ws + L.grid, vt, stream);
+  if (e == hipSuccess)
+    e = launch_fft3d<double>(g, tb, ws + L.grid, ws + L.grid2, (long)g.nk * g.ni, h->ncu, stream);
+  if (e != hipSuccess) return hip_check(h, e, "potentials");
+  // Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r)
+  const double omega = (double)g.L[0] * g.L[1] * g.L[2];
+  e = launch_potential_phase(g, tb, ws + L.grid2, pts, omega / ((double)g.ng * g.ng), stream);
+  if (e != hipSuccess) return hip_check(h, e, "potential phase");
+  // Gamma^n again (the fit turned its copy into Z^m), into grid
+  e = launch_gamma<double>(g, occ_pts, psi_grid, ws + L.grid, stream);
+  if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
+  // CZ^n over the grid and CS^n over the points (U^m = conj Vb^m: Vb^m is Hermitian)
+  e = launch_grad_xcorr(g, ws + L.grid2, false, ws + L.grid, ws + L.g3, nig, stream);
+  if (e == hipSuccess)
+    e = launch_grad_xcorr(g, ws + L.V2, true, ws + L.G, ws + L.gCS, nn, stream);
+  if (e != hipSuccess) return hip_check(h, e, "k-correlation of the derivative");
+  // T = CS conj(X^T) - 2 CZ conj(phi)^T, then conj A = (1/N_k^2) X^H conj T
+  double2* T = (double2*)(ws + L.gT);
+  e = gemm<double, double, double, double>(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig,
+                                           B_C, ao_grid, g.ng, (long)g.nao * g.ng, T, g.nao, na_i,
+                                           -2.0, false, stream);
+  if (e == hipSuccess)
+    e = gemm<double, double, double, double>(g.ni, g.nao, g.ni, g.nk, A_N, ws + L.gCS, g.ni, nn,
+                                             B_R, ao_pts, g.nao, na_i, T, g.nao, na_i, 1.0, true,
+                                             stream);
+  if (e == hipSuccess)
+    e = gemm<double, double, double, double>(g.nao, g.nao, g.ni, g.nk, A_C, ao_pts, g.nao, na_i,
+                                             B_R, T, g.nao, na_i, ws + L.gA, g.nao,
+                                             (long)g.nao * g.nao, 1.0 / ((double)g.nk * g.nk),
+                                             false, stream);
+  if (e != hipSuccess) return hip_check(h, e, "AO contraction of the derivative");
+  e = launch_grad_assemble(g, ws + L.gA, Kgrad, stream);
+  if (e != hipSuccess) return hip_check(h, e, "gradient assembly");
+  s = scan(h, Kgrad, 2L * g.nk * g.nao * g.nao, SITE_OUTPUT, stream);
+  return s == EXX_OK ? finish(h, stream) : s;
+}
+
 exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec prec, int32_t call,
                               size_t* bytes) {
   if (!h) return EXX_ERR_ARG;
@@ -1422,6 +1510,10 @@ exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec pre
       size_t b = layout(h, g, prec, NEED_BUILD).total;
     b = std::max(b, layout(h, g, prec, NEED_FIT | NEED_COULOMB | NEED_K).total);
     *bytes = b;
+    return EXX_OK;
+  }
+  if (call == EXX_CALL_GRADIENT) {
+    *bytes = layout(h, g, EXX_F64, NEED_GRAD).total;
     return EXX_OK;
   }
   if (call == EXX_CALL_SELECT) {

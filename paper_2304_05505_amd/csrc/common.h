@@ -421,6 +421,21 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
                           const int* rep = nullptr, const int* bar = nullptr, int nslice = 0,
                           bool raw = false, int form = 0, bool shared_f = false);
 enum { COUL_F64 = 0, COUL_BF16 = 1, COUL_BF16X3 = 2 };
+// v^m(g) = 4 pi/|K|^2 (K-box rule, K = 0 dropped) of every transfer: vt [N_k][N_g]
+hipError_t launch_kernel_table(const Geom& g, double* vt, hipStream_t st);
+
+// density derivative of the fitted exchange energy (grad.hip), FP64:
+// F <- conj(v^m F) over [N_k][N_ISDF][N_g]
+hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hipStream_t st);
+// X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]
+hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, const int32_t* pts,
+                                  double scale, hipStream_t st);
+// out[n] = sum_m [p^m conj Q^{n+m} + conj(p^m) conj Q^{n-m}] over `elems` elements per
+// k, p^m = P^m (or conj P^m)
+hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
+                             long elems, hipStream_t st);
+// Kg[n][mu][nu] = -(N_k/4) (Ac[n][mu][nu] + conj Ac[n][nu][mu])
+hipError_t launch_grad_assemble(const Geom& g, const void* Ac, void* Kg, hipStream_t st);
 // V[rep[s]] = e^{-i q_m.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and, where
 // bar[s] >= 0, V[bar[s]] = conj of that; U holds nslice (<= 64) matrices
 hipError_t launch_coulomb_phase(const Geom& g, const Tables& tb, const int32_t* pts,

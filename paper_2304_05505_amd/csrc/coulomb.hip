@@ -1013,6 +1013,23 @@ template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void
                                           void*, int, double2*, bool, hipStream_t, const int*,
                                           const int*, int, bool, int, bool);
 
+// v^m(g) of every transfer: vt [N_k][N_g]
+hipError_t launch_kernel_table(const Geom& g, double* vt, hipStream_t st) {
+  CoulArgs a;
+  for (int m = 0; m < 64; ++m) a.rep[m] = m < g.nk ? m : 0;
+  for (int i = 0; i < 3; ++i) {
+    a.L[i] = g.L[i];
+    a.n[i] = g.n[i];
+    a.N[i] = g.N[i];
+  }
+  a.ng = g.ng;
+  a.ni = g.ni;
+  a.nk = g.nk;
+  hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), g.nk), dim3(256),
+                     0, st, vt, a);
+  return hipGetLastError();
+}
+
 // V[rep[s]] = e^{-i q.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and
 // V[bar[s]] = conj of that, for the nslice unphased matrices U
 hipError_t launch_coulomb_phase(const Geom& g, const Tables& tb, const int32_t* pts,

@@ -135,6 +135,7 @@ hipError_t gemm(int M, int N, int K, int batch, OpA oa, const void* A, long lda,
   EXX_GEMM_CASE(A_N, B_R)
   EXX_GEMM_CASE(A_N, B_C)
   EXX_GEMM_CASE(A_C, B_N)
+  EXX_GEMM_CASE(A_C, B_R)
 #undef EXX_GEMM_CASE
   return hipErrorInvalidValue;
 }

@@ -1,0 +1,162 @@
+// Kernels of the density derivative of the fitted exchange energy (the
+// occupied-virtual block of Sec. 2.3, Eq. 19): the potentials of the fitted
+// functions on the grid, their k-mesh cross-correlations with Gamma^n and G^n,
+// and the Hermitian assembly. The transforms, the Gamma^n and the AO-basis
+// contractions reuse the build's FFT and GEMM kernels.
+#include "common.h"
+
+namespace exx {
+
+namespace {
+
+struct GradMesh {
+  int N[3];
+  int nk;
+};
+
+__device__ __forceinline__ int mesh_add(const GradMesh& a, int n, int m, int sign) {
+  const int n1 = n / (a.N[1] * a.N[2]), n2 = (n / a.N[2]) % a.N[1], n3 = n % a.N[2];
+  const int m1 = m / (a.N[1] * a.N[2]), m2 = (m / a.N[2]) % a.N[1], m3 = m % a.N[2];
+  const int r1 = (n1 + sign * m1 + a.N[0]) % a.N[0];
+  const int r2 = (n2 + sign * m2 + a.N[1]) % a.N[1];
+  const int r3 = (n3 + sign * m3 + a.N[2]) % a.N[2];
+  return (r1 * a.N[1] + r2) * a.N[2] + r3;
+}
+
+// F[m][P][g] <- conj(v^m(g) F[m][P][g])
+__global__ __launch_bounds__(256) void kernel_scale_conj_kernel(double2* __restrict__ F,
+                                                                const double* __restrict__ vt,
+                                                                long per_m, long ng, long total) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const long m = e / per_m;
+  const long g = e % ng;
+  const double v = vt[m * ng + g];
+  const double2 f = F[e];
+  F[e] = make_double2(v * f.x, -v * f.y);
+}
+
+struct PhaseArgs {
+  const double2* root[3];  // e^{-2 pi i t / (N_a n_a)}
+  int n[3], N[3];
+  int ni;
+  long ng;
+  double scale;
+};
+
+// X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]
+__global__ __launch_bounds__(256) void potential_phase_kernel(double2* __restrict__ X,
+                                                              const int32_t* __restrict__ pts,
+                                                              PhaseArgs a, long total) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const long r = e % a.ng;
+  const long mp = e / a.ng;
+  const int P = (int)(mp % a.ni);
+  const int m = (int)(mp / a.ni);
+  const int n23 = a.n[1] * a.n[2];
+  const int gp = pts[P];
+  const int pc[3] = {gp / n23, (gp / a.n[2]) % a.n[1], gp % a.n[2]};
+  const int rc[3] = {(int)(r / n23), (int)((r / a.n[2]) % a.n[1]), (int)(r % a.n[2])};
+  const int mm[3] = {m / (a.N[1] * a.N[2]), (m / a.N[2]) % a.N[1], m % a.N[2]};
+  // e^{i q.(r_P - r)} = prod_a conj(root_a[m_a p_a]) root_a[m_a c_a]
+  double px = a.scale, py = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int Lr = a.N[ax] * a.n[ax];
+    const double2 fp = a.root[ax][(mm[ax] * pc[ax]) % Lr];
+    const double2 fc = a.root[ax][(mm[ax] * rc[ax]) % Lr];
+    const double wx = fp.x * fc.x + fp.y * fc.y, wy = fp.x * fc.y - fp.y * fc.x;
+    const double tx = px * wx - py * wy;
+    py = px * wy + py * wx;
+    px = tx;
+  }
+  const double2 x = X[e];
+  X[e] = make_double2(px * x.x - py * x.y, px * x.y + py * x.x);
+}
+
+// out[n][e] = sum_m [p^m(e) conj Q^{n+m}(e) + conj(p^m(e)) conj Q^{n-m}(e)],
+// p^m = P^m, or conj(P^m) with CONJ_P
+template <bool CONJ_P>
+__global__ __launch_bounds__(256) void grad_xcorr_kernel(const double2* __restrict__ P,
+                                                         const double2* __restrict__ Q,
+                                                         double2* __restrict__ out, long elems,
+                                                         GradMesh a) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= elems) return;
+  for (int n = 0; n < a.nk; ++n) {
+    double sx = 0.0, sy = 0.0;
+    for (int m = 0; m < a.nk; ++m) {
+      double2 p = P[(long)m * elems + e];
+      if (CONJ_P) p.y = -p.y;
+      const double2 qu = Q[(long)mesh_add(a, n, m, 1) * elems + e];
+      const double2 qd = Q[(long)mesh_add(a, n, m, -1) * elems + e];
+      // p conj(qu) + conj(p) conj(qd)
+      sx += p.x * qu.x + p.y * qu.y + p.x * qd.x - p.y * qd.y;
+      sy += p.y * qu.x - p.x * qu.y - p.x * qd.y - p.y * qd.x;
+    }
+    out[(long)n * elems + e] = make_double2(sx, sy);
+  }
+}
+
+// Kg[n][mu][nu] = -(N_k/4) (Ac[n][mu][nu] + conj(Ac[n][nu][mu]))
+__global__ __launch_bounds__(256) void grad_assemble_kernel(const double2* __restrict__ Ac,
+                                                            double2* __restrict__ Kg, int nao,
+                                                            long total, double f) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const long nn = (long)nao * nao;
+  const long n = e / nn;
+  const int mu = (int)((e % nn) / nao), nu = (int)(e % nao);
+  const double2 a = Ac[e], b = Ac[n * nn + (long)nu * nao + mu];
+  Kg[e] = make_double2(f * (a.x + b.x), f * (a.y - b.y));
+}
+
+}  // namespace
+
+hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hipStream_t st) {
+  const long per_m = (long)g.ni * g.ng, total = per_m * g.nk;
+  hipLaunchKernelGGL(kernel_scale_conj_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     st, (double2*)F, vt, per_m, (long)g.ng, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, const int32_t* pts,
+                                  double scale, hipStream_t st) {
+  PhaseArgs a;
+  for (int ax = 0; ax < 3; ++ax) {
+    a.root[ax] = tb.root[ax];
+    a.n[ax] = g.n[ax];
+    a.N[ax] = g.N[ax];
+  }
+  a.ni = g.ni;
+  a.ng = g.ng;
+  a.scale = scale;
+  const long total = (long)g.nk * g.ni * g.ng;
+  hipLaunchKernelGGL(potential_phase_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     st, (double2*)X, pts, a, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
+                             long elems, hipStream_t st) {
+  GradMesh a;
+  for (int ax = 0; ax < 3; ++ax) a.N[ax] = g.N[ax];
+  a.nk = g.nk;
+  const dim3 grid((unsigned)((elems + 255) / 256));
+  if (conj_p)
+    hipLaunchKernelGGL(grad_xcorr_kernel<true>, grid, dim3(256), 0, st, (const double2*)P,
+                       (const double2*)Q, (double2*)out, elems, a);
+  else
+    hipLaunchKernelGGL(grad_xcorr_kernel<false>, grid, dim3(256), 0, st, (const double2*)P,
+                       (const double2*)Q, (double2*)out, elems, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_assemble(const Geom& g, const void* Ac, void* Kg, hipStream_t st) {
+  const long total = (long)g.nk * g.nao * g.nao;
+  hipLaunchKernelGGL(grad_assemble_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     (const double2*)Ac, (double2*)Kg, g.nao, total, -0.25 * g.nk);
+  return hipGetLastError();
+}
+
+}  // namespace exx

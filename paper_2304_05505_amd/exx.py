@@ -61,10 +61,11 @@ EXPORTED = (
     "exx_set_contraction",
     "exx_set_fit",
     "exx_mlp_moments",
+    "exx_exchange_gradient",
 )
 
 EXX_BATCH_GRAPH, EXX_BATCH_TUNE, EXX_BATCH_CONCURRENT = 1, 2, 4
-EXX_CALL_BUILD, EXX_CALL_SELECT, EXX_CALL_SELECT_MLP = 0, 1, 2
+EXX_CALL_BUILD, EXX_CALL_SELECT, EXX_CALL_SELECT_MLP, EXX_CALL_GRADIENT = 0, 1, 2, 3
 EXX_CHECK_FINITE, EXX_STRICT_PD, EXX_CHECK_SYNC = 1, 2, 4
 EXX_ERR_NOT_PD, EXX_ERR_NONFINITE = -4, -5
 EXX_CONTRACT_AUTO, EXX_CONTRACT_F64, EXX_CONTRACT_BF16, EXX_CONTRACT_BF16X3 = 0, 1, 2, 3
@@ -122,6 +123,8 @@ def _load():
         "exx_coulomb_V": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "exx_build_K": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "exx_build": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "exx_exchange_gradient": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+                                  ctypes.c_int),
         "exx_select_points": ([vp, cellp, vp, vp, vp, vp], ctypes.c_int),
         "exx_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "exx_set_refinement": ([vp, ctypes.c_int32], ctypes.c_int),
@@ -381,6 +384,25 @@ def exx_build(h: Handle, cell: ExxCell, prec: int, psi_grid, occ_pts, ao_pts, pt
         _ptr(rank, "rank", torch.int32, (nk,), d),
     )
     h._check(_lib.exx_build(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
+
+
+def exx_exchange_gradient(h: Handle, cell: ExxCell, psi_grid, occ_pts, ao_pts, ao_grid, pts, K,
+                          Kgrad, Ex, rank, prec: int = EXX_F64):
+    """K, E_x and the density derivative Kgrad of the fitted exchange energy (FP64)."""
+    nk, ng, ni, no, na = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ, cell.n_ao
+    d = h.device
+    args = (
+        _ptr(psi_grid, "psi_grid", torch.complex128, (nk, no, ng), d),
+        _ptr(occ_pts, "occ_pts", torch.complex128, (nk, ni, no), d),
+        _ptr(ao_pts, "ao_pts", torch.complex128, (nk, ni, na), d),
+        _ptr(ao_grid, "ao_grid", torch.complex128, (nk, na, ng), d),
+        _ptr(pts, "pts", torch.int32, (ni,), d),
+        _ptr(K, "K", torch.complex128, (nk, na, na), d),
+        _ptr(Kgrad, "Kgrad", torch.complex128, (nk, na, na), d),
+        _ptr(Ex, "Ex", torch.float64, (1,), d),
+        _ptr(rank, "rank", torch.int32, (nk,), d),
+    )
+    h._check(_lib.exx_exchange_gradient(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
 
 
 def exx_select_points(h: Handle, cell: ExxCell, psi_grid, pts, n_pivot):
