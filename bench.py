@@ -332,8 +332,39 @@ def ring_leg(config, args, h, exx, torch, dev):
              if "dEx_vs_oracle" in r else ""))
     for label in res:
         res[label]["speedup_vs_f64"] = res["f64"]["ms_per_build"] / res[label]["ms_per_build"]
+    if config == 2:  # the 3x3x3 cell's potentials would need ~150 GB more
+        res.update(potential_legs(args, h, exx, torch, dev, cell, t, res["f64"]["ms_per_build"],
+                                  tag))
     return {"workload": f"48-atom four-ring cell, {'x'.join(map(str, cell.kmesh))} k-mesh, N=192, "
                         f"n_occ=84, grid 60x75x54, N_ISDF=420", "paths": res}
+
+
+def potential_legs(args, h, exx, torch, dev, cell, t, f64_ms, tag):
+    """The FP64 calls that add the potentials of the fitted functions to a build:
+    the exchange gradient (K, E_x and Kgrad) and the robust-fit K, each timed as
+    one whole call (its build included) and against the FP64 build."""
+    from synth.fast import ao_on_grid_torch
+
+    ao_grid = torch.stack([ao_on_grid_torch(cell, n, dev) for n in range(cell.N_k)]).contiguous()
+    out = {}
+    o = outputs(torch, cell, dev)
+    Kg = torch.empty_like(o["K"])
+    calls = {
+        "f64-gradient": lambda: exx.exx_exchange_gradient(
+            h, t["cell"], t["psi64"], t["occ_pts"], t["ao_pts"], ao_grid, t["pts"], o["K"], Kg,
+            o["Ex"], o["rank"]),
+        "f64-robust": lambda: exx.exx_build_robust(
+            h, t["cell"], t["psi64"], t["occ_pts"], t["ao_pts"], ao_grid, t["pts"], o["K"],
+            o["Ex"], o["rank"]),
+    }
+    for label, fn in calls.items():
+        s = time_steps(fn, max(1, min(args.steps, 3)), 1, torch)
+        out[label] = {"ms_per_call": s * 1e3, "ratio_to_f64_build": s * 1e3 / f64_ms,
+                      "Ex": float(o["Ex"].cpu()[0]), "precision": "f64"}
+        log(f"[{tag}] {label}: {s * 1e3:.2f} ms/call ({s * 1e3 / f64_ms:.2f}x the FP64 build)")
+    del ao_grid, Kg
+    torch.cuda.empty_cache()
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -642,6 +673,25 @@ def profile_target_ring(args, config):
     gold = load_json(f"config{config}.json")
     t = cell_inputs(h, exx, torch, cell, dev, pts=gold["pts"] if gold else None)
     o = outputs(torch, cell, dev)
+    if args.potentials:
+        # the exchange gradient and the robust-fit K instead of the builds
+        from synth.fast import ao_on_grid_torch
+
+        ao_grid = torch.stack([ao_on_grid_torch(cell, n, dev) for n in range(cell.N_k)])
+        Kg = torch.empty_like(o["K"])
+        for rep in range(2):
+            if rep == 1:
+                exx.exx_mlp_moments(h, torch.zeros((1, 3), dtype=torch.float32, device=dev),
+                                    torch.zeros((6,), dtype=torch.float64, device=dev))
+                torch.cuda.synchronize()
+            exx.exx_exchange_gradient(h, t["cell"], t["psi64"], t["occ_pts"], t["ao_pts"], ao_grid,
+                                      t["pts"], o["K"], Kg, o["Ex"], o["rank"])
+            torch.cuda.synchronize()
+            exx.exx_build_robust(h, t["cell"], t["psi64"], t["occ_pts"], t["ao_pts"], ao_grid,
+                                 t["pts"], o["K"], o["Ex"], o["rank"])
+            torch.cuda.synchronize()
+            log(f"profile target: ring cell {config} potentials, pass {rep} done")
+        return
     for rep in range(2):
         if rep == 1:
             exx.exx_mlp_moments(h, torch.zeros((1, 3), dtype=torch.float32, device=dev),
@@ -703,6 +753,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true")
+    ap.add_argument("--potentials", action="store_true",
+                    help="with --profile and a ring workload: profile the exchange gradient "
+                         "and the robust-fit K instead of the builds")
     ap.add_argument("--workload", choices=("batch24", "rings-k2", "rings-k3", "select-k4"),
                     default="batch24")
     args = ap.parse_args()

@@ -123,7 +123,7 @@ exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes);
  *                        an exx_build_batched item (the largest of them)
  *   EXX_CALL_SELECT      exx_select_points
  *   EXX_CALL_SELECT_MLP  exx_select_points_mlp (n_probe up to 8192)
- *   EXX_CALL_GRADIENT    exx_exchange_gradient (prec ignored: FP64)
+ *   EXX_CALL_GRADIENT    exx_exchange_gradient, exx_build_robust (prec ignored: FP64)
  * exx_set_workspace hands the handle a device buffer (256-byte aligned, caller
  * owned, e.g. a torch tensor) that every later call uses as its scratch; the
  * library then allocates no scratch of its own and releases what it held. A
@@ -299,6 +299,37 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
                                  const void* psi_grid, const void* occ_pts, const void* ao_pts,
                                  const void* ao_grid, const int32_t* pts, void* K, void* Kgrad,
                                  double* Ex, int32_t* rank, hipStream_t stream);
+
+/*
+ * exx_build_robust -- the robust-fit exchange matrix (the one-sided fit that
+ * the discussion of Sec. 5 proposes for THC-oo-K): every exchange integral
+ * takes one exact and one fitted pair density,
+ *   K_rob = K[rho, rho~] + K[rho~, rho] - K[rho~, rho~],
+ * with K[a, b]^n_{mu nu} = (1/N_k) sum_{n' j} J^m[a_{mu j}, b_{nu j}] over the
+ * pairs rho_{mu j} = e^{-i q.r} conj phi_mu^n psi_jn' of direct exchange and
+ * rho~ their interpolation by the per-transfer occupied-pair fit; K[rho~, rho~]
+ * is exx_build's K. The error K_direct - K_rob = K[delta, delta] is second order
+ * in the fit's residual delta = rho - rho~ (first order for the plain fit), and
+ * at full occupied-pair rank the occupied rows C^H K_rob are exact. The
+ * one-sided term uses the potentials Phi^m of the fitted functions on the grid
+ * (one more transform of every F^m) and Gamma^n:
+ *   K[rho, rho~]^n = (1/N_k) conj(phi^n) R^n^T A^n,
+ *   R^n(Q, r) = sum_m e^{i q_m.(r_Q - r)} conj Phi^m_Q(r) conj Gamma^{n+m}(Q, r).
+ * E_x is the fitted one, which is also the robust energy (the least-squares
+ * fit projects the occupied pairs, so the two one-sided terms add up to the
+ * fitted energy). A reference path, FP64 only.
+ *
+ *   psi_grid, occ_pts, ao_pts, pts, Ex, rank as in exx_build (EXX_F64)
+ *   ao_grid  [N_k][n_ao][N_g] c128: the AO functions phi^n_mu on the grid
+ *   K        out [N_k][n_ao][n_ao] c128: K_rob, Hermitian
+ * prec must be EXX_F64 (else EXX_ERR_UNSUPPORTED); scratch as for
+ * exx_exchange_gradient (EXX_CALL_GRADIENT). Ordered on `stream` like
+ * exx_build; error behaviour as above.
+ */
+exx_status exx_build_robust(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                            const void* psi_grid, const void* occ_pts, const void* ao_pts,
+                            const void* ao_grid, const int32_t* pts, void* K, double* Ex,
+                            int32_t* rank, hipStream_t stream);
 
 /*
  * exx_select_points -- interpolation points by QR with column pivoting

@@ -291,6 +291,74 @@ def thc_ao_k(L, grid, kmesh, phi, psi, pts, rel_tol=1e-12):
     return dict(K=K, Ex=Ex, Vb=fit["Vb"], rank=fit["rank"], Y=Y, S=fit["S"], keep=fit["keep"])
 
 
+def phased_potentials(L, grid, kmesh, xi: np.ndarray, pts) -> np.ndarray:
+    """Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r) for every transfer, with
+    Phi^m_P(r) = (Omega/N_g^2) sum_g e^{i g.r} v^m(g) F^m_P(g) the Coulomb potential
+    of the fitted function xi^m_P (F^m_P its FFT; the paper's potentials of the
+    interpolating vectors, Sec. 2.3 and the discussion of the robust fit)."""
+    grid = tuple(int(x) for x in grid)
+    nk, nI, ng = xi.shape
+    omega = float(np.prod(L))
+    rP = coulomb.positions(L, grid, pts)
+    r_all = coulomb.positions(L, grid)
+    Pw = np.empty((nk, nI, ng), dtype=np.complex128)
+    for m in range(nk):
+        q = coulomb.qvec(L, kmesh, m)
+        F = sfft.fftn(xi[m].reshape((nI,) + grid), axes=(1, 2, 3), workers=WORKERS)
+        v = coulomb.kernel(L, grid, kmesh, m)
+        Phi = (omega / ng) * sfft.ifftn(F * v[None], axes=(1, 2, 3), workers=WORKERS).reshape(nI, ng)
+        Pw[m] = np.exp(1j * (rP @ q))[:, None] * np.exp(-1j * (r_all @ q))[None, :] * Phi.conj()
+    return Pw
+
+
+def thc_oo_k_robust(L, grid, kmesh, psi, phi, pts, rel_tol=1e-12):
+    """Robust-fit THC-oo-K (the one-sided fit of the discussion in Sec. 5): the
+    exchange matrix with one fitted and one exact pair density in each integral,
+      K_rob = K[rho, rho~] + K[rho~, rho] - K[rho~, rho~],
+    where K[a, b]^n_{mu nu} = (1/N_k) sum_{n' j} J^m[a_{mu j}, b_{nu j}] (the pair
+    densities of direct exchange), rho the exact pairs e^{-i q.r} conj phi_mu^n
+    psi_jn' and rho~ their interpolation sum_P xi^m_P(r) e^{-i q.r_P} conj
+    phi_mu^n(r_P) psi_jn'(r_P) with the per-transfer occupied-pair fit. Then
+    K_direct - K_rob = K[delta, delta] (delta = rho - rho~): second order in the
+    fit's residual, where K_fit = K[rho~, rho~] is first order.
+
+    The one-sided term needs the potentials Phi^m of the fitted functions on the
+    grid (never the exact pair potentials): with J[f1, f2] = sum_r f1(r) conj
+    Phi[f2](r) and the sum over j of the exact pair giving conj Gamma^{n'},
+      K[rho, rho~]^n = (1/N_k) conj(phi^n) R^n^T A^n,
+      R^n(Q, r) = sum_m Pw^m(Q, r) conj Gamma^{n+m}(Q, r),
+    A^n_{Q nu} = phi_nu^n(r_Q) and Pw as in phased_potentials. Its energy
+    E_cross = -(1/N_k^2) Re sum_n sum_{Q,r} Gamma^n(Q, r) R^n(Q, r) equals the
+    fitted E_x: the least-squares fit projects every occupied pair onto the fit
+    space, so the robust energy 2 E_cross - E_x is E_x itself; only K moves.
+
+    phi: AO functions on the grid (N_k, N, N_g). Returns K (robust), K_fit,
+    K_cross, Ex (fitted), Ex_rob (2 E_cross - E_x), rank, S, keep.
+    """
+    L = np.asarray(L, dtype=np.float64)
+    grid = tuple(int(x) for x in grid)
+    kmesh = tuple(int(x) for x in kmesh)
+    pts = np.asarray(pts, dtype=np.int64)
+    nk = psi.shape[0]
+    ao_pts = np.stack([phi[n][:, pts] for n in range(nk)])
+    o = thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol, keep_intermediates=("xi",))
+    Psi, X, G = gather(psi, pts, ao_pts)
+    Gam = np.stack([_gamma(Psi[n], psi[n]) for n in range(nk)])
+    Pw = phased_potentials(L, grid, kmesh, o["xi"], pts)
+    Kc = np.empty_like(o["K"])
+    e_cross = 0.0
+    for n in range(nk):
+        R = np.zeros_like(Pw[0])
+        for m in range(nk):
+            R += Pw[m] * Gam[coulomb.add_index(kmesh, n, m)].conj()
+        Kc[n] = phi[n].conj() @ R.T @ ao_pts[n].T / nk
+        e_cross += np.sum(Gam[n] * R).real
+    e_cross = -e_cross / nk ** 2
+    Kr = Kc + np.conj(np.transpose(Kc, (0, 2, 1))) - o["K"]
+    return dict(K=Kr, K_fit=o["K"], K_cross=Kc, Ex=o["Ex"], Ex_rob=2.0 * e_cross - o["Ex"],
+                rank=o["rank"], S=o["S"], keep=o["keep"])
+
+
 def thc_oo_k_gradient(L, grid, kmesh, psi, phi, pts, rel_tol=1e-12):
     """The derivative of the fitted exchange energy in the AO density matrices:
     the full exchange matrix whose occupied-virtual block is the orbital
@@ -320,23 +388,16 @@ def thc_oo_k_gradient(L, grid, kmesh, psi, phi, pts, rel_tol=1e-12):
     pts = np.asarray(pts, dtype=np.int64)
     nk, no, ng = psi.shape
     nI = len(pts)
-    omega = float(np.prod(L))
     ao_pts = np.stack([phi[n][:, pts] for n in range(nk)])
     o = thc_oo_k(L, grid, kmesh, psi, pts, ao_pts, rel_tol, keep_intermediates=("xi",))
     Psi, X, G = gather(psi, pts, ao_pts)
     rP = coulomb.positions(L, grid, pts)
-    r_all = coulomb.positions(L, grid)
     Gam = np.stack([_gamma(Psi[n], psi[n]) for n in range(nk)])
     # Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r) and U^m_PQ = V^m_QP e^{i q_m.(r_P - r_Q)}
-    Pw = np.empty((nk, nI, ng), dtype=np.complex128)
+    Pw = phased_potentials(L, grid, kmesh, o["xi"], pts)
     U = np.empty((nk, nI, nI), dtype=np.complex128)
     for m in range(nk):
-        q = coulomb.qvec(L, kmesh, m)
-        F = sfft.fftn(o["xi"][m].reshape((nI,) + grid), axes=(1, 2, 3), workers=WORKERS)
-        v = coulomb.kernel(L, grid, kmesh, m)
-        Phi = (omega / ng) * sfft.ifftn(F * v[None], axes=(1, 2, 3), workers=WORKERS).reshape(nI, ng)
-        eP = np.exp(1j * (rP @ q))
-        Pw[m] = eP[:, None] * np.exp(-1j * (r_all @ q))[None, :] * Phi.conj()
+        eP = np.exp(1j * (rP @ coulomb.qvec(L, kmesh, m)))
         U[m] = o["V"][m].T * (eP[:, None] * eP.conj()[None, :])
     Kgrad = np.empty_like(o["K"])
     for n in range(nk):

@@ -1427,23 +1427,20 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
   return s == EXX_OK ? finish(h, stream) : s;
 }
 
-exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec prec,
-                                 const void* psi_grid, const void* occ_pts, const void* ao_pts,
-                                 const void* ao_grid, const int32_t* pts, void* K, void* Kgrad,
-                                 double* Ex, int32_t* rank, hipStream_t stream) {
-  if (!h) return EXX_ERR_ARG;
-  h->err.clear();
-  if (!psi_grid || !occ_pts || !ao_pts || !ao_grid || !pts || !K || !Kgrad || !Ex || !rank)
-    return fail(h, EXX_ERR_ARG, "exx_exchange_gradient: null array argument");
-  if (cell && prec != EXX_F64)
-    return fail(h, EXX_ERR_UNSUPPORTED, "exx_exchange_gradient: FP64 (EXX_F64) only");
-  Geom g;
-  Tables tb;
-  Layout L;
-  char* ws;
-  exx_status s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
-  if (s != EXX_OK) return s;
-  s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
+}  // extern "C"
+
+namespace exx {
+namespace {
+
+// The FP64 build (fit into grid2/S2, V^m into V2, K and E_x) followed by the
+// potentials of the fitted functions and Gamma^n, shared by the gradient and the
+// robust-fit K. On return: grid2 = Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r)
+// [N_k][N_ISDF][N_g], grid = Gamma^n [N_k][N_ISDF][N_g], G = G^n, V2 = Vb^m.
+exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb, char* ws,
+                                 const Layout& L, const void* psi_grid, const void* occ_pts,
+                                 const void* ao_pts, const int32_t* pts, void* K, double* Ex,
+                                 int32_t* rank, hipStream_t stream) {
+  exx_status s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
   if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
   if (s != EXX_OK) return s;
   // the fit (xi into grid2, S into S2), V^m (Bloch gauge, into V2; the transforms
@@ -1455,7 +1452,6 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   if (s == EXX_OK)
     s = buildK_impl(h, g, kscratch(ws, L), ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
   if (s != EXX_OK) return s;
-  const long nn = (long)g.ni * g.ni, na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   double* vt = (double*)(ws + L.gvt);
   hipError_t e = launch_kernel_table(g, vt, stream);
   if (e != hipSuccess) return hip_check(h, e, "kernel table");
@@ -1465,15 +1461,50 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   if (e == hipSuccess)
     e = launch_fft3d<double>(g, tb, ws + L.grid, ws + L.grid2, (long)g.nk * g.ni, h->ncu, stream);
   if (e != hipSuccess) return hip_check(h, e, "potentials");
-  // Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r)
   const double omega = (double)g.L[0] * g.L[1] * g.L[2];
   e = launch_potential_phase(g, tb, ws + L.grid2, pts, omega / ((double)g.ng * g.ng), stream);
   if (e != hipSuccess) return hip_check(h, e, "potential phase");
   // Gamma^n again (the fit turned its copy into Z^m), into grid
   e = launch_gamma<double>(g, occ_pts, psi_grid, ws + L.grid, stream);
   if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
+  return EXX_OK;
+}
+
+exx_status potential_args(exx_context* h, const exx_cell* cell, exx_prec prec, const char* name,
+                          bool ok) {
+  if (!ok) return fail(h, EXX_ERR_ARG, std::string(name) + ": null array argument");
+  if (cell && prec != EXX_F64)
+    return fail(h, EXX_ERR_UNSUPPORTED, std::string(name) + ": FP64 (EXX_F64) only");
+  return EXX_OK;
+}
+
+}  // namespace
+}  // namespace exx
+
+extern "C" {
+
+exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                                 const void* psi_grid, const void* occ_pts, const void* ao_pts,
+                                 const void* ao_grid, const int32_t* pts, void* K, void* Kgrad,
+                                 double* Ex, int32_t* rank, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  exx_status s = potential_args(h, cell, prec, "exx_exchange_gradient",
+                                psi_grid && occ_pts && ao_pts && ao_grid && pts && K && Kgrad &&
+                                    Ex && rank);
+  if (s != EXX_OK) return s;
+  Geom g;
+  Tables tb;
+  Layout L;
+  char* ws;
+  s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
+  if (s == EXX_OK)
+    s = build_with_potentials(h, g, tb, ws, L, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
+                              stream);
+  if (s != EXX_OK) return s;
+  const long nn = (long)g.ni * g.ni, na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // CZ^n over the grid and CS^n over the points (U^m = conj Vb^m: Vb^m is Hermitian)
-  e = launch_grad_xcorr(g, ws + L.grid2, false, ws + L.grid, ws + L.g3, nig, stream);
+  hipError_t e = launch_grad_xcorr(g, ws + L.grid2, false, ws + L.grid, ws + L.g3, nig, stream);
   if (e == hipSuccess)
     e = launch_grad_xcorr(g, ws + L.V2, true, ws + L.G, ws + L.gCS, nn, stream);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the derivative");
@@ -1498,6 +1529,47 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   return s == EXX_OK ? finish(h, stream) : s;
 }
 
+exx_status exx_build_robust(exx_handle_t h, const exx_cell* cell, exx_prec prec,
+                            const void* psi_grid, const void* occ_pts, const void* ao_pts,
+                            const void* ao_grid, const int32_t* pts, void* K, double* Ex,
+                            int32_t* rank, hipStream_t stream) {
+  if (!h) return EXX_ERR_ARG;
+  h->err.clear();
+  exx_status s = potential_args(h, cell, prec, "exx_build_robust",
+                                psi_grid && occ_pts && ao_pts && ao_grid && pts && K && Ex && rank);
+  if (s != EXX_OK) return s;
+  Geom g;
+  Tables tb;
+  Layout L;
+  char* ws;
+  s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
+  if (s == EXX_OK)
+    s = build_with_potentials(h, g, tb, ws, L, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
+                              stream);
+  if (s != EXX_OK) return s;
+  const long na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
+  // R^n = sum_m Pw^m o conj Gamma^{n+m}
+  hipError_t e =
+      launch_grad_xcorr(g, ws + L.grid2, false, ws + L.grid, ws + L.g3, nig, stream, true);
+  if (e != hipSuccess) return hip_check(h, e, "k-correlation of the one-sided term");
+  // T = R conj(phi)^T [N_ISDF][n_ao], then conj of the one-sided term
+  // (1/N_k) T^T A = conj((1/N_k) T^H conj A)
+  double2* T = (double2*)(ws + L.gT);
+  e = gemm<double, double, double, double>(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig,
+                                           B_C, ao_grid, g.ng, (long)g.nao * g.ng, T, g.nao, na_i,
+                                           1.0, false, stream);
+  if (e == hipSuccess)
+    e = gemm<double, double, double, double>(g.nao, g.nao, g.ni, g.nk, A_C, T, g.nao, na_i, B_R,
+                                             ao_pts, g.nao, na_i, ws + L.gA, g.nao,
+                                             (long)g.nao * g.nao, 1.0 / g.nk, false, stream);
+  if (e != hipSuccess) return hip_check(h, e, "AO contraction of the one-sided term");
+  // K <- K_cross + K_cross^H - K_fit
+  e = launch_robust_assemble(g, ws + L.gA, K, stream);
+  if (e != hipSuccess) return hip_check(h, e, "robust assembly");
+  s = scan(h, K, 2L * g.nk * g.nao * g.nao, SITE_OUTPUT, stream);
+  return s == EXX_OK ? finish(h, stream) : s;
+}
+
 exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec prec, int32_t call,
                               size_t* bytes) {
   if (!h) return EXX_ERR_ARG;
@@ -1512,7 +1584,7 @@ exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec pre
     *bytes = b;
     return EXX_OK;
   }
-  if (call == EXX_CALL_GRADIENT) {
+  if (call == EXX_CALL_GRADIENT) {  // also exx_build_robust
     *bytes = layout(h, g, EXX_F64, NEED_GRAD).total;
     return EXX_OK;
   }

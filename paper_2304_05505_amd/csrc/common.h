@@ -431,9 +431,11 @@ hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hi
 hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, const int32_t* pts,
                                   double scale, hipStream_t st);
 // out[n] = sum_m [p^m conj Q^{n+m} + conj(p^m) conj Q^{n-m}] over `elems` elements per
-// k, p^m = P^m (or conj P^m)
+// k, p^m = P^m (or conj P^m); up_only: the first term alone
 hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
-                             long elems, hipStream_t st);
+                             long elems, hipStream_t st, bool up_only = false);
+// K[n][mu][nu] <- conj(Ac[n][mu][nu]) + Ac[n][nu][mu] - K[n][mu][nu]
+hipError_t launch_robust_assemble(const Geom& g, const void* Ac, void* K, hipStream_t st);
 // Kg[n][mu][nu] = -(N_k/4) (Ac[n][mu][nu] + conj Ac[n][nu][mu])
 hipError_t launch_grad_assemble(const Geom& g, const void* Ac, void* Kg, hipStream_t st);
 // V[rep[s]] = e^{-i q_m.(r_P - r_Q)} U[s] (lower triangle of U mirrored) and, where

@@ -1,8 +1,10 @@
 // Kernels of the density derivative of the fitted exchange energy (the
-// occupied-virtual block of Sec. 2.3, Eq. 19): the potentials of the fitted
-// functions on the grid, their k-mesh cross-correlations with Gamma^n and G^n,
-// and the Hermitian assembly. The transforms, the Gamma^n and the AO-basis
-// contractions reuse the build's FFT and GEMM kernels.
+// occupied-virtual block of Sec. 2.3, Eq. 19) and of the robust-fit exchange
+// matrix (one fitted and one exact pair density per integral, the one-sided fit
+// discussed in Sec. 5): the potentials of the fitted functions on the grid,
+// their k-mesh cross-correlations with Gamma^n and G^n, and the Hermitian
+// assemblies. The transforms, the Gamma^n and the AO-basis contractions reuse
+// the build's FFT and GEMM kernels.
 #include "common.h"
 
 namespace exx {
@@ -75,8 +77,8 @@ __global__ __launch_bounds__(256) void potential_phase_kernel(double2* __restric
 }
 
 // out[n][e] = sum_m [p^m(e) conj Q^{n+m}(e) + conj(p^m(e)) conj Q^{n-m}(e)],
-// p^m = P^m, or conj(P^m) with CONJ_P
-template <bool CONJ_P>
+// p^m = P^m, or conj(P^m) with CONJ_P; UP_ONLY keeps the first term
+template <bool CONJ_P, bool UP_ONLY>
 __global__ __launch_bounds__(256) void grad_xcorr_kernel(const double2* __restrict__ P,
                                                          const double2* __restrict__ Q,
                                                          double2* __restrict__ out, long elems,
@@ -89,10 +91,14 @@ __global__ __launch_bounds__(256) void grad_xcorr_kernel(const double2* __restri
       double2 p = P[(long)m * elems + e];
       if (CONJ_P) p.y = -p.y;
       const double2 qu = Q[(long)mesh_add(a, n, m, 1) * elems + e];
-      const double2 qd = Q[(long)mesh_add(a, n, m, -1) * elems + e];
-      // p conj(qu) + conj(p) conj(qd)
-      sx += p.x * qu.x + p.y * qu.y + p.x * qd.x - p.y * qd.y;
-      sy += p.y * qu.x - p.x * qu.y - p.x * qd.y - p.y * qd.x;
+      // p conj(qu) (+ conj(p) conj(qd))
+      sx += p.x * qu.x + p.y * qu.y;
+      sy += p.y * qu.x - p.x * qu.y;
+      if (!UP_ONLY) {
+        const double2 qd = Q[(long)mesh_add(a, n, m, -1) * elems + e];
+        sx += p.x * qd.x - p.y * qd.y;
+        sy += -p.x * qd.y - p.y * qd.x;
+      }
     }
     out[(long)n * elems + e] = make_double2(sx, sy);
   }
@@ -109,6 +115,20 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(const double2* __res
   const int mu = (int)((e % nn) / nao), nu = (int)(e % nao);
   const double2 a = Ac[e], b = Ac[n * nn + (long)nu * nao + mu];
   Kg[e] = make_double2(f * (a.x + b.x), f * (a.y - b.y));
+}
+
+// robust K: Kr[n][mu][nu] = conj(Ac[n][mu][nu]) + Ac[n][nu][mu] - Kr[n][mu][nu],
+// Ac = conj of the one-sided term, Kr holding the fitted K on entry
+__global__ __launch_bounds__(256) void robust_assemble_kernel(const double2* __restrict__ Ac,
+                                                              double2* __restrict__ Kr, int nao,
+                                                              long total) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const long nn = (long)nao * nao;
+  const long n = e / nn;
+  const int mu = (int)((e % nn) / nao), nu = (int)(e % nao);
+  const double2 a = Ac[e], b = Ac[n * nn + (long)nu * nao + mu], k = Kr[e];
+  Kr[e] = make_double2(a.x + b.x - k.x, -a.y + b.y - k.y);
 }
 
 }  // namespace
@@ -138,17 +158,33 @@ hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, cons
 }
 
 hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
-                             long elems, hipStream_t st) {
+                             long elems, hipStream_t st, bool up_only) {
   GradMesh a;
   for (int ax = 0; ax < 3; ++ax) a.N[ax] = g.N[ax];
   a.nk = g.nk;
   const dim3 grid((unsigned)((elems + 255) / 256));
-  if (conj_p)
-    hipLaunchKernelGGL(grad_xcorr_kernel<true>, grid, dim3(256), 0, st, (const double2*)P,
-                       (const double2*)Q, (double2*)out, elems, a);
-  else
-    hipLaunchKernelGGL(grad_xcorr_kernel<false>, grid, dim3(256), 0, st, (const double2*)P,
-                       (const double2*)Q, (double2*)out, elems, a);
+  const double2* p = (const double2*)P;
+  const double2* q = (const double2*)Q;
+  double2* o = (double2*)out;
+  if (up_only) {
+    if (conj_p)
+      hipLaunchKernelGGL((grad_xcorr_kernel<true, true>), grid, dim3(256), 0, st, p, q, o, elems, a);
+    else
+      hipLaunchKernelGGL((grad_xcorr_kernel<false, true>), grid, dim3(256), 0, st, p, q, o, elems, a);
+  } else {
+    if (conj_p)
+      hipLaunchKernelGGL((grad_xcorr_kernel<true, false>), grid, dim3(256), 0, st, p, q, o, elems, a);
+    else
+      hipLaunchKernelGGL((grad_xcorr_kernel<false, false>), grid, dim3(256), 0, st, p, q, o, elems,
+                         a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_robust_assemble(const Geom& g, const void* Ac, void* K, hipStream_t st) {
+  const long total = (long)g.nk * g.nao * g.nao;
+  hipLaunchKernelGGL(robust_assemble_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     st, (const double2*)Ac, (double2*)K, g.nao, total);
   return hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ EXPORTED = (
     "exx_set_fit",
     "exx_mlp_moments",
     "exx_exchange_gradient",
+    "exx_build_robust",
 )
 
 EXX_BATCH_GRAPH, EXX_BATCH_TUNE, EXX_BATCH_CONCURRENT = 1, 2, 4
@@ -125,6 +126,8 @@ def _load():
         "exx_build": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "exx_exchange_gradient": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp],
                                   ctypes.c_int),
+        "exx_build_robust": ([vp, cellp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+                             ctypes.c_int),
         "exx_select_points": ([vp, cellp, vp, vp, vp, vp], ctypes.c_int),
         "exx_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "exx_set_refinement": ([vp, ctypes.c_int32], ctypes.c_int),
@@ -403,6 +406,24 @@ def exx_exchange_gradient(h: Handle, cell: ExxCell, psi_grid, occ_pts, ao_pts, a
         _ptr(rank, "rank", torch.int32, (nk,), d),
     )
     h._check(_lib.exx_exchange_gradient(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
+
+
+def exx_build_robust(h: Handle, cell: ExxCell, psi_grid, occ_pts, ao_pts, ao_grid, pts, K, Ex,
+                     rank, prec: int = EXX_F64):
+    """The robust-fit exchange matrix K_rob and E_x (FP64)."""
+    nk, ng, ni, no, na = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ, cell.n_ao
+    d = h.device
+    args = (
+        _ptr(psi_grid, "psi_grid", torch.complex128, (nk, no, ng), d),
+        _ptr(occ_pts, "occ_pts", torch.complex128, (nk, ni, no), d),
+        _ptr(ao_pts, "ao_pts", torch.complex128, (nk, ni, na), d),
+        _ptr(ao_grid, "ao_grid", torch.complex128, (nk, na, ng), d),
+        _ptr(pts, "pts", torch.int32, (ni,), d),
+        _ptr(K, "K", torch.complex128, (nk, na, na), d),
+        _ptr(Ex, "Ex", torch.float64, (1,), d),
+        _ptr(rank, "rank", torch.int32, (nk,), d),
+    )
+    h._check(_lib.exx_build_robust(h.raw, ctypes.byref(cell), prec, *args, _stream(d)))
 
 
 def exx_select_points(h: Handle, cell: ExxCell, psi_grid, pts, n_pivot):

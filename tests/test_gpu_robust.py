@@ -1,0 +1,89 @@
+"""The robust-fit exchange matrix (exx_build_robust, FP64) against the robust
+oracle (thc.thc_oo_k_robust, pinned by the residual identity
+K_direct - K_rob = K[delta, delta] on explicit residual pair densities) on the
+meshes of the gradient test (Gamma point, real path, odd grid, ragged N_ISDF,
+3x3x3; fits at and below the pair rank).
+
+* Ranks equal; E_x and K_rob (relative to max|K_rob|) to
+  min(1e-8, max(1e-12, 64 eps64 cond)), cond the largest cond(S^m) over the
+  retained points (the one-sided term is a product of the potentials of the
+  fitted xi^m with Gamma^n, its rounding the fit's, as for the gradient).
+* E_x equals exx_build's to the same tolerance (the robust energy is the
+  fitted one; the fused build reaches it by another rounding route).
+* At full occupied-pair rank (the 2x1x1 cell) the occupied rows C^H K_rob of
+  the GPU result equal direct exchange's, where the plain fit's do not.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, select, thc
+
+from test_gpu_gradient import GRAD_CELLS, _cond
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+
+
+def _run(cell, psi, phi, pts):
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    nk, na, ni = cell.N_k, cell.n_ao, len(pts)
+    ao = np.stack([phi[n][:, pts] for n in range(nk)])
+    t = dict(
+        psi_grid=torch.from_numpy(psi).to(dev),
+        occ_pts=torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev),
+        ao_pts=torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+        ao_grid=torch.from_numpy(np.ascontiguousarray(phi)).to(dev),
+        pts=torch.from_numpy(np.asarray(pts, dtype=np.int32)).to(dev),
+    )
+    K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, ni)
+    h = exx.Handle(0)
+    exx.exx_build_robust(h, c, t["psi_grid"], t["occ_pts"], t["ao_pts"], t["ao_grid"], t["pts"],
+                         K, Ex, rank)
+    K2 = torch.empty_like(K)
+    Ex2 = torch.empty_like(Ex)
+    exx.exx_build(h, c, exx.EXX_F64, t["psi_grid"], t["occ_pts"], t["ao_pts"], t["pts"], K2, Ex2,
+                  rank)
+    torch.cuda.synchronize()
+    return (K.cpu().numpy(), float(Ex.cpu()[0]), rank.cpu().numpy(), K2.cpu().numpy(),
+            float(Ex2.cpu()[0]))
+
+
+@pytest.mark.parametrize("name", list(GRAD_CELLS))
+def test_robust_build_matches_oracle(name, gpu):
+    cell = GRAD_CELLS[name]()
+    C = synth.orbital_coeffs(cell)
+    psi = synth.orbitals_on_grid(cell, C)
+    phi = np.stack([synth.ao_on_grid(cell, n) for n in range(cell.N_k)])
+    pts, _ = select.select_points(psi, cell.n_isdf)
+    o = thc.thc_oo_k_robust(cell.L, cell.grid, cell.kmesh, psi, phi, pts)
+    cond = _cond(o)
+    tol = min(1e-8, max(1e-12, 64 * EPS64 * cond))
+    K, E, r, Kfit, Efit = _run(cell, psi, phi, pts)
+    dE = abs(E - o["Ex"]) / abs(o["Ex"])
+    dK = np.abs(K - o["K"]).max() / np.abs(o["K"]).max()
+    herm = max(np.abs(K[n] - K[n].conj().T).max() for n in range(cell.N_k)) / np.abs(K).max()
+    print(f"{name}: cond {cond:.2e} rank {r.tolist()} tol {tol:.1e} rel dE {dE:.2e} "
+          f"dK_rob {dK:.2e} hermiticity {herm:.1e} |K_rob - K_fit| "
+          f"{np.abs(K - Kfit).max() / np.abs(K).max():.2e}")
+    assert np.array_equal(r, o["rank"])
+    assert dE <= tol and dK <= tol
+    assert abs(E - Efit) <= tol * abs(Efit)   # the fused build's route, to rounding
+    assert herm <= tol
+    if name == "k211":  # full occupied-pair rank
+        Kd = direct.exchange_matrix(cell.L, cell.grid, cell.kmesh, psi, phi)
+        rows = lambda A: np.stack([C[n].conj().T @ A[n] for n in range(cell.N_k)])  # noqa: E731
+        ref = rows(Kd)
+        e_rob = np.abs(rows(K) - ref).max() / np.abs(ref).max()
+        e_fit = np.abs(rows(Kfit) - ref).max() / np.abs(ref).max()
+        print(f"occupied rows against direct exchange: robust {e_rob:.2e}, plain {e_fit:.2e}")
+        assert e_rob <= 1e-9 and e_fit >= 1e-4
