@@ -342,13 +342,33 @@ def ring_leg(config, args, h, exx, torch, dev):
 def potential_legs(args, h, exx, torch, dev, cell, t, f64_ms, tag):
     """The FP64 calls that add the potentials of the fitted functions to a build:
     the exchange gradient (K, E_x and Kgrad) and the robust-fit K, each timed as
-    one whole call (its build included) and against the FP64 build."""
+    one whole call (its build included) and against the fused FP64 build and the
+    stage-wise one (fit, Coulomb, K: the route these calls take, since they need
+    xi^m of every transfer)."""
     from synth.fast import ao_on_grid_torch
 
     ao_grid = torch.stack([ao_on_grid_torch(cell, n, dev) for n in range(cell.N_k)]).contiguous()
     out = {}
     o = outputs(torch, cell, dev)
     Kg = torch.empty_like(o["K"])
+    nk, ni, ng = cell.N_k, cell.n_isdf, int(np.prod(cell.grid))
+    xi = torch.empty((nk, ni, ng), dtype=torch.complex128, device=dev)
+    S = torch.empty((nk, ni, ni), dtype=torch.complex128, device=dev)
+    V = torch.empty_like(S)
+
+    def stagewise():
+        # the build route of these calls: xi^m of every transfer formed
+        exx.exx_isdf_fit(h, t["cell"], exx.EXX_F64, t["psi64"], t["occ_pts"], t["pts"], xi, S,
+                         o["rank"])
+        exx.exx_coulomb_V(h, t["cell"], exx.EXX_F64, xi, t["pts"], V)
+        exx.exx_build_K(h, t["cell"], exx.EXX_F64, t["ao_pts"], t["occ_pts"], V, o["K"], o["Ex"])
+
+    s = time_steps(stagewise, max(1, min(args.steps, 3)), 1, torch)
+    out["f64-stagewise"] = {"ms_per_build": s * 1e3, "ratio_to_f64_build": s * 1e3 / f64_ms,
+                            "precision": "f64", "Ex": float(o["Ex"].cpu()[0])}
+    log(f"[{tag}] f64-stagewise: {s * 1e3:.2f} ms/build ({s * 1e3 / f64_ms:.2f}x the fused build)")
+    del xi, S, V
+    stage_ms = s * 1e3
     calls = {
         "f64-gradient": lambda: exx.exx_exchange_gradient(
             h, t["cell"], t["psi64"], t["occ_pts"], t["ao_pts"], ao_grid, t["pts"], o["K"], Kg,
@@ -360,8 +380,10 @@ def potential_legs(args, h, exx, torch, dev, cell, t, f64_ms, tag):
     for label, fn in calls.items():
         s = time_steps(fn, max(1, min(args.steps, 3)), 1, torch)
         out[label] = {"ms_per_call": s * 1e3, "ratio_to_f64_build": s * 1e3 / f64_ms,
+                      "ratio_to_f64_stagewise_build": s * 1e3 / stage_ms,
                       "Ex": float(o["Ex"].cpu()[0]), "precision": "f64"}
-        log(f"[{tag}] {label}: {s * 1e3:.2f} ms/call ({s * 1e3 / f64_ms:.2f}x the FP64 build)")
+        log(f"[{tag}] {label}: {s * 1e3:.2f} ms/call ({s * 1e3 / f64_ms:.2f}x the fused FP64 "
+            f"build, {s * 1e3 / stage_ms:.2f}x the stage-wise one)")
     del ao_grid, Kg
     torch.cuda.empty_cache()
     return out

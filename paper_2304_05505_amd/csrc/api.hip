@@ -240,7 +240,7 @@ struct Layout {
   size_t G, Lf, W, Sp, keep, Y, T, epart, cpart, S2, V2, rank2, tol, Tinv, grid, grid2, F, total;
   // the exchange gradient's buffers: a third grid-sized array, the kernel table,
   // the point-sized correlation and the AO-sized products
-  size_t g3, gvt, gCS, gT, gA;
+  size_t g3, gvt, gCS, gT, gA, gP;
   int nsplit;
   PairedDims pd;
 };
@@ -307,7 +307,7 @@ Layout layout(const exx_context* h, const Geom& g, exx_prec prec, int need) {
     o += 2 * al(cx * (size_t)L.pd.per * g.ni * g.ng);
   else if (shared)  // the one transform
     o += al(cx * (size_t)g.ni * g.ng);
-  L.g3 = L.gvt = L.gCS = L.gT = L.gA = o;
+  L.g3 = L.gvt = L.gCS = L.gT = L.gA = L.gP = o;
   if (grad) {
     L.g3 = o;
     o += al(sizeof(double2) * (size_t)g.nk * g.ni * g.ng);
@@ -319,6 +319,9 @@ Layout layout(const exx_context* h, const Geom& g, exx_prec prec, int need) {
     o += al(sizeof(double2) * (size_t)g.nk * g.ni * g.nao);
     L.gA = o;
     o += al(sizeof(double2) * (size_t)g.nk * g.nao * g.nao);
+    L.gP = o;  // slices of the split sum over the grid
+    o += al(sizeof(double2) * (size_t)gemm_splitk_parts(g.ni, g.nao, g.ng, g.nk) * g.nk * g.ni *
+            g.nao);
   }
   L.total = o;
   return L;
@@ -1465,7 +1468,9 @@ exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb
   e = launch_potential_phase(g, tb, ws + L.grid2, pts, omega / ((double)g.ng * g.ng), stream);
   if (e != hipSuccess) return hip_check(h, e, "potential phase");
   // Gamma^n again (the fit turned its copy into Z^m), into grid
-  e = launch_gamma<double>(g, occ_pts, psi_grid, ws + L.grid, stream);
+  e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ_pts, g.no, (long)g.ni * g.no, true,
+                                    psi_grid, g.ng, (long)g.no * g.ng, ws + L.grid, g.ng,
+                                    (long)g.ni * g.ng, stream, h->tile_gamma);
   if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
   return EXX_OK;
 }
@@ -1510,9 +1515,8 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the derivative");
   // T = CS conj(X^T) - 2 CZ conj(phi)^T, then conj A = (1/N_k^2) X^H conj T
   double2* T = (double2*)(ws + L.gT);
-  e = gemm<double, double, double, double>(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig,
-                                           B_C, ao_grid, g.ng, (long)g.nao * g.ng, T, g.nao, na_i,
-                                           -2.0, false, stream);
+  e = zgemm_splitk(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig, B_C, ao_grid, g.ng,
+                   (long)g.nao * g.ng, T, g.nao, na_i, -2.0, false, ws + L.gP, stream);
   if (e == hipSuccess)
     e = gemm<double, double, double, double>(g.ni, g.nao, g.ni, g.nk, A_N, ws + L.gCS, g.ni, nn,
                                              B_R, ao_pts, g.nao, na_i, T, g.nao, na_i, 1.0, true,
@@ -1555,9 +1559,8 @@ exx_status exx_build_robust(exx_handle_t h, const exx_cell* cell, exx_prec prec,
   // T = R conj(phi)^T [N_ISDF][n_ao], then conj of the one-sided term
   // (1/N_k) T^T A = conj((1/N_k) T^H conj A)
   double2* T = (double2*)(ws + L.gT);
-  e = gemm<double, double, double, double>(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig,
-                                           B_C, ao_grid, g.ng, (long)g.nao * g.ng, T, g.nao, na_i,
-                                           1.0, false, stream);
+  e = zgemm_splitk(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig, B_C, ao_grid, g.ng,
+                   (long)g.nao * g.ng, T, g.nao, na_i, 1.0, false, ws + L.gP, stream);
   if (e == hipSuccess)
     e = gemm<double, double, double, double>(g.nao, g.nao, g.ni, g.nk, A_C, T, g.nao, na_i, B_R,
                                              ao_pts, g.nao, na_i, ws + L.gA, g.nao,

@@ -245,6 +245,15 @@ hipError_t gemm(int M, int N, int K, int batch, OpA oa, const void* A, long lda,
                 const void* B, long ldb, long sB, void* C, long ldc, long sC, T alpha_re,
                 bool accumulate, hipStream_t st);
 
+// gemm in FP64 (c128 operands) for a long K (a sum over the grid): the K range is
+// split into gemm_splitk_parts(M, N, K, batch) slices whose products go to `part`
+// (that many x batch x M x N c128) and are then added in slice order
+// (deterministic) into C, scaled by alpha; op cases (A_N, B_C) and (A_N, B_R).
+int gemm_splitk_parts(int M, int N, int K, int batch);
+hipError_t zgemm_splitk(int M, int N, int K, int batch, OpA oa, const void* A, long lda, long sA,
+                        OpB ob, const void* B, long ldb, long sB, void* C, long ldc, long sC,
+                        double alpha, bool accumulate, void* part, hipStream_t st);
+
 // C[b] = A[b] * op(B[b]) on the matrix cores in FP64: A (M x K) c128, B (K x N) and
 // C (M x N) row-major with storage types TB, TC; op = conj if conjB. `tile` picks the
 // wave tile in 16x16 blocks (22, 24 or 42; any other value means 24; workgroup =

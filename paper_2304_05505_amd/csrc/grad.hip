@@ -104,6 +104,86 @@ __global__ __launch_bounds__(256) void grad_xcorr_kernel(const double2* __restri
   }
 }
 
+// The same sums with each element's N_k values of P and Q staged once in LDS
+// (each lane reads back only its own column, so no barrier is needed): 2 N_k
+// loads per element instead of up to 3 N_k^2. One wave per workgroup, 64
+// elements; LDS 2 N_k x 64 x 16 bytes.
+template <bool CONJ_P, bool UP_ONLY>
+__global__ __launch_bounds__(64) void grad_xcorr_lds_kernel(const double2* __restrict__ P,
+                                                            const double2* __restrict__ Q,
+                                                            double2* __restrict__ out, long elems,
+                                                            GradMesh a) {
+  extern __shared__ double2 stage[];
+  double2* Ps = stage;
+  double2* Qs = stage + a.nk * 64;
+  const int t = threadIdx.x;
+  const long e = (long)blockIdx.x * 64 + t;
+  const bool in = e < elems;
+  for (int m = 0; m < a.nk; ++m) {
+    double2 p = in ? P[(long)m * elems + e] : make_double2(0.0, 0.0);
+    if (CONJ_P) p.y = -p.y;
+    Ps[m * 64 + t] = p;
+    Qs[m * 64 + t] = in ? Q[(long)m * elems + e] : make_double2(0.0, 0.0);
+  }
+  for (int n = 0; n < a.nk; ++n) {
+    double sx = 0.0, sy = 0.0;
+    for (int m = 0; m < a.nk; ++m) {
+      const double2 p = Ps[m * 64 + t];
+      const double2 qu = Qs[mesh_add(a, n, m, 1) * 64 + t];
+      sx += p.x * qu.x + p.y * qu.y;
+      sy += p.y * qu.x - p.x * qu.y;
+      if (!UP_ONLY) {
+        const double2 qd = Qs[mesh_add(a, n, m, -1) * 64 + t];
+        sx += p.x * qd.x - p.y * qd.y;
+        sy += -p.x * qd.y - p.y * qd.x;
+      }
+    }
+    if (in) out[(long)n * elems + e] = make_double2(sx, sy);
+  }
+}
+
+// index of k_n + sign * q_m on an N1 x N2 x N3 mesh (constant once unrolled)
+template <int N1, int N2, int N3>
+__device__ constexpr int mesh_add_c(int n, int m, int sign) {
+  return ((n / (N2 * N3) + sign * (m / (N2 * N3)) + N1) % N1 * N2 +
+          ((n / N3) % N2 + sign * ((m / N3) % N2) + N2) % N2) * N3 +
+         (n % N3 + sign * (m % N3) + N3) % N3;
+}
+
+// The same sums (p^m = P^m) on a mesh known at compile time: each element's N_k
+// values of P and Q are held in registers, every transfer index is a constant.
+template <bool UP_ONLY, int N1, int N2, int N3>
+__global__ __launch_bounds__(256) void grad_xcorr_reg_kernel(const double2* __restrict__ P,
+                                                            const double2* __restrict__ Q,
+                                                            double2* __restrict__ out,
+                                                            long elems) {
+  constexpr int NK = N1 * N2 * N3;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= elems) return;
+  double2 p[NK], q[NK];
+#pragma unroll
+  for (int m = 0; m < NK; ++m) {
+    p[m] = P[(long)m * elems + e];
+    q[m] = Q[(long)m * elems + e];
+  }
+#pragma unroll
+  for (int n = 0; n < NK; ++n) {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int m = 0; m < NK; ++m) {
+      const double2 qu = q[mesh_add_c<N1, N2, N3>(n, m, 1)];
+      sx += p[m].x * qu.x + p[m].y * qu.y;
+      sy += p[m].y * qu.x - p[m].x * qu.y;
+      if (!UP_ONLY) {
+        const double2 qd = q[mesh_add_c<N1, N2, N3>(n, m, -1)];
+        sx += p[m].x * qd.x - p[m].y * qd.y;
+        sy += -p[m].x * qd.y - p[m].y * qd.x;
+      }
+    }
+    out[(long)n * elems + e] = make_double2(sx, sy);
+  }
+}
+
 // Kg[n][mu][nu] = -(N_k/4) (Ac[n][mu][nu] + conj(Ac[n][nu][mu]))
 __global__ __launch_bounds__(256) void grad_assemble_kernel(const double2* __restrict__ Ac,
                                                             double2* __restrict__ Kg, int nao,
@@ -166,6 +246,53 @@ hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const vo
   const double2* p = (const double2*)P;
   const double2* q = (const double2*)Q;
   double2* o = (double2*)out;
+  if (!conj_p) {  // register-resident forms for the common small meshes
+#define EXX_XREG(a, b, c)                                                                      \
+  if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                             \
+    if (up_only)                                                                               \
+      hipLaunchKernelGGL((grad_xcorr_reg_kernel<true, a, b, c>), grid, dim3(256), 0, st, p, q, \
+                         o, elems);                                                            \
+    else                                                                                       \
+      hipLaunchKernelGGL((grad_xcorr_reg_kernel<false, a, b, c>), grid, dim3(256), 0, st, p,   \
+                         q, o, elems);                                                         \
+    return hipGetLastError();                                                                  \
+  }
+    EXX_XREG(1, 1, 1)
+    EXX_XREG(2, 1, 1)
+    EXX_XREG(1, 2, 1)
+    EXX_XREG(1, 1, 2)
+    EXX_XREG(2, 2, 1)
+    EXX_XREG(2, 1, 2)
+    EXX_XREG(1, 2, 2)
+    EXX_XREG(2, 2, 2)
+    EXX_XREG(3, 1, 1)
+    EXX_XREG(1, 3, 1)
+    EXX_XREG(1, 1, 3)
+    EXX_XREG(3, 2, 1)
+    EXX_XREG(1, 2, 3)
+    EXX_XREG(2, 3, 1)
+#undef EXX_XREG
+  }
+  if (g.nk <= 32) {  // LDS staging, at most 64 KiB per workgroup
+    const dim3 gl((unsigned)((elems + 63) / 64));
+    const size_t lds = sizeof(double2) * 2 * 64 * (size_t)g.nk;
+    if (up_only) {
+      if (conj_p)
+        hipLaunchKernelGGL((grad_xcorr_lds_kernel<true, true>), gl, dim3(64), lds, st, p, q, o,
+                           elems, a);
+      else
+        hipLaunchKernelGGL((grad_xcorr_lds_kernel<false, true>), gl, dim3(64), lds, st, p, q, o,
+                           elems, a);
+    } else {
+      if (conj_p)
+        hipLaunchKernelGGL((grad_xcorr_lds_kernel<true, false>), gl, dim3(64), lds, st, p, q, o,
+                           elems, a);
+      else
+        hipLaunchKernelGGL((grad_xcorr_lds_kernel<false, false>), gl, dim3(64), lds, st, p, q, o,
+                           elems, a);
+    }
+    return hipGetLastError();
+  }
   if (up_only) {
     if (conj_p)
       hipLaunchKernelGGL((grad_xcorr_kernel<true, true>), grid, dim3(256), 0, st, p, q, o, elems, a);
