@@ -254,6 +254,13 @@ hipError_t zgemm_splitk(int M, int N, int K, int batch, OpA oa, const void* A, l
                         OpB ob, const void* B, long ldb, long sB, void* C, long ldc, long sC,
                         double alpha, bool accumulate, void* part, hipStream_t st);
 
+// slices of C = A B^H (A [M][K], B [N][K] c128) on the FP64 matrix cores:
+// part[s][b][M][N] = sum over k in [s kc, min(K, (s + 1) kc)) of A[b][i][k] conj B[b][j][k],
+// s < ns; kc a multiple of 8
+hipError_t zgemm_abh_parts(int M, int N, int K, int batch, const void* A, long lda, long sA,
+                           const void* B, long ldb, long sB, void* part, int ns, int kc,
+                           hipStream_t st);
+
 // C[b] = A[b] * op(B[b]) on the matrix cores in FP64: A (M x K) c128, B (K x N) and
 // C (M x N) row-major with storage types TB, TC; op = conj if conjB. `tile` picks the
 // wave tile in 16x16 blocks (22, 24 or 42; any other value means 24; workgroup =

@@ -192,9 +192,8 @@ hipError_t zgemm_splitk(int M, int N, int K, int batch, OpA oa, const void* A, l
   const int kc = splitk_chunk(K, ns);
   const long per = (long)batch * M * N;
   hipError_t e = hipErrorInvalidValue;
-  if (oa == A_N && ob == B_C)
-    e = run<double, double, double, double, A_N, B_C>(M, N, K, batch, A, lda, sA, B, ldb, sB, part,
-                                                      N, (long)M * N, 1.0, false, st, ns, kc, per);
+  if (oa == A_N && ob == B_C)  // C = A B^H: the slices on the FP64 matrix cores
+    e = zgemm_abh_parts(M, N, K, batch, A, lda, sA, B, ldb, sB, part, ns, kc, st);
   else if (oa == A_N && ob == B_R)
     e = run<double, double, double, double, A_N, B_R>(M, N, K, batch, A, lda, sA, B, ldb, sB, part,
                                                       N, (long)M * N, 1.0, false, st, ns, kc, per);

@@ -44,36 +44,48 @@ struct PhaseArgs {
   int ni;
   long ng;
   double scale;
+  int nrb;  // workgroups per row (1024 grid points each)
 };
 
-// X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]
+// X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]: workgroup (row, rb) with
+// row = (m, P), whose factor scale e^{i q.r_P} is uniform; a thread takes four grid
+// points r (stride 256), each with e^{-i q.r} from the three axis tables
+// (root_a[m_a c_a mod N_a n_a] = e^{-2 pi i m_a c_a / (N_a n_a)}).
 __global__ __launch_bounds__(256) void potential_phase_kernel(double2* __restrict__ X,
                                                               const int32_t* __restrict__ pts,
-                                                              PhaseArgs a, long total) {
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= total) return;
-  const long r = e % a.ng;
-  const long mp = e / a.ng;
-  const int P = (int)(mp % a.ni);
-  const int m = (int)(mp / a.ni);
-  const int n23 = a.n[1] * a.n[2];
+                                                              PhaseArgs a) {
+  const int row = blockIdx.x / a.nrb, rb = blockIdx.x % a.nrb;
+  const int P = row % a.ni, m = row / a.ni;
+  const int n2 = a.n[1], n3 = a.n[2], n23 = n2 * n3;
   const int gp = pts[P];
-  const int pc[3] = {gp / n23, (gp / a.n[2]) % a.n[1], gp % a.n[2]};
-  const int rc[3] = {(int)(r / n23), (int)((r / a.n[2]) % a.n[1]), (int)(r % a.n[2])};
   const int mm[3] = {m / (a.N[1] * a.N[2]), (m / a.N[2]) % a.N[1], m % a.N[2]};
-  // e^{i q.(r_P - r)} = prod_a conj(root_a[m_a p_a]) root_a[m_a c_a]
+  const int pc[3] = {gp / n23, (gp / n3) % n2, gp % n3};
+  // scale e^{i q.r_P} = scale prod_a conj(root_a[m_a p_a])
   double px = a.scale, py = 0.0;
   for (int ax = 0; ax < 3; ++ax) {
-    const int Lr = a.N[ax] * a.n[ax];
-    const double2 fp = a.root[ax][(mm[ax] * pc[ax]) % Lr];
-    const double2 fc = a.root[ax][(mm[ax] * rc[ax]) % Lr];
-    const double wx = fp.x * fc.x + fp.y * fc.y, wy = fp.x * fc.y - fp.y * fc.x;
-    const double tx = px * wx - py * wy;
-    py = px * wy + py * wx;
+    const double2 f = a.root[ax][(mm[ax] * pc[ax]) % (a.N[ax] * a.n[ax])];
+    const double tx = px * f.x + py * f.y;
+    py = py * f.x - px * f.y;
     px = tx;
   }
-  const double2 x = X[e];
-  X[e] = make_double2(px * x.x - py * x.y, px * x.y + py * x.x);
+  double2* Xr = X + (long)row * a.ng;
+  const int ng = (int)a.ng;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = (rb * 4 + u) * 256 + threadIdx.x;
+    if (r >= ng) break;
+    const int c0 = r / n23, c1 = (r / n3) % n2, c2 = r % n3;
+    const double2 f0 = a.root[0][(mm[0] * c0) % (a.N[0] * a.n[0])];
+    const double2 f1 = a.root[1][(mm[1] * c1) % (a.N[1] * a.n[1])];
+    const double2 f2 = a.root[2][(mm[2] * c2) % (a.N[2] * a.n[2])];
+    double wx = f0.x * f1.x - f0.y * f1.y, wy = f0.x * f1.y + f0.y * f1.x;
+    const double tx = wx * f2.x - wy * f2.y;
+    wy = wx * f2.y + wy * f2.x;
+    wx = tx;
+    const double qx = px * wx - py * wy, qy = px * wy + py * wx;
+    const double2 x = Xr[r];
+    Xr[r] = make_double2(qx * x.x - qy * x.y, qx * x.y + qy * x.x);
+  }
 }
 
 // out[n][e] = sum_m [p^m(e) conj Q^{n+m}(e) + conj(p^m(e)) conj Q^{n-m}(e)],
@@ -231,9 +243,10 @@ hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, cons
   a.ni = g.ni;
   a.ng = g.ng;
   a.scale = scale;
-  const long total = (long)g.nk * g.ni * g.ng;
-  hipLaunchKernelGGL(potential_phase_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                     st, (double2*)X, pts, a, total);
+  a.nrb = (int)((g.ng + 1023) / 1024);
+  const long nblk = (long)g.nk * g.ni * a.nrb;
+  hipLaunchKernelGGL(potential_phase_kernel, dim3((unsigned)nblk), dim3(256), 0, st, (double2*)X,
+                     pts, a);
   return hipGetLastError();
 }
 
