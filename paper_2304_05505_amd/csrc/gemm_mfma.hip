@@ -780,134 +780,6 @@ EXX_ACC_INST(double, float)
 EXX_ACC_INST(float, float)
 #undef EXX_ACC_INST
 
-namespace {
-
-// One slice [k0, k1) of C = A B^H (A [M][K], B [N][K], FP64 complex, K the long
-// axis): a workgroup of 2 x 2 waves computes a 64 x 64 tile, each wave a 32 x 32
-// tile of 2 x 2 blocks of 16 x 16 on the FP64 matrix cores with three real
-// products per complex one (Re x conj y = T1 + T2, Im = T3 - T1 + T2 from
-// T1 = sum xr yr, T2 = sum xi yi, T3 = sum (xr + xi)(yr - yi)). A lane feeds two
-// consecutive k of its row per step (eight k per step); loads are clamped into
-// the arrays and masked to zero past the slice, and three steps' operands are
-// in flight while a step's products issue. Work item w = ((b ns + s) tm + ti)
-// tn + tj, laid out XCD-contiguously so that the tiles of one slice share an L2.
-__global__ __launch_bounds__(256, 2) void zgemm_abh_kernel(
-    const double2* __restrict__ A, long lda, long sA, const double2* __restrict__ B, long ldb,
-    long sB, double2* __restrict__ part, int M, int N, int K, int kc, int tm, int tn, int batch,
-    int ns, long nwork, long nwork_pad) {
-  const long w = (blockIdx.x % 8) * (nwork_pad / 8) + blockIdx.x / 8;
-  if (w >= nwork) return;
-  const int tj = (int)(w % tn);
-  long r = w / tn;
-  const int ti = (int)(r % tm);
-  r /= tm;
-  const int sk = (int)(r % ns);
-  const long b = r / ns;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int li = lane & 15, gq = lane >> 4;
-  const int P0 = ti * 64 + (wave & 1) * 32, Q0 = tj * 64 + (wave >> 1) * 32;
-  const long k0 = (long)sk * kc, k1 = min((long)K, k0 + kc);
-  const double2* Ab = A + b * sA;
-  const double2* Bb = B + b * sB;
-  long xrow[2], yrow[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    xrow[i] = (long)min(P0 + 16 * i + li, M - 1) * lda;
-    yrow[i] = (long)min(Q0 + 16 * i + li, N - 1) * ldb;
-  }
-  d4 t1[2][2], t2[2][2], t3[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) t1[i][j] = t2[i][j] = t3[i][j] = d4{0, 0, 0, 0};
-  // operands of the step at kb; NPF steps are in flight in registers (a slot is
-  // refilled with the step NPF ahead as soon as its products are issued)
-  constexpr int NPF = 3;
-  auto load = [&](long kb, double2 (*x)[2], double2 (*y)[2]) {
-    const long g = kb + 2 * gq;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const long gi = min(g + t, (long)K - 1);
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        x[i][t] = Ab[xrow[i] + gi];
-        y[i][t] = Bb[yrow[i] + gi];
-      }
-    }
-  };
-  double2 xb[NPF][2][2], yb[NPF][2][2];
-#pragma unroll
-  for (int sl = 0; sl < NPF; ++sl) load(k0 + 8 * sl, xb[sl], yb[sl]);
-  for (long kc0 = k0; kc0 < k1; kc0 += 8 * NPF) {
-#pragma unroll
-    for (int sl = 0; sl < NPF; ++sl) {
-      const long kb = kc0 + 8 * sl;
-      const long g = kb + 2 * gq;
-      double2 x[2][2], y[2][2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const bool ok = g + t < k1;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          x[i][t] = ok ? xb[sl][i][t] : make_double2(0.0, 0.0);
-          y[i][t] = ok ? yb[sl][i][t] : make_double2(0.0, 0.0);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        double ys[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) ys[j] = y[j][t].x - y[j][t].y;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const double xs = x[i][t].x + x[i][t].y;
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            t1[i][j] =
-                __builtin_amdgcn_mfma_f64_16x16x4f64(x[i][t].x, y[j][t].x, t1[i][j], 0, 0, 0);
-            t2[i][j] =
-                __builtin_amdgcn_mfma_f64_16x16x4f64(x[i][t].y, y[j][t].y, t2[i][j], 0, 0, 0);
-            t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs, ys[j], t3[i][j], 0, 0, 0);
-          }
-        }
-      }
-      // refill the slot (clamped into the arrays past the end; masked at use)
-      __builtin_amdgcn_sched_barrier(0);
-      load(kb + 8 * NPF, xb[sl], yb[sl]);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  // register v of a lane holds row 4 v + lane/16, column lane%16 of a block
-  double2* out = part + ((long)sk * batch + b) * M * N;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int P = P0 + 16 * i + 4 * v + gq, Q = Q0 + 16 * j + li;
-        if (P < M && Q < N)
-          out[(long)P * N + Q] = make_double2(t1[i][j][v] + t2[i][j][v],
-                                              t3[i][j][v] - t1[i][j][v] + t2[i][j][v]);
-      }
-}
-
-}  // namespace
-
-hipError_t zgemm_abh_parts(int M, int N, int K, int batch, const void* A, long lda, long sA,
-                           const void* B, long ldb, long sB, void* part, int ns, int kc,
-                           hipStream_t st) {
-  if (M <= 0 || N <= 0 || K <= 0 || batch <= 0 || ns <= 0 || kc <= 0 || kc % 8)
-    return hipErrorInvalidValue;
-  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
-  const long nwork = (long)batch * ns * tm * tn;
-  const long pad = (nwork + 7) / 8 * 8;
-  hipLaunchKernelGGL(zgemm_abh_kernel, dim3((unsigned)pad), dim3(256), 0, st, (const double2*)A,
-                     lda, sA, (const double2*)B, ldb, sB, (double2*)part, M, N, K, kc, tm, tn,
-                     batch, ns, nwork, pad);
-  return hipGetLastError();
-}
-
 template hipError_t zgemm_nn_grid<double, double>(int, int, int, int, const void*, long, long,
                                                   bool, const void*, long, long, void*, long, long,
                                                   hipStream_t, int, bool);
