@@ -24,7 +24,9 @@ against the per-transfer oracle's shows the fit's own error).
 Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --profile
 (the profiler's target, no JSON: the mixed batch twice and a 1 GiB copy; with
 --workload rings-k2 | rings-k3, two builds per precision of that cell and the
-copy); --workload rings-k2 | rings-k3 | select-k4 print a single leg.
+copy; with --potentials and a ring workload, the exchange gradient and the
+robust-fit K instead); --workload rings-k2 | rings-k3 | select-k4 print a single
+leg; --workload nk-series times the ring cell's build on 1^3..4^3 k-meshes.
 """
 
 from __future__ import annotations
@@ -679,6 +681,48 @@ def bench_select5(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_nk_series(args):
+    """The fused build of the 48-atom ring cell (configs 2 and 3: 60x75x54 grid,
+    N 192, n_occ 84, N_ISDF 420) on 1^3, 2^3, 3^3 and 4^3 k-meshes, FP64 and
+    MIXED, points by the GPU QRCP: time per build against N_k (the paper's
+    K-build time grows linearly with the number of k-points)."""
+    import torch
+
+    import synth
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    rows = []
+    for k in (1, 2, 3, 4):
+        cell = synth.make_ring_series_cell(k)
+        t = cell_inputs(h, exx, torch, cell, dev)
+        o = outputs(torch, cell, dev)
+        row = {"kmesh": [k, k, k], "N_k": cell.N_k}
+        for prec in ("f64", "mixed"):
+            def step():
+                exx.exx_build(h, t["cell"], exx.PREC[prec], psi_for(t, prec, torch), t["occ_pts"],
+                              t["ao_pts"], t["pts"], o["K"], o["Ex"], o["rank"])
+
+            s = time_steps(step, max(1, min(args.steps, 3)), 1, torch)
+            row[f"{prec}_ms"] = s * 1e3
+            row[f"{prec}_ms_per_k"] = s * 1e3 / cell.N_k
+            row[f"{prec}_Ex"] = float(o["Ex"].cpu()[0])
+            log(f"[nk-series] {k}x{k}x{k}: {prec} {s * 1e3:.2f} ms/build "
+                f"({s * 1e3 / cell.N_k:.2f} ms per k-point)")
+        rows.append(row)
+        del t, o
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    for prec in ("f64", "mixed"):
+        # slope of log(time) against log(N_k) between consecutive meshes
+        for a, b in zip(rows[1:-1], rows[2:]):
+            b[f"{prec}_exponent_from_prev"] = float(
+                np.log(b[f"{prec}_ms"] / a[f"{prec}_ms"]) / np.log(b["N_k"] / a["N_k"]))
+    print(json.dumps({"workload": "48-atom four-ring cell (60x75x54 grid, N 192, n_occ 84, "
+                                  "N_ISDF 420) on 1^3..4^3 k-meshes", "series": rows}), flush=True)
+
+
 def profile_target_ring(args, config):
     """A profiler's target for one ring cell: one untimed build per precision
     (F64, MIXED, F32), a marker dispatch (one-row exx_mlp_moments), one build per
@@ -778,8 +822,8 @@ def main():
     ap.add_argument("--potentials", action="store_true",
                     help="with --profile and a ring workload: profile the exchange gradient "
                          "and the robust-fit K instead of the builds")
-    ap.add_argument("--workload", choices=("batch24", "rings-k2", "rings-k3", "select-k4"),
-                    default="batch24")
+    ap.add_argument("--workload", choices=("batch24", "rings-k2", "rings-k3", "select-k4",
+                                            "nk-series"), default="batch24")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every GPU box here has one "
@@ -787,6 +831,9 @@ def main():
         sys.exit(2)
     if args.workload == "select-k4":
         bench_select5(args)
+        return
+    if args.workload == "nk-series":
+        bench_nk_series(args)
         return
     if args.profile:
         if args.workload in ("rings-k2", "rings-k3"):

@@ -14,6 +14,7 @@ from .cells import (  # noqa: F401
     make_batch_cells,
     make_random_cell,
     make_ring_cell,
+    make_ring_series_cell,
     ao_on_grid,
     ao_at_points,
     ao_overlap,

@@ -284,6 +284,13 @@ def make_config(config: int, cell_index: int = 0) -> Cell:
     raise ValueError(config)
 
 
+def make_ring_series_cell(k: int) -> Cell:
+    """The 48-atom four-ring cell of configs 2 and 3 (same geometry and basis,
+    60x75x54 grid, n_occ 84, N_ISDF 420) on a k x k x k mesh: the N_k series."""
+    return make_ring_cell(RING_CELL_L, RING_CENTRES_4, (60, 75, 54), (k, k, k), 84, 420,
+                          (SEED_ROOT, 2, 0), name=f"rings-series-k{k}")
+
+
 BATCH_ATOMS = (8, 16, 24, 48)
 BATCH_KMESH = ((1, 1, 1), (2, 2, 2), (3, 3, 3))
 
