@@ -130,3 +130,51 @@ def test_exchange_gradient_rejects_reduced_precision(gpu):
                                   torch.arange(ni, dtype=torch.int32, device=dev), z(nk, na, na),
                                   z(nk, na, na), torch.zeros(1, dtype=torch.float64, device=dev),
                                   torch.zeros(nk, dtype=torch.int32, device=dev), prec=exx.EXX_MIXED)
+
+
+def test_gradient_and_robust_on_caller_workspace(gpu):
+    """exx_workspace_size with EXX_CALL_GRADIENT covers both calls: on a caller
+    buffer of exactly that size they give the results of library-owned scratch
+    bit for bit, and a buffer 256 bytes short is rejected before anything runs."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    cell = GRAD_CELLS["k222-ragged"]()
+    C = synth.orbital_coeffs(cell)
+    psi = synth.orbitals_on_grid(cell, C)
+    phi = np.stack([synth.ao_on_grid(cell, n) for n in range(cell.N_k)])
+    pts, _ = select.select_points(psi, cell.n_isdf)
+    dev = torch.device("cuda", 0)
+    nk, na, ni = cell.N_k, cell.n_ao, len(pts)
+    ao = np.stack([phi[n][:, pts] for n in range(nk)])
+    args = (torch.from_numpy(psi).to(dev),
+            torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev),
+            torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+            torch.from_numpy(np.ascontiguousarray(phi)).to(dev),
+            torch.from_numpy(np.asarray(pts, dtype=np.int32)).to(dev))
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, cell.n_ao, ni)
+
+    def run(h):
+        K = torch.zeros((nk, na, na), dtype=torch.complex128, device=dev)
+        Kg = torch.zeros_like(K)
+        Kr = torch.zeros_like(K)
+        Ex = torch.zeros((1,), dtype=torch.float64, device=dev)
+        rank = torch.zeros((nk,), dtype=torch.int32, device=dev)
+        exx.exx_exchange_gradient(h, c, *args, K, Kg, Ex, rank)
+        exx.exx_build_robust(h, c, *args, Kr, Ex, rank)
+        torch.cuda.synchronize()
+        return K, Kg, Kr
+
+    h = exx.Handle(0)
+    ref = run(h)
+    need = h.workspace_size(c, exx.EXX_F64, exx.EXX_CALL_GRADIENT)
+    buf = torch.empty((need,), dtype=torch.uint8, device=dev)
+    h.set_workspace(buf)
+    got = run(h)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    h.set_workspace(buf[: need - 256])
+    with pytest.raises(exx.ExxError, match="workspace"):
+        run(h)
+    h.set_workspace(None)
