@@ -1513,7 +1513,8 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   if (e == hipSuccess)
     e = launch_grad_xcorr(g, ws + L.V2, true, ws + L.G, ws + L.gCS, nn, stream);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the derivative");
-  // T = CS conj(X^T) - 2 CZ conj(phi)^T, then conj A = (1/N_k^2) X^H conj T
+  // T = CS X^T - 2 CZ phi^H [N_ISDF][n_ao] (X_{mu P} = conj phi_mu(r_P): the conjugated
+  // ao_pts, transposed), then conj A = (1/N_k^2) X conj T
   double2* T = (double2*)(ws + L.gT);
   e = zgemm_splitk(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig, B_C, ao_grid, g.ng,
                    (long)g.nao * g.ng, T, g.nao, na_i, -2.0, false, ws + L.gP, stream);
