@@ -26,7 +26,8 @@ Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --profile
 --workload rings-k2 | rings-k3, two builds per precision of that cell and the
 copy; with --potentials and a ring workload, the exchange gradient and the
 robust-fit K instead); --workload rings-k2 | rings-k3 | select-k4 print a single
-leg; --workload nk-series times the ring cell's build on 1^3..4^3 k-meshes.
+leg; --workload nk-series times the ring cell's build on 1^3..4^3 k-meshes;
+--workload ao-k times THC-AO-K (fit once, K per iteration) on the 2x2x2 ring cell.
 """
 
 from __future__ import annotations
@@ -723,6 +724,94 @@ def bench_nk_series(args):
                                   "N_ISDF 420) on 1^3..4^3 k-meshes", "series": rows}), flush=True)
 
 
+def bench_ao_k(args):
+    """THC-AO-K (Algorithm 1) as the composition of the stage-wise calls on the
+    2x2x2 ring cell (N 192, n_occ 84, 60x75x54 grid): the AO-pair fit and its
+    Coulomb matrices M^q once (exx_isdf_fit + exx_coulomb_V with the AO functions
+    in place of the orbitals, N_ISDF = 2048 = 10.7 N, points by the GPU QRCP on
+    the AO functions), then the per-iteration K-build from the occupied orbitals
+    (exx_build_K), beside THC-oo-K's fused build of the same cell. FP64."""
+    import torch
+
+    import synth
+    from paper_2304_05505_amd import exx
+    from synth.fast import ao_on_grid_torch, orbitals_on_grid_torch
+
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    cell = synth.make_config(2)
+    N, nk, ng = cell.n_ao, cell.N_k, int(np.prod(cell.grid))
+    ni = min(2048, 25 * N)
+    phi = torch.stack([ao_on_grid_torch(cell, n, dev) for n in range(nk)]).contiguous()
+    c_fit = exx.make_cell(cell.L, cell.grid, cell.kmesh, N, N, ni)
+    pts = torch.empty((ni,), dtype=torch.int32, device=dev)
+    npiv = torch.empty((1,), dtype=torch.int32, device=dev)
+    t0 = time.perf_counter()
+    exx.exx_select_points(h, c_fit, phi, pts, npiv)
+    torch.cuda.synchronize()
+    t_sel = time.perf_counter() - t0
+    log(f"[ao-k] QRCP on the AO functions: {int(npiv.cpu()[0])} pivots in {t_sel:.1f} s")
+    ao_pts = phi[:, :, pts.long()].permute(0, 2, 1).contiguous()  # (N_k, N_I, N)
+    xi = torch.empty((nk, ni, ng), dtype=torch.complex128, device=dev)
+    S = torch.empty((nk, ni, ni), dtype=torch.complex128, device=dev)
+    V = torch.empty_like(S)
+    rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+
+    def fit():
+        exx.exx_isdf_fit(h, c_fit, exx.EXX_F64, phi, ao_pts, pts, xi, S, rank)
+        exx.exx_coulomb_V(h, c_fit, exx.EXX_F64, xi, pts, V)
+
+    s_fit = time_steps(fit, 1, 1, torch)
+    log(f"[ao-k] AO-pair fit + M^q: {s_fit * 1e3:.1f} ms, ranks {rank.cpu().tolist()}")
+    del xi, S
+    torch.cuda.empty_cache()
+    psi = orbitals_on_grid_torch(cell, synth.orbital_coeffs(cell), dev)
+    occ = psi[:, :, pts.long()].permute(0, 2, 1).contiguous()
+    c_k = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, N, ni)
+    o = outputs(torch, cell, dev)
+
+    def iteration():
+        exx.exx_build_K(h, c_k, exx.EXX_F64, ao_pts, occ, V, o["K"], o["Ex"])
+
+    s_it = time_steps(iteration, max(1, args.steps), max(1, args.warmup), torch)
+    ex_ao = float(o["Ex"].cpu()[0])
+    log(f"[ao-k] per-iteration K-build: {s_it * 1e3:.2f} ms, E_x {ex_ao:.8f}")
+    del V, phi, ao_pts
+    torch.cuda.empty_cache()
+    # THC-oo-K's fused build of the same cell (refit every iteration)
+    t = cell_inputs(h, exx, torch, cell, dev)
+
+    def oo():
+        exx.exx_build(h, t["cell"], exx.EXX_F64, t["psi64"], t["occ_pts"], t["ao_pts"], t["pts"],
+                      o["K"], o["Ex"], o["rank"])
+
+    s_oo = time_steps(oo, max(1, args.steps), max(1, args.warmup), torch)
+    ex_oo = float(o["Ex"].cpu()[0])
+    log(f"[ao-k] THC-oo-K fused build: {s_oo * 1e3:.2f} ms, E_x {ex_oo:.8f}")
+    del t
+    torch.cuda.empty_cache()
+    # THC-oo-K at the same point count as the AO fit: its least-squares fit
+    # projects the occupied pairs, so |E_x| grows towards the exact value with
+    # N_ISDF; the larger fit bounds how much exchange the exact answer holds
+    from synth import cells as sc
+
+    big = synth.make_ring_cell(sc.RING_CELL_L, sc.RING_CENTRES_4, cell.grid, cell.kmesh,
+                               cell.n_occ, ni, (sc.SEED_ROOT, 2, 0), name="rings-k2-2048")
+    t2 = cell_inputs(h, exx, torch, big, dev)
+    exx.exx_build(h, t2["cell"], exx.EXX_F64, t2["psi64"], t2["occ_pts"], t2["ao_pts"], t2["pts"],
+                  o["K"], o["Ex"], o["rank"])
+    torch.cuda.synchronize()
+    ex_oo_big = float(o["Ex"].cpu()[0])
+    log(f"[ao-k] THC-oo-K with N_ISDF {ni}: E_x {ex_oo_big:.8f}")
+    print(json.dumps({
+        "workload": "48-atom four-ring cell, 2x2x2 k-mesh, N=192, n_occ=84, grid 60x75x54",
+        "ao_k": {"n_isdf": ni, "n_pivot": int(npiv.cpu()[0]), "selection_s": t_sel,
+                 "fit_and_Mq_ms": s_fit * 1e3, "per_iteration_ms": s_it * 1e3, "Ex": ex_ao},
+        "oo_k": {"n_isdf": cell.n_isdf, "build_ms": s_oo * 1e3, "Ex": ex_oo,
+                 "Ex_at_ao_k_point_count": ex_oo_big},
+        "precision": "f64"}), flush=True)
+
+
 def profile_target_ring(args, config):
     """A profiler's target for one ring cell: one untimed build per precision
     (F64, MIXED, F32), a marker dispatch (one-row exx_mlp_moments), one build per
@@ -823,7 +912,7 @@ def main():
                     help="with --profile and a ring workload: profile the exchange gradient "
                          "and the robust-fit K instead of the builds")
     ap.add_argument("--workload", choices=("batch24", "rings-k2", "rings-k3", "select-k4",
-                                            "nk-series"), default="batch24")
+                                            "nk-series", "ao-k"), default="batch24")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every GPU box here has one "
@@ -834,6 +923,9 @@ def main():
         return
     if args.workload == "nk-series":
         bench_nk_series(args)
+        return
+    if args.workload == "ao-k":
+        bench_ao_k(args)
         return
     if args.profile:
         if args.workload in ("rings-k2", "rings-k3"):
