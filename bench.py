@@ -335,7 +335,10 @@ def ring_leg(config, args, h, exx, torch, dev):
              if "dEx_vs_oracle" in r else ""))
     for label in res:
         res[label]["speedup_vs_f64"] = res["f64"]["ms_per_build"] / res[label]["ms_per_build"]
-    if config == 2:  # the 3x3x3 cell's potentials would need ~150 GB more
+    # the gradient and robust calls: on the 2x2x2 cell always; on the 3x3x3 cell
+    # (three N_k N_I N_g c128 arrays, 132 GB, beside the build's scratch) only
+    # when that workload is asked for by itself
+    if config == 2 or args.workload == "rings-k3":
         res.update(potential_legs(args, h, exx, torch, dev, cell, t, res["f64"]["ms_per_build"],
                                   tag))
     return {"workload": f"48-atom four-ring cell, {'x'.join(map(str, cell.kmesh))} k-mesh, N=192, "

@@ -166,7 +166,11 @@ __device__ constexpr int mesh_add_c(int n, int m, int sign) {
 
 // The same sums (p^m = P^m) on a mesh known at compile time: each element's N_k
 // values of P and Q are held in registers, every transfer index is a constant.
-template <bool UP_ONLY, int N1, int N2, int N3>
+// MODE: XR_BOTH writes both terms, XR_UP the first term alone, XR_DOWN adds the
+// second term to out (a larger mesh runs XR_UP then XR_DOWN, so that one pass
+// holds no more than 2 N_k complex values in registers).
+enum { XR_BOTH = 0, XR_UP = 1, XR_DOWN = 2 };
+template <int MODE, int N1, int N2, int N3>
 __global__ __launch_bounds__(256) void grad_xcorr_reg_kernel(const double2* __restrict__ P,
                                                             const double2* __restrict__ Q,
                                                             double2* __restrict__ out,
@@ -183,12 +187,19 @@ __global__ __launch_bounds__(256) void grad_xcorr_reg_kernel(const double2* __re
 #pragma unroll
   for (int n = 0; n < NK; ++n) {
     double sx = 0.0, sy = 0.0;
+    if (MODE == XR_DOWN) {
+      const double2 o = out[(long)n * elems + e];
+      sx = o.x;
+      sy = o.y;
+    }
 #pragma unroll
     for (int m = 0; m < NK; ++m) {
-      const double2 qu = q[mesh_add_c<N1, N2, N3>(n, m, 1)];
-      sx += p[m].x * qu.x + p[m].y * qu.y;
-      sy += p[m].y * qu.x - p[m].x * qu.y;
-      if (!UP_ONLY) {
+      if (MODE != XR_DOWN) {
+        const double2 qu = q[mesh_add_c<N1, N2, N3>(n, m, 1)];
+        sx += p[m].x * qu.x + p[m].y * qu.y;
+        sy += p[m].y * qu.x - p[m].x * qu.y;
+      }
+      if (MODE != XR_UP) {
         const double2 qd = q[mesh_add_c<N1, N2, N3>(n, m, -1)];
         sx += p[m].x * qd.x - p[m].y * qd.y;
         sy += -p[m].x * qd.y - p[m].y * qd.x;
@@ -265,10 +276,10 @@ hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const vo
 #define EXX_XREG(a, b, c)                                                                      \
   if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                             \
     if (up_only)                                                                               \
-      hipLaunchKernelGGL((grad_xcorr_reg_kernel<true, a, b, c>), grid, dim3(256), 0, st, p, q, \
-                         o, elems);                                                            \
+      hipLaunchKernelGGL((grad_xcorr_reg_kernel<XR_UP, a, b, c>), grid, dim3(256), 0, st, p,   \
+                         q, o, elems);                                                         \
     else                                                                                       \
-      hipLaunchKernelGGL((grad_xcorr_reg_kernel<false, a, b, c>), grid, dim3(256), 0, st, p,   \
+      hipLaunchKernelGGL((grad_xcorr_reg_kernel<XR_BOTH, a, b, c>), grid, dim3(256), 0, st, p, \
                          q, o, elems);                                                         \
     return hipGetLastError();                                                                  \
   }
@@ -287,6 +298,14 @@ hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const vo
     EXX_XREG(1, 2, 3)
     EXX_XREG(2, 3, 1)
 #undef EXX_XREG
+    if (g.N[0] == 3 && g.N[1] == 3 && g.N[2] == 3) {  // two passes: 2 x 27 values each
+      hipLaunchKernelGGL((grad_xcorr_reg_kernel<XR_UP, 3, 3, 3>), grid, dim3(256), 0, st, p, q,
+                         o, elems);
+      if (!up_only)
+        hipLaunchKernelGGL((grad_xcorr_reg_kernel<XR_DOWN, 3, 3, 3>), grid, dim3(256), 0, st, p,
+                           q, o, elems);
+      return hipGetLastError();
+    }
   }
   if (g.nk <= 32) {  // LDS staging, at most 64 KiB per workgroup
     const dim3 gl((unsigned)((elems + 63) / 64));

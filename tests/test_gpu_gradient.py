@@ -1,8 +1,8 @@
 """The density derivative of the fitted exchange energy (exx_exchange_gradient,
 FP64) against the gradient oracle (thc.thc_oo_k_gradient, itself pinned by finite
 differences of the fitted energy) on the Gamma point, real-path, odd-grid,
-ragged, 3x3x3 and 4x4x4 meshes (the k-correlations' register, LDS-staged and
-direct forms), with the fit at and below the pair rank.
+ragged, 3x3x3, 5x1x1 and 4x4x4 meshes (the k-correlations' register, two-pass
+register, LDS-staged and direct forms), with the fit at and below the pair rank.
 
 * Ranks equal; E_x, K and Kgrad (relative to max|Kgrad|) to
   min(1e-8, max(1e-12, 64 eps64 cond)), cond the largest cond(S^m) over the
@@ -41,7 +41,8 @@ GRAD_CELLS = {
                                             (7, 7, 9)),
     "k222-ragged": CELLS["k222-ragged"],
     "k112-odd": CELLS["k112-odd"],
-    "k333": CELLS["k333"],
+    "k333": CELLS["k333"],  # the correlations' two-pass register form
+    "k511": CELLS["k511"],  # a mesh without a compiled form: LDS staging
     "k444": CELLS["k444"],  # 64 transfers: the correlations' direct form (no staging)
 }
 

@@ -2,7 +2,7 @@
 oracle (thc.thc_oo_k_robust, pinned by the residual identity
 K_direct - K_rob = K[delta, delta] on explicit residual pair densities) on the
 meshes of the gradient test (Gamma point, real path, odd grid, ragged N_ISDF,
-3x3x3, 4x4x4; fits at and below the pair rank).
+3x3x3, 5x1x1, 4x4x4; fits at and below the pair rank).
 
 * Ranks equal; E_x and K_rob (relative to max|K_rob|) to
   min(1e-8, max(1e-12, 64 eps64 cond)), cond the largest cond(S^m) over the
