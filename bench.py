@@ -73,7 +73,7 @@ def real_path(cell):
 
 
 def work(cell, prec):
-    """Per-build work of each phase: {phase: (unit, executed, survey)}.
+    """Per-build work of each phase: {phase: (unit, executed, plain)}.
 
     `executed` counts what the kernels do after the method's exact identities:
     on meshes with every N_i <= 2 the unphased metric and right-hand side are
@@ -82,7 +82,7 @@ def work(cell, prec):
     n1 n2 (n3/2 + 1) points, lower triangle); elsewhere one transfer of each
     pair (m, -m) is fitted, transformed and contracted (complex, Gauss's
     three-product form on the FP64 matrix cores: 6 flops per complex
-    multiply-add; triangular solve; lower triangle of V). `survey` counts the
+    multiply-add; triangular solve; lower triangle of V). `plain` counts the
     plain method: Gamma 8 N_k N_I n_o N_g, solve 8 N_k N_I^2 N_g, Coulomb
     (Hermitian) 4 N_k N_I^2 N_g, one read and one write of the N_k N_I N_g
     intermediate for the k-correlation and the transform.
@@ -166,28 +166,28 @@ def traffic_for(phase):
                        "lines served by the last-level cache"}
 
 
-def phase_rate(p, phase_ms, work_exec, work_survey, units, prec):
-    """Achieved rate of phase p (executed and survey work counts) over its summed time."""
+def phase_rate(p, phase_ms, work_exec, work_plain, units, prec):
+    """Achieved rate of phase p (executed and plain-method work counts) over its summed time."""
     s = phase_ms[p] / 1e3
     if units[p] == "byte":
-        a, a_sv = work_exec[p] / s / 1e9, work_survey[p] / s / 1e9
+        a, a_sv = work_exec[p] / s / 1e9, work_plain[p] / s / 1e9
         out = {"bound": "hbm", "achieved": a, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
                "frac": a / PEAK["hbm_GBs"]}
     else:
-        a, a_sv = work_exec[p] / s / 1e12, work_survey[p] / s / 1e12
+        a, a_sv = work_exec[p] / s / 1e12, work_plain[p] / s / 1e12
         peak = PEAK["fp64_TF"] if p in FP64_CORES[prec] else PEAK["fp32_TF"]
         out = {"bound": "mfma", "achieved": a, "peak": peak, "unit": "TFLOP/s", "frac": a / peak}
     out.update({"phase_ms": phase_ms[p], "work_executed": work_exec[p],
-                "work_survey": work_survey[p], "achieved_survey_count": a_sv,
-                "frac_survey_count": a_sv / out["peak"]})
+                "work_plain": work_plain[p], "achieved_plain_count": a_sv,
+                "frac_plain_count": a_sv / out["peak"]})
     return out
 
 
-def roofline(phase_ms, work_exec, work_survey, units, prec):
+def roofline(phase_ms, work_exec, work_plain, units, prec):
     """Roofline of the phase with the largest summed time. phase_ms: {phase: ms};
     work_*: {phase: amount} summed over the same builds."""
     best = max((p for p in phase_ms if p in work_exec and phase_ms[p] > 0), key=lambda p: phase_ms[p])
-    out = phase_rate(best, phase_ms, work_exec, work_survey, units, prec)
+    out = phase_rate(best, phase_ms, work_exec, work_plain, units, prec)
     out.update({"traffic": traffic_for(best), "phase": best})
     return out
 
@@ -531,7 +531,7 @@ CPU_SAMPLE = ("batch0-a8-k1", "batch1-a8-k2", "batch3-a16-k1")
 def cpu_baseline(cells):
     """Complete FP64 oracle K-builds (same steps as the GPU build) of three small
     cells of the batch, median of three passes; scaled to the batch by the plain
-    method's work (Gamma + solve + Coulomb flops of the survey count)."""
+    method's work (Gamma + solve + Coulomb flops of the plain-method count)."""
     import synth
     from oracle import select, thc
     from oracle._threads import WORKERS
@@ -918,8 +918,8 @@ def main():
                                             "nk-series", "ao-k"), default="batch24")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): every GPU box here has one "
-              "GPU; the batch would shard by cell across GPUs with no exchange", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}); across GPUs the batch would "
+              "shard by cell with no exchange, which is not timed", file=sys.stderr)
         sys.exit(2)
     if args.workload == "select-k4":
         bench_select5(args)
