@@ -392,7 +392,45 @@ def potential_legs(args, h, exx, torch, dev, cell, t, f64_ms, tag):
             f"build, {s * 1e3 / stage_ms:.2f}x the stage-wise one)")
     del ao_grid, Kg
     torch.cuda.empty_cache()
+    if not args.no_cpu:
+        out["f64-gradient"]["cpu_oracle"] = gradient_cpu_sample(h, exx, torch, dev, tag)
     return out
+
+
+def gradient_cpu_sample(h, exx, torch, dev, tag):
+    """The gradient oracle timed beside the GPU call on one small cell of the
+    batch (the 8-atom 2x2x2 cell: N 32, n_occ 14, N_ISDF 70, 36x45x32 grid):
+    one oracle call (thc_oo_k_gradient: fit, potentials, correlations, AO
+    products, all FP64 on the host) against the median GPU call."""
+    import synth
+    from oracle import select, thc
+    from oracle._threads import WORKERS
+
+    cell = [c for c in synth.make_batch_cells() if c.name == "batch1-a8-k2"][0]
+    psi = synth.orbitals_on_grid(cell, synth.orbital_coeffs(cell))
+    phi = np.stack([synth.ao_on_grid(cell, n) for n in range(cell.N_k)])
+    pts, _ = select.select_points(psi, cell.n_isdf)
+    t0 = time.perf_counter()
+    ref = thc.thc_oo_k_gradient(cell.L, cell.grid, cell.kmesh, psi, phi, pts)
+    t_cpu = time.perf_counter() - t0
+    nk, na, ni = cell.N_k, cell.n_ao, len(pts)
+    ao = np.stack([phi[n][:, pts] for n in range(nk)])
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, na, ni)
+    args_t = (torch.from_numpy(psi).to(dev),
+              torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev),
+              torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+              torch.from_numpy(np.ascontiguousarray(phi)).to(dev),
+              torch.from_numpy(np.asarray(pts, dtype=np.int32)).to(dev))
+    K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+    Kg = torch.empty_like(K)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+    s = time_steps(lambda: exx.exx_exchange_gradient(h, c, *args_t, K, Kg, Ex, rank), 5, 1, torch)
+    dG = float(np.abs(Kg.cpu().numpy() - ref["Kgrad"]).max() / np.abs(ref["Kgrad"]).max())
+    log(f"[{tag}] gradient on {cell.name}: oracle {t_cpu:.1f} s on the host, GPU {s * 1e3:.2f} ms, "
+        f"rel max|dKgrad| {dG:.1e}")
+    return {"cell": cell.name, "oracle_s": t_cpu, "gpu_ms": s * 1e3, "cores": WORKERS,
+            "cpu_model": cpu_info(), "rel_max_dKgrad": dG}
 
 
 # ---------------------------------------------------------------------------
