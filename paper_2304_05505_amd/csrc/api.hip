@@ -392,10 +392,12 @@ exx_status finish(exx_context* h, hipStream_t st) {
 
 // TF: type of Gamma^n / Z^m (and of psi_grid); TX: storage type of xi
 // bf16 (with TF = float): Gamma^n on the BF16 matrix cores
+// in_grid (TF == TX): leave xi in the handle's grid buffer and use `xi` only as
+// the solve's scratch (no final copy)
 template <typename TF, typename TX>
 exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                     const void* psi, const void* occ, const int32_t* pts, void* xi, void* S,
-                    int32_t* rank, hipStream_t st, bool bf16 = false) {
+                    int32_t* rank, hipStream_t st, bool bf16 = false, bool in_grid = false) {
   double2* G = (double2*)(ws + L.G);
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
@@ -501,7 +503,7 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
       e = zgemm_nn_grid<TX, TF>(g.ni, g.ng, g.ni, g.nk, WH, g.ni, nn, false, xi, g.ng,
                                 (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, st,
                                 h->tile_solve);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !in_grid)
       e = launch_convert<TF, TX>(grid, xi, (long)g.nk * g.ni * g.ng, st);
     if (e != hipSuccess) return hip_check(h, e, "solve gemm");
     return EXX_OK;
@@ -523,6 +525,10 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
                                   (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, 1, st);
     if (e != hipSuccess) return hip_check(h, e, "refinement update");
   }
+  if (in_grid) {
+    e = launch_convert<TX, TF>(xi, grid, (long)g.nk * g.ni * g.ng, st);
+    if (e != hipSuccess) return hip_check(h, e, "xi into the grid buffer");
+  }
   return EXX_OK;
 }
 
@@ -530,8 +536,8 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
 template <typename T>
 exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                         const void* xi, const int32_t* pts, void* V, hipStream_t st,
-                        int cform = COUL_F64) {
-  void* F = ws + L.grid;
+                        int cform = COUL_F64, void* Fout = nullptr) {
+  void* F = Fout ? Fout : ws + L.grid;  // the transforms F^m
   hipError_t e;
   {
     PhaseTimer pt(h, PH_FFT, st);
@@ -1435,10 +1441,11 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
 namespace exx {
 namespace {
 
-// The FP64 build (fit into grid2/S2, V^m into V2, K and E_x) followed by the
+// The FP64 build (the fit leaves xi in grid, with grid2 as the solve's scratch;
+// S into S2, V^m into V2 with the transforms in grid2; K and E_x) followed by the
 // potentials of the fitted functions and Gamma^n, shared by the gradient and the
-// robust-fit K. On return: grid2 = Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r)
-// [N_k][N_ISDF][N_g], grid = Gamma^n [N_k][N_ISDF][N_g], G = G^n, V2 = Vb^m.
+// robust-fit K. On return: grid = Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r)
+// [N_k][N_ISDF][N_g], grid2 = Gamma^n [N_k][N_ISDF][N_g], G = G^n, V2 = Vb^m.
 exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                                  const Layout& L, const void* psi_grid, const void* occ_pts,
                                  const void* ao_pts, const int32_t* pts, void* K, double* Ex,
@@ -1446,12 +1453,14 @@ exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb
   exx_status s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
   if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
   if (s != EXX_OK) return s;
-  // the fit (xi into grid2, S into S2), V^m (Bloch gauge, into V2; the transforms
-  // F^m stay in grid), K and E_x with the fit's G^n
-  void* xi = ws + L.grid2;
-  s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, ws + L.S2, rank,
-                               stream);
-  if (s == EXX_OK) s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream);
+  // the fit (xi left in grid, S into S2), V^m (Bloch gauge, into V2; the
+  // transforms F^m into grid2), K and E_x with the fit's G^n
+  void* xi = ws + L.grid;
+  s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, ws + L.grid2, ws + L.S2,
+                               rank, stream, false, true);
+  if (s == EXX_OK)
+    s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, COUL_F64,
+                             ws + L.grid2);
   if (s == EXX_OK)
     s = buildK_impl(h, g, kscratch(ws, L), ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
   if (s != EXX_OK) return s;
@@ -1459,17 +1468,17 @@ exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb
   hipError_t e = launch_kernel_table(g, vt, stream);
   if (e != hipSuccess) return hip_check(h, e, "kernel table");
   // conj Phi^m scaled by N_g^2 / Omega: the forward transform of conj(v^m F^m)
-  // (xi is no longer needed: grid2 takes the potentials)
-  e = launch_kernel_scale_conj(g, ws + L.grid, vt, stream);
+  // (xi is no longer needed: grid takes the potentials)
+  e = launch_kernel_scale_conj(g, ws + L.grid2, vt, stream);
   if (e == hipSuccess)
-    e = launch_fft3d<double>(g, tb, ws + L.grid, ws + L.grid2, (long)g.nk * g.ni, h->ncu, stream);
+    e = launch_fft3d<double>(g, tb, ws + L.grid2, ws + L.grid, (long)g.nk * g.ni, h->ncu, stream);
   if (e != hipSuccess) return hip_check(h, e, "potentials");
   const double omega = (double)g.L[0] * g.L[1] * g.L[2];
-  e = launch_potential_phase(g, tb, ws + L.grid2, pts, omega / ((double)g.ng * g.ng), stream);
+  e = launch_potential_phase(g, tb, ws + L.grid, pts, omega / ((double)g.ng * g.ng), stream);
   if (e != hipSuccess) return hip_check(h, e, "potential phase");
-  // Gamma^n again (the fit turned its copy into Z^m), into grid
+  // Gamma^n again (the fit turned its copy into Z^m), into grid2
   e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ_pts, g.no, (long)g.ni * g.no, true,
-                                    psi_grid, g.ng, (long)g.no * g.ng, ws + L.grid, g.ng,
+                                    psi_grid, g.ng, (long)g.no * g.ng, ws + L.grid2, g.ng,
                                     (long)g.ni * g.ng, stream, h->tile_gamma);
   if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
   return EXX_OK;
@@ -1509,7 +1518,7 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   if (s != EXX_OK) return s;
   const long nn = (long)g.ni * g.ni, na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // CZ^n over the grid and CS^n over the points (U^m = conj Vb^m: Vb^m is Hermitian)
-  hipError_t e = launch_grad_xcorr(g, ws + L.grid2, false, ws + L.grid, ws + L.g3, nig, stream);
+  hipError_t e = launch_grad_xcorr(g, ws + L.grid, false, ws + L.grid2, ws + L.g3, nig, stream);
   if (e == hipSuccess)
     e = launch_grad_xcorr(g, ws + L.V2, true, ws + L.G, ws + L.gCS, nn, stream);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the derivative");
@@ -1555,7 +1564,7 @@ exx_status exx_build_robust(exx_handle_t h, const exx_cell* cell, exx_prec prec,
   const long na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // R^n = sum_m Pw^m o conj Gamma^{n+m}
   hipError_t e =
-      launch_grad_xcorr(g, ws + L.grid2, false, ws + L.grid, ws + L.g3, nig, stream, true);
+      launch_grad_xcorr(g, ws + L.grid, false, ws + L.grid2, ws + L.g3, nig, stream, true);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the one-sided term");
   // T = R conj(phi)^T [N_ISDF][n_ao], then conj of the one-sided term
   // (1/N_k) T^T A = conj((1/N_k) T^H conj A)

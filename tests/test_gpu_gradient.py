@@ -179,3 +179,41 @@ def test_gradient_and_robust_on_caller_workspace(gpu):
     with pytest.raises(exx.ExxError, match="workspace"):
         run(h)
     h.set_workspace(None)
+
+
+def test_gradient_with_one_refinement_step(gpu):
+    """With one step of iterative refinement the fit applies the explicit S^+
+    and refines it (the path that leaves xi in the caller-side buffer and copies
+    it for the potentials): the gradient is still the oracle's to the same
+    tolerance (refinement only reduces the solve's residual)."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    cell = GRAD_CELLS["k311"]()
+    psi = synth.orbitals_on_grid(cell, synth.orbital_coeffs(cell))
+    phi = np.stack([synth.ao_on_grid(cell, n) for n in range(cell.N_k)])
+    pts, _ = select.select_points(psi, cell.n_isdf)
+    o = thc.thc_oo_k_gradient(cell.L, cell.grid, cell.kmesh, psi, phi, pts)
+    tol = min(1e-8, max(1e-12, 64 * EPS64 * _cond(o)))
+    dev = torch.device("cuda", 0)
+    nk, na, ni = cell.N_k, cell.n_ao, len(pts)
+    ao = np.stack([phi[n][:, pts] for n in range(nk)])
+    K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+    Kg = torch.empty_like(K)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+    h = exx.Handle(0)
+    h.set_refinement(1)
+    exx.exx_exchange_gradient(
+        h, exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, na, ni),
+        torch.from_numpy(psi).to(dev),
+        torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev),
+        torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+        torch.from_numpy(np.ascontiguousarray(phi)).to(dev),
+        torch.from_numpy(np.asarray(pts, dtype=np.int32)).to(dev), K, Kg, Ex, rank)
+    torch.cuda.synchronize()
+    dG = np.abs(Kg.cpu().numpy() - o["Kgrad"]).max() / np.abs(o["Kgrad"]).max()
+    dE = abs(float(Ex.cpu()[0]) - o["Ex"]) / abs(o["Ex"])
+    print(f"refined: rel dE {dE:.2e} dKgrad {dG:.2e} tol {tol:.1e}")
+    assert dE <= tol and dG <= tol
