@@ -51,3 +51,9 @@ def test_null_handle_paths_need_no_device(lib):
     assert lib.exx_create(None, 0) == -1  # EXX_ERR_ARG
     lib.exx_destroy.argtypes = [ctypes.c_void_p]
     assert lib.exx_destroy(None) == -1
+    # the calls beyond the build reject a null handle before touching the device
+    vp = ctypes.c_void_p
+    lib.exx_exchange_gradient.argtypes = [vp, vp, ctypes.c_int] + [vp] * 10
+    assert lib.exx_exchange_gradient(None, None, 0, *([None] * 10)) == -1
+    lib.exx_build_robust.argtypes = [vp, vp, ctypes.c_int] + [vp] * 9
+    assert lib.exx_build_robust(None, None, 0, *([None] * 9)) == -1

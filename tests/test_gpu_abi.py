@@ -47,6 +47,43 @@ def test_bad_arguments_are_rejected(gpu):
     assert "precision" in msg
 
 
+def test_gradient_and_robust_reject_bad_arguments(gpu):
+    """exx_exchange_gradient and exx_build_robust: a null array, a bad shape and a
+    precision other than EXX_F64 are rejected before launch, with the message."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    h = exx.Handle(0)
+    dev = torch.device("cuda", 0)
+    lib = exx._lib
+    st = torch.cuda.current_stream().cuda_stream
+
+    def call(fn, c, prec, null_ao_grid=False):
+        nk = c.kmesh[0] * c.kmesh[1] * c.kmesh[2]
+        ng = c.grid[0] * c.grid[1] * c.grid[2]
+        z = lambda *shape: torch.zeros(shape, dtype=torch.complex128, device=dev)  # noqa: E731
+        t = [z(nk, c.n_occ, ng), z(nk, c.n_isdf, c.n_occ), z(nk, c.n_isdf, c.n_ao),
+             z(nk, c.n_ao, ng), torch.arange(c.n_isdf, dtype=torch.int32, device=dev),
+             z(nk, c.n_ao, c.n_ao), z(nk, c.n_ao, c.n_ao),
+             torch.zeros((1,), dtype=torch.float64, device=dev),
+             torch.zeros((nk,), dtype=torch.int32, device=dev)]
+        ptrs = [x.data_ptr() for x in t]
+        if null_ao_grid:
+            ptrs[3] = None
+        if fn == "robust":
+            del ptrs[6]  # no Kgrad
+            return lib.exx_build_robust(h.raw, ctypes.byref(c), prec, *ptrs, st)
+        return lib.exx_exchange_gradient(h.raw, ctypes.byref(c), prec, *ptrs, st)
+
+    for fn in ("gradient", "robust"):
+        assert call(fn, _cell(exx), exx.EXX_F64, null_ao_grid=True) == -1
+        assert "null array" in exx._lib.exx_last_error(h.raw).decode()
+        assert call(fn, _cell(exx, grid=(12, 12, 7)), exx.EXX_F64) == -2
+        assert call(fn, _cell(exx), exx.EXX_MIXED) == -7  # EXX_ERR_UNSUPPORTED
+        assert "FP64" in exx._lib.exx_last_error(h.raw).decode()
+
+
 def test_all_zero_orbitals_drop_every_point(gpu):
     """S = 0: every pivot is dropped, rank 0, xi = 0, and nothing faults."""
     from paper_2304_05505_amd import exx
