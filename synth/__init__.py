@@ -15,6 +15,7 @@ from .cells import (  # noqa: F401
     make_random_cell,
     make_ring_cell,
     make_ring_series_cell,
+    make_config5_coarse,
     ao_on_grid,
     ao_at_points,
     ao_overlap,

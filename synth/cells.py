@@ -284,6 +284,15 @@ def make_config(config: int, cell_index: int = 0) -> Cell:
     raise ValueError(config)
 
 
+def make_config5_coarse() -> Cell:
+    """Config 5's cell (4x4x4 mesh, four-ring cell with 2s + 2p per atom,
+    n_occ 84, N_ISDF 420, the same seed) sampled on the coarser 36x45x32 grid:
+    the 4x4x4 parity case whose FP64 oracle finishes in about an hour."""
+    return make_ring_cell(RING_CELL_L, RING_CENTRES_4, (36, 45, 32), (4, 4, 4), 84, 420,
+                          (SEED_ROOT, 5, 0), name="config5c-rings-2s2p-k4-coarse",
+                          basis="2s2p")
+
+
 def make_ring_series_cell(k: int) -> Cell:
     """The 48-atom four-ring cell of configs 2 and 3 (same geometry and basis,
     60x75x54 grid, n_occ 84, N_ISDF 420) on a k x k x k mesh: the N_k series."""

@@ -12,6 +12,8 @@ Runs only the FP64 oracle (``oracle/``) on the seeded inputs from ``synth``:
 * ``config5.json`` + ``config5_K.npz``: the 4x4x4 ring cell with 2s + 2p per atom
   (N = 384, n_occ = 84, grid 72x90x64, N_ISDF = 420), all 64 transfers: E_x,
   ranks, cond(S^m), every diagonal of K and 4000 seeded entries.
+* ``config5c.json`` + ``config5c_K.npz``: the same 4x4x4 cell on the coarser
+  36x45x32 grid (same seed, basis, n_occ and N_ISDF), with the same contents.
 * ``config4.json`` + ``config4_K.npz``: the 24 cells of the batched workload
   (2 x {8, 16, 24, 48 atoms} x {1^3, 2^3, 3^3}), each with its own oracle
   points: E_x (two forms), ranks, cond(S^m), the diagonal of every K^k and
@@ -19,10 +21,10 @@ Runs only the FP64 oracle (``oracle/``) on the seeded inputs from ``synth``:
 
 Each ``.npz`` holds plain complex128 arrays (no pickled objects).
 
-Usage: ``python tests/golden/make_golden.py [config2] [config3] [config4] [config5]``.
+Usage: ``python tests/golden/make_golden.py [config2] [config3] [config4] [config5] [config5c]``.
 Wall times on 8 cores: config2 a few minutes (~25 GB RAM), config3 about
-half an hour (~30 GB), config4 about an hour (~30 GB), config5 a few hours
-(~50 GB).
+half an hour (~30 GB), config4 about an hour (~30 GB), config5c about an hour
+(~35 GB), config5 about half a day (~40 GB).
 """
 
 from __future__ import annotations
@@ -190,16 +192,18 @@ def make_config4(path):
     print(f"wrote {path}", flush=True)
 
 
-def make_config5(path):
+def make_config5(path, coarse=False):
     """The 4x4x4 ring cell with the 2s + 2p basis (N = 384, n_occ = 84, grid
-    72x90x64, N_ISDF = 420): oracle points, E_x (two forms), ranks, cond(S^m),
-    the diagonal of every K^k and 4000 seeded entries of K."""
+    72x90x64, N_ISDF = 420; with coarse, the same cell on the 36x45x32 grid):
+    oracle points, E_x (two forms), ranks, cond(S^m), the diagonal of every K^k
+    and 4000 seeded entries of K."""
     t0 = time.time()
-    c = synth.make_config(5)
+    c = synth.make_config5_coarse() if coarse else synth.make_config(5)
+    tag = "config5c" if coarse else "config5"
     C = synth.orbital_coeffs(c)
     psi = synth.orbitals_on_grid(c, C)
     pts, npiv = select.select_points(psi, c.n_isdf)
-    print(f"config5: points selected ({npiv} pivots) in {time.time() - t0:.0f} s", flush=True)
+    print(f"{tag}: points selected ({npiv} pivots) in {time.time() - t0:.0f} s", flush=True)
     ao = np.stack([synth.ao_at_points(c, n, pts) for n in range(c.N_k)])
     t1 = time.time()
     o = thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao)
@@ -211,7 +215,7 @@ def make_config5(path):
     knu = rng.integers(0, na, 4000)
     out = {
         "workload": "48-atom four-ring cell, 4x4x4 mesh, 2s+2p basis N=384, n_occ=84, grid "
-                    "72x90x64, N_ISDF=420",
+                    f"{'x'.join(map(str, c.grid))}, N_ISDF=420",
         "seed": list(c.seed),
         "pts": [int(x) for x in pts],
         "n_pivot": int(npiv),
@@ -241,3 +245,5 @@ if __name__ == "__main__":
         make_config4(os.path.join(HERE, "config4.json"))
     if "config5" in which:
         make_config5(os.path.join(HERE, "config5.json"))
+    if "config5c" in which:
+        make_config5(os.path.join(HERE, "config5c.json"), coarse=True)
