@@ -67,3 +67,32 @@ def test_gradient_matches_finite_differences(kind):
     assert abs(e_euler - g["Ex"]) <= 1e-10 * abs(g["Ex"])
     for n in range(c.N_k):
         assert np.abs(g["Kgrad"][n] - g["Kgrad"][n].conj().T).max() <= 1e-12 * np.abs(g["Kgrad"]).max()
+
+
+@pytest.mark.parametrize("m", [0, 1])
+def test_potentials_of_a_plane_wave(m):
+    """phased_potentials on single Fourier modes: xi_P(r) = e^{2 pi i g_P.c / n}
+    (grid index c) has F_P = N_g at g_P alone, so its potential is
+    Phi_P = (Omega/N_g) v^m(g_P) e^{2 pi i g_P.c / n}, and the returned
+    Pw_P(r) = e^{i q_m.(r_P - r)} conj Phi_P(r) follows in closed form (the
+    normalisation, the sign of the exponent, the conjugate and the phase)."""
+    from oracle import coulomb
+
+    L, grid, kmesh = (5.0, 6.0, 7.0), (8, 9, 10), (2, 1, 1)
+    ng = int(np.prod(grid))
+    c = np.stack(np.unravel_index(np.arange(ng), grid), axis=-1)
+    modes = np.array([[1, 2, 3], [0, 0, 1], [7, 8, 9], [3, 0, 5]])
+    pts = np.array([0, 17, 250, 719])
+    arg = 2 * np.pi * (modes[:, None, :] * c[None, :, :] / np.array(grid)).sum(-1)
+    xi = np.zeros((2, len(pts), ng), dtype=np.complex128)
+    xi[m] = np.exp(1j * arg)
+    Pw = thc.phased_potentials(L, grid, kmesh, xi, pts)
+    v = coulomb.kernel(L, grid, kmesh, m)
+    q = coulomb.qvec(L, kmesh, m)
+    r = coulomb.positions(L, grid)
+    omega = float(np.prod(L))
+    for P, (g, p) in enumerate(zip(modes, pts)):
+        phi = (omega / ng) * v[tuple(g)] * np.exp(1j * arg[P])
+        ref = np.exp(1j * ((r[p] - r) @ q)) * phi.conj()
+        assert np.abs(Pw[m, P] - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
+    assert np.abs(Pw[1 - m]).max() == 0.0
