@@ -382,12 +382,18 @@ def potential_legs(args, h, exx, torch, dev, cell, t, f64_ms, tag):
         "f64-robust": lambda: exx.exx_build_robust(
             h, t["cell"], t["psi64"], t["occ_pts"], t["ao_pts"], ao_grid, t["pts"], o["K"],
             o["Ex"], o["rank"]),
+        "mixed-gradient": lambda: exx.exx_exchange_gradient(
+            h, t["cell"], t["psi64"], t["occ_pts"], t["ao_pts"], ao_grid, t["pts"], o["K"], Kg,
+            o["Ex"], o["rank"], prec=exx.EXX_MIXED),
+        "mixed-robust": lambda: exx.exx_build_robust(
+            h, t["cell"], t["psi64"], t["occ_pts"], t["ao_pts"], ao_grid, t["pts"], o["K"],
+            o["Ex"], o["rank"], prec=exx.EXX_MIXED),
     }
     for label, fn in calls.items():
         s = time_steps(fn, max(1, min(args.steps, 3)), 1, torch)
         out[label] = {"ms_per_call": s * 1e3, "ratio_to_f64_build": s * 1e3 / f64_ms,
                       "ratio_to_f64_stagewise_build": s * 1e3 / stage_ms,
-                      "Ex": float(o["Ex"].cpu()[0]), "precision": "f64"}
+                      "Ex": float(o["Ex"].cpu()[0]), "precision": label.split("-")[0]}
         log(f"[{tag}] {label}: {s * 1e3:.2f} ms/call ({s * 1e3 / f64_ms:.2f}x the fused FP64 "
             f"build, {s * 1e3 / stage_ms:.2f}x the stage-wise one)")
     del ao_grid, Kg

@@ -123,7 +123,7 @@ exx_status exx_scratch_bytes(exx_handle_t h, size_t* bytes);
  *                        an exx_build_batched item (the largest of them)
  *   EXX_CALL_SELECT      exx_select_points
  *   EXX_CALL_SELECT_MLP  exx_select_points_mlp (n_probe up to 8192)
- *   EXX_CALL_GRADIENT    exx_exchange_gradient, exx_build_robust (prec ignored: FP64)
+ *   EXX_CALL_GRADIENT    exx_exchange_gradient, exx_build_robust (EXX_F64 or EXX_MIXED)
  * exx_set_workspace hands the handle a device buffer (256-byte aligned, caller
  * owned, e.g. a torch tensor) that every later call uses as its scratch; the
  * library then allocates no scratch of its own and releases what it held. A
@@ -283,17 +283,19 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec,
  *   Kgrad^n = -(N_k/4) (A^n + A^n^H)^T,
  * normalised like K (dE_x = -(2/N_k) sum_n Tr(Kgrad^n dD^n) for Hermitian dD^n,
  * E_x = -(1/N_k) sum_n Tr(Kgrad^n D^n)); holding V^m fixed instead gives K.
- * A reference path: the per-transfer fit, every array in FP64, the
+ * The per-transfer fit is formed for every transfer (its xi^m are needed), the
  * potentials by one more forward transform of conj(v^m F^m), the k-mesh sums
- * by plain kernels and the AO contractions on the FP64 matrix cores.
+ * in registers and the AO contractions on the FP64 matrix cores.
  *
- *   psi_grid, occ_pts, ao_pts, pts, K, Ex, rank as in exx_build (EXX_F64)
+ *   psi_grid, occ_pts, ao_pts, pts, K, Ex, rank as in exx_build
  *   ao_grid  [N_k][n_ao][N_g] c128: the AO functions phi^n_mu on the grid
  *   Kgrad    out [N_k][n_ao][n_ao] c128, Hermitian
- * prec must be EXX_F64 (else EXX_ERR_UNSUPPORTED). Scratch: three grid-sized
- * complex128 arrays [N_k][N_ISDF][N_g] plus the build's point-sized ones
- * (exx_workspace_size with EXX_CALL_GRADIENT). Ordered on `stream` like
- * exx_build; error behaviour as above.
+ * prec: EXX_F64, or EXX_MIXED (the fit as in the MIXED builds, xi, the
+ * transforms and the potentials stored as c64, everything after them in FP64);
+ * anything else returns EXX_ERR_UNSUPPORTED. Scratch: three grid-sized arrays
+ * [N_k][N_ISDF][N_g] (c128; in MIXED one of them c64) plus the build's
+ * point-sized ones (exx_workspace_size with EXX_CALL_GRADIENT). Ordered on
+ * `stream` like exx_build; error behaviour as above.
  */
 exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec prec,
                                  const void* psi_grid, const void* occ_pts, const void* ao_pts,
@@ -317,14 +319,15 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
  *   R^n(Q, r) = sum_m e^{i q_m.(r_Q - r)} conj Phi^m_Q(r) conj Gamma^{n+m}(Q, r).
  * E_x is the fitted one, which is also the robust energy (the least-squares
  * fit projects the occupied pairs, so the two one-sided terms add up to the
- * fitted energy). A reference path, FP64 only.
+ * fitted energy).
  *
- *   psi_grid, occ_pts, ao_pts, pts, Ex, rank as in exx_build (EXX_F64)
+ *   psi_grid, occ_pts, ao_pts, pts, Ex, rank as in exx_build
  *   ao_grid  [N_k][n_ao][N_g] c128: the AO functions phi^n_mu on the grid
  *   K        out [N_k][n_ao][n_ao] c128: K_rob, Hermitian
- * prec must be EXX_F64 (else EXX_ERR_UNSUPPORTED); scratch as for
- * exx_exchange_gradient (EXX_CALL_GRADIENT). Ordered on `stream` like
- * exx_build; error behaviour as above.
+ * prec: EXX_F64 or EXX_MIXED, as for exx_exchange_gradient (else
+ * EXX_ERR_UNSUPPORTED); scratch as for exx_exchange_gradient
+ * (EXX_CALL_GRADIENT). Ordered on `stream` like exx_build; error behaviour as
+ * above.
  */
 exx_status exx_build_robust(exx_handle_t h, const exx_cell* cell, exx_prec prec,
                             const void* psi_grid, const void* occ_pts, const void* ao_pts,

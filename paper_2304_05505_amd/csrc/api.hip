@@ -1441,26 +1441,46 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
 namespace exx {
 namespace {
 
-// The FP64 build (the fit leaves xi in grid, with grid2 as the solve's scratch;
-// S into S2, V^m into V2 with the transforms in grid2; K and E_x) followed by the
-// potentials of the fitted functions and Gamma^n, shared by the gradient and the
-// robust-fit K. On return: grid = Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r)
-// [N_k][N_ISDF][N_g], grid2 = Gamma^n [N_k][N_ISDF][N_g], G = G^n, V2 = Vb^m.
+// The build followed by the potentials of the fitted functions and Gamma^n,
+// shared by the gradient and the robust-fit K. On return *pw holds
+// Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r) [N_k][N_ISDF][N_g] (c64 when
+// *pw_f32), *gam holds Gamma^n [N_k][N_ISDF][N_g] (c128), G = G^n, V2 = Vb^m.
+//   EXX_F64: the fit leaves xi in grid (grid2 is the solve's scratch), the
+//     transforms go to grid2, the potentials to grid, Gamma^n to grid2.
+//   EXX_MIXED: the fit as in the MIXED builds (Gamma^n, Z^m and the solve in
+//     FP64, xi stored as c64 in grid2), the transforms (c64) to grid, the
+//     potentials (c64, FP64 arithmetic) to grid2, Gamma^n (FP64) to grid.
 exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb, char* ws,
-                                 const Layout& L, const void* psi_grid, const void* occ_pts,
-                                 const void* ao_pts, const int32_t* pts, void* K, double* Ex,
-                                 int32_t* rank, hipStream_t stream) {
+                                 const Layout& L, exx_prec prec, const void* psi_grid,
+                                 const void* occ_pts, const void* ao_pts, const int32_t* pts,
+                                 void* K, double* Ex, int32_t* rank, hipStream_t stream,
+                                 void** pw, void** gam, bool* pw_f32) {
   exx_status s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
   if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
   if (s != EXX_OK) return s;
-  // the fit (xi left in grid, S into S2), V^m (Bloch gauge, into V2; the
-  // transforms F^m into grid2), K and E_x with the fit's G^n
-  void* xi = ws + L.grid;
-  s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, ws + L.grid2, ws + L.S2,
-                               rank, stream, false, true);
-  if (s == EXX_OK)
-    s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, COUL_F64,
-                             ws + L.grid2);
+  const bool f32 = prec == EXX_MIXED;
+  // the fit (S into S2), V^m (Bloch gauge, into V2), K and E_x with the fit's G^n
+  void* xi;   // the fitted functions
+  void* F;    // their transforms, then conj(v F)
+  void* pot;  // the potentials
+  void* gm;   // Gamma^n
+  if (!f32) {
+    xi = ws + L.grid;
+    F = ws + L.grid2;
+    s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, ws + L.grid2,
+                                 ws + L.S2, rank, stream, false, true);
+    if (s == EXX_OK)
+      s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, COUL_F64, F);
+  } else {
+    xi = ws + L.grid2;
+    F = ws + L.grid;
+    s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, ws + L.S2, rank,
+                                stream);
+    if (s == EXX_OK)
+      s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, coul_form(h, prec), F);
+  }
+  pot = xi;  // xi is no longer needed once the transforms exist
+  gm = F;    // nor are the transforms once the potentials exist
   if (s == EXX_OK)
     s = buildK_impl(h, g, kscratch(ws, L), ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
   if (s != EXX_OK) return s;
@@ -1468,27 +1488,35 @@ exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb
   hipError_t e = launch_kernel_table(g, vt, stream);
   if (e != hipSuccess) return hip_check(h, e, "kernel table");
   // conj Phi^m scaled by N_g^2 / Omega: the forward transform of conj(v^m F^m)
-  // (xi is no longer needed: grid takes the potentials)
-  e = launch_kernel_scale_conj(g, ws + L.grid2, vt, stream);
-  if (e == hipSuccess)
-    e = launch_fft3d<double>(g, tb, ws + L.grid2, ws + L.grid, (long)g.nk * g.ni, h->ncu, stream);
+  e = launch_kernel_scale_conj(g, F, vt, stream, f32);
+  if (e == hipSuccess) {
+    if (f32)
+      e = launch_fft3d<float>(g, tb, F, pot, (long)g.nk * g.ni, h->ncu, stream);
+    else
+      e = launch_fft3d<double>(g, tb, F, pot, (long)g.nk * g.ni, h->ncu, stream);
+  }
   if (e != hipSuccess) return hip_check(h, e, "potentials");
   const double omega = (double)g.L[0] * g.L[1] * g.L[2];
-  e = launch_potential_phase(g, tb, ws + L.grid, pts, omega / ((double)g.ng * g.ng), stream);
+  e = launch_potential_phase(g, tb, pot, pts, omega / ((double)g.ng * g.ng), stream, f32);
   if (e != hipSuccess) return hip_check(h, e, "potential phase");
-  // Gamma^n again (the fit turned its copy into Z^m), into grid2
+  // Gamma^n again (the fit turned its copy into Z^m), in FP64
   e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ_pts, g.no, (long)g.ni * g.no, true,
-                                    psi_grid, g.ng, (long)g.no * g.ng, ws + L.grid2, g.ng,
+                                    psi_grid, g.ng, (long)g.no * g.ng, gm, g.ng,
                                     (long)g.ni * g.ng, stream, h->tile_gamma);
   if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
+  *pw = pot;
+  *gam = gm;
+  *pw_f32 = f32;
   return EXX_OK;
 }
 
 exx_status potential_args(exx_context* h, const exx_cell* cell, exx_prec prec, const char* name,
                           bool ok) {
   if (!ok) return fail(h, EXX_ERR_ARG, std::string(name) + ": null array argument");
-  if (cell && prec != EXX_F64)
-    return fail(h, EXX_ERR_UNSUPPORTED, std::string(name) + ": FP64 (EXX_F64) only");
+  if (cell && prec != EXX_F64 && prec != EXX_MIXED)
+    return fail(h, EXX_ERR_UNSUPPORTED,
+                std::string(name) + ": FP64 or MIXED only (EXX_F64, EXX_MIXED)");
+  if (cell && prec == EXX_MIXED && check_form(h, prec) != EXX_OK) return EXX_ERR_UNSUPPORTED;
   return EXX_OK;
 }
 
@@ -1512,13 +1540,15 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   Layout L;
   char* ws;
   s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
+  void *pw = nullptr, *gam = nullptr;
+  bool pw_f32 = false;
   if (s == EXX_OK)
-    s = build_with_potentials(h, g, tb, ws, L, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
-                              stream);
+    s = build_with_potentials(h, g, tb, ws, L, prec, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
+                              stream, &pw, &gam, &pw_f32);
   if (s != EXX_OK) return s;
   const long nn = (long)g.ni * g.ni, na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // CZ^n over the grid and CS^n over the points (U^m = conj Vb^m: Vb^m is Hermitian)
-  hipError_t e = launch_grad_xcorr(g, ws + L.grid, false, ws + L.grid2, ws + L.g3, nig, stream);
+  hipError_t e = launch_grad_xcorr(g, pw, false, gam, ws + L.g3, nig, stream, false, pw_f32);
   if (e == hipSuccess)
     e = launch_grad_xcorr(g, ws + L.V2, true, ws + L.G, ws + L.gCS, nn, stream);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the derivative");
@@ -1557,14 +1587,15 @@ exx_status exx_build_robust(exx_handle_t h, const exx_cell* cell, exx_prec prec,
   Layout L;
   char* ws;
   s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
+  void *pw = nullptr, *gam = nullptr;
+  bool pw_f32 = false;
   if (s == EXX_OK)
-    s = build_with_potentials(h, g, tb, ws, L, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
-                              stream);
+    s = build_with_potentials(h, g, tb, ws, L, prec, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
+                              stream, &pw, &gam, &pw_f32);
   if (s != EXX_OK) return s;
   const long na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // R^n = sum_m Pw^m o conj Gamma^{n+m}
-  hipError_t e =
-      launch_grad_xcorr(g, ws + L.grid, false, ws + L.grid2, ws + L.g3, nig, stream, true);
+  hipError_t e = launch_grad_xcorr(g, pw, false, gam, ws + L.g3, nig, stream, true, pw_f32);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the one-sided term");
   // T = R conj(phi)^T [N_ISDF][n_ao], then conj of the one-sided term
   // (1/N_k) T^T A = conj((1/N_k) T^H conj A)
@@ -1598,7 +1629,7 @@ exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec pre
     return EXX_OK;
   }
   if (call == EXX_CALL_GRADIENT) {  // also exx_build_robust
-    *bytes = layout(h, g, EXX_F64, NEED_GRAD).total;
+    *bytes = layout(h, g, prec == EXX_MIXED ? EXX_MIXED : EXX_F64, NEED_GRAD).total;
     return EXX_OK;
   }
   if (call == EXX_CALL_SELECT) {

@@ -441,15 +441,17 @@ enum { COUL_F64 = 0, COUL_BF16 = 1, COUL_BF16X3 = 2 };
 hipError_t launch_kernel_table(const Geom& g, double* vt, hipStream_t st);
 
 // density derivative of the fitted exchange energy (grad.hip), FP64:
-// F <- conj(v^m F) over [N_k][N_ISDF][N_g]
-hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hipStream_t st);
-// X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]
+// F <- conj(v^m F) over [N_k][N_ISDF][N_g]; f32: F stored as c64
+hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hipStream_t st,
+                                    bool f32 = false);
+// X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]; f32: X stored as c64
 hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, const int32_t* pts,
-                                  double scale, hipStream_t st);
+                                  double scale, hipStream_t st, bool f32 = false);
 // out[n] = sum_m [p^m conj Q^{n+m} + conj(p^m) conj Q^{n-m}] over `elems` elements per
-// k, p^m = P^m (or conj P^m); up_only: the first term alone
+// k, p^m = P^m (or conj P^m); up_only: the first term alone; P stored as c64 with p_f32
+// (Q and out c128, FP64 arithmetic)
 hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
-                             long elems, hipStream_t st, bool up_only = false);
+                             long elems, hipStream_t st, bool up_only = false, bool p_f32 = false);
 // K[n][mu][nu] <- conj(Ac[n][mu][nu]) + Ac[n][nu][mu] - K[n][mu][nu]
 hipError_t launch_robust_assemble(const Geom& g, const void* Ac, void* K, hipStream_t st);
 // Kg[n][mu][nu] = -(N_k/4) (Ac[n][mu][nu] + conj Ac[n][nu][mu])

@@ -27,8 +27,16 @@ __device__ __forceinline__ int mesh_add(const GradMesh& a, int n, int m, int sig
   return (r1 * a.N[1] + r2) * a.N[2] + r3;
 }
 
-// F[m][P][g] <- conj(v^m(g) F[m][P][g])
-__global__ __launch_bounds__(256) void kernel_scale_conj_kernel(double2* __restrict__ F,
+// a complex value of storage T as FP64
+template <typename T>
+__device__ __forceinline__ double2 ld2(const cplx<T>* __restrict__ p, long i) {
+  const cplx<T> v = p[i];
+  return make_double2((double)v.x, (double)v.y);
+}
+
+// F[m][P][g] <- conj(v^m(g) F[m][P][g]), F of storage T (FP64 arithmetic)
+template <typename T>
+__global__ __launch_bounds__(256) void kernel_scale_conj_kernel(cplx<T>* __restrict__ F,
                                                                 const double* __restrict__ vt,
                                                                 long per_m, long ng, long total) {
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
@@ -36,8 +44,8 @@ __global__ __launch_bounds__(256) void kernel_scale_conj_kernel(double2* __restr
   const long m = e / per_m;
   const long g = e % ng;
   const double v = vt[m * ng + g];
-  const double2 f = F[e];
-  F[e] = make_double2(v * f.x, -v * f.y);
+  const double2 f = ld2<T>(F, e);
+  F[e] = mk<T>((T)(v * f.x), (T)(-v * f.y));
 }
 
 struct PhaseArgs {
@@ -53,7 +61,8 @@ struct PhaseArgs {
 // row = (m, P), whose factor scale e^{i q.r_P} is uniform; a thread takes four grid
 // points r (stride 256), each with e^{-i q.r} from the three axis tables
 // (root_a[m_a c_a mod N_a n_a] = e^{-2 pi i m_a c_a / (N_a n_a)}).
-__global__ __launch_bounds__(256) void potential_phase_kernel(double2* __restrict__ X,
+template <typename T>
+__global__ __launch_bounds__(256) void potential_phase_kernel(cplx<T>* __restrict__ X,
                                                               const int32_t* __restrict__ pts,
                                                               PhaseArgs a) {
   const int row = blockIdx.x / a.nrb, rb = blockIdx.x % a.nrb;
@@ -70,7 +79,7 @@ __global__ __launch_bounds__(256) void potential_phase_kernel(double2* __restric
     py = py * f.x - px * f.y;
     px = tx;
   }
-  double2* Xr = X + (long)row * a.ng;
+  cplx<T>* Xr = X + (long)row * a.ng;
   const int ng = (int)a.ng;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -85,15 +94,15 @@ __global__ __launch_bounds__(256) void potential_phase_kernel(double2* __restric
     wy = wx * f2.y + wy * f2.x;
     wx = tx;
     const double qx = px * wx - py * wy, qy = px * wy + py * wx;
-    const double2 x = Xr[r];
-    Xr[r] = make_double2(qx * x.x - qy * x.y, qx * x.y + qy * x.x);
+    const double2 x = ld2<T>(Xr, r);
+    Xr[r] = mk<T>((T)(qx * x.x - qy * x.y), (T)(qx * x.y + qy * x.x));
   }
 }
 
 // out[n][e] = sum_m [p^m(e) conj Q^{n+m}(e) + conj(p^m(e)) conj Q^{n-m}(e)],
 // p^m = P^m, or conj(P^m) with CONJ_P; UP_ONLY keeps the first term
-template <bool CONJ_P, bool UP_ONLY>
-__global__ __launch_bounds__(256) void grad_xcorr_kernel(const double2* __restrict__ P,
+template <typename TP, bool CONJ_P, bool UP_ONLY>
+__global__ __launch_bounds__(256) void grad_xcorr_kernel(const cplx<TP>* __restrict__ P,
                                                          const double2* __restrict__ Q,
                                                          double2* __restrict__ out, long elems,
                                                          GradMesh a) {
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(256) void grad_xcorr_kernel(const double2* __restri
   for (int n = 0; n < a.nk; ++n) {
     double sx = 0.0, sy = 0.0;
     for (int m = 0; m < a.nk; ++m) {
-      double2 p = P[(long)m * elems + e];
+      double2 p = ld2<TP>(P, (long)m * elems + e);
       if (CONJ_P) p.y = -p.y;
       const double2 qu = Q[(long)mesh_add(a, n, m, 1) * elems + e];
       // p conj(qu) (+ conj(p) conj(qd))
@@ -122,8 +131,8 @@ __global__ __launch_bounds__(256) void grad_xcorr_kernel(const double2* __restri
 // (each lane reads back only its own column, so no barrier is needed): 2 N_k
 // loads per element instead of up to 3 N_k^2. One wave per workgroup, 64
 // elements; LDS 2 N_k x 64 x 16 bytes.
-template <bool CONJ_P, bool UP_ONLY>
-__global__ __launch_bounds__(64) void grad_xcorr_lds_kernel(const double2* __restrict__ P,
+template <typename TP, bool CONJ_P, bool UP_ONLY>
+__global__ __launch_bounds__(64) void grad_xcorr_lds_kernel(const cplx<TP>* __restrict__ P,
                                                             const double2* __restrict__ Q,
                                                             double2* __restrict__ out, long elems,
                                                             GradMesh a) {
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(64) void grad_xcorr_lds_kernel(const double2* __res
   const long e = (long)blockIdx.x * 64 + t;
   const bool in = e < elems;
   for (int m = 0; m < a.nk; ++m) {
-    double2 p = in ? P[(long)m * elems + e] : make_double2(0.0, 0.0);
+    double2 p = in ? ld2<TP>(P, (long)m * elems + e) : make_double2(0.0, 0.0);
     if (CONJ_P) p.y = -p.y;
     Ps[m * 64 + t] = p;
     Qs[m * 64 + t] = in ? Q[(long)m * elems + e] : make_double2(0.0, 0.0);
@@ -165,13 +174,14 @@ __device__ constexpr int mesh_add_c(int n, int m, int sign) {
 }
 
 // The same sums (p^m = P^m) on a mesh known at compile time: each element's N_k
-// values of P and Q are held in registers, every transfer index is a constant.
+// values of P (storage TP, read as FP64) and Q are held in registers, every
+// transfer index is a constant.
 // MODE: XR_BOTH writes both terms, XR_UP the first term alone, XR_DOWN adds the
 // second term to out (a larger mesh runs XR_UP then XR_DOWN, so that one pass
 // holds no more than 2 N_k complex values in registers).
 enum { XR_BOTH = 0, XR_UP = 1, XR_DOWN = 2 };
-template <int MODE, int N1, int N2, int N3>
-__global__ __launch_bounds__(256) void grad_xcorr_reg_kernel(const double2* __restrict__ P,
+template <typename TP, int MODE, int N1, int N2, int N3>
+__global__ __launch_bounds__(256) void grad_xcorr_reg_kernel(const cplx<TP>* __restrict__ P,
                                                             const double2* __restrict__ Q,
                                                             double2* __restrict__ out,
                                                             long elems) {
@@ -181,7 +191,7 @@ __global__ __launch_bounds__(256) void grad_xcorr_reg_kernel(const double2* __re
   double2 p[NK], q[NK];
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
-    p[m] = P[(long)m * elems + e];
+    p[m] = ld2<TP>(P, (long)m * elems + e);
     q[m] = Q[(long)m * elems + e];
   }
 #pragma unroll
@@ -238,15 +248,21 @@ __global__ __launch_bounds__(256) void robust_assemble_kernel(const double2* __r
 
 }  // namespace
 
-hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hipStream_t st) {
+hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hipStream_t st,
+                                    bool f32) {
   const long per_m = (long)g.ni * g.ng, total = per_m * g.nk;
-  hipLaunchKernelGGL(kernel_scale_conj_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                     st, (double2*)F, vt, per_m, (long)g.ng, total);
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (f32)
+    hipLaunchKernelGGL(kernel_scale_conj_kernel<float>, grid, dim3(256), 0, st, (float2*)F, vt,
+                       per_m, (long)g.ng, total);
+  else
+    hipLaunchKernelGGL(kernel_scale_conj_kernel<double>, grid, dim3(256), 0, st, (double2*)F, vt,
+                       per_m, (long)g.ng, total);
   return hipGetLastError();
 }
 
 hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, const int32_t* pts,
-                                  double scale, hipStream_t st) {
+                                  double scale, hipStream_t st, bool f32) {
   PhaseArgs a;
   for (int ax = 0; ax < 3; ++ax) {
     a.root[ax] = tb.root[ax];
@@ -258,28 +274,35 @@ hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, cons
   a.scale = scale;
   a.nrb = (int)((g.ng + 1023) / 1024);
   const long nblk = (long)g.nk * g.ni * a.nrb;
-  hipLaunchKernelGGL(potential_phase_kernel, dim3((unsigned)nblk), dim3(256), 0, st, (double2*)X,
-                     pts, a);
+  if (f32)
+    hipLaunchKernelGGL(potential_phase_kernel<float>, dim3((unsigned)nblk), dim3(256), 0, st,
+                       (float2*)X, pts, a);
+  else
+    hipLaunchKernelGGL(potential_phase_kernel<double>, dim3((unsigned)nblk), dim3(256), 0, st,
+                       (double2*)X, pts, a);
   return hipGetLastError();
 }
 
-hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
-                             long elems, hipStream_t st, bool up_only) {
+namespace {
+
+template <typename TP>
+hipError_t grad_xcorr_run(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
+                          long elems, hipStream_t st, bool up_only) {
   GradMesh a;
   for (int ax = 0; ax < 3; ++ax) a.N[ax] = g.N[ax];
   a.nk = g.nk;
   const dim3 grid((unsigned)((elems + 255) / 256));
-  const double2* p = (const double2*)P;
+  const cplx<TP>* p = (const cplx<TP>*)P;
   const double2* q = (const double2*)Q;
   double2* o = (double2*)out;
   if (!conj_p) {  // register-resident forms for the common small meshes
 #define EXX_XREG(a, b, c)                                                                      \
   if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                             \
     if (up_only)                                                                               \
-      hipLaunchKernelGGL((grad_xcorr_reg_kernel<XR_UP, a, b, c>), grid, dim3(256), 0, st, p,   \
+      hipLaunchKernelGGL((grad_xcorr_reg_kernel<TP, XR_UP, a, b, c>), grid, dim3(256), 0, st, p,   \
                          q, o, elems);                                                         \
     else                                                                                       \
-      hipLaunchKernelGGL((grad_xcorr_reg_kernel<XR_BOTH, a, b, c>), grid, dim3(256), 0, st, p, \
+      hipLaunchKernelGGL((grad_xcorr_reg_kernel<TP, XR_BOTH, a, b, c>), grid, dim3(256), 0, st, p, \
                          q, o, elems);                                                         \
     return hipGetLastError();                                                                  \
   }
@@ -299,10 +322,10 @@ hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const vo
     EXX_XREG(2, 3, 1)
 #undef EXX_XREG
     if (g.N[0] == 3 && g.N[1] == 3 && g.N[2] == 3) {  // two passes: 2 x 27 values each
-      hipLaunchKernelGGL((grad_xcorr_reg_kernel<XR_UP, 3, 3, 3>), grid, dim3(256), 0, st, p, q,
+      hipLaunchKernelGGL((grad_xcorr_reg_kernel<TP, XR_UP, 3, 3, 3>), grid, dim3(256), 0, st, p, q,
                          o, elems);
       if (!up_only)
-        hipLaunchKernelGGL((grad_xcorr_reg_kernel<XR_DOWN, 3, 3, 3>), grid, dim3(256), 0, st, p,
+        hipLaunchKernelGGL((grad_xcorr_reg_kernel<TP, XR_DOWN, 3, 3, 3>), grid, dim3(256), 0, st, p,
                            q, o, elems);
       return hipGetLastError();
     }
@@ -312,34 +335,45 @@ hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const vo
     const size_t lds = sizeof(double2) * 2 * 64 * (size_t)g.nk;
     if (up_only) {
       if (conj_p)
-        hipLaunchKernelGGL((grad_xcorr_lds_kernel<true, true>), gl, dim3(64), lds, st, p, q, o,
+        hipLaunchKernelGGL((grad_xcorr_lds_kernel<TP, true, true>), gl, dim3(64), lds, st, p, q, o,
                            elems, a);
       else
-        hipLaunchKernelGGL((grad_xcorr_lds_kernel<false, true>), gl, dim3(64), lds, st, p, q, o,
+        hipLaunchKernelGGL((grad_xcorr_lds_kernel<TP, false, true>), gl, dim3(64), lds, st, p, q, o,
                            elems, a);
     } else {
       if (conj_p)
-        hipLaunchKernelGGL((grad_xcorr_lds_kernel<true, false>), gl, dim3(64), lds, st, p, q, o,
-                           elems, a);
+        hipLaunchKernelGGL((grad_xcorr_lds_kernel<TP, true, false>), gl, dim3(64), lds, st, p, q,
+                           o, elems, a);
       else
-        hipLaunchKernelGGL((grad_xcorr_lds_kernel<false, false>), gl, dim3(64), lds, st, p, q, o,
-                           elems, a);
+        hipLaunchKernelGGL((grad_xcorr_lds_kernel<TP, false, false>), gl, dim3(64), lds, st, p, q,
+                           o, elems, a);
     }
     return hipGetLastError();
   }
   if (up_only) {
     if (conj_p)
-      hipLaunchKernelGGL((grad_xcorr_kernel<true, true>), grid, dim3(256), 0, st, p, q, o, elems, a);
+      hipLaunchKernelGGL((grad_xcorr_kernel<TP, true, true>), grid, dim3(256), 0, st, p, q, o,
+                         elems, a);
     else
-      hipLaunchKernelGGL((grad_xcorr_kernel<false, true>), grid, dim3(256), 0, st, p, q, o, elems, a);
+      hipLaunchKernelGGL((grad_xcorr_kernel<TP, false, true>), grid, dim3(256), 0, st, p, q, o,
+                         elems, a);
   } else {
     if (conj_p)
-      hipLaunchKernelGGL((grad_xcorr_kernel<true, false>), grid, dim3(256), 0, st, p, q, o, elems, a);
+      hipLaunchKernelGGL((grad_xcorr_kernel<TP, true, false>), grid, dim3(256), 0, st, p, q, o,
+                         elems, a);
     else
-      hipLaunchKernelGGL((grad_xcorr_kernel<false, false>), grid, dim3(256), 0, st, p, q, o, elems,
-                         a);
+      hipLaunchKernelGGL((grad_xcorr_kernel<TP, false, false>), grid, dim3(256), 0, st, p, q, o,
+                         elems, a);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
+                             long elems, hipStream_t st, bool up_only, bool p_f32) {
+  if (p_f32) return grad_xcorr_run<float>(g, P, conj_p, Q, out, elems, st, up_only);
+  return grad_xcorr_run<double>(g, P, conj_p, Q, out, elems, st, up_only);
 }
 
 hipError_t launch_robust_assemble(const Geom& g, const void* Ac, void* K, hipStream_t st) {

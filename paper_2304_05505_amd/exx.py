@@ -391,7 +391,8 @@ def exx_build(h: Handle, cell: ExxCell, prec: int, psi_grid, occ_pts, ao_pts, pt
 
 def exx_exchange_gradient(h: Handle, cell: ExxCell, psi_grid, occ_pts, ao_pts, ao_grid, pts, K,
                           Kgrad, Ex, rank, prec: int = EXX_F64):
-    """K, E_x and the density derivative Kgrad of the fitted exchange energy (FP64)."""
+    """K, E_x and the density derivative Kgrad of the fitted exchange energy
+    (prec EXX_F64 or EXX_MIXED)."""
     nk, ng, ni, no, na = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ, cell.n_ao
     d = h.device
     args = (
@@ -410,7 +411,7 @@ def exx_exchange_gradient(h: Handle, cell: ExxCell, psi_grid, occ_pts, ao_pts, a
 
 def exx_build_robust(h: Handle, cell: ExxCell, psi_grid, occ_pts, ao_pts, ao_grid, pts, K, Ex,
                      rank, prec: int = EXX_F64):
-    """The robust-fit exchange matrix K_rob and E_x (FP64)."""
+    """The robust-fit exchange matrix K_rob and E_x (prec EXX_F64 or EXX_MIXED)."""
     nk, ng, ni, no, na = _nk(cell), _ng(cell), cell.n_isdf, cell.n_occ, cell.n_ao
     d = h.device
     args = (

@@ -49,7 +49,8 @@ def test_bad_arguments_are_rejected(gpu):
 
 def test_gradient_and_robust_reject_bad_arguments(gpu):
     """exx_exchange_gradient and exx_build_robust: a null array, a bad shape and a
-    precision other than EXX_F64 are rejected before launch, with the message."""
+    precision other than EXX_F64 or EXX_MIXED are rejected before launch, with
+    the message."""
     import torch
 
     from paper_2304_05505_amd import exx
@@ -80,8 +81,8 @@ def test_gradient_and_robust_reject_bad_arguments(gpu):
         assert call(fn, _cell(exx), exx.EXX_F64, null_ao_grid=True) == -1
         assert "null array" in exx._lib.exx_last_error(h.raw).decode()
         assert call(fn, _cell(exx, grid=(12, 12, 7)), exx.EXX_F64) == -2
-        assert call(fn, _cell(exx), exx.EXX_MIXED) == -7  # EXX_ERR_UNSUPPORTED
-        assert "FP64" in exx._lib.exx_last_error(h.raw).decode()
+        assert call(fn, _cell(exx), exx.EXX_F32) == -7  # EXX_ERR_UNSUPPORTED
+        assert "FP64 or MIXED" in exx._lib.exx_last_error(h.raw).decode()
 
 
 def test_all_zero_orbitals_drop_every_point(gpu):

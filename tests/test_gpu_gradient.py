@@ -115,7 +115,7 @@ def test_exchange_gradient_matches_oracle(name, gpu):
         assert np.abs(Kgn[n] - Kgn[n].conj().T).max() <= 1e-12 * scale
 
 
-def test_exchange_gradient_rejects_reduced_precision(gpu):
+def test_exchange_gradient_rejects_fp32(gpu):
     import torch
 
     from paper_2304_05505_amd import exx
@@ -126,11 +126,11 @@ def test_exchange_gradient_rejects_reduced_precision(gpu):
     z = lambda *s: torch.zeros(s, dtype=torch.complex128, device=dev)  # noqa: E731
     c = exx.make_cell(cell.L, cell.grid, cell.kmesh, no, na, ni)
     h = exx.Handle(0)
-    with pytest.raises(RuntimeError, match="FP64"):
+    with pytest.raises(RuntimeError, match="FP64 or MIXED"):
         exx.exx_exchange_gradient(h, c, z(nk, no, ng), z(nk, ni, no), z(nk, ni, na), z(nk, na, ng),
                                   torch.arange(ni, dtype=torch.int32, device=dev), z(nk, na, na),
                                   z(nk, na, na), torch.zeros(1, dtype=torch.float64, device=dev),
-                                  torch.zeros(nk, dtype=torch.int32, device=dev), prec=exx.EXX_MIXED)
+                                  torch.zeros(nk, dtype=torch.int32, device=dev), prec=exx.EXX_F32)
 
 
 def test_gradient_and_robust_on_caller_workspace(gpu):
@@ -217,3 +217,54 @@ def test_gradient_with_one_refinement_step(gpu):
     dE = abs(float(Ex.cpu()[0]) - o["Ex"]) / abs(o["Ex"])
     print(f"refined: rel dE {dE:.2e} dKgrad {dG:.2e} tol {tol:.1e}")
     assert dE <= tol and dG <= tol
+
+
+MIXED_CELLS = ["k211", "k311", "gamma", "k222-ragged", "k112-odd", "k333", "k511"]
+
+
+@pytest.mark.parametrize("name", MIXED_CELLS)
+def test_mixed_gradient_and_robust_against_oracle(name, gpu):
+    """EXX_MIXED: the fit as in the MIXED builds (FP64 Gamma^n, Z^m and solve,
+    xi stored as c64), the transforms and the potentials stored as c64 (FP32
+    transform arithmetic), the correlations and AO contractions in FP64. The
+    FP32 steps are the storage of xi, of F and of Pw and the transform's
+    log2(N_g) stages, so K, Kgrad, K_rob and E_x are held to
+    16 eps32 log2(N_g) relative (about 2e-5 on these grids)."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    cell = GRAD_CELLS[name]()
+    psi = synth.orbitals_on_grid(cell, synth.orbital_coeffs(cell))
+    phi = np.stack([synth.ao_on_grid(cell, n) for n in range(cell.N_k)])
+    pts, _ = select.select_points(psi, cell.n_isdf)
+    og = thc.thc_oo_k_gradient(cell.L, cell.grid, cell.kmesh, psi, phi, pts)
+    orb = thc.thc_oo_k_robust(cell.L, cell.grid, cell.kmesh, psi, phi, pts)
+    cond = _cond(og)
+    dev = torch.device("cuda", 0)
+    nk, na, ni = cell.N_k, cell.n_ao, len(pts)
+    ao = np.stack([phi[n][:, pts] for n in range(nk)])
+    args = (torch.from_numpy(psi).to(dev),
+            torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev),
+            torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+            torch.from_numpy(np.ascontiguousarray(phi)).to(dev),
+            torch.from_numpy(np.asarray(pts, dtype=np.int32)).to(dev))
+    K = torch.empty((nk, na, na), dtype=torch.complex128, device=dev)
+    Kg = torch.empty_like(K)
+    Kr = torch.empty_like(K)
+    Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+    rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+    h = exx.Handle(0)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, cell.n_occ, na, ni)
+    exx.exx_exchange_gradient(h, c, *args, K, Kg, Ex, rank, prec=exx.EXX_MIXED)
+    exx.exx_build_robust(h, c, *args, Kr, Ex, rank, prec=exx.EXX_MIXED)
+    torch.cuda.synchronize()
+    rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())  # noqa: E731
+    dG, dR, dK = rel(Kg.cpu().numpy(), og["Kgrad"]), rel(Kr.cpu().numpy(), orb["K"]), \
+        rel(K.cpu().numpy(), og["K"])
+    dE = abs(float(Ex.cpu()[0]) - og["Ex"]) / abs(og["Ex"])
+    tol = 16 * np.finfo(np.float32).eps * np.log2(cell.N_g)
+    print(f"{name} mixed: cond {cond:.2e} tol {tol:.1e} rel dE {dE:.2e} dK {dK:.2e} "
+          f"dKgrad {dG:.2e} dKrob {dR:.2e}")
+    assert np.array_equal(rank.cpu().numpy(), og["rank"])
+    assert max(dE, dK, dG, dR) <= tol
