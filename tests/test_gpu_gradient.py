@@ -15,6 +15,8 @@ register, LDS-staged and direct forms), with the fit at and below the pair rank.
   build's, to rounding).
 * On the GPU result itself: Kgrad Hermitian, and Euler's identity of a
   degree-two function, -(1/N_k) sum_n Tr(Kgrad^n D^n) = E_x.
+* Also: one refinement step, a caller-owned workspace, FP32 rejected, and
+  EXX_MIXED (with the robust K) against the oracle on seven meshes.
 """
 
 import numpy as np
