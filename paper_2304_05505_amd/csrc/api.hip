@@ -392,12 +392,13 @@ exx_status finish(exx_context* h, hipStream_t st) {
 
 // TF: type of Gamma^n / Z^m (and of psi_grid); TX: storage type of xi
 // bf16 (with TF = float): Gamma^n on the BF16 matrix cores
-// in_grid (TF == TX): leave xi in the handle's grid buffer and use `xi` only as
-// the solve's scratch (no final copy)
+// in_grid (TF == TX): leave xi where Z^m was (the grid buffer, or zbuf) and use
+// `xi` only as the solve's scratch (no final copy)
 template <typename TF, typename TX>
 exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                     const void* psi, const void* occ, const int32_t* pts, void* xi, void* S,
-                    int32_t* rank, hipStream_t st, bool bf16 = false, bool in_grid = false) {
+                    int32_t* rank, hipStream_t st, bool bf16 = false, bool in_grid = false,
+                    void* zbuf = nullptr) {
   double2* G = (double2*)(ws + L.G);
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
@@ -405,6 +406,9 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   double2* WH = (double2*)(ws + L.Y);  // W^H (the K-build's Y region is free during a fit)
   int32_t* keep = (int32_t*)(ws + L.keep);
   void* grid = ws + L.grid;
+  // Z^m (and then the solve's output) go to zbuf when given, so that Gamma^n
+  // stays in grid; otherwise Z^m replaces Gamma^n in place
+  void* zg = zbuf ? zbuf : grid;
   const long nn = (long)g.ni * g.ni;
   hipError_t e;
   // The point-metric chain (a0, a2 at the points, a3) runs on the handle's
@@ -481,7 +485,7 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   // a2: Z^m in place
   if (!what) {
     PhaseTimer pt(h, PH_KCORR, st);
-    e = launch_kcorr<TF>(g, tb, grid, grid, g.ng, pts, false, st);
+    e = launch_kcorr<TF>(g, tb, grid, zg, g.ng, pts, false, st);
     if (e != hipSuccess) what = "Z kcorr";
   }
   hipError_t ew = hipStreamWaitEvent(st, h->join_ev, 0);
@@ -496,21 +500,21 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   // applied and then refined below.
   if (h->refine == 0) {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, W, g.ni, nn, false, grid, g.ng,
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, W, g.ni, nn, false, zg, g.ng,
                               (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve,
                               true);
     if (e == hipSuccess)
       e = zgemm_nn_grid<TX, TF>(g.ni, g.ng, g.ni, g.nk, WH, g.ni, nn, false, xi, g.ng,
-                                (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, st,
+                                (long)g.ni * g.ng, zg, g.ng, (long)g.ni * g.ng, st,
                                 h->tile_solve);
     if (e == hipSuccess && !in_grid)
-      e = launch_convert<TF, TX>(grid, xi, (long)g.nk * g.ni * g.ng, st);
+      e = launch_convert<TF, TX>(zg, xi, (long)g.nk * g.ni * g.ng, st);
     if (e != hipSuccess) return hip_check(h, e, "solve gemm");
     return EXX_OK;
   }
   {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, false, grid, g.ng,
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, false, zg, g.ng,
                             (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
@@ -519,14 +523,14 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
     // then xi <- xi + S^+ Z; both products in FP64 arithmetic
     PhaseTimer pt(h, PH_SOLVE, st);
     e = zgemm_nn_grid_acc<TX, TF>(g.ni, g.ng, g.ni, g.nk, S, g.ni, nn, xi, g.ng,
-                                  (long)g.ni * g.ng, grid, g.ng, (long)g.ni * g.ng, -1, st);
+                                  (long)g.ni * g.ng, zg, g.ng, (long)g.ni * g.ng, -1, st);
     if (e != hipSuccess) return hip_check(h, e, "refinement residual");
-    e = zgemm_nn_grid_acc<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, grid, g.ng,
+    e = zgemm_nn_grid_acc<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, zg, g.ng,
                                   (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, 1, st);
     if (e != hipSuccess) return hip_check(h, e, "refinement update");
   }
   if (in_grid) {
-    e = launch_convert<TX, TF>(xi, grid, (long)g.nk * g.ni * g.ng, st);
+    e = launch_convert<TX, TF>(xi, zg, (long)g.nk * g.ni * g.ng, st);
     if (e != hipSuccess) return hip_check(h, e, "xi into the grid buffer");
   }
   return EXX_OK;
@@ -1441,46 +1445,47 @@ exx_status exx_build(exx_handle_t h, const exx_cell* cell, exx_prec prec, const 
 namespace exx {
 namespace {
 
-// The build followed by the potentials of the fitted functions and Gamma^n,
-// shared by the gradient and the robust-fit K. On return *pw holds
+// The build followed by the potentials of the fitted functions, shared by the
+// gradient and the robust-fit K. The fit writes Z^m to a buffer of its own so
+// that Gamma^n survives it. On return *pw holds
 // Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r) [N_k][N_ISDF][N_g] (c64 when
-// *pw_f32), *gam holds Gamma^n [N_k][N_ISDF][N_g] (c128), G = G^n, V2 = Vb^m.
-//   EXX_F64: the fit leaves xi in grid (grid2 is the solve's scratch), the
-//     transforms go to grid2, the potentials to grid, Gamma^n to grid2.
-//   EXX_MIXED: the fit as in the MIXED builds (Gamma^n, Z^m and the solve in
-//     FP64, xi stored as c64 in grid2), the transforms (c64) to grid, the
-//     potentials (c64, FP64 arithmetic) to grid2, Gamma^n (FP64) to grid.
+// *pw_f32), *gam holds Gamma^n [N_k][N_ISDF][N_g] (c128), *cz is a free
+// grid-sized c128 buffer, G = G^n, V2 = Vb^m.
+//   EXX_F64: Gamma^n in grid; Z^m and then xi in g3 (grid2 the solve's
+//     scratch); the transforms to grid2, the potentials to g3; cz = grid2.
+//   EXX_MIXED: as the MIXED builds (Gamma^n, Z^m and the solve in FP64, xi
+//     stored as c64): Gamma^n in grid, Z^m in g3, xi (c64) in grid2; the
+//     transforms (c64) to g3, the potentials (c64, FP64 arithmetic) to grid2;
+//     cz = g3.
 exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb, char* ws,
                                  const Layout& L, exx_prec prec, const void* psi_grid,
                                  const void* occ_pts, const void* ao_pts, const int32_t* pts,
                                  void* K, double* Ex, int32_t* rank, hipStream_t stream,
-                                 void** pw, void** gam, bool* pw_f32) {
+                                 void** pw, void** gam, bool* pw_f32, void** cz) {
   exx_status s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
   if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
   if (s != EXX_OK) return s;
   const bool f32 = prec == EXX_MIXED;
   // the fit (S into S2), V^m (Bloch gauge, into V2), K and E_x with the fit's G^n
-  void* xi;   // the fitted functions
-  void* F;    // their transforms, then conj(v F)
-  void* pot;  // the potentials
-  void* gm;   // Gamma^n
+  void* gm = ws + L.grid;  // Gamma^n, kept by the fit
+  void* xi;                // the fitted functions, then the potentials
+  void* F;                 // their transforms, then conj(v F), then free
   if (!f32) {
-    xi = ws + L.grid;
+    xi = ws + L.g3;
     F = ws + L.grid2;
     s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, ws + L.grid2,
-                                 ws + L.S2, rank, stream, false, true);
+                                 ws + L.S2, rank, stream, false, true, ws + L.g3);
     if (s == EXX_OK)
       s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, COUL_F64, F);
   } else {
     xi = ws + L.grid2;
-    F = ws + L.grid;
+    F = ws + L.g3;
     s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, ws + L.S2, rank,
-                                stream);
+                                stream, false, false, ws + L.g3);
     if (s == EXX_OK)
       s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, coul_form(h, prec), F);
   }
-  pot = xi;  // xi is no longer needed once the transforms exist
-  gm = F;    // nor are the transforms once the potentials exist
+  void* pot = xi;  // xi is no longer needed once the transforms exist
   if (s == EXX_OK)
     s = buildK_impl(h, g, kscratch(ws, L), ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
   if (s != EXX_OK) return s;
@@ -1499,14 +1504,10 @@ exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb
   const double omega = (double)g.L[0] * g.L[1] * g.L[2];
   e = launch_potential_phase(g, tb, pot, pts, omega / ((double)g.ng * g.ng), stream, f32);
   if (e != hipSuccess) return hip_check(h, e, "potential phase");
-  // Gamma^n again (the fit turned its copy into Z^m), in FP64
-  e = zgemm_nn_grid<double, double>(g.ni, g.ng, g.no, g.nk, occ_pts, g.no, (long)g.ni * g.no, true,
-                                    psi_grid, g.ng, (long)g.no * g.ng, gm, g.ng,
-                                    (long)g.ni * g.ng, stream, h->tile_gamma);
-  if (e != hipSuccess) return hip_check(h, e, "Gamma gemm");
   *pw = pot;
   *gam = gm;
   *pw_f32 = f32;
+  *cz = F;
   return EXX_OK;
 }
 
@@ -1540,22 +1541,22 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   Layout L;
   char* ws;
   s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
-  void *pw = nullptr, *gam = nullptr;
+  void *pw = nullptr, *gam = nullptr, *cz = nullptr;
   bool pw_f32 = false;
   if (s == EXX_OK)
     s = build_with_potentials(h, g, tb, ws, L, prec, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
-                              stream, &pw, &gam, &pw_f32);
+                              stream, &pw, &gam, &pw_f32, &cz);
   if (s != EXX_OK) return s;
   const long nn = (long)g.ni * g.ni, na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // CZ^n over the grid and CS^n over the points (U^m = conj Vb^m: Vb^m is Hermitian)
-  hipError_t e = launch_grad_xcorr(g, pw, false, gam, ws + L.g3, nig, stream, false, pw_f32);
+  hipError_t e = launch_grad_xcorr(g, pw, false, gam, cz, nig, stream, false, pw_f32);
   if (e == hipSuccess)
     e = launch_grad_xcorr(g, ws + L.V2, true, ws + L.G, ws + L.gCS, nn, stream);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the derivative");
   // T = CS X^T - 2 CZ phi^H [N_ISDF][n_ao] (X_{mu P} = conj phi_mu(r_P): the conjugated
   // ao_pts, transposed), then conj A = (1/N_k^2) X conj T
   double2* T = (double2*)(ws + L.gT);
-  e = zgemm_splitk(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig, B_C, ao_grid, g.ng,
+  e = zgemm_splitk(g.ni, g.nao, g.ng, g.nk, A_N, cz, g.ng, nig, B_C, ao_grid, g.ng,
                    (long)g.nao * g.ng, T, g.nao, na_i, -2.0, false, ws + L.gP, stream);
   if (e == hipSuccess)
     e = gemm<double, double, double, double>(g.ni, g.nao, g.ni, g.nk, A_N, ws + L.gCS, g.ni, nn,
@@ -1587,20 +1588,20 @@ exx_status exx_build_robust(exx_handle_t h, const exx_cell* cell, exx_prec prec,
   Layout L;
   char* ws;
   s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
-  void *pw = nullptr, *gam = nullptr;
+  void *pw = nullptr, *gam = nullptr, *cz = nullptr;
   bool pw_f32 = false;
   if (s == EXX_OK)
     s = build_with_potentials(h, g, tb, ws, L, prec, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
-                              stream, &pw, &gam, &pw_f32);
+                              stream, &pw, &gam, &pw_f32, &cz);
   if (s != EXX_OK) return s;
   const long na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // R^n = sum_m Pw^m o conj Gamma^{n+m}
-  hipError_t e = launch_grad_xcorr(g, pw, false, gam, ws + L.g3, nig, stream, true, pw_f32);
+  hipError_t e = launch_grad_xcorr(g, pw, false, gam, cz, nig, stream, true, pw_f32);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the one-sided term");
   // T = R conj(phi)^T [N_ISDF][n_ao], then conj of the one-sided term
   // (1/N_k) T^T A = conj((1/N_k) T^H conj A)
   double2* T = (double2*)(ws + L.gT);
-  e = zgemm_splitk(g.ni, g.nao, g.ng, g.nk, A_N, ws + L.g3, g.ng, nig, B_C, ao_grid, g.ng,
+  e = zgemm_splitk(g.ni, g.nao, g.ng, g.nk, A_N, cz, g.ng, nig, B_C, ao_grid, g.ng,
                    (long)g.nao * g.ng, T, g.nao, na_i, 1.0, false, ws + L.gP, stream);
   if (e == hipSuccess)
     e = gemm<double, double, double, double>(g.nao, g.nao, g.ni, g.nk, A_C, T, g.nao, na_i, B_R,
