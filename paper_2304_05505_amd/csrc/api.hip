@@ -398,7 +398,7 @@ template <typename TF, typename TX>
 exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                     const void* psi, const void* occ, const int32_t* pts, void* xi, void* S,
                     int32_t* rank, hipStream_t st, bool bf16 = false, bool in_grid = false,
-                    void* zbuf = nullptr) {
+                    void* zbuf = nullptr, const Pairs* pr = nullptr) {
   double2* G = (double2*)(ws + L.G);
   double2* Lf = (double2*)(ws + L.Lf);
   double2* W = (double2*)(ws + L.W);
@@ -409,6 +409,17 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   // Z^m (and then the solve's output) go to zbuf when given, so that Gamma^n
   // stays in grid; otherwise Z^m replaces Gamma^n in place
   void* zg = zbuf ? zbuf : grid;
+  // pr: fit one transfer of each conjugate pair (its slices compacted in the
+  // order of pr->rep); the ranks are copied to the partners
+  Geom gr = g;
+  int32_t* rk = rank;
+  QLabel lab;
+  if (pr) {
+    gr.nk = pr->n;
+    rk = (int32_t*)(ws + L.rank2);
+    for (int k = 0; k < 64; ++k) lab.q[k] = k < pr->n ? pr->rep[k] : 0;
+  }
+  const int* slot = pr ? pr->slot : nullptr;
   const long nn = (long)g.ni * g.ni;
   hipError_t e;
   // The point-metric chain (a0, a2 at the points, a3) runs on the handle's
@@ -431,32 +442,36 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   // a2 at the points: S^m = e^{iq(r_P - r_Q)} sum_n G^n o conj G^{n+m}
   if (!what) {
     PhaseTimer pt(h, PH_METRIC, ax);
-    e = launch_kcorr<double>(g, tb, G, S, g.ni, pts, true, ax);
+    e = launch_kcorr<double>(g, tb, G, S, g.ni, pts, true, ax, slot);
     if (e != hipSuccess) what = "S kcorr";
   }
   // a3: Cholesky with drop, inverse factor, S^+ = W^H W
   if (!what) {
     PhaseTimer pt(h, PH_CHOL, ax);
-    e = launch_copy(Lf, (const double2*)S, (long)g.nk * nn, ax);
+    e = launch_copy(Lf, (const double2*)S, (long)gr.nk * nn, ax);
     if (e != hipSuccess) what = "copy S";
     if (!what) {
-      e = launch_chol_blocked(g, Lf, keep, rank, (double*)(ws + L.tol), 1e-12, ax, stat_ptr(h),
-                              strict_pd(h));
+      e = launch_chol_blocked(gr, Lf, keep, rk, (double*)(ws + L.tol), 1e-12, ax, stat_ptr(h),
+                              strict_pd(h), pr ? &lab : nullptr);
       if (e != hipSuccess) what = "cholesky";
     }
   }
   if (!what) {
     PhaseTimer pt(h, PH_PINV, ax);
-    e = launch_tri_inv_blocked(g, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
+    e = launch_tri_inv_blocked(gr, Lf, keep, W, (double2*)(ws + L.Tinv), ax);
     if (e != hipSuccess) what = "triangular inverse";
     if (!what) {
-      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, g.nk, A_C, W, g.ni, nn, B_N, W,
+      e = gemm<double, double, double, double>(g.ni, g.ni, g.ni, gr.nk, A_C, W, g.ni, nn, B_N, W,
                                                g.ni, nn, Sp, g.ni, nn, 1.0, false, ax);
       if (e != hipSuccess) what = "S+ gemm";
     }
     if (!what) {
-      e = launch_conj_transpose(W, WH, g.ni, g.ni, g.nk, 1.0, ax);
+      e = launch_conj_transpose(W, WH, g.ni, g.ni, gr.nk, 1.0, ax);
       if (e != hipSuccess) what = "W^H";
+    }
+    if (!what && pr) {
+      e = launch_rank_scatter(rk, rank, pr->rep, pr->bar, pr->n, ax);
+      if (e != hipSuccess) what = "rank scatter";
     }
   }
   // join back into st even after an error, so that st never runs ahead of the
@@ -485,7 +500,7 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   // a2: Z^m in place
   if (!what) {
     PhaseTimer pt(h, PH_KCORR, st);
-    e = launch_kcorr<TF>(g, tb, grid, zg, g.ng, pts, false, st);
+    e = launch_kcorr<TF>(g, tb, grid, zg, g.ng, pts, false, st, slot);
     if (e != hipSuccess) what = "Z kcorr";
   }
   hipError_t ew = hipStreamWaitEvent(st, h->join_ev, 0);
@@ -500,21 +515,21 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
   // applied and then refined below.
   if (h->refine == 0) {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, W, g.ni, nn, false, zg, g.ng,
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, gr.nk, W, g.ni, nn, false, zg, g.ng,
                               (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve,
                               true);
     if (e == hipSuccess)
-      e = zgemm_nn_grid<TX, TF>(g.ni, g.ng, g.ni, g.nk, WH, g.ni, nn, false, xi, g.ng,
+      e = zgemm_nn_grid<TX, TF>(g.ni, g.ng, g.ni, gr.nk, WH, g.ni, nn, false, xi, g.ng,
                                 (long)g.ni * g.ng, zg, g.ng, (long)g.ni * g.ng, st,
                                 h->tile_solve);
     if (e == hipSuccess && !in_grid)
-      e = launch_convert<TF, TX>(zg, xi, (long)g.nk * g.ni * g.ng, st);
+      e = launch_convert<TF, TX>(zg, xi, (long)gr.nk * g.ni * g.ng, st);
     if (e != hipSuccess) return hip_check(h, e, "solve gemm");
     return EXX_OK;
   }
   {
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, false, zg, g.ng,
+    e = zgemm_nn_grid<TF, TX>(g.ni, g.ng, g.ni, gr.nk, Sp, g.ni, nn, false, zg, g.ng,
                             (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, st, h->tile_solve);
   }
   if (e != hipSuccess) return hip_check(h, e, "solve gemm");
@@ -522,36 +537,40 @@ exx_status fit_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, c
     // one step of iterative refinement: Z <- Z - S^m xi (the residual, over Z),
     // then xi <- xi + S^+ Z; both products in FP64 arithmetic
     PhaseTimer pt(h, PH_SOLVE, st);
-    e = zgemm_nn_grid_acc<TX, TF>(g.ni, g.ng, g.ni, g.nk, S, g.ni, nn, xi, g.ng,
+    e = zgemm_nn_grid_acc<TX, TF>(g.ni, g.ng, g.ni, gr.nk, S, g.ni, nn, xi, g.ng,
                                   (long)g.ni * g.ng, zg, g.ng, (long)g.ni * g.ng, -1, st);
     if (e != hipSuccess) return hip_check(h, e, "refinement residual");
-    e = zgemm_nn_grid_acc<TF, TX>(g.ni, g.ng, g.ni, g.nk, Sp, g.ni, nn, zg, g.ng,
+    e = zgemm_nn_grid_acc<TF, TX>(g.ni, g.ng, g.ni, gr.nk, Sp, g.ni, nn, zg, g.ng,
                                   (long)g.ni * g.ng, xi, g.ng, (long)g.ni * g.ng, 1, st);
     if (e != hipSuccess) return hip_check(h, e, "refinement update");
   }
   if (in_grid) {
-    e = launch_convert<TX, TF>(xi, zg, (long)g.nk * g.ni * g.ng, st);
+    e = launch_convert<TX, TF>(xi, zg, (long)gr.nk * g.ni * g.ng, st);
     if (e != hipSuccess) return hip_check(h, e, "xi into the grid buffer");
   }
   return EXX_OK;
 }
 
 // T: storage of xi and F; cform: the contraction's form (COUL_*; FP32 storage only)
+// pr: xi holds one transfer of each conjugate pair (slices in the order of
+// pr->rep); V is written for every transfer (Vb^{-m} = conj Vb^m)
 template <typename T>
 exx_status coulomb_impl(exx_context* h, const Geom& g, const Tables& tb, char* ws, const Layout& L,
                         const void* xi, const int32_t* pts, void* V, hipStream_t st,
-                        int cform = COUL_F64, void* Fout = nullptr) {
+                        int cform = COUL_F64, void* Fout = nullptr, const Pairs* pr = nullptr) {
   void* F = Fout ? Fout : ws + L.grid;  // the transforms F^m
+  const int ns = pr ? pr->n : g.nk;
   hipError_t e;
   {
     PhaseTimer pt(h, PH_FFT, st);
-    e = launch_fft3d<T>(g, tb, xi, F, (long)g.nk * g.ni, h->ncu, st);
+    e = launch_fft3d<T>(g, tb, xi, F, (long)ns * g.ni, h->ncu, st);
   }
   if (e != hipSuccess) return hip_check(h, e, "fft");
   {
     PhaseTimer pt(h, PH_COULOMB, st);
-    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st, nullptr,
-                          nullptr, 0, false, cform);
+    e = launch_coulomb<T>(g, tb, F, pts, ws + L.cpart, L.nsplit, (double2*)V, false, st,
+                          pr ? pr->rep : nullptr, pr ? pr->bar : nullptr, pr ? pr->n : 0, false,
+                          cform);
   }
   if (e != hipSuccess) return hip_check(h, e, "coulomb");
   return EXX_OK;
@@ -1447,7 +1466,8 @@ namespace {
 
 // The build followed by the potentials of the fitted functions, shared by the
 // gradient and the robust-fit K. The fit writes Z^m to a buffer of its own so
-// that Gamma^n survives it. On return *pw holds
+// that Gamma^n survives it; on meshes with conjugate pairs it fits one transfer
+// of each pair (the slices of xi, F and Pw then follow pairs order). On return *pw holds
 // Pw^m(P, r) = e^{i q_m.(r_P - r)} conj Phi^m_P(r) [N_k][N_ISDF][N_g] (c64 when
 // *pw_f32), *gam holds Gamma^n [N_k][N_ISDF][N_g] (c128), *cz is a free
 // grid-sized c128 buffer, G = G^n, V2 = Vb^m.
@@ -1461,11 +1481,35 @@ exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb
                                  const Layout& L, exx_prec prec, const void* psi_grid,
                                  const void* occ_pts, const void* ao_pts, const int32_t* pts,
                                  void* K, double* Ex, int32_t* rank, hipStream_t stream,
-                                 void** pw, void** gam, bool* pw_f32, void** cz) {
+                                 void** pw, void** gam, bool* pw_f32, void** cz, int* src,
+                                 int* cj) {
   exx_status s = scan(h, occ_pts, 2L * g.nk * g.ni * g.no, SITE_OCC, stream);
   if (s == EXX_OK) s = scan(h, ao_pts, 2L * g.nk * g.ni * g.nao, SITE_AO, stream);
   if (s != EXX_OK) return s;
   const bool f32 = prec == EXX_MIXED;
+  // On meshes with conjugate pairs the fit, the transforms and the potentials
+  // cover one transfer of each pair (Pw^{-m} = conj Pw^m): slice s holds
+  // transfer prs.rep[s]; src/cj tell the correlation where each transfer is.
+  const Pairs prs = make_pairs(g);
+  const Pairs* pp = prs.n < g.nk ? &prs : nullptr;
+  const int ns = pp ? pp->n : g.nk;
+  Geom gs = g;
+  gs.nk = ns;
+  for (int m = 0; m < 64; ++m) {
+    src[m] = m;
+    cj[m] = 0;
+  }
+  if (pp) {
+    for (int m = 0; m < g.nk; ++m) {
+      if (prs.slot[m] >= 0) {
+        src[m] = prs.slot[m];
+      } else {
+        for (int k = 0; k < prs.n; ++k)
+          if (prs.bar[k] == m) src[m] = k;
+        cj[m] = 1;
+      }
+    }
+  }
   // the fit (S into S2), V^m (Bloch gauge, into V2), K and E_x with the fit's G^n
   void* gm = ws + L.grid;  // Gamma^n, kept by the fit
   void* xi;                // the fitted functions, then the potentials
@@ -1474,35 +1518,37 @@ exx_status build_with_potentials(exx_context* h, const Geom& g, const Tables& tb
     xi = ws + L.g3;
     F = ws + L.grid2;
     s = fit_impl<double, double>(h, g, tb, ws, L, psi_grid, occ_pts, pts, ws + L.grid2,
-                                 ws + L.S2, rank, stream, false, true, ws + L.g3);
+                                 ws + L.S2, rank, stream, false, true, ws + L.g3, pp);
     if (s == EXX_OK)
-      s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, COUL_F64, F);
+      s = coulomb_impl<double>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, COUL_F64, F, pp);
   } else {
     xi = ws + L.grid2;
     F = ws + L.g3;
     s = fit_impl<double, float>(h, g, tb, ws, L, psi_grid, occ_pts, pts, xi, ws + L.S2, rank,
-                                stream, false, false, ws + L.g3);
+                                stream, false, false, ws + L.g3, pp);
     if (s == EXX_OK)
-      s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, coul_form(h, prec), F);
+      s = coulomb_impl<float>(h, g, tb, ws, L, xi, pts, ws + L.V2, stream, coul_form(h, prec), F,
+                              pp);
   }
   void* pot = xi;  // xi is no longer needed once the transforms exist
   if (s == EXX_OK)
     s = buildK_impl(h, g, kscratch(ws, L), ao_pts, occ_pts, ws + L.V2, K, Ex, stream, true);
   if (s != EXX_OK) return s;
   double* vt = (double*)(ws + L.gvt);
-  hipError_t e = launch_kernel_table(g, vt, stream);
+  hipError_t e = launch_kernel_table(g, vt, stream, pp ? pp->rep : nullptr, ns);
   if (e != hipSuccess) return hip_check(h, e, "kernel table");
   // conj Phi^m scaled by N_g^2 / Omega: the forward transform of conj(v^m F^m)
-  e = launch_kernel_scale_conj(g, F, vt, stream, f32);
+  e = launch_kernel_scale_conj(gs, F, vt, stream, f32);
   if (e == hipSuccess) {
     if (f32)
-      e = launch_fft3d<float>(g, tb, F, pot, (long)g.nk * g.ni, h->ncu, stream);
+      e = launch_fft3d<float>(g, tb, F, pot, (long)ns * g.ni, h->ncu, stream);
     else
-      e = launch_fft3d<double>(g, tb, F, pot, (long)g.nk * g.ni, h->ncu, stream);
+      e = launch_fft3d<double>(g, tb, F, pot, (long)ns * g.ni, h->ncu, stream);
   }
   if (e != hipSuccess) return hip_check(h, e, "potentials");
   const double omega = (double)g.L[0] * g.L[1] * g.L[2];
-  e = launch_potential_phase(g, tb, pot, pts, omega / ((double)g.ng * g.ng), stream, f32);
+  e = launch_potential_phase(g, tb, pot, pts, omega / ((double)g.ng * g.ng), stream, f32,
+                             pp ? pp->rep : nullptr, ns);
   if (e != hipSuccess) return hip_check(h, e, "potential phase");
   *pw = pot;
   *gam = gm;
@@ -1543,13 +1589,14 @@ exx_status exx_exchange_gradient(exx_handle_t h, const exx_cell* cell, exx_prec 
   s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
   void *pw = nullptr, *gam = nullptr, *cz = nullptr;
   bool pw_f32 = false;
+  int src[64], cj[64];
   if (s == EXX_OK)
     s = build_with_potentials(h, g, tb, ws, L, prec, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
-                              stream, &pw, &gam, &pw_f32, &cz);
+                              stream, &pw, &gam, &pw_f32, &cz, src, cj);
   if (s != EXX_OK) return s;
   const long nn = (long)g.ni * g.ni, na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // CZ^n over the grid and CS^n over the points (U^m = conj Vb^m: Vb^m is Hermitian)
-  hipError_t e = launch_grad_xcorr(g, pw, false, gam, cz, nig, stream, false, pw_f32);
+  hipError_t e = launch_grad_xcorr(g, pw, false, gam, cz, nig, stream, false, pw_f32, src, cj);
   if (e == hipSuccess)
     e = launch_grad_xcorr(g, ws + L.V2, true, ws + L.G, ws + L.gCS, nn, stream);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the derivative");
@@ -1590,13 +1637,14 @@ exx_status exx_build_robust(exx_handle_t h, const exx_cell* cell, exx_prec prec,
   s = setup(h, cell, prec, NEED_GRAD, &g, &tb, &L, &ws, stream);
   void *pw = nullptr, *gam = nullptr, *cz = nullptr;
   bool pw_f32 = false;
+  int src[64], cj[64];
   if (s == EXX_OK)
     s = build_with_potentials(h, g, tb, ws, L, prec, psi_grid, occ_pts, ao_pts, pts, K, Ex, rank,
-                              stream, &pw, &gam, &pw_f32, &cz);
+                              stream, &pw, &gam, &pw_f32, &cz, src, cj);
   if (s != EXX_OK) return s;
   const long na_i = (long)g.ni * g.nao, nig = (long)g.ni * g.ng;
   // R^n = sum_m Pw^m o conj Gamma^{n+m}
-  hipError_t e = launch_grad_xcorr(g, pw, false, gam, cz, nig, stream, true, pw_f32);
+  hipError_t e = launch_grad_xcorr(g, pw, false, gam, cz, nig, stream, true, pw_f32, src, cj);
   if (e != hipSuccess) return hip_check(h, e, "k-correlation of the one-sided term");
   // T = R conj(phi)^T [N_ISDF][n_ao], then conj of the one-sided term
   // (1/N_k) T^T A = conj((1/N_k) T^H conj A)

@@ -438,20 +438,26 @@ hipError_t launch_coulomb(const Geom& g, const Tables& tb, const void* F, const 
                           bool raw = false, int form = 0, bool shared_f = false);
 enum { COUL_F64 = 0, COUL_BF16 = 1, COUL_BF16X3 = 2 };
 // v^m(g) = 4 pi/|K|^2 (K-box rule, K = 0 dropped) of every transfer: vt [N_k][N_g]
-hipError_t launch_kernel_table(const Geom& g, double* vt, hipStream_t st);
+// (rep: the transfers rep[s] of ns slices instead of all)
+hipError_t launch_kernel_table(const Geom& g, double* vt, hipStream_t st,
+                               const int* rep = nullptr, int ns = 0);
 
 // density derivative of the fitted exchange energy (grad.hip), FP64:
 // F <- conj(v^m F) over [N_k][N_ISDF][N_g]; f32: F stored as c64
 hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hipStream_t st,
                                     bool f32 = false);
-// X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]; f32: X stored as c64
+// X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]; f32: X stored as c64; rep: slice s
+// holds transfer rep[s] (ns slices) instead of slice m transfer m
 hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, const int32_t* pts,
-                                  double scale, hipStream_t st, bool f32 = false);
+                                  double scale, hipStream_t st, bool f32 = false,
+                                  const int* rep = nullptr, int ns = 0);
 // out[n] = sum_m [p^m conj Q^{n+m} + conj(p^m) conj Q^{n-m}] over `elems` elements per
 // k, p^m = P^m (or conj P^m); up_only: the first term alone; P stored as c64 with p_f32
-// (Q and out c128, FP64 arithmetic)
+// (Q and out c128, FP64 arithmetic). src/cj (N_k entries): P^m is slice src[m] of P,
+// conjugated where cj[m] (one transfer of each conjugate pair stored); default src[m] = m
 hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
-                             long elems, hipStream_t st, bool up_only = false, bool p_f32 = false);
+                             long elems, hipStream_t st, bool up_only = false, bool p_f32 = false,
+                             const int* src = nullptr, const int* cj = nullptr);
 // K[n][mu][nu] <- conj(Ac[n][mu][nu]) + Ac[n][nu][mu] - K[n][mu][nu]
 hipError_t launch_robust_assemble(const Geom& g, const void* Ac, void* K, hipStream_t st);
 // Kg[n][mu][nu] = -(N_k/4) (Ac[n][mu][nu] + conj Ac[n][nu][mu])

@@ -1013,10 +1013,12 @@ template hipError_t launch_coulomb<float>(const Geom&, const Tables&, const void
                                           void*, int, double2*, bool, hipStream_t, const int*,
                                           const int*, int, bool, int, bool);
 
-// v^m(g) of every transfer: vt [N_k][N_g]
-hipError_t launch_kernel_table(const Geom& g, double* vt, hipStream_t st) {
+// v^m(g) of every transfer (or of the transfers rep[s], s < ns): vt [slice][N_g]
+hipError_t launch_kernel_table(const Geom& g, double* vt, hipStream_t st, const int* rep,
+                               int ns) {
+  if (!rep) ns = g.nk;
   CoulArgs a;
-  for (int m = 0; m < 64; ++m) a.rep[m] = m < g.nk ? m : 0;
+  for (int m = 0; m < 64; ++m) a.rep[m] = m < ns ? (rep ? rep[m] : m) : 0;
   for (int i = 0; i < 3; ++i) {
     a.L[i] = g.L[i];
     a.n[i] = g.n[i];
@@ -1025,7 +1027,7 @@ hipError_t launch_kernel_table(const Geom& g, double* vt, hipStream_t st) {
   a.ng = g.ng;
   a.ni = g.ni;
   a.nk = g.nk;
-  hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), g.nk), dim3(256),
+  hipLaunchKernelGGL(coulomb_vtab_kernel, dim3((unsigned)((g.ng + 255) / 256), ns), dim3(256),
                      0, st, vt, a);
   return hipGetLastError();
 }

@@ -16,6 +16,8 @@ namespace {
 struct GradMesh {
   int N[3];
   int nk;
+  int src[64];  // P^m is slice src[m] of P ...
+  int cj[64];   // ... conjugated where cj[m]
 };
 
 __device__ __forceinline__ int mesh_add(const GradMesh& a, int n, int m, int sign) {
@@ -54,7 +56,8 @@ struct PhaseArgs {
   int ni;
   long ng;
   double scale;
-  int nrb;  // workgroups per row (1024 grid points each)
+  int nrb;      // workgroups per row (1024 grid points each)
+  int rep[64];  // slice s holds transfer rep[s]
 };
 
 // X[m][P][r] <- scale e^{i q_m.(r_P - r)} X[m][P][r]: workgroup (row, rb) with
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(256) void potential_phase_kernel(cplx<T>* __restric
                                                               const int32_t* __restrict__ pts,
                                                               PhaseArgs a) {
   const int row = blockIdx.x / a.nrb, rb = blockIdx.x % a.nrb;
-  const int P = row % a.ni, m = row / a.ni;
+  const int P = row % a.ni, m = a.rep[row / a.ni];
   const int n2 = a.n[1], n3 = a.n[2], n23 = n2 * n3;
   const int gp = pts[P];
   const int mm[3] = {m / (a.N[1] * a.N[2]), (m / a.N[2]) % a.N[1], m % a.N[2]};
@@ -111,8 +114,8 @@ __global__ __launch_bounds__(256) void grad_xcorr_kernel(const cplx<TP>* __restr
   for (int n = 0; n < a.nk; ++n) {
     double sx = 0.0, sy = 0.0;
     for (int m = 0; m < a.nk; ++m) {
-      double2 p = ld2<TP>(P, (long)m * elems + e);
-      if (CONJ_P) p.y = -p.y;
+      double2 p = ld2<TP>(P, (long)a.src[m] * elems + e);
+      if (CONJ_P != (a.cj[m] != 0)) p.y = -p.y;
       const double2 qu = Q[(long)mesh_add(a, n, m, 1) * elems + e];
       // p conj(qu) (+ conj(p) conj(qd))
       sx += p.x * qu.x + p.y * qu.y;
@@ -143,8 +146,8 @@ __global__ __launch_bounds__(64) void grad_xcorr_lds_kernel(const cplx<TP>* __re
   const long e = (long)blockIdx.x * 64 + t;
   const bool in = e < elems;
   for (int m = 0; m < a.nk; ++m) {
-    double2 p = in ? ld2<TP>(P, (long)m * elems + e) : make_double2(0.0, 0.0);
-    if (CONJ_P) p.y = -p.y;
+    double2 p = in ? ld2<TP>(P, (long)a.src[m] * elems + e) : make_double2(0.0, 0.0);
+    if (CONJ_P != (a.cj[m] != 0)) p.y = -p.y;
     Ps[m * 64 + t] = p;
     Qs[m * 64 + t] = in ? Q[(long)m * elems + e] : make_double2(0.0, 0.0);
   }
@@ -183,15 +186,16 @@ enum { XR_BOTH = 0, XR_UP = 1, XR_DOWN = 2 };
 template <typename TP, int MODE, int N1, int N2, int N3>
 __global__ __launch_bounds__(256) void grad_xcorr_reg_kernel(const cplx<TP>* __restrict__ P,
                                                             const double2* __restrict__ Q,
-                                                            double2* __restrict__ out,
-                                                            long elems) {
+                                                            double2* __restrict__ out, long elems,
+                                                            GradMesh a) {
   constexpr int NK = N1 * N2 * N3;
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
   if (e >= elems) return;
   double2 p[NK], q[NK];
 #pragma unroll
   for (int m = 0; m < NK; ++m) {
-    p[m] = ld2<TP>(P, (long)m * elems + e);
+    p[m] = ld2<TP>(P, (long)a.src[m] * elems + e);
+    if (a.cj[m]) p[m].y = -p[m].y;
     q[m] = Q[(long)m * elems + e];
   }
 #pragma unroll
@@ -262,7 +266,8 @@ hipError_t launch_kernel_scale_conj(const Geom& g, void* F, const double* vt, hi
 }
 
 hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, const int32_t* pts,
-                                  double scale, hipStream_t st, bool f32) {
+                                  double scale, hipStream_t st, bool f32, const int* rep, int ns) {
+  if (!rep) ns = g.nk;
   PhaseArgs a;
   for (int ax = 0; ax < 3; ++ax) {
     a.root[ax] = tb.root[ax];
@@ -273,7 +278,8 @@ hipError_t launch_potential_phase(const Geom& g, const Tables& tb, void* X, cons
   a.ng = g.ng;
   a.scale = scale;
   a.nrb = (int)((g.ng + 1023) / 1024);
-  const long nblk = (long)g.nk * g.ni * a.nrb;
+  for (int m = 0; m < 64; ++m) a.rep[m] = m < ns ? (rep ? rep[m] : m) : 0;
+  const long nblk = (long)ns * g.ni * a.nrb;
   if (f32)
     hipLaunchKernelGGL(potential_phase_kernel<float>, dim3((unsigned)nblk), dim3(256), 0, st,
                        (float2*)X, pts, a);
@@ -287,10 +293,15 @@ namespace {
 
 template <typename TP>
 hipError_t grad_xcorr_run(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
-                          long elems, hipStream_t st, bool up_only) {
-  GradMesh a;
-  for (int ax = 0; ax < 3; ++ax) a.N[ax] = g.N[ax];
-  a.nk = g.nk;
+                          long elems, hipStream_t st, bool up_only, const int* src,
+                          const int* cj) {
+  GradMesh gm;
+  for (int ax = 0; ax < 3; ++ax) gm.N[ax] = g.N[ax];
+  gm.nk = g.nk;
+  for (int m = 0; m < 64; ++m) {
+    gm.src[m] = src && m < g.nk ? src[m] : m;
+    gm.cj[m] = cj && m < g.nk ? cj[m] : 0;
+  }
   const dim3 grid((unsigned)((elems + 255) / 256));
   const cplx<TP>* p = (const cplx<TP>*)P;
   const double2* q = (const double2*)Q;
@@ -300,10 +311,10 @@ hipError_t grad_xcorr_run(const Geom& g, const void* P, bool conj_p, const void*
   if (g.N[0] == a && g.N[1] == b && g.N[2] == c) {                                             \
     if (up_only)                                                                               \
       hipLaunchKernelGGL((grad_xcorr_reg_kernel<TP, XR_UP, a, b, c>), grid, dim3(256), 0, st, p,   \
-                         q, o, elems);                                                         \
+                         q, o, elems, gm);                                                     \
     else                                                                                       \
       hipLaunchKernelGGL((grad_xcorr_reg_kernel<TP, XR_BOTH, a, b, c>), grid, dim3(256), 0, st, p, \
-                         q, o, elems);                                                         \
+                         q, o, elems, gm);                                                     \
     return hipGetLastError();                                                                  \
   }
     EXX_XREG(1, 1, 1)
@@ -323,10 +334,10 @@ hipError_t grad_xcorr_run(const Geom& g, const void* P, bool conj_p, const void*
 #undef EXX_XREG
     if (g.N[0] == 3 && g.N[1] == 3 && g.N[2] == 3) {  // two passes: 2 x 27 values each
       hipLaunchKernelGGL((grad_xcorr_reg_kernel<TP, XR_UP, 3, 3, 3>), grid, dim3(256), 0, st, p, q,
-                         o, elems);
+                         o, elems, gm);
       if (!up_only)
         hipLaunchKernelGGL((grad_xcorr_reg_kernel<TP, XR_DOWN, 3, 3, 3>), grid, dim3(256), 0, st, p,
-                           q, o, elems);
+                           q, o, elems, gm);
       return hipGetLastError();
     }
   }
@@ -336,34 +347,34 @@ hipError_t grad_xcorr_run(const Geom& g, const void* P, bool conj_p, const void*
     if (up_only) {
       if (conj_p)
         hipLaunchKernelGGL((grad_xcorr_lds_kernel<TP, true, true>), gl, dim3(64), lds, st, p, q, o,
-                           elems, a);
+                           elems, gm);
       else
         hipLaunchKernelGGL((grad_xcorr_lds_kernel<TP, false, true>), gl, dim3(64), lds, st, p, q, o,
-                           elems, a);
+                           elems, gm);
     } else {
       if (conj_p)
         hipLaunchKernelGGL((grad_xcorr_lds_kernel<TP, true, false>), gl, dim3(64), lds, st, p, q,
-                           o, elems, a);
+                           o, elems, gm);
       else
         hipLaunchKernelGGL((grad_xcorr_lds_kernel<TP, false, false>), gl, dim3(64), lds, st, p, q,
-                           o, elems, a);
+                           o, elems, gm);
     }
     return hipGetLastError();
   }
   if (up_only) {
     if (conj_p)
       hipLaunchKernelGGL((grad_xcorr_kernel<TP, true, true>), grid, dim3(256), 0, st, p, q, o,
-                         elems, a);
+                         elems, gm);
     else
       hipLaunchKernelGGL((grad_xcorr_kernel<TP, false, true>), grid, dim3(256), 0, st, p, q, o,
-                         elems, a);
+                         elems, gm);
   } else {
     if (conj_p)
       hipLaunchKernelGGL((grad_xcorr_kernel<TP, true, false>), grid, dim3(256), 0, st, p, q, o,
-                         elems, a);
+                         elems, gm);
     else
       hipLaunchKernelGGL((grad_xcorr_kernel<TP, false, false>), grid, dim3(256), 0, st, p, q, o,
-                         elems, a);
+                         elems, gm);
   }
   return hipGetLastError();
 }
@@ -371,9 +382,10 @@ hipError_t grad_xcorr_run(const Geom& g, const void* P, bool conj_p, const void*
 }  // namespace
 
 hipError_t launch_grad_xcorr(const Geom& g, const void* P, bool conj_p, const void* Q, void* out,
-                             long elems, hipStream_t st, bool up_only, bool p_f32) {
-  if (p_f32) return grad_xcorr_run<float>(g, P, conj_p, Q, out, elems, st, up_only);
-  return grad_xcorr_run<double>(g, P, conj_p, Q, out, elems, st, up_only);
+                             long elems, hipStream_t st, bool up_only, bool p_f32, const int* src,
+                             const int* cj) {
+  if (p_f32) return grad_xcorr_run<float>(g, P, conj_p, Q, out, elems, st, up_only, src, cj);
+  return grad_xcorr_run<double>(g, P, conj_p, Q, out, elems, st, up_only, src, cj);
 }
 
 hipError_t launch_robust_assemble(const Geom& g, const void* Ac, void* K, hipStream_t st) {
