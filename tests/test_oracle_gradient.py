@@ -96,3 +96,27 @@ def test_potentials_of_a_plane_wave(m):
         ref = np.exp(1j * ((r[p] - r) @ q)) * phi.conj()
         assert np.abs(Pw[m, P] - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
     assert np.abs(Pw[1 - m]).max() == 0.0
+
+
+@pytest.mark.parametrize("kmesh", [(3, 1, 1), (3, 2, 1)])
+def test_potentials_of_conjugate_transfers_are_conjugate(kmesh):
+    """Pw^{-m} = conj Pw^m for every transfer m and its partner -m (the identity
+    that lets a build fit one transfer of each conjugate pair), although the
+    fitted functions themselves differ by a phase (xi^{-m} != conj xi^m when
+    q_{-m} is q_m's partner shifted by a reciprocal lattice vector)."""
+    from oracle import coulomb
+
+    c = synth.make_random_cell((6.0, 5.0, 5.0), 2, (12, 10, 10), kmesh, 2, 16, (7, 7, 8))
+    psi = synth.orbitals_on_grid(c, synth.orbital_coeffs(c))
+    pts, _ = select.select_points(psi, c.n_isdf)
+    ao = np.stack([synth.ao_at_points(c, n, pts) for n in range(c.N_k)])
+    o = thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao, keep_intermediates=("xi",))
+    Pw = thc.phased_potentials(c.L, c.grid, c.kmesh, o["xi"], pts)
+    differs = False
+    for m in range(c.N_k):
+        mb = coulomb.transfer_index(c.kmesh, m, 0)  # the transfer -m
+        scale = np.abs(Pw[m]).max()
+        assert np.abs(Pw[mb] - Pw[m].conj()).max() <= 1e-10 * scale
+        if mb != m:
+            differs |= np.abs(o["xi"][mb] - o["xi"][m].conj()).max() > 1e-3 * np.abs(o["xi"][m]).max()
+    assert differs
