@@ -12,6 +12,9 @@ meshes of the gradient test (Gamma point, real path, odd grid, ragged N_ISDF,
   fitted one; the fused build reaches it by another rounding route).
 * At full occupied-pair rank (the 2x1x1 cell) the occupied rows C^H K_rob of
   the GPU result equal direct exchange's, where the plain fit's do not.
+
+(EXX_MIXED is compared with the oracle beside the gradient, in
+test_gpu_gradient.test_mixed_gradient_and_robust_against_oracle.)
 """
 
 import numpy as np
