@@ -21,7 +21,8 @@ every precision, with the split-BF16 contraction in MIXED and F32, each
 against its stored oracle K and E_x, and the shared-xi fit (timed; its E_x
 against the per-transfer oracle's shows the fit's own error).
 
-Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --profile
+Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --record PATH (append
+JSONL run records) --profile
 (the profiler's target, no JSON: the mixed batch twice and a 1 GiB copy; with
 --workload rings-k2 | rings-k3, two builds per precision of that cell and the
 copy; with --potentials and a ring workload, the exchange gradient and the
@@ -948,12 +949,58 @@ def profile_target(args):
     log(f"profile target: copied {src.numel() * 8} bytes")
 
 
+def run_records(out, workload, gold=None):
+    """JSONL run records of one bench invocation: one record per measured path
+    (config, dtype, E_x, |dE_x| and max|dK| against the stored oracle values,
+    per-cell errors with the oracle's ranks and cond(S^m), time per phase and
+    the phase rates)."""
+    import datetime
+
+    stamp = datetime.datetime.now(datetime.timezone.utc).isoformat(timespec="seconds")
+    recs = []
+    if workload == "batch24":
+        cells = gold["cells"] if gold else None
+        for prec, r in out.get("batched", {}).items():
+            per = out.get("batched_per_cell", {}).get(prec, {})
+            rec = {"time": stamp, "workload": "batch24", "path": f"batched-{prec}", "dtype": prec,
+                   "ms_per_step": r.get("seconds", 0.0) * 1e3,
+                   "builds_per_s": r.get("builds_per_s"),
+                   "max_dEx": r.get("max_dEx_vs_oracle"), "max_dK": r.get("max_dK_vs_oracle"),
+                   "cells_in_gate": r.get("cells_meeting_gate")}
+            if cells and per.get("dEx") is not None:
+                rec["cells"] = [{"name": c["name"], "Ex_oracle": c["Ex"], "dEx": dE, "max_dK": dK,
+                                 "rank": c["rank"], "cond_S_max": max(c["cond_S"])}
+                                for c, dE, dK in zip(cells, per["dEx"], per["dK"])]
+            if prec == out.get("config", {}).get("prec"):
+                rec["phases_ms"] = out.get("phases_ms_batch_mixed")
+                rec["phase_rates"] = out.get("phase_rates_batch_mixed")
+                rec["roofline"] = out.get("roofline")
+            recs.append(rec)
+    for leg_name, leg in out.get("paths", {}).items():
+        for label, r in leg.get("paths", {}).items():
+            recs.append({"time": stamp, "workload": leg_name, "path": label,
+                         "dtype": r.get("precision"),
+                         "ms": r.get("ms_per_build", r.get("ms_per_call")), "Ex": r.get("Ex"),
+                         "dEx": r.get("dEx_vs_oracle"), "max_dK": r.get("maxdK_vs_oracle"),
+                         "phases_ms": r.get("phases_ms")})
+    return recs
+
+
+def write_records(path, recs):
+    with open(path, "a") as f:
+        for r in recs:
+            f.write(json.dumps(r) + "\n")
+    log(f"appended {len(recs)} run records to {path}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--record", metavar="PATH",
+                    help="append JSONL run records (one per measured path) to PATH")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--potentials", action="store_true",
                     help="with --profile and a ring workload: profile the exchange gradient "
@@ -990,6 +1037,9 @@ def main():
     if args.workload in ("rings-k2", "rings-k3"):
         leg = ring_leg(2 if args.workload == "rings-k2" else 3, args, h, exx, torch, dev)
         print(json.dumps(leg), flush=True)
+        if args.record:
+            write_records(args.record, run_records({"paths": {args.workload: leg}},
+                                                   args.workload))
         return
 
     cells, res, seq_r, phase_ms, wex, wsv, units = batch_leg(args, h, exx, torch, dev)
@@ -1044,6 +1094,8 @@ def main():
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(cells)
     print(json.dumps(out), flush=True)
+    if args.record:
+        write_records(args.record, run_records(out, "batch24", load_json("config4.json")))
 
 
 if __name__ == "__main__":
