@@ -90,7 +90,12 @@ typedef enum {
  *              psi_grid and xi are c64. Its error is that of 8-bit
  *              significands amplified by the metric's conditioning (reported,
  *              not within the 1e-5 / 1e-6 accuracy target). */
-typedef enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 } exx_prec;
+/* The precision is a plain 32-bit integer holding one of these constants, so
+ * that any value a caller passes can be checked (an enum type would make an
+ * out-of-range value undefined in the C++ implementation); anything else is
+ * rejected with EXX_ERR_ARG. */
+typedef int32_t exx_prec;
+enum { EXX_F64 = 0, EXX_F32 = 1, EXX_BF16 = 2, EXX_MIXED = 3 };
 
 typedef struct {
   double L[3];       /* orthorhombic cell edges, bohr */

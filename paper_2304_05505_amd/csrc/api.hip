@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, scratch layout and the launch sequence
 // of one THC-oo-K exchange build.
 #include <algorithm>
+#include <cerrno>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -1672,7 +1673,7 @@ exx_status exx_workspace_size(exx_handle_t h, const exx_cell* cell, exx_prec pre
   if (s != EXX_OK) return s;
   const Geom g = make_geom(*cell);
   if (call == EXX_CALL_BUILD) {
-      size_t b = layout(h, g, prec, NEED_BUILD).total;
+    size_t b = layout(h, g, prec, NEED_BUILD).total;
     b = std::max(b, layout(h, g, prec, NEED_FIT | NEED_COULOMB | NEED_K).total);
     *bytes = b;
     return EXX_OK;
@@ -2031,7 +2032,7 @@ extern "C" exx_status exx_build_batched(exx_handle_t h, int32_t n, const exx_bat
     const exx_batch_item& it = items[i];
     exx_status s = check_cell(h, &it.cell, prec);
     if (s != EXX_OK) return fail(h, s, "item " + std::to_string(i) + ": " + h->err);
-      if (!it.psi_grid || !it.occ_pts || !it.ao_pts || !it.pts || !it.K || !it.Ex || !it.rank)
+    if (!it.psi_grid || !it.occ_pts || !it.ao_pts || !it.pts || !it.K || !it.Ex || !it.rank)
       return fail(h, EXX_ERR_ARG, "item " + std::to_string(i) + ": null array");
     geo[i] = make_geom(it.cell);
     lay[i] = layout(h, geo[i], prec, NEED_BUILD);
@@ -2192,19 +2193,43 @@ extern "C" exx_status exx_load_tuning(exx_handle_t h, const char* path) {
   if (!path) return fail(h, EXX_ERR_ARG, "exx_load_tuning: path is NULL");
   FILE* f = fopen(path, "r");
   if (!f) return fail(h, EXX_ERR_ARG, std::string("exx_load_tuning: cannot read ") + path);
-  char line[256];
   std::vector<exx_context::Tune> got;
   bool bad = false;
-  while (fgets(line, sizeof line, f)) {
+  std::string line;
+  char buf[256];
+  for (;;) {
+    // one whole line, however long
+    line.clear();
+    while (fgets(buf, sizeof buf, f)) {
+      line += buf;
+      if (!line.empty() && line.back() == '\n') break;
+    }
+    if (line.empty()) break;  // end of file
     if (line[0] == '#' || line[0] == '\n') continue;
-    exx_context::Tune t;
-    if (sscanf(line, "%ld %ld %ld %ld %ld %d %d", &t.key[0], &t.key[1], &t.key[2], &t.key[3],
-               &t.key[4], &t.gamma, &t.solve) != 7 ||
-        (t.gamma != 22 && t.gamma != 24 && t.gamma != 42) ||
-        (t.solve != 22 && t.solve != 24 && t.solve != 42)) {
+    // seven decimal integers: five key fields, then the two wave tiles
+    long v[7];
+    const char* p = line.c_str();
+    for (int i = 0; i < 7 && !bad; ++i) {
+      char* end = nullptr;
+      errno = 0;
+      v[i] = strtol(p, &end, 10);
+      if (end == p || errno == ERANGE) bad = true;
+      p = end;
+    }
+    while (!bad && (*p == ' ' || *p == '\t' || *p == '\r' || *p == '\n')) ++p;
+    if (bad || *p != '\0') {
       bad = true;
       break;
     }
+    exx_context::Tune t;
+    std::copy(v, v + 5, t.key);
+    auto tile_ok = [](long x) { return x == 22 || x == 24 || x == 42; };
+    if (!tile_ok(v[5]) || !tile_ok(v[6])) {
+      bad = true;
+      break;
+    }
+    t.gamma = (int)v[5];
+    t.solve = (int)v[6];
     got.push_back(t);
   }
   fclose(f);
