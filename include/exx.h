@@ -109,6 +109,10 @@ typedef struct {
   int32_t n_ao;      /* basis functions per k, 1..4096 */
   int32_t n_isdf;    /* interpolation points, 1..2048 */
 } exx_cell;
+/* Besides the ranges above: n_isdf N_g < 2^28 and n_occ N_g < 2^28 (N_g =
+ * n1 n2 n3), because one transfer's grid-sized arrays are addressed with 32-bit
+ * byte offsets; larger cells are rejected with EXX_ERR_UNSUPPORTED before any
+ * work is queued. */
 
 typedef struct exx_context* exx_handle_t;
 

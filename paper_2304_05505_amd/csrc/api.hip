@@ -176,6 +176,12 @@ exx_status check_cell(exx_context* h, const exx_cell* c, exx_prec prec) {
   if (!kcorr_supported(g)) return fail(h, EXX_ERR_SHAPE, "the k-mesh may hold at most 64 points");
   if (!fft_supported(g, prec == EXX_F64))
     return fail(h, EXX_ERR_UNSUPPORTED, "grid shape not supported by the FFT (n2*n3 <= 6144)");
+  // the grid GEMMs and k-correlations address one transfer's grid-sized arrays
+  // (n_isdf or n_occ complex128 functions over the grid) with 32-bit byte offsets
+  if ((long)std::max(g.ni, g.no) * g.ng * (long)sizeof(double2) >= 0xffffffffL)
+    return fail(h, EXX_ERR_UNSUPPORTED,
+                "n_isdf * N_g and n_occ * N_g must be below 2^28 (one transfer's grid arrays "
+                "are addressed with 32-bit offsets)");
   return EXX_OK;
 }
 

@@ -140,6 +140,15 @@ void shape_errors(exx_context* h) {
   with([](exx_cell& c) { c.n_isdf = 2049; }, EXX_ERR_SHAPE);
   with([](exx_cell& c) { c.grid[0] = c.grid[1] = c.grid[2] = 2; }, EXX_ERR_SHAPE);  // n_isdf > N_g
   with([](exx_cell& c) { c.grid[1] = c.grid[2] = 120; }, EXX_ERR_UNSUPPORTED);    // n2 n3 > 6144
+  // one transfer's grid arrays beyond 32-bit byte offsets: n_isdf N_g or n_occ N_g >= 2^28
+  with([](exx_cell& c) {
+    c.grid[0] = 128, c.grid[1] = 48, c.grid[2] = 48;
+    c.n_isdf = 2048;
+  }, EXX_ERR_UNSUPPORTED);
+  with([](exx_cell& c) {
+    c.grid[0] = 128, c.grid[1] = 48, c.grid[2] = 128;
+    c.n_occ = 512;
+  }, EXX_ERR_UNSUPPORTED);
   with([](exx_cell&) {}, EXX_ERR_ARG, (exx_prec)7);
   with([](exx_cell&) {}, EXX_ERR_ARG, (exx_prec)-1);
   int dummy = 0;
@@ -170,6 +179,12 @@ void shape_errors(exx_context* h) {
             (int)w);
     }
   }
+  // the largest accepted cell: every size at its maximum, n_isdf N_g just below 2^28
+  const exx_cell big = make_cell(128, 32, 30, 1, 1, 1, 512, 4096, 2048);
+  for (exx_prec pr : {EXX_F64, EXX_F32, EXX_BF16, EXX_MIXED})
+    for (int call = 0; call < 4; ++call)
+      check(exx_workspace_size(h, &big, pr, call, &sz) == EXX_OK && sz > 0,
+            "largest cell, call %d: %s", call, h->err.c_str());
   // a NULL cell and NULL arrays
   check(exx_workspace_size(h, nullptr, EXX_F64, EXX_CALL_BUILD, &sz) == EXX_ERR_ARG, "NULL cell");
   check(exx_workspace_size(h, &ok, EXX_F64, EXX_CALL_BUILD, nullptr) == EXX_ERR_ARG, "NULL bytes");

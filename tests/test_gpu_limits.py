@@ -1,0 +1,190 @@
+"""The build at the ends of the ABI's size ranges.
+
+* Smallest sizes (one occupied orbital, one interpolation point, one AO
+  function, on Gamma and on 2x1x1 / 2x2x1 meshes) against the FP64 oracle: the
+  fit metric is 1 x 1 there (cond 1), so FP64 gets 1e-12 relative on K and
+  E_x, MIXED 3e-7 and F32 1e-6, and the ranks must be 1.
+* The largest accepted cell: n_occ 512, n_isdf 2048 and n_ao 4096 (each at its
+  maximum), a 128-point grid axis, n_isdf N_g = 2048 x 122 880 just below the
+  2^28 bound of the 32-bit per-transfer offsets. The oracle cannot finish this
+  size in a test, so the checks are properties that hold at any size:
+  - with the occupied orbitals as the AO basis (ao_pts = occ_pts), the energy
+    the build forms from the occupied pairs equals -(1/N_k) Tr K from its own K
+    (the contraction and the energy reduction are separate kernels);
+  - K is Hermitian;
+  - rows of K belong to single AO functions: appending 3584 more functions
+    (n_ao 4096) leaves the first 512 x 512 block and E_x unchanged;
+  - the stage-wise calls (fit by S^+ Z, Coulomb, contraction) and the fused
+    build (inverse Cholesky factor on the grid) agree to the rounding that
+    cond(S) allows (tolerance as in the parity tests), and MIXED to 3e-7;
+  and one step past the bound (n_isdf N_g >= 2^28) is rejected before any
+  work with EXX_ERR_UNSUPPORTED.
+Inputs of the large cell are drawn on the device from a seeded generator
+(complex Gaussian orbitals, distinct random points).
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import select, thc
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = np.finfo(np.float64).eps
+
+
+def _dev_tensors(psi, pts, ao, prec):
+    import torch
+
+    dev = torch.device("cuda", 0)
+    wide = prec in ("f64", "mixed")
+    return dict(
+        psi_grid=torch.from_numpy(psi.astype(np.complex128 if wide else np.complex64)).to(dev),
+        occ_pts=torch.from_numpy(np.ascontiguousarray(np.transpose(psi[:, :, pts], (0, 2, 1)))).to(dev),
+        ao_pts=torch.from_numpy(np.ascontiguousarray(np.transpose(ao, (0, 2, 1)))).to(dev),
+        pts=torch.from_numpy(np.asarray(pts, dtype=np.int32)).to(dev),
+    )
+
+
+@pytest.mark.parametrize("kmesh", [(1, 1, 1), (2, 1, 1), (2, 2, 1)])
+def test_smallest_sizes_match_oracle(kmesh, gpu):
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    cell = synth.make_random_cell((5.0, 5.0, 5.0), 1, (8, 8, 8), kmesh, 1, 1, (12, len(kmesh), sum(kmesh)))
+    psi = synth.orbitals_on_grid(cell, synth.orbital_coeffs(cell))
+    pts, _ = select.select_points(psi, 1)
+    ao = np.stack([synth.ao_at_points(cell, n, pts)[:1] for n in range(cell.N_k)])  # one AO function
+    o = thc.thc_oo_k(cell.L, cell.grid, cell.kmesh, psi, pts, ao)
+    assert np.all(o["rank"] == 1)
+    dev = torch.device("cuda", 0)
+    h = exx.Handle(0)
+    c = exx.make_cell(cell.L, cell.grid, cell.kmesh, 1, 1, 1)
+    nk, ng = cell.N_k, cell.N_g
+    for prec, stages in (("f64", False), ("f64", True), ("mixed", False), ("f32", False)):
+        t = _dev_tensors(psi, pts, ao, prec)
+        K = torch.empty((nk, 1, 1), dtype=torch.complex128, device=dev)
+        Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+        rank = torch.empty((nk,), dtype=torch.int32, device=dev)
+        p = exx.PREC[prec]
+        if stages:
+            xi = torch.empty((nk, 1, ng), dtype=torch.complex128, device=dev)
+            S = torch.empty((nk, 1, 1), dtype=torch.complex128, device=dev)
+            V = torch.empty((nk, 1, 1), dtype=torch.complex128, device=dev)
+            exx.exx_isdf_fit(h, c, p, t["psi_grid"], t["occ_pts"], t["pts"], xi, S, rank)
+            exx.exx_coulomb_V(h, c, p, xi, t["pts"], V)
+            exx.exx_build_K(h, c, p, t["ao_pts"], t["occ_pts"], V, K, Ex)
+        else:
+            exx.exx_build(h, c, p, t["psi_grid"], t["occ_pts"], t["ao_pts"], t["pts"], K, Ex, rank)
+        torch.cuda.synchronize()
+        Kg, Eg = K.cpu().numpy(), float(Ex.cpu()[0])
+        dK = np.abs(Kg - o["K"]).max() / np.abs(o["K"]).max()
+        dE = abs(Eg - o["Ex"]) / abs(o["Ex"])
+        print(f"{kmesh} {prec}{' stages' if stages else ''}: rel dK {dK:.2e} rel dE {dE:.2e}")
+        assert np.all(rank.cpu().numpy() == 1)
+        tol = {"f64": 1e-12, "mixed": 3e-7, "f32": 1e-6}[prec]
+        assert dK <= tol and dE <= tol
+
+
+def _largest(torch, dev):
+    """The largest accepted cell's inputs, drawn on the device (seeded)."""
+    grid, no, ni = (128, 32, 30), 512, 2048
+    ng = grid[0] * grid[1] * grid[2]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2304_05505)
+    psi = torch.randn((1, no, ng), dtype=torch.complex128, device=dev, generator=gen)
+    cpu = torch.Generator()
+    cpu.manual_seed(2304_05505)
+    pts = torch.randperm(ng, generator=cpu)[:ni].to(torch.int32).to(dev)
+    occ = psi[:, :, pts.long()].transpose(1, 2).contiguous()
+    extra = torch.randn((1, ni, 4096 - no), dtype=torch.complex128, device=dev, generator=gen)
+    return grid, no, ni, ng, psi, pts, occ, extra
+
+
+def test_largest_accepted_cell(gpu):
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    L = (25.6, 6.4, 6.0)
+    grid, no, ni, ng, psi, pts, occ, extra = _largest(torch, dev)
+    assert ni * ng < 2**28 <= ni * 2 * ng
+    h = exx.Handle(0)
+
+    def fused(prec, ao, psi_grid):
+        na = ao.shape[2]
+        c = exx.make_cell(L, grid, (1, 1, 1), no, na, ni)
+        K = torch.empty((1, na, na), dtype=torch.complex128, device=dev)
+        Ex = torch.empty((1,), dtype=torch.float64, device=dev)
+        rank = torch.empty((1,), dtype=torch.int32, device=dev)
+        exx.exx_build(h, c, exx.PREC[prec], psi_grid, occ, ao, pts, K, Ex, rank)
+        torch.cuda.synchronize()
+        return K, float(Ex.cpu()[0]), int(rank.cpu()[0])
+
+    print(f"largest cell: grid {grid} N_g {ng}, n_occ {no}, n_isdf {ni}, n_ao 512 / 4096", flush=True)
+    KA, EA, rA = fused("f64", occ, psi)
+    assert 1 <= rA <= ni
+    trK = -float(torch.diagonal(KA[0]).real.sum().cpu())
+    scale = float(KA.abs().max().cpu())
+    herm = float((KA[0] - KA[0].conj().T).abs().max().cpu()) / scale
+    print(f"  f64 n_ao 512: rank {rA}, E_x {EA:.12f}, -Tr K {trK:.12f}, hermiticity {herm:.1e}",
+          flush=True)
+    assert abs(EA - trK) <= 1e-12 * abs(EA)
+    assert herm <= 1e-13
+    # n_ao at its maximum: the first 512 functions are the same
+    aoB = torch.cat([occ, extra], dim=2).contiguous()
+    KB, EB, rB = fused("f64", aoB, psi)
+    dB = float((KB[0, :no, :no] - KA[0]).abs().max().cpu()) / scale
+    hB = float((KB[0] - KB[0].conj().T).abs().max().cpu()) / float(KB.abs().max().cpu())
+    print(f"  f64 n_ao 4096: block diff {dB:.1e}, E_x diff {abs(EB - EA):.1e}, hermiticity {hB:.1e}",
+          flush=True)
+    del aoB, KB
+    assert rB == rA and abs(EB - EA) <= 1e-14 * abs(EA)
+    assert dB <= 1e-13 and hB <= 1e-13
+    # the stage-wise calls
+    c = exx.make_cell(L, grid, (1, 1, 1), no, no, ni)
+    xi = torch.empty((1, ni, ng), dtype=torch.complex128, device=dev)
+    S = torch.empty((1, ni, ni), dtype=torch.complex128, device=dev)
+    V = torch.empty((1, ni, ni), dtype=torch.complex128, device=dev)
+    KC = torch.empty((1, no, no), dtype=torch.complex128, device=dev)
+    EC = torch.empty((1,), dtype=torch.float64, device=dev)
+    rC = torch.empty((1,), dtype=torch.int32, device=dev)
+    exx.exx_isdf_fit(h, c, exx.EXX_F64, psi, occ, pts, xi, S, rC)
+    exx.exx_coulomb_V(h, c, exx.EXX_F64, xi, pts, V)
+    exx.exx_build_K(h, c, exx.EXX_F64, occ, occ, V, KC, EC)
+    torch.cuda.synchronize()
+    del xi, V
+    Sh = S[0].cpu().numpy()
+    ev = np.linalg.eigvalsh(0.5 * (Sh + Sh.conj().T))
+    cond = float(ev[-1] / ev[0]) if ev[0] > 0 else float("inf")
+    tol = min(1e-8, max(1e-12, 64 * EPS64 * cond))  # the parity tests' bound
+    dC = float((KC - KA).abs().max().cpu()) / scale
+    dEC = abs(float(EC.cpu()[0]) - EA) / abs(EA)
+    print(f"  stages: rank {int(rC.cpu()[0])}, cond {cond:.2e}, rel dK {dC:.1e}, rel dE {dEC:.1e} "
+          f"(tol {tol:.1e})", flush=True)
+    assert int(rC.cpu()[0]) == rA
+    assert dC <= tol and dEC <= tol
+    # MIXED
+    KM, EM, rM = fused("mixed", occ, psi)
+    dM = float((KM - KA).abs().max().cpu()) / scale
+    print(f"  mixed: rel dK {dM:.1e}, rel dE {abs(EM - EA) / abs(EA):.1e}", flush=True)
+    assert rM == rA and dM <= 3e-7 and abs(EM - EA) <= 3e-7 * abs(EA)
+    # one step past the bound: rejected before any work (the library checks the
+    # cell before it touches an array, so the arrays of the accepted cell serve)
+    c2 = exx.make_cell(L, (128, 32, 64), (1, 1, 1), no, no, ni)
+    Ex2 = torch.empty(1, dtype=torch.float64, device=dev)
+    r2 = torch.empty(1, dtype=torch.int32, device=dev)
+    st = exx._lib.exx_build(h.raw, ctypes.byref(c2), exx.EXX_F64, psi.data_ptr(), occ.data_ptr(),
+                            occ.data_ptr(), pts.data_ptr(), KA.data_ptr(), Ex2.data_ptr(),
+                            r2.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    msg = exx._lib.exx_last_error(h.raw).decode()
+    print(f"  n_isdf N_g = {ni * 128 * 32 * 64}: status {st}, '{msg}'")
+    assert st == -7  # EXX_ERR_UNSUPPORTED
+    assert "2^28" in msg
+    del h
+    torch.cuda.empty_cache()
