@@ -575,8 +575,9 @@ CPU_SAMPLE = ("batch0-a8-k1", "batch1-a8-k2", "batch3-a16-k1")
 
 def cpu_baseline(cells):
     """Complete FP64 oracle K-builds (same steps as the GPU build) of three small
-    cells of the batch, median of three passes; scaled to the batch by the plain
-    method's work (Gamma + solve + Coulomb flops of the plain-method count)."""
+    cells of the batch, median of five passes (about 12 s of CPU work); scaled
+    to the batch by the plain method's work (Gamma + solve + Coulomb flops of the
+    plain-method count)."""
     import synth
     from oracle import select, thc
     from oracle._threads import WORKERS
@@ -589,7 +590,7 @@ def cpu_baseline(cells):
         ao = np.stack([synth.ao_at_points(c, n, pts) for n in range(c.N_k)])
         prepared.append((c, psi, pts, ao))
     passes = []
-    for _ in range(3):
+    for _ in range(5):
         t0 = time.perf_counter()
         for c, psi, pts, ao in prepared:
             thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao)
@@ -608,7 +609,7 @@ def cpu_baseline(cells):
         "kind": "oracle",
         "cpu_model": cpu_info(),
         "sample": (f"complete oracle K-builds of {', '.join(c.name for c, *_ in prepared)} "
-                   f"(median of 3 passes: {med:.2f} s for the {len(prepared)} cells, "
+                   f"(median of 5 passes: {med:.2f} s for the {len(prepared)} cells, "
                    f"{len(prepared) / med:.3f} builds/s); scaled to the 24-cell batch by the "
                    f"plain method's flops (x{scale:.0f})"),
         "sample_seconds": passes,
