@@ -577,9 +577,10 @@ def cpu_baseline(cells):
     """Complete FP64 oracle K-builds (same steps as the GPU build) of three small
     cells of the batch, median of five passes (about 12 s of CPU work); scaled
     to the batch by the plain method's work (Gamma + solve + Coulomb flops of the
-    plain-method count)."""
+    plain-method count). Beside it, exact exchange (the direct oracle) on the
+    first sample cell, timed once, with the fitted E_x of the same cell."""
     import synth
-    from oracle import select, thc
+    from oracle import direct, select, thc
     from oracle._threads import WORKERS
 
     sample = [c for c in cells if c.name in CPU_SAMPLE]
@@ -592,10 +593,18 @@ def cpu_baseline(cells):
     passes = []
     for _ in range(5):
         t0 = time.perf_counter()
-        for c, psi, pts, ao in prepared:
-            thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao)
+        for j, (c, psi, pts, ao) in enumerate(prepared):
+            o = thc.thc_oo_k(c.L, c.grid, c.kmesh, psi, pts, ao)
+            if j == 0:
+                e_thc = float(o["Ex"])
         passes.append(time.perf_counter() - t0)
     med = float(np.median(passes))
+    # exact exchange (one FFT-Poisson solve per occupied pair density) on the
+    # first sample cell: its cost, and what the fit at this N_ISDF misses there
+    c0, psi0 = prepared[0][0], prepared[0][1]
+    t0 = time.perf_counter()
+    e_direct = float(direct.exchange_energy(c0.L, c0.grid, c0.kmesh, psi0))
+    t_direct = time.perf_counter() - t0
 
     def w(c):
         sv = work(c, "f64")
@@ -613,6 +622,8 @@ def cpu_baseline(cells):
                    f"{len(prepared) / med:.3f} builds/s); scaled to the 24-cell batch by the "
                    f"plain method's flops (x{scale:.0f})"),
         "sample_seconds": passes,
+        "direct_exchange": {"cell": c0.name, "seconds": t_direct, "Ex_direct": e_direct,
+                            "Ex_thc": e_thc, "n_isdf": c0.n_isdf},
     }
 
 
