@@ -24,6 +24,8 @@ against the per-transfer oracle's shows the fit's own error).
 Options: --steps K --warmup W --gpus N (N must be 1) --no-cpu --record PATH (append
 JSONL run records) --profile
 (the profiler's target, no JSON: the mixed batch twice and a 1 GiB copy; with
+--phases, the tuning batch, then the 24 single builds with serial phase events
+that the roofline is computed from, and the copy; with
 --workload rings-k2 | rings-k3, two builds per precision of that cell and the
 copy; with --potentials and a ring workload, the exchange gradient and the
 robust-fit K instead); --workload rings-k2 | rings-k3 | select-k4 print a single
@@ -929,7 +931,9 @@ def profile_target(args):
     concurrent lanes (after one untimed warm-up batch, which also tunes the tiles,
     and a one-row exx_mlp_moments dispatch that marks where the measured batch
     starts), then a plain 1 GiB device copy whose counter readings calibrate the
-    traffic counters."""
+    traffic counters. With --phases the measured part is instead the pass of 24
+    single MIXED builds with serial phase events from which the bench line's
+    roofline is computed, and the phase times are printed."""
     import torch
 
     import synth
@@ -950,10 +954,26 @@ def profile_target(args):
             exx.exx_mlp_moments(h, torch.zeros((1, 3), dtype=torch.float32, device=dev),
                                 torch.zeros((6,), dtype=torch.float64, device=dev))
             torch.cuda.synchronize()
+            if args.phases:
+                break
         exx.exx_build_batched(h, its, exx.EXX_MIXED,
                               exx.EXX_BATCH_CONCURRENT | exx.EXX_BATCH_TUNE)
         torch.cuda.synchronize()
         log(f"profile target: mixed batch {rep} done")
+    if args.phases:
+        # the pass the bench line's roofline is measured on: every cell's build,
+        # the normally overlapping phases one after another, with phase events
+        h.set_timing(True, serial=True)
+        phase_ms = {}
+        for it in its:
+            exx.exx_build(h, it["cell"], exx.EXX_MIXED, it["psi_grid"], it["occ_pts"],
+                          it["ao_pts"], it["pts"], it["K"], it["Ex"], it["rank"])
+            torch.cuda.synchronize()
+            for p, (ms, _) in h.phase_times().items():
+                phase_ms[p] = phase_ms.get(p, 0.0) + ms
+        h.set_timing(False)
+        log("profile target: phase pass done; phase ms " +
+            ", ".join(f"{p} {ms:.2f}" for p, ms in sorted(phase_ms.items())))
     src = torch.ones((1 << 27,), dtype=torch.float64, device=dev)  # 1 GiB
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -1014,6 +1034,9 @@ def main():
     ap.add_argument("--record", metavar="PATH",
                     help="append JSONL run records (one per measured path) to PATH")
     ap.add_argument("--profile", action="store_true")
+    ap.add_argument("--phases", action="store_true",
+                    help="with --profile on the batch: after the tuning batch, profile the "
+                         "pass of single builds with phase events that the roofline uses")
     ap.add_argument("--potentials", action="store_true",
                     help="with --profile and a ring workload: profile the exchange gradient "
                          "and the robust-fit K instead of the builds")
