@@ -18,7 +18,9 @@
     build (inverse Cholesky factor on the grid) agree to the rounding that
     cond(S) allows (tolerance as in the parity tests), and MIXED to 3e-7;
   and one step past the bound (n_isdf N_g >= 2^28) is rejected before any
-  work with EXX_ERR_UNSUPPORTED.
+  work with EXX_ERR_UNSUPPORTED. The exchange gradient and the robust fit at
+  the same cell are held to Euler's identity and to the robust energy being
+  the fitted one.
 Inputs of the large cell are drawn on the device from a seeded generator
 (complex Gaussian orbitals, distinct random points).
 """
@@ -186,5 +188,52 @@ def test_largest_accepted_cell(gpu):
     print(f"  n_isdf N_g = {ni * 128 * 32 * 64}: status {st}, '{msg}'")
     assert st == -7  # EXX_ERR_UNSUPPORTED
     assert "2^28" in msg
+    del h
+    torch.cuda.empty_cache()
+
+
+def test_largest_accepted_cell_gradient_and_robust(gpu):
+    """The exchange gradient and the robust fit at the largest accepted cell, with
+    the occupied orbitals as the AO basis (ao_grid = psi_grid, ao_pts = occ_pts,
+    n_ao = n_occ = 512, so the density matrix is the identity): Euler's identity
+    for the energy, homogeneous of degree two in the density, gives
+    -(1/N_k) Tr Kgrad = E_x; the robust energy equals the fitted one, so
+    -(1/N_k) Tr K_rob = E_x; Kgrad and K_rob are Hermitian; and the gradient
+    call's K equals the fused build's to the parity tests' FP64 bound."""
+    import torch
+
+    from paper_2304_05505_amd import exx
+
+    dev = torch.device("cuda", 0)
+    L = (25.6, 6.4, 6.0)
+    grid, no, ni, ng, psi, pts, occ, _ = _largest(torch, dev)
+    h = exx.Handle(0)
+    c = exx.make_cell(L, grid, (1, 1, 1), no, no, ni)
+
+    def empty(shape, dt=torch.complex128):
+        return torch.empty(shape, dtype=dt, device=dev)
+
+    K0, E0, r0 = empty((1, no, no)), empty((1,), torch.float64), empty((1,), torch.int32)
+    exx.exx_build(h, c, exx.EXX_F64, psi, occ, occ, pts, K0, E0, r0)
+    K, Kg, Ex, rank = empty((1, no, no)), empty((1, no, no)), empty((1,), torch.float64), \
+        empty((1,), torch.int32)
+    exx.exx_exchange_gradient(h, c, psi, occ, occ, psi, pts, K, Kg, Ex, rank)
+    Kr, Er, rr = empty((1, no, no)), empty((1,), torch.float64), empty((1,), torch.int32)
+    exx.exx_build_robust(h, c, psi, occ, occ, psi, pts, Kr, Er, rr)
+    torch.cuda.synchronize()
+    e0, eg, er = float(E0.cpu()[0]), float(Ex.cpu()[0]), float(Er.cpu()[0])
+    euler = -float(torch.diagonal(Kg[0]).real.sum().cpu())
+    rob = -float(torch.diagonal(Kr[0]).real.sum().cpu())
+    dK = float((K - K0).abs().max().cpu()) / float(K0.abs().max().cpu())
+    hg = float((Kg[0] - Kg[0].conj().T).abs().max().cpu()) / float(Kg.abs().max().cpu())
+    hr = float((Kr[0] - Kr[0].conj().T).abs().max().cpu()) / float(Kr.abs().max().cpu())
+    print(f"largest cell: E_x {e0:.10f}; gradient: -Tr Kgrad {euler:.10f}, E_x {eg:.10f}, "
+          f"rel dK {dK:.1e}, hermiticity {hg:.1e}; robust: -Tr K_rob {rob:.10f}, E_x {er:.10f}, "
+          f"hermiticity {hr:.1e}", flush=True)
+    assert int(rank.cpu()[0]) == int(r0.cpu()[0]) == int(rr.cpu()[0])
+    assert abs(eg - e0) <= 1e-12 * abs(e0) and abs(er - e0) <= 1e-12 * abs(e0)
+    assert abs(euler - e0) <= 1e-10 * abs(e0)
+    assert abs(rob - e0) <= 1e-10 * abs(e0)
+    assert dK <= 1e-12 and hg <= 1e-12 and hr <= 1e-12
     del h
     torch.cuda.empty_cache()
