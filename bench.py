@@ -773,6 +773,15 @@ def bench_nk_series(args):
             row[f"{prec}_Ex"] = float(o["Ex"].cpu()[0])
             log(f"[nk-series] {k}x{k}x{k}: {prec} {s * 1e3:.2f} ms/build "
                 f"({s * 1e3 / cell.N_k:.2f} ms per k-point)")
+        # one MIXED build with phase events, the overlapping phases serialised
+        h.set_timing(True, serial=True)
+        exx.exx_build(h, t["cell"], exx.EXX_MIXED, psi_for(t, "mixed", torch), t["occ_pts"],
+                      t["ao_pts"], t["pts"], o["K"], o["Ex"], o["rank"])
+        torch.cuda.synchronize()
+        row["mixed_phases_ms"] = {p: ms for p, (ms, _) in h.phase_times().items()}
+        h.set_timing(False)
+        log(f"[nk-series] {k}x{k}x{k}: mixed phases " +
+            ", ".join(f"{p} {ms:.2f}" for p, ms in sorted(row["mixed_phases_ms"].items())))
         rows.append(row)
         del t, o
         torch.cuda.synchronize()
