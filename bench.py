@@ -148,7 +148,7 @@ KERNELS = {  # dominant kernel(s) of each phase, real path / paired path
 TRAFFIC = {
     "solve": {"source": "paper_2304_05505_amd/csrc/gemm_mfma.hip",
               "sha256": "20b9f74537d768698d899cf87c6d402ee90c1e5f49d29311f9b3873cd09a23ef",
-              "bytes": 344.24e9, "launches": 38,
+              "bytes": 344.59e9, "launches": 38,
               "kernels": ["zgemm_nn_mfma<double, float, 2, 2, 0, 0, 1>",
                           "dgemm_nn_mfma<double, float, 1, 0>"]},
 }
